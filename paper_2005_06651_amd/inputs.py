@@ -1,0 +1,361 @@
+"""Seeded synthetic inputs for the MHD step.
+
+This module only builds initial states: primitive or conserved cell fields and
+face-averaged magnetic fields on the block layout.  It holds none of the
+solver's arithmetic (no reconstruction, Riemann solver, EMF or update), so both
+the HIP library and the CPU oracle can be fed from it.
+
+Layout (shared by every producer and consumer of block data):
+  cell arrays  [v][k][j][i], shape (nv, N3, N2, N1), N_d = n_d + 2*ng, i fastest
+  face arrays  [c][k][j][i], shape (3, N3+1, N2+1, N1+1); component c at index
+               (k, j, i) is the face on the lower side of cell (k, j, i) along c.
+Ghost entries are the periodic images of active entries: every value is
+evaluated at the coordinates of the image, so ghosts match their source bitwise.
+
+Face fields come from a vector potential: each face value is the circulation of
+A around the face (Stokes) divided by the face area, with every edge integral
+computed once and shared by the faces that meet at that edge.  The discrete
+divergence then telescopes to round-off.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+
+@dataclass
+class Block:
+    n: tuple            # active cells (n1, n2, n3)
+    ng: int
+    dx: tuple           # (dx1, dx2, dx3)
+    gamma: float
+    bface: np.ndarray   # (3, N3+1, N2+1, N1+1)
+    prim: np.ndarray | None = None   # (5, N3, N2, N1): rho, v1, v2, v3, p
+    cons: np.ndarray | None = None   # (5, N3, N2, N1): rho, M1, M2, M3, E
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def shape(self):
+        n1, n2, n3 = self.n
+        return (n3 + 2 * self.ng, n2 + 2 * self.ng, n1 + 2 * self.ng)
+
+    @property
+    def active(self):
+        """Slices of the active cells of a cell array (last three axes)."""
+        g = self.ng
+        n1, n2, n3 = self.n
+        return (slice(g, g + n3), slice(g, g + n2), slice(g, g + n1))
+
+
+def _wrapped_index(N: int, n: int, ng: int) -> np.ndarray:
+    """Active index of the periodic image of every stored index 0..N-1."""
+    idx = np.arange(N)
+    return ng + np.mod(idx - ng, n)
+
+
+def _cell_centres(n: int, ng: int, h: float, extra: int = 0) -> np.ndarray:
+    """Coordinate of the cell centre of the periodic image of every stored index
+    (extra=1 adds the padded entry of face arrays)."""
+    N = n + 2 * ng + extra
+    return (_wrapped_index(N, n, ng) - ng + 0.5) * h
+
+
+def _lower_faces(n: int, ng: int, h: float, extra: int = 1) -> np.ndarray:
+    N = n + 2 * ng + extra
+    return (_wrapped_index(N, n, ng) - ng) * h
+
+
+# ---------------------------------------------------------------------------
+# Face fields from a vector potential given as a sum of Fourier modes
+#   A(x) = sum_m  a_m * sin(k_m . x + phi_m)
+# Edge integrals of each mode are closed-form.
+# ---------------------------------------------------------------------------
+def _edge_integral(kd, x0, h, theta):
+    """Integral over [x0, x0+h] of sin(kd*x + theta) dx (arrays broadcast)."""
+    if abs(kd) < 1e-300:
+        return h * np.sin(theta + 0.0 * x0)
+    return (np.cos(kd * x0 + theta) - np.cos(kd * (x0 + h) + theta)) / kd
+
+
+def faces_from_modes(n, ng, dx, modes):
+    """Face-averaged B of curl A for A = sum a sin(k.x + phi) (modes = list of
+    (k(3), a(3), phi)).  Returns (3, N3+1, N2+1, N1+1)."""
+    n1, n2, n3 = n
+    h1, h2, h3 = dx
+    # coordinates along each axis, padded length N+1, of the periodic images
+    xc = [_cell_centres(n1, ng, h1, 1), _cell_centres(n2, ng, h2, 1), _cell_centres(n3, ng, h3, 1)]
+    xf = [_lower_faces(n1, ng, h1), _lower_faces(n2, ng, h2), _lower_faces(n3, ng, h3)]
+    shp = (n3 + 2 * ng + 1, n2 + 2 * ng + 1, n1 + 2 * ng + 1)
+    # G1: integral of A_x along x over cell i, at (y_{j-1/2}, z_{k-1/2}); G2, G3 alike
+    G1 = np.zeros(shp)
+    G2 = np.zeros(shp)
+    G3 = np.zeros(shp)
+    X1f, X2f, X3f = xf[0][None, None, :], xf[1][None, :, None], xf[2][:, None, None]
+    for k, a, phi in modes:
+        k1, k2, k3 = k
+        if a[0] != 0.0:
+            G1 += a[0] * _edge_integral(k1, X1f, h1, k2 * X2f + k3 * X3f + phi)
+        if a[1] != 0.0:
+            G2 += a[1] * _edge_integral(k2, X2f, h2, k1 * X1f + k3 * X3f + phi)
+        if a[2] != 0.0:
+            G3 += a[2] * _edge_integral(k3, X3f, h3, k1 * X1f + k2 * X2f + phi)
+    return _faces_from_edges(G1, G2, G3, n, ng, dx)
+
+
+def _faces_from_edges(G1, G2, G3, n, ng, dx):
+    """Circulation around each face / area.  The G arrays live on the padded
+    grid; neighbours one index up are taken at the periodic image index so the
+    last padded entry stays consistent."""
+    n1, n2, n3 = n
+    h1, h2, h3 = dx
+    N1, N2, N3 = n1 + 2 * ng, n2 + 2 * ng, n3 + 2 * ng
+    up1 = _wrapped_index(N1 + 2, n1, ng)[1:N1 + 2]   # image of index+1
+    up2 = _wrapped_index(N2 + 2, n2, ng)[1:N2 + 2]
+    up3 = _wrapped_index(N3 + 2, n3, ng)[1:N3 + 2]
+    B = np.zeros((3,) + G1.shape)
+    # B1 at (i-1/2, j, k): G3(i-1/2, j+1/2, k) - G3(i-1/2, j-1/2, k) - G2(i-1/2, j, k+1/2) + G2(i-1/2, j, k-1/2)
+    B[0] = (G3[:, up2, :] - G3 - G2[up3, :, :] + G2) / (h2 * h3)
+    # B2 at (i, j-1/2, k): G1(k+1/2) - G1(k-1/2) - G3(i+1/2) + G3(i-1/2)
+    B[1] = (G1[up3, :, :] - G1 - G3[:, :, up1] + G3) / (h3 * h1)
+    # B3 at (i, j, k-1/2): G2(i+1/2) - G2(i-1/2) - G1(j+1/2) + G1(j-1/2)
+    B[2] = (G2[:, :, up1] - G2 - G1[:, up2, :] + G1) / (h1 * h2)
+    return B
+
+
+def _spectral_edges(n, ng, dx, L, Ahat):
+    """Edge integrals of a real periodic vector potential given by its rfft
+    spectrum on the active grid (Ahat: 3 complex arrays from rfftn of point
+    values at cell centres).  Evaluated exactly for the band-limited field."""
+    n1, n2, n3 = n
+    h1, h2, h3 = dx
+    k1 = np.fft.rfftfreq(n1, d=1.0 / n1)[None, None, :]
+    k2 = np.fft.fftfreq(n2, d=1.0 / n2)[None, :, None]
+    k3 = np.fft.fftfreq(n3, d=1.0 / n3)[:, None, None]
+    w1, w2, w3 = 2 * np.pi * k1 / L[0], 2 * np.pi * k2 / L[1], 2 * np.pi * k3 / L[2]
+
+    def sinc_int(w, h):  # integral over a cell of e^{i w x} relative to the centre value, times h
+        with np.errstate(invalid="ignore", divide="ignore"):
+            s = np.where(np.abs(w) > 0, np.sin(0.5 * w * h) / (0.5 * w * h + 1e-300), 1.0)
+        return h * s
+
+    # shift from cell centre (grid of Ahat) to lower face: e^{-i w h/2}
+    s1, s2, s3 = np.exp(-0.5j * w1 * h1), np.exp(-0.5j * w2 * h2), np.exp(-0.5j * w3 * h3)
+    G1 = np.fft.irfftn(Ahat[0] * sinc_int(w1, h1) * s2 * s3, s=(n3, n2, n1), axes=(0, 1, 2))
+    G2 = np.fft.irfftn(Ahat[1] * sinc_int(w2, h2) * s1 * s3, s=(n3, n2, n1), axes=(0, 1, 2))
+    G3 = np.fft.irfftn(Ahat[2] * sinc_int(w3, h3) * s1 * s2, s=(n3, n2, n1), axes=(0, 1, 2))
+    return [_pad_periodic(G, ng, extra=1) for G in (G1, G2, G3)]
+
+
+def _pad_periodic(a_active: np.ndarray, ng: int, extra: int = 0) -> np.ndarray:
+    """Stored array (ghosts + optional padded entry) of periodic images."""
+    n3, n2, n1 = a_active.shape
+    i1 = _wrapped_index(n1 + 2 * ng + extra, n1, ng) - ng
+    i2 = _wrapped_index(n2 + 2 * ng + extra, n2, ng) - ng
+    i3 = _wrapped_index(n3 + 2 * ng + extra, n3, ng) - ng
+    return a_active[np.ix_(i3, i2, i1)]
+
+
+def _band_modes(rng, n, kmin, kmax):
+    """Random complex spectrum on integer wavevectors kmin <= |k| <= kmax, as
+    rfft-shaped arrays for a grid of n = (n1, n2, n3) cells on a unit-period box."""
+    n1, n2, n3 = n
+    k1 = np.fft.rfftfreq(n1, d=1.0 / n1)[None, None, :]
+    k2 = np.fft.fftfreq(n2, d=1.0 / n2)[None, :, None]
+    k3 = np.fft.fftfreq(n3, d=1.0 / n3)[:, None, None]
+    kk = np.sqrt(k1 ** 2 + k2 ** 2 + k3 ** 2)
+    band = (kk >= kmin) & (kk <= kmax)
+    shp = (n3, n2, n1 // 2 + 1)
+    spec = np.zeros((3,) + shp, complex)
+    for c in range(3):
+        re = rng.standard_normal(shp)
+        im = rng.standard_normal(shp)
+        spec[c] = np.where(band, re + 1j * im, 0.0)
+    return spec, (k1, k2, k3)
+
+
+def _project_solenoidal(spec, kvec):
+    k1, k2, k3 = kvec
+    kk = k1 ** 2 + k2 ** 2 + k3 ** 2
+    kk = np.where(kk == 0, 1.0, kk)
+    dot = (spec[0] * k1 + spec[1] * k2 + spec[2] * k3) / kk
+    return np.stack([spec[0] - dot * k1, spec[1] - dot * k2, spec[2] - dot * k3])
+
+
+# ---------------------------------------------------------------------------
+# Workloads
+# ---------------------------------------------------------------------------
+def linear_wave(N: int = 16, gamma: float = 5.0 / 3.0, amp: float = 1.0e-6, ng: int = 2) -> Block:
+    """Fast magnetosonic eigenmode along the grid diagonal (Sec. 3.3.1): box
+    3 x 1.5 x 1.5 on 2N x N x N cells, wavelength 1, amplitude amp.  Wave frame
+    n1 = (1,2,2)/3, n2 = (-2,1,0)/sqrt5, n3 = n1 x n2.  Background rho = 1,
+    p = 1/gamma, v = 0, B = (1, sqrt2, 1/2) in the wave frame, so a = 1 and the
+    fast speed is 2.  Conserved state U = U0 + amp * R cos(k.x) with the fast
+    right eigenvector R (normalised to drho = 1); B from a vector potential."""
+    n = (2 * N, N, N)
+    L = (3.0, 1.5, 1.5)
+    dx = tuple(L[d] / n[d] for d in range(3))
+    e1 = np.array([1.0, 2.0, 2.0]) / 3.0
+    e2 = np.array([-2.0, 1.0, 0.0]) / math.sqrt(5.0)
+    e3 = np.cross(e1, e2)
+    r2 = math.sqrt(2.0)
+    b_wave = (1.0, r2, 0.5)
+    B0 = b_wave[0] * e1 + b_wave[1] * e2 + b_wave[2] * e3
+    # R = (drho, dMn, dMt1, dMt2, dE, dBt1, dBt2)
+    R = (1.0, 2.0, -2.0 * r2 / 3.0, -1.0 / 3.0, 4.5, 4.0 * r2 / 3.0, 2.0 / 3.0)
+    dM = R[1] * e1 + R[2] * e2 + R[3] * e3
+    dB = R[5] * e2 + R[6] * e3
+    p0 = 1.0 / gamma
+    E0 = p0 / (gamma - 1.0) + 0.5 * float(B0 @ B0)
+    kvec = 2.0 * math.pi * e1  # wavelength 1
+
+    x1 = _cell_centres(n[0], ng, dx[0])[None, None, :]
+    x2 = _cell_centres(n[1], ng, dx[1])[None, :, None]
+    x3 = _cell_centres(n[2], ng, dx[2])[:, None, None]
+    phase = np.cos(kvec[0] * x1 + kvec[1] * x2 + kvec[2] * x3)
+    shape = (n[2] + 2 * ng, n[1] + 2 * ng, n[0] + 2 * ng)
+    cons = np.empty((5,) + shape)
+    cons[0] = 1.0 + amp * R[0] * phase
+    cons[1] = amp * dM[0] * phase
+    cons[2] = amp * dM[1] * phase
+    cons[3] = amp * dM[2] * phase
+    cons[4] = E0 + amp * R[4] * phase
+    # perturbation potential a sin(k.x) with curl = amp * dB cos(k.x)
+    a = amp * np.cross(dB, kvec) / float(kvec @ kvec)
+    bf = faces_from_modes(n, ng, dx, [(tuple(kvec), tuple(a), 0.0)])
+    for c in range(3):
+        bf[c] += B0[c]
+    return Block(n=n, ng=ng, dx=dx, gamma=gamma, bface=bf, cons=cons,
+                 meta=dict(workload="linear_wave_fast", N=N, amp=amp, t_end=0.5, cfl=0.3,
+                           fast_speed=2.0, box=L))
+
+
+def turbulence(n: int = 256, seed: int = 1, mach: float = 1.0, brms: float = 0.1, bx0: float = 0.5,
+               gamma: float = 5.0 / 3.0, ng: int = 2, kmin: float = 1.0, kmax: float = 4.0) -> Block:
+    """Decaying-turbulence initial state on the unit periodic cube with n^3
+    cells: rho = 1, p = 1, solenoidal velocity with power on 1 <= |k| <= 4
+    scaled to rms |v| = mach * sqrt(gamma p / rho), point-sampled at cell
+    centres; B = (bx0, 0, 0) + curl A with A on the same band, scaled so the
+    rms of the face values of curl A is brms."""
+    rng = np.random.default_rng(seed)
+    nn = (n, n, n)
+    dx = (1.0 / n,) * 3
+    vspec, kv = _band_modes(rng, nn, kmin, kmax)
+    vspec = _project_solenoidal(vspec, kv)
+    vel = np.stack([np.fft.irfftn(vspec[c], s=(n, n, n), axes=(0, 1, 2)) for c in range(3)])
+    vrms = math.sqrt(float(np.mean(np.sum(vel ** 2, axis=0))))
+    vel *= mach * math.sqrt(gamma) / vrms
+    aspec, _ = _band_modes(rng, nn, kmin, kmax)
+    # aspec holds the rfft of point values of A at cell centres
+    G = _spectral_edges(nn, ng, dx, (1.0, 1.0, 1.0), aspec)
+    dB = _faces_from_edges(G[0], G[1], G[2], nn, ng, dx)
+    g = ng
+    act = dB[:, g:g + n, g:g + n, g:g + n]
+    brms_now = math.sqrt(float(np.mean(np.sum(act ** 2, axis=0))))
+    bf = dB * (brms / brms_now)
+    bf[0] += bx0
+    prim = np.empty((5,) + (n + 2 * ng,) * 3)
+    prim[0] = 1.0
+    for c in range(3):
+        prim[1 + c] = _pad_periodic(vel[c], ng)
+    prim[4] = 1.0
+    return Block(n=nn, ng=ng, dx=dx, gamma=gamma, bface=bf, prim=prim,
+                 meta=dict(workload="turbulence", seed=seed, mach=mach, brms=brms, bx0=bx0, cfl=0.3))
+
+
+def blast(n: int = 512, seed: int = 1, gamma: float = 5.0 / 3.0, ng: int = 3, p_amb: float = 0.1,
+          p_in: float = 10.0, radius: float = 0.1) -> Block:
+    """MHD blast on the unit periodic cube: rho = 1, p = p_amb, p = p_in where
+    the (periodic, minimum-image) distance to a seeded random centre is below
+    radius (sampled at cell centres); uniform B = (1/sqrt2, 1/sqrt2, 0)."""
+    rng = np.random.default_rng(seed)
+    c = rng.random(3)
+    nn = (n, n, n)
+    h = 1.0 / n
+    x = [_cell_centres(n, ng, h)] * 3
+    d1 = np.abs(x[0][None, None, :] - c[0]); d1 = np.minimum(d1, 1.0 - d1)
+    d2 = np.abs(x[1][None, :, None] - c[1]); d2 = np.minimum(d2, 1.0 - d2)
+    d3 = np.abs(x[2][:, None, None] - c[2]); d3 = np.minimum(d3, 1.0 - d3)
+    r2 = d1 ** 2 + d2 ** 2 + d3 ** 2
+    prim = np.zeros((5,) + (n + 2 * ng,) * 3)
+    prim[0] = 1.0
+    prim[4] = np.where(r2 < radius * radius, p_in, p_amb)
+    bf = np.zeros((3,) + (n + 2 * ng + 1,) * 3)
+    bf[0] = 1.0 / math.sqrt(2.0)
+    bf[1] = 1.0 / math.sqrt(2.0)
+    return Block(n=nn, ng=ng, dx=(h, h, h), gamma=gamma, bface=bf, prim=prim,
+                 meta=dict(workload="blast", seed=seed, centre=c.tolist(), cfl=0.3))
+
+
+def uniform(n=(8, 8, 8), ng=2, rho=1.0, v=(0.3, -0.2, 0.1), p=0.7, B=(0.5, -0.4, 0.3),
+            gamma=5.0 / 3.0, dx=(0.1, 0.1, 0.1)) -> Block:
+    """Spatially uniform state."""
+    n1, n2, n3 = n
+    shape = (n3 + 2 * ng, n2 + 2 * ng, n1 + 2 * ng)
+    prim = np.empty((5,) + shape)
+    prim[0] = rho
+    for c in range(3):
+        prim[1 + c] = v[c]
+    prim[4] = p
+    bf = np.empty((3, shape[0] + 1, shape[1] + 1, shape[2] + 1))
+    for c in range(3):
+        bf[c] = B[c]
+    return Block(n=tuple(n), ng=ng, dx=tuple(dx), gamma=gamma, bface=bf, prim=prim,
+                 meta=dict(workload="uniform"))
+
+
+def smooth_random(n=(16, 16, 16), seed=0, ng=2, gamma=5.0 / 3.0, vmax=0.9, kmax=2.0,
+                  rho_range=(0.5, 2.0), p_range=(0.5, 2.0), B0=(0.3, 0.2, -0.1), brms=0.2,
+                  dx=None) -> Block:
+    """Smooth periodic random state on a block of n cells (unit-period box
+    unless dx is given): rho, p in the given ranges via 1.25 + 0.75 f/max|f|
+    (for the default ranges), |v| < vmax, B = B0 + curl A."""
+    rng = np.random.default_rng(seed)
+    n1, n2, n3 = n
+    if dx is None:
+        dx = (1.0 / n1, 1.0 / n2, 1.0 / n3)
+    L = (dx[0] * n1, dx[1] * n2, dx[2] * n3)
+
+    def field_(spec):
+        return np.fft.irfftn(spec, s=(n3, n2, n1), axes=(0, 1, 2))
+
+    spec, kv = _band_modes(rng, (n1, n2, n3), 1.0, kmax)
+    f_rho = field_(spec[0]); f_p = field_(spec[1])
+    vspec, _ = _band_modes(rng, (n1, n2, n3), 1.0, kmax)
+    vel = np.stack([field_(vspec[c]) for c in range(3)])
+    vmag = np.sqrt(np.sum(vel ** 2, axis=0)).max()
+    vel *= vmax / vmag
+    mid_r, half_r = 0.5 * (rho_range[0] + rho_range[1]), 0.5 * (rho_range[1] - rho_range[0])
+    mid_p, half_p = 0.5 * (p_range[0] + p_range[1]), 0.5 * (p_range[1] - p_range[0])
+    rho = mid_r + half_r * f_rho / np.abs(f_rho).max()
+    pr = mid_p + half_p * f_p / np.abs(f_p).max()
+    aspec, _ = _band_modes(rng, (n1, n2, n3), 1.0, kmax)
+    G = _spectral_edges((n1, n2, n3), ng, dx, L, aspec)
+    dB = _faces_from_edges(G[0], G[1], G[2], (n1, n2, n3), ng, dx)
+    g = ng
+    act = dB[:, g:g + n3, g:g + n2, g:g + n1]
+    scale = brms / max(math.sqrt(float(np.mean(np.sum(act ** 2, axis=0)))), 1e-300)
+    bf = dB * scale
+    for c in range(3):
+        bf[c] += B0[c]
+    prim = np.empty((5, n3 + 2 * ng, n2 + 2 * ng, n1 + 2 * ng))
+    prim[0] = _pad_periodic(rho, ng)
+    for c in range(3):
+        prim[1 + c] = _pad_periodic(vel[c], ng)
+    prim[4] = _pad_periodic(pr, ng)
+    return Block(n=(n1, n2, n3), ng=ng, dx=tuple(dx), gamma=gamma, bface=bf, prim=prim,
+                 meta=dict(workload="smooth_random", seed=seed))
+
+
+def divb_metric(bf: np.ndarray, n, ng, dx) -> float:
+    """max over active cells of |sum_d (B_d+ - B_d-)/dx_d| * min dx / max|B|."""
+    g = ng
+    n1, n2, n3 = n
+    a = (slice(g, g + n3), slice(g, g + n2), slice(g, g + n1))
+    b1 = bf[0][a[0], a[1], g:g + n1 + 1]
+    b2 = bf[1][a[0], g:g + n2 + 1, a[2]]
+    b3 = bf[2][g:g + n3 + 1, a[1], a[2]]
+    div = (np.diff(b1, axis=2) / dx[0] + np.diff(b2, axis=1) / dx[1] + np.diff(b3, axis=0) / dx[2])
+    bmax = max(np.abs(b1).max(), np.abs(b2).max(), np.abs(b3).max(), 1e-300)
+    return float(np.abs(div).max() * min(dx) / bmax)

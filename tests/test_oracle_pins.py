@@ -1,0 +1,617 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test names the property it checks and where it comes from.  None of them
+re-types the oracle's own formulas: they use exact solutions of the equations
+(Eq. (cons) of Sec. 3.1), invariants of the discretisation (conservation,
+div B, symmetry), closed forms (stability polynomials, the fast speed) and
+special cases with known answers.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2005_06651_amd import inputs
+
+GAM = 5.0 / 3.0
+
+
+# ---------------------------------------------------------------------------
+# Exact physical flux of ideal MHD in the face frame, from Eq. (cons) with
+# Pi = eta = eta_AD = Q = 0 and the ideal-gas EOS.  Used only to state what an
+# exact solution's flux is.
+# ---------------------------------------------------------------------------
+def exact_flux(w, bx, g=GAM):
+    rho, u, v, ww, p, by, bz = w
+    e = p / (g - 1) + 0.5 * rho * (u * u + v * v + ww * ww) + 0.5 * (bx * bx + by * by + bz * bz)
+    ptot = p + 0.5 * (bx * bx + by * by + bz * bz)
+    return np.array([
+        rho * u,
+        rho * u * u + ptot - bx * bx,
+        rho * u * v - bx * by,
+        rho * u * ww - bx * bz,
+        (e + ptot) * u - bx * (u * bx + v * by + ww * bz),
+        by * u - bx * v,
+        bz * u - bx * ww,
+    ])
+
+
+def exact_cons(w, bx, g=GAM):
+    rho, u, v, ww, p, by, bz = w
+    e = p / (g - 1) + 0.5 * rho * (u * u + v * v + ww * ww) + 0.5 * (bx * bx + by * by + bz * bz)
+    return np.array([rho, rho * u, rho * v, rho * ww, e, by, bz])
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def random_state(rng):
+    return np.array([rng.uniform(0.3, 3), rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(-1, 1),
+                     rng.uniform(0.2, 3), rng.uniform(-1.5, 1.5), rng.uniform(-1.5, 1.5)])
+
+
+# ---------------------------------------------------------------------------
+# Riemann solvers (Sec. 3.2.2)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("rs", ["hlld", "hlle"])
+def test_riemann_consistency(orc, rs):
+    """F(U, U) = F(U): an approximate Riemann solver must return the exact flux
+    when both states are equal."""
+    rng = np.random.default_rng(11)
+    for _ in range(500):
+        w = random_state(rng)
+        bx = rng.uniform(-1.5, 1.5)
+        f, _ = orc.riemann(rs, GAM, w, w, bx)
+        assert rel(f, exact_flux(w, bx)) < 2e-13
+
+
+@pytest.mark.parametrize("rs", ["hlld", "hlle"])
+def test_riemann_supersonic_upwind(orc, rs):
+    """When every wave moves right (left) the flux is the exact flux of the left
+    (right) state."""
+    rng = np.random.default_rng(12)
+    for _ in range(200):
+        wl = random_state(rng)
+        wr = random_state(rng)
+        bx = rng.uniform(-1, 1)
+        cmax = max(orc.fast_speed(wl[0], wl[4], bx, wl[5], wl[6], GAM),
+                   orc.fast_speed(wr[0], wr[4], bx, wr[5], wr[6], GAM))
+        for sgn in (1.0, -1.0):
+            a, b = wl.copy(), wr.copy()
+            a[1] = sgn * (cmax + 0.5 + abs(a[1]))
+            b[1] = sgn * (cmax + 0.5 + abs(b[1]))
+            f, _ = orc.riemann(rs, GAM, a, b, bx)
+            up = a if sgn > 0 else b
+            assert rel(f, exact_flux(up, bx)) < 1e-14
+
+
+def test_riemann_fast_speed_closed_form(orc):
+    """Fast magnetosonic speed of the linear-wave background of Sec. 3.3.1
+    (rho = 1, p = 1/gamma, B = (1, sqrt2, 1/2)): a = 1, c_A,x = 1 and
+    c_f^2 = ((a^2 + B^2) + sqrt((a^2 + B^2)^2 - 4 a^2 B_x^2))/2 = 4."""
+    cf = orc.fast_speed(1.0, 1.0 / GAM, 1.0, math.sqrt(2.0), 0.5, GAM)
+    assert abs(cf - 2.0) < 1e-15
+    # field-free gas: the fast speed is the sound speed sqrt(gamma p / rho)
+    assert abs(orc.fast_speed(2.0, 3.0, 0.0, 0.0, 0.0, GAM) - math.sqrt(GAM * 1.5)) < 1e-15
+    # cold gas along the field: the fast speed is the Alfven speed |B|/sqrt(rho)... or a if larger
+    assert abs(orc.fast_speed(4.0, 1e-300, 2.0, 0.0, 0.0, GAM) - 1.0) < 1e-15
+
+
+def test_phys_flux_matches_equations(orc):
+    rng = np.random.default_rng(13)
+    for _ in range(100):
+        w = random_state(rng)
+        bx = rng.uniform(-1, 1)
+        u, f = orc.phys_flux(GAM, w, bx)
+        assert rel(f, exact_flux(w, bx)) < 1e-14
+        assert rel(u, exact_cons(w, bx)) < 1e-15
+
+
+@pytest.mark.parametrize("rs", ["hlld", "hlle"])
+def test_riemann_mirror_symmetry(orc, rs):
+    """Reflection x -> -x maps the problem (L, R, Bx) to (R', L', -Bx) with
+    w' = (rho, -u, v, w, p, By, Bz); the flux must map to -M F with M flipping
+    the normal momentum (Sec. 3.3.5 on exact symmetry)."""
+    rng = np.random.default_rng(14)
+    M = np.array([1, -1, 1, 1, 1, 1, 1.0])
+    for _ in range(300):
+        wl, wr = random_state(rng), random_state(rng)
+        bx = rng.uniform(-1.5, 1.5)
+        f, _ = orc.riemann(rs, GAM, wl, wr, bx)
+        ml, mr = wl.copy(), wr.copy()
+        ml[1] *= -1
+        mr[1] *= -1
+        g, _ = orc.riemann(rs, GAM, mr, ml, -bx)
+        assert np.max(np.abs(g + M * f)) < 1e-13 * max(1.0, np.max(np.abs(f)))
+
+
+@pytest.mark.parametrize("bx", [0.8, -1.3])
+@pytest.mark.parametrize("u", [0.0, 0.37, -0.52])
+def test_hlld_resolves_contact(orc, bx, u):
+    """An isolated contact discontinuity (only rho jumps) is an exact solution
+    moving at speed u; HLLD returns its exact upwind flux."""
+    wl = np.array([1.7, u, 0.3, -0.2, 0.9, 0.6, -0.4])
+    wr = wl.copy()
+    wr[0] = 0.45
+    f, _ = orc.riemann("hlld", GAM, wl, wr, bx)
+    up = wl if u >= 0 else wr
+    assert rel(f, exact_flux(up, bx)) < 1e-13
+
+
+@pytest.mark.parametrize("u", [0.21, -0.33])
+def test_hlld_resolves_tangential_discontinuity(orc, u):
+    """Bx = 0: a tangential discontinuity (rho, v_t, B_t, p jump with u and
+    p + B^2/2 continuous) is exact; HLLD returns the upwind flux."""
+    wl = np.array([1.3, u, 0.4, -0.1, 1.0, 0.8, 0.2])
+    wr = np.array([0.6, u, -0.7, 0.5, 0.0, -0.3, 0.9])
+    ptl = wl[4] + 0.5 * (wl[5] ** 2 + wl[6] ** 2)
+    wr[4] = ptl - 0.5 * (wr[5] ** 2 + wr[6] ** 2)
+    assert wr[4] > 0
+    f, _ = orc.riemann("hlld", GAM, wl, wr, 0.0)
+    up = wl if u >= 0 else wr
+    assert rel(f, exact_flux(up, 0.0)) < 1e-13
+
+
+@pytest.mark.parametrize("bx", [1.1, -0.7])
+@pytest.mark.parametrize("side", [-1, 1])
+@pytest.mark.parametrize("u", [0.0, 0.4, -0.9])
+def test_hlld_resolves_rotational_discontinuity(orc, bx, side, u):
+    """An isolated rotational (Alfven) discontinuity: rho, p, u, |B_t|
+    continuous, B_t rotated, v_t jumping so that the Rankine-Hugoniot
+    conditions of Eq. (cons) hold with speed S = u + side |Bx|/sqrt(rho).
+    HLLD resolves it exactly: the flux is the exact flux of the upwind side."""
+    rho, p = 1.4, 0.8
+    bt = 0.9
+    th_l, th_r = 0.3, 2.1
+    byl, bzl = bt * math.cos(th_l), bt * math.sin(th_l)
+    byr, bzr = bt * math.cos(th_r), bt * math.sin(th_r)
+    vyl, vzl = 0.2, -0.3
+    # (S - u) [B_t] = -Bx [v_t]  ->  [v_t] = -(S - u) [B_t] / Bx
+    s_minus_u = side * abs(bx) / math.sqrt(rho)
+    vyr = vyl - s_minus_u * (byr - byl) / bx
+    vzr = vzl - s_minus_u * (bzr - bzl) / bx
+    wl = np.array([rho, u, vyl, vzl, p, byl, bzl])
+    wr = np.array([rho, u, vyr, vzr, p, byr, bzr])
+    S = u + s_minus_u
+    # the construction must satisfy every jump condition
+    jump = exact_flux(wr, bx) - exact_flux(wl, bx) - S * (exact_cons(wr, bx) - exact_cons(wl, bx))
+    assert np.max(np.abs(jump)) < 1e-14
+    f, _ = orc.riemann("hlld", GAM, wl, wr, bx)
+    up = wl if S > 0 else wr
+    if S == 0.0:
+        assert rel(exact_flux(wl, bx), exact_flux(wr, bx)) < 1e-14
+    assert rel(f, exact_flux(up, bx)) < 1e-13
+
+
+def test_hlle_is_hll_average(orc):
+    """HLLE flux satisfies the HLL integral relation: with bp = max(S_R, 0),
+    bm = min(S_L, 0), (bp - bm) F = bp F_L - bm F_R + bp bm (U_R - U_L); for a
+    subsonic pair this makes F differ from both F_L and F_R.  Check the
+    relation with Davis bounds computed from the closed-form fast speed."""
+    rng = np.random.default_rng(15)
+    for _ in range(100):
+        wl, wr = random_state(rng), random_state(rng)
+        bx = rng.uniform(-1, 1)
+        cl = orc.fast_speed(wl[0], wl[4], bx, wl[5], wl[6], GAM)
+        cr = orc.fast_speed(wr[0], wr[4], bx, wr[5], wr[6], GAM)
+        sl, sr = min(wl[1] - cl, wr[1] - cr), max(wl[1] + cl, wr[1] + cr)
+        bp, bm = max(sr, 0.0), min(sl, 0.0)
+        expect = (bp * exact_flux(wl, bx) - bm * exact_flux(wr, bx)
+                  + bp * bm * (exact_cons(wr, bx) - exact_cons(wl, bx))) / (bp - bm)
+        f, smax = orc.riemann("hlle", GAM, wl, wr, bx)
+        assert rel(f, expect) < 1e-13
+        assert abs(smax - max(abs(sl), abs(sr))) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Reconstruction (Sec. 3.2.1)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("recon", ["dc", "plm", "ppm"])
+def test_recon_constant(orc, recon):
+    q = np.full(16, 0.37)
+    ql, qr = orc.recon_line(recon, q)
+    assert np.all(ql[3:14] == 0.37) and np.all(qr[3:14] == 0.37)
+
+
+@pytest.mark.parametrize("recon", ["plm", "ppm"])
+def test_recon_exact_for_linear(orc, recon):
+    """PLM and PPM reproduce linear data exactly at faces (the limiters do not
+    act on monotone linear data)."""
+    c = np.arange(20, dtype=float)
+    q = 0.3 + 0.7 * c
+    ql, qr = orc.recon_line(recon, q)
+    face = 0.3 + 0.7 * (c - 0.5)
+    s = slice(3, 18)
+    assert np.max(np.abs(ql[s] - face[s])) < 1e-13
+    assert np.max(np.abs(qr[s] - face[s])) < 1e-13
+
+
+def test_ppm_face_weights_exact_for_cubic(orc):
+    """Eq. (ppm-uniform-weights) is exact for cell averages of a cubic: the
+    reconstructed face values of monotone cubic data equal the point values."""
+    h = 0.1
+    c = np.arange(24, dtype=float)
+    P = lambda x: 1.0 + 0.5 * x + 0.2 * x ** 2 + 0.05 * x ** 3  # monotone for x >= 0
+    Pint = lambda x: x + 0.25 * x ** 2 + 0.2 / 3 * x ** 3 + 0.0125 * x ** 4
+    avg = (Pint((c + 1) * h) - Pint(c * h)) / h
+    ql, qr = orc.recon_line("ppm", avg)
+    face = P(c * h)  # face c-1/2 sits at x = c*h
+    s = slice(4, 20)
+    assert np.max(np.abs(ql[s] - face[s])) < 1e-13
+    assert np.max(np.abs(qr[s] - face[s])) < 1e-13
+
+
+@pytest.mark.parametrize("recon", ["dc", "plm"])
+def test_recon_bounded(orc, recon):
+    """TVD: every face state of DC and van Leer PLM lies within the range of the
+    two cells that share the face."""
+    rng = np.random.default_rng(16)
+    for _ in range(50):
+        q = rng.normal(size=40)
+        ql, qr = orc.recon_line(recon, q)
+        for c in range(3, 38):
+            lo, hi = min(q[c - 1], q[c]), max(q[c - 1], q[c])
+            assert lo - 1e-14 <= ql[c] <= hi + 1e-14
+            assert lo - 1e-14 <= qr[c] <= hi + 1e-14
+
+
+def test_ppm_monotone_data_stays_in_range(orc):
+    """PPM on monotone data (a step of random height on random monotone
+    increments) creates no value outside the range of its stencil, and the
+    states at a face are ordered like the data."""
+    rng = np.random.default_rng(17)
+    for _ in range(50):
+        inc = rng.exponential(size=40) * (rng.random(40) < 0.7)
+        inc[20] += 10.0 * rng.random()
+        q = np.cumsum(inc)
+        ql, qr = orc.recon_line("ppm", q)
+        for c in range(3, 38):
+            lo, hi = q[c - 3:c + 3].min(), q[c - 3:c + 3].max()
+            assert lo - 1e-13 <= ql[c] <= hi + 1e-13
+            assert lo - 1e-13 <= qr[c] <= hi + 1e-13
+
+
+def test_plm_slope_is_harmonic_mean(orc):
+    """van Leer (1974): the face value of cell c is q_c + d/2 with d the
+    harmonic mean 2ab/(a+b) of the one-sided differences when they share a
+    sign, else 0 (first order at extrema)."""
+    q = np.array([0, 0, 0, 1.0, 3.0, 4.0, 2.0, 2.5, 0, 0, 0])
+    ql, qr = orc.recon_line("plm", q)
+    # face between cells 4 and 5: left state = q4 + d4/2, d4 from (2, 1)
+    d4 = 2 * 2.0 * 1.0 / 3.0
+    assert abs(ql[5] - (3.0 + d4 / 2)) < 1e-15
+    # cell 5 is an extremum (1, -2): right state at face 4/5 is q5 itself
+    assert qr[5] == 4.0
+
+
+# ---------------------------------------------------------------------------
+# Time integrators (Sec. 3.2.3, Eq. (rk-2s))
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("integ,poly", [
+    ("rk1", lambda z: 1 + z),
+    ("vl2", lambda z: 1 + z + z * z / 2),
+    ("rk2", lambda z: 1 + z + z * z / 2),
+    ("rk3", lambda z: 1 + z + z * z / 2 + z ** 3 / 6),
+])
+def test_2s_stability_polynomial(orc, integ, poly):
+    """On u' = lambda u one step multiplies u by the stability polynomial of
+    the method: forward Euler, the two second-order two-stage methods, and
+    SSPRK(3,3)."""
+    for lam in (-1.3, 0.7 + 2.0j, -0.2 - 1.1j):
+        dt = 0.37
+        got = orc.drive_scalar(integ, complex(lam), dt, 1)
+        assert abs(got - poly(lam * dt)) < 1e-15 * max(1.0, abs(poly(lam * dt)))
+
+
+# ---------------------------------------------------------------------------
+# Whole step
+# ---------------------------------------------------------------------------
+COMBOS = [("rk1", "dc", "hlld"), ("vl2", "plm", "hlld"), ("vl2", "plm", "hlle"), ("rk2", "plm", "hlld"),
+          ("rk3", "ppm", "hlld"), ("rk3", "ppm", "hlle"), ("vl2", "ppm", "hlld")]
+
+
+@pytest.mark.parametrize("integ,recon,rs", COMBOS)
+def test_uniform_state_is_preserved_bitwise(orc, integ, recon, rs):
+    """P1: a uniform state is a steady solution; every flux and EMF is the same
+    on every face, so the update is exactly zero."""
+    ng = 3 if recon == "ppm" else 2
+    b = inputs.uniform(n=(6, 5, 4), ng=ng)
+    cfg = orc.cfg_for(b, integrator=integ, recon=recon, riemann=rs)
+    cons = orc.prim2cons(cfg, b.prim, b.bface)
+    c1, b1 = cons.copy(), b.bface.copy()
+    assert orc.step(cfg, c1, b1, 0.01) == 0
+    assert np.array_equal(c1, cons)
+    assert np.array_equal(b1, b.bface)
+
+
+def _totals(b, cons, bf):
+    a = b.active
+    g = b.ng
+    n1, n2, n3 = b.n
+    out = [cons[v][a].sum() for v in range(5)]
+    # magnetic flux through every x_d plane of faces
+    out.append(bf[0][g:g + n3, g:g + n2, g:g + n1].sum(axis=(0, 1)))
+    out.append(bf[1][g:g + n3, g:g + n2, g:g + n1].sum(axis=(0, 2)))
+    out.append(bf[2][g:g + n3, g:g + n2, g:g + n1].sum(axis=(1, 2)))
+    return out
+
+
+@pytest.mark.parametrize("integ,recon,rs", [("vl2", "plm", "hlld"), ("rk3", "ppm", "hlle")])
+def test_conservation_and_flux_invariants(orc, integ, recon, rs):
+    """P2: on a periodic block the flux divergence telescopes, so the totals of
+    mass, momentum and energy are constant; CT keeps the magnetic flux through
+    every plane of faces constant."""
+    ng = 3 if recon == "ppm" else 2
+    b = inputs.smooth_random(n=(12, 10, 8), seed=3, ng=ng)
+    cfg = orc.cfg_for(b, integrator=integ, recon=recon, riemann=rs)
+    cons = orc.prim2cons(cfg, b.prim, b.bface)
+    t0 = _totals(b, cons, b.bface)
+    c, bf, _, nst = orc.run(cfg, cons, b.bface, 6)
+    t1 = _totals(b, c, bf)
+    scale = [np.abs(cons[v][b.active]).sum() for v in range(5)]
+    for v in range(5):
+        assert abs(t1[v] - t0[v]) <= 1e-14 * scale[v] * math.sqrt(nst) * 10
+    for d in range(3):
+        assert np.max(np.abs(t1[5 + d] - t0[5 + d])) < 1e-13
+
+
+@pytest.mark.parametrize("integ,recon,rs", [("vl2", "plm", "hlld"), ("rk3", "ppm", "hlld")])
+def test_divb_preserved(orc, integ, recon, rs):
+    """P3: the vector-potential initial field is divergence free to round-off
+    and CT keeps it so (Sec. 2.1.2 / Sec. 3.1)."""
+    ng = 3 if recon == "ppm" else 2
+    b = inputs.smooth_random(n=(10, 12, 8), seed=4, ng=ng)
+    assert inputs.divb_metric(b.bface, b.n, b.ng, b.dx) < 1e-15 * 4
+    cfg = orc.cfg_for(b, integrator=integ, recon=recon, riemann=rs)
+    cons = orc.prim2cons(cfg, b.prim, b.bface)
+    c, bf, _, _ = orc.run(cfg, cons, b.bface, 8)
+    assert inputs.divb_metric(bf, b.n, b.ng, b.dx) < 1e-13
+
+
+def test_newdt_by_hand(orc):
+    """P10: dt = C0 min_d dx_d / (|v_d| + c_f,d) on a uniform state, computed
+    from the closed-form fast speed."""
+    v = (0.3, -0.8, 0.1)
+    B = (0.5, -0.4, 0.3)
+    rho, p = 1.2, 0.7
+    dx = (0.1, 0.07, 0.13)
+    b = inputs.uniform(n=(4, 4, 4), rho=rho, v=v, p=p, B=B, dx=dx)
+    cfg = orc.cfg_for(b, cfl=0.4)
+    cons = orc.prim2cons(cfg, b.prim, b.bface)
+    dt, bad = orc.newdt(cfg, cons, b.bface)
+    assert bad == 0
+    a2 = GAM * p / rho
+    b2 = sum(x * x for x in B) / rho
+    best = []
+    for d in range(3):
+        bd2 = B[d] ** 2 / rho
+        cf = math.sqrt(0.5 * ((a2 + b2) + math.sqrt((a2 + b2) ** 2 - 4 * a2 * bd2)))
+        best.append(dx[d] / (abs(v[d]) + cf))
+    assert abs(dt - 0.4 * min(best)) < 1e-15
+
+
+def _line_problem(n, axis, ng=2):
+    """A 1D Riemann-type problem (two smooth steps) along `axis`, with at most
+    two nonzero components of v and of B, on a block n x 4 x 4 (rotated)."""
+    x = (np.arange(n) + 0.5) / n
+    step = 0.5 * (1 + np.tanh((x - 0.3) / 0.05)) - 0.5 * (1 + np.tanh((x - 0.75) / 0.05))
+    rho = 1.0 + 0.8 * step
+    p = 1.0 - 0.5 * step
+    u = 0.2 - 0.3 * step      # velocity along the axis
+    vt = 0.1 * step           # first transverse component
+    bn = 0.75                 # normal field
+    bt = 1.0 - 1.5 * step     # first transverse field component
+    dims = [4, 4, 4]
+    dims[axis] = n
+    t1 = (axis + 1) % 3
+    N = [d + 2 * ng for d in dims]
+    prim = np.zeros((5, N[2], N[1], N[0]))
+    bf = np.zeros((3, N[2] + 1, N[1] + 1, N[0] + 1))
+
+    def along(arr, extra=0):
+        idx = np.mod(np.arange(n + 2 * ng + extra) - ng, n)
+        vals = arr[idx]
+        shape = [1, 1, 1]
+        shape[2 - axis] = len(vals)
+        return vals.reshape(shape)
+
+    def put(dst, vals):
+        dst[...] = np.broadcast_to(vals, dst.shape)
+
+    put(prim[0], along(rho))
+    put(prim[4], along(p))
+    put(prim[1 + axis], along(u))
+    put(prim[1 + t1], along(vt))
+    put(bf[axis], bn)
+    sub = [slice(None)] * 3
+    put(bf[t1], along(bt, extra=1))
+    return tuple(dims), prim, bf
+
+
+@pytest.mark.parametrize("integ,recon,rs", [("vl2", "plm", "hlld"), ("rk1", "dc", "hlle"), ("rk3", "ppm", "hlld")])
+def test_1d_problem_is_direction_independent(orc, integ, recon, rs):
+    """P6 (Sec. 3.3.3): the same 1D problem along x1, x2 and x3 gives the same
+    profiles.  With two nonzero components of v and B every sum in the method
+    has one exact zero, so the agreement is bitwise."""
+    ng = 3 if recon == "ppm" else 2
+    n = 24
+    outs = []
+    for axis in range(3):
+        dims, prim, bf = _line_problem(n, axis, ng)
+        cfg = orc.make_cfg(dims, ng, (1.0 / n,) * 3, GAM, recon=recon, riemann=rs, integrator=integ)
+        cons = orc.prim2cons(cfg, prim, bf)
+        c, b, _, _ = orc.run(cfg, cons, bf, 5, dt=0.004)
+        t1 = (axis + 1) % 3
+        s = [ng + 1] * 3
+        sl = [slice(ng + 1, ng + 2)] * 3
+        sl[2 - axis] = slice(ng, ng + n)
+        sl = tuple(sl)
+        prof = [c[0][sl].ravel(), c[1 + axis][sl].ravel(), c[1 + t1][sl].ravel(), c[4][sl].ravel(),
+                b[t1][sl].ravel()]
+        outs.append(np.stack(prof))
+    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[2])
+
+
+def test_1d_problem_matches_godunov_update(orc):
+    """P6: for a plane-parallel problem the corner EMFs reduce to the face EMFs
+    and the 3D step must equal the 1D conservative update
+    U_i - dt/dx (F_{i+1/2} - F_{i-1/2}) with the face fluxes of the Riemann
+    solver (forward Euler, donor cell), transverse B included."""
+    n, ng = 16, 2
+    dims, prim, bf = _line_problem(n, 0, ng)
+    dx = 1.0 / n
+    dt = 0.01
+    cfg = orc.make_cfg(dims, ng, (dx,) * 3, GAM, recon="dc", riemann="hlld", integrator="rk1")
+    cons = orc.prim2cons(cfg, prim, bf)
+    c, b = cons.copy(), bf.copy()
+    assert orc.step(cfg, c, b, dt) == 0
+    j = k = ng
+    # 1D data along x (with ghosts)
+    w = np.stack([prim[0][k, j], prim[1][k, j], prim[2][k, j], prim[3][k, j], prim[4][k, j],
+                  0.5 * (bf[1][k, j, :-1] + bf[1][k, j + 1, :-1]), 0.5 * (bf[2][k, j, :-1] + bf[2][k + 1, j, :-1])])
+    bn = bf[0][k, j]
+    F = np.zeros((7, n + 1))
+    for f in range(n + 1):
+        i = ng + f
+        F[:, f], _ = orc.riemann("hlld", GAM, w[:, i - 1], w[:, i], bn[i])
+    U = np.stack([cons[v][k, j, ng:ng + n] for v in range(5)])
+    expect = U - dt / dx * (F[:5, 1:] - F[:5, :-1])
+    got = np.stack([c[v][k, j, ng:ng + n] for v in range(5)])
+    assert rel(got, expect) < 1e-14
+    by_new = b[1][k, j, ng:ng + n]
+    by_old = bf[1][k, j, ng:ng + n]
+    assert rel(by_new, by_old - dt / dx * (F[5, 1:] - F[5, :-1])) < 1e-14
+
+
+def test_mirror_symmetry(orc):
+    """P14 (Sec. 3.3.5): a state symmetric under x -> -x stays symmetric.
+    Checked to round-off (the oracle is not written for bitwise symmetry).
+    On the symmetry planes the face mass flux is zero only up to round-off, so
+    the three-way sign switch of the CT upwinding would pick an arbitrary side
+    there (a 1e-4 effect here); the continuous weight (ct_eps > 0) is used."""
+    n, ng = 16, 2
+    b = inputs.smooth_random(n=(n, 8, 8), seed=5, ng=ng)
+    # symmetrise: cells i <-> n-1-i; rho, p, v2, v3, B2, B3 even; v1, B1 odd
+    g = ng
+    P = b.prim.copy()
+    act = slice(g, g + n)
+    for v in range(5):
+        a = P[v][:, :, act]
+        sgn = -1.0 if v == 1 else 1.0
+        P[v][:, :, act] = 0.5 * (a + sgn * a[:, :, ::-1])
+    bf = b.bface.copy()
+    f1 = bf[0][:, :, g:g + n + 1]
+    bf[0][:, :, g:g + n + 1] = 0.5 * (f1 - f1[:, :, ::-1])
+    for c in (1, 2):
+        a = bf[c][:, :, act]
+        bf[c][:, :, act] = 0.5 * (a + a[:, :, ::-1])
+    cfg = orc.cfg_for(b, ct_eps=1e-3)
+    orc.fill_ghosts(cfg, P, bf)  # ghosts of the symmetrised arrays
+    cons = orc.prim2cons(cfg, P, bf)
+    orc.fill_ghosts(cfg, cons, bf)
+    assert inputs.divb_metric(bf, b.n, b.ng, b.dx) < 1e-14
+    c, bb, _, _ = orc.run(cfg, cons, bf, 6, dt=0.003)
+    for v in range(5):
+        a = c[v][g:g + 8, g:g + 8, act]
+        sgn = -1.0 if v == 1 else 1.0
+        assert np.max(np.abs(a - sgn * a[:, :, ::-1])) < 1e-13
+    f1 = bb[0][g:g + 8, g:g + 8, g:g + n + 1]
+    assert np.max(np.abs(f1 + f1[:, :, ::-1])) < 1e-13
+
+
+def test_positivity_vl2_dc(orc):
+    """P9 (Sec. 3.2.3): VL2 with donor-cell fluxes in both stages is positive
+    for C0 <= 1/3.  Strong blast (pressure ratio 1e3, ambient plasma beta 0.2)
+    with dt from newdt.  (At beta ~ 0.02 the pressure recovered from the total
+    energy can still go negative: the cell-centred magnetic energy is not a
+    conserved quantity of the CT scheme, which the positivity statement does
+    not cover.)"""
+    b = inputs.blast(n=24, seed=2, ng=2, p_amb=0.1, p_in=100.0, radius=0.2)
+    cfg = orc.cfg_for(b, integrator="vl2", recon="dc", riemann="hlld", cfl=1.0 / 3.0)
+    cons = orc.prim2cons(cfg, b.prim, b.bface)
+    c, bf = cons, b.bface
+    for _ in range(15):
+        c, bf, _, _ = orc.run(cfg, c, bf, 1)
+        prim, _, bad = orc.cons2prim(cfg, c, bf)
+        assert bad == 0
+        assert prim[0].min() > 0 and prim[4].min() > 0
+
+
+def test_ct_ramp_limit_is_switch(orc):
+    """P11: the continuous CT weight tends to the sign switch as its width goes
+    to zero."""
+    b = inputs.smooth_random(n=(10, 10, 10), seed=6)
+    out = []
+    for eps in (0.0, 1e-13):
+        cfg = orc.cfg_for(b, ct_eps=eps)
+        cons = orc.prim2cons(cfg, b.prim, b.bface)
+        c, bf, _, _ = orc.run(cfg, cons, b.bface, 3, dt=0.01)
+        out.append((c, bf))
+    assert rel(out[1][0], out[0][0]) < 1e-14
+    assert rel(out[1][1], out[0][1]) < 1e-14
+
+
+def test_linear_wave_eigenvector(orc):
+    """Sec. 3.3.1 set-up: the perturbation of the linear-wave generator is a
+    right eigenvector of the flux Jacobian along the wave normal with
+    eigenvalue c_f = 2 (Jacobian from the exact flux by central differences)."""
+    p0 = 1.0 / GAM
+    bx, by, bz = 1.0, math.sqrt(2.0), 0.5
+    w0 = np.array([1.0, 0, 0, 0, p0, by, bz])
+    U0 = exact_cons(w0, bx)
+
+    def F_of_U(U):
+        rho, mx, my, mz, E, b1, b2 = U
+        u, v, w = mx / rho, my / rho, mz / rho
+        p = (GAM - 1) * (E - 0.5 * rho * (u * u + v * v + w * w) - 0.5 * (bx * bx + b1 * b1 + b2 * b2))
+        return exact_flux(np.array([rho, u, v, w, p, b1, b2]), bx)
+
+    J = np.zeros((7, 7))
+    h = 1e-6
+    for c in range(7):
+        e = np.zeros(7)
+        e[c] = h
+        J[:, c] = (F_of_U(U0 + e) - F_of_U(U0 - e)) / (2 * h)
+    r2 = math.sqrt(2.0)
+    R = np.array([1.0, 2.0, -2 * r2 / 3, -1.0 / 3, 4.5, 4 * r2 / 3, 2.0 / 3])
+    assert np.max(np.abs(J @ R - 2.0 * R)) < 1e-8
+    # and the generator uses exactly this background and normal direction
+    blk = inputs.linear_wave(8)
+    assert blk.meta["fast_speed"] == 2.0
+    assert inputs.divb_metric(blk.bface, blk.n, blk.ng, blk.dx) < 1e-14
+
+
+def _wave_error(orc, N, **kw):
+    b = inputs.linear_wave(N)
+    cfg = orc.cfg_for(b, **kw)
+    c, bf, t, _ = orc.run(cfg, b.cons, b.bface, 0, t_end=0.5)
+    a = b.active
+    _, bcc0, _ = orc.cons2prim(cfg, b.cons, b.bface)
+    _, bcc1, _ = orc.cons2prim(cfg, c, bf)
+    # Eq. (RMS-error): RMS over variables of the volume-weighted L1 norms
+    e = [np.mean(np.abs(c[v][a] - b.cons[v][a])) for v in range(5)]
+    e += [np.mean(np.abs(bcc1[v][a] - bcc0[v][a])) for v in range(3)]
+    return math.sqrt(sum(x * x for x in e))
+
+
+def test_linear_wave_convergence_rk3_ppm(orc):
+    """P4 (Sec. 3.3.1): after one period the fast wave returns to its initial
+    state; with RK3+PPM+HLLD the error falls at least ~4x per doubling of N
+    (second order) and is far below the VL2+PLM error at equal N."""
+    e16 = _wave_error(orc, 16, integrator="rk3", recon="ppm")
+    e32 = _wave_error(orc, 32, integrator="rk3", recon="ppm")
+    assert math.log2(e16 / e32) > 1.9
+    ev = _wave_error(orc, 16, integrator="vl2", recon="plm")
+    assert e16 < 0.2 * ev
+
+
+@pytest.mark.slow
+def test_linear_wave_convergence_vl2_plm(orc):
+    """P4 (Sec. 3.3.1): VL2+PLM+HLLD converges at second order (measured from
+    N=32 to N=64; at N=16 the van Leer limiter is not yet asymptotic)."""
+    e32 = _wave_error(orc, 32, integrator="vl2", recon="plm")
+    e64 = _wave_error(orc, 64, integrator="vl2", recon="plm")
+    assert math.log2(e32 / e64) > 1.9
