@@ -1,0 +1,126 @@
+/*
+ * athmhd.h -- C ABI of libathmhd.so, an MI355X (gfx950) implementation of the
+ * unsplit finite-volume ideal-MHD update of Stone, Tomida, White & Felker
+ * (2020), Section 3: primitive reconstruction (DC / PLM / PPM, Sec. 3.2.1),
+ * HLLE / HLLD fluxes (Sec. 3.2.2), upwind constrained-transport corner EMFs
+ * (Sec. 3.1), and the conservative plus face-field update inside the 2S
+ * Runge-Kutta / VL2 integrators (Sec. 3.2.3, Eq. (rk-2s)), all in FP64.
+ *
+ * Problem solved by one step (Sec. 3.1, Eqs. (cons) and (total_energy) with
+ * Pi = eta = eta_AD = Q = 0 and mu = 1): given volume-averaged conserved
+ * variables U = (rho, rho v, E) with E = P/(gamma-1) + rho v^2/2 + B^2/2 and
+ * face-area-averaged B on a uniform Cartesian MeshBlock, advance the ideal-MHD
+ * conservation laws by dt so that the totals of U are conserved on a periodic
+ * block and the discrete div B is unchanged.
+ *
+ * Memory layout (all arrays FP64, device memory, owned by the caller):
+ *   N_d = n_d + 2*nghost (ghost layers on both sides, Sec. 2.1.1).
+ *   cons  : [b][v][k][j][i], v in (rho, M1, M2, M3, E); shape per block
+ *           5 x N3 x N2 x N1, i fastest.  Blocks are contiguous.
+ *   bface : [b][c][k][j][i], shape per block 3 x (N3+1) x (N2+1) x (N1+1);
+ *           component c at index (k,j,i) is the face on the lower side of cell
+ *           (k,j,i) along direction c (B1 at x1-faces, B2 at x2-faces, B3 at
+ *           x3-faces, padded to a common shape).
+ *   prim  : same shape as cons, v in (rho, v1, v2, v3, P).
+ * Every block is its own periodic neighbour: ghost cells and the boundary
+ * faces n_d+nghost are periodic images, filled by the library.
+ *
+ * Streams: every call that takes `stream` (a hipStream_t, NULL = default
+ * stream) is asynchronous on it unless stated otherwise.
+ *
+ * Errors: every function returns ATHMHD_OK (0) or a negative code.  Argument
+ * errors are detected on the host before any HIP call.  Asynchronous HIP errors
+ * and non-physical cells met by a step (rho <= 0, P <= 0 or not finite; no
+ * floors are applied) surface at the next athmhd_newdt.  athmhd_last_error
+ * returns a text description of the last failure of a handle.
+ */
+#ifndef ATHMHD_H
+#define ATHMHD_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define ATHMHD_API __attribute__((visibility("default")))
+#else
+#define ATHMHD_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct athmhd_s* athmhd_t;
+
+enum athmhd_status {
+  ATHMHD_OK = 0,
+  ATHMHD_EINVAL = -1,   /* bad argument or configuration                      */
+  ATHMHD_ENOMEM = -2,   /* device allocation failed                            */
+  ATHMHD_EHIP = -3,     /* a HIP runtime call failed                           */
+  ATHMHD_ENONPHYS = -4, /* a step met rho <= 0, P <= 0 or a non-finite value   */
+  ATHMHD_EUNSUP = -5    /* valid but not supported combination                 */
+};
+
+/* Reconstruction (Sec. 3.2.1).  The VL2 predictor always uses DC. */
+enum { ATHMHD_RECON_DC = 0, ATHMHD_RECON_PLM = 1, ATHMHD_RECON_PPM = 2 };
+/* Riemann solver (Sec. 3.2.2). */
+enum { ATHMHD_RS_HLLE = 0, ATHMHD_RS_HLLD = 1 };
+/* Time integrator (Sec. 3.2.3). */
+enum { ATHMHD_RK1 = 0, ATHMHD_VL2 = 1, ATHMHD_RK2 = 2, ATHMHD_RK3 = 3 };
+
+typedef struct {
+  int32_t n1, n2, n3;      /* active cells per block, >= 2 each                    */
+  int32_t nghost;          /* >= 2 for DC/PLM, >= 3 for PPM (Sec. 2.1.1)           */
+  double gamma;            /* adiabatic index, > 1 (Sec. 3.1)                      */
+  double dx1, dx2, dx3;    /* uniform Cartesian cell widths, > 0                   */
+  int32_t recon;           /* ATHMHD_RECON_*                                       */
+  int32_t riemann;         /* ATHMHD_RS_*                                          */
+  int32_t integrator;      /* ATHMHD_RK1 / VL2 / RK2 / RK3                         */
+  int32_t reserved;        /* must be 0                                            */
+  double cfl;              /* Courant number C0 for athmhd_newdt, in (0, 1]        */
+  double ct_eps;           /* 0: CT upwinding by the sign of the face mass flux    */
+                           /* (Gardiner & Stone 2005); > 0: continuous weight      */
+                           /* clamp(1/2 + (F_rho/rho_bar)/(2 ct_eps c_max), 0, 1)  */
+} athmhd_config;
+
+/* Version of this ABI (major*100 + minor). */
+ATHMHD_API int athmhd_version(void);
+
+/* Validate `cfg` on the host, then allocate the stage registers and scratch of
+ * one block on the current device.  nblocks_max identical blocks may later be
+ * advanced together (each periodic on its own).  On success *out receives a
+ * handle owned by the caller (free with athmhd_destroy). */
+ATHMHD_API int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out);
+
+/* One full time step of nblocks (<= nblocks_max) blocks, in place:
+ * (cons, bface) hold U^n on entry and U^{n+1} on return, ghosts filled.
+ * dt > 0 and finite.  Asynchronous on `stream`. */
+ATHMHD_API int athmhd_step(athmhd_t h, double* cons, double* bface, double dt, int nblocks, void* stream);
+
+/* Global time step dt = cfl * min over active cells and directions of
+ * dx_d / (|v_d| + c_f,d) (Sec. 2.1.6, Sec. 3.2.3), written to *dt_host.
+ * Synchronises `stream`.  Returns ATHMHD_ENONPHYS if this state or any step
+ * since the previous call met a non-physical cell (the flag is then cleared),
+ * ATHMHD_EHIP if an asynchronous HIP error is pending. */
+ATHMHD_API int athmhd_newdt(athmhd_t h, const double* cons, const double* bface, int nblocks, double* dt_host,
+                 void* stream);
+
+/* cons <- conserved variables of (prim, bface) on every stored cell, using the
+ * cell-centred field (mean of the two bounding faces).  Asynchronous. */
+ATHMHD_API int athmhd_prim2cons(athmhd_t h, const double* prim, const double* bface, double* cons, int nblocks,
+                     void* stream);
+
+/* Fill the ghost cells and periodic image faces of (cons, bface). */
+ATHMHD_API int athmhd_fill_ghosts(athmhd_t h, double* cons, double* bface, int nblocks, void* stream);
+
+/* Text of the last error recorded on `h` (or of the last failed create when
+ * h is NULL).  Valid until the next call on the same handle. */
+ATHMHD_API const char* athmhd_last_error(athmhd_t h);
+
+/* Release the handle and its device memory (synchronises the device). */
+ATHMHD_API void athmhd_destroy(athmhd_t h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ATHMHD_H */

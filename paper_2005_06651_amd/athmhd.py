@@ -1,0 +1,170 @@
+"""Thin ctypes binding of libathmhd.so (argument marshalling only).
+
+Every step of the method runs in the HIP kernels of the library; this module
+only turns torch tensors (device memory, float64, contiguous) into pointers and
+the current torch stream into a hipStream_t.  There is no fallback: if the
+library is missing or the device is not a HIP GPU, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libathmhd.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENONPHYS, EUNSUP = 0, -1, -2, -3, -4, -5
+RECON = {"dc": 0, "plm": 1, "ppm": 2}
+RIEMANN = {"hlle": 0, "hlld": 1}
+INTEGRATOR = {"rk1": 0, "vl2": 1, "rk2": 2, "rk3": 3}
+EXPORTED = ["athmhd_version", "athmhd_create", "athmhd_step", "athmhd_newdt", "athmhd_prim2cons",
+            "athmhd_fill_ghosts", "athmhd_last_error", "athmhd_destroy"]
+
+
+class AthmhdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"athmhd error {code}: {msg}")
+        self.code = code
+
+
+class NonPhysicalState(AthmhdError):
+    pass
+
+
+class Config(C.Structure):
+    """Mirror of athmhd_config (include/athmhd.h)."""
+    _fields_ = [("n1", C.c_int32), ("n2", C.c_int32), ("n3", C.c_int32), ("nghost", C.c_int32),
+                ("gamma", C.c_double), ("dx1", C.c_double), ("dx2", C.c_double), ("dx3", C.c_double),
+                ("recon", C.c_int32), ("riemann", C.c_int32), ("integrator", C.c_int32),
+                ("reserved", C.c_int32), ("cfl", C.c_double), ("ct_eps", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libathmhd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2005_06651_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.athmhd_version.restype = C.c_int
+        L.athmhd_create.argtypes = [C.POINTER(Config), C.c_int, C.POINTER(vp)]
+        L.athmhd_step.argtypes = [vp, vp, vp, C.c_double, C.c_int, vp]
+        L.athmhd_newdt.argtypes = [vp, vp, vp, C.c_int, C.POINTER(C.c_double), vp]
+        L.athmhd_prim2cons.argtypes = [vp, vp, vp, vp, C.c_int, vp]
+        L.athmhd_fill_ghosts.argtypes = [vp, vp, vp, C.c_int, vp]
+        L.athmhd_last_error.argtypes = [vp]
+        L.athmhd_last_error.restype = C.c_char_p
+        L.athmhd_destroy.argtypes = [vp]
+        L.athmhd_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def make_config(n, nghost, dx, gamma, recon="plm", riemann="hlld", integrator="vl2", cfl=0.3,
+                ct_eps=0.0) -> Config:
+    return Config(int(n[0]), int(n[1]), int(n[2]), int(nghost), float(gamma), float(dx[0]), float(dx[1]),
+                  float(dx[2]), RECON[recon], RIEMANN[riemann], INTEGRATOR[integrator], 0, float(cfl),
+                  float(ct_eps))
+
+
+def _check(rc: int, h) -> None:
+    if rc != OK:
+        msg = lib().athmhd_last_error(h).decode(errors="replace")
+        raise (NonPhysicalState if rc == ENONPHYS else AthmhdError)(rc, msg)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Solver:
+    """One handle of the library: nblocks identical periodic MeshBlocks.
+
+    Tensors: cons (nb, 5, N3, N2, N1) and bface (nb, 3, N3+1, N2+1, N1+1),
+    float64, contiguous, on the current HIP device (leading nb axis optional
+    when nb == 1)."""
+
+    def __init__(self, n, nghost, dx, gamma, recon="plm", riemann="hlld", integrator="vl2", cfl=0.3,
+                 ct_eps=0.0, nblocks=1):
+        self.n = tuple(int(x) for x in n)
+        self.ng = int(nghost)
+        self.nblocks = int(nblocks)
+        self.cfg = make_config(n, nghost, dx, gamma, recon, riemann, integrator, cfl, ct_eps)
+        h = C.c_void_p()
+        rc = lib().athmhd_create(C.byref(self.cfg), self.nblocks, C.byref(h))
+        if rc != OK:
+            raise AthmhdError(rc, lib().athmhd_last_error(None).decode(errors="replace"))
+        self._h = h
+
+    @property
+    def cell_shape(self):
+        n1, n2, n3 = self.n
+        g = self.ng
+        return (n3 + 2 * g, n2 + 2 * g, n1 + 2 * g)
+
+    @property
+    def face_shape(self):
+        return tuple(x + 1 for x in self.cell_shape)
+
+    def _arr(self, t, nvar, shape):
+        import torch
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+            raise TypeError("expected a float64 tensor in HIP device memory")
+        if not t.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        sh = tuple(t.shape)
+        if sh == (nvar,) + shape:
+            nb = 1
+        elif len(sh) == 5 and sh[1:] == (nvar,) + shape:
+            nb = sh[0]
+        else:
+            raise ValueError(f"bad shape {sh}, expected (nb, {nvar}) + {shape}")
+        return C.c_void_p(t.data_ptr()), nb
+
+    def _pair(self, cons, bface):
+        pc, nb = self._arr(cons, 5, self.cell_shape)
+        pb, nb2 = self._arr(bface, 3, self.face_shape)
+        if nb != nb2:
+            raise ValueError("cons and bface hold different block counts")
+        return pc, pb, nb
+
+    def step(self, cons, bface, dt: float, stream=None) -> None:
+        pc, pb, nb = self._pair(cons, bface)
+        _check(lib().athmhd_step(self._h, pc, pb, float(dt), nb, _stream(stream)), self._h)
+
+    def newdt(self, cons, bface, stream=None) -> float:
+        pc, pb, nb = self._pair(cons, bface)
+        out = C.c_double()
+        _check(lib().athmhd_newdt(self._h, pc, pb, nb, C.byref(out), _stream(stream)), self._h)
+        return out.value
+
+    def prim2cons(self, prim, bface, out=None, stream=None):
+        import torch
+        pp, pb, nb = self._pair(prim, bface)
+        if out is None:
+            out = torch.empty_like(prim)
+        po, _ = self._arr(out, 5, self.cell_shape)
+        _check(lib().athmhd_prim2cons(self._h, pp, pb, po, nb, _stream(stream)), self._h)
+        return out
+
+    def fill_ghosts(self, cons, bface, stream=None) -> None:
+        pc, pb, nb = self._pair(cons, bface)
+        _check(lib().athmhd_fill_ghosts(self._h, pc, pb, nb, _stream(stream)), self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().athmhd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

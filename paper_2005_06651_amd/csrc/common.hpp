@@ -1,0 +1,54 @@
+// common.hpp -- block geometry, launch helpers and kernel entry points shared
+// by the host ABI and the HIP kernels of libathmhd.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace athmhd {
+
+// Geometry of one MeshBlock as stored: n_d active cells, ng ghost layers on
+// each side (Sec. 2.1.1), N_d = n_d + 2 ng stored cells, face arrays padded to
+// N_d + 1 in every direction.  i (direction 1) is fastest.
+struct Geo {
+  int n1, n2, n3, ng;
+  int N1, N2, N3;
+  int F1, F2, F3;
+  int64_t cvar;    // cells per variable (stride between cell arrays)
+  int64_t fvar;    // faces per component (stride between face arrays)
+  int64_t cblock;  // 5 * cvar: stride between blocks in cons
+  int64_t fblock;  // 3 * fvar: stride between blocks in bface
+  double dx1, dx2, dx3;
+
+  __host__ __device__ __forceinline__ int c(int i, int j, int k) const { return (k * N2 + j) * N1 + i; }
+  __host__ __device__ __forceinline__ int f(int i, int j, int k) const { return (k * F2 + j) * F1 + i; }
+};
+
+inline Geo make_geo(int n1, int n2, int n3, int ng, double dx1, double dx2, double dx3) {
+  Geo g;
+  g.n1 = n1; g.n2 = n2; g.n3 = n3; g.ng = ng;
+  g.N1 = n1 + 2 * ng; g.N2 = n2 + 2 * ng; g.N3 = n3 + 2 * ng;
+  g.F1 = g.N1 + 1; g.F2 = g.N2 + 1; g.F3 = g.N3 + 1;
+  g.cvar = (int64_t)g.N1 * g.N2 * g.N3;
+  g.fvar = (int64_t)g.F1 * g.F2 * g.F3;
+  g.cblock = 5 * g.cvar;
+  g.fblock = 3 * g.fvar;
+  g.dx1 = dx1; g.dx2 = dx2; g.dx3 = dx3;
+  return g;
+}
+
+// Coefficients of one stage of the 2S scheme (Eq. (rk-2s)):
+//   out = g0 * x + g1 * un + beta * dt * L(x)
+struct StageCoef {
+  double g0, g1, bdt;
+};
+
+// Periodic image of a stored index along a direction with n active cells.
+__host__ __device__ __forceinline__ int wrap_index(int idx, int n, int ng) {
+  int r = (idx - ng) % n;
+  if (r < 0) r += n;
+  return ng + r;
+}
+
+}  // namespace athmhd

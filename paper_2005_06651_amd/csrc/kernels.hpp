@@ -1,0 +1,38 @@
+// kernels.hpp -- host-side launchers of the HIP kernels (defined in the .hip
+// files).  All launchers are asynchronous on `s` and return the launch status.
+#pragma once
+
+#include "common.hpp"
+
+namespace athmhd {
+
+struct Gas;
+
+// Scratch of the unfused pipeline for nb blocks: cell primitives (8 arrays:
+// rho, v1, v2, v3, p, B1cc, B2cc, B3cc), per-direction face data (8 arrays:
+// 5 fluxes, EMF of component t1, EMF of component t2, upwind weight) and the
+// three corner-EMF arrays.
+struct UnfusedScratch {
+  double* w;       // nb * 8 * cvar
+  double* face[3]; // nb * 8 * fvar each
+  double* edge;    // nb * 3 * fvar
+};
+
+hipError_t launch_fill_ghosts(const Geo& g, double* cons, double* bface, int nb, hipStream_t s);
+hipError_t launch_prim2cons(const Geo& g, double gamma, const double* prim, const double* bface, double* cons,
+                            int nb, hipStream_t s);
+// dt_bits: device uint64 holding the bit pattern of the running minimum of
+// dx_d/(|v_d| + c_f) (initialise to +inf bits); bad: device int counter
+hipError_t launch_newdt(const Geo& g, double gamma, const double* cons, const double* bface, int nb,
+                        unsigned long long* dt_bits, int* bad, hipStream_t s);
+
+// One stage of the unfused pipeline: out = g0*x + g1*un + bdt * L(x), where
+// x must have filled ghosts.  out must not alias x; un may alias out.
+hipError_t launch_stage_unfused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
+                                const double* xb, const double* unc, const double* unb, double* outc,
+                                double* outb, StageCoef coef, int nb, UnfusedScratch& scr, int* bad,
+                                hipStream_t s);
+
+hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
+
+}  // namespace athmhd

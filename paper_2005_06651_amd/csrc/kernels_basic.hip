@@ -1,0 +1,144 @@
+// kernels_basic.hip -- ghost fill, prim->cons, CFL time step and copy kernels.
+#include <cfloat>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "mhd_math.hpp"
+
+namespace athmhd {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline unsigned grid_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+// Ghost cells and the periodic image faces (Sec. 2.1.1; a periodic block is
+// its own neighbour).  One thread per entry of the padded face grid; threads
+// on active entries exit.
+__global__ void __launch_bounds__(kThreads) k_fill_ghosts(Geo g, double* __restrict__ cons,
+                                                         double* __restrict__ bface) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= g.fvar) return;
+  const int i = (int)(t % g.F1);
+  const int r = (int)(t / g.F1);
+  const int j = r % g.F2, k = r / g.F2;
+  const int ii = wrap_index(i, g.n1, g.ng), jj = wrap_index(j, g.n2, g.ng), kk = wrap_index(k, g.n3, g.ng);
+  if (ii == i && jj == j && kk == k) return;
+  double* cb = cons + blockIdx.y * g.cblock;
+  double* fb = bface + blockIdx.y * g.fblock;
+  if (i < g.N1 && j < g.N2 && k < g.N3) {
+    const int d = g.c(i, j, k), s = g.c(ii, jj, kk);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) cb[v * g.cvar + d] = cb[v * g.cvar + s];
+  }
+  const int d = g.f(i, j, k), s = g.f(ii, jj, kk);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) fb[c * g.fvar + d] = fb[c * g.fvar + s];
+}
+
+// Conserved variables from primitives with the cell-centred field (mean of the
+// two bounding faces), Eq. (total_energy) with P = (gamma-1) e.
+__global__ void __launch_bounds__(kThreads) k_prim2cons(Geo g, double gamma, const double* __restrict__ prim,
+                                                       const double* __restrict__ bface,
+                                                       double* __restrict__ cons) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= g.cvar) return;
+  const int i = (int)(t % g.N1);
+  const int r = (int)(t / g.N1);
+  const int j = r % g.N2, k = r / g.N2;
+  const double* w = prim + blockIdx.y * g.cblock;
+  const double* fb = bface + blockIdx.y * g.fblock;
+  double* u = cons + blockIdx.y * g.cblock;
+  const double b1 = 0.5 * (fb[g.f(i, j, k)] + fb[g.f(i + 1, j, k)]);
+  const double b2 = 0.5 * (fb[g.fvar + g.f(i, j, k)] + fb[g.fvar + g.f(i, j + 1, k)]);
+  const double b3 = 0.5 * (fb[2 * g.fvar + g.f(i, j, k)] + fb[2 * g.fvar + g.f(i, j, k + 1)]);
+  const double rho = w[t], v1 = w[g.cvar + t], v2 = w[2 * g.cvar + t], v3 = w[3 * g.cvar + t];
+  const double p = w[4 * g.cvar + t];
+  u[t] = rho;
+  u[g.cvar + t] = rho * v1;
+  u[2 * g.cvar + t] = rho * v2;
+  u[3 * g.cvar + t] = rho * v3;
+  u[4 * g.cvar + t] = p / (gamma - 1.0) + 0.5 * rho * (v1 * v1 + v2 * v2 + v3 * v3) + 0.5 * (b1 * b1 + b2 * b2 + b3 * b3);
+}
+
+// Smallest dx_d / (|v_d| + c_f,d) over the active cells (Sec. 2.1.6, Sec. 3.2.3).
+// Wavefront min by cross-lane shuffles, then LDS across the workgroup, then one
+// atomicMin on the bit pattern (non-negative doubles order like their bits).
+__global__ void __launch_bounds__(kThreads) k_newdt(Geo g, double gamma, const double* __restrict__ cons,
+                                                   const double* __restrict__ bface,
+                                                   unsigned long long* __restrict__ dt_bits,
+                                                   int* __restrict__ bad) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t nact = (int64_t)g.n1 * g.n2 * g.n3;
+  double best = DBL_MAX;
+  if (t < nact) {
+    const int i = g.ng + (int)(t % g.n1);
+    const int r = (int)(t / g.n1);
+    const int j = g.ng + r % g.n2, k = g.ng + r / g.n2;
+    const double* u = cons + blockIdx.y * g.cblock;
+    const double* fb = bface + blockIdx.y * g.fblock;
+    const int q = g.c(i, j, k);
+    const double b1 = 0.5 * (fb[g.f(i, j, k)] + fb[g.f(i + 1, j, k)]);
+    const double b2 = 0.5 * (fb[g.fvar + g.f(i, j, k)] + fb[g.fvar + g.f(i, j + 1, k)]);
+    const double b3 = 0.5 * (fb[2 * g.fvar + g.f(i, j, k)] + fb[2 * g.fvar + g.f(i, j, k + 1)]);
+    const double rho = u[q], ir = 1.0 / rho;
+    const double v1 = u[g.cvar + q] * ir, v2 = u[2 * g.cvar + q] * ir, v3 = u[3 * g.cvar + q] * ir;
+    const double p = (gamma - 1.0) * (u[4 * g.cvar + q] - 0.5 * rho * (v1 * v1 + v2 * v2 + v3 * v3) -
+                                      0.5 * (b1 * b1 + b2 * b2 + b3 * b3));
+    const double bs1 = b1 * b1, bs2 = b2 * b2, bs3 = b3 * b3;
+    const double c1 = fast_speed(ir, p, bs1, bs2 + bs3, gamma);
+    const double c2 = fast_speed(ir, p, bs2, bs3 + bs1, gamma);
+    const double c3 = fast_speed(ir, p, bs3, bs1 + bs2, gamma);
+    const double d = fmin(g.dx1 / (fabs(v1) + c1), fmin(g.dx2 / (fabs(v2) + c2), g.dx3 / (fabs(v3) + c3)));
+    if (!(rho > 0.0) || !(p > 0.0) || !(d > 0.0) || !(d < DBL_MAX)) {
+      atomicAdd(bad, 1);
+    } else {
+      best = d;
+    }
+  }
+  // wavefront minimum
+  for (int off = 32; off > 0; off >>= 1) best = fmin(best, __shfl_xor(best, off, 64));
+  __shared__ double part[kThreads / 64];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = part[0];
+    for (int w = 1; w < kThreads / 64; ++w) m = fmin(m, part[w]);
+    if (m < DBL_MAX) atomicMin(dt_bits, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_copy(double* __restrict__ dst, const double* __restrict__ src,
+                                                  int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t < n) dst[t] = src[t];
+}
+
+}  // namespace
+
+hipError_t launch_fill_ghosts(const Geo& g, double* cons, double* bface, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_ghosts, dim3(grid_for(g.fvar), nb), dim3(kThreads), 0, s, g, cons, bface);
+  return hipGetLastError();
+}
+
+hipError_t launch_prim2cons(const Geo& g, double gamma, const double* prim, const double* bface, double* cons,
+                            int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_prim2cons, dim3(grid_for(g.cvar), nb), dim3(kThreads), 0, s, g, gamma, prim, bface, cons);
+  return hipGetLastError();
+}
+
+hipError_t launch_newdt(const Geo& g, double gamma, const double* cons, const double* bface, int nb,
+                        unsigned long long* dt_bits, int* bad, hipStream_t s) {
+  const int64_t nact = (int64_t)g.n1 * g.n2 * g.n3;
+  hipLaunchKernelGGL(k_newdt, dim3(grid_for(nact), nb), dim3(kThreads), 0, s, g, gamma, cons, bface, dt_bits,
+                     bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(kThreads), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+
+}  // namespace athmhd

@@ -1,0 +1,246 @@
+// kernels_unfused.hip -- one stage of the MHD update as a pipeline of simple
+// kernels that exchange data through HBM: primitives, face fluxes per
+// direction, corner EMFs, update.  It is the straightforward reading of the
+// method (Sec. 3.2: reconstruct -> Riemann solve -> CT -> integrate) and the
+// reference point for the fused kernel.
+#include "common.hpp"
+#include "kernels.hpp"
+#include "mhd_math.hpp"
+
+namespace athmhd {
+
+namespace {
+
+constexpr int kThreads = 256;
+inline unsigned grid_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+// cons -> prim on every stored cell; 8 output arrays (rho, v1..3, P, B1..3 cc)
+__global__ void __launch_bounds__(kThreads) k_prim(Geo g, double gamma, const double* __restrict__ cons,
+                                                  const double* __restrict__ bface, double* __restrict__ w,
+                                                  int* __restrict__ bad) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= g.cvar) return;
+  const int i = (int)(t % g.N1);
+  const int r = (int)(t / g.N1);
+  const int j = r % g.N2, k = r / g.N2;
+  const double* u = cons + blockIdx.y * g.cblock;
+  const double* fb = bface + blockIdx.y * g.fblock;
+  double* wb = w + blockIdx.y * 8 * g.cvar;
+  const double b1 = 0.5 * (fb[g.f(i, j, k)] + fb[g.f(i + 1, j, k)]);
+  const double b2 = 0.5 * (fb[g.fvar + g.f(i, j, k)] + fb[g.fvar + g.f(i, j + 1, k)]);
+  const double b3 = 0.5 * (fb[2 * g.fvar + g.f(i, j, k)] + fb[2 * g.fvar + g.f(i, j, k + 1)]);
+  const double rho = u[t], ir = 1.0 / rho;
+  const double v1 = u[g.cvar + t] * ir, v2 = u[2 * g.cvar + t] * ir, v3 = u[3 * g.cvar + t] * ir;
+  const double p = (gamma - 1.0) * (u[4 * g.cvar + t] - 0.5 * rho * (v1 * v1 + v2 * v2 + v3 * v3) -
+                                    0.5 * (b1 * b1 + b2 * b2 + b3 * b3));
+  wb[t] = rho;
+  wb[g.cvar + t] = v1;
+  wb[2 * g.cvar + t] = v2;
+  wb[3 * g.cvar + t] = v3;
+  wb[4 * g.cvar + t] = p;
+  wb[5 * g.cvar + t] = b1;
+  wb[6 * g.cvar + t] = b2;
+  wb[7 * g.cvar + t] = b3;
+  if (!(rho > 0.0) || !(p > 0.0)) atomicAdd(bad, 1);
+}
+
+template <int RECON>
+__device__ __forceinline__ void recon_pair(const double* __restrict__ q, int s, double& ql, double& qr) {
+  // q points at cell c (the face is c-1/2), s is the stride along the direction
+  if (RECON == 0) {
+    ql = q[-s];
+    qr = q[0];
+  } else if (RECON == 1) {
+    const double a = q[-2 * s], b = q[-s], c = q[0], d = q[s];
+    ql = b + 0.5 * vl_slope(a, b, c);
+    qr = c - 0.5 * vl_slope(b, c, d);
+  } else {
+    const double a = q[-3 * s], b = q[-2 * s], c = q[-s], d = q[0], e = q[s], f = q[2 * s];
+    const double f0 = ppm_face(a, b, c, d);  // face between b and c
+    const double f1 = ppm_face(b, c, d, e);  // face between c and d (this face)
+    const double f2 = ppm_face(c, d, e, f);  // face between d and e
+    double lm = f0, lp = f1;
+    ppm_cell(a, b, c, d, e, lm, lp);  // cell c-1
+    double rm = f1, rp = f2;
+    ppm_cell(b, c, d, e, f, rm, rp);  // cell c
+    ql = lp;
+    qr = rm;
+  }
+}
+
+// Fluxes through the faces normal to D: normal index [ng, ng+n_D], transverse
+// indices [ng-1, ng+n_t] (one extra ring for the corner EMFs).
+template <int D, int RECON, int RS>
+__global__ void __launch_bounds__(kThreads) k_flux(Geo g, Gas gas, double ct_eps, const double* __restrict__ w,
+                                                  const double* __restrict__ bface, double* __restrict__ fo) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  const int e1 = D == 0 ? g.n1 + 1 : g.n1 + 2;
+  const int e2 = D == 1 ? g.n2 + 1 : g.n2 + 2;
+  const int e3 = D == 2 ? g.n3 + 1 : g.n3 + 2;
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= (int64_t)e1 * e2 * e3) return;
+  const int i = (int)(t % e1) + (D == 0 ? g.ng : g.ng - 1);
+  const int r = (int)(t / e1);
+  const int j = r % e2 + (D == 1 ? g.ng : g.ng - 1);
+  const int k = r / e2 + (D == 2 ? g.ng : g.ng - 1);
+  const double* wb = w + blockIdx.y * 8 * g.cvar;
+  const double* fb = bface + blockIdx.y * g.fblock;
+  double* ob = fo + blockIdx.y * 8 * g.fvar;
+  const int s = D == 0 ? 1 : (D == 1 ? g.N1 : g.N1 * g.N2);
+  const int q = g.c(i, j, k);
+  FaceState L, R;
+  recon_pair<RECON>(wb + q, s, L.rho, R.rho);
+  recon_pair<RECON>(wb + (1 + D) * g.cvar + q, s, L.vn, R.vn);
+  recon_pair<RECON>(wb + (1 + T1) * g.cvar + q, s, L.vt1, R.vt1);
+  recon_pair<RECON>(wb + (1 + T2) * g.cvar + q, s, L.vt2, R.vt2);
+  recon_pair<RECON>(wb + 4 * g.cvar + q, s, L.p, R.p);
+  recon_pair<RECON>(wb + (5 + T1) * g.cvar + q, s, L.bt1, R.bt1);
+  recon_pair<RECON>(wb + (5 + T2) * g.cvar + q, s, L.bt2, R.bt2);
+  const int fi = g.f(i, j, k);
+  const double bn = fb[D * g.fvar + fi];
+  FaceFlux F;
+  double smax;
+  if (RS == 1) hlld(L, R, bn, gas, F, smax);
+  else hlle(L, R, bn, gas, F, smax);
+  ob[fi] = F.rho;
+  ob[(1 + D) * g.fvar + fi] = F.mn;
+  ob[(1 + T1) * g.fvar + fi] = F.mt1;
+  ob[(1 + T2) * g.fvar + fi] = F.mt2;
+  ob[4 * g.fvar + fi] = F.e;
+  // E = -v x B: flux of B_t1 along D is -E_t2, flux of B_t2 is +E_t1
+  ob[5 * g.fvar + fi] = F.bt2;   // EMF component T1
+  ob[6 * g.fvar + fi] = -F.bt1;  // EMF component T2
+  ob[7 * g.fvar + fi] = ct_weight(F.rho, 0.5 * (L.rho + R.rho), smax, ct_eps);
+}
+
+// Corner EMFs on every edge that bounds an active face.
+__global__ void __launch_bounds__(kThreads) k_corner(Geo g, const double* __restrict__ w,
+                                                    const double* __restrict__ f0, const double* __restrict__ f1,
+                                                    const double* __restrict__ f2, double* __restrict__ edge) {
+  const int e1 = g.n1 + 1, e2 = g.n2 + 1, e3 = g.n3 + 1;
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= (int64_t)e1 * e2 * e3) return;
+  const int i = (int)(t % e1) + g.ng;
+  const int r = (int)(t / e1);
+  const int j = r % e2 + g.ng, k = r / e2 + g.ng;
+  const int b = blockIdx.y;
+  const double* wb = w + b * 8 * g.cvar;
+  const double* fd[3] = {f0 + b * 8 * g.fvar, f1 + b * 8 * g.fvar, f2 + b * 8 * g.fvar};
+  double* eb = edge + b * 3 * g.fvar;
+  const int idx[3] = {i, j, k};
+  const int last[3] = {g.ng + g.n1 - 1, g.ng + g.n2 - 1, g.ng + g.n3 - 1};
+  const int cstr[3] = {1, g.N1, g.N1 * g.N2};
+  const int fstr[3] = {1, g.F1, g.F1 * g.F2};
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    if (idx[e] > last[e]) continue;
+    const int a = (e + 1) % 3, bb = (e + 2) % 3;
+    const int fc = g.f(i, j, k), qc = g.c(i, j, k);
+    const int fa = fstr[a], fbs = fstr[bb];
+    const int ca = cstr[a], cb = cstr[bb];
+    const double* Fa = fd[a];
+    const double* Fb = fd[bb];
+    // face-a EMF of component e is slot 6 (component T2 of a), face-b is slot 5
+    const double ea0 = Fa[6 * g.fvar + fc], ea1 = Fa[6 * g.fvar + fc - fbs];
+    const double eb0 = Fb[5 * g.fvar + fc], eb1 = Fb[5 * g.fvar + fc - fa];
+    const double wa0 = Fa[7 * g.fvar + fc], wa1 = Fa[7 * g.fvar + fc - fbs];
+    const double wb0 = Fb[7 * g.fvar + fc], wb1 = Fb[7 * g.fvar + fc - fa];
+    // cell EMF component e: -(v_a B_b - v_b B_a)
+    auto ecell = [&](int q) {
+      return -(wb[(1 + a) * g.cvar + q] * wb[(5 + bb) * g.cvar + q] - wb[(1 + bb) * g.cvar + q] * wb[(5 + a) * g.cvar + q]);
+    };
+    const double c00 = ecell(qc), cA = ecell(qc - ca), cB = ecell(qc - cb), cAB = ecell(qc - ca - cb);
+    eb[e * g.fvar + fc] = corner_emf(ea0, ea1, eb0, eb1, c00, cA, cB, cAB, wa0, wa1, wb0, wb1);
+  }
+}
+
+// out = g0 x + g1 un + bdt L(x) on the active cells and their lower faces.
+__global__ void __launch_bounds__(kThreads) k_update(Geo g, StageCoef cf, const double* __restrict__ xc,
+                                                    const double* __restrict__ xb, const double* unc,
+                                                    const double* unb, const double* __restrict__ f0,
+                                                    const double* __restrict__ f1, const double* __restrict__ f2,
+                                                    const double* __restrict__ edge, double* outc, double* outb) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= (int64_t)g.n1 * g.n2 * g.n3) return;
+  const int i = g.ng + (int)(t % g.n1);
+  const int r = (int)(t / g.n1);
+  const int j = g.ng + r % g.n2, k = g.ng + r / g.n2;
+  const int b = blockIdx.y;
+  const int q = g.c(i, j, k), fc = g.f(i, j, k);
+  const int s2 = g.F1, s3 = g.F1 * g.F2;
+  const double* F0 = f0 + b * 8 * g.fvar;
+  const double* F1 = f1 + b * 8 * g.fvar;
+  const double* F2 = f2 + b * 8 * g.fvar;
+  const double i1 = 1.0 / g.dx1, i2 = 1.0 / g.dx2, i3 = 1.0 / g.dx3;
+  const double* x = xc + b * g.cblock;
+  const double* un = unc + b * g.cblock;
+  double* o = outc + b * g.cblock;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const int64_t fv = v * g.fvar + fc;
+    const double div = (F0[fv + 1] - F0[fv]) * i1 + (F1[fv + s2] - F1[fv]) * i2 + (F2[fv + s3] - F2[fv]) * i3;
+    const int64_t cv = v * g.cvar + q;
+    o[cv] = cf.g0 * x[cv] + cf.g1 * un[cv] - cf.bdt * div;
+  }
+  const double* E = edge + b * 3 * g.fvar;
+  const double* xbb = xb + b * g.fblock;
+  const double* unbb = unb + b * g.fblock;
+  double* ob = outb + b * g.fblock;
+  const double* E1 = E;
+  const double* E2 = E + g.fvar;
+  const double* E3 = E + 2 * g.fvar;
+  // dB1 = -[(E3(j+1) - E3(j))/dx2 - (E2(k+1) - E2(k))/dx3]
+  const double c1 = (E3[fc + s2] - E3[fc]) * i2 - (E2[fc + s3] - E2[fc]) * i3;
+  // dB2 = -[(E1(k+1) - E1(k))/dx3 - (E3(i+1) - E3(i))/dx1]
+  const double c2 = (E1[fc + s3] - E1[fc]) * i3 - (E3[fc + 1] - E3[fc]) * i1;
+  // dB3 = -[(E2(i+1) - E2(i))/dx1 - (E1(j+1) - E1(j))/dx2]
+  const double c3 = (E2[fc + 1] - E2[fc]) * i1 - (E1[fc + s2] - E1[fc]) * i2;
+  ob[fc] = cf.g0 * xbb[fc] + cf.g1 * unbb[fc] - cf.bdt * c1;
+  ob[g.fvar + fc] = cf.g0 * xbb[g.fvar + fc] + cf.g1 * unbb[g.fvar + fc] - cf.bdt * c2;
+  ob[2 * g.fvar + fc] = cf.g0 * xbb[2 * g.fvar + fc] + cf.g1 * unbb[2 * g.fvar + fc] - cf.bdt * c3;
+}
+
+template <int D, int RECON>
+hipError_t flux_rs(const Geo& g, const Gas& gas, int rs, double ct_eps, const double* w, const double* xb,
+                   double* fo, int nb, hipStream_t s) {
+  const int64_t n = (int64_t)(D == 0 ? g.n1 + 1 : g.n1 + 2) * (D == 1 ? g.n2 + 1 : g.n2 + 2) *
+                    (D == 2 ? g.n3 + 1 : g.n3 + 2);
+  if (rs == 1)
+    hipLaunchKernelGGL((k_flux<D, RECON, 1>), dim3(grid_for(n), nb), dim3(kThreads), 0, s, g, gas, ct_eps, w, xb, fo);
+  else
+    hipLaunchKernelGGL((k_flux<D, RECON, 0>), dim3(grid_for(n), nb), dim3(kThreads), 0, s, g, gas, ct_eps, w, xb, fo);
+  return hipGetLastError();
+}
+
+template <int D>
+hipError_t flux_dir(const Geo& g, const Gas& gas, int recon, int rs, double ct_eps, const double* w,
+                    const double* xb, double* fo, int nb, hipStream_t s) {
+  if (recon == 0) return flux_rs<D, 0>(g, gas, rs, ct_eps, w, xb, fo, nb, s);
+  if (recon == 1) return flux_rs<D, 1>(g, gas, rs, ct_eps, w, xb, fo, nb, s);
+  return flux_rs<D, 2>(g, gas, rs, ct_eps, w, xb, fo, nb, s);
+}
+
+}  // namespace
+
+hipError_t launch_stage_unfused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
+                                const double* xb, const double* unc, const double* unb, double* outc,
+                                double* outb, StageCoef coef, int nb, UnfusedScratch& scr, int* bad,
+                                hipStream_t s) {
+  Gas gas{gamma, gamma - 1.0, 1.0 / (gamma - 1.0)};
+  hipLaunchKernelGGL(k_prim, dim3(grid_for(g.cvar), nb), dim3(kThreads), 0, s, g, gamma, xc, xb, scr.w, bad);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = flux_dir<0>(g, gas, recon, rs, ct_eps, scr.w, xb, scr.face[0], nb, s)) != hipSuccess) return e;
+  if ((e = flux_dir<1>(g, gas, recon, rs, ct_eps, scr.w, xb, scr.face[1], nb, s)) != hipSuccess) return e;
+  if ((e = flux_dir<2>(g, gas, recon, rs, ct_eps, scr.w, xb, scr.face[2], nb, s)) != hipSuccess) return e;
+  const int64_t ne = (int64_t)(g.n1 + 1) * (g.n2 + 1) * (g.n3 + 1);
+  hipLaunchKernelGGL(k_corner, dim3(grid_for(ne), nb), dim3(kThreads), 0, s, g, scr.w, scr.face[0], scr.face[1],
+                     scr.face[2], scr.edge);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int64_t na = (int64_t)g.n1 * g.n2 * g.n3;
+  hipLaunchKernelGGL(k_update, dim3(grid_for(na), nb), dim3(kThreads), 0, s, g, coef, xc, xb, unc, unb,
+                     scr.face[0], scr.face[1], scr.face[2], scr.edge, outc, outb);
+  return hipGetLastError();
+}
+
+}  // namespace athmhd

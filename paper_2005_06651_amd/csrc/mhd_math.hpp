@@ -1,0 +1,289 @@
+// mhd_math.hpp -- device-side pointwise physics of the ideal-MHD update
+// (Stone, Tomida, White & Felker 2020, Sec. 3): fast magnetosonic speed,
+// face-frame physical flux, HLLE and HLLD Riemann solvers (Sec. 3.2.2),
+// van Leer PLM and Colella-Sekora PPM reconstruction (Sec. 3.2.1), and the
+// upwind CT corner-EMF average of Gardiner & Stone (2005) (Sec. 3.1).
+//
+// All functions are branch-light straight-line FP64 code meant to be inlined
+// into the stencil kernels; every lane of a wavefront follows the same
+// instruction stream and regions of the Riemann fan are chosen with selects.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace athmhd {
+
+// Primitive state in the frame of a face: normal direction n, transverse t1, t2
+// (cyclic), normal field supplied separately.
+struct FaceState {
+  double rho, vn, vt1, vt2, p, bt1, bt2;
+};
+
+// Flux in the same frame: mass, normal/t1/t2 momentum, energy, B_t1, B_t2.
+struct FaceFlux {
+  double rho, mn, mt1, mt2, e, bt1, bt2;
+};
+
+struct Gas {
+  double gamma, gm1, igm1;  // gamma, gamma-1, 1/(gamma-1)
+};
+
+__device__ __forceinline__ double sqr(double x) { return x * x; }
+
+// Fast magnetosonic speed along the normal:
+//   c_f^2 = ((a^2 + B^2/rho) + sqrt((a^2 + B^2/rho)^2 - 4 a^2 B_n^2/rho)) / 2
+__device__ __forceinline__ double fast_speed(double irho, double p, double bnsq, double btsq, double gamma) {
+  double asq = gamma * p * irho;
+  double s = asq + (bnsq + btsq) * irho;
+  double disc = fmax(s * s - 4.0 * asq * bnsq * irho, 0.0);
+  return sqrt(0.5 * (s + sqrt(disc)));
+}
+
+// HLLE with Davis wave-speed bounds.
+__device__ __forceinline__ void hlle(const FaceState& L, const FaceState& R, double bn, const Gas& g, FaceFlux& F,
+                                     double& smax) {
+  const double bnsq = bn * bn;
+  const double irl = 1.0 / L.rho, irr = 1.0 / R.rho;
+  const double btl = L.bt1 * L.bt1 + L.bt2 * L.bt2, btr = R.bt1 * R.bt1 + R.bt2 * R.bt2;
+  const double cfl = fast_speed(irl, L.p, bnsq, btl, g.gamma);
+  const double cfr = fast_speed(irr, R.p, bnsq, btr, g.gamma);
+  const double sl = fmin(L.vn - cfl, R.vn - cfr);
+  const double sr = fmax(L.vn + cfl, R.vn + cfr);
+  smax = fmax(fabs(sl), fabs(sr));
+  const double bp = fmax(sr, 0.0), bm = fmin(sl, 0.0);
+  const double idb = 1.0 / (bp - bm);
+  const double wl = bp * idb, wr = -bm * idb, wd = bp * bm * idb;
+  // left and right conserved states and physical fluxes
+  const double pml = 0.5 * (bnsq + btl), pmr = 0.5 * (bnsq + btr);
+  const double ptl = L.p + pml, ptr = R.p + pmr;
+  const double el = L.p * g.igm1 + 0.5 * L.rho * (L.vn * L.vn + L.vt1 * L.vt1 + L.vt2 * L.vt2) + pml;
+  const double er = R.p * g.igm1 + 0.5 * R.rho * (R.vn * R.vn + R.vt1 * R.vt1 + R.vt2 * R.vt2) + pmr;
+  const double mnl = L.rho * L.vn, mnr = R.rho * R.vn;
+  const double vbl = L.vn * bn + L.vt1 * L.bt1 + L.vt2 * L.bt2;
+  const double vbr = R.vn * bn + R.vt1 * R.bt1 + R.vt2 * R.bt2;
+  F.rho = wl * mnl + wr * mnr + wd * (R.rho - L.rho);
+  F.mn = wl * (mnl * L.vn + ptl - bnsq) + wr * (mnr * R.vn + ptr - bnsq) + wd * (mnr - mnl);
+  F.mt1 = wl * (mnl * L.vt1 - bn * L.bt1) + wr * (mnr * R.vt1 - bn * R.bt1) + wd * (R.rho * R.vt1 - L.rho * L.vt1);
+  F.mt2 = wl * (mnl * L.vt2 - bn * L.bt2) + wr * (mnr * R.vt2 - bn * R.bt2) + wd * (R.rho * R.vt2 - L.rho * L.vt2);
+  F.e = wl * ((el + ptl) * L.vn - bn * vbl) + wr * ((er + ptr) * R.vn - bn * vbr) + wd * (er - el);
+  F.bt1 = wl * (L.bt1 * L.vn - bn * L.vt1) + wr * (R.bt1 * R.vn - bn * R.vt1) + wd * (R.bt1 - L.bt1);
+  F.bt2 = wl * (L.bt2 * L.vn - bn * L.vt2) + wr * (R.bt2 * R.vn - bn * R.vt2) + wd * (R.bt2 - L.bt2);
+}
+
+// HLLD (Miyoshi & Kusano 2005): outer fast waves, contact S_M, rotational
+// waves S*_L, S*_R.  Degenerate star states (|rho (S-u)(S-S_M) - Bn^2| or
+// Bn^2/2 below 1e-8 of the star total pressure) fall back to the unmodified
+// transverse state / the single-star state.
+__device__ __forceinline__ void hlld(const FaceState& L, const FaceState& R, double bn, const Gas& g, FaceFlux& F,
+                                     double& smax) {
+  constexpr double kSmall = 1.0e-8;
+  const double bnsq = bn * bn;
+  const double irl = 1.0 / L.rho, irr = 1.0 / R.rho;
+  const double btl = L.bt1 * L.bt1 + L.bt2 * L.bt2, btr = R.bt1 * R.bt1 + R.bt2 * R.bt2;
+  const double pml = 0.5 * (bnsq + btl), pmr = 0.5 * (bnsq + btr);
+  const double ptl = L.p + pml, ptr = R.p + pmr;
+  const double el = L.p * g.igm1 + 0.5 * L.rho * (L.vn * L.vn + L.vt1 * L.vt1 + L.vt2 * L.vt2) + pml;
+  const double er = R.p * g.igm1 + 0.5 * R.rho * (R.vn * R.vn + R.vt1 * R.vt1 + R.vt2 * R.vt2) + pmr;
+
+  const double cfl = fast_speed(irl, L.p, bnsq, btl, g.gamma);
+  const double cfr = fast_speed(irr, R.p, bnsq, btr, g.gamma);
+  const double cmax = fmax(cfl, cfr);
+  const double sl = fmin(L.vn, R.vn) - cmax;
+  const double sr = fmax(L.vn, R.vn) + cmax;
+  smax = fmax(fabs(sl), fabs(sr));
+
+  // contact speed and total pressure of the star region
+  const double ml = (sl - L.vn) * L.rho;  // < 0
+  const double mr = (sr - R.vn) * R.rho;  // > 0
+  const double iden = 1.0 / (mr - ml);
+  const double sm = (mr * R.vn - ml * L.vn - ptr + ptl) * iden;
+  const double pts = (mr * ptl - ml * ptr + ml * mr * (R.vn - L.vn)) * iden;
+
+  // single-star states
+  const double isl = 1.0 / (sl - sm), isr = 1.0 / (sr - sm);
+  const double rsl = ml * isl, rsr = mr * isr;  // rho*_L, rho*_R
+  double vt1sl, vt2sl, bt1sl, bt2sl, vt1sr, vt2sr, bt1sr, bt2sr;
+  {
+    const double d = ml * (sl - sm) - bnsq;
+    const bool degen = fabs(d) < kSmall * pts;
+    const double id = 1.0 / (degen ? 1.0 : d);
+    const double c1 = bn * (sm - L.vn) * id;
+    const double c2 = (ml * (sl - L.vn) - bnsq) * id;
+    vt1sl = degen ? L.vt1 : L.vt1 - L.bt1 * c1;
+    vt2sl = degen ? L.vt2 : L.vt2 - L.bt2 * c1;
+    bt1sl = degen ? L.bt1 : L.bt1 * c2;
+    bt2sl = degen ? L.bt2 : L.bt2 * c2;
+  }
+  {
+    const double d = mr * (sr - sm) - bnsq;
+    const bool degen = fabs(d) < kSmall * pts;
+    const double id = 1.0 / (degen ? 1.0 : d);
+    const double c1 = bn * (sm - R.vn) * id;
+    const double c2 = (mr * (sr - R.vn) - bnsq) * id;
+    vt1sr = degen ? R.vt1 : R.vt1 - R.bt1 * c1;
+    vt2sr = degen ? R.vt2 : R.vt2 - R.bt2 * c1;
+    bt1sr = degen ? R.bt1 : R.bt1 * c2;
+    bt2sr = degen ? R.bt2 : R.bt2 * c2;
+  }
+  const double vbl = L.vn * bn + L.vt1 * L.bt1 + L.vt2 * L.bt2;
+  const double vbr = R.vn * bn + R.vt1 * R.bt1 + R.vt2 * R.bt2;
+  const double vbsl = sm * bn + vt1sl * bt1sl + vt2sl * bt2sl;
+  const double vbsr = sm * bn + vt1sr * bt1sr + vt2sr * bt2sr;
+  const double esl = ((sl - L.vn) * el - ptl * L.vn + pts * sm + bn * (vbl - vbsl)) * isl;
+  const double esr = ((sr - R.vn) * er - ptr * R.vn + pts * sm + bn * (vbr - vbsr)) * isr;
+
+  const double sqrl = sqrt(rsl), sqrr = sqrt(rsr);
+  const double ssl = sm - fabs(bn) / sqrl;
+  const double ssr = sm + fabs(bn) / sqrr;
+
+  // double-star state (shared velocity and field, separate energies)
+  const bool dstar = !(0.5 * bnsq < kSmall * pts);
+  const double sgn = bn > 0.0 ? 1.0 : (bn < 0.0 ? -1.0 : 0.0);
+  const double isum = 1.0 / (sqrl + sqrr);
+  const double vt1ss = (sqrl * vt1sl + sqrr * vt1sr + (bt1sr - bt1sl) * sgn) * isum;
+  const double vt2ss = (sqrl * vt2sl + sqrr * vt2sr + (bt2sr - bt2sl) * sgn) * isum;
+  const double bt1ss = (sqrl * bt1sr + sqrr * bt1sl + sqrl * sqrr * (vt1sr - vt1sl) * sgn) * isum;
+  const double bt2ss = (sqrl * bt2sr + sqrr * bt2sl + sqrl * sqrr * (vt2sr - vt2sl) * sgn) * isum;
+  const double vbss = sm * bn + vt1ss * bt1ss + vt2ss * bt2ss;
+
+  // region of the fan that contains x/t = 0
+  //   0: left state, 1: L*, 2: L**, 3: R**, 4: R*, 5: right state
+  const bool useL = (sl > 0.0) || (!(sr < 0.0) && (ssl >= 0.0 || (!(ssr <= 0.0) && sm >= 0.0)));
+  const bool star = !(sl > 0.0) && !(sr < 0.0);
+  const bool dbl = star && !(ssl >= 0.0) && !(ssr <= 0.0) && dstar;
+
+  // chosen side: its state, flux, star and double-star states
+  const double rho = useL ? L.rho : R.rho;
+  const double vn = useL ? L.vn : R.vn;
+  const double vt1 = useL ? L.vt1 : R.vt1;
+  const double vt2 = useL ? L.vt2 : R.vt2;
+  const double bt1 = useL ? L.bt1 : R.bt1;
+  const double bt2 = useL ? L.bt2 : R.bt2;
+  const double pt = useL ? ptl : ptr;
+  const double en = useL ? el : er;
+  const double vb = useL ? vbl : vbr;
+  const double s = useL ? sl : sr;
+  const double ss = useL ? ssl : ssr;
+  const double rs = useL ? rsl : rsr;
+  const double vt1s = useL ? vt1sl : vt1sr, vt2s = useL ? vt2sl : vt2sr;
+  const double bt1s = useL ? bt1sl : bt1sr, bt2s = useL ? bt2sl : bt2sr;
+  const double es = useL ? esl : esr;
+  const double sq = useL ? sqrl : sqrr;
+  const double vbs = useL ? vbsl : vbsr;
+  const double ess = useL ? es - sq * (vbs - vbss) * sgn : es + sq * (vbs - vbss) * sgn;
+
+  const double mn = rho * vn;
+  F.rho = mn;
+  F.mn = mn * vn + pt - bnsq;
+  F.mt1 = mn * vt1 - bn * bt1;
+  F.mt2 = mn * vt2 - bn * bt2;
+  F.e = (en + pt) * vn - bn * vb;
+  F.bt1 = bt1 * vn - bn * vt1;
+  F.bt2 = bt2 * vn - bn * vt2;
+  if (star) {
+    // F + S (U* - U)
+    F.rho += s * (rs - rho);
+    F.mn += s * (rs * sm - mn);
+    F.mt1 += s * (rs * vt1s - rho * vt1);
+    F.mt2 += s * (rs * vt2s - rho * vt2);
+    F.e += s * (es - en);
+    F.bt1 += s * (bt1s - bt1);
+    F.bt2 += s * (bt2s - bt2);
+  }
+  if (dbl) {
+    // + S* (U** - U*)
+    F.mt1 += ss * (rs * vt1ss - rs * vt1s);
+    F.mt2 += ss * (rs * vt2ss - rs * vt2s);
+    F.e += ss * (ess - es);
+    F.bt1 += ss * (bt1ss - bt1s);
+    F.bt2 += ss * (bt2ss - bt2s);
+  }
+}
+
+// van Leer (1974) slope: harmonic mean of the one-sided differences when they
+// share a sign, else zero.
+__device__ __forceinline__ double vl_slope(double qm, double q0, double qp) {
+  const double dm = q0 - qm, dp = qp - q0;
+  const double pr = dm * dp;
+  return pr > 0.0 ? 2.0 * pr / (dm + dp) : 0.0;
+}
+
+// Colella & Sekora (2008) extremum-preserving PPM on a uniform grid.
+__device__ __forceinline__ double cs_lim3(double a, double b, double c) {
+  constexpr double C = 1.25;
+  const bool pos = a > 0.0 && b > 0.0 && c > 0.0;
+  const bool neg = a < 0.0 && b < 0.0 && c < 0.0;
+  const double m = fmin(fabs(a), fmin(C * fabs(b), C * fabs(c)));
+  return pos ? m : (neg ? -m : 0.0);
+}
+
+// limited face value between q0 (=q_{c-1}) and q1 (=q_c); qm1 = q_{c-2}, q2 = q_{c+1}
+__device__ __forceinline__ double ppm_face(double qm1, double q0, double q1, double q2) {
+  double qf = (7.0 / 12.0) * (q0 + q1) - (1.0 / 12.0) * (qm1 + q2);
+  if ((qf - q0) * (q1 - qf) < 0.0) {
+    const double d2 = 3.0 * (q0 - 2.0 * qf + q1);
+    const double d2l = qm1 - 2.0 * q0 + q1;
+    const double d2r = q0 - 2.0 * q1 + q2;
+    qf = 0.5 * (q0 + q1) - cs_lim3(d2, d2l, d2r) * (1.0 / 6.0);
+  }
+  return qf;
+}
+
+// limited parabola of cell c from q_{c-2..c+2} and its two raw face values;
+// returns the left (qm) and right (qp) edge values
+__device__ __forceinline__ void ppm_cell(double qa, double qb, double qc, double qd, double qe, double& qm,
+                                         double& qp) {
+  constexpr double C = 1.25;
+  // qa..qe = q_{c-2}, q_{c-1}, q_c, q_{c+1}, q_{c+2}
+  if ((qp - qc) * (qc - qm) <= 0.0 || (qb - qc) * (qc - qd) <= 0.0) {
+    const double d2 = 6.0 * (qm + qp) - 12.0 * qc;
+    const double d2c = qb - 2.0 * qc + qd;
+    const double d2l = qa - 2.0 * qb + qc;
+    const double d2r = qc - 2.0 * qd + qe;
+    const bool pos = d2 > 0.0 && d2c > 0.0 && d2l > 0.0 && d2r > 0.0;
+    const bool neg = d2 < 0.0 && d2c < 0.0 && d2l < 0.0 && d2r < 0.0;
+    const double m = fmin(fabs(d2), fmin(C * fabs(d2l), fmin(C * fabs(d2r), C * fabs(d2c))));
+    const double lim = pos ? m : (neg ? -m : 0.0);
+    if (d2 != 0.0) {
+      const double r = lim / d2;
+      qm = qc + (qm - qc) * r;
+      qp = qc + (qp - qc) * r;
+    } else {
+      qm = qc;
+      qp = qc;
+    }
+  } else {
+    const double dqm = qm - qc, dqp = qp - qc;
+    if (fabs(dqp) >= 2.0 * fabs(dqm)) qp = qc - 2.0 * dqm;
+    if (fabs(dqm) >= 2.0 * fabs(qp - qc)) qm = qc - 2.0 * (qp - qc);
+  }
+}
+
+// Upwind CT corner EMF (Gardiner & Stone 2005) at the edge shared by four
+// cells.  Notation for component e with transverse directions a, b:
+//   ea0 = face-a EMF at (c), ea1 = at (c - b)   [faces normal to a]
+//   eb0 = face-b EMF at (c), eb1 = at (c - a)   [faces normal to b]
+//   c00 = cell EMF at c, ca = at c - a, cb = at c - b, cab = at c - a - b
+//   wa0, wa1 = upwind weights of the a-faces (c), (c - b); wb0, wb1 of the
+//   b-faces (c), (c - a); weight 1 selects the cell on the low side.
+__device__ __forceinline__ double corner_emf(double ea0, double ea1, double eb0, double eb1, double c00, double ca,
+                                             double cb, double cab, double wa0, double wa1, double wb0,
+                                             double wb1) {
+  const double avg = 0.25 * (ea0 + ea1 + eb0 + eb1);
+  const double dbp = wa0 * (ca - eb1) + (1.0 - wa0) * (c00 - eb0);
+  const double dbm = wa1 * (eb1 - cab) + (1.0 - wa1) * (eb0 - cb);
+  const double dap = wb0 * (cb - ea1) + (1.0 - wb0) * (c00 - ea0);
+  const double dam = wb1 * (ea1 - cab) + (1.0 - wb1) * (ea0 - ca);
+  return avg + 0.25 * (dbm - dbp) + 0.25 * (dam - dap);
+}
+
+// upwind weight of a face from its mass flux
+__device__ __forceinline__ double ct_weight(double frho, double rhobar, double smax, double eps) {
+  if (eps > 0.0) {
+    const double r = 0.5 + 0.5 * (frho / rhobar) / (eps * smax);
+    return fmin(1.0, fmax(0.0, r));
+  }
+  return frho > 0.0 ? 1.0 : (frho < 0.0 ? 0.0 : 0.5);
+}
+
+}  // namespace athmhd

@@ -1,0 +1,86 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol that include/athmhd.h declares, and rejects bad configurations
+and calls before touching the HIP runtime."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2005_06651_amd import athmhd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    out = []
+    for name in os.listdir(os.path.join(ROOT, "include")):
+        if name.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", name)).read()
+            out += re.findall(r"ATHMHD_API\s+[\w\s\*]*?\b(athmhd_\w+)\s*\(", text)
+    return sorted(set(out))
+
+
+def test_library_exports_every_declared_symbol():
+    L = athmhd.lib()
+    syms = declared_symbols()
+    assert len(syms) >= 8
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(athmhd.EXPORTED) <= set(syms)
+
+
+def test_version():
+    assert athmhd.lib().athmhd_version() == 100
+
+
+def _create(**over):
+    kw = dict(n=(8, 8, 8), nghost=2, dx=(0.1, 0.1, 0.1), gamma=5 / 3)
+    kw.update({k: v for k, v in over.items() if k in kw})
+    cfg = athmhd.make_config(**kw)
+    for k, v in over.items():
+        if k not in kw:
+            setattr(cfg, k, v)
+    h = C.c_void_p()
+    rc = athmhd.lib().athmhd_create(C.byref(cfg), 1, C.byref(h))
+    msg = athmhd.lib().athmhd_last_error(None).decode()
+    return rc, msg
+
+
+@pytest.mark.parametrize("over,needle", [
+    (dict(n=(0, 8, 8)), "dims"),
+    (dict(nghost=1), "nghost"),
+    (dict(recon=2, nghost=2), "nghost"),
+    (dict(gamma=1.0), "gamma"),
+    (dict(gamma=float("nan")), "gamma"),
+    (dict(dx=(0.1, 0.0, 0.1)), "widths"),
+    (dict(dx=(0.1, float("inf"), 0.1)), "widths"),
+    (dict(recon=7), "reconstruction"),
+    (dict(riemann=3), "Riemann"),
+    (dict(integrator=9), "integrator"),
+    (dict(cfl=0.0), "cfl"),
+    (dict(cfl=1.5), "cfl"),
+    (dict(ct_eps=-1.0), "ct_eps"),
+    (dict(reserved=1), "reserved"),
+    (dict(n=(2000, 2000, 2000)), "too large"),
+])
+def test_create_rejects_bad_config_before_any_hip_call(over, needle):
+    rc, msg = _create(**over)
+    assert rc == athmhd.EINVAL
+    assert needle in msg
+
+
+def test_calls_reject_null_handle():
+    L = athmhd.lib()
+    out = C.c_double()
+    assert L.athmhd_step(None, None, None, 0.1, 1, None) == athmhd.EINVAL
+    assert L.athmhd_newdt(None, None, None, 1, C.byref(out), None) == athmhd.EINVAL
+    assert L.athmhd_fill_ghosts(None, None, None, 1, None) == athmhd.EINVAL
+    assert L.athmhd_prim2cons(None, None, None, None, 1, None) == athmhd.EINVAL
+    L.athmhd_destroy(None)
+
+
+def test_create_rejects_null_out():
+    cfg = athmhd.make_config((8, 8, 8), 2, (0.1,) * 3, 5 / 3)
+    assert athmhd.lib().athmhd_create(C.byref(cfg), 1, None) == athmhd.EINVAL
+    assert athmhd.lib().athmhd_create(C.byref(cfg), 0, C.byref(C.c_void_p())) == athmhd.EINVAL

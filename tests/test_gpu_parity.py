@@ -1,0 +1,272 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bar: relative L1 (sum |gpu - oracle| / sum |oracle| over the active cells or
+faces, worst of the 5 conserved and 3 face arrays) <= 1e-12; div B metric
+<= 1e-13; bitwise equality for pure data movement (ghost fill).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2005_06651_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def athmhd():
+    from paper_2005_06651_amd import athmhd as A
+    A.lib()
+    return A
+
+
+def rel_l1(b, gc, gb, rc, rb):
+    """worst relative L1 over the 5 conserved arrays and the 3 face arrays"""
+    g = b.ng
+    n1, n2, n3 = b.n
+    a = b.active
+    worst = 0.0
+    for v in range(5):
+        den = np.abs(rc[v][a]).sum()
+        worst = max(worst, np.abs(gc[v][a] - rc[v][a]).sum() / max(den, 1e-300))
+    for c in range(3):
+        sl = (c, slice(g, g + n3), slice(g, g + n2), slice(g, g + n1))
+        den = np.abs(rb[sl]).sum()
+        worst = max(worst, np.abs(gb[sl] - rb[sl]).sum() / max(den, 1e-300))
+    return worst
+
+
+def to_dev(torch, dev, x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def make_pair(athmhd, orc, b, **kw):
+    solver = athmhd.Solver(b.n, b.ng, b.dx, b.gamma, **kw)
+    cfg = orc.cfg_for(b, **kw)
+    return solver, cfg
+
+
+def test_fill_ghosts_bitwise(torch_dev, athmhd, orc):
+    torch, dev = torch_dev
+    b = inputs.smooth_random(n=(13, 9, 7), seed=21)
+    s, cfg = make_pair(athmhd, orc, b)
+    cons = orc.prim2cons(cfg, b.prim, b.bface)
+    rng = np.random.default_rng(0)
+    # scramble every ghost entry, then fill on both sides
+    junk_c = cons.copy()
+    junk_b = b.bface.copy()
+    g = b.ng
+    n1, n2, n3 = b.n
+    mask_c = np.ones(junk_c.shape[1:], bool)
+    mask_c[g:g + n3, g:g + n2, g:g + n1] = False
+    junk_c[:, mask_c] = rng.normal(size=(5, mask_c.sum()))
+    mask_f = np.ones(junk_b.shape[1:], bool)
+    mask_f[g:g + n3, g:g + n2, g:g + n1] = False
+    junk_b[:, mask_f] = rng.normal(size=(3, mask_f.sum()))
+    tc, tb = to_dev(torch, dev, junk_c), to_dev(torch, dev, junk_b)
+    s.fill_ghosts(tc, tb)
+    orc.fill_ghosts(cfg, junk_c, junk_b)
+    assert np.array_equal(tc.cpu().numpy(), junk_c)
+    assert np.array_equal(tb.cpu().numpy(), junk_b)
+    s.close()
+
+
+def test_prim2cons_and_newdt(torch_dev, athmhd, orc):
+    torch, dev = torch_dev
+    b = inputs.smooth_random(n=(16, 12, 8), seed=22)
+    s, cfg = make_pair(athmhd, orc, b)
+    ref = orc.prim2cons(cfg, b.prim, b.bface)
+    tb = to_dev(torch, dev, b.bface)
+    tc = s.prim2cons(to_dev(torch, dev, b.prim), tb)
+    got = tc.cpu().numpy()
+    assert np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)) < 1e-15
+    dt_ref, bad = orc.newdt(cfg, ref, b.bface)
+    assert bad == 0
+    dt = s.newdt(tc, tb)
+    assert abs(dt - dt_ref) <= 2e-15 * dt_ref
+    s.close()
+
+
+COMBOS = [
+    ("vl2", "plm", "hlld"),
+    ("vl2", "plm", "hlle"),
+    ("rk1", "dc", "hlld"),
+    ("rk2", "plm", "hlld"),
+    ("rk3", "ppm", "hlld"),
+    ("rk3", "ppm", "hlle"),
+    ("vl2", "ppm", "hlld"),
+]
+
+
+@pytest.mark.parametrize("integ,recon,rs", COMBOS)
+def test_steps_match_oracle(torch_dev, athmhd, orc, integ, recon, rs):
+    """A few steps on a ragged block (sizes not multiples of any tile) of
+    smooth random data."""
+    torch, dev = torch_dev
+    ng = 3 if recon == "ppm" else 2
+    b = inputs.smooth_random(n=(37, 19, 11), seed=23, ng=ng)
+    kw = dict(integrator=integ, recon=recon, riemann=rs)
+    s, cfg = make_pair(athmhd, orc, b, **kw)
+    cons = orc.prim2cons(cfg, b.prim, b.bface)
+    tc, tb = to_dev(torch, dev, cons), to_dev(torch, dev, b.bface)
+    rc, rb = cons.copy(), b.bface.copy()
+    for _ in range(3):
+        dt, bad = orc.newdt(cfg, rc, rb)
+        assert orc.step(cfg, rc, rb, dt) == 0
+        s.step(tc, tb, dt)
+    err = rel_l1(b, tc.cpu().numpy(), tb.cpu().numpy(), rc, rb)
+    assert err <= TOL, err
+    assert inputs.divb_metric(tb.cpu().numpy(), b.n, b.ng, b.dx) <= 1e-13
+    s.close()
+
+
+def test_ct_ramp_matches_oracle(torch_dev, athmhd, orc):
+    torch, dev = torch_dev
+    b = inputs.smooth_random(n=(24, 16, 12), seed=24)
+    kw = dict(ct_eps=1e-3)
+    s, cfg = make_pair(athmhd, orc, b, **kw)
+    cons = orc.prim2cons(cfg, b.prim, b.bface)
+    tc, tb = to_dev(torch, dev, cons), to_dev(torch, dev, b.bface)
+    rc, rb = cons.copy(), b.bface.copy()
+    for _ in range(3):
+        dt, _ = orc.newdt(cfg, rc, rb)
+        orc.step(cfg, rc, rb, dt)
+        s.step(tc, tb, dt)
+    assert rel_l1(b, tc.cpu().numpy(), tb.cpu().numpy(), rc, rb) <= TOL
+    s.close()
+
+
+def test_linear_wave_one_period(torch_dev, athmhd, orc):
+    """Workload: 32x16x16 fast-mode linear wave, VL2+PLM+HLLD, CFL 0.3, one
+    wave period, dt from each side's own newdt."""
+    torch, dev = torch_dev
+    b = inputs.linear_wave(16)
+    kw = dict(integrator="vl2", recon="plm", riemann="hlld", cfl=0.3)
+    s, cfg = make_pair(athmhd, orc, b, **kw)
+    rc, rb, t, nsteps = orc.run(cfg, b.cons, b.bface, 0, t_end=0.5)
+    tc, tb = to_dev(torch, dev, b.cons), to_dev(torch, dev, b.bface)
+    tt = 0.0
+    steps = 0
+    while tt < 0.5 * (1 - 1e-14):
+        dt = min(s.newdt(tc, tb), 0.5 - tt)
+        s.step(tc, tb, dt)
+        tt += dt
+        steps += 1
+    assert steps == nsteps
+    gc, gb = tc.cpu().numpy(), tb.cpu().numpy()
+    assert rel_l1(b, gc, gb, rc, rb) <= TOL
+    assert inputs.divb_metric(gb, b.n, b.ng, b.dx) <= 1e-13
+    # and the error against the initial state is the oracle's (second-order accurate)
+    a = b.active
+    e_gpu = np.mean(np.abs(gc[0][a] - b.cons[0][a]))
+    e_orc = np.mean(np.abs(rc[0][a] - b.cons[0][a]))
+    assert abs(e_gpu - e_orc) <= 1e-6 * e_orc
+    s.close()
+
+
+def test_turbulence_small_matches_oracle(torch_dev, athmhd, orc):
+    """Turbulence recipe (Mach 1, |k| in [1,4], B = 0.5 x + curl A) at 32^3,
+    10 steps VL2+PLM+HLLD."""
+    torch, dev = torch_dev
+    b = inputs.turbulence(n=32, seed=3)
+    kw = dict(integrator="vl2", recon="plm", riemann="hlld")
+    s, cfg = make_pair(athmhd, orc, b, **kw)
+    cons = orc.prim2cons(cfg, b.prim, b.bface)
+    tc, tb = to_dev(torch, dev, cons), to_dev(torch, dev, b.bface)
+    rc, rb = cons.copy(), b.bface.copy()
+    for _ in range(10):
+        dt, bad = orc.newdt(cfg, rc, rb)
+        assert bad == 0
+        assert orc.step(cfg, rc, rb, dt) == 0
+        s.step(tc, tb, dt)
+    assert rel_l1(b, tc.cpu().numpy(), tb.cpu().numpy(), rc, rb) <= TOL
+    s.close()
+
+
+def test_multiple_blocks_are_independent(torch_dev, athmhd, orc):
+    torch, dev = torch_dev
+    blocks = [inputs.smooth_random(n=(12, 10, 8), seed=30 + i) for i in range(3)]
+    b0 = blocks[0]
+    s = athmhd.Solver(b0.n, b0.ng, b0.dx, b0.gamma, nblocks=3)
+    cfg = orc.cfg_for(b0)
+    cons = np.stack([orc.prim2cons(cfg, b.prim, b.bface) for b in blocks])
+    bf = np.stack([b.bface for b in blocks])
+    tc, tb = to_dev(torch, dev, cons), to_dev(torch, dev, bf)
+    dt = 0.004
+    s.step(tc, tb, dt)
+    gc, gb = tc.cpu().numpy(), tb.cpu().numpy()
+    for i, b in enumerate(blocks):
+        rc, rb = cons[i].copy(), bf[i].copy()
+        orc.step(cfg, rc, rb, dt)
+        assert rel_l1(b, gc[i], gb[i], rc, rb) <= TOL
+    s.close()
+
+
+def test_step_is_deterministic(torch_dev, athmhd, orc):
+    torch, dev = torch_dev
+    b = inputs.turbulence(n=48, seed=4)
+    s, cfg = make_pair(athmhd, orc, b)
+    cons = orc.prim2cons(cfg, b.prim, b.bface)
+    outs = []
+    for _ in range(2):
+        tc, tb = to_dev(torch, dev, cons), to_dev(torch, dev, b.bface)
+        for _ in range(3):
+            s.step(tc, tb, 1e-3)
+        outs.append((tc.cpu().numpy(), tb.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    s.close()
+
+
+def test_nonphysical_state_is_reported(torch_dev, athmhd, orc):
+    torch, dev = torch_dev
+    b = inputs.uniform(n=(8, 8, 8))
+    s, cfg = make_pair(athmhd, orc, b)
+    cons = orc.prim2cons(cfg, b.prim, b.bface)
+    cons[4, 4, 4, 4] = 0.0  # energy below the kinetic + magnetic energy -> P < 0
+    tc, tb = to_dev(torch, dev, cons), to_dev(torch, dev, b.bface)
+    with pytest.raises(athmhd.NonPhysicalState):
+        s.newdt(tc, tb)
+    # the flag is cleared by the report
+    good = to_dev(torch, dev, orc.prim2cons(cfg, b.prim, b.bface))
+    assert s.newdt(good, tb) > 0
+    s.close()
+
+
+def test_full_size_conservation_and_divb(torch_dev, athmhd, orc):
+    """At the 256^3 turbulence size: totals of the conserved variables and the
+    magnetic flux through every face plane are unchanged, div B stays at
+    round-off (properties that hold at any size)."""
+    torch, dev = torch_dev
+    b = inputs.turbulence(n=256, seed=1)
+    s = athmhd.Solver(b.n, b.ng, b.dx, b.gamma)
+    tb = to_dev(torch, dev, b.bface)
+    tc = s.prim2cons(to_dev(torch, dev, b.prim), tb)
+    g, n = b.ng, 256
+    act = (slice(None), slice(g, g + n), slice(g, g + n), slice(g, g + n))
+
+    def totals():
+        c = tc[act].sum(dim=(1, 2, 3)).cpu().numpy()
+        f1 = tb[0, g:g + n, g:g + n, g:g + n].sum(dim=(0, 1)).cpu().numpy()
+        return c, f1
+
+    c0, f0 = totals()
+    scale = tc[act].abs().sum(dim=(1, 2, 3)).cpu().numpy()
+    for _ in range(4):
+        dt = s.newdt(tc, tb)
+        s.step(tc, tb, dt)
+    c1, f1 = totals()
+    assert np.all(np.abs(c1 - c0) <= 1e-13 * scale)
+    assert np.max(np.abs(f1 - f0)) <= 1e-9
+    bf = tb.cpu().numpy()
+    assert inputs.divb_metric(bf, b.n, b.ng, b.dx) <= 1e-13
+    s.close()
