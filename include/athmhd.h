@@ -112,6 +112,15 @@ ATHMHD_API int athmhd_prim2cons(athmhd_t h, const double* prim, const double* bf
 /* Fill the ghost cells and periodic image faces of (cons, bface). */
 ATHMHD_API int athmhd_fill_ghosts(athmhd_t h, double* cons, double* bface, int nblocks, void* stream);
 
+/* Kernel timing for measurement.  enable = 1 starts recording a pair of HIP
+ * events around every launch of the stage kernel (the kernel that does
+ * reconstruction, Riemann fluxes, CT and the update of one stage) on the stream
+ * it is launched on, and clears the totals.  enable = 0 stops recording,
+ * synchronises the recorded events and writes the summed duration in
+ * milliseconds and the number of launches to *total_ms and *launches (either
+ * may be NULL). */
+ATHMHD_API int athmhd_profile(athmhd_t h, int enable, double* total_ms, int* launches);
+
 /* Text of the last error recorded on `h` (or of the last failed create when
  * h is NULL).  Valid until the next call on the same handle. */
 ATHMHD_API const char* athmhd_last_error(athmhd_t h);

@@ -18,7 +18,7 @@ RECON = {"dc": 0, "plm": 1, "ppm": 2}
 RIEMANN = {"hlle": 0, "hlld": 1}
 INTEGRATOR = {"rk1": 0, "vl2": 1, "rk2": 2, "rk3": 3}
 EXPORTED = ["athmhd_version", "athmhd_create", "athmhd_step", "athmhd_newdt", "athmhd_prim2cons",
-            "athmhd_fill_ghosts", "athmhd_last_error", "athmhd_destroy"]
+            "athmhd_fill_ghosts", "athmhd_profile", "athmhd_last_error", "athmhd_destroy"]
 
 
 class AthmhdError(RuntimeError):
@@ -56,6 +56,7 @@ def lib():
         L.athmhd_newdt.argtypes = [vp, vp, vp, C.c_int, C.POINTER(C.c_double), vp]
         L.athmhd_prim2cons.argtypes = [vp, vp, vp, vp, C.c_int, vp]
         L.athmhd_fill_ghosts.argtypes = [vp, vp, vp, C.c_int, vp]
+        L.athmhd_profile.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]
         L.athmhd_last_error.argtypes = [vp]
         L.athmhd_last_error.restype = C.c_char_p
         L.athmhd_destroy.argtypes = [vp]
@@ -157,6 +158,16 @@ class Solver:
     def fill_ghosts(self, cons, bface, stream=None) -> None:
         pc, pb, nb = self._pair(cons, bface)
         _check(lib().athmhd_fill_ghosts(self._h, pc, pb, nb, _stream(stream)), self._h)
+
+    def profile_start(self) -> None:
+        _check(lib().athmhd_profile(self._h, 1, None, None), self._h)
+
+    def profile_stop(self):
+        """(summed stage-kernel milliseconds, number of launches) since start"""
+        ms = C.c_double()
+        n = C.c_int()
+        _check(lib().athmhd_profile(self._h, 0, C.byref(ms), C.byref(n)), self._h)
+        return ms.value, n.value
 
     def close(self):
         if getattr(self, "_h", None):

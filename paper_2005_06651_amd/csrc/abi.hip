@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/athmhd.h"
 #include "common.hpp"
@@ -25,6 +26,8 @@ struct athmhd_s {
   unsigned long long* d_dt = nullptr;   // running min of dx/(|v|+cf), bit pattern
   int* d_bad = nullptr;                 // non-physical cells met since the last newdt
   void* h_pinned = nullptr;             // 16 bytes of pinned host memory for newdt
+  bool profiling = false;
+  std::vector<hipEvent_t> events;       // (start, stop) pairs around stage kernels
   std::string err;
 };
 
@@ -109,8 +112,24 @@ int check_call(athmhd_t h, const void* a, const void* b, int nb) {
   return ATHMHD_OK;
 }
 
+void drop_events(athmhd_t h) {
+  for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);
+  h->events.clear();
+}
+
+// record one event of a (start, stop) pair when profiling
+hipError_t mark(athmhd_t h, hipStream_t s) {
+  if (!h->profiling) return hipSuccess;
+  hipEvent_t ev;
+  hipError_t e = hipEventCreate(&ev);
+  if (e != hipSuccess) return e;
+  h->events.push_back(ev);
+  return hipEventRecord(ev, s);
+}
+
 void free_all(athmhd_t h) {
   if (!h) return;
+  drop_events(h);
   for (int r = 0; r < 2; ++r)
     if (h->reg[r]) (void)hipFree(h->reg[r]);
   if (h->scratch_base) (void)hipFree(h->scratch_base);
@@ -230,9 +249,11 @@ int athmhd_step(athmhd_t h, double* cons, double* bface, double dt, int nblocks,
     // the VL2 predictor always uses donor-cell fluxes (Sec. 3.2.3)
     const int recon = (h->cfg.integrator == ATHMHD_VL2 && st == 0) ? ATHMHD_RECON_DC : h->cfg.recon;
     StageCoef cf{sc.g0[st], sc.g1[st], sc.beta[st] * dt};
+    if ((e = mark(h, s)) != hipSuccess) return hip_fail(h, e, "profiling event");
     e = launch_stage_unfused(g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc, xb, cons, bface, oc, ob,
                              cf, nblocks, h->scr, h->d_bad, s);
     if (e != hipSuccess) return hip_fail(h, e, "stage launch");
+    if ((e = mark(h, s)) != hipSuccess) return hip_fail(h, e, "profiling event");
     xc = oc;
     xb = ob;
   }
@@ -278,6 +299,31 @@ int athmhd_newdt(athmhd_t h, const double* cons, const double* bface, int nblock
     (void)hipStreamSynchronize(s);
     return fail(h, ATHMHD_ENONPHYS, "%d non-physical cell evaluations (rho <= 0, P <= 0 or not finite)", bad);
   }
+  return ATHMHD_OK;
+}
+
+int athmhd_profile(athmhd_t h, int enable, double* total_ms, int* launches) {
+  if (!h) return ATHMHD_EINVAL;
+  if (enable) {
+    drop_events(h);
+    h->profiling = true;
+    return ATHMHD_OK;
+  }
+  h->profiling = false;
+  double sum = 0.0;
+  int n = 0;
+  for (size_t q = 0; q + 1 < h->events.size(); q += 2) {
+    hipError_t e = hipEventSynchronize(h->events[q + 1]);
+    if (e != hipSuccess) return hip_fail(h, e, "profiling event synchronise");
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, h->events[q], h->events[q + 1]);
+    if (e != hipSuccess) return hip_fail(h, e, "profiling elapsed time");
+    sum += ms;
+    ++n;
+  }
+  drop_events(h);
+  if (total_ms) *total_ms = sum;
+  if (launches) *launches = n;
   return ATHMHD_OK;
 }
 
