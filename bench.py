@@ -39,6 +39,7 @@ def parse():
     p.add_argument("--seed", type=int, default=1)
     p.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle timing")
     p.add_argument("--cpu-steps", type=int, default=1, help="oracle steps in the CPU baseline sample")
+    p.add_argument("--kernel-path", default="fused", choices=["fused", "unfused"])
     return p.parse_args()
 
 
@@ -80,7 +81,7 @@ def main():
     n = args.n
     block = inputs.turbulence(n=n, seed=args.seed)
     solver = athmhd.Solver(block.n, block.ng, block.dx, block.gamma, recon="plm", riemann="hlld",
-                           integrator="vl2", cfl=0.3)
+                           integrator="vl2", cfl=0.3, kernel_path=args.kernel_path)
     tb = torch.from_numpy(block.bface).to(dev)
     tc = solver.prim2cons(torch.from_numpy(block.prim).to(dev), tb)
     torch.cuda.synchronize()
@@ -133,7 +134,7 @@ def main():
             "workload": f"decaying MHD turbulence {n}^3 periodic, VL2+PLM+HLLD+CT, gamma 5/3, rms Mach 1, "
                         f"B = 0.5 x + curl A (rms 0.1), CFL 0.3, dt from newdt every step",
             "cells": zones, "nghost": g, "integrator": "vl2", "recon": "plm", "riemann": "hlld",
-            "seed": args.seed,
+            "seed": args.seed, "kernel_path": args.kernel_path,
         },
         "roofline": {
             "bound": "hbm",

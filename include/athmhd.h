@@ -75,7 +75,8 @@ typedef struct {
   int32_t recon;           /* ATHMHD_RECON_*                                       */
   int32_t riemann;         /* ATHMHD_RS_*                                          */
   int32_t integrator;      /* ATHMHD_RK1 / VL2 / RK2 / RK3                         */
-  int32_t reserved;        /* must be 0                                            */
+  int32_t kernel_path;     /* 0: one fused kernel per stage (default);             */
+                           /* 1: unfused pipeline of simple kernels (reference)    */
   double cfl;              /* Courant number C0 for athmhd_newdt, in (0, 1]        */
   double ct_eps;           /* 0: CT upwinding by the sign of the face mass flux    */
                            /* (Gardiner & Stone 2005); > 0: continuous weight      */

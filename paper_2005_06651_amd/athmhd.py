@@ -36,7 +36,7 @@ class Config(C.Structure):
     _fields_ = [("n1", C.c_int32), ("n2", C.c_int32), ("n3", C.c_int32), ("nghost", C.c_int32),
                 ("gamma", C.c_double), ("dx1", C.c_double), ("dx2", C.c_double), ("dx3", C.c_double),
                 ("recon", C.c_int32), ("riemann", C.c_int32), ("integrator", C.c_int32),
-                ("reserved", C.c_int32), ("cfl", C.c_double), ("ct_eps", C.c_double)]
+                ("kernel_path", C.c_int32), ("cfl", C.c_double), ("ct_eps", C.c_double)]
 
 
 _lib = None
@@ -65,11 +65,14 @@ def lib():
     return _lib
 
 
+KERNEL_PATH = {"fused": 0, "unfused": 1}
+
+
 def make_config(n, nghost, dx, gamma, recon="plm", riemann="hlld", integrator="vl2", cfl=0.3,
-                ct_eps=0.0) -> Config:
+                ct_eps=0.0, kernel_path="fused") -> Config:
     return Config(int(n[0]), int(n[1]), int(n[2]), int(nghost), float(gamma), float(dx[0]), float(dx[1]),
-                  float(dx[2]), RECON[recon], RIEMANN[riemann], INTEGRATOR[integrator], 0, float(cfl),
-                  float(ct_eps))
+                  float(dx[2]), RECON[recon], RIEMANN[riemann], INTEGRATOR[integrator],
+                  KERNEL_PATH[kernel_path], float(cfl), float(ct_eps))
 
 
 def _check(rc: int, h) -> None:
@@ -93,11 +96,11 @@ class Solver:
     when nb == 1)."""
 
     def __init__(self, n, nghost, dx, gamma, recon="plm", riemann="hlld", integrator="vl2", cfl=0.3,
-                 ct_eps=0.0, nblocks=1):
+                 ct_eps=0.0, nblocks=1, kernel_path="fused"):
         self.n = tuple(int(x) for x in n)
         self.ng = int(nghost)
         self.nblocks = int(nblocks)
-        self.cfg = make_config(n, nghost, dx, gamma, recon, riemann, integrator, cfl, ct_eps)
+        self.cfg = make_config(n, nghost, dx, gamma, recon, riemann, integrator, cfl, ct_eps, kernel_path)
         h = C.c_void_p()
         rc = lib().athmhd_create(C.byref(self.cfg), self.nblocks, C.byref(h))
         if rc != OK:

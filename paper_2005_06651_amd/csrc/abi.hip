@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -26,6 +27,8 @@ struct athmhd_s {
   unsigned long long* d_dt = nullptr;   // running min of dx/(|v|+cf), bit pattern
   int* d_bad = nullptr;                 // non-physical cells met since the last newdt
   void* h_pinned = nullptr;             // 16 bytes of pinned host memory for newdt
+  int kz = 0;                           // x3 planes per fused workgroup (0: default)
+  int occ = 1;                          // register target of the fused kernel (waves per SIMD)
   bool profiling = false;
   std::vector<hipEvent_t> events;       // (start, stop) pairs around stage kernels
   std::string err;
@@ -99,7 +102,8 @@ int validate_cfg(const athmhd_config* c) {
     return fail(nullptr, ATHMHD_EINVAL, "cfl must be in (0, 1] (got %g)", c->cfl);
   if (!(std::isfinite(c->ct_eps) && c->ct_eps >= 0.0))
     return fail(nullptr, ATHMHD_EINVAL, "ct_eps must be finite and >= 0 (got %g)", c->ct_eps);
-  if (c->reserved != 0) return fail(nullptr, ATHMHD_EINVAL, "reserved field must be 0");
+  if (c->kernel_path != 0 && c->kernel_path != 1)
+    return fail(nullptr, ATHMHD_EINVAL, "kernel_path must be 0 (fused) or 1 (unfused)");
   const double faces = (double)(c->n1 + 2 * c->nghost + 1) * (c->n2 + 2 * c->nghost + 1) * (c->n3 + 2 * c->nghost + 1);
   if (faces >= 2147483647.0) return fail(nullptr, ATHMHD_EINVAL, "block too large for 32-bit in-array indices");
   return ATHMHD_OK;
@@ -162,7 +166,8 @@ int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
     return rc;
   }
   const int64_t state = (h->g.cblock + h->g.fblock) * (int64_t)nblocks_max;
-  const int64_t nscr = (8 * h->g.cvar + 24 * h->g.fvar + 3 * h->g.fvar) * (int64_t)nblocks_max;
+  const int64_t nscr =
+      cfg->kernel_path == 1 ? (8 * h->g.cvar + 24 * h->g.fvar + 3 * h->g.fvar) * (int64_t)nblocks_max : 1;
   bool ok = hipMalloc(&h->reg[0], state * sizeof(double)) == hipSuccess &&
             hipMalloc(&h->reg[1], state * sizeof(double)) == hipSuccess &&
             hipMalloc(&h->scratch_base, nscr * sizeof(double)) == hipSuccess &&
@@ -184,6 +189,8 @@ int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
     p += 8 * h->g.fvar * nblocks_max;
   }
   h->scr.edge = p;
+  if (const char* kz = getenv("ATHMHD_KZ")) h->kz = atoi(kz);
+  if (const char* oc = getenv("ATHMHD_OCC")) h->occ = atoi(oc) == 2 ? 2 : 1;
   hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, nullptr, h->d_dt, 0ull, h->d_bad, 1);
   e = hipDeviceSynchronize();
   if (e != hipSuccess) {
@@ -250,8 +257,12 @@ int athmhd_step(athmhd_t h, double* cons, double* bface, double dt, int nblocks,
     const int recon = (h->cfg.integrator == ATHMHD_VL2 && st == 0) ? ATHMHD_RECON_DC : h->cfg.recon;
     StageCoef cf{sc.g0[st], sc.g1[st], sc.beta[st] * dt};
     if ((e = mark(h, s)) != hipSuccess) return hip_fail(h, e, "profiling event");
-    e = launch_stage_unfused(g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc, xb, cons, bface, oc, ob,
-                             cf, nblocks, h->scr, h->d_bad, s);
+    if (h->cfg.kernel_path == 0)
+      e = launch_stage_fused(g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc, xb, cons, bface, oc, ob, cf,
+                             nblocks, h->kz, h->occ, h->d_bad, s);
+    else
+      e = launch_stage_unfused(g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc, xb, cons, bface, oc, ob,
+                               cf, nblocks, h->scr, h->d_bad, s);
     if (e != hipSuccess) return hip_fail(h, e, "stage launch");
     if ((e = mark(h, s)) != hipSuccess) return hip_fail(h, e, "profiling event");
     xc = oc;

@@ -33,6 +33,14 @@ hipError_t launch_stage_unfused(const Geo& g, double gamma, int recon, int rs, d
                                 double* outb, StageCoef coef, int nb, UnfusedScratch& scr, int* bad,
                                 hipStream_t s);
 
+// One stage in a single fused kernel (same contract as launch_stage_unfused);
+// kz = x3 planes per workgroup segment (0: default for the block size);
+// occ = register-allocation target in waves per SIMD (1 or 2).
+hipError_t launch_stage_fused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
+                              const double* xb, const double* unc, const double* unb, double* outc, double* outb,
+                              StageCoef coef, int nb, int kz, int occ, int* bad, hipStream_t s);
+int fused_default_kz(const Geo& g);
+
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
 
 }  // namespace athmhd

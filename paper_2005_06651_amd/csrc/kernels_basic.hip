@@ -1,4 +1,5 @@
 // kernels_basic.hip -- ghost fill, prim->cons, CFL time step and copy kernels.
+#include <algorithm>
 #include <cfloat>
 
 #include "common.hpp"
@@ -14,17 +15,40 @@ constexpr int kThreads = 256;
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 // Ghost cells and the periodic image faces (Sec. 2.1.1; a periodic block is
-// its own neighbour).  One thread per entry of the padded face grid; threads
-// on active entries exit.
+// its own neighbour).  Only the shell of stored entries outside the active box
+// is visited: whole ghost planes along x3, then ghost rows along x2 of the
+// active planes, then ghost entries along x1 of the active rows.  Every
+// source is an active entry, so the three regions are independent.
+__host__ __device__ __forceinline__ int ghost_index(int q, int n, int ng) { return q < ng ? q : q + n; }
+
 __global__ void __launch_bounds__(kThreads) k_fill_ghosts(Geo g, double* __restrict__ cons,
                                                          double* __restrict__ bface) {
   const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (t >= g.fvar) return;
-  const int i = (int)(t % g.F1);
-  const int r = (int)(t / g.F1);
-  const int j = r % g.F2, k = r / g.F2;
+  const int64_t nz = (int64_t)(g.F3 - g.n3) * g.F2 * g.F1;
+  const int64_t ny = (int64_t)g.n3 * (g.F2 - g.n2) * g.F1;
+  const int64_t nx = (int64_t)g.n3 * g.n2 * (g.F1 - g.n1);
+  int i, j, k;
+  if (t < nz) {
+    i = (int)(t % g.F1);
+    const int64_t r = t / g.F1;
+    j = (int)(r % g.F2);
+    k = ghost_index((int)(r / g.F2), g.n3, g.ng);
+  } else if (t < nz + ny) {
+    const int64_t u = t - nz;
+    i = (int)(u % g.F1);
+    const int64_t r = u / g.F1;
+    j = ghost_index((int)(r % (g.F2 - g.n2)), g.n2, g.ng);
+    k = g.ng + (int)(r / (g.F2 - g.n2));
+  } else if (t < nz + ny + nx) {
+    const int64_t u = t - nz - ny;
+    i = ghost_index((int)(u % (g.F1 - g.n1)), g.n1, g.ng);
+    const int64_t r = u / (g.F1 - g.n1);
+    j = g.ng + (int)(r % g.n2);
+    k = g.ng + (int)(r / g.n2);
+  } else {
+    return;
+  }
   const int ii = wrap_index(i, g.n1, g.ng), jj = wrap_index(j, g.n2, g.ng), kk = wrap_index(k, g.n3, g.ng);
-  if (ii == i && jj == j && kk == k) return;
   double* cb = cons + blockIdx.y * g.cblock;
   double* fb = bface + blockIdx.y * g.fblock;
   if (i < g.N1 && j < g.N2 && k < g.N3) {
@@ -35,6 +59,11 @@ __global__ void __launch_bounds__(kThreads) k_fill_ghosts(Geo g, double* __restr
   const int d = g.f(i, j, k), s = g.f(ii, jj, kk);
 #pragma unroll
   for (int c = 0; c < 3; ++c) fb[c * g.fvar + d] = fb[c * g.fvar + s];
+}
+
+inline int64_t ghost_count(const Geo& g) {
+  return (int64_t)(g.F3 - g.n3) * g.F2 * g.F1 + (int64_t)g.n3 * (g.F2 - g.n2) * g.F1 +
+         (int64_t)g.n3 * g.n2 * (g.F1 - g.n1);
 }
 
 // Conserved variables from primitives with the cell-centred field (mean of the
@@ -63,40 +92,45 @@ __global__ void __launch_bounds__(kThreads) k_prim2cons(Geo g, double gamma, con
 }
 
 // Smallest dx_d / (|v_d| + c_f,d) over the active cells (Sec. 2.1.6, Sec. 3.2.3).
-// Wavefront min by cross-lane shuffles, then LDS across the workgroup, then one
-// atomicMin on the bit pattern (non-negative doubles order like their bits).
+// Grid-stride loop per thread, wavefront min by cross-lane shuffles, LDS
+// across the workgroup, then one atomicMin per workgroup on the bit pattern
+// (non-negative doubles order like their bits).
+constexpr int kDtBlocks = 1024;
+
 __global__ void __launch_bounds__(kThreads) k_newdt(Geo g, double gamma, const double* __restrict__ cons,
                                                    const double* __restrict__ bface,
                                                    unsigned long long* __restrict__ dt_bits,
                                                    int* __restrict__ bad) {
-  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int64_t nact = (int64_t)g.n1 * g.n2 * g.n3;
+  const double* u = cons + blockIdx.y * g.cblock;
+  const double* fb = bface + blockIdx.y * g.fblock;
   double best = DBL_MAX;
-  if (t < nact) {
+  int nbad = 0;
+  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < nact; t += (int64_t)gridDim.x * kThreads) {
     const int i = g.ng + (int)(t % g.n1);
     const int r = (int)(t / g.n1);
     const int j = g.ng + r % g.n2, k = g.ng + r / g.n2;
-    const double* u = cons + blockIdx.y * g.cblock;
-    const double* fb = bface + blockIdx.y * g.fblock;
-    const int q = g.c(i, j, k);
-    const double b1 = 0.5 * (fb[g.f(i, j, k)] + fb[g.f(i + 1, j, k)]);
-    const double b2 = 0.5 * (fb[g.fvar + g.f(i, j, k)] + fb[g.fvar + g.f(i, j + 1, k)]);
-    const double b3 = 0.5 * (fb[2 * g.fvar + g.f(i, j, k)] + fb[2 * g.fvar + g.f(i, j, k + 1)]);
-    const double rho = u[q], ir = 1.0 / rho;
+    const int q = g.c(i, j, k), f = g.f(i, j, k);
+    const double b1 = 0.5 * (fb[f] + fb[f + 1]);
+    const double b2 = 0.5 * (fb[g.fvar + f] + fb[g.fvar + f + g.F1]);
+    const double b3 = 0.5 * (fb[2 * g.fvar + f] + fb[2 * g.fvar + f + g.F1 * g.F2]);
+    const double rho = u[q], ir = frcp(rho);
     const double v1 = u[g.cvar + q] * ir, v2 = u[2 * g.cvar + q] * ir, v3 = u[3 * g.cvar + q] * ir;
     const double p = (gamma - 1.0) * (u[4 * g.cvar + q] - 0.5 * rho * (v1 * v1 + v2 * v2 + v3 * v3) -
                                       0.5 * (b1 * b1 + b2 * b2 + b3 * b3));
+    if (!(rho > 0.0) || !(p > 0.0)) {
+      ++nbad;
+      continue;
+    }
     const double bs1 = b1 * b1, bs2 = b2 * b2, bs3 = b3 * b3;
     const double c1 = fast_speed(ir, p, bs1, bs2 + bs3, gamma);
     const double c2 = fast_speed(ir, p, bs2, bs3 + bs1, gamma);
     const double c3 = fast_speed(ir, p, bs3, bs1 + bs2, gamma);
-    const double d = fmin(g.dx1 / (fabs(v1) + c1), fmin(g.dx2 / (fabs(v2) + c2), g.dx3 / (fabs(v3) + c3)));
-    if (!(rho > 0.0) || !(p > 0.0) || !(d > 0.0) || !(d < DBL_MAX)) {
-      atomicAdd(bad, 1);
-    } else {
-      best = d;
-    }
+    const double d = fmin(g.dx1 * frcp(fabs(v1) + c1), fmin(g.dx2 * frcp(fabs(v2) + c2), g.dx3 * frcp(fabs(v3) + c3)));
+    if (!(d > 0.0) || !(d < DBL_MAX)) ++nbad;
+    else best = fmin(best, d);
   }
+  if (nbad) atomicAdd(bad, nbad);
   // wavefront minimum
   for (int off = 32; off > 0; off >>= 1) best = fmin(best, __shfl_xor(best, off, 64));
   __shared__ double part[kThreads / 64];
@@ -118,7 +152,7 @@ __global__ void __launch_bounds__(kThreads) k_copy(double* __restrict__ dst, con
 }  // namespace
 
 hipError_t launch_fill_ghosts(const Geo& g, double* cons, double* bface, int nb, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_ghosts, dim3(grid_for(g.fvar), nb), dim3(kThreads), 0, s, g, cons, bface);
+  hipLaunchKernelGGL(k_fill_ghosts, dim3(grid_for(ghost_count(g)), nb), dim3(kThreads), 0, s, g, cons, bface);
   return hipGetLastError();
 }
 
@@ -131,8 +165,8 @@ hipError_t launch_prim2cons(const Geo& g, double gamma, const double* prim, cons
 hipError_t launch_newdt(const Geo& g, double gamma, const double* cons, const double* bface, int nb,
                         unsigned long long* dt_bits, int* bad, hipStream_t s) {
   const int64_t nact = (int64_t)g.n1 * g.n2 * g.n3;
-  hipLaunchKernelGGL(k_newdt, dim3(grid_for(nact), nb), dim3(kThreads), 0, s, g, gamma, cons, bface, dt_bits,
-                     bad);
+  const unsigned blocks = (unsigned)std::min<int64_t>(grid_for(nact), kDtBlocks);
+  hipLaunchKernelGGL(k_newdt, dim3(blocks, nb), dim3(kThreads), 0, s, g, gamma, cons, bface, dt_bits, bad);
   return hipGetLastError();
 }
 

@@ -1,0 +1,511 @@
+// kernels_fused.hip -- one stage of the MHD update in a single kernel.
+//
+// Each workgroup (16 x 16 threads) owns a tile of 14 x 14 active columns in
+// (x1, x2) plus a one-cell ring, and marches along x3 over a segment of KZ
+// planes.  Per plane everything stays on chip:
+//   * every thread owns one column of the 16 x 16 region; it converts its
+//     column's conserved state to primitives (Sec. 3.1) one plane ahead of use
+//     and keeps a short window of planes in registers for the reconstruction
+//     along x3;
+//   * the primitives of the current plane, plus LA extra rings, go to LDS for
+//     the reconstructions along x1 and x2 (DC / PLM / PPM, Sec. 3.2.1);
+//   * each thread solves the Riemann problems (HLLD / HLLE, Sec. 3.2.2) on the
+//     lower x1-face and x2-face of its column in this plane and on the lower
+//     x3-face of its column's cell;
+//   * face fluxes, face EMFs, upwind weights and cell-centred EMFs are
+//     exchanged through LDS to form the upwind-CT corner EMFs (Sec. 3.1);
+//   * the flux divergence and the CT curl accumulate in registers and the
+//     plane below is written out once its upper x3 fluxes / EMFs exist
+//     (2S stage update, Eq. (rk-2s)).
+// HBM traffic per stage is the input state (with the halo overlap of
+// neighbouring tiles), U^n where the stage needs it, and the output state.
+#include "common.hpp"
+#include "kernels.hpp"
+#include "mhd_math.hpp"
+
+namespace athmhd {
+
+namespace {
+
+constexpr int BX = 16, BY = 16, NT = BX * BY;  // threads per workgroup
+constexpr int TX = BX - 2, TY = BY - 2;        // active columns per tile
+
+struct FusedArgs {
+  Geo g;
+  Gas gas;
+  double ct_eps;
+  const double* xc;   // stage input, ghosts filled
+  const double* xb;
+  const double* unc;  // U^n (the u^(1) register)
+  const double* unb;
+  double* oc;         // stage output (active cells and their lower faces)
+  double* ob;
+  StageCoef cf;
+  int ntx, nty, nseg, kz;
+  int64_t total;      // workgroups doing work
+  int64_t per_xcd;    // ceil(total / 8)
+  int* bad;
+};
+
+// z-frame primitive vector of a cell: (rho, v3, v1, v2, P, B1cc, B2cc) plus
+// B3cc kept alongside
+struct ZCell {
+  double q[7];
+  double b3;
+};
+
+// Raw data of one cell needed to form its primitives.
+struct Raw {
+  double u[5];
+  double b1lo, b1hi, b2lo, b2hi, b3lo, b3hi;
+};
+
+__device__ __forceinline__ void load_raw(const Geo& g, const double* __restrict__ xc, const double* __restrict__ xb,
+                                         int i, int j, int k, Raw& r) {
+  const int q = g.c(i, j, k);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) r.u[v] = xc[v * g.cvar + q];
+  const int f = g.f(i, j, k);
+  r.b1lo = xb[f];
+  r.b1hi = xb[f + 1];
+  r.b2lo = xb[g.fvar + f];
+  r.b2hi = xb[g.fvar + f + g.F1];
+  r.b3lo = xb[2 * g.fvar + f];
+  r.b3hi = xb[2 * g.fvar + f + g.F1 * g.F2];
+}
+
+// cons -> prim: w = (rho, v1, v2, v3, P, B1cc, B2cc, B3cc)
+__device__ __forceinline__ bool to_prim(const Raw& r, double gm1, double* w) {
+  const double b1 = 0.5 * (r.b1lo + r.b1hi), b2 = 0.5 * (r.b2lo + r.b2hi), b3 = 0.5 * (r.b3lo + r.b3hi);
+  const double rho = r.u[0], ir = frcp(rho);
+  const double v1 = r.u[1] * ir, v2 = r.u[2] * ir, v3 = r.u[3] * ir;
+  const double p = gm1 * (r.u[4] - 0.5 * rho * (v1 * v1 + v2 * v2 + v3 * v3) - 0.5 * (b1 * b1 + b2 * b2 + b3 * b3));
+  w[0] = rho; w[1] = v1; w[2] = v2; w[3] = v3; w[4] = p; w[5] = b1; w[6] = b2; w[7] = b3;
+  return rho > 0.0 && p > 0.0;
+}
+
+__device__ __forceinline__ void to_zcell(const double* w, ZCell& z) {
+  z.q[0] = w[0]; z.q[1] = w[3]; z.q[2] = w[1]; z.q[3] = w[2]; z.q[4] = w[4]; z.q[5] = w[5]; z.q[6] = w[6];
+  z.b3 = w[7];
+}
+
+// Reconstruct the two edge values of cell c from a line of cells centred on
+// it: s[LA + o] = q_{c+o}, o in [-LA, LA]; returns (left edge, right edge).
+template <int RECON>
+__device__ __forceinline__ void cell_edges(const double* s, double& left, double& right) {
+  if (RECON == 0) {
+    left = s[0];
+    right = s[0];
+  } else if (RECON == 1) {
+    const double d = vl_slope(s[0], s[1], s[2]);
+    left = s[1] - 0.5 * d;
+    right = s[1] + 0.5 * d;
+  } else {
+    double qm = ppm_face(s[0], s[1], s[2], s[3]);
+    double qp = ppm_face(s[1], s[2], s[3], s[4]);
+    ppm_cell(s[0], s[1], s[2], s[3], s[4], qm, qp);
+    left = qm;
+    right = qp;
+  }
+}
+
+__device__ __forceinline__ FaceState make_state(const double* q) {
+  FaceState s;
+  s.rho = q[0]; s.vn = q[1]; s.vt1 = q[2]; s.vt2 = q[3]; s.p = q[4]; s.bt1 = q[5]; s.bt2 = q[6];
+  return s;
+}
+
+template <int RS>
+__device__ __forceinline__ void riemann(const double* ql, const double* qr, double bn, const Gas& gas, double ct_eps,
+                                        FaceFlux& F, double& w) {
+  FaceState L = make_state(ql), R = make_state(qr);
+  double smax;
+  if (RS == 1) hlld(L, R, bn, gas, F, smax);
+  else hlle(L, R, bn, gas, F, smax);
+  w = ct_weight(F.rho, 0.5 * (L.rho + R.rho), smax, ct_eps);
+}
+
+// LDS layout: the primitive plane (with LA extra rings), the per-thread
+// exchange slots and the corner EMFs are separate, so a thread can publish
+// each Riemann result as soon as it has it.
+template <int LA>
+struct Smem {
+  static constexpr int PW = BX + 2 * LA;  // width of the primitive plane incl. extra rings
+  static constexpr int PH = BY + 2 * LA;
+  static constexpr int PL = PW * PH;
+};
+
+enum {
+  X_FX = 0, X_FY = 5, X_E3X = 10, X_WX, X_E3Y, X_WY, X_E3C, X_E1Z, X_E2Z, X_WZ, X_E1C, X_E2C, X_E1CP, X_E2CP, X_N
+};
+
+// OCC: minimum waves per SIMD the register allocation must allow (1 lets the
+// compiler use the whole register file, 2 caps it at 256 with some spilling).
+template <int RECON, int RS, int OCC>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) k_stage_fused(FusedArgs a) {
+  constexpr int LA = RECON;  // cells of look-ahead / extra LDS rings: DC 0, PLM 1, PPM 2
+  constexpr int NW = 2 * LA + 1;
+  using S = Smem<LA>;
+  constexpr int PW = S::PW, PL = S::PL;
+  __shared__ double sp[8 * PL];    // primitives of the current plane
+  __shared__ double sx[X_N * NT];  // exchange slots
+  __shared__ double sc[3 * NT];    // corner EMFs E1, E2, E3 of the current (half-)plane
+
+  // ---- workgroup -> (tile, segment, block), XCD-aware: consecutive logical
+  // tiles land on the same XCD so that halo overlap hits its L2
+  const int64_t bid = blockIdx.x;
+  const int64_t logical = (bid % 8) * a.per_xcd + bid / 8;
+  if (logical >= a.total) return;
+  const Geo& g = a.g;
+  int64_t r = logical;
+  const int tile_x = (int)(r % a.ntx); r /= a.ntx;
+  const int tile_y = (int)(r % a.nty); r /= a.nty;
+  const int seg = (int)(r % a.nseg); r /= a.nseg;
+  const int blk = (int)r;
+  const double* xc = a.xc + blk * g.cblock;
+  const double* xb = a.xb + blk * g.fblock;
+  const double* unc = a.unc + blk * g.cblock;
+  const double* unb = a.unb + blk * g.fblock;
+  double* oc = a.oc + blk * g.cblock;
+  double* ob = a.ob + blk * g.fblock;
+
+  const int tid = threadIdx.x;
+  const int tx = tid % BX, ty = tid / BX;
+  const int x0 = g.ng + tile_x * TX, y0 = g.ng + tile_y * TY;
+  // own column (clamped into the array; columns outside the block only feed
+  // values that are never written out)
+  const int gi_raw = x0 - 1 + tx, gj_raw = y0 - 1 + ty;
+  const int gi = min(gi_raw, g.N1 - 1), gj = min(gj_raw, g.N2 - 1);
+  const bool act = tx >= 1 && tx <= TX && ty >= 1 && ty <= TY && gi_raw < g.ng + g.n1 && gj_raw < g.ng + g.n2;
+  const int k0 = g.ng + seg * a.kz;
+  const int kend = min(k0 + a.kz, g.ng + g.n3);  // exclusive
+
+  // ---- extra LDS rings (LA per side), one cell per thread for tid < 64 LA
+  constexpr int NRING = 64 * LA;
+  const bool ring = tid < NRING;
+  int rl = 0, rgi = 0, rgj = 0;
+  if (ring) {
+    const int side = tid / (16 * LA), e = tid % (16 * LA), d = e / 16, pos = e % 16;
+    int rlx, rly;
+    if (side == 0) { rlx = LA - 1 - d; rly = LA + pos; }
+    else if (side == 1) { rlx = LA + 16 + d; rly = LA + pos; }
+    else if (side == 2) { rlx = LA + pos; rly = LA - 1 - d; }
+    else { rlx = LA + pos; rly = LA + 16 + d; }
+    rl = rly * PW + rlx;
+    rgi = min(max(x0 - 1 - LA + rlx, 0), g.N1 - 1);
+    rgj = min(max(y0 - 1 - LA + rly, 0), g.N2 - 1);
+  }
+
+  const double i1 = 1.0 / g.dx1, i2 = 1.0 / g.dx2, i3 = 1.0 / g.dx3;
+  const double gm1 = a.gas.gm1;
+  int nbad = 0;
+
+  // ---- z window: planes p-LA .. p+LA of the own column
+  ZCell win[NW];
+  {
+    double w[8];
+    Raw raw;
+#pragma unroll
+    for (int o = 0; o < NW - 1; ++o) {
+      load_raw(g, xc, xb, gi, gj, k0 - 1 - LA + o, raw);
+      nbad += !to_prim(raw, gm1, w);
+      to_zcell(w, win[o + 1]);
+    }
+  }
+  Raw pre;  // raw data of the next look-ahead plane
+  load_raw(g, xc, xb, gi, gj, k0 - 1 + LA, pre);
+
+  double qz_carry[7];  // left state of the next x3-face (right edge of the cell below)
+  double e2x_prev = 0.0, wx_prev = 0.5, e1y_prev = 0.0, wy_prev = 0.5, e1c_prev = 0.0, e2c_prev = 0.0;
+  double acc_prev[7];  // partial update of the plane below: 5 conserved, B1, B2
+#pragma unroll
+  for (int v = 0; v < 7; ++v) { acc_prev[v] = 0.0; qz_carry[v] = 0.0; }
+
+  for (int p = k0 - 1; p <= kend; ++p) {
+    const bool zface = p >= k0;
+    // ---- 1. ring cells of plane p: issue their loads first
+    Raw rraw;
+    if (ring) load_raw(g, xc, xb, rgi, rgj, p, rraw);
+
+    // ---- 2. shift the window and convert the look-ahead plane p+LA
+#pragma unroll
+    for (int o = 0; o < NW - 1; ++o) win[o] = win[o + 1];
+    {
+      double w[8];
+      nbad += !to_prim(pre, gm1, w);
+      to_zcell(w, win[NW - 1]);
+    }
+
+    // ---- 3. own cell of plane p: primitives to LDS, cell EMFs to the exchange
+    double e1c, e2c;
+    {
+      const ZCell& cur = win[LA];
+      const int l = (ty + LA) * PW + tx + LA;
+      sp[0 * PL + l] = cur.q[0];
+      sp[1 * PL + l] = cur.q[2];
+      sp[2 * PL + l] = cur.q[3];
+      sp[3 * PL + l] = cur.q[1];
+      sp[4 * PL + l] = cur.q[4];
+      sp[5 * PL + l] = cur.q[5];
+      sp[6 * PL + l] = cur.q[6];
+      sp[7 * PL + l] = cur.b3;
+      // E = -v x B at the cell centre
+      const double v1 = cur.q[2], v2 = cur.q[3], v3 = cur.q[1];
+      const double b1c = cur.q[5], b2c = cur.q[6], b3c = cur.b3;
+      e1c = -(v2 * b3c - v3 * b2c);
+      e2c = -(v3 * b1c - v1 * b3c);
+      sx[X_E3C * NT + tid] = -(v1 * b2c - v2 * b1c);
+      sx[X_E1C * NT + tid] = e1c;
+      sx[X_E2C * NT + tid] = e2c;
+      sx[X_E1CP * NT + tid] = e1c_prev;
+      sx[X_E2CP * NT + tid] = e2c_prev;
+    }
+
+    // ---- 4. ring cells to LDS
+    if (ring) {
+      double w[8];
+      to_prim(rraw, gm1, w);
+#pragma unroll
+      for (int v = 0; v < 8; ++v) sp[v * PL + rl] = w[v];
+    }
+
+    // ---- 5. reconstruction along x3 and the Riemann problem on the lower
+    // x3-face (p-1/2) of the own cell
+    double fz_cons[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    {
+      double zl[7], zr[7];
+#pragma unroll
+      for (int v = 0; v < 7; ++v) {
+        double line[NW];
+#pragma unroll
+        for (int o = 0; o < NW; ++o) line[o] = win[o].q[v];
+        double left, right;
+        cell_edges<RECON>(line, left, right);
+        zl[v] = qz_carry[v];
+        zr[v] = left;
+        qz_carry[v] = right;
+      }
+      double wz = 0.5, e1z = 0.0, e2z = 0.0;
+      if (zface) {
+        const double bn3 = xb[2 * g.fvar + g.f(gi, gj, p)];
+        FaceFlux fz;
+        riemann<RS>(zl, zr, bn3, a.gas, a.ct_eps, fz, wz);
+        // z-frame -> (rho, M1, M2, M3, E); x3-face E2 = -F(B1), E1 = +F(B2)
+        fz_cons[0] = fz.rho; fz_cons[1] = fz.mt1; fz_cons[2] = fz.mt2; fz_cons[3] = fz.mn; fz_cons[4] = fz.e;
+        e2z = -fz.bt1;
+        e1z = fz.bt2;
+      }
+      sx[X_E1Z * NT + tid] = e1z;
+      sx[X_E2Z * NT + tid] = e2z;
+      sx[X_WZ * NT + tid] = wz;
+    }
+    __syncthreads();
+
+    // ---- 6. Riemann problems on the lower x1-face and x2-face in plane p
+    double e2x = 0.0, wx = 0.5, e1y = 0.0, wy = 0.5;
+    {
+      double e3x = 0.0;
+      if (tx >= 1) {
+        double ql[7], qr[7];
+        const int row = (ty + LA) * PW + tx + LA;
+        // x-frame order: rho, v1, v2, v3, P, B2, B3
+        const int map[7] = {0, 1, 2, 3, 4, 6, 7};
+#pragma unroll
+        for (int v = 0; v < 7; ++v) {
+          const double* s = sp + map[v] * PL + row;
+          double lineL[NW], lineR[NW];
+#pragma unroll
+          for (int o = 0; o < NW; ++o) {
+            lineL[o] = s[o - LA - 1];
+            lineR[o] = s[o - LA];
+          }
+          double a0, a1, b0, b1;
+          cell_edges<RECON>(lineL, a0, a1);
+          cell_edges<RECON>(lineR, b0, b1);
+          ql[v] = a1;
+          qr[v] = b0;
+        }
+        const double bn1 = xb[g.f(gi, gj, p)];
+        FaceFlux fx;
+        riemann<RS>(ql, qr, bn1, a.gas, a.ct_eps, fx, wx);
+        sx[(X_FX + 0) * NT + tid] = fx.rho;
+        sx[(X_FX + 1) * NT + tid] = fx.mn;   // M1
+        sx[(X_FX + 2) * NT + tid] = fx.mt1;  // M2
+        sx[(X_FX + 3) * NT + tid] = fx.mt2;  // M3
+        sx[(X_FX + 4) * NT + tid] = fx.e;
+        // x1-face E3 = -F(B2), E2 = +F(B3)
+        e3x = -fx.bt1;
+        e2x = fx.bt2;
+      }
+      sx[X_E3X * NT + tid] = e3x;
+      sx[X_WX * NT + tid] = wx;
+    }
+    {
+      double e3y = 0.0;
+      if (ty >= 1) {
+        double ql[7], qr[7];
+        const int col = (ty + LA) * PW + tx + LA;
+        // y-frame order: rho, v2, v3, v1, P, B3, B1
+        const int map[7] = {0, 2, 3, 1, 4, 7, 5};
+#pragma unroll
+        for (int v = 0; v < 7; ++v) {
+          const double* s = sp + map[v] * PL + col;
+          double lineL[NW], lineR[NW];
+#pragma unroll
+          for (int o = 0; o < NW; ++o) {
+            lineL[o] = s[(o - LA - 1) * PW];
+            lineR[o] = s[(o - LA) * PW];
+          }
+          double a0, a1, b0, b1;
+          cell_edges<RECON>(lineL, a0, a1);
+          cell_edges<RECON>(lineR, b0, b1);
+          ql[v] = a1;
+          qr[v] = b0;
+        }
+        const double bn2 = xb[g.fvar + g.f(gi, gj, p)];
+        FaceFlux fy;
+        riemann<RS>(ql, qr, bn2, a.gas, a.ct_eps, fy, wy);
+        sx[(X_FY + 0) * NT + tid] = fy.rho;
+        sx[(X_FY + 1) * NT + tid] = fy.mt2;  // M1
+        sx[(X_FY + 2) * NT + tid] = fy.mn;   // M2
+        sx[(X_FY + 3) * NT + tid] = fy.mt1;  // M3
+        sx[(X_FY + 4) * NT + tid] = fy.e;
+        // x2-face E1 = -F(B3), E3 = +F(B1)
+        e1y = -fy.bt1;
+        e3y = fy.bt2;
+      }
+      sx[X_E3Y * NT + tid] = e3y;
+      sx[X_WY * NT + tid] = wy;
+    }
+    // prefetch the look-ahead plane of the next iteration
+    if (p + 1 <= kend) load_raw(g, xc, xb, gi, gj, p + 1 + LA, pre);
+    __syncthreads();
+
+    // ---- 7. corner EMFs of the own edges and the conserved update
+    const int tW = tid - 1, tS = tid - BX, tSW = tid - BX - 1, tE = tid + 1, tN = tid + BX;
+    double c1 = 0.0, c2 = 0.0, c3 = 0.0;
+    if (tx >= 1 && ty >= 1 && p >= k0 && p < kend) {
+      // E3 at (i-1/2, j-1/2, p): a = x1, b = x2
+      c3 = corner_emf(sx[X_E3X * NT + tid], sx[X_E3X * NT + tS], sx[X_E3Y * NT + tid], sx[X_E3Y * NT + tW],
+                      sx[X_E3C * NT + tid], sx[X_E3C * NT + tW], sx[X_E3C * NT + tS], sx[X_E3C * NT + tSW], wx,
+                      sx[X_WX * NT + tS], wy, sx[X_WY * NT + tW]);
+    }
+    if (ty >= 1 && zface) {
+      // E1 at (i, j-1/2, p-1/2): a = x2, b = x3
+      c1 = corner_emf(e1y, e1y_prev, sx[X_E1Z * NT + tid], sx[X_E1Z * NT + tS], e1c, sx[X_E1C * NT + tS],
+                      e1c_prev, sx[X_E1CP * NT + tS], wy, wy_prev, sx[X_WZ * NT + tid], sx[X_WZ * NT + tS]);
+    }
+    if (tx >= 1 && zface) {
+      // E2 at (i-1/2, j, p-1/2): a = x3, b = x1
+      c2 = corner_emf(sx[X_E2Z * NT + tid], sx[X_E2Z * NT + tW], e2x, e2x_prev, e2c, e2c_prev,
+                      sx[X_E2C * NT + tW], sx[X_E2CP * NT + tW], sx[X_WZ * NT + tid], sx[X_WZ * NT + tW], wx,
+                      wx_prev);
+    }
+    sc[0 * NT + tid] = c1;
+    sc[1 * NT + tid] = c2;
+    sc[2 * NT + tid] = c3;
+
+    double acc[7];
+    if (act && zface) {
+      // flux divergence of plane p (x1, x2) and the x3 flux through p-1/2
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const double dfx = sx[(X_FX + v) * NT + tE] - sx[(X_FX + v) * NT + tid];
+        const double dfy = sx[(X_FY + v) * NT + tN] - sx[(X_FY + v) * NT + tid];
+        acc[v] = -(dfx * i1 + dfy * i2) + fz_cons[v] * i3;
+        acc_prev[v] -= fz_cons[v] * i3;
+      }
+      if (p - 1 >= k0) {
+        const int q = g.c(gi, gj, p - 1);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          double y = a.cf.g1 * unc[v * g.cvar + q] + a.cf.bdt * acc_prev[v];
+          if (a.cf.g0 != 0.0) y += a.cf.g0 * xc[v * g.cvar + q];
+          oc[v * g.cvar + q] = y;
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- 8. face-field updates from the corner EMFs
+    if (act && zface) {
+      const double e1 = sc[0 * NT + tid], e2 = sc[1 * NT + tid], e3 = sc[2 * NT + tid];
+      // B1(i-1/2, j): -(E3(j+1/2) - E3(j-1/2))/dx2 + (E2(k+1/2) - E2(k-1/2))/dx3
+      acc[5] = -(sc[2 * NT + tN] - e3) * i2 - e2 * i3;
+      acc_prev[5] += e2 * i3;
+      // B2(i, j-1/2): -(E1(k+1/2) - E1(k-1/2))/dx3 + (E3(i+1/2) - E3(i-1/2))/dx1
+      acc[6] = (sc[2 * NT + tE] - e3) * i1 + e1 * i3;
+      acc_prev[6] -= e1 * i3;
+      // B3(i, j, p-1/2): -(E2(i+1/2) - E2(i-1/2))/dx1 + (E1(j+1/2) - E1(j-1/2))/dx2
+      const double db3 = -(sc[1 * NT + tE] - e2) * i1 + (sc[0 * NT + tN] - e1) * i2;
+      if (p < kend) {
+        const int f = g.f(gi, gj, p);
+        double y = a.cf.g1 * unb[2 * g.fvar + f] + a.cf.bdt * db3;
+        if (a.cf.g0 != 0.0) y += a.cf.g0 * xb[2 * g.fvar + f];
+        ob[2 * g.fvar + f] = y;
+      }
+      if (p - 1 >= k0) {
+        const int f = g.f(gi, gj, p - 1);
+        double y1 = a.cf.g1 * unb[f] + a.cf.bdt * acc_prev[5];
+        double y2 = a.cf.g1 * unb[g.fvar + f] + a.cf.bdt * acc_prev[6];
+        if (a.cf.g0 != 0.0) {
+          y1 += a.cf.g0 * xb[f];
+          y2 += a.cf.g0 * xb[g.fvar + f];
+        }
+        ob[f] = y1;
+        ob[g.fvar + f] = y2;
+      }
+#pragma unroll
+      for (int v = 0; v < 7; ++v) acc_prev[v] = acc[v];
+    }
+
+    // ---- 9. carry this plane's face EMFs / weights / cell EMFs upward
+    e2x_prev = e2x;
+    wx_prev = wx;
+    e1y_prev = e1y;
+    wy_prev = wy;
+    e1c_prev = e1c;
+    e2c_prev = e2c;
+  }
+  if (nbad && act) atomicAdd(a.bad, 1);
+}
+
+template <int RECON>
+hipError_t launch_rs(int rs, int occ, const FusedArgs& fa, hipStream_t s) {
+  const unsigned grid = (unsigned)(8 * fa.per_xcd);
+  if (occ == 2) {
+    if (rs == 1) hipLaunchKernelGGL((k_stage_fused<RECON, 1, 2>), dim3(grid), dim3(NT), 0, s, fa);
+    else hipLaunchKernelGGL((k_stage_fused<RECON, 0, 2>), dim3(grid), dim3(NT), 0, s, fa);
+  } else {
+    if (rs == 1) hipLaunchKernelGGL((k_stage_fused<RECON, 1, 1>), dim3(grid), dim3(NT), 0, s, fa);
+    else hipLaunchKernelGGL((k_stage_fused<RECON, 0, 1>), dim3(grid), dim3(NT), 0, s, fa);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int fused_default_kz(const Geo& g) { return g.n3 >= 64 ? 32 : (g.n3 >= 16 ? 16 : g.n3); }
+
+hipError_t launch_stage_fused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
+                              const double* xb, const double* unc, const double* unb, double* outc, double* outb,
+                              StageCoef coef, int nb, int kz, int occ, int* bad, hipStream_t s) {
+  FusedArgs fa;
+  fa.g = g;
+  fa.gas = Gas{gamma, gamma - 1.0, 1.0 / (gamma - 1.0)};
+  fa.ct_eps = ct_eps;
+  fa.xc = xc; fa.xb = xb; fa.unc = unc; fa.unb = unb; fa.oc = outc; fa.ob = outb;
+  fa.cf = coef;
+  fa.kz = kz > 0 ? kz : fused_default_kz(g);
+  fa.ntx = (g.n1 + TX - 1) / TX;
+  fa.nty = (g.n2 + TY - 1) / TY;
+  fa.nseg = (g.n3 + fa.kz - 1) / fa.kz;
+  fa.total = (int64_t)fa.ntx * fa.nty * fa.nseg * nb;
+  fa.per_xcd = (fa.total + 7) / 8;
+  fa.bad = bad;
+  if (recon == 0) return launch_rs<0>(rs, occ, fa, s);
+  if (recon == 1) return launch_rs<1>(rs, occ, fa, s);
+  return launch_rs<2>(rs, occ, fa, s);
+}
+
+}  // namespace athmhd

@@ -30,20 +30,64 @@ struct Gas {
 
 __device__ __forceinline__ double sqr(double x) { return x * x; }
 
+// Reciprocal: hardware estimate (v_rcp_f64) refined by two Newton-Raphson
+// steps r <- r + r (1 - x r); each step squares the relative error.  x must be
+// finite and non-zero.
+__device__ __forceinline__ double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// a / b through the refined reciprocal plus one residual correction.
+__device__ __forceinline__ double fdiv(double a, double b) {
+  const double r = frcp(b);
+  const double q = a * r;
+  return fma(fma(-b, q, a), r, q);
+}
+
+// 1/sqrt(x), x > 0: hardware estimate (v_rsq_f64) refined by two Newton-Raphson
+// steps r <- r + r (1 - x r^2) / 2.
+__device__ __forceinline__ double frsq(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  double e = fma(-(x * r), r, 1.0);
+  r = fma(0.5 * r, e, r);
+  e = fma(-(x * r), r, 1.0);
+  return fma(0.5 * r, e, r);
+}
+
+// sqrt(x), x >= 0: Goldschmidt iteration from the reciprocal square root
+// estimate (g -> sqrt(x), h -> 1/(2 sqrt(x))), finished by a residual step.
+__device__ __forceinline__ double fsqrt(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  double g = x * r, h = 0.5 * r;
+  double e = fma(-g, h, 0.5);
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  e = fma(-g, h, 0.5);
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  const double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  return x > 0.0 ? g : 0.0;
+}
+
 // Fast magnetosonic speed along the normal:
 //   c_f^2 = ((a^2 + B^2/rho) + sqrt((a^2 + B^2/rho)^2 - 4 a^2 B_n^2/rho)) / 2
 __device__ __forceinline__ double fast_speed(double irho, double p, double bnsq, double btsq, double gamma) {
   double asq = gamma * p * irho;
   double s = asq + (bnsq + btsq) * irho;
   double disc = fmax(s * s - 4.0 * asq * bnsq * irho, 0.0);
-  return sqrt(0.5 * (s + sqrt(disc)));
+  return fsqrt(0.5 * (s + fsqrt(disc)));
 }
 
 // HLLE with Davis wave-speed bounds.
 __device__ __forceinline__ void hlle(const FaceState& L, const FaceState& R, double bn, const Gas& g, FaceFlux& F,
                                      double& smax) {
   const double bnsq = bn * bn;
-  const double irl = 1.0 / L.rho, irr = 1.0 / R.rho;
+  const double irl = frcp(L.rho), irr = frcp(R.rho);
   const double btl = L.bt1 * L.bt1 + L.bt2 * L.bt2, btr = R.bt1 * R.bt1 + R.bt2 * R.bt2;
   const double cfl = fast_speed(irl, L.p, bnsq, btl, g.gamma);
   const double cfr = fast_speed(irr, R.p, bnsq, btr, g.gamma);
@@ -51,7 +95,7 @@ __device__ __forceinline__ void hlle(const FaceState& L, const FaceState& R, dou
   const double sr = fmax(L.vn + cfl, R.vn + cfr);
   smax = fmax(fabs(sl), fabs(sr));
   const double bp = fmax(sr, 0.0), bm = fmin(sl, 0.0);
-  const double idb = 1.0 / (bp - bm);
+  const double idb = frcp(bp - bm);
   const double wl = bp * idb, wr = -bm * idb, wd = bp * bm * idb;
   // left and right conserved states and physical fluxes
   const double pml = 0.5 * (bnsq + btl), pmr = 0.5 * (bnsq + btr);
@@ -78,12 +122,9 @@ __device__ __forceinline__ void hlld(const FaceState& L, const FaceState& R, dou
                                      double& smax) {
   constexpr double kSmall = 1.0e-8;
   const double bnsq = bn * bn;
-  const double irl = 1.0 / L.rho, irr = 1.0 / R.rho;
+  const double irl = frcp(L.rho), irr = frcp(R.rho);
   const double btl = L.bt1 * L.bt1 + L.bt2 * L.bt2, btr = R.bt1 * R.bt1 + R.bt2 * R.bt2;
-  const double pml = 0.5 * (bnsq + btl), pmr = 0.5 * (bnsq + btr);
-  const double ptl = L.p + pml, ptr = R.p + pmr;
-  const double el = L.p * g.igm1 + 0.5 * L.rho * (L.vn * L.vn + L.vt1 * L.vt1 + L.vt2 * L.vt2) + pml;
-  const double er = R.p * g.igm1 + 0.5 * R.rho * (R.vn * R.vn + R.vt1 * R.vt1 + R.vt2 * R.vt2) + pmr;
+  const double ptl = L.p + 0.5 * (bnsq + btl), ptr = R.p + 0.5 * (bnsq + btr);
 
   const double cfl = fast_speed(irl, L.p, bnsq, btl, g.gamma);
   const double cfr = fast_speed(irr, R.p, bnsq, btr, g.gamma);
@@ -95,18 +136,32 @@ __device__ __forceinline__ void hlld(const FaceState& L, const FaceState& R, dou
   // contact speed and total pressure of the star region
   const double ml = (sl - L.vn) * L.rho;  // < 0
   const double mr = (sr - R.vn) * R.rho;  // > 0
-  const double iden = 1.0 / (mr - ml);
+  const double iden = frcp(mr - ml);
   const double sm = (mr * R.vn - ml * L.vn - ptr + ptl) * iden;
   const double pts = (mr * ptl - ml * ptr + ml * mr * (R.vn - L.vn)) * iden;
 
-  // single-star states
-  const double isl = 1.0 / (sl - sm), isr = 1.0 / (sr - sm);
+  // single-star densities and rotational speeds
+  const double isl = frcp(sl - sm), isr = frcp(sr - sm);
   const double rsl = ml * isl, rsr = mr * isr;  // rho*_L, rho*_R
+  // sqrt(rho*) and 1/sqrt(rho*) from one refined reciprocal square root
+  const double irql = frsq(rsl), irqr = frsq(rsr);
+  const double sqrl = rsl * irql, sqrr = rsr * irqr;
+  const double ssl = sm - fabs(bn) * irql;
+  const double ssr = sm + fabs(bn) * irqr;
+
+  // region of the fan that contains x/t = 0, and which side's states it uses
+  const bool useL = (sl > 0.0) || (!(sr < 0.0) && (ssl >= 0.0 || (!(ssr <= 0.0) && sm >= 0.0)));
+  const bool star = !(sl > 0.0) && !(sr < 0.0);
+  const bool dstar = !(0.5 * bnsq < kSmall * pts);
+  const bool dbl = star && !(ssl >= 0.0) && !(ssr <= 0.0) && dstar;
+
+  // transverse velocity and field of the single-star states (both sides are
+  // needed by the double-star state)
   double vt1sl, vt2sl, bt1sl, bt2sl, vt1sr, vt2sr, bt1sr, bt2sr;
   {
     const double d = ml * (sl - sm) - bnsq;
     const bool degen = fabs(d) < kSmall * pts;
-    const double id = 1.0 / (degen ? 1.0 : d);
+    const double id = frcp(degen ? 1.0 : d);
     const double c1 = bn * (sm - L.vn) * id;
     const double c2 = (ml * (sl - L.vn) - bnsq) * id;
     vt1sl = degen ? L.vt1 : L.vt1 - L.bt1 * c1;
@@ -117,7 +172,7 @@ __device__ __forceinline__ void hlld(const FaceState& L, const FaceState& R, dou
   {
     const double d = mr * (sr - sm) - bnsq;
     const bool degen = fabs(d) < kSmall * pts;
-    const double id = 1.0 / (degen ? 1.0 : d);
+    const double id = frcp(degen ? 1.0 : d);
     const double c1 = bn * (sm - R.vn) * id;
     const double c2 = (mr * (sr - R.vn) - bnsq) * id;
     vt1sr = degen ? R.vt1 : R.vt1 - R.bt1 * c1;
@@ -125,51 +180,37 @@ __device__ __forceinline__ void hlld(const FaceState& L, const FaceState& R, dou
     bt1sr = degen ? R.bt1 : R.bt1 * c2;
     bt2sr = degen ? R.bt2 : R.bt2 * c2;
   }
-  const double vbl = L.vn * bn + L.vt1 * L.bt1 + L.vt2 * L.bt2;
-  const double vbr = R.vn * bn + R.vt1 * R.bt1 + R.vt2 * R.bt2;
-  const double vbsl = sm * bn + vt1sl * bt1sl + vt2sl * bt2sl;
-  const double vbsr = sm * bn + vt1sr * bt1sr + vt2sr * bt2sr;
-  const double esl = ((sl - L.vn) * el - ptl * L.vn + pts * sm + bn * (vbl - vbsl)) * isl;
-  const double esr = ((sr - R.vn) * er - ptr * R.vn + pts * sm + bn * (vbr - vbsr)) * isr;
 
-  const double sqrl = sqrt(rsl), sqrr = sqrt(rsr);
-  const double ssl = sm - fabs(bn) / sqrl;
-  const double ssr = sm + fabs(bn) / sqrr;
-
-  // double-star state (shared velocity and field, separate energies)
-  const bool dstar = !(0.5 * bnsq < kSmall * pts);
+  // double-star state (shared velocity and field)
   const double sgn = bn > 0.0 ? 1.0 : (bn < 0.0 ? -1.0 : 0.0);
-  const double isum = 1.0 / (sqrl + sqrr);
+  const double isum = frcp(sqrl + sqrr);
   const double vt1ss = (sqrl * vt1sl + sqrr * vt1sr + (bt1sr - bt1sl) * sgn) * isum;
   const double vt2ss = (sqrl * vt2sl + sqrr * vt2sr + (bt2sr - bt2sl) * sgn) * isum;
   const double bt1ss = (sqrl * bt1sr + sqrr * bt1sl + sqrl * sqrr * (vt1sr - vt1sl) * sgn) * isum;
   const double bt2ss = (sqrl * bt2sr + sqrr * bt2sl + sqrl * sqrr * (vt2sr - vt2sl) * sgn) * isum;
   const double vbss = sm * bn + vt1ss * bt1ss + vt2ss * bt2ss;
 
-  // region of the fan that contains x/t = 0
-  //   0: left state, 1: L*, 2: L**, 3: R**, 4: R*, 5: right state
-  const bool useL = (sl > 0.0) || (!(sr < 0.0) && (ssl >= 0.0 || (!(ssr <= 0.0) && sm >= 0.0)));
-  const bool star = !(sl > 0.0) && !(sr < 0.0);
-  const bool dbl = star && !(ssl >= 0.0) && !(ssr <= 0.0) && dstar;
-
-  // chosen side: its state, flux, star and double-star states
+  // chosen side: its state, energy and physical flux, then its star and
+  // double-star energies
   const double rho = useL ? L.rho : R.rho;
   const double vn = useL ? L.vn : R.vn;
   const double vt1 = useL ? L.vt1 : R.vt1;
   const double vt2 = useL ? L.vt2 : R.vt2;
+  const double p = useL ? L.p : R.p;
   const double bt1 = useL ? L.bt1 : R.bt1;
   const double bt2 = useL ? L.bt2 : R.bt2;
   const double pt = useL ? ptl : ptr;
-  const double en = useL ? el : er;
-  const double vb = useL ? vbl : vbr;
   const double s = useL ? sl : sr;
+  const double is = useL ? isl : isr;
   const double ss = useL ? ssl : ssr;
   const double rs = useL ? rsl : rsr;
+  const double sq = useL ? sqrl : sqrr;
   const double vt1s = useL ? vt1sl : vt1sr, vt2s = useL ? vt2sl : vt2sr;
   const double bt1s = useL ? bt1sl : bt1sr, bt2s = useL ? bt2sl : bt2sr;
-  const double es = useL ? esl : esr;
-  const double sq = useL ? sqrl : sqrr;
-  const double vbs = useL ? vbsl : vbsr;
+  const double en = p * g.igm1 + 0.5 * rho * (vn * vn + vt1 * vt1 + vt2 * vt2) + 0.5 * (bnsq + bt1 * bt1 + bt2 * bt2);
+  const double vb = vn * bn + vt1 * bt1 + vt2 * bt2;
+  const double vbs = sm * bn + vt1s * bt1s + vt2s * bt2s;
+  const double es = ((s - vn) * en - pt * vn + pts * sm + bn * (vb - vbs)) * is;
   const double ess = useL ? es - sq * (vbs - vbss) * sgn : es + sq * (vbs - vbss) * sgn;
 
   const double mn = rho * vn;
@@ -205,7 +246,7 @@ __device__ __forceinline__ void hlld(const FaceState& L, const FaceState& R, dou
 __device__ __forceinline__ double vl_slope(double qm, double q0, double qp) {
   const double dm = q0 - qm, dp = qp - q0;
   const double pr = dm * dp;
-  return pr > 0.0 ? 2.0 * pr / (dm + dp) : 0.0;
+  return pr > 0.0 ? 2.0 * pr * frcp(dm + dp) : 0.0;
 }
 
 // Colella & Sekora (2008) extremum-preserving PPM on a uniform grid.
@@ -245,7 +286,7 @@ __device__ __forceinline__ void ppm_cell(double qa, double qb, double qc, double
     const double m = fmin(fabs(d2), fmin(C * fabs(d2l), fmin(C * fabs(d2r), C * fabs(d2c))));
     const double lim = pos ? m : (neg ? -m : 0.0);
     if (d2 != 0.0) {
-      const double r = lim / d2;
+      const double r = lim * frcp(d2);
       qm = qc + (qm - qc) * r;
       qp = qc + (qp - qc) * r;
     } else {
@@ -280,7 +321,7 @@ __device__ __forceinline__ double corner_emf(double ea0, double ea1, double eb0,
 // upwind weight of a face from its mass flux
 __device__ __forceinline__ double ct_weight(double frho, double rhobar, double smax, double eps) {
   if (eps > 0.0) {
-    const double r = 0.5 + 0.5 * (frho / rhobar) / (eps * smax);
+    const double r = 0.5 + 0.5 * frho * frcp(rhobar * eps * smax);
     return fmin(1.0, fmax(0.0, r));
   }
   return frho > 0.0 ? 1.0 : (frho < 0.0 ? 0.0 : 0.5);

@@ -61,7 +61,7 @@ def _create(**over):
     (dict(cfl=0.0), "cfl"),
     (dict(cfl=1.5), "cfl"),
     (dict(ct_eps=-1.0), "ct_eps"),
-    (dict(reserved=1), "reserved"),
+    (dict(kernel_path=2), "kernel_path"),
     (dict(n=(2000, 2000, 2000)), "too large"),
 ])
 def test_create_rejects_bad_config_before_any_hip_call(over, needle):

@@ -153,6 +153,43 @@ def test_steps_match_oracle(torch_dev, athmhd, orc, integ, recon, rs):
     s.close()
 
 
+@pytest.mark.parametrize("integ,recon,rs", [("vl2", "plm", "hlld"), ("rk3", "ppm", "hlle"), ("rk1", "dc", "hlld")])
+def test_segmented_tiles_match_oracle(torch_dev, athmhd, orc, integ, recon, rs):
+    """Block split into several x3 segments (the last one ragged) and tiles
+    whose last row and column are partly outside the block."""
+    torch, dev = torch_dev
+    ng = 3 if recon == "ppm" else 2
+    b = inputs.smooth_random(n=(30, 29, 40), seed=25, ng=ng)
+    kw = dict(integrator=integ, recon=recon, riemann=rs)
+    s, cfg = make_pair(athmhd, orc, b, **kw)
+    cons = orc.prim2cons(cfg, b.prim, b.bface)
+    tc, tb = to_dev(torch, dev, cons), to_dev(torch, dev, b.bface)
+    rc, rb = cons.copy(), b.bface.copy()
+    for _ in range(2):
+        dt, _ = orc.newdt(cfg, rc, rb)
+        assert orc.step(cfg, rc, rb, dt) == 0
+        s.step(tc, tb, dt)
+    assert rel_l1(b, tc.cpu().numpy(), tb.cpu().numpy(), rc, rb) <= TOL
+    s.close()
+
+
+def test_fused_and_unfused_paths_agree(torch_dev, athmhd, orc):
+    """The single-kernel stage and the pipeline of simple kernels compute the
+    same step (different summation orders only)."""
+    torch, dev = torch_dev
+    b = inputs.turbulence(n=48, seed=5)
+    outs = []
+    for path in ("fused", "unfused"):
+        s = athmhd.Solver(b.n, b.ng, b.dx, b.gamma, kernel_path=path)
+        tb = to_dev(torch, dev, b.bface)
+        tc = s.prim2cons(to_dev(torch, dev, b.prim), tb)
+        for _ in range(3):
+            s.step(tc, tb, 1e-3)
+        outs.append((tc.cpu().numpy(), tb.cpu().numpy()))
+        s.close()
+    assert rel_l1(b, outs[0][0], outs[0][1], outs[1][0], outs[1][1]) <= 1e-13
+
+
 def test_ct_ramp_matches_oracle(torch_dev, athmhd, orc):
     torch, dev = torch_dev
     b = inputs.smooth_random(n=(24, 16, 12), seed=24)
