@@ -28,7 +28,7 @@ struct athmhd_s {
   int* d_bad = nullptr;                 // non-physical cells met since the last newdt
   void* h_pinned = nullptr;             // 16 bytes of pinned host memory for newdt
   int kz = 0;                           // x3 planes per fused workgroup (0: default)
-  int occ = 1;                          // register target of the fused kernel (waves per SIMD)
+  int occ = 2;                          // register target of the fused kernel (waves per SIMD)
   bool profiling = false;
   std::vector<hipEvent_t> events;       // (start, stop) pairs around stage kernels
   std::string err;
@@ -190,7 +190,7 @@ int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
   }
   h->scr.edge = p;
   if (const char* kz = getenv("ATHMHD_KZ")) h->kz = atoi(kz);
-  if (const char* oc = getenv("ATHMHD_OCC")) h->occ = atoi(oc) == 2 ? 2 : 1;
+  if (const char* oc = getenv("ATHMHD_OCC")) h->occ = atoi(oc) == 1 ? 1 : 2;
   hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, nullptr, h->d_dt, 0ull, h->d_bad, 1);
   e = hipDeviceSynchronize();
   if (e != hipSuccess) {
