@@ -26,8 +26,17 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
-FP64_VECTOR_TFLOPS = 78.6    # MI355X FP64 vector peak (FMA = 2 flops)
+FP64_VECTOR_TFLOPS = 78.6    # MI355X FP64 vector peak: 256 CU x 64 lanes x 2 flops (FMA) x 2.4 GHz
 STATE_BYTES_PER_CELL = 64    # 5 conserved + 3 face-field doubles
+# Algorithmic FP64 operations (add/sub, mul, div, sqrt) of one VL2+PLM+HLLD
+# step per active cell, counted by `python -m oracle.count_flops 256` on this
+# workload (per-cell slope form): 2560.0 per zone-cycle, i.e. 1280 per stage.
+ALG_FLOPS_PER_ZONE_CYCLE = 2560.0
+# HBM bytes per stage launch measured by rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+# on this workload, scaled by the counters of a plain 1 GiB copy, and the hash
+# of the stage-kernel sources they were measured on (traffic is reported only
+# while the sources are unchanged).
+STAGE_TRAFFIC = None
 
 
 def parse():
@@ -40,7 +49,23 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle timing")
     p.add_argument("--cpu-steps", type=int, default=1, help="oracle steps in the CPU baseline sample")
     p.add_argument("--kernel-path", default="fused", choices=["fused", "unfused"])
+    p.add_argument("--workload", default="turbulence", choices=["turbulence", "batch"],
+                   help="turbulence: the 256^3 block (default); batch: 1024 uneven AMR-shaped blocks")
+    p.add_argument("--no-tune", action="store_true", help="batch: keep the default tile instead of autotuning")
+    p.add_argument("--graph", action="store_true", help="replay each step from a hipGraph")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a plain device copy of 1 GiB (for scaling PMC byte counters) and exit")
     return p.parse_args()
+
+
+def stage_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2005_06651_amd", "csrc")
+    for name in ("kernels_fused.hip", "mhd_math.hpp", "common.hpp"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(block, steps: int):
@@ -66,6 +91,55 @@ def cpu_baseline(block, steps: int):
     }
 
 
+def bench_batch(args):
+    """1024 MeshBlocks of uneven sizes (40% 16^3, 40% 24^3, 20% 32^3, nghost 2)
+    from a seeded 2:1-balanced octree, each with a smooth periodic state, one
+    persistent launch per stage, VL2+PLM+HLLD, dt from newdt every step."""
+    import torch
+
+    from paper_2005_06651_amd import athmhd, inputs
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    blocks = inputs.amr_batch(1024, seed=args.seed)
+    s = athmhd.BatchSolver([b.n for b in blocks], [b.dx for b in blocks], 2, blocks[0].gamma, recon="plm",
+                           riemann="hlld", integrator="vl2", cfl=0.3)
+    tb = torch.from_numpy(inputs.pack([b.bface for b in blocks])).to(dev)
+    tc = s.prim2cons(torch.from_numpy(inputs.pack([b.prim for b in blocks])).to(dev), tb)
+    stream = torch.cuda.Stream() if args.graph else torch.cuda.current_stream()
+    tuned = None
+    if not args.no_tune:
+        tuned = s.tune(tc, tb, stream=stream)
+    if args.graph:
+        s.set_graph(True)
+    zones = sum(b.n[0] * b.n[1] * b.n[2] for b in blocks)
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            s.step(tc, tb, s.newdt(tc, tb, stream=stream), stream=stream)
+        stream.synchronize()
+        if not args.graph:
+            s.profile_start()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            s.step(tc, tb, s.newdt(tc, tb, stream=stream), stream=stream)
+        stream.synchronize()
+        elapsed = time.perf_counter() - t0
+        stage_ms, launches = (0.0, 0) if args.graph else s.profile_stop()
+    out = {
+        "metric": "zone-cycles/s, FP64 3D MHD VL2+PLM+HLLD, 1 MI355X, batched uneven blocks",
+        "value": zones * args.steps / elapsed, "unit": "zone-cycles/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "1024 AMR-shaped blocks (410x16^3, 410x24^3, 204x32^3, nghost 2) of a seeded "
+                               "2:1-balanced octree, smooth periodic states, VL2+PLM+HLLD+CT, CFL 0.3",
+                   "cells": zones, "tile": None if tuned is None else {"shape": athmhd.BATCH_TILES[tuned[0]],
+                                                                        "split": tuned[1]},
+                   "graph": bool(args.graph)},
+        "stage_ms_per_launch": stage_ms / max(launches, 1) if launches else None,
+    }
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -78,6 +152,17 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "batch":
+        bench_batch(args)
+        return
+    if args.copy_calibration:
+        a = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 8, "launches": 3}))
+        return
     n = args.n
     block = inputs.turbulence(n=n, seed=args.seed)
     solver = athmhd.Solver(block.n, block.ng, block.dx, block.gamma, recon="plm", riemann="hlld",
@@ -102,12 +187,20 @@ def main():
 
     zones = n ** 3
     value = zones * args.steps / elapsed
-    # stage kernel roofline: VL2 stage 0 reads U^n and writes U^(n+1/2) (128 B
-    # per active cell), stage 1 reads U^(n+1/2) and U^n and writes U^(n+1)
-    # (192 B); algorithmic bytes per launch averaged over the two stages
-    alg_bytes = (128 + 192) / 2 * zones
+    # dominant kernel = the fused stage kernel (two launches per step).  It is
+    # bound by FP64 VALU issue, not by HBM: report the ALU roofline with the
+    # algorithmic flops, and the HBM view with the algorithmic bytes (VL2 stage
+    # 0 reads U^n and writes U^(n+1/2): 128 B per cell; stage 1 reads U^(n+1/2)
+    # and U^n and writes U^(n+1): 192 B per cell).
     per_launch_s = stage_ms / 1e3 / max(launches, 1)
-    achieved = alg_bytes / per_launch_s / 1e9
+    alg_flops = ALG_FLOPS_PER_ZONE_CYCLE / 2 * zones
+    alg_bytes = (128 + 192) / 2 * zones
+    achieved_tf = alg_flops / per_launch_s / 1e12
+    achieved_gbs = alg_bytes / per_launch_s / 1e9
+    traffic = None
+    if STAGE_TRAFFIC and STAGE_TRAFFIC.get("source_hash") == stage_source_hash() and args.kernel_path == "fused" \
+            and n == 256:
+        traffic = STAGE_TRAFFIC["bytes_per_launch"]
     # sanity of the final state
     g = block.ng
     b1 = tb[0, g:g + n, g:g + n, g:g + n + 1]
@@ -137,15 +230,18 @@ def main():
             "seed": args.seed, "kernel_path": args.kernel_path,
         },
         "roofline": {
-            "bound": "hbm",
-            "kernel": "stage (reconstruct + HLLD + CT + update), per launch",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "bound": "alu",
+            "kernel": "k_stage_fused (reconstruct + HLLD + CT + update of one stage), per launch",
+            "achieved": achieved_tf,
+            "peak": FP64_VECTOR_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved_tf / FP64_VECTOR_TFLOPS,
+            "traffic": traffic,
+            "alg_flops_per_launch": alg_flops,
             "stage_ms_per_launch": per_launch_s * 1e3,
             "launches": launches,
+            "hbm_view": {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved_gbs / HBM_PEAK_GBS, "alg_bytes_per_launch": alg_bytes},
         },
         "divb_after": divb,
     }

@@ -113,6 +113,41 @@ ATHMHD_API int athmhd_prim2cons(athmhd_t h, const double* prim, const double* bf
 /* Fill the ghost cells and periodic image faces of (cons, bface). */
 ATHMHD_API int athmhd_fill_ghosts(athmhd_t h, double* cons, double* bface, int nblocks, void* stream);
 
+/* Batched MeshBlocks of uneven sizes (Sec. 2.1: a Mesh of MeshBlocks, each
+ * with its own cell count here, advanced with one global dt, Sec. 2.1.6).
+ * `base` gives everything but the block shape (its n1..n3 and dx1..dx3 are
+ * ignored); dims[3b..3b+2] and dx[3b..3b+2] give block b.  cons and bface of
+ * a batched handle are the concatenations of the per-block arrays (block b's
+ * cons at offsets[2b], its bface at offsets[2b+1], see athmhd_batch_info);
+ * nblocks in later calls must equal the batch size.  Every block is its own
+ * periodic neighbour.  Each stage runs as one persistent launch whose
+ * workgroups pull (block, tile, x3 segment) items from a device queue; ghost
+ * fill, prim2cons and newdt run over all blocks from a descriptor table.
+ * Only the fused kernel path is supported (kernel_path must be 0). */
+ATHMHD_API int athmhd_create_batch(const athmhd_config* base, const int32_t* dims, const double* dx, int nblocks,
+                                   athmhd_t* out);
+
+/* Sizes (in doubles) of the concatenated cons and bface arrays of a batched
+ * handle and, if offsets is not NULL, the per-block offsets (2 per block). */
+ATHMHD_API int athmhd_batch_info(athmhd_t h, int64_t* cons_len, int64_t* bface_len, int64_t* offsets);
+
+/* Choose the thread tile of the batched stage kernel: shape indexes the
+ * candidate tiles (0: 16x8, 1: 8x16, 2: 14x14, 3: 8x8 active columns) and
+ * split = 1 halves the x3 extent of each work item. */
+ATHMHD_API int athmhd_batch_set_tile(athmhd_t h, int shape, int split);
+
+/* Autotuner: time the configured stage on (cons, bface) for every candidate
+ * tile and split (the caller's arrays are not modified), keep the fastest and
+ * report it (any output may be NULL).  Synchronises `stream`. */
+ATHMHD_API int athmhd_batch_tune(athmhd_t h, const double* cons, const double* bface, void* stream, int* best_shape,
+                                 int* best_split, double* best_ms);
+
+/* enable = 1: athmhd_step records its launches once into a hipGraph (for the
+ * given arrays, block count and stream, which must not be the default stream)
+ * and replays the graph afterwards, updating only dt; any change of those
+ * arguments recaptures.  Ignored while profiling is enabled. */
+ATHMHD_API int athmhd_set_graph(athmhd_t h, int enable);
+
 /* Kernel timing for measurement.  enable = 1 starts recording a pair of HIP
  * events around every launch of the stage kernel (the kernel that does
  * reconstruction, Riemann fluxes, CT and the update of one stage) on the stream

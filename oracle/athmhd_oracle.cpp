@@ -78,8 +78,36 @@ inline Dual sqrt(Dual a) {
 }
 inline Dual fabs(Dual a) { return a.v < 0.0 ? -a : a; }
 
+// Operation-counting scalar: every add, subtract, multiply, divide and square
+// root of the algorithm is tallied (comparisons and selects are not flops).
+struct OpCount {
+  unsigned long long add, mul, div, sqrt;
+};
+static OpCount g_ops = {0, 0, 0, 0};
+struct Cnt {
+  double v;
+  Cnt() : v(0.0) {}
+  Cnt(double x) : v(x) {}  // NOLINT: implicit on purpose
+};
+inline Cnt operator+(Cnt a, Cnt b) { ++g_ops.add; return Cnt(a.v + b.v); }
+inline Cnt operator-(Cnt a, Cnt b) { ++g_ops.add; return Cnt(a.v - b.v); }
+inline Cnt operator-(Cnt a) { return Cnt(-a.v); }
+inline Cnt operator*(Cnt a, Cnt b) { ++g_ops.mul; return Cnt(a.v * b.v); }
+inline Cnt operator/(Cnt a, Cnt b) { ++g_ops.div; return Cnt(a.v / b.v); }
+inline Cnt operator+(double a, Cnt b) { return Cnt(a) + b; }
+inline Cnt operator+(Cnt a, double b) { return a + Cnt(b); }
+inline Cnt operator-(double a, Cnt b) { return Cnt(a) - b; }
+inline Cnt operator-(Cnt a, double b) { return a - Cnt(b); }
+inline Cnt operator*(double a, Cnt b) { return Cnt(a) * b; }
+inline Cnt operator*(Cnt a, double b) { return a * Cnt(b); }
+inline Cnt operator/(Cnt a, double b) { return a / Cnt(b); }
+inline Cnt operator/(double a, Cnt b) { return Cnt(a) / b; }
+inline Cnt sqrt(Cnt a) { ++g_ops.sqrt; return Cnt(std::sqrt(a.v)); }
+inline Cnt fabs(Cnt a) { return Cnt(std::fabs(a.v)); }
+
 inline double val(double x) { return x; }
 inline double val(const Dual& x) { return x.v; }
+inline double val(const Cnt& x) { return x.v; }
 using std::fabs;
 using std::sqrt;
 
@@ -747,6 +775,22 @@ int orc_step_jvp(const orc::Cfg* c, double* cons, double* bface, double* dcons, 
   int r = orc::step<orc::Dual>(*c, uc.data(), ub.data(), dt);
   for (size_t q = 0; q < 5 * nc; ++q) { cons[q] = uc[q].v; dcons[q] = uc[q].d; }
   for (size_t q = 0; q < 3 * nf; ++q) { bface[q] = ub[q].v; dbface[q] = ub[q].d; }
+  return r;
+}
+
+// Floating-point operations of one step of the algorithm on this state:
+// out = (adds+subtracts, multiplies, divides, square roots).  The state is not
+// modified.
+int orc_count_ops(const orc::Cfg* c, const double* cons, const double* bface, double dt, unsigned long long* out) {
+  orc::Geo g(*c);
+  const size_t nc = g.ncell(), nf = g.nface();
+  std::vector<orc::Cnt> uc(cons, cons + 5 * nc), ub(bface, bface + 3 * nf);
+  orc::g_ops = {0, 0, 0, 0};
+  int r = orc::step<orc::Cnt>(*c, uc.data(), ub.data(), dt);
+  out[0] = orc::g_ops.add;
+  out[1] = orc::g_ops.mul;
+  out[2] = orc::g_ops.div;
+  out[3] = orc::g_ops.sqrt;
   return r;
 }
 

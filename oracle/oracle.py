@@ -53,6 +53,7 @@ def lib():
         _lib.orc_step.argtypes = [cp, P, P, C.c_double]
         _lib.orc_step_jvp.argtypes = [cp, P, P, P, P, C.c_double]
         _lib.orc_newdt.argtypes = [cp, P, P, P]
+        _lib.orc_count_ops.argtypes = [cp, P, P, C.c_double, C.POINTER(C.c_ulonglong)]
         _lib.orc_riemann.argtypes = [C.c_int, C.c_double, P, P, C.c_double, P, P]
         _lib.orc_phys_flux.argtypes = [C.c_double, P, C.c_double, P, P]
         _lib.orc_fast_speed.argtypes = [C.c_double] * 6
@@ -103,6 +104,14 @@ def step(cfg: Cfg, cons: np.ndarray, bface: np.ndarray, dt: float) -> int:
 
 def step_jvp(cfg: Cfg, cons, bface, dcons, dbface, dt: float) -> int:
     return lib().orc_step_jvp(C.byref(cfg), _p(cons), _p(bface), _p(dcons), _p(dbface), float(dt))
+
+
+def count_ops(cfg: Cfg, cons: np.ndarray, bface: np.ndarray, dt: float):
+    """(adds, multiplies, divides, square roots) of one step on this state."""
+    out = (C.c_ulonglong * 4)()
+    r = lib().orc_count_ops(C.byref(cfg), _p(cons), _p(bface), float(dt), out)
+    assert r >= 0
+    return tuple(int(x) for x in out)
 
 
 def newdt(cfg: Cfg, cons: np.ndarray, bface: np.ndarray):

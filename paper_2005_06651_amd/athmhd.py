@@ -17,8 +17,10 @@ OK, EINVAL, ENOMEM, EHIP, ENONPHYS, EUNSUP = 0, -1, -2, -3, -4, -5
 RECON = {"dc": 0, "plm": 1, "ppm": 2}
 RIEMANN = {"hlle": 0, "hlld": 1}
 INTEGRATOR = {"rk1": 0, "vl2": 1, "rk2": 2, "rk3": 3}
-EXPORTED = ["athmhd_version", "athmhd_create", "athmhd_step", "athmhd_newdt", "athmhd_prim2cons",
-            "athmhd_fill_ghosts", "athmhd_profile", "athmhd_last_error", "athmhd_destroy"]
+EXPORTED = ["athmhd_version", "athmhd_create", "athmhd_create_batch", "athmhd_batch_info",
+            "athmhd_batch_set_tile", "athmhd_batch_tune", "athmhd_set_graph", "athmhd_step", "athmhd_newdt",
+            "athmhd_prim2cons", "athmhd_fill_ghosts", "athmhd_profile", "athmhd_last_error", "athmhd_destroy"]
+BATCH_TILES = [(16, 8), (8, 16), (14, 14), (8, 8)]  # active columns of the batch tile candidates
 
 
 class AthmhdError(RuntimeError):
@@ -52,6 +54,13 @@ def lib():
         vp = C.c_void_p
         L.athmhd_version.restype = C.c_int
         L.athmhd_create.argtypes = [C.POINTER(Config), C.c_int, C.POINTER(vp)]
+        L.athmhd_create_batch.argtypes = [C.POINTER(Config), C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int,
+                                          C.POINTER(vp)]
+        L.athmhd_batch_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.athmhd_batch_set_tile.argtypes = [vp, C.c_int, C.c_int]
+        L.athmhd_batch_tune.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                        C.POINTER(C.c_double)]
+        L.athmhd_set_graph.argtypes = [vp, C.c_int]
         L.athmhd_step.argtypes = [vp, vp, vp, C.c_double, C.c_int, vp]
         L.athmhd_newdt.argtypes = [vp, vp, vp, C.c_int, C.POINTER(C.c_double), vp]
         L.athmhd_prim2cons.argtypes = [vp, vp, vp, vp, C.c_int, vp]
@@ -162,11 +171,133 @@ class Solver:
         pc, pb, nb = self._pair(cons, bface)
         _check(lib().athmhd_fill_ghosts(self._h, pc, pb, nb, _stream(stream)), self._h)
 
+    def set_graph(self, enable: bool) -> None:
+        """Record the step once into a hipGraph and replay it (needs a
+        non-default stream)."""
+        _check(lib().athmhd_set_graph(self._h, int(bool(enable))), self._h)
+
     def profile_start(self) -> None:
         _check(lib().athmhd_profile(self._h, 1, None, None), self._h)
 
     def profile_stop(self):
         """(summed stage-kernel milliseconds, number of launches) since start"""
+        ms = C.c_double()
+        n = C.c_int()
+        _check(lib().athmhd_profile(self._h, 0, C.byref(ms), C.byref(n)), self._h)
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().athmhd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchSolver:
+    """Blocks of uneven sizes advanced together (one persistent launch per
+    stage).  cons / bface are flat float64 tensors: the concatenation of every
+    block's (5, N3, N2, N1) and (3, N3+1, N2+1, N1+1) arrays."""
+
+    def __init__(self, dims, dxs, nghost, gamma, recon="plm", riemann="hlld", integrator="vl2", cfl=0.3,
+                 ct_eps=0.0):
+        import numpy as np
+        self.dims = [tuple(int(x) for x in d) for d in dims]
+        self.ng = int(nghost)
+        self.nblocks = len(self.dims)
+        self.cfg = make_config(self.dims[0], nghost, dxs[0], gamma, recon, riemann, integrator, cfl, ct_eps)
+        d = np.ascontiguousarray(np.array(self.dims, dtype=np.int32).reshape(-1))
+        x = np.ascontiguousarray(np.array(dxs, dtype=np.float64).reshape(-1))
+        h = C.c_void_p()
+        rc = lib().athmhd_create_batch(C.byref(self.cfg), d.ctypes.data_as(C.POINTER(C.c_int32)),
+                                       x.ctypes.data_as(C.POINTER(C.c_double)), self.nblocks, C.byref(h))
+        if rc != OK:
+            raise AthmhdError(rc, lib().athmhd_last_error(None).decode(errors="replace"))
+        self._h = h
+        cl, bl = C.c_int64(), C.c_int64()
+        offs = (C.c_int64 * (2 * self.nblocks))()
+        _check(lib().athmhd_batch_info(self._h, C.byref(cl), C.byref(bl), offs), self._h)
+        self.cons_len, self.bface_len = cl.value, bl.value
+        self.offsets = [(offs[2 * b], offs[2 * b + 1]) for b in range(self.nblocks)]
+
+    def cell_shape(self, b):
+        n1, n2, n3 = self.dims[b]
+        g = self.ng
+        return (n3 + 2 * g, n2 + 2 * g, n1 + 2 * g)
+
+    def face_shape(self, b):
+        return tuple(x + 1 for x in self.cell_shape(b))
+
+    def views(self, flat, kind):
+        """Per-block views (5, ...) of a flat cons-like array or (3, ...) of a
+        flat bface-like array (numpy or torch)."""
+        out = []
+        for b in range(self.nblocks):
+            if kind == "cons":
+                o, sh, nv = self.offsets[b][0], self.cell_shape(b), 5
+            else:
+                o, sh, nv = self.offsets[b][1], self.face_shape(b), 3
+            n = nv * sh[0] * sh[1] * sh[2]
+            out.append(flat[o:o + n].reshape((nv,) + sh))
+        return out
+
+    def _flat(self, t, n):
+        import torch
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+            raise TypeError("expected a float64 tensor in HIP device memory")
+        if not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"expected a contiguous tensor of {n} elements")
+        return C.c_void_p(t.data_ptr())
+
+    def _pair(self, cons, bface):
+        return self._flat(cons, self.cons_len), self._flat(bface, self.bface_len)
+
+    def step(self, cons, bface, dt: float, stream=None) -> None:
+        pc, pb = self._pair(cons, bface)
+        _check(lib().athmhd_step(self._h, pc, pb, float(dt), self.nblocks, _stream(stream)), self._h)
+
+    def newdt(self, cons, bface, stream=None) -> float:
+        pc, pb = self._pair(cons, bface)
+        out = C.c_double()
+        _check(lib().athmhd_newdt(self._h, pc, pb, self.nblocks, C.byref(out), _stream(stream)), self._h)
+        return out.value
+
+    def prim2cons(self, prim, bface, out=None, stream=None):
+        import torch
+        pp, pb = self._pair(prim, bface)
+        if out is None:
+            out = torch.empty_like(prim)
+        po = self._flat(out, self.cons_len)
+        _check(lib().athmhd_prim2cons(self._h, pp, pb, po, self.nblocks, _stream(stream)), self._h)
+        return out
+
+    def fill_ghosts(self, cons, bface, stream=None) -> None:
+        pc, pb = self._pair(cons, bface)
+        _check(lib().athmhd_fill_ghosts(self._h, pc, pb, self.nblocks, _stream(stream)), self._h)
+
+    def set_tile(self, shape: int, split: int = 0) -> None:
+        _check(lib().athmhd_batch_set_tile(self._h, int(shape), int(split)), self._h)
+
+    def tune(self, cons, bface, stream=None):
+        """Time every tile candidate on this state, keep the fastest; returns
+        (shape, split, ms per stage)."""
+        pc, pb = self._pair(cons, bface)
+        sh, sp, ms = C.c_int(), C.c_int(), C.c_double()
+        _check(lib().athmhd_batch_tune(self._h, pc, pb, _stream(stream), C.byref(sh), C.byref(sp), C.byref(ms)),
+               self._h)
+        return sh.value, sp.value, ms.value
+
+    def set_graph(self, enable: bool) -> None:
+        _check(lib().athmhd_set_graph(self._h, int(bool(enable))), self._h)
+
+    def profile_start(self) -> None:
+        _check(lib().athmhd_profile(self._h, 1, None, None), self._h)
+
+    def profile_stop(self):
         ms = C.c_double()
         n = C.c_int()
         _check(lib().athmhd_profile(self._h, 0, C.byref(ms), C.byref(n)), self._h)

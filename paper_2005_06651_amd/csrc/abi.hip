@@ -1,6 +1,9 @@
 // abi.hip -- host side of the C ABI declared in include/athmhd.h: argument
 // validation (entirely before any HIP call), device buffers, the stage driver
-// of the 2S integrators (Eq. (rk-2s), Sec. 3.2.3) and error reporting.
+// of the 2S integrators (Eq. (rk-2s), Sec. 3.2.3), batched blocks of uneven
+// sizes (work items, tile autotuner), optional hipGraph replay of a step, and
+// error reporting.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -18,19 +21,42 @@ using namespace athmhd;
 
 struct athmhd_s {
   athmhd_config cfg;
+  int device = 0;
+  // uniform handle: nbmax identical blocks of geometry g
   Geo g;
   int nbmax = 0;
-  int device = 0;
-  double* reg[2] = {nullptr, nullptr};  // two stage registers (cons followed by bface), nbmax blocks each
+  // batched handle: blocks of their own sizes, concatenated in the arrays
+  bool batch = false;
+  int nbatch = 0;
+  std::vector<BatchDesc> desc;
+  int64_t ctot = 0, ftot = 0;            // doubles of cons / bface over all blocks
+  int64_t max_shell = 0, max_cells = 0;  // per-block maxima (ghost shell, stored cells)
+  BatchDesc* d_desc = nullptr;
+  WorkItem* d_items = nullptr;
+  int nitems = 0, items_cap = 0;
+  unsigned* d_queue = nullptr;
+  int shape = 0, split = 0, grid = 0;   // batch tile candidate, x3 split, persistent grid
+  // state registers and scratch
+  double* reg[2] = {nullptr, nullptr};  // two stage registers (cons followed by bface)
+  int64_t reg_coff = 0;                  // offset of bface inside a register
   UnfusedScratch scr{};
   double* scratch_base = nullptr;
-  unsigned long long* d_dt = nullptr;   // running min of dx/(|v|+cf), bit pattern
-  int* d_bad = nullptr;                 // non-physical cells met since the last newdt
-  void* h_pinned = nullptr;             // 16 bytes of pinned host memory for newdt
-  int kz = 0;                           // x3 planes per fused workgroup (0: default)
-  int occ = 2;                          // register target of the fused kernel (waves per SIMD)
+  unsigned long long* d_dtmin = nullptr;  // running min of dx/(|v|+cf), bit pattern
+  int* d_bad = nullptr;                   // non-physical cells met since the last newdt
+  double* d_dtval = nullptr;              // dt of the step on the device (graph replay)
+  void* h_pinned = nullptr;               // 16 bytes of pinned host memory for newdt
+  int kz = 0;                             // x3 planes per fused workgroup (0: default)
+  int occ = 2;                            // register target of the fused kernel (waves per SIMD)
+  // kernel timing
   bool profiling = false;
-  std::vector<hipEvent_t> events;       // (start, stop) pairs around stage kernels
+  std::vector<hipEvent_t> events;  // (start, stop) pairs around stage kernels
+  // hipGraph replay of a step
+  bool use_graph = false;
+  hipGraph_t graph = nullptr;  // kept alive: its dt node is updated in the executable graph
+  hipGraphExec_t gexec = nullptr;
+  hipGraphNode_t dt_node = nullptr;
+  const void* gkey[3] = {nullptr, nullptr, nullptr};
+  int gkey_nb = 0;
   std::string err;
 };
 
@@ -80,10 +106,13 @@ __global__ void k_set_u64(unsigned long long* p, unsigned long long v, int* bad,
   }
 }
 
-int validate_cfg(const athmhd_config* c) {
+// first node of a replayed step: puts this step's dt on the device
+__global__ void k_set_dt(double* p, double dt) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = dt;
+}
+
+int validate_common(const athmhd_config* c) {
   if (!c) return fail(nullptr, ATHMHD_EINVAL, "config is NULL");
-  if (c->n1 < 1 || c->n2 < 1 || c->n3 < 1)
-    return fail(nullptr, ATHMHD_EINVAL, "block dims must be >= 1 (got %d %d %d)", c->n1, c->n2, c->n3);
   if (c->recon < ATHMHD_RECON_DC || c->recon > ATHMHD_RECON_PPM)
     return fail(nullptr, ATHMHD_EINVAL, "unknown reconstruction %d", c->recon);
   if (c->riemann != ATHMHD_RS_HLLE && c->riemann != ATHMHD_RS_HLLD)
@@ -96,15 +125,21 @@ int validate_cfg(const athmhd_config* c) {
                 c->nghost);
   if (!(std::isfinite(c->gamma) && c->gamma > 1.0))
     return fail(nullptr, ATHMHD_EINVAL, "gamma must be finite and > 1 (got %g)", c->gamma);
-  if (!finite_pos(c->dx1) || !finite_pos(c->dx2) || !finite_pos(c->dx3))
-    return fail(nullptr, ATHMHD_EINVAL, "cell widths must be finite and > 0");
   if (!(std::isfinite(c->cfl) && c->cfl > 0.0 && c->cfl <= 1.0))
     return fail(nullptr, ATHMHD_EINVAL, "cfl must be in (0, 1] (got %g)", c->cfl);
   if (!(std::isfinite(c->ct_eps) && c->ct_eps >= 0.0))
     return fail(nullptr, ATHMHD_EINVAL, "ct_eps must be finite and >= 0 (got %g)", c->ct_eps);
   if (c->kernel_path != 0 && c->kernel_path != 1)
     return fail(nullptr, ATHMHD_EINVAL, "kernel_path must be 0 (fused) or 1 (unfused)");
-  const double faces = (double)(c->n1 + 2 * c->nghost + 1) * (c->n2 + 2 * c->nghost + 1) * (c->n3 + 2 * c->nghost + 1);
+  return ATHMHD_OK;
+}
+
+int validate_block(int n1, int n2, int n3, int ng, double dx1, double dx2, double dx3) {
+  if (n1 < 1 || n2 < 1 || n3 < 1)
+    return fail(nullptr, ATHMHD_EINVAL, "block dims must be >= 1 (got %d %d %d)", n1, n2, n3);
+  if (!finite_pos(dx1) || !finite_pos(dx2) || !finite_pos(dx3))
+    return fail(nullptr, ATHMHD_EINVAL, "cell widths must be finite and > 0");
+  const double faces = (double)(n1 + 2 * ng + 1) * (n2 + 2 * ng + 1) * (n3 + 2 * ng + 1);
   if (faces >= 2147483647.0) return fail(nullptr, ATHMHD_EINVAL, "block too large for 32-bit in-array indices");
   return ATHMHD_OK;
 }
@@ -112,13 +147,28 @@ int validate_cfg(const athmhd_config* c) {
 int check_call(athmhd_t h, const void* a, const void* b, int nb) {
   if (!h) return ATHMHD_EINVAL;
   if (!a || !b) return fail(h, ATHMHD_EINVAL, "NULL array argument");
-  if (nb < 1 || nb > h->nbmax) return fail(h, ATHMHD_EINVAL, "nblocks %d outside [1, %d]", nb, h->nbmax);
+  if (h->batch) {
+    if (nb != h->nbatch)
+      return fail(h, ATHMHD_EINVAL, "nblocks must equal the batch size %d (got %d)", h->nbatch, nb);
+  } else if (nb < 1 || nb > h->nbmax) {
+    return fail(h, ATHMHD_EINVAL, "nblocks %d outside [1, %d]", nb, h->nbmax);
+  }
   return ATHMHD_OK;
 }
 
 void drop_events(athmhd_t h) {
   for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);
   h->events.clear();
+}
+
+void drop_graph(athmhd_t h) {
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->gexec = nullptr;
+  h->graph = nullptr;
+  h->dt_node = nullptr;
+  h->gkey[0] = h->gkey[1] = h->gkey[2] = nullptr;
+  h->gkey_nb = 0;
 }
 
 // record one event of a (start, stop) pair when profiling
@@ -134,24 +184,195 @@ hipError_t mark(athmhd_t h, hipStream_t s) {
 void free_all(athmhd_t h) {
   if (!h) return;
   drop_events(h);
+  drop_graph(h);
   for (int r = 0; r < 2; ++r)
     if (h->reg[r]) (void)hipFree(h->reg[r]);
   if (h->scratch_base) (void)hipFree(h->scratch_base);
-  if (h->d_dt) (void)hipFree(h->d_dt);
+  if (h->d_dtmin) (void)hipFree(h->d_dtmin);
   if (h->d_bad) (void)hipFree(h->d_bad);
+  if (h->d_dtval) (void)hipFree(h->d_dtval);
+  if (h->d_desc) (void)hipFree(h->d_desc);
+  if (h->d_items) (void)hipFree(h->d_items);
+  if (h->d_queue) (void)hipFree(h->d_queue);
   if (h->h_pinned) (void)hipHostFree(h->h_pinned);
+}
+
+// Small device buffers every handle has.
+bool alloc_common(athmhd_t h) {
+  return hipMalloc(&h->d_dtmin, sizeof(unsigned long long)) == hipSuccess &&
+         hipMalloc(&h->d_bad, sizeof(int)) == hipSuccess && hipMalloc(&h->d_dtval, sizeof(double)) == hipSuccess &&
+         hipHostMalloc(&h->h_pinned, 16, hipHostMallocDefault) == hipSuccess;
+}
+
+void read_env(athmhd_t h) {
+  if (const char* kz = getenv("ATHMHD_KZ")) h->kz = atoi(kz);
+  if (const char* oc = getenv("ATHMHD_OCC")) h->occ = atoi(oc) == 1 ? 1 : 2;
+}
+
+// ---- batched blocks: work items of one tile candidate ---------------------
+int build_items(athmhd_t h, int shape, int split) {
+  int TX, TY;
+  batch_tile_shape(shape, &TX, &TY);
+  std::vector<WorkItem> items;
+  for (int b = 0; b < h->nbatch; ++b) {
+    const Geo& g = h->desc[b].g;
+    const int ntx = (g.n1 + TX - 1) / TX, nty = (g.n2 + TY - 1) / TY;
+    const int kz = split ? (g.n3 + 1) / 2 : g.n3;
+    for (int k0 = g.ng; k0 < g.ng + g.n3; k0 += kz)
+      for (int ty = 0; ty < nty; ++ty)
+        for (int tx = 0; tx < ntx; ++tx) items.push_back({b, tx, ty, k0, std::min(k0 + kz, g.ng + g.n3)});
+  }
+  // longest items first, so the short ones fill the tail of the persistent grid
+  std::stable_sort(items.begin(), items.end(),
+                   [](const WorkItem& a, const WorkItem& b) { return (a.kend - a.k0) > (b.kend - b.k0); });
+  if ((int)items.size() > h->items_cap) {
+    if (h->d_items) (void)hipFree(h->d_items);
+    h->d_items = nullptr;
+    if (hipMalloc(&h->d_items, items.size() * sizeof(WorkItem)) != hipSuccess)
+      return fail(h, ATHMHD_ENOMEM, "work item table");
+    h->items_cap = (int)items.size();
+  }
+  hipError_t e = hipMemcpy(h->d_items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(h, e, "work item upload");
+  h->nitems = (int)items.size();
+  h->shape = shape;
+  h->split = split;
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, h->device);
+  if (e != hipSuccess) return hip_fail(h, e, "device properties");
+  // persistent grid: enough workgroups to fill every CU at the kernels' LDS and
+  // register occupancy (at most 3 per CU), never more than there are items
+  h->grid = std::max(1, std::min(h->nitems, prop.multiProcessorCount * 3));
+  drop_graph(h);
+  return ATHMHD_OK;
+}
+
+// One stage: uniform or batched, fused or unfused.
+hipError_t launch_stage(athmhd_t h, int recon, const double* xc, const double* xb, const double* unc,
+                        const double* unb, double* oc, double* ob, StageCoef cf, double beta, const double* dt_dev,
+                        int nblocks, hipStream_t s) {
+  if (h->batch)
+    return launch_stage_batch(h->shape, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, h->d_desc, h->d_items,
+                              h->nitems, h->d_queue, xc, xb, unc, unb, oc, ob, cf, dt_dev, beta, h->grid, h->d_bad,
+                              s);
+  if (h->cfg.kernel_path == 0)
+    return launch_stage_fused(h->g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc, xb, unc, unb, oc, ob, cf,
+                              dt_dev, beta, nblocks, h->kz, h->occ, h->d_bad, s);
+  return launch_stage_unfused(h->g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc, xb, unc, unb, oc, ob,
+                              cf, nblocks, h->scr, h->d_bad, s);
+}
+
+hipError_t fill_ghosts(athmhd_t h, double* cons, double* bface, int nblocks, hipStream_t s) {
+  if (h->batch) return launch_fill_ghosts_batch(h->d_desc, h->nbatch, h->max_shell, cons, bface, s);
+  return launch_fill_ghosts(h->g, cons, bface, nblocks, s);
+}
+
+// The launches of one full step (everything asynchronous on s).  With
+// dt_dev != NULL the stage kernels read dt from the device.
+int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const double* dt_dev, int nblocks,
+                 hipStream_t s) {
+  const Scheme sc = scheme_of(h->cfg.integrator);
+  const double* xc = cons;
+  const double* xb = bface;
+  hipError_t e;
+  for (int st = 0; st < sc.nstage; ++st) {
+    if ((e = fill_ghosts(h, const_cast<double*>(xc), const_cast<double*>(xb), nblocks, s)) != hipSuccess)
+      return hip_fail(h, e, "fill_ghosts launch");
+    const bool last = st == sc.nstage - 1;
+    double* oc;
+    double* ob;
+    if (last && xc != cons) {
+      oc = cons;
+      ob = bface;
+    } else {
+      double* r = h->reg[st % 2];
+      oc = r;
+      ob = r + h->reg_coff;
+    }
+    // the VL2 predictor always uses donor-cell fluxes (Sec. 3.2.3)
+    const int recon = (h->cfg.integrator == ATHMHD_VL2 && st == 0) ? ATHMHD_RECON_DC : h->cfg.recon;
+    StageCoef cf{sc.g0[st], sc.g1[st], sc.beta[st] * dt};
+    if ((e = mark(h, s)) != hipSuccess) return hip_fail(h, e, "profiling event");
+    e = launch_stage(h, recon, xc, xb, cons, bface, oc, ob, cf, sc.beta[st], dt_dev, nblocks, s);
+    if (e != hipSuccess) return hip_fail(h, e, "stage launch");
+    if ((e = mark(h, s)) != hipSuccess) return hip_fail(h, e, "profiling event");
+    xc = oc;
+    xb = ob;
+  }
+  if (xc != cons) {  // single-stage scheme: the result sits in a register
+    const int64_t nc = h->batch ? h->ctot : h->g.cblock * nblocks;
+    const int64_t nf = h->batch ? h->ftot : h->g.fblock * nblocks;
+    if ((e = launch_copy(cons, xc, nc, s)) != hipSuccess) return hip_fail(h, e, "copy launch");
+    if ((e = launch_copy(bface, xb, nf, s)) != hipSuccess) return hip_fail(h, e, "copy launch");
+  }
+  if ((e = fill_ghosts(h, cons, bface, nblocks, s)) != hipSuccess) return hip_fail(h, e, "fill_ghosts launch");
+  return ATHMHD_OK;
+}
+
+// Capture one step into a graph whose first node writes dt to the device.
+int capture_step(athmhd_t h, double* cons, double* bface, int nblocks, hipStream_t s) {
+  drop_graph(h);
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(h, e, "begin graph capture");
+  hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(64), 0, s, h->d_dtval, 0.0);
+  int rc = enqueue_step(h, cons, bface, 0.0, h->d_dtval, nblocks, s);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(s, &graph);
+  if (rc != ATHMHD_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(h, e, "end graph capture");
+  // the dt node is the only root of the captured graph
+  size_t nroot = 0;
+  e = hipGraphGetRootNodes(graph, nullptr, &nroot);
+  if (e != hipSuccess || nroot != 1) {
+    (void)hipGraphDestroy(graph);
+    return fail(h, ATHMHD_EHIP, "captured step graph has %zu roots", nroot);
+  }
+  e = hipGraphGetRootNodes(graph, &h->dt_node, &nroot);
+  if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    h->gexec = nullptr;
+    h->dt_node = nullptr;
+    return hip_fail(h, e, "graph instantiate");
+  }
+  h->graph = graph;
+  h->gkey[0] = cons;
+  h->gkey[1] = bface;
+  h->gkey[2] = s;
+  h->gkey_nb = nblocks;
+  return ATHMHD_OK;
+}
+
+int replay_step(athmhd_t h, double dt, hipStream_t s) {
+  hipKernelNodeParams p{};
+  hipError_t e = hipGraphKernelNodeGetParams(h->dt_node, &p);
+  if (e != hipSuccess) return hip_fail(h, e, "graph dt node");
+  double* dst = h->d_dtval;
+  void* args[2] = {&dst, &dt};
+  p.kernelParams = args;
+  p.extra = nullptr;
+  e = hipGraphExecKernelNodeSetParams(h->gexec, h->dt_node, &p);
+  if (e != hipSuccess) return hip_fail(h, e, "graph dt update");
+  e = hipGraphLaunch(h->gexec, s);
+  if (e != hipSuccess) return hip_fail(h, e, "graph launch");
+  return ATHMHD_OK;
 }
 
 }  // namespace
 
 extern "C" {
 
-int athmhd_version(void) { return 100; }
+int athmhd_version(void) { return 101; }
 
 int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
   if (!out) return fail(nullptr, ATHMHD_EINVAL, "out is NULL");
   *out = nullptr;
-  int rc = validate_cfg(cfg);
+  int rc = validate_common(cfg);
+  if (rc != ATHMHD_OK) return rc;
+  rc = validate_block(cfg->n1, cfg->n2, cfg->n3, cfg->nghost, cfg->dx1, cfg->dx2, cfg->dx3);
   if (rc != ATHMHD_OK) return rc;
   if (nblocks_max < 1) return fail(nullptr, ATHMHD_EINVAL, "nblocks_max must be >= 1");
   athmhd_t h = new (std::nothrow) athmhd_s();
@@ -159,27 +380,25 @@ int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
   h->cfg = *cfg;
   h->g = make_geo(cfg->n1, cfg->n2, cfg->n3, cfg->nghost, cfg->dx1, cfg->dx2, cfg->dx3);
   h->nbmax = nblocks_max;
+  read_env(h);
   hipError_t e = hipGetDevice(&h->device);
   if (e != hipSuccess) {
     rc = fail(nullptr, ATHMHD_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
     delete h;
     return rc;
   }
+  h->reg_coff = h->g.cblock * (int64_t)nblocks_max;
   const int64_t state = (h->g.cblock + h->g.fblock) * (int64_t)nblocks_max;
   const int64_t nscr =
       cfg->kernel_path == 1 ? (8 * h->g.cvar + 24 * h->g.fvar + 3 * h->g.fvar) * (int64_t)nblocks_max : 1;
   bool ok = hipMalloc(&h->reg[0], state * sizeof(double)) == hipSuccess &&
             hipMalloc(&h->reg[1], state * sizeof(double)) == hipSuccess &&
-            hipMalloc(&h->scratch_base, nscr * sizeof(double)) == hipSuccess &&
-            hipMalloc(&h->d_dt, sizeof(unsigned long long)) == hipSuccess &&
-            hipMalloc(&h->d_bad, sizeof(int)) == hipSuccess &&
-            hipHostMalloc(&h->h_pinned, 16, hipHostMallocDefault) == hipSuccess;
+            hipMalloc(&h->scratch_base, nscr * sizeof(double)) == hipSuccess && alloc_common(h);
   if (!ok) {
     (void)hipGetLastError();
     free_all(h);
     delete h;
-    return fail(nullptr, ATHMHD_ENOMEM, "device allocation of %.3f GB failed",
-                (2.0 * state + nscr) * 8.0 / 1e9);
+    return fail(nullptr, ATHMHD_ENOMEM, "device allocation of %.3f GB failed", (2.0 * state + nscr) * 8.0 / 1e9);
   }
   double* p = h->scratch_base;
   h->scr.w = p;
@@ -189,9 +408,7 @@ int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
     p += 8 * h->g.fvar * nblocks_max;
   }
   h->scr.edge = p;
-  if (const char* kz = getenv("ATHMHD_KZ")) h->kz = atoi(kz);
-  if (const char* oc = getenv("ATHMHD_OCC")) h->occ = atoi(oc) == 1 ? 1 : 2;
-  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, nullptr, h->d_dt, 0ull, h->d_bad, 1);
+  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, nullptr, h->d_dtmin, 0ull, h->d_bad, 1);
   e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     free_all(h);
@@ -199,6 +416,174 @@ int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
     return fail(nullptr, ATHMHD_EHIP, "initialisation: %s", hipGetErrorString(e));
   }
   *out = h;
+  return ATHMHD_OK;
+}
+
+int athmhd_create_batch(const athmhd_config* base, const int32_t* dims, const double* dx, int nblocks,
+                        athmhd_t* out) {
+  if (!out) return fail(nullptr, ATHMHD_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate_common(base);
+  if (rc != ATHMHD_OK) return rc;
+  if (base->kernel_path != 0) return fail(nullptr, ATHMHD_EUNSUP, "batched blocks run on the fused kernel only");
+  if (!dims || !dx) return fail(nullptr, ATHMHD_EINVAL, "NULL dims or dx");
+  if (nblocks < 1 || nblocks > 65535) return fail(nullptr, ATHMHD_EINVAL, "nblocks must be in [1, 65535]");
+  for (int b = 0; b < nblocks; ++b) {
+    rc = validate_block(dims[3 * b], dims[3 * b + 1], dims[3 * b + 2], base->nghost, dx[3 * b], dx[3 * b + 1],
+                        dx[3 * b + 2]);
+    if (rc != ATHMHD_OK) {
+      const std::string msg = g_create_err;
+      return fail(nullptr, rc, "block %d: %s", b, msg.c_str());
+    }
+  }
+  athmhd_t h = new (std::nothrow) athmhd_s();
+  if (!h) return fail(nullptr, ATHMHD_ENOMEM, "host allocation failed");
+  h->cfg = *base;
+  h->batch = true;
+  h->nbatch = nblocks;
+  h->desc.resize(nblocks);
+  for (int b = 0; b < nblocks; ++b) {
+    BatchDesc& d = h->desc[b];
+    d.g = make_geo(dims[3 * b], dims[3 * b + 1], dims[3 * b + 2], base->nghost, dx[3 * b], dx[3 * b + 1],
+                   dx[3 * b + 2]);
+    d.coff = h->ctot;
+    d.foff = h->ftot;
+    h->ctot += d.g.cblock;
+    h->ftot += d.g.fblock;
+    const Geo& g = d.g;
+    h->max_shell = std::max<int64_t>(h->max_shell, g.fvar - (int64_t)g.n1 * g.n2 * g.n3);
+    h->max_cells = std::max<int64_t>(h->max_cells, g.cvar);
+  }
+  h->g = h->desc[0].g;
+  h->nbmax = nblocks;
+  read_env(h);
+  hipError_t e = hipGetDevice(&h->device);
+  if (e != hipSuccess) {
+    rc = fail(nullptr, ATHMHD_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    delete h;
+    return rc;
+  }
+  h->reg_coff = h->ctot;
+  const int64_t state = h->ctot + h->ftot;
+  bool ok = hipMalloc(&h->reg[0], state * sizeof(double)) == hipSuccess &&
+            hipMalloc(&h->reg[1], state * sizeof(double)) == hipSuccess &&
+            hipMalloc(&h->d_desc, nblocks * sizeof(BatchDesc)) == hipSuccess &&
+            hipMalloc(&h->d_queue, sizeof(unsigned)) == hipSuccess && alloc_common(h);
+  if (!ok) {
+    (void)hipGetLastError();
+    free_all(h);
+    delete h;
+    return fail(nullptr, ATHMHD_ENOMEM, "device allocation of %.3f GB failed", 2.0 * state * 8.0 / 1e9);
+  }
+  e = hipMemcpy(h->d_desc, h->desc.data(), nblocks * sizeof(BatchDesc), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_all(h);
+    delete h;
+    return fail(nullptr, ATHMHD_EHIP, "descriptor upload: %s", hipGetErrorString(e));
+  }
+  rc = build_items(h, 0, 0);
+  if (rc != ATHMHD_OK) {
+    const std::string msg = h->err;
+    free_all(h);
+    delete h;
+    return fail(nullptr, rc, "%s", msg.c_str());
+  }
+  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, nullptr, h->d_dtmin, 0ull, h->d_bad, 1);
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free_all(h);
+    delete h;
+    return fail(nullptr, ATHMHD_EHIP, "initialisation: %s", hipGetErrorString(e));
+  }
+  *out = h;
+  return ATHMHD_OK;
+}
+
+int athmhd_batch_info(athmhd_t h, int64_t* cons_len, int64_t* bface_len, int64_t* offsets) {
+  if (!h) return ATHMHD_EINVAL;
+  if (!h->batch) return fail(h, ATHMHD_EINVAL, "not a batched handle");
+  if (cons_len) *cons_len = h->ctot;
+  if (bface_len) *bface_len = h->ftot;
+  if (offsets)
+    for (int b = 0; b < h->nbatch; ++b) {
+      offsets[2 * b] = h->desc[b].coff;
+      offsets[2 * b + 1] = h->desc[b].foff;
+    }
+  return ATHMHD_OK;
+}
+
+int athmhd_batch_set_tile(athmhd_t h, int shape, int split) {
+  if (!h) return ATHMHD_EINVAL;
+  if (!h->batch) return fail(h, ATHMHD_EINVAL, "not a batched handle");
+  if (shape < 0 || shape >= batch_tile_count() || (split != 0 && split != 1))
+    return fail(h, ATHMHD_EINVAL, "tile candidate %d / split %d out of range", shape, split);
+  return build_items(h, shape, split);
+}
+
+int athmhd_batch_tune(athmhd_t h, const double* cons, const double* bface, void* stream, int* best_shape,
+                      int* best_split, double* best_ms) {
+  if (!h) return ATHMHD_EINVAL;
+  if (!h->batch) return fail(h, ATHMHD_EINVAL, "not a batched handle");
+  int rc = check_call(h, cons, bface, h->nbatch);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  // the tuning input is a copy in register 1 with its ghosts filled, so the
+  // caller's arrays are untouched
+  hipError_t e = launch_copy(h->reg[1], cons, h->ctot, s);
+  if (e == hipSuccess) e = launch_copy(h->reg[1] + h->reg_coff, bface, h->ftot, s);
+  if (e == hipSuccess) e = fill_ghosts(h, h->reg[1], h->reg[1] + h->reg_coff, h->nbatch, s);
+  if (e != hipSuccess) return hip_fail(h, e, "tune set-up");
+  const double* xc = h->reg[1];
+  const double* xb = h->reg[1] + h->reg_coff;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(h, e, "tune events");
+  }
+  double best = 1e300;
+  int bs = 0, bsp = 0;
+  for (int shape = 0; shape < batch_tile_count() && rc == ATHMHD_OK; ++shape)
+    for (int split = 0; split < 2 && rc == ATHMHD_OK; ++split) {
+      if ((rc = build_items(h, shape, split)) != ATHMHD_OK) break;
+      const StageCoef cf{0.0, 1.0, 1e-6};
+      // one warm-up launch, then three timed launches of the configured stage
+      for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+        if (rep == 1) e = hipEventRecord(e0, s);
+        if (e == hipSuccess)
+          e = launch_stage(h, h->cfg.recon, xc, xb, xc, xb, h->reg[0], h->reg[0] + h->reg_coff, cf, 1.0, nullptr,
+                           h->nbatch, s);
+      }
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        rc = hip_fail(h, e, "tune launch");
+        break;
+      }
+      if (ms / 3.0 < best) {
+        best = ms / 3.0;
+        bs = shape;
+        bsp = split;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // the tuning launches may have counted non-physical cells of the scratch output
+  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, h->d_dtmin, 0ull, h->d_bad, 1);
+  if (rc != ATHMHD_OK) return rc;
+  if ((rc = build_items(h, bs, bsp)) != ATHMHD_OK) return rc;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(h, e, "tune synchronise");
+  if (best_shape) *best_shape = bs;
+  if (best_split) *best_split = bsp;
+  if (best_ms) *best_ms = best;
+  return ATHMHD_OK;
+}
+
+int athmhd_set_graph(athmhd_t h, int enable) {
+  if (!h) return ATHMHD_EINVAL;
+  drop_graph(h);
+  h->use_graph = enable != 0;
   return ATHMHD_OK;
 }
 
@@ -214,7 +599,7 @@ const char* athmhd_last_error(athmhd_t h) { return h ? h->err.c_str() : g_create
 int athmhd_fill_ghosts(athmhd_t h, double* cons, double* bface, int nblocks, void* stream) {
   int rc = check_call(h, cons, bface, nblocks);
   if (rc) return rc;
-  hipError_t e = launch_fill_ghosts(h->g, cons, bface, nblocks, (hipStream_t)stream);
+  hipError_t e = fill_ghosts(h, cons, bface, nblocks, (hipStream_t)stream);
   return e == hipSuccess ? ATHMHD_OK : hip_fail(h, e, "fill_ghosts launch");
 }
 
@@ -223,7 +608,9 @@ int athmhd_prim2cons(athmhd_t h, const double* prim, const double* bface, double
   int rc = check_call(h, prim, bface, nblocks);
   if (rc) return rc;
   if (!cons) return fail(h, ATHMHD_EINVAL, "NULL cons");
-  hipError_t e = launch_prim2cons(h->g, h->cfg.gamma, prim, bface, cons, nblocks, (hipStream_t)stream);
+  hipError_t e = h->batch ? launch_prim2cons_batch(h->d_desc, h->nbatch, h->max_cells, h->cfg.gamma, prim, bface,
+                                                   cons, (hipStream_t)stream)
+                          : launch_prim2cons(h->g, h->cfg.gamma, prim, bface, cons, nblocks, (hipStream_t)stream);
   return e == hipSuccess ? ATHMHD_OK : hip_fail(h, e, "prim2cons launch");
 }
 
@@ -232,52 +619,13 @@ int athmhd_step(athmhd_t h, double* cons, double* bface, double dt, int nblocks,
   if (rc) return rc;
   if (!(std::isfinite(dt) && dt > 0.0)) return fail(h, ATHMHD_EINVAL, "dt must be finite and > 0 (got %g)", dt);
   hipStream_t s = (hipStream_t)stream;
-  const Geo& g = h->g;
-  const Scheme sc = scheme_of(h->cfg.integrator);
-  const int64_t coff = g.cblock * h->nbmax;  // bface of a register follows its cons
-  const double* xc = cons;
-  const double* xb = bface;
-  hipError_t e;
-  for (int st = 0; st < sc.nstage; ++st) {
-    // ghosts of the stage input (the caller's U^n, or a register)
-    if ((e = launch_fill_ghosts(g, const_cast<double*>(xc), const_cast<double*>(xb), nblocks, s)) != hipSuccess)
-      return hip_fail(h, e, "fill_ghosts launch");
-    const bool last = st == sc.nstage - 1;
-    double* oc;
-    double* ob;
-    if (last && xc != cons) {
-      oc = cons;
-      ob = bface;
-    } else {
-      double* r = h->reg[st % 2];
-      oc = r;
-      ob = r + coff;
-    }
-    // the VL2 predictor always uses donor-cell fluxes (Sec. 3.2.3)
-    const int recon = (h->cfg.integrator == ATHMHD_VL2 && st == 0) ? ATHMHD_RECON_DC : h->cfg.recon;
-    StageCoef cf{sc.g0[st], sc.g1[st], sc.beta[st] * dt};
-    if ((e = mark(h, s)) != hipSuccess) return hip_fail(h, e, "profiling event");
-    if (h->cfg.kernel_path == 0)
-      e = launch_stage_fused(g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc, xb, cons, bface, oc, ob, cf,
-                             nblocks, h->kz, h->occ, h->d_bad, s);
-    else
-      e = launch_stage_unfused(g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc, xb, cons, bface, oc, ob,
-                               cf, nblocks, h->scr, h->d_bad, s);
-    if (e != hipSuccess) return hip_fail(h, e, "stage launch");
-    if ((e = mark(h, s)) != hipSuccess) return hip_fail(h, e, "profiling event");
-    xc = oc;
-    xb = ob;
+  if (!h->use_graph || h->profiling) return enqueue_step(h, cons, bface, dt, nullptr, nblocks, s);
+  if (!s) return fail(h, ATHMHD_EINVAL, "graph replay needs a non-default stream");
+  if (!(h->gexec && h->gkey[0] == cons && h->gkey[1] == bface && h->gkey[2] == s && h->gkey_nb == nblocks)) {
+    rc = capture_step(h, cons, bface, nblocks, s);
+    if (rc != ATHMHD_OK) return rc;
   }
-  if (xc != cons) {  // single-stage scheme: result sits in a register
-    for (int b = 0; b < nblocks; ++b) {
-      if ((e = launch_copy(cons + b * g.cblock, xc + b * g.cblock, g.cblock, s)) != hipSuccess)
-        return hip_fail(h, e, "copy launch");
-      if ((e = launch_copy(bface + b * g.fblock, xb + b * g.fblock, g.fblock, s)) != hipSuccess)
-        return hip_fail(h, e, "copy launch");
-    }
-  }
-  if ((e = launch_fill_ghosts(g, cons, bface, nblocks, s)) != hipSuccess) return hip_fail(h, e, "fill_ghosts launch");
-  return ATHMHD_OK;
+  return replay_step(h, dt, s);
 }
 
 int athmhd_newdt(athmhd_t h, const double* cons, const double* bface, int nblocks, double* dt_host, void* stream) {
@@ -288,13 +636,14 @@ int athmhd_newdt(athmhd_t h, const double* cons, const double* bface, int nblock
   const double inf = INFINITY;
   unsigned long long inf_bits;
   std::memcpy(&inf_bits, &inf, 8);
-  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, h->d_dt, inf_bits, h->d_bad, 0);
+  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, h->d_dtmin, inf_bits, h->d_bad, 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(h, e, "newdt init launch");
-  if ((e = launch_newdt(h->g, h->cfg.gamma, cons, bface, nblocks, h->d_dt, h->d_bad, s)) != hipSuccess)
-    return hip_fail(h, e, "newdt launch");
+  e = h->batch ? launch_newdt_batch(h->d_desc, h->nbatch, 0, h->cfg.gamma, cons, bface, h->d_dtmin, h->d_bad, s)
+               : launch_newdt(h->g, h->cfg.gamma, cons, bface, nblocks, h->d_dtmin, h->d_bad, s);
+  if (e != hipSuccess) return hip_fail(h, e, "newdt launch");
   char* hp = (char*)h->h_pinned;
-  if ((e = hipMemcpyAsync(hp, h->d_dt, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+  if ((e = hipMemcpyAsync(hp, h->d_dtmin, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
       (e = hipMemcpyAsync(hp + 8, h->d_bad, 4, hipMemcpyDeviceToHost, s)) != hipSuccess)
     return hip_fail(h, e, "newdt copy");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(h, e, "newdt synchronise");
@@ -306,7 +655,7 @@ int athmhd_newdt(athmhd_t h, const double* cons, const double* bface, int nblock
   std::memcpy(&m, &bits, 8);
   *dt_host = h->cfg.cfl * m;
   if (bad != 0) {
-    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, h->d_dt, bits, h->d_bad, 1);
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, h->d_dtmin, bits, h->d_bad, 1);
     (void)hipStreamSynchronize(s);
     return fail(h, ATHMHD_ENONPHYS, "%d non-physical cell evaluations (rho <= 0, P <= 0 or not finite)", bad);
   }

@@ -36,10 +36,42 @@ hipError_t launch_stage_unfused(const Geo& g, double gamma, int recon, int rs, d
 // One stage in a single fused kernel (same contract as launch_stage_unfused);
 // kz = x3 planes per workgroup segment (0: default for the block size);
 // occ = register-allocation target in waves per SIMD (1 or 2).
+// dt_dev, if not NULL, supplies dt on the device (bdt = beta * dt).
 hipError_t launch_stage_fused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
                               const double* xb, const double* unc, const double* unb, double* outc, double* outb,
-                              StageCoef coef, int nb, int kz, int occ, int* bad, hipStream_t s);
+                              StageCoef coef, const double* dt_dev, double beta, int nb, int kz, int occ, int* bad,
+                              hipStream_t s);
 int fused_default_kz(const Geo& g);
+
+// Batched blocks of uneven sizes.  One block descriptor per block: its
+// geometry and the offsets (in doubles) of its cons and bface in the
+// concatenated arrays.  One work item per (block, tile, x3 segment).
+struct BatchDesc {
+  Geo g;
+  int64_t coff, foff;
+};
+struct WorkItem {
+  int block, tile_x, tile_y, k0, kend;
+};
+int batch_tile_count();                             // candidate thread tiles
+void batch_tile_shape(int shape, int* tx, int* ty);  // active columns of a candidate
+int batch_tile_threads(int shape);
+// One stage of all blocks in one persistent launch of `grid` workgroups that
+// drain the item queue.  dt_dev, if not NULL, supplies dt on the device
+// (bdt = beta * dt); otherwise coef.bdt is used.
+hipError_t launch_stage_batch(int shape, double gamma, int recon, int rs, double ct_eps, const BatchDesc* desc,
+                              const WorkItem* items, int nitems, unsigned* queue, const double* xc,
+                              const double* xb, const double* unc, const double* unb, double* outc, double* outb,
+                              StageCoef coef, const double* dt_dev, double beta, int grid, int* bad,
+                              hipStream_t s);
+// Ghost fill, prim->cons and the CFL reduction over all blocks of a batch.
+hipError_t launch_fill_ghosts_batch(const BatchDesc* desc, int nblocks, int64_t max_shell, double* cons,
+                                    double* bface, hipStream_t s);
+hipError_t launch_prim2cons_batch(const BatchDesc* desc, int nblocks, int64_t max_cells, double gamma,
+                                  const double* prim, const double* bface, double* cons, hipStream_t s);
+hipError_t launch_newdt_batch(const BatchDesc* desc, int nblocks, int64_t max_active, double gamma,
+                              const double* cons, const double* bface, unsigned long long* dt_bits, int* bad,
+                              hipStream_t s);
 
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
 

@@ -149,7 +149,148 @@ __global__ void __launch_bounds__(kThreads) k_copy(double* __restrict__ dst, con
   if (t < n) dst[t] = src[t];
 }
 
+// ---- batched variants: blockIdx.y selects the block, its geometry and the
+// offsets of its arrays come from the descriptor table
+__global__ void __launch_bounds__(kThreads) k_fill_ghosts_batch(const BatchDesc* __restrict__ desc, double* cons,
+                                                               double* bface) {
+  const BatchDesc& d = desc[blockIdx.y];
+  const Geo& g = d.g;
+  const int64_t nz = (int64_t)(g.F3 - g.n3) * g.F2 * g.F1;
+  const int64_t ny = (int64_t)g.n3 * (g.F2 - g.n2) * g.F1;
+  const int64_t nx = (int64_t)g.n3 * g.n2 * (g.F1 - g.n1);
+  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < nz + ny + nx;
+       t += (int64_t)gridDim.x * kThreads) {
+    int i, j, k;
+    if (t < nz) {
+      i = (int)(t % g.F1);
+      const int64_t r = t / g.F1;
+      j = (int)(r % g.F2);
+      k = ghost_index((int)(r / g.F2), g.n3, g.ng);
+    } else if (t < nz + ny) {
+      const int64_t u = t - nz;
+      i = (int)(u % g.F1);
+      const int64_t r = u / g.F1;
+      j = ghost_index((int)(r % (g.F2 - g.n2)), g.n2, g.ng);
+      k = g.ng + (int)(r / (g.F2 - g.n2));
+    } else {
+      const int64_t u = t - nz - ny;
+      i = ghost_index((int)(u % (g.F1 - g.n1)), g.n1, g.ng);
+      const int64_t r = u / (g.F1 - g.n1);
+      j = g.ng + (int)(r % g.n2);
+      k = g.ng + (int)(r / g.n2);
+    }
+    const int ii = wrap_index(i, g.n1, g.ng), jj = wrap_index(j, g.n2, g.ng), kk = wrap_index(k, g.n3, g.ng);
+    double* cb = cons + d.coff;
+    double* fb = bface + d.foff;
+    if (i < g.N1 && j < g.N2 && k < g.N3) {
+      const int dd = g.c(i, j, k), ss = g.c(ii, jj, kk);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) cb[v * g.cvar + dd] = cb[v * g.cvar + ss];
+    }
+    const int dd = g.f(i, j, k), ss = g.f(ii, jj, kk);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fb[c * g.fvar + dd] = fb[c * g.fvar + ss];
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_prim2cons_batch(const BatchDesc* __restrict__ desc, double gamma,
+                                                             const double* __restrict__ prim,
+                                                             const double* __restrict__ bface,
+                                                             double* __restrict__ cons) {
+  const BatchDesc& d = desc[blockIdx.y];
+  const Geo& g = d.g;
+  const double* w = prim + d.coff;
+  const double* fb = bface + d.foff;
+  double* u = cons + d.coff;
+  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < g.cvar; t += (int64_t)gridDim.x * kThreads) {
+    const int i = (int)(t % g.N1);
+    const int r = (int)(t / g.N1);
+    const int j = r % g.N2, k = r / g.N2;
+    const double b1 = 0.5 * (fb[g.f(i, j, k)] + fb[g.f(i + 1, j, k)]);
+    const double b2 = 0.5 * (fb[g.fvar + g.f(i, j, k)] + fb[g.fvar + g.f(i, j + 1, k)]);
+    const double b3 = 0.5 * (fb[2 * g.fvar + g.f(i, j, k)] + fb[2 * g.fvar + g.f(i, j, k + 1)]);
+    const double rho = w[t], v1 = w[g.cvar + t], v2 = w[2 * g.cvar + t], v3 = w[3 * g.cvar + t];
+    const double p = w[4 * g.cvar + t];
+    u[t] = rho;
+    u[g.cvar + t] = rho * v1;
+    u[2 * g.cvar + t] = rho * v2;
+    u[3 * g.cvar + t] = rho * v3;
+    u[4 * g.cvar + t] =
+        p / (gamma - 1.0) + 0.5 * rho * (v1 * v1 + v2 * v2 + v3 * v3) + 0.5 * (b1 * b1 + b2 * b2 + b3 * b3);
+  }
+}
+
+// one workgroup per block: its minimum of dx_d/(|v_d| + c_f,d), then one
+// atomicMin per block
+__global__ void __launch_bounds__(kThreads) k_newdt_batch(const BatchDesc* __restrict__ desc, double gamma,
+                                                         const double* __restrict__ cons,
+                                                         const double* __restrict__ bface,
+                                                         unsigned long long* __restrict__ dt_bits,
+                                                         int* __restrict__ bad) {
+  const BatchDesc& d = desc[blockIdx.x];
+  const Geo& g = d.g;
+  const double* u = cons + d.coff;
+  const double* fb = bface + d.foff;
+  const int64_t nact = (int64_t)g.n1 * g.n2 * g.n3;
+  double best = DBL_MAX;
+  int nbad = 0;
+  for (int64_t t = threadIdx.x; t < nact; t += kThreads) {
+    const int i = g.ng + (int)(t % g.n1);
+    const int r = (int)(t / g.n1);
+    const int j = g.ng + r % g.n2, k = g.ng + r / g.n2;
+    const int q = g.c(i, j, k), f = g.f(i, j, k);
+    const double b1 = 0.5 * (fb[f] + fb[f + 1]);
+    const double b2 = 0.5 * (fb[g.fvar + f] + fb[g.fvar + f + g.F1]);
+    const double b3 = 0.5 * (fb[2 * g.fvar + f] + fb[2 * g.fvar + f + g.F1 * g.F2]);
+    const double rho = u[q], ir = frcp(rho);
+    const double v1 = u[g.cvar + q] * ir, v2 = u[2 * g.cvar + q] * ir, v3 = u[3 * g.cvar + q] * ir;
+    const double p = (gamma - 1.0) * (u[4 * g.cvar + q] - 0.5 * rho * (v1 * v1 + v2 * v2 + v3 * v3) -
+                                      0.5 * (b1 * b1 + b2 * b2 + b3 * b3));
+    if (!(rho > 0.0) || !(p > 0.0)) {
+      ++nbad;
+      continue;
+    }
+    const double bs1 = b1 * b1, bs2 = b2 * b2, bs3 = b3 * b3;
+    const double c1 = fast_speed(ir, p, bs1, bs2 + bs3, gamma);
+    const double c2 = fast_speed(ir, p, bs2, bs3 + bs1, gamma);
+    const double c3 = fast_speed(ir, p, bs3, bs1 + bs2, gamma);
+    const double dd = fmin(g.dx1 * frcp(fabs(v1) + c1), fmin(g.dx2 * frcp(fabs(v2) + c2), g.dx3 * frcp(fabs(v3) + c3)));
+    if (!(dd > 0.0) || !(dd < DBL_MAX)) ++nbad;
+    else best = fmin(best, dd);
+  }
+  if (nbad) atomicAdd(bad, nbad);
+  for (int off = 32; off > 0; off >>= 1) best = fmin(best, __shfl_xor(best, off, 64));
+  __shared__ double part[kThreads / 64];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = part[0];
+    for (int w = 1; w < kThreads / 64; ++w) m = fmin(m, part[w]);
+    if (m < DBL_MAX) atomicMin(dt_bits, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
 }  // namespace
+
+hipError_t launch_fill_ghosts_batch(const BatchDesc* desc, int nblocks, int64_t max_shell, double* cons,
+                                    double* bface, hipStream_t s) {
+  const unsigned gx = (unsigned)std::min<int64_t>(grid_for(max_shell), 64);
+  hipLaunchKernelGGL(k_fill_ghosts_batch, dim3(gx, nblocks), dim3(kThreads), 0, s, desc, cons, bface);
+  return hipGetLastError();
+}
+
+hipError_t launch_prim2cons_batch(const BatchDesc* desc, int nblocks, int64_t max_cells, double gamma,
+                                  const double* prim, const double* bface, double* cons, hipStream_t s) {
+  const unsigned gx = (unsigned)std::min<int64_t>(grid_for(max_cells), 64);
+  hipLaunchKernelGGL(k_prim2cons_batch, dim3(gx, nblocks), dim3(kThreads), 0, s, desc, gamma, prim, bface, cons);
+  return hipGetLastError();
+}
+
+hipError_t launch_newdt_batch(const BatchDesc* desc, int nblocks, int64_t, double gamma, const double* cons,
+                              const double* bface, unsigned long long* dt_bits, int* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_newdt_batch, dim3(nblocks), dim3(kThreads), 0, s, desc, gamma, cons, bface, dt_bits, bad);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill_ghosts(const Geo& g, double* cons, double* bface, int nb, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_ghosts, dim3(grid_for(ghost_count(g)), nb), dim3(kThreads), 0, s, g, cons, bface);

@@ -27,24 +27,61 @@ namespace athmhd {
 
 namespace {
 
-constexpr int BX = 16, BY = 16, NT = BX * BY;  // threads per workgroup
-constexpr int TX = BX - 2, TY = BY - 2;        // active columns per tile
+// Thread tile: BX x BY threads, one per column of a (BX-2) x (BY-2) tile of
+// active columns plus a one-column ring.
+template <int BX_, int BY_>
+struct Tile {
+  static constexpr int BX = BX_, BY = BY_, NT = BX_ * BY_, TX = BX_ - 2, TY = BY_ - 2;
+};
+using TileU = Tile<16, 16>;  // uniform blocks: 14 x 14 active columns
 
-struct FusedArgs {
-  Geo g;
+// Arguments shared by every tile of a stage.
+struct StageArgs {
   Gas gas;
   double ct_eps;
-  const double* xc;   // stage input, ghosts filled
-  const double* xb;
-  const double* unc;  // U^n (the u^(1) register)
-  const double* unb;
-  double* oc;         // stage output (active cells and their lower faces)
-  double* ob;
-  StageCoef cf;
-  int ntx, nty, nseg, kz;
-  int64_t total;      // workgroups doing work
-  int64_t per_xcd;    // ceil(total / 8)
+  StageCoef cf;          // g0, g1 and (when dt_dev is NULL) beta * dt
+  const double* dt_dev;  // optional device copy of dt: bdt = beta * (*dt_dev)
+  double beta;
   int* bad;
+};
+
+// Arrays of one block: stage input (ghosts filled), U^n (the u^(1) register),
+// stage output (active cells and their lower faces).
+struct BlockPtrs {
+  const double* xc;
+  const double* xb;
+  const double* unc;
+  const double* unb;
+  double* oc;
+  double* ob;
+};
+
+struct UniformArgs {
+  Geo g;
+  StageArgs sa;
+  const double* xc;
+  const double* xb;
+  const double* unc;
+  const double* unb;
+  double* oc;
+  double* ob;
+  int ntx, nty, nseg, kz;
+  int64_t total;    // workgroups doing work
+  int64_t per_xcd;  // ceil(total / 8)
+};
+
+struct BatchArgs {
+  const BatchDesc* desc;
+  const WorkItem* items;
+  int nitems;
+  unsigned* queue;  // work counter, zero at launch
+  StageArgs sa;
+  const double* xc;
+  const double* xb;
+  const double* unc;
+  const double* unb;
+  double* oc;
+  double* ob;
 };
 
 // z-frame primitive vector of a cell: (rho, v3, v1, v2, P, B1cc, B2cc) plus
@@ -128,10 +165,10 @@ __device__ __forceinline__ void riemann(const double* ql, const double* qr, doub
 // LDS layout: the primitive plane (with LA extra rings), the per-thread
 // exchange slots and the corner EMFs are separate, so a thread can publish
 // each Riemann result as soon as it has it.
-template <int LA>
+template <int LA, class T>
 struct Smem {
-  static constexpr int PW = BX + 2 * LA;  // width of the primitive plane incl. extra rings
-  static constexpr int PH = BY + 2 * LA;
+  static constexpr int PW = T::BX + 2 * LA;  // width of the primitive plane incl. extra rings
+  static constexpr int PH = T::BY + 2 * LA;
   static constexpr int PL = PW * PH;
 };
 
@@ -139,35 +176,23 @@ enum {
   X_FX = 0, X_FY = 5, X_E3X = 10, X_WX, X_E3Y, X_WY, X_E3C, X_E1Z, X_E2Z, X_WZ, X_E1C, X_E2C, X_E1CP, X_E2CP, X_N
 };
 
-// OCC: minimum waves per SIMD the register allocation must allow (1 lets the
-// compiler use the whole register file, 2 caps it at 256 with some spilling).
-template <int RECON, int RS, int OCC>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) k_stage_fused(FusedArgs a) {
+// One tile (tile_x, tile_y) of a block over the active planes [k0, kend).
+template <int RECON, int RS, class T>
+__device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, const StageArgs& sa, int tile_x,
+                                           int tile_y, int k0, int kend, double* __restrict__ sp,
+                                           double* __restrict__ sx, double* __restrict__ sc) {
   constexpr int LA = RECON;  // cells of look-ahead / extra LDS rings: DC 0, PLM 1, PPM 2
   constexpr int NW = 2 * LA + 1;
-  using S = Smem<LA>;
+  constexpr int BX = T::BX, BY = T::BY, NT = T::NT, TX = T::TX, TY = T::TY;
+  using S = Smem<LA, T>;
   constexpr int PW = S::PW, PL = S::PL;
-  __shared__ double sp[8 * PL];    // primitives of the current plane
-  __shared__ double sx[X_N * NT];  // exchange slots
-  __shared__ double sc[3 * NT];    // corner EMFs E1, E2, E3 of the current (half-)plane
-
-  // ---- workgroup -> (tile, segment, block), XCD-aware: consecutive logical
-  // tiles land on the same XCD so that halo overlap hits its L2
-  const int64_t bid = blockIdx.x;
-  const int64_t logical = (bid % 8) * a.per_xcd + bid / 8;
-  if (logical >= a.total) return;
-  const Geo& g = a.g;
-  int64_t r = logical;
-  const int tile_x = (int)(r % a.ntx); r /= a.ntx;
-  const int tile_y = (int)(r % a.nty); r /= a.nty;
-  const int seg = (int)(r % a.nseg); r /= a.nseg;
-  const int blk = (int)r;
-  const double* xc = a.xc + blk * g.cblock;
-  const double* xb = a.xb + blk * g.fblock;
-  const double* unc = a.unc + blk * g.cblock;
-  const double* unb = a.unb + blk * g.fblock;
-  double* oc = a.oc + blk * g.cblock;
-  double* ob = a.ob + blk * g.fblock;
+  const double* __restrict__ xc = bp.xc;
+  const double* __restrict__ xb = bp.xb;
+  const double* __restrict__ unc = bp.unc;
+  const double* __restrict__ unb = bp.unb;
+  double* __restrict__ oc = bp.oc;
+  double* __restrict__ ob = bp.ob;
+  const double bdt = sa.dt_dev ? sa.beta * *sa.dt_dev : sa.cf.bdt;
 
   const int tid = threadIdx.x;
   const int tx = tid % BX, ty = tid / BX;
@@ -177,27 +202,32 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) 
   const int gi_raw = x0 - 1 + tx, gj_raw = y0 - 1 + ty;
   const int gi = min(gi_raw, g.N1 - 1), gj = min(gj_raw, g.N2 - 1);
   const bool act = tx >= 1 && tx <= TX && ty >= 1 && ty <= TY && gi_raw < g.ng + g.n1 && gj_raw < g.ng + g.n2;
-  const int k0 = g.ng + seg * a.kz;
-  const int kend = min(k0 + a.kz, g.ng + g.n3);  // exclusive
 
-  // ---- extra LDS rings (LA per side), one cell per thread for tid < 64 LA
-  constexpr int NRING = 64 * LA;
+  // ---- extra LDS rings (LA per side): left and right columns (BY cells per
+  // depth), bottom and top rows (BX cells per depth), one cell per thread
+  constexpr int NRING = 2 * LA * (BX + BY);
+  static_assert(NRING <= NT, "ring cells must fit the workgroup");
   const bool ring = tid < NRING;
   int rl = 0, rgi = 0, rgj = 0;
   if (ring) {
-    const int side = tid / (16 * LA), e = tid % (16 * LA), d = e / 16, pos = e % 16;
     int rlx, rly;
-    if (side == 0) { rlx = LA - 1 - d; rly = LA + pos; }
-    else if (side == 1) { rlx = LA + 16 + d; rly = LA + pos; }
-    else if (side == 2) { rlx = LA + pos; rly = LA - 1 - d; }
-    else { rlx = LA + pos; rly = LA + 16 + d; }
+    if (tid < 2 * LA * BY) {
+      const int side = tid / (LA * BY), e = tid % (LA * BY), d = e / BY, pos = e % BY;
+      rly = LA + pos;
+      rlx = side == 0 ? LA - 1 - d : LA + BX + d;
+    } else {
+      const int u = tid - 2 * LA * BY;
+      const int side = u / (LA * BX), e = u % (LA * BX), d = e / BX, pos = e % BX;
+      rlx = LA + pos;
+      rly = side == 0 ? LA - 1 - d : LA + BY + d;
+    }
     rl = rly * PW + rlx;
     rgi = min(max(x0 - 1 - LA + rlx, 0), g.N1 - 1);
     rgj = min(max(y0 - 1 - LA + rly, 0), g.N2 - 1);
   }
 
   const double i1 = 1.0 / g.dx1, i2 = 1.0 / g.dx2, i3 = 1.0 / g.dx3;
-  const double gm1 = a.gas.gm1;
+  const double gm1 = sa.gas.gm1;
   int nbad = 0;
 
   // ---- z window: planes p-LA .. p+LA of the own column
@@ -289,7 +319,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) 
       if (zface) {
         const double bn3 = xb[2 * g.fvar + g.f(gi, gj, p)];
         FaceFlux fz;
-        riemann<RS>(zl, zr, bn3, a.gas, a.ct_eps, fz, wz);
+        riemann<RS>(zl, zr, bn3, sa.gas, sa.ct_eps, fz, wz);
         // z-frame -> (rho, M1, M2, M3, E); x3-face E2 = -F(B1), E1 = +F(B2)
         fz_cons[0] = fz.rho; fz_cons[1] = fz.mt1; fz_cons[2] = fz.mt2; fz_cons[3] = fz.mn; fz_cons[4] = fz.e;
         e2z = -fz.bt1;
@@ -327,7 +357,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) 
         }
         const double bn1 = xb[g.f(gi, gj, p)];
         FaceFlux fx;
-        riemann<RS>(ql, qr, bn1, a.gas, a.ct_eps, fx, wx);
+        riemann<RS>(ql, qr, bn1, sa.gas, sa.ct_eps, fx, wx);
         sx[(X_FX + 0) * NT + tid] = fx.rho;
         sx[(X_FX + 1) * NT + tid] = fx.mn;   // M1
         sx[(X_FX + 2) * NT + tid] = fx.mt1;  // M2
@@ -364,7 +394,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) 
         }
         const double bn2 = xb[g.fvar + g.f(gi, gj, p)];
         FaceFlux fy;
-        riemann<RS>(ql, qr, bn2, a.gas, a.ct_eps, fy, wy);
+        riemann<RS>(ql, qr, bn2, sa.gas, sa.ct_eps, fy, wy);
         sx[(X_FY + 0) * NT + tid] = fy.rho;
         sx[(X_FY + 1) * NT + tid] = fy.mt2;  // M1
         sx[(X_FY + 2) * NT + tid] = fy.mn;   // M2
@@ -419,8 +449,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) 
         const int q = g.c(gi, gj, p - 1);
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-          double y = a.cf.g1 * unc[v * g.cvar + q] + a.cf.bdt * acc_prev[v];
-          if (a.cf.g0 != 0.0) y += a.cf.g0 * xc[v * g.cvar + q];
+          double y = sa.cf.g1 * unc[v * g.cvar + q] + bdt * acc_prev[v];
+          if (sa.cf.g0 != 0.0) y += sa.cf.g0 * xc[v * g.cvar + q];
           oc[v * g.cvar + q] = y;
         }
       }
@@ -440,17 +470,17 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) 
       const double db3 = -(sc[1 * NT + tE] - e2) * i1 + (sc[0 * NT + tN] - e1) * i2;
       if (p < kend) {
         const int f = g.f(gi, gj, p);
-        double y = a.cf.g1 * unb[2 * g.fvar + f] + a.cf.bdt * db3;
-        if (a.cf.g0 != 0.0) y += a.cf.g0 * xb[2 * g.fvar + f];
+        double y = sa.cf.g1 * unb[2 * g.fvar + f] + bdt * db3;
+        if (sa.cf.g0 != 0.0) y += sa.cf.g0 * xb[2 * g.fvar + f];
         ob[2 * g.fvar + f] = y;
       }
       if (p - 1 >= k0) {
         const int f = g.f(gi, gj, p - 1);
-        double y1 = a.cf.g1 * unb[f] + a.cf.bdt * acc_prev[5];
-        double y2 = a.cf.g1 * unb[g.fvar + f] + a.cf.bdt * acc_prev[6];
-        if (a.cf.g0 != 0.0) {
-          y1 += a.cf.g0 * xb[f];
-          y2 += a.cf.g0 * xb[g.fvar + f];
+        double y1 = sa.cf.g1 * unb[f] + bdt * acc_prev[5];
+        double y2 = sa.cf.g1 * unb[g.fvar + f] + bdt * acc_prev[6];
+        if (sa.cf.g0 != 0.0) {
+          y1 += sa.cf.g0 * xb[f];
+          y2 += sa.cf.g0 * xb[g.fvar + f];
         }
         ob[f] = y1;
         ob[g.fvar + f] = y2;
@@ -467,12 +497,63 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) 
     e1c_prev = e1c;
     e2c_prev = e2c;
   }
-  if (nbad && act) atomicAdd(a.bad, 1);
+  if (nbad && act) atomicAdd(sa.bad, 1);
+}
+
+// Uniform blocks: one workgroup per (tile, x3 segment, block), XCD-aware:
+// consecutive logical tiles land on the same XCD so that halo overlap hits its
+// L2.
+template <int RECON, int RS, int OCC>
+__global__ void __launch_bounds__(TileU::NT) __attribute__((amdgpu_waves_per_eu(OCC)))
+k_stage_fused(UniformArgs a) {
+  using T = TileU;
+  using S = Smem<RECON, T>;
+  __shared__ double sp[8 * S::PL];      // primitives of the current plane
+  __shared__ double sx[X_N * T::NT];    // exchange slots
+  __shared__ double sc[3 * T::NT];      // corner EMFs E1, E2, E3 of the current (half-)plane
+  const int64_t bid = blockIdx.x;
+  const int64_t logical = (bid % 8) * a.per_xcd + bid / 8;
+  if (logical >= a.total) return;
+  const Geo& g = a.g;
+  int64_t r = logical;
+  const int tile_x = (int)(r % a.ntx); r /= a.ntx;
+  const int tile_y = (int)(r % a.nty); r /= a.nty;
+  const int seg = (int)(r % a.nseg); r /= a.nseg;
+  const int64_t blk = r;
+  BlockPtrs bp{a.xc + blk * g.cblock, a.xb + blk * g.fblock, a.unc + blk * g.cblock,
+               a.unb + blk * g.fblock, a.oc + blk * g.cblock, a.ob + blk * g.fblock};
+  const int k0 = g.ng + seg * a.kz;
+  const int kend = min(k0 + a.kz, g.ng + g.n3);
+  stage_tile<RECON, RS, T>(g, bp, a.sa, tile_x, tile_y, k0, kend, sp, sx, sc);
+}
+
+// Batched blocks of uneven sizes: a persistent grid whose workgroups pull
+// (block, tile, x3 segment) items from a device queue until it is drained.
+template <int RECON, int RS, class T>
+__global__ void __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(2))) k_stage_batch(BatchArgs a) {
+  using S = Smem<RECON, T>;
+  __shared__ double sp[8 * S::PL];
+  __shared__ double sx[X_N * T::NT];
+  __shared__ double sc[3 * T::NT];
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(a.queue, 1u);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    if (it >= a.nitems) break;
+    const WorkItem w = a.items[it];
+    const BatchDesc& d = a.desc[w.block];
+    BlockPtrs bp{a.xc + d.coff, a.xb + d.foff, a.unc + d.coff, a.unb + d.foff, a.oc + d.coff, a.ob + d.foff};
+    stage_tile<RECON, RS, T>(d.g, bp, a.sa, w.tile_x, w.tile_y, w.k0, w.kend, sp, sx, sc);
+    __syncthreads();
+  }
 }
 
 template <int RECON>
-hipError_t launch_rs(int rs, int occ, const FusedArgs& fa, hipStream_t s) {
+hipError_t launch_rs(int rs, int occ, const UniformArgs& fa, hipStream_t s) {
   const unsigned grid = (unsigned)(8 * fa.per_xcd);
+  constexpr int NT = TileU::NT;
   if (occ == 2) {
     if (rs == 1) hipLaunchKernelGGL((k_stage_fused<RECON, 1, 2>), dim3(grid), dim3(NT), 0, s, fa);
     else hipLaunchKernelGGL((k_stage_fused<RECON, 0, 2>), dim3(grid), dim3(NT), 0, s, fa);
@@ -483,29 +564,94 @@ hipError_t launch_rs(int rs, int occ, const FusedArgs& fa, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ void k_zero_u32(unsigned* p) {
+  if (threadIdx.x == 0) *p = 0u;
+}
+
+template <class T, int RECON>
+hipError_t launch_batch_t(int rs, const BatchArgs& ba, int grid, hipStream_t s) {
+  if (rs == 1) hipLaunchKernelGGL((k_stage_batch<RECON, 1, T>), dim3(grid), dim3(T::NT), 0, s, ba);
+  else hipLaunchKernelGGL((k_stage_batch<RECON, 0, T>), dim3(grid), dim3(T::NT), 0, s, ba);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_batch_recon(int recon, int rs, const BatchArgs& ba, int grid, hipStream_t s) {
+  if (recon == 0) return launch_batch_t<T, 0>(rs, ba, grid, s);
+  if (recon == 1) return launch_batch_t<T, 1>(rs, ba, grid, s);
+  return launch_batch_t<T, 2>(rs, ba, grid, s);
+}
+
 }  // namespace
 
 int fused_default_kz(const Geo& g) { return g.n3 >= 64 ? 32 : (g.n3 >= 16 ? 16 : g.n3); }
 
+static StageArgs make_stage_args(double gamma, double ct_eps, StageCoef coef, const double* dt_dev, double beta,
+                                 int* bad) {
+  StageArgs sa;
+  sa.gas = Gas{gamma, gamma - 1.0, 1.0 / (gamma - 1.0)};
+  sa.ct_eps = ct_eps;
+  sa.cf = coef;
+  sa.dt_dev = dt_dev;
+  sa.beta = beta;
+  sa.bad = bad;
+  return sa;
+}
+
 hipError_t launch_stage_fused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
                               const double* xb, const double* unc, const double* unb, double* outc, double* outb,
-                              StageCoef coef, int nb, int kz, int occ, int* bad, hipStream_t s) {
-  FusedArgs fa;
+                              StageCoef coef, const double* dt_dev, double beta, int nb, int kz, int occ, int* bad,
+                              hipStream_t s) {
+  UniformArgs fa;
   fa.g = g;
-  fa.gas = Gas{gamma, gamma - 1.0, 1.0 / (gamma - 1.0)};
-  fa.ct_eps = ct_eps;
+  fa.sa = make_stage_args(gamma, ct_eps, coef, dt_dev, beta, bad);
   fa.xc = xc; fa.xb = xb; fa.unc = unc; fa.unb = unb; fa.oc = outc; fa.ob = outb;
-  fa.cf = coef;
   fa.kz = kz > 0 ? kz : fused_default_kz(g);
-  fa.ntx = (g.n1 + TX - 1) / TX;
-  fa.nty = (g.n2 + TY - 1) / TY;
+  fa.ntx = (g.n1 + TileU::TX - 1) / TileU::TX;
+  fa.nty = (g.n2 + TileU::TY - 1) / TileU::TY;
   fa.nseg = (g.n3 + fa.kz - 1) / fa.kz;
   fa.total = (int64_t)fa.ntx * fa.nty * fa.nseg * nb;
   fa.per_xcd = (fa.total + 7) / 8;
-  fa.bad = bad;
   if (recon == 0) return launch_rs<0>(rs, occ, fa, s);
   if (recon == 1) return launch_rs<1>(rs, occ, fa, s);
   return launch_rs<2>(rs, occ, fa, s);
+}
+
+int batch_tile_count() { return 4; }
+
+void batch_tile_shape(int shape, int* tx, int* ty) {
+  static const int t[4][2] = {{16, 8}, {8, 16}, {14, 14}, {8, 8}};
+  *tx = t[shape][0];
+  *ty = t[shape][1];
+}
+
+int batch_tile_threads(int shape) {
+  int tx, ty;
+  batch_tile_shape(shape, &tx, &ty);
+  return (tx + 2) * (ty + 2);
+}
+
+hipError_t launch_stage_batch(int shape, double gamma, int recon, int rs, double ct_eps, const BatchDesc* desc,
+                              const WorkItem* items, int nitems, unsigned* queue, const double* xc,
+                              const double* xb, const double* unc, const double* unb, double* outc, double* outb,
+                              StageCoef coef, const double* dt_dev, double beta, int grid, int* bad,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, queue);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  BatchArgs ba;
+  ba.desc = desc;
+  ba.items = items;
+  ba.nitems = nitems;
+  ba.queue = queue;
+  ba.sa = make_stage_args(gamma, ct_eps, coef, dt_dev, beta, bad);
+  ba.xc = xc; ba.xb = xb; ba.unc = unc; ba.unb = unb; ba.oc = outc; ba.ob = outb;
+  switch (shape) {
+    case 0: return launch_batch_recon<Tile<18, 10>>(recon, rs, ba, grid, s);
+    case 1: return launch_batch_recon<Tile<10, 18>>(recon, rs, ba, grid, s);
+    case 2: return launch_batch_recon<Tile<16, 16>>(recon, rs, ba, grid, s);
+    default: return launch_batch_recon<Tile<10, 10>>(recon, rs, ba, grid, s);
+  }
 }
 
 }  // namespace athmhd

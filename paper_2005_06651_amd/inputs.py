@@ -359,3 +359,90 @@ def divb_metric(bf: np.ndarray, n, ng, dx) -> float:
     div = (np.diff(b1, axis=2) / dx[0] + np.diff(b2, axis=1) / dx[1] + np.diff(b3, axis=0) / dx[2])
     bmax = max(np.abs(b1).max(), np.abs(b2).max(), np.abs(b3).max(), 1e-300)
     return float(np.abs(div).max() * min(dx) / bmax)
+
+
+# ---------------------------------------------------------------------------
+# Batched AMR-shaped workload: leaves of a seeded 2:1-balanced octree
+# ---------------------------------------------------------------------------
+def _morton3(x: int, y: int, z: int, bits: int = 10) -> int:
+    key = 0
+    for b in range(bits):
+        key |= ((x >> b) & 1) << (3 * b) | ((y >> b) & 1) << (3 * b + 1) | ((z >> b) & 1) << (3 * b + 2)
+    return key
+
+
+def balanced_octree(nleaves: int, seed: int = 0, root_level: int = 2, max_level: int = 6):
+    """Leaves (level, i, j, k) of a periodic octree on the unit cube, grown by
+    refining seeded random leaves while keeping every pair of touching leaves
+    (faces, edges, corners, periodic) within one level; at least nleaves
+    leaves, returned in Morton order of their lower corner."""
+    rng = np.random.default_rng(seed)
+    leaves = {(root_level, i, j, k) for i in range(1 << root_level) for j in range(1 << root_level)
+              for k in range(1 << root_level)}
+
+    def level_at(lev, i, j, k):
+        # level of the leaf covering the fine cell (i, j, k) at level lev
+        n = 1 << lev
+        i, j, k = i % n, j % n, k % n
+        for L in range(lev, -1, -1):
+            s = lev - L
+            key = (L, i >> s, j >> s, k >> s)
+            if key in leaves:
+                return L
+        return None
+
+    def neighbours_ok(leaf):
+        L, i, j, k = leaf
+        for di in (-1, 0, 1):
+            for dj in (-1, 0, 1):
+                for dk in (-1, 0, 1):
+                    if di == dj == dk == 0:
+                        continue
+                    lv = level_at(L, i + di, j + dj, k + dk)
+                    if lv is not None and lv < L:
+                        return False
+        return True
+
+    while len(leaves) < nleaves:
+        cand = sorted(leaves)
+        leaf = cand[int(rng.integers(len(cand)))]
+        L, i, j, k = leaf
+        if L >= max_level or not neighbours_ok(leaf):
+            continue
+        leaves.remove(leaf)
+        for a in (0, 1):
+            for b in (0, 1):
+                for c in (0, 1):
+                    leaves.add((L + 1, 2 * i + a, 2 * j + b, 2 * k + c))
+    out = sorted(leaves, key=lambda t: _morton3(t[1] << (max_level - t[0]), t[2] << (max_level - t[0]),
+                                                 t[3] << (max_level - t[0])))
+    return out
+
+
+def amr_batch(nblocks: int = 1024, seed: int = 3, sizes=(16, 24, 32), fractions=(0.4, 0.4, 0.2), ng: int = 2,
+              gamma: float = 5.0 / 3.0):
+    """Blocks of uneven sizes shaped like an AMR mesh: the first nblocks leaves
+    (Morton order) of a seeded 2:1-balanced octree give each block a level and
+    a physical edge 2^-level; block sizes follow the given mix (seeded
+    shuffle) and dx = edge / n.  Each block carries its own smooth periodic
+    state: rho, p in [0.5, 2], |v| < 0.9, B = B0 + curl A."""
+    rng = np.random.default_rng(seed)
+    leaves = balanced_octree(nblocks, seed=seed)[:nblocks]
+    counts = [int(round(f * nblocks)) for f in fractions]
+    counts[-1] = nblocks - sum(counts[:-1])
+    size_list = np.concatenate([np.full(c, s) for c, s in zip(counts, sizes)])
+    rng.shuffle(size_list)
+    blocks = []
+    for b, (leaf, n) in enumerate(zip(leaves, size_list)):
+        edge = 2.0 ** (-leaf[0])
+        n = int(n)
+        blk = smooth_random(n=(n, n, n), seed=seed * 100003 + b, ng=ng, gamma=gamma, vmax=0.9,
+                            dx=(edge / n,) * 3, B0=tuple(0.3 * rng.standard_normal(3)), brms=0.2)
+        blk.meta.update(level=leaf[0], morton=leaf[1:])
+        blocks.append(blk)
+    return blocks
+
+
+def pack(arrays) -> np.ndarray:
+    """Concatenate per-block arrays into the flat batched layout."""
+    return np.concatenate([np.ascontiguousarray(a).reshape(-1) for a in arrays])

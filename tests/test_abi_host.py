@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version():
-    assert athmhd.lib().athmhd_version() == 100
+    assert athmhd.lib().athmhd_version() == 101
 
 
 def _create(**over):
@@ -84,3 +84,57 @@ def test_create_rejects_null_out():
     cfg = athmhd.make_config((8, 8, 8), 2, (0.1,) * 3, 5 / 3)
     assert athmhd.lib().athmhd_create(C.byref(cfg), 1, None) == athmhd.EINVAL
     assert athmhd.lib().athmhd_create(C.byref(cfg), 0, C.byref(C.c_void_p())) == athmhd.EINVAL
+
+
+def _create_batch(dims, dxs, **over):
+    import numpy as np
+    cfg = athmhd.make_config((8, 8, 8), 2, (0.1, 0.1, 0.1), 5 / 3)
+    for k, v in over.items():
+        setattr(cfg, k, v)
+    d = np.ascontiguousarray(np.array(dims, dtype=np.int32).reshape(-1))
+    x = np.ascontiguousarray(np.array(dxs, dtype=np.float64).reshape(-1))
+    h = C.c_void_p()
+    rc = athmhd.lib().athmhd_create_batch(C.byref(cfg), d.ctypes.data_as(C.POINTER(C.c_int32)),
+                                          x.ctypes.data_as(C.POINTER(C.c_double)), len(dims), C.byref(h))
+    return rc, athmhd.lib().athmhd_last_error(None).decode()
+
+
+@pytest.mark.parametrize("dims,dxs,over,code,needle", [
+    ([(16, 16, 16), (0, 8, 8)], [(0.1,) * 3, (0.1,) * 3], {}, athmhd.EINVAL, "block 1"),
+    ([(16, 16, 16)], [(0.1, -1.0, 0.1)], {}, athmhd.EINVAL, "widths"),
+    ([(16, 16, 16)], [(0.1,) * 3], {"kernel_path": 1}, athmhd.EUNSUP, "fused"),
+    ([(16, 16, 16)], [(0.1,) * 3], {"nghost": 1}, athmhd.EINVAL, "nghost"),
+])
+def test_create_batch_rejects_bad_blocks(dims, dxs, over, code, needle):
+    rc, msg = _create_batch(dims, dxs, **over)
+    assert rc == code
+    assert needle in msg
+
+
+def test_batch_calls_reject_non_batch_use():
+    L = athmhd.lib()
+    assert L.athmhd_batch_set_tile(None, 0, 0) == athmhd.EINVAL
+    assert L.athmhd_batch_info(None, None, None, None) == athmhd.EINVAL
+    assert L.athmhd_set_graph(None, 1) == athmhd.EINVAL
+
+
+def test_octree_is_two_to_one_balanced():
+    """The batched workload's block levels come from a periodic octree in which
+    touching leaves differ by at most one level."""
+    from paper_2005_06651_amd import inputs
+    leaves = inputs.balanced_octree(300, seed=5)
+    assert len(leaves) >= 300
+    maxl = max(l[0] for l in leaves)
+    n = 1 << maxl
+    grid = {}
+    for L, i, j, k in leaves:
+        s = 1 << (maxl - L)
+        for a in range(i * s, (i + 1) * s):
+            for b in range(j * s, (j + 1) * s):
+                for c in range(k * s, (k + 1) * s):
+                    grid[(a, b, c)] = L
+    assert len(grid) == n ** 3  # the leaves tile the cube
+    for (a, b, c), L in grid.items():
+        for d in ((1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 0, 1), (0, 1, 1), (1, 1, 1)):
+            M = grid[((a + d[0]) % n, (b + d[1]) % n, (c + d[2]) % n)]
+            assert abs(M - L) <= 1
