@@ -202,6 +202,8 @@ def main():
             and n == 256:
         traffic = STAGE_TRAFFIC["bytes_per_launch"]
     # sanity of the final state
+    solver.fill_ghosts(tc, tb)
+    torch.cuda.synchronize()
     g = block.ng
     b1 = tb[0, g:g + n, g:g + n, g:g + n + 1]
     b2 = tb[1, g:g + n, g:g + n + 1, g:g + n]

@@ -93,7 +93,10 @@ ATHMHD_API int athmhd_version(void);
 ATHMHD_API int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out);
 
 /* One full time step of nblocks (<= nblocks_max) blocks, in place:
- * (cons, bface) hold U^n on entry and U^{n+1} on return, ghosts filled.
+ * (cons, bface) hold U^n on entry and U^{n+1} on return on the active cells
+ * and faces.  Ghost entries are neither read nor written by the fused kernels
+ * (each block is its own periodic neighbour and reads its periodic images
+ * directly); call athmhd_fill_ghosts when the ghost entries are wanted.
  * dt > 0 and finite.  Asynchronous on `stream`. */
 ATHMHD_API int athmhd_step(athmhd_t h, double* cons, double* bface, double dt, int nblocks, void* stream);
 

@@ -275,8 +275,11 @@ int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const doubl
   const double* xc = cons;
   const double* xb = bface;
   hipError_t e;
+  // the fused kernels read periodic images directly; the unfused pipeline
+  // reads ghost entries, which are filled before each of its stages
+  const bool ghosts = h->cfg.kernel_path == 1 && !h->batch;
   for (int st = 0; st < sc.nstage; ++st) {
-    if ((e = fill_ghosts(h, const_cast<double*>(xc), const_cast<double*>(xb), nblocks, s)) != hipSuccess)
+    if (ghosts && (e = fill_ghosts(h, const_cast<double*>(xc), const_cast<double*>(xb), nblocks, s)) != hipSuccess)
       return hip_fail(h, e, "fill_ghosts launch");
     const bool last = st == sc.nstage - 1;
     double* oc;
@@ -305,7 +308,6 @@ int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const doubl
     if ((e = launch_copy(cons, xc, nc, s)) != hipSuccess) return hip_fail(h, e, "copy launch");
     if ((e = launch_copy(bface, xb, nf, s)) != hipSuccess) return hip_fail(h, e, "copy launch");
   }
-  if ((e = fill_ghosts(h, cons, bface, nblocks, s)) != hipSuccess) return hip_fail(h, e, "fill_ghosts launch");
   return ATHMHD_OK;
 }
 
@@ -527,14 +529,10 @@ int athmhd_batch_tune(athmhd_t h, const double* cons, const double* bface, void*
   int rc = check_call(h, cons, bface, h->nbatch);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
-  // the tuning input is a copy in register 1 with its ghosts filled, so the
-  // caller's arrays are untouched
-  hipError_t e = launch_copy(h->reg[1], cons, h->ctot, s);
-  if (e == hipSuccess) e = launch_copy(h->reg[1] + h->reg_coff, bface, h->ftot, s);
-  if (e == hipSuccess) e = fill_ghosts(h, h->reg[1], h->reg[1] + h->reg_coff, h->nbatch, s);
-  if (e != hipSuccess) return hip_fail(h, e, "tune set-up");
-  const double* xc = h->reg[1];
-  const double* xb = h->reg[1] + h->reg_coff;
+  // the stage reads the caller's arrays and writes register 0 only
+  hipError_t e = hipSuccess;
+  const double* xc = cons;
+  const double* xb = bface;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);

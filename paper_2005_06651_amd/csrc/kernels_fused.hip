@@ -97,18 +97,38 @@ struct Raw {
   double b1lo, b1hi, b2lo, b2hi, b3lo, b3hi;
 };
 
+// Periodic column of a block: wrapped indices of a column and of its upper
+// neighbours along x1 and x2.  Every block is its own periodic neighbour, so
+// the stage kernel reads the periodic images directly and never needs the
+// ghost entries of its input.
+struct Col {
+  int i0, i1, j0, j1;
+};
+
+__device__ __forceinline__ Col make_col(const Geo& g, int i, int j) {
+  Col c;
+  c.i0 = wrap_index(i, g.n1, g.ng);
+  c.i1 = wrap_index(i + 1, g.n1, g.ng);
+  c.j0 = wrap_index(j, g.n2, g.ng);
+  c.j1 = wrap_index(j + 1, g.n2, g.ng);
+  return c;
+}
+
+// Conserved state and the six bounding face fields of the cell of column c in
+// (unwrapped) plane k.
 __device__ __forceinline__ void load_raw(const Geo& g, const double* __restrict__ xc, const double* __restrict__ xb,
-                                         int i, int j, int k, Raw& r) {
-  const int q = g.c(i, j, k);
+                                         const Col& c, int k, Raw& r) {
+  const int k0 = wrap_index(k, g.n3, g.ng), k1 = wrap_index(k + 1, g.n3, g.ng);
+  const int q = g.c(c.i0, c.j0, k0);
 #pragma unroll
   for (int v = 0; v < 5; ++v) r.u[v] = xc[v * g.cvar + q];
-  const int f = g.f(i, j, k);
+  const int f = g.f(c.i0, c.j0, k0);
   r.b1lo = xb[f];
-  r.b1hi = xb[f + 1];
+  r.b1hi = xb[g.f(c.i1, c.j0, k0)];
   r.b2lo = xb[g.fvar + f];
-  r.b2hi = xb[g.fvar + f + g.F1];
+  r.b2hi = xb[g.fvar + g.f(c.i0, c.j1, k0)];
   r.b3lo = xb[2 * g.fvar + f];
-  r.b3hi = xb[2 * g.fvar + f + g.F1 * g.F2];
+  r.b3hi = xb[2 * g.fvar + g.f(c.i0, c.j0, k1)];
 }
 
 // cons -> prim: w = (rho, v1, v2, v3, P, B1cc, B2cc, B3cc)
@@ -197,18 +217,19 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
   const int tid = threadIdx.x;
   const int tx = tid % BX, ty = tid / BX;
   const int x0 = g.ng + tile_x * TX, y0 = g.ng + tile_y * TY;
-  // own column (clamped into the array; columns outside the block only feed
-  // values that are never written out)
-  const int gi_raw = x0 - 1 + tx, gj_raw = y0 - 1 + ty;
-  const int gi = min(gi_raw, g.N1 - 1), gj = min(gj_raw, g.N2 - 1);
-  const bool act = tx >= 1 && tx <= TX && ty >= 1 && ty <= TY && gi_raw < g.ng + g.n1 && gj_raw < g.ng + g.n2;
+  // own column (columns of a ragged tile past the block edge only feed values
+  // that are never written out); reads use the periodic images
+  const int gi = x0 - 1 + tx, gj = y0 - 1 + ty;
+  const Col own = make_col(g, gi, gj);
+  const bool act = tx >= 1 && tx <= TX && ty >= 1 && ty <= TY && gi < g.ng + g.n1 && gj < g.ng + g.n2;
 
   // ---- extra LDS rings (LA per side): left and right columns (BY cells per
   // depth), bottom and top rows (BX cells per depth), one cell per thread
   constexpr int NRING = 2 * LA * (BX + BY);
   static_assert(NRING <= NT, "ring cells must fit the workgroup");
   const bool ring = tid < NRING;
-  int rl = 0, rgi = 0, rgj = 0;
+  int rl = 0;
+  Col rcol{0, 0, 0, 0};
   if (ring) {
     int rlx, rly;
     if (tid < 2 * LA * BY) {
@@ -222,8 +243,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
       rly = side == 0 ? LA - 1 - d : LA + BY + d;
     }
     rl = rly * PW + rlx;
-    rgi = min(max(x0 - 1 - LA + rlx, 0), g.N1 - 1);
-    rgj = min(max(y0 - 1 - LA + rly, 0), g.N2 - 1);
+    rcol = make_col(g, x0 - 1 - LA + rlx, y0 - 1 - LA + rly);
   }
 
   const double i1 = 1.0 / g.dx1, i2 = 1.0 / g.dx2, i3 = 1.0 / g.dx3;
@@ -232,18 +252,27 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
 
   // ---- z window: planes p-LA .. p+LA of the own column
   ZCell win[NW];
+  // normal fields (lower x1, x2, x3 faces of the own cell) of planes p .. p+LA
+  double bnq[LA + 1][3];
   {
     double w[8];
     Raw raw;
 #pragma unroll
     for (int o = 0; o < NW - 1; ++o) {
-      load_raw(g, xc, xb, gi, gj, k0 - 1 - LA + o, raw);
+      load_raw(g, xc, xb, own, k0 - 1 - LA + o, raw);
       nbad += !to_prim(raw, gm1, w);
       to_zcell(w, win[o + 1]);
+      if (o >= LA) {
+        bnq[o - LA][0] = raw.b1lo;
+        bnq[o - LA][1] = raw.b2lo;
+        bnq[o - LA][2] = raw.b3lo;
+      }
     }
   }
-  Raw pre;  // raw data of the next look-ahead plane
-  load_raw(g, xc, xb, gi, gj, k0 - 1 + LA, pre);
+  Raw pre;   // raw data of the next look-ahead plane
+  load_raw(g, xc, xb, own, k0 - 1 + LA, pre);
+  Raw rpre;  // raw data of this thread's ring cell in the next plane
+  if (ring) load_raw(g, xc, xb, rcol, k0 - 1, rpre);
 
   double qz_carry[7];  // left state of the next x3-face (right edge of the cell below)
   double e2x_prev = 0.0, wx_prev = 0.5, e1y_prev = 0.0, wy_prev = 0.5, e1c_prev = 0.0, e2c_prev = 0.0;
@@ -253,17 +282,16 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
 
   for (int p = k0 - 1; p <= kend; ++p) {
     const bool zface = p >= k0;
-    // ---- 1. ring cells of plane p: issue their loads first
-    Raw rraw;
-    if (ring) load_raw(g, xc, xb, rgi, rgj, p, rraw);
-
-    // ---- 2. shift the window and convert the look-ahead plane p+LA
+    // ---- 1-2. shift the window and convert the look-ahead plane p+LA
 #pragma unroll
     for (int o = 0; o < NW - 1; ++o) win[o] = win[o + 1];
     {
       double w[8];
       nbad += !to_prim(pre, gm1, w);
       to_zcell(w, win[NW - 1]);
+      bnq[LA][0] = pre.b1lo;
+      bnq[LA][1] = pre.b2lo;
+      bnq[LA][2] = pre.b3lo;
     }
 
     // ---- 3. own cell of plane p: primitives to LDS, cell EMFs to the exchange
@@ -294,7 +322,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
     // ---- 4. ring cells to LDS
     if (ring) {
       double w[8];
-      to_prim(rraw, gm1, w);
+      to_prim(rpre, gm1, w);
 #pragma unroll
       for (int v = 0; v < 8; ++v) sp[v * PL + rl] = w[v];
     }
@@ -317,7 +345,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
       }
       double wz = 0.5, e1z = 0.0, e2z = 0.0;
       if (zface) {
-        const double bn3 = xb[2 * g.fvar + g.f(gi, gj, p)];
+        const double bn3 = bnq[0][2];
         FaceFlux fz;
         riemann<RS>(zl, zr, bn3, sa.gas, sa.ct_eps, fz, wz);
         // z-frame -> (rho, M1, M2, M3, E); x3-face E2 = -F(B1), E1 = +F(B2)
@@ -355,7 +383,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
           ql[v] = a1;
           qr[v] = b0;
         }
-        const double bn1 = xb[g.f(gi, gj, p)];
+        const double bn1 = bnq[0][0];
         FaceFlux fx;
         riemann<RS>(ql, qr, bn1, sa.gas, sa.ct_eps, fx, wx);
         sx[(X_FX + 0) * NT + tid] = fx.rho;
@@ -392,7 +420,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
           ql[v] = a1;
           qr[v] = b0;
         }
-        const double bn2 = xb[g.fvar + g.f(gi, gj, p)];
+        const double bn2 = bnq[0][1];
         FaceFlux fy;
         riemann<RS>(ql, qr, bn2, sa.gas, sa.ct_eps, fy, wy);
         sx[(X_FY + 0) * NT + tid] = fy.rho;
@@ -407,8 +435,35 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
       sx[X_E3Y * NT + tid] = e3y;
       sx[X_WY * NT + tid] = wy;
     }
-    // prefetch the look-ahead plane of the next iteration
-    if (p + 1 <= kend) load_raw(g, xc, xb, gi, gj, p + 1 + LA, pre);
+    // prefetch the look-ahead plane and the ring cell of the next iteration,
+    // and the pointwise terms of this iteration's output (U^n, and the stage
+    // input where g0 != 0)
+    if (p + 1 <= kend) {
+      load_raw(g, xc, xb, own, p + 1 + LA, pre);
+      if (ring) load_raw(g, xc, xb, rcol, p + 1, rpre);
+    }
+    const bool out_cell = act && zface && p - 1 >= k0;
+    const bool out_b3 = act && zface && p < kend;
+    double pw[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // g1 U^n + g0 X of cell p-1 (5), B1, B2 at p-1, B3 at p
+    {
+      const int q = g.c(gi, gj, p - 1), f = g.f(gi, gj, p - 1), f3 = g.f(gi, gj, p);
+      if (out_cell) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) pw[v] = sa.cf.g1 * unc[v * g.cvar + q];
+        pw[5] = sa.cf.g1 * unb[f];
+        pw[6] = sa.cf.g1 * unb[g.fvar + f];
+        if (sa.cf.g0 != 0.0) {
+#pragma unroll
+          for (int v = 0; v < 5; ++v) pw[v] += sa.cf.g0 * xc[v * g.cvar + q];
+          pw[5] += sa.cf.g0 * xb[f];
+          pw[6] += sa.cf.g0 * xb[g.fvar + f];
+        }
+      }
+      if (out_b3) {
+        pw[7] = sa.cf.g1 * unb[2 * g.fvar + f3];
+        if (sa.cf.g0 != 0.0) pw[7] += sa.cf.g0 * xb[2 * g.fvar + f3];
+      }
+    }
     __syncthreads();
 
     // ---- 7. corner EMFs of the own edges and the conserved update
@@ -445,14 +500,10 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
         acc[v] = -(dfx * i1 + dfy * i2) + fz_cons[v] * i3;
         acc_prev[v] -= fz_cons[v] * i3;
       }
-      if (p - 1 >= k0) {
+      if (out_cell) {
         const int q = g.c(gi, gj, p - 1);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          double y = sa.cf.g1 * unc[v * g.cvar + q] + bdt * acc_prev[v];
-          if (sa.cf.g0 != 0.0) y += sa.cf.g0 * xc[v * g.cvar + q];
-          oc[v * g.cvar + q] = y;
-        }
+        for (int v = 0; v < 5; ++v) oc[v * g.cvar + q] = pw[v] + bdt * acc_prev[v];
       }
     }
     __syncthreads();
@@ -468,28 +519,23 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
       acc_prev[6] -= e1 * i3;
       // B3(i, j, p-1/2): -(E2(i+1/2) - E2(i-1/2))/dx1 + (E1(j+1/2) - E1(j-1/2))/dx2
       const double db3 = -(sc[1 * NT + tE] - e2) * i1 + (sc[0 * NT + tN] - e1) * i2;
-      if (p < kend) {
-        const int f = g.f(gi, gj, p);
-        double y = sa.cf.g1 * unb[2 * g.fvar + f] + bdt * db3;
-        if (sa.cf.g0 != 0.0) y += sa.cf.g0 * xb[2 * g.fvar + f];
-        ob[2 * g.fvar + f] = y;
-      }
-      if (p - 1 >= k0) {
+      if (out_b3) ob[2 * g.fvar + g.f(gi, gj, p)] = pw[7] + bdt * db3;
+      if (out_cell) {
         const int f = g.f(gi, gj, p - 1);
-        double y1 = sa.cf.g1 * unb[f] + bdt * acc_prev[5];
-        double y2 = sa.cf.g1 * unb[g.fvar + f] + bdt * acc_prev[6];
-        if (sa.cf.g0 != 0.0) {
-          y1 += sa.cf.g0 * xb[f];
-          y2 += sa.cf.g0 * xb[g.fvar + f];
-        }
-        ob[f] = y1;
-        ob[g.fvar + f] = y2;
+        ob[f] = pw[5] + bdt * acc_prev[5];
+        ob[g.fvar + f] = pw[6] + bdt * acc_prev[6];
       }
 #pragma unroll
       for (int v = 0; v < 7; ++v) acc_prev[v] = acc[v];
     }
 
     // ---- 9. carry this plane's face EMFs / weights / cell EMFs upward
+#pragma unroll
+    for (int o = 0; o < LA; ++o) {
+      bnq[o][0] = bnq[o + 1][0];
+      bnq[o][1] = bnq[o + 1][1];
+      bnq[o][2] = bnq[o + 1][2];
+    }
     e2x_prev = e2x;
     wx_prev = wx;
     e1y_prev = e1y;

@@ -77,6 +77,7 @@ def test_batch_matches_oracle_per_block(torch_dev, athmhd, orc, shape, split, in
         for c, x, y in zip(cfgs, rc, rb):
             assert orc.step(c, x, y, dt) == 0
         s.step(tc, tb, dt)
+    s.fill_ghosts(tc, tb)  # the step leaves ghosts and periodic image faces as they were
     gc = s.views(tc.cpu().numpy(), "cons")
     gb = s.views(tb.cpu().numpy(), "bface")
     for b, blk in enumerate(blocks):
