@@ -52,8 +52,16 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle timing")
     p.add_argument("--cpu-steps", type=int, default=1, help="oracle steps in the CPU baseline sample")
     p.add_argument("--kernel-path", default="fused", choices=["fused", "unfused"])
-    p.add_argument("--workload", default="turbulence", choices=["turbulence", "batch"],
-                   help="turbulence: the 256^3 block (default); batch: 1024 uneven AMR-shaped blocks")
+    p.add_argument("--workload", default="turbulence", choices=["turbulence", "batch", "adjoint"],
+                   help="turbulence: the 256^3 block (default); batch: 1024 uneven AMR-shaped blocks; "
+                        "adjoint: gradient of a 128^3 x 64-step rollout (cost ratio and finite differences)")
+    p.add_argument("--adj-n", type=int, default=128, help="adjoint: cells per side")
+    p.add_argument("--adj-steps", type=int, default=64, help="adjoint: rollout steps")
+    p.add_argument("--adj-dirs", type=int, default=16, help="adjoint: finite-difference directions")
+    p.add_argument("--adj-eps", type=float, default=1e-3, help="adjoint: continuous CT weight eps")
+    p.add_argument("--adj-no-fd", action="store_true", help="adjoint: skip the finite-difference check")
+    p.add_argument("--adj-dir-kind", default="smooth", choices=["smooth", "white"],
+                   help="adjoint: finite-difference directions: band-limited fields or white noise")
     p.add_argument("--no-tune", action="store_true", help="batch: keep the default tile instead of autotuning")
     p.add_argument("--graph", action="store_true", help="replay each step from a hipGraph")
     p.add_argument("--copy-calibration", action="store_true",
@@ -143,6 +151,104 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_adjoint(args):
+    """Gradient of L = sum over active cells of (rho_N - rho_target)^2 dV after
+    N steps (VL2+PLM+HLLD, continuous CT weight eps (default 1e-3), dt frozen at its
+    value for the initial state) with respect to the initial velocity, through
+    prim -> cons, the checkpointed rollout (sqrt(N) checkpoints) and the
+    library's reverse mode.  Reports the forward time, the forward + backward
+    time and their ratio, and checks the gradient against central differences
+    of the loss along seeded unit directions (h swept 1e-2 .. 1e-6)."""
+    import numpy as np
+    import torch
+
+    from paper_2005_06651_amd import athmhd, inputs
+    from paper_2005_06651_amd.rollout import Prim2Cons, Rollout
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n, nsteps = args.adj_n, args.adj_steps
+    ncheck = max(1, int(math.isqrt(nsteps)))
+    blk = inputs.turbulence(n=n, seed=args.seed, mach=0.3)
+    s = athmhd.Solver(blk.n, blk.ng, blk.dx, blk.gamma, recon="plm", riemann="hlld", integrator="vl2", cfl=0.3,
+                      ct_eps=args.adj_eps)
+    g = blk.ng
+    prim0 = torch.from_numpy(blk.prim).to(dev)
+    bf0 = torch.from_numpy(blk.bface).to(dev)
+    dt = s.newdt(s.prim2cons(prim0, bf0), bf0)
+    rng = np.random.default_rng(args.seed + 1000)
+    # smooth target density 1 + 0.05 f with f from the same band-limited generator
+    tgt = inputs.smooth_random(n=(n, n, n), seed=args.seed + 2000, ng=g, kmax=4.0, rho_range=(0.95, 1.05))
+    target = torch.from_numpy(np.ascontiguousarray(tgt.prim[0, g:g + n, g:g + n, g:g + n])).to(dev)
+    dV = blk.dx[0] * blk.dx[1] * blk.dx[2]
+
+    def loss_of(prim):
+        c0 = Prim2Cons.apply(prim, bf0, s)
+        cN, _ = Rollout.apply(c0, bf0, s, dt, nsteps, ncheck)
+        return ((cN[0, g:g + n, g:g + n, g:g + n] - target) ** 2).sum() * dV
+
+    # warm-up (also allocates the reverse-mode scratch)
+    p = prim0.clone().requires_grad_(True)
+    loss_of(p).backward()
+    torch.cuda.synchronize()
+    # forward only
+    t0 = time.perf_counter()
+    with torch.no_grad():
+        lval = loss_of(prim0).item()
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    # forward + backward
+    p = prim0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = loss_of(p)
+    loss.backward()
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
+    grad_v = p.grad[1:4, g:g + n, g:g + n, g:g + n].double().cpu().numpy()
+    errs = []
+    plateau = []
+    hs = (1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7)
+    ads = []
+    for q in range(0 if args.adj_no_fd else args.adj_dirs):
+        if args.adj_dir_kind == "smooth":
+            # band-limited random velocity field (|k| <= 4), unit norm
+            d = inputs.smooth_random(n=(n, n, n), seed=args.seed + 3000 + q, ng=g, kmax=4.0).prim[
+                1:4, g:g + n, g:g + n, g:g + n].copy()
+        else:
+            d = rng.standard_normal((3, n, n, n))
+        d /= np.linalg.norm(d)
+        ad = float(np.sum(grad_v * d))
+        ads.append(ad)
+        row = []
+        for h in hs:
+            dp = torch.zeros_like(prim0)
+            dp[1:4, g:g + n, g:g + n, g:g + n] = torch.from_numpy(h * d).to(dev)
+            with torch.no_grad():
+                fd = (loss_of(prim0 + dp).item() - loss_of(prim0 - dp).item()) / (2 * h)
+            row.append(abs(fd - ad) / max(abs(ad), 1e-300))
+        plateau.append(row)
+        errs.append(min(row))
+    out = {
+        "metric": "adjoint cost: (forward + backward) / forward time of a checkpointed 64-step rollout "
+                  "gradient, FP64 VL2+PLM+HLLD+CT, 1 MI355X",
+        "value": t_all / t_fwd, "unit": "ratio", "n_gpus": 1, "steps": nsteps, "warmup": 1,
+        "ms_per_step": t_fwd / nsteps * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{n}^3 periodic MHD turbulence at rms Mach 0.3 (B = 0.5 x + curl A, rms 0.1), "
+                               f"{nsteps} steps of frozen dt, CT weight eps {args.adj_eps:g}, {ncheck} checkpoints; loss = "
+                               "sum (rho_N - rho_target)^2 dV, gradient w.r.t. the initial velocity",
+                   "cells": n ** 3, "dt": dt, "checkpoints": ncheck},
+        "forward_s": t_fwd, "forward_backward_s": t_all, "loss": lval,
+        "fd_check": None if not errs else {
+            "directions": len(errs), "h": list(hs), "max_rel_err": max(errs),
+            "median_rel_err": float(np.median(errs)),
+            "rel_err_by_h_max_over_dirs": [max(r[k] for r in plateau) for k in range(len(hs))],
+            "direction_kind": args.adj_dir_kind, "abs_directional_derivative_median": float(np.median(np.abs(ads)))},
+    }
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -157,6 +263,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.workload == "adjoint":
+        bench_adjoint(args)
         return
     if args.copy_calibration:
         a = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB

@@ -116,6 +116,41 @@ ATHMHD_API int athmhd_prim2cons(athmhd_t h, const double* prim, const double* bf
 /* Fill the ghost cells and periodic image faces of (cons, bface). */
 ATHMHD_API int athmhd_fill_ghosts(athmhd_t h, double* cons, double* bface, int nblocks, void* stream);
 
+/* Reverse mode of one step (vector-Jacobian product).  The step is the map
+ * S: (U^n, B^n) -> (U^{n+1}, B^{n+1}) that athmhd_step computes with this
+ * handle's configuration and the given dt, on each of nblocks periodic
+ * blocks (Sec. 3.2: reconstruction, Riemann fluxes, upwind CT and the 2S
+ * stages of Eq. (rk-2s)).  Given the state (cons_n, bface_n) at the start of
+ * the step and cotangents (g_cons_np1, g_bface_np1) of the step's output,
+ * writes (g_cons_n, g_bface_n) = J_S^T (g_cons_np1, g_bface_np1), the
+ * gradient of <g_np1, S(x)> with respect to x = (cons_n, bface_n).
+ *   - Layouts as cons / bface.  The independent entries are the active cells
+ *     and, per component, the lower face of each active cell.  Every other
+ *     entry (ghost cells, the periodic-image faces n_d + nghost, padding) is
+ *     left unchanged by a step, so its cotangent passes through: g_n equals
+ *     g_np1 there.
+ *   - g_cons_n / g_bface_n may alias g_cons_np1 / g_bface_np1; they must not
+ *     alias cons_n / bface_n.
+ *   - The stage states are recomputed from (cons_n, bface_n); the library
+ *     allocates its reverse-mode scratch on the first call (about 100 doubles
+ *     per active cell and block, plus one state per stage beyond the first).
+ *   - Supported: DC and PLM reconstruction, HLLE and HLLD, all integrators.
+ *     The derivative of the CT weight is taken for ct_eps > 0; with ct_eps = 0
+ *     the weight is piecewise constant and contributes nothing.  PPM and
+ *     batched handles return ATHMHD_EUNSUP.
+ * Asynchronous on `stream`. */
+ATHMHD_API int athmhd_step_vjp(athmhd_t h, const double* cons_n, const double* bface_n, double dt,
+                               const double* g_cons_np1, const double* g_bface_np1, double* g_cons_n,
+                               double* g_bface_n, int nblocks, void* stream);
+
+/* Reverse mode of athmhd_prim2cons on every stored cell: with U = prim2cons(W, B),
+ * writes g_prim = (dU/dW)^T g_cons and adds (dU/dB)^T g_cons to g_bface (the
+ * energy depends on the cell-centred field, the mean of the two bounding
+ * faces, Sec. 3.1).  g_prim must not alias g_cons or prim.  Uniform handles
+ * only (batched: ATHMHD_EUNSUP).  Asynchronous on `stream`. */
+ATHMHD_API int athmhd_prim2cons_vjp(athmhd_t h, const double* prim, const double* bface, const double* g_cons,
+                                    double* g_prim, double* g_bface, int nblocks, void* stream);
+
 /* Batched MeshBlocks of uneven sizes (Sec. 2.1: a Mesh of MeshBlocks, each
  * with its own cell count here, advanced with one global dt, Sec. 2.1.6).
  * `base` gives everything but the block shape (its n1..n3 and dx1..dx3 are

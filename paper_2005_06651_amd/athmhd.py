@@ -19,7 +19,8 @@ RIEMANN = {"hlle": 0, "hlld": 1}
 INTEGRATOR = {"rk1": 0, "vl2": 1, "rk2": 2, "rk3": 3}
 EXPORTED = ["athmhd_version", "athmhd_create", "athmhd_create_batch", "athmhd_batch_info",
             "athmhd_batch_set_tile", "athmhd_batch_tune", "athmhd_set_graph", "athmhd_step", "athmhd_newdt",
-            "athmhd_prim2cons", "athmhd_fill_ghosts", "athmhd_profile", "athmhd_last_error", "athmhd_destroy"]
+            "athmhd_prim2cons", "athmhd_fill_ghosts", "athmhd_profile", "athmhd_last_error", "athmhd_destroy",
+            "athmhd_step_vjp", "athmhd_prim2cons_vjp"]
 BATCH_TILES = [(16, 8), (8, 16), (14, 14), (8, 8)]  # active columns of the batch tile candidates
 
 
@@ -65,6 +66,8 @@ def lib():
         L.athmhd_newdt.argtypes = [vp, vp, vp, C.c_int, C.POINTER(C.c_double), vp]
         L.athmhd_prim2cons.argtypes = [vp, vp, vp, vp, C.c_int, vp]
         L.athmhd_fill_ghosts.argtypes = [vp, vp, vp, C.c_int, vp]
+        L.athmhd_step_vjp.argtypes = [vp, vp, vp, C.c_double, vp, vp, vp, vp, C.c_int, vp]
+        L.athmhd_prim2cons_vjp.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int, vp]
         L.athmhd_profile.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]
         L.athmhd_last_error.argtypes = [vp]
         L.athmhd_last_error.restype = C.c_char_p
@@ -170,6 +173,36 @@ class Solver:
     def fill_ghosts(self, cons, bface, stream=None) -> None:
         pc, pb, nb = self._pair(cons, bface)
         _check(lib().athmhd_fill_ghosts(self._h, pc, pb, nb, _stream(stream)), self._h)
+
+    def step_vjp(self, cons, bface, dt: float, g_cons, g_bface, out_cons=None, out_bface=None, stream=None):
+        """Cotangents of (cons, bface) at the start of a step of size dt, given
+        the cotangents (g_cons, g_bface) of its result; out_* may be g_* (in
+        place).  Returns (out_cons, out_bface)."""
+        import torch
+        pc, pb, nb = self._pair(cons, bface)
+        gc, gb, nb2 = self._pair(g_cons, g_bface)
+        if out_cons is None:
+            out_cons = torch.empty_like(g_cons)
+        if out_bface is None:
+            out_bface = torch.empty_like(g_bface)
+        oc, ob, nb3 = self._pair(out_cons, out_bface)
+        if not nb == nb2 == nb3:
+            raise ValueError("state and cotangents hold different block counts")
+        _check(lib().athmhd_step_vjp(self._h, pc, pb, float(dt), gc, gb, oc, ob, nb, _stream(stream)), self._h)
+        return out_cons, out_bface
+
+    def prim2cons_vjp(self, prim, bface, g_cons, g_bface, out_prim=None, stream=None):
+        """Cotangent of prim for cons = prim2cons(prim, bface); the face-field
+        part is added to g_bface in place.  Returns out_prim."""
+        import torch
+        pp, pb, nb = self._pair(prim, bface)
+        gc, _ = self._arr(g_cons, 5, self.cell_shape)
+        gbp, _ = self._arr(g_bface, 3, self.face_shape)
+        if out_prim is None:
+            out_prim = torch.empty_like(prim)
+        op, _ = self._arr(out_prim, 5, self.cell_shape)
+        _check(lib().athmhd_prim2cons_vjp(self._h, pp, pb, gc, op, gbp, nb, _stream(stream)), self._h)
+        return out_prim
 
     def set_graph(self, enable: bool) -> None:
         """Record the step once into a hipGraph and replay it (needs a

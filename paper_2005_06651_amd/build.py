@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libathmhd.so")
-SOURCES = ["abi.hip", "kernels_basic.hip", "kernels_unfused.hip", "kernels_fused.hip"]
+SOURCES = ["abi.hip", "kernels_basic.hip", "kernels_unfused.hip", "kernels_fused.hip", "kernels_adjoint.hip"]
+OBJDIR = os.path.join(ROOT, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -28,14 +29,33 @@ def sources():
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every HIP source into paper_2005_06651_amd/libathmhd.so."""
+    """Compile every HIP source (in parallel, one object each) and link
+    paper_2005_06651_amd/libathmhd.so."""
+    os.makedirs(OBJDIR, exist_ok=True)
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    procs = []
+    objs = []
+    for src in sources():
+        obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+        cmd = [HIPCC] + compile_flags + ["-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+        objs.append(obj)
+    errors = []
+    for src, p in procs:
+        _, err = p.communicate()
+        if p.returncode != 0:
+            errors.append(f"{src}:\n{err[-6000:]}")
+    if errors:
+        raise RuntimeError("hipcc failed:\n" + "\n".join(errors))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-o", tmp] + sources()
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     proc = subprocess.run(cmd, capture_output=True, text=True)
     if proc.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + proc.stderr[-8000:])
+        raise RuntimeError("hipcc link failed:\n" + proc.stderr[-8000:])
     os.replace(tmp, LIB)
     return LIB
 

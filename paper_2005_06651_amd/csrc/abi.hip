@@ -57,6 +57,11 @@ struct athmhd_s {
   hipGraphNode_t dt_node = nullptr;
   const void* gkey[3] = {nullptr, nullptr, nullptr};
   int gkey_nb = 0;
+  // reverse mode (allocated by the first athmhd_step_vjp)
+  double* adj_base = nullptr;
+  double* adj_state[2] = {nullptr, nullptr};  // recomputed stage inputs X_1, X_2
+  double* adj_scr = nullptr;                  // per-block scratch of the stage VJP
+  double* adj_cot[3] = {nullptr, nullptr, nullptr};  // cotangent sets A, A', Z
   std::string err;
 };
 
@@ -195,6 +200,7 @@ void free_all(athmhd_t h) {
   if (h->d_items) (void)hipFree(h->d_items);
   if (h->d_queue) (void)hipFree(h->d_queue);
   if (h->h_pinned) (void)hipHostFree(h->h_pinned);
+  if (h->adj_base) (void)hipFree(h->adj_base);
 }
 
 // Small device buffers every handle has.
@@ -363,11 +369,40 @@ int replay_step(athmhd_t h, double dt, hipStream_t s) {
   return ATHMHD_OK;
 }
 
+// Reverse-mode buffers of a uniform handle: stage states beyond the first,
+// the stage-VJP scratch and three cotangent sets, for nbmax blocks.
+int alloc_adjoint(athmhd_t h) {
+  if (h->adj_base) return ATHMHD_OK;
+  const Geo& g = h->g;
+  const int64_t state = g.cblock + g.fblock;
+  const int64_t nc = (int64_t)g.n1 * g.n2 * g.n3;
+  const int nst = scheme_of(h->cfg.integrator).nstage;
+  const int64_t nb = h->nbmax;
+  const int64_t total = ((nst - 1) * state + adj_scratch_per_block(g) + 3 * 8 * nc) * nb;
+  if (hipMalloc(&h->adj_base, total * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    h->adj_base = nullptr;
+    return fail(h, ATHMHD_ENOMEM, "reverse-mode scratch of %.3f GB", total * 8.0 / 1e9);
+  }
+  double* p = h->adj_base;
+  for (int st = 0; st < nst - 1; ++st) {
+    h->adj_state[st] = p;
+    p += state * nb;
+  }
+  h->adj_scr = p;
+  p += adj_scratch_per_block(g) * nb;
+  for (int q = 0; q < 3; ++q) {
+    h->adj_cot[q] = p;
+    p += 8 * nc * nb;
+  }
+  return ATHMHD_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-int athmhd_version(void) { return 101; }
+int athmhd_version(void) { return 102; }
 
 int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
   if (!out) return fail(nullptr, ATHMHD_EINVAL, "out is NULL");
@@ -624,6 +659,76 @@ int athmhd_step(athmhd_t h, double* cons, double* bface, double dt, int nblocks,
     if (rc != ATHMHD_OK) return rc;
   }
   return replay_step(h, dt, s);
+}
+
+int athmhd_step_vjp(athmhd_t h, const double* cons_n, const double* bface_n, double dt, const double* g_cons_np1,
+                    const double* g_bface_np1, double* g_cons_n, double* g_bface_n, int nblocks, void* stream) {
+  int rc = check_call(h, cons_n, bface_n, nblocks);
+  if (rc) return rc;
+  if (h->batch) return fail(h, ATHMHD_EUNSUP, "reverse mode is available for uniform handles only");
+  if (!g_cons_np1 || !g_bface_np1 || !g_cons_n || !g_bface_n) return fail(h, ATHMHD_EINVAL, "NULL cotangent array");
+  if (g_cons_n == cons_n || g_bface_n == bface_n || g_cons_n == (const double*)bface_n ||
+      g_bface_n == (const double*)cons_n)
+    return fail(h, ATHMHD_EINVAL, "cotangent outputs must not alias the state");
+  if (!(std::isfinite(dt) && dt > 0.0)) return fail(h, ATHMHD_EINVAL, "dt must be finite and > 0 (got %g)", dt);
+  const Scheme sc = scheme_of(h->cfg.integrator);
+  for (int st = 0; st < sc.nstage; ++st) {
+    const int recon = (h->cfg.integrator == ATHMHD_VL2 && st == 0) ? ATHMHD_RECON_DC : h->cfg.recon;
+    if (recon == ATHMHD_RECON_PPM) return fail(h, ATHMHD_EUNSUP, "reverse mode supports DC and PLM only");
+  }
+  if ((rc = alloc_adjoint(h)) != ATHMHD_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const Geo& g = h->g;
+  const int64_t nset = 8 * (int64_t)g.n1 * g.n2 * g.n3 * nblocks;
+  hipError_t e = hipSuccess;
+  // forward: stage inputs X_0 = (cons_n, bface_n), X_1, ..., X_{S-1}
+  const double* xc[3] = {cons_n, nullptr, nullptr};
+  const double* xb[3] = {bface_n, nullptr, nullptr};
+  for (int st = 0; st + 1 < sc.nstage; ++st) {
+    double* oc = h->adj_state[st];
+    double* ob = oc + g.cblock * (int64_t)nblocks;
+    const int recon = (h->cfg.integrator == ATHMHD_VL2 && st == 0) ? ATHMHD_RECON_DC : h->cfg.recon;
+    const StageCoef cf{sc.g0[st], sc.g1[st], sc.beta[st] * dt};
+    e = launch_stage_fused(g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc[st], xb[st], cons_n, bface_n,
+                           oc, ob, cf, nullptr, sc.beta[st], nblocks, h->kz, h->occ, h->d_bad, s);
+    if (e != hipSuccess) return hip_fail(h, e, "vjp forward stage launch");
+    xc[st + 1] = oc;
+    xb[st + 1] = ob;
+  }
+  // reverse: with A the cotangent of X_{s+1},
+  //   cotangent of X_s  = g0_s A + beta_s dt J_L(X_s)^T A,   and X_0 also
+  //   collects g1_s A from every stage (its U^n term).
+  double* A = h->adj_cot[0];
+  double* An = h->adj_cot[1];
+  double* Z = h->adj_cot[2];
+  if ((e = launch_adj_gather(g, g_cons_np1, g_bface_np1, A, nblocks, s)) != hipSuccess ||
+      (e = launch_adj_fill(Z, 0.0, nset, s)) != hipSuccess)
+    return hip_fail(h, e, "vjp set-up launch");
+  for (int st = sc.nstage - 1; st >= 0; --st) {
+    const int recon = (h->cfg.integrator == ATHMHD_VL2 && st == 0) ? ATHMHD_RECON_DC : h->cfg.recon;
+    if (sc.g1[st] != 0.0 && (e = launch_adj_axpby(Z, 1.0, Z, sc.g1[st], A, nset, s)) != hipSuccess)
+      return hip_fail(h, e, "vjp axpby launch");
+    e = sc.g0[st] != 0.0 ? launch_adj_axpby(An, sc.g0[st], A, 0.0, A, nset, s) : launch_adj_fill(An, 0.0, nset, s);
+    if (e != hipSuccess) return hip_fail(h, e, "vjp axpby launch");
+    e = launch_stage_vjp(g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc[st], xb[st], A, An,
+                         sc.beta[st] * dt, h->adj_scr, nblocks, s);
+    if (e != hipSuccess) return hip_fail(h, e, "stage vjp launch");
+    std::swap(A, An);
+  }
+  e = launch_adj_scatter(g, A, Z, g_cons_np1, g_bface_np1, g_cons_n, g_bface_n, nblocks, s);
+  return e == hipSuccess ? ATHMHD_OK : hip_fail(h, e, "vjp scatter launch");
+}
+
+int athmhd_prim2cons_vjp(athmhd_t h, const double* prim, const double* bface, const double* g_cons, double* g_prim,
+                         double* g_bface, int nblocks, void* stream) {
+  int rc = check_call(h, prim, bface, nblocks);
+  if (rc) return rc;
+  if (h->batch) return fail(h, ATHMHD_EUNSUP, "reverse mode is available for uniform handles only");
+  if (!g_cons || !g_prim || !g_bface) return fail(h, ATHMHD_EINVAL, "NULL cotangent array");
+  if (g_prim == g_cons || g_prim == prim) return fail(h, ATHMHD_EINVAL, "g_prim must not alias g_cons or prim");
+  hipError_t e = launch_prim2cons_vjp(h->g, h->cfg.gamma, prim, bface, g_cons, g_prim, g_bface, nblocks,
+                                      (hipStream_t)stream);
+  return e == hipSuccess ? ATHMHD_OK : hip_fail(h, e, "prim2cons vjp launch");
 }
 
 int athmhd_newdt(athmhd_t h, const double* cons, const double* bface, int nblocks, double* dt_host, void* stream) {

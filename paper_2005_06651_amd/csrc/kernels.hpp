@@ -75,4 +75,30 @@ hipError_t launch_newdt_batch(const BatchDesc* desc, int nblocks, int64_t max_ac
 
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
 
+// ---- reverse mode (periodic uniform blocks) ---------------------------------
+// Cotangent sets are 8 active-only arrays per block (5 conserved variables,
+// then the lower face of each active cell for B1, B2, B3), x1 fastest, block
+// stride 8 * n1 * n2 * n3 doubles.
+// Scratch doubles per block needed by launch_stage_vjp.
+int64_t adj_scratch_per_block(const Geo& g);
+// O += scale * J_L(X)^T V for the spatial operator L of one stage (recon DC or
+// PLM, HLLE or HLLD, CT weight eps), X in the padded layout.  V and O must not
+// alias.
+hipError_t launch_stage_vjp(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
+                            const double* xb, const double* V, double* O, double scale, double* scr, int nb,
+                            hipStream_t s);
+hipError_t launch_adj_fill(double* p, double v, int64_t n, hipStream_t s);
+// out = xc * x + yc * y (elementwise; out may alias x or y)
+hipError_t launch_adj_axpby(double* out, double xc, const double* x, double yc, const double* y, int64_t n,
+                            hipStream_t s);
+// reverse of prim -> cons on every stored cell: gprim <- J^T gcons,
+// gbface += (dcons/dbface)^T gcons
+hipError_t launch_prim2cons_vjp(const Geo& g, double gamma, const double* prim, const double* bface,
+                                const double* gcons, double* gprim, double* gbface, int nb, hipStream_t s);
+// active entries of padded (cons, bface) arrays -> cotangent set
+hipError_t launch_adj_gather(const Geo& g, const double* gc, const double* gb, double* V, int nb, hipStream_t s);
+// padded outputs: active entries X + Y, all other entries copied from the inputs
+hipError_t launch_adj_scatter(const Geo& g, const double* X, const double* Y, const double* gc_in,
+                              const double* gb_in, double* gc_out, double* gb_out, int nb, hipStream_t s);
+
 }  // namespace athmhd

@@ -615,3 +615,36 @@ def test_linear_wave_convergence_vl2_plm(orc):
     e32 = _wave_error(orc, 32, integrator="vl2", recon="plm")
     e64 = _wave_error(orc, 64, integrator="vl2", recon="plm")
     assert math.log2(e32 / e64) > 1.9
+
+
+# ---------------------------------------------------------------------------
+# Forward-mode derivative of the step (dual numbers through the same oracle
+# code): it must be the derivative of the plain step, i.e. agree with central
+# differences of orc.step.  The adjoint's parity tests rest on this.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("integ,recon,rs,eps", [("vl2", "plm", "hlld", 1e-3), ("rk3", "plm", "hlle", 1e-2),
+                                                ("rk1", "dc", "hlld", 0.0), ("rk2", "dc", "hlle", 1e-3)])
+def test_step_jvp_is_derivative_of_step(orc, integ, recon, rs, eps):
+    blk = inputs.smooth_random(n=(8, 6, 5), seed=41, ng=2)
+    cfg = orc.cfg_for(blk, integrator=integ, recon=recon, riemann=rs, ct_eps=eps)
+    cons = orc.prim2cons(cfg, blk.prim, blk.bface)
+    dt = orc.newdt(cfg, cons, blk.bface)[0]
+    g = blk.ng
+    n1, n2, n3 = blk.n
+    act = (slice(None), slice(g, g + n3), slice(g, g + n2), slice(g, g + n1))
+    rng = np.random.default_rng(3)
+    dc = np.zeros_like(cons)
+    db = np.zeros_like(blk.bface)
+    dc[act] = rng.standard_normal(dc[act].shape) * np.abs(cons[act]).mean(axis=(1, 2, 3), keepdims=True)
+    db[act] = rng.standard_normal(db[act].shape) * 0.1
+    jc, jb = dc.copy(), db.copy()
+    assert orc.step_jvp(cfg, cons.copy(), blk.bface.copy(), jc, jb, dt) == 0
+    h = 1e-6
+    cp, bp = cons + h * dc, blk.bface + h * db
+    cm, bm = cons - h * dc, blk.bface - h * db
+    orc.step(cfg, cp, bp, dt)
+    orc.step(cfg, cm, bm, dt)
+    fc = (cp - cm) / (2 * h)
+    fb = (bp - bm) / (2 * h)
+    for got, ref in ((jc[act], fc[act]), (jb[act], fb[act])):
+        assert np.max(np.abs(got - ref)) <= 1e-6 * np.max(np.abs(ref))
