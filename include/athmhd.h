@@ -180,6 +180,27 @@ ATHMHD_API int athmhd_batch_set_tile(athmhd_t h, int shape, int split);
 ATHMHD_API int athmhd_batch_tune(athmhd_t h, const double* cons, const double* bface, void* stream, int* best_shape,
                                  int* best_split, double* best_ms);
 
+/* Optional density and pressure floors (both 0, the default, disables them).
+ * With dfloor or pfloor > 0:
+ *   - after every stage, a cell whose density is below dfloor gets
+ *     rho = dfloor, and a cell whose pressure (from U and the cell-centred
+ *     field) is below pfloor gets its total energy raised so that P = pfloor;
+ *     kinetic and magnetic energy are unchanged.  Mass and energy are then
+ *     conserved up to what the floors add;
+ *   - every conversion to primitives and every reconstructed face state uses
+ *     rho_W = max(rho, dfloor), v = M / rho_W, P_W = max(P, pfloor).
+ * Non-physical cells then no longer stop a run (only non-finite values are
+ * reported by athmhd_newdt); every activation is counted instead.  The paper
+ * names floors only for prolongation (Sec. 2.1.4); they are needed here by
+ * strong blasts in low-beta gas, whose pressure otherwise falls below zero.
+ * dfloor and pfloor must be finite and >= 0.  Reverse mode is unavailable with
+ * floors. */
+ATHMHD_API int athmhd_set_floors(athmhd_t h, double dfloor, double pfloor);
+
+/* Number of floor activations (cells and face states) since the previous
+ * call, which clears the counter.  Synchronises `stream`. */
+ATHMHD_API int athmhd_floor_count(athmhd_t h, long long* count, void* stream);
+
 /* enable = 1: athmhd_step records its launches once into a hipGraph (for the
  * given arrays, block count and stream, which must not be the default stream)
  * and replays the graph afterwards, updating only dt; any change of those

@@ -129,7 +129,12 @@ struct Cfg {
   int32_t recon, riemann, integrator, pad_;
   double cfl;                   // Courant number C0 used by newdt
   double ct_eps;                // 0: sign switch for the CT upwinding; >0: ramp width
+  double dfloor, pfloor;        // optional density / pressure floors (0: off)
 };
+
+// Number of primitive evaluations (cells and reconstructed face states) that a
+// floor changed since the counter was last read.
+static long long g_floored = 0;
 
 // Array geometry.  Cell arrays are [v][k][j][i] with N_d = n_d + 2 ng,
 // i fastest.  Face arrays are [c][k][j][i] padded to (N3+1)(N2+1)(N1+1);
@@ -183,11 +188,16 @@ template <class T> void fill_ghosts(const Geo& g, T* cons, T* bf) {
 // ---------------------------------------------------------------------------
 // Conserved <-> primitive (Eq. (total_energy) with the ideal-gas law of
 // Sec. 3.1).  The cell-centred field is the mean of the two face values that
-// bound the cell along each direction.  No floors: non-physical cells are
-// counted and reported.
+// bound the cell along each direction.  Without floors, non-physical cells are
+// counted and reported.  With floors (dfloor, pfloor > 0) the primitives -- and
+// only they, never the conserved variables -- are limited from below:
+// rho_W = max(rho, dfloor), v = M / rho_W, P = max(P(U, rho_W), pfloor); every
+// change is counted; a non-finite input still counts as non-physical.
 // ---------------------------------------------------------------------------
 template <class T>
-int cons_to_prim(const Geo& g, double gamma, const T* cons, const T* bf, T* w, T* bcc) {
+int cons_to_prim(const Geo& g, double gamma, const T* cons, const T* bf, T* w, T* bcc, double dfloor = 0.0,
+                 double pfloor = 0.0) {
+  const bool floors = dfloor > 0.0 || pfloor > 0.0;
   const size_t nc = g.ncell(), nf = g.nface();
   int bad = 0;
   for (int k = 0; k < g.N[2]; ++k)
@@ -200,9 +210,20 @@ int cons_to_prim(const Geo& g, double gamma, const T* cons, const T* bf, T* w, T
         T rho = cons[0 * nc + q];
         T m1 = cons[1 * nc + q], m2 = cons[2 * nc + q], m3 = cons[3 * nc + q];
         T en = cons[4 * nc + q];
+        const bool finite_in = std::isfinite(val(rho)) && std::isfinite(val(en));
+        bool floored = false;
+        if (floors && finite_in && !(val(rho) >= dfloor)) {
+          rho = T(dfloor);
+          floored = true;
+        }
         T kin = 0.5 * (m1 * m1 + m2 * m2 + m3 * m3) / rho;
         T mag = 0.5 * (b1 * b1 + b2 * b2 + b3 * b3);
         T p = (gamma - 1.0) * (en - kin - mag);
+        if (floors && finite_in && !(val(p) >= pfloor)) {
+          p = T(pfloor);
+          floored = true;
+        }
+        if (floored) ++g_floored;
         w[0 * nc + q] = rho;
         w[1 * nc + q] = m1 / rho;
         w[2 * nc + q] = m2 / rho;
@@ -493,7 +514,7 @@ int spatial_operator(const Cfg& cfg, const Geo& g, int recon, const T* cons, con
   const size_t nc = g.ncell(), nf = g.nface();
   wk.w.assign(5 * nc, T(0.0));
   wk.bcc.assign(3 * nc, T(0.0));
-  int bad = cons_to_prim(g, cfg.gamma, cons, bf, wk.w.data(), wk.bcc.data());
+  int bad = cons_to_prim(g, cfg.gamma, cons, bf, wk.w.data(), wk.bcc.data(), cfg.dfloor, cfg.pfloor);
   const double dx[3] = {cfg.dx1, cfg.dx2, cfg.dx3};
   const int sten = recon == RECON_PPM ? 3 : (recon == RECON_PLM ? 2 : 1);
 
@@ -530,6 +551,16 @@ int spatial_operator(const Cfg& cfg, const Geo& g, int recon, const T* cons, con
           }
           T wl[7], wr[7];
           for (int n = 0; n < 7; ++n) recon_face(recon, &line[n][3], wl[n], wr[n]);
+          // floors, when enabled, also apply to the reconstructed face states
+          if (cfg.dfloor > 0.0 || cfg.pfloor > 0.0) {
+            T* st[2] = {wl, wr};
+            for (T* q : st) {
+              bool floored = false;
+              if (!(val(q[0]) >= cfg.dfloor)) { q[0] = T(cfg.dfloor); floored = true; }
+              if (!(val(q[4]) >= cfg.pfloor)) { q[4] = T(cfg.pfloor); floored = true; }
+              if (floored) ++g_floored;
+            }
+          }
           T bn = bf[d * nf + g.f(i, j, k)];
           T fx[7], smax;
           riemann(cfg.riemann, wl, wr, bn, cfg.gamma, fx, smax);
@@ -664,6 +695,12 @@ inline bool scheme_for(int integrator, Scheme& s) {
 // left as they are.
 template <class T, class Rhs>
 int drive_2s(const Scheme& sc, size_t n, T* u0, const unsigned char* mask, double dt, Rhs rhs) {
+  return drive_2s(sc, n, u0, mask, dt, rhs, [](T*) {});
+}
+
+// Same, with `post(u0)` applied to the state after every stage.
+template <class T, class Rhs, class Post>
+int drive_2s(const Scheme& sc, size_t n, T* u0, const unsigned char* mask, double dt, Rhs rhs, Post post) {
   std::vector<T> u1(n, T(0.0)), L(n, T(0.0));
   int bad = 0;
   for (int s = 0; s < sc.nstage; ++s) {
@@ -673,8 +710,47 @@ int drive_2s(const Scheme& sc, size_t n, T* u0, const unsigned char* mask, doubl
     bad += b;
     for (size_t q = 0; q < n; ++q)
       if (mask[q]) u0[q] = sc.g0[s] * u0[q] + sc.g1[s] * u1[q] + sc.beta[s] * dt * L[q];
+    post(u0);
   }
   return bad;
+}
+
+// Floors on the conserved state after a stage (only with floors enabled):
+// density below dfloor is raised to dfloor, and where the pressure implied by
+// (U, B) is below pfloor the total energy is raised so that it equals pfloor
+// (kinetic and magnetic energy unchanged).  The cell-centred field uses the
+// lower face and the periodic image of the upper one.  Returns the number of
+// cells changed.
+template <class T> int floor_state(const Cfg& cfg, const Geo& g, T* cons, const T* bf) {
+  const size_t nc = g.ncell(), nf = g.nface();
+  int changed = 0;
+  for (int k = g.s(2); k <= g.e(2); ++k)
+    for (int j = g.s(1); j <= g.e(1); ++j)
+      for (int i = g.s(0); i <= g.e(0); ++i) {
+        const size_t q = g.c(i, j, k);
+        T b[3];
+        for (int d = 0; d < 3; ++d) {
+          int up[3] = {i, j, k};
+          up[d] = g.wrap(up[d] + 1, d);
+          b[d] = 0.5 * (bf[d * nf + g.f(i, j, k)] + bf[d * nf + g.f(up[0], up[1], up[2])]);
+        }
+        bool hit = false;
+        if (!(val(cons[q]) >= cfg.dfloor)) {
+          cons[q] = T(cfg.dfloor);
+          hit = true;
+        }
+        const T rho = cons[q];
+        const T kin = 0.5 * (cons[nc + q] * cons[nc + q] + cons[2 * nc + q] * cons[2 * nc + q] +
+                             cons[3 * nc + q] * cons[3 * nc + q]) / rho;
+        const T mag = 0.5 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+        const T p = (cfg.gamma - 1.0) * (cons[4 * nc + q] - kin - mag);
+        if (!(val(p) >= cfg.pfloor)) {
+          cons[4 * nc + q] = cfg.pfloor / (cfg.gamma - 1.0) + kin + mag;
+          hit = true;
+        }
+        if (hit) ++changed;
+      }
+  return changed;
 }
 
 // Full MHD step: state = cons (5 cell arrays) followed by bface (3 face arrays)
@@ -704,7 +780,12 @@ template <class T> int step(const Cfg& cfg, T* cons, T* bf, double dt) {
     int recon = (cfg.integrator == INT_VL2 && s == 0) ? RECON_DC : cfg.recon;
     return spatial_operator(cfg, g, recon, state, state + 5 * nc, L, L + 5 * nc, wk);
   };
-  int bad = drive_2s(sc, n, u.data(), mask.data(), dt, rhs);
+  int bad;
+  if (cfg.dfloor > 0.0 || cfg.pfloor > 0.0)
+    bad = drive_2s(sc, n, u.data(), mask.data(), dt, rhs,
+                   [&](T* state) { g_floored += floor_state(cfg, g, state, state + 5 * nc); });
+  else
+    bad = drive_2s(sc, n, u.data(), mask.data(), dt, rhs);
   if (bad < 0) return bad;
   fill_ghosts(g, u.data(), u.data() + 5 * nc);
   std::copy(u.begin(), u.begin() + 5 * nc, cons);
@@ -718,7 +799,7 @@ inline int newdt(const Cfg& cfg, const double* cons, const double* bf, double* d
   Geo g(cfg);
   const size_t nc = g.ncell();
   std::vector<double> w(5 * nc), bcc(3 * nc);
-  int bad = cons_to_prim(g, cfg.gamma, cons, bf, w.data(), bcc.data());
+  int bad = cons_to_prim(g, cfg.gamma, cons, bf, w.data(), bcc.data(), cfg.dfloor, cfg.pfloor);
   const double dx[3] = {cfg.dx1, cfg.dx2, cfg.dx3};
   double best = INFINITY;
   for (int k = g.s(2); k <= g.e(2); ++k)
@@ -751,7 +832,7 @@ int orc_fill_ghosts(const orc::Cfg* c, double* cons, double* bface) {
 
 int orc_cons2prim(const orc::Cfg* c, const double* cons, const double* bface, double* prim, double* bcc) {
   orc::Geo g(*c);
-  return orc::cons_to_prim(g, c->gamma, cons, bface, prim, bcc);
+  return orc::cons_to_prim(g, c->gamma, cons, bface, prim, bcc, c->dfloor, c->pfloor);
 }
 
 int orc_prim2cons(const orc::Cfg* c, const double* prim, const double* bface, double* cons) {
@@ -792,6 +873,13 @@ int orc_count_ops(const orc::Cfg* c, const double* cons, const double* bface, do
   out[2] = orc::g_ops.div;
   out[3] = orc::g_ops.sqrt;
   return r;
+}
+
+// Floor activations since the previous call (then reset to zero).
+long long orc_take_floor_count(void) {
+  const long long n = orc::g_floored;
+  orc::g_floored = 0;
+  return n;
 }
 
 int orc_newdt(const orc::Cfg* c, const double* cons, const double* bface, double* dt_out) {

@@ -35,7 +35,7 @@ class Cfg(C.Structure):
     _fields_ = [("n1", C.c_int32), ("n2", C.c_int32), ("n3", C.c_int32), ("ng", C.c_int32),
                 ("gamma", C.c_double), ("dx1", C.c_double), ("dx2", C.c_double), ("dx3", C.c_double),
                 ("recon", C.c_int32), ("riemann", C.c_int32), ("integrator", C.c_int32), ("pad_", C.c_int32),
-                ("cfl", C.c_double), ("ct_eps", C.c_double)]
+                ("cfl", C.c_double), ("ct_eps", C.c_double), ("dfloor", C.c_double), ("pfloor", C.c_double)]
 
 
 _lib = None
@@ -61,6 +61,7 @@ def lib():
         _lib.orc_recon_line.argtypes = [C.c_int, C.c_int, P, P, P]
         _lib.orc_drive_scalar.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_int,
                                           P, P]
+        _lib.orc_take_floor_count.restype = C.c_longlong
     return _lib
 
 
@@ -69,10 +70,16 @@ def _p(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-def make_cfg(n, ng, dx, gamma, recon="plm", riemann="hlld", integrator="vl2", cfl=0.3, ct_eps=0.0) -> Cfg:
+def make_cfg(n, ng, dx, gamma, recon="plm", riemann="hlld", integrator="vl2", cfl=0.3, ct_eps=0.0,
+             dfloor=0.0, pfloor=0.0) -> Cfg:
     return Cfg(int(n[0]), int(n[1]), int(n[2]), int(ng), float(gamma), float(dx[0]), float(dx[1]),
                float(dx[2]), RECON[recon], RIEMANN[riemann], INTEGRATOR[integrator], 0, float(cfl),
-               float(ct_eps))
+               float(ct_eps), float(dfloor), float(pfloor))
+
+
+def take_floor_count() -> int:
+    """Floor activations (cells and face states) since the previous call."""
+    return int(lib().orc_take_floor_count())
 
 
 def cfg_for(block, **kw) -> Cfg:

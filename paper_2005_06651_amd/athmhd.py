@@ -20,7 +20,7 @@ INTEGRATOR = {"rk1": 0, "vl2": 1, "rk2": 2, "rk3": 3}
 EXPORTED = ["athmhd_version", "athmhd_create", "athmhd_create_batch", "athmhd_batch_info",
             "athmhd_batch_set_tile", "athmhd_batch_tune", "athmhd_set_graph", "athmhd_step", "athmhd_newdt",
             "athmhd_prim2cons", "athmhd_fill_ghosts", "athmhd_profile", "athmhd_last_error", "athmhd_destroy",
-            "athmhd_step_vjp", "athmhd_prim2cons_vjp"]
+            "athmhd_step_vjp", "athmhd_prim2cons_vjp", "athmhd_set_floors", "athmhd_floor_count"]
 BATCH_TILES = [(16, 8), (8, 16), (14, 14), (8, 8)]  # active columns of the batch tile candidates
 
 
@@ -67,6 +67,8 @@ def lib():
         L.athmhd_prim2cons.argtypes = [vp, vp, vp, vp, C.c_int, vp]
         L.athmhd_fill_ghosts.argtypes = [vp, vp, vp, C.c_int, vp]
         L.athmhd_step_vjp.argtypes = [vp, vp, vp, C.c_double, vp, vp, vp, vp, C.c_int, vp]
+        L.athmhd_set_floors.argtypes = [vp, C.c_double, C.c_double]
+        L.athmhd_floor_count.argtypes = [vp, C.POINTER(C.c_longlong), vp]
         L.athmhd_prim2cons_vjp.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int, vp]
         L.athmhd_profile.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]
         L.athmhd_last_error.argtypes = [vp]
@@ -204,6 +206,16 @@ class Solver:
         _check(lib().athmhd_prim2cons_vjp(self._h, pp, pb, gc, op, gbp, nb, _stream(stream)), self._h)
         return out_prim
 
+    def set_floors(self, dfloor: float, pfloor: float) -> None:
+        """Optional density / pressure floors on the primitives (0, 0: off)."""
+        _check(lib().athmhd_set_floors(self._h, float(dfloor), float(pfloor)), self._h)
+
+    def floor_count(self, stream=None) -> int:
+        """Floor activations since the previous call (synchronises)."""
+        n = C.c_longlong()
+        _check(lib().athmhd_floor_count(self._h, C.byref(n), _stream(stream)), self._h)
+        return n.value
+
     def set_graph(self, enable: bool) -> None:
         """Record the step once into a hipGraph and replay it (needs a
         non-default stream)."""
@@ -323,6 +335,16 @@ class BatchSolver:
         _check(lib().athmhd_batch_tune(self._h, pc, pb, _stream(stream), C.byref(sh), C.byref(sp), C.byref(ms)),
                self._h)
         return sh.value, sp.value, ms.value
+
+    def set_floors(self, dfloor: float, pfloor: float) -> None:
+        """Optional density / pressure floors on the primitives (0, 0: off)."""
+        _check(lib().athmhd_set_floors(self._h, float(dfloor), float(pfloor)), self._h)
+
+    def floor_count(self, stream=None) -> int:
+        """Floor activations since the previous call (synchronises)."""
+        n = C.c_longlong()
+        _check(lib().athmhd_floor_count(self._h, C.byref(n), _stream(stream)), self._h)
+        return n.value
 
     def set_graph(self, enable: bool) -> None:
         _check(lib().athmhd_set_graph(self._h, int(bool(enable))), self._h)

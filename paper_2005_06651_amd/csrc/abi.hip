@@ -42,7 +42,8 @@ struct athmhd_s {
   UnfusedScratch scr{};
   double* scratch_base = nullptr;
   unsigned long long* d_dtmin = nullptr;  // running min of dx/(|v|+cf), bit pattern
-  int* d_bad = nullptr;                   // non-physical cells met since the last newdt
+  int* d_bad = nullptr;                   // [0] non-physical cells met since the last newdt, [1] floor activations
+  Floors floors{0.0, 0.0};                // optional primitive floors (off by default)
   double* d_dtval = nullptr;              // dt of the step on the device (graph replay)
   void* h_pinned = nullptr;               // 16 bytes of pinned host memory for newdt
   int kz = 0;                             // x3 planes per fused workgroup (0: default)
@@ -104,10 +105,12 @@ Scheme scheme_of(int integ) {
   }
 }
 
+// clear_bad: bit 0 clears the non-physical counter, bit 1 the floor counter
 __global__ void k_set_u64(unsigned long long* p, unsigned long long v, int* bad, int clear_bad) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     *p = v;
-    if (clear_bad) *bad = 0;
+    if (clear_bad & 1) bad[0] = 0;
+    if (clear_bad & 2) bad[1] = 0;
   }
 }
 
@@ -206,7 +209,7 @@ void free_all(athmhd_t h) {
 // Small device buffers every handle has.
 bool alloc_common(athmhd_t h) {
   return hipMalloc(&h->d_dtmin, sizeof(unsigned long long)) == hipSuccess &&
-         hipMalloc(&h->d_bad, sizeof(int)) == hipSuccess && hipMalloc(&h->d_dtval, sizeof(double)) == hipSuccess &&
+         hipMalloc(&h->d_bad, 2 * sizeof(int)) == hipSuccess && hipMalloc(&h->d_dtval, sizeof(double)) == hipSuccess &&
          hipHostMalloc(&h->h_pinned, 16, hipHostMallocDefault) == hipSuccess;
 }
 
@@ -259,13 +262,13 @@ hipError_t launch_stage(athmhd_t h, int recon, const double* xc, const double* x
                         int nblocks, hipStream_t s) {
   if (h->batch)
     return launch_stage_batch(h->shape, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, h->d_desc, h->d_items,
-                              h->nitems, h->d_queue, xc, xb, unc, unb, oc, ob, cf, dt_dev, beta, h->grid, h->d_bad,
-                              s);
+                              h->nitems, h->d_queue, xc, xb, unc, unb, oc, ob, cf, dt_dev, beta, h->grid, h->floors,
+                              h->d_bad, s);
   if (h->cfg.kernel_path == 0)
     return launch_stage_fused(h->g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc, xb, unc, unb, oc, ob, cf,
-                              dt_dev, beta, nblocks, h->kz, h->occ, h->d_bad, s);
+                              dt_dev, beta, nblocks, h->kz, h->occ, h->floors, h->d_bad, s);
   return launch_stage_unfused(h->g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc, xb, unc, unb, oc, ob,
-                              cf, nblocks, h->scr, h->d_bad, s);
+                              cf, nblocks, h->scr, h->floors, h->d_bad, s);
 }
 
 hipError_t fill_ghosts(athmhd_t h, double* cons, double* bface, int nblocks, hipStream_t s) {
@@ -305,6 +308,11 @@ int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const doubl
     e = launch_stage(h, recon, xc, xb, cons, bface, oc, ob, cf, sc.beta[st], dt_dev, nblocks, s);
     if (e != hipSuccess) return hip_fail(h, e, "stage launch");
     if ((e = mark(h, s)) != hipSuccess) return hip_fail(h, e, "profiling event");
+    if (h->floors.on()) {
+      e = h->batch ? launch_floor_state_batch(h->d_desc, h->nbatch, h->cfg.gamma, h->floors, oc, ob, h->d_bad, s)
+                   : launch_floor_state(h->g, h->cfg.gamma, h->floors, oc, ob, nblocks, h->d_bad, s);
+      if (e != hipSuccess) return hip_fail(h, e, "floor launch");
+    }
     xc = oc;
     xb = ob;
   }
@@ -445,7 +453,7 @@ int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
     p += 8 * h->g.fvar * nblocks_max;
   }
   h->scr.edge = p;
-  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, nullptr, h->d_dtmin, 0ull, h->d_bad, 1);
+  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, nullptr, h->d_dtmin, 0ull, h->d_bad, 3);
   e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     free_all(h);
@@ -525,7 +533,7 @@ int athmhd_create_batch(const athmhd_config* base, const int32_t* dims, const do
     delete h;
     return fail(nullptr, rc, "%s", msg.c_str());
   }
-  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, nullptr, h->d_dtmin, 0ull, h->d_bad, 1);
+  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, nullptr, h->d_dtmin, 0ull, h->d_bad, 3);
   e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     free_all(h);
@@ -603,13 +611,38 @@ int athmhd_batch_tune(athmhd_t h, const double* cons, const double* bface, void*
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   // the tuning launches may have counted non-physical cells of the scratch output
-  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, h->d_dtmin, 0ull, h->d_bad, 1);
+  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, h->d_dtmin, 0ull, h->d_bad, 3);
   if (rc != ATHMHD_OK) return rc;
   if ((rc = build_items(h, bs, bsp)) != ATHMHD_OK) return rc;
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(h, e, "tune synchronise");
   if (best_shape) *best_shape = bs;
   if (best_split) *best_split = bsp;
   if (best_ms) *best_ms = best;
+  return ATHMHD_OK;
+}
+
+int athmhd_set_floors(athmhd_t h, double dfloor, double pfloor) {
+  if (!h) return ATHMHD_EINVAL;
+  if (!(std::isfinite(dfloor) && dfloor >= 0.0 && std::isfinite(pfloor) && pfloor >= 0.0))
+    return fail(h, ATHMHD_EINVAL, "floors must be finite and >= 0 (got %g, %g)", dfloor, pfloor);
+  h->floors = Floors{dfloor, pfloor};
+  drop_graph(h);  // captured launches carry the floors as arguments
+  return ATHMHD_OK;
+}
+
+int athmhd_floor_count(athmhd_t h, long long* count, void* stream) {
+  if (!h) return ATHMHD_EINVAL;
+  if (!count) return fail(h, ATHMHD_EINVAL, "NULL count");
+  hipStream_t s = (hipStream_t)stream;
+  char* hp = (char*)h->h_pinned;
+  hipError_t e = hipMemcpyAsync(hp + 12, h->d_bad + 1, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, h->d_dtmin, 0ull, h->d_bad, 2);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(h, e, "floor count");
+  int n;
+  std::memcpy(&n, hp + 12, 4);
+  *count = n;
   return ATHMHD_OK;
 }
 
@@ -666,6 +699,7 @@ int athmhd_step_vjp(athmhd_t h, const double* cons_n, const double* bface_n, dou
   int rc = check_call(h, cons_n, bface_n, nblocks);
   if (rc) return rc;
   if (h->batch) return fail(h, ATHMHD_EUNSUP, "reverse mode is available for uniform handles only");
+  if (h->floors.on()) return fail(h, ATHMHD_EUNSUP, "reverse mode is not available with floors");
   if (!g_cons_np1 || !g_bface_np1 || !g_cons_n || !g_bface_n) return fail(h, ATHMHD_EINVAL, "NULL cotangent array");
   if (g_cons_n == cons_n || g_bface_n == bface_n || g_cons_n == (const double*)bface_n ||
       g_bface_n == (const double*)cons_n)
@@ -679,7 +713,6 @@ int athmhd_step_vjp(athmhd_t h, const double* cons_n, const double* bface_n, dou
   if ((rc = alloc_adjoint(h)) != ATHMHD_OK) return rc;
   hipStream_t s = (hipStream_t)stream;
   const Geo& g = h->g;
-  const int64_t nset = 8 * (int64_t)g.n1 * g.n2 * g.n3 * nblocks;
   hipError_t e = hipSuccess;
   // forward: stage inputs X_0 = (cons_n, bface_n), X_1, ..., X_{S-1}
   const double* xc[3] = {cons_n, nullptr, nullptr};
@@ -690,7 +723,7 @@ int athmhd_step_vjp(athmhd_t h, const double* cons_n, const double* bface_n, dou
     const int recon = (h->cfg.integrator == ATHMHD_VL2 && st == 0) ? ATHMHD_RECON_DC : h->cfg.recon;
     const StageCoef cf{sc.g0[st], sc.g1[st], sc.beta[st] * dt};
     e = launch_stage_fused(g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc[st], xb[st], cons_n, bface_n,
-                           oc, ob, cf, nullptr, sc.beta[st], nblocks, h->kz, h->occ, h->d_bad, s);
+                           oc, ob, cf, nullptr, sc.beta[st], nblocks, h->kz, h->occ, h->floors, h->d_bad, s);
     if (e != hipSuccess) return hip_fail(h, e, "vjp forward stage launch");
     xc[st + 1] = oc;
     xb[st + 1] = ob;
@@ -701,17 +734,12 @@ int athmhd_step_vjp(athmhd_t h, const double* cons_n, const double* bface_n, dou
   double* A = h->adj_cot[0];
   double* An = h->adj_cot[1];
   double* Z = h->adj_cot[2];
-  if ((e = launch_adj_gather(g, g_cons_np1, g_bface_np1, A, nblocks, s)) != hipSuccess ||
-      (e = launch_adj_fill(Z, 0.0, nset, s)) != hipSuccess)
+  if ((e = launch_adj_gather(g, g_cons_np1, g_bface_np1, A, nblocks, s)) != hipSuccess)
     return hip_fail(h, e, "vjp set-up launch");
   for (int st = sc.nstage - 1; st >= 0; --st) {
     const int recon = (h->cfg.integrator == ATHMHD_VL2 && st == 0) ? ATHMHD_RECON_DC : h->cfg.recon;
-    if (sc.g1[st] != 0.0 && (e = launch_adj_axpby(Z, 1.0, Z, sc.g1[st], A, nset, s)) != hipSuccess)
-      return hip_fail(h, e, "vjp axpby launch");
-    e = sc.g0[st] != 0.0 ? launch_adj_axpby(An, sc.g0[st], A, 0.0, A, nset, s) : launch_adj_fill(An, 0.0, nset, s);
-    if (e != hipSuccess) return hip_fail(h, e, "vjp axpby launch");
-    e = launch_stage_vjp(g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc[st], xb[st], A, An,
-                         sc.beta[st] * dt, h->adj_scr, nblocks, s);
+    e = launch_stage_vjp(g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc[st], xb[st], A, An, sc.g0[st],
+                         sc.beta[st] * dt, Z, sc.g1[st], st == sc.nstage - 1, h->adj_scr, nblocks, s);
     if (e != hipSuccess) return hip_fail(h, e, "stage vjp launch");
     std::swap(A, An);
   }
@@ -742,8 +770,9 @@ int athmhd_newdt(athmhd_t h, const double* cons, const double* bface, int nblock
   hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, h->d_dtmin, inf_bits, h->d_bad, 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(h, e, "newdt init launch");
-  e = h->batch ? launch_newdt_batch(h->d_desc, h->nbatch, 0, h->cfg.gamma, cons, bface, h->d_dtmin, h->d_bad, s)
-               : launch_newdt(h->g, h->cfg.gamma, cons, bface, nblocks, h->d_dtmin, h->d_bad, s);
+  e = h->batch ? launch_newdt_batch(h->d_desc, h->nbatch, 0, h->cfg.gamma, cons, bface, h->d_dtmin, h->floors,
+                                    h->d_bad, s)
+               : launch_newdt(h->g, h->cfg.gamma, cons, bface, nblocks, h->d_dtmin, h->floors, h->d_bad, s);
   if (e != hipSuccess) return hip_fail(h, e, "newdt launch");
   char* hp = (char*)h->h_pinned;
   if ((e = hipMemcpyAsync(hp, h->d_dtmin, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||

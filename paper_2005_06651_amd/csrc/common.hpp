@@ -44,6 +44,15 @@ struct StageCoef {
   double g0, g1, bdt;
 };
 
+// Optional floors on the primitive variables (0 disables each).  They limit
+// density and pressure from below in the primitives only -- cell values and
+// reconstructed face states -- and never modify the conserved variables, so
+// the update stays conservative.
+struct Floors {
+  double d, p;
+  __host__ __device__ bool on() const { return d > 0.0 || p > 0.0; }
+};
+
 // Periodic image of a stored index along a direction with n active cells.
 __host__ __device__ __forceinline__ int wrap_index(int idx, int n, int ng) {
   int r = (idx - ng) % n;

@@ -24,23 +24,24 @@ hipError_t launch_prim2cons(const Geo& g, double gamma, const double* prim, cons
 // dt_bits: device uint64 holding the bit pattern of the running minimum of
 // dx_d/(|v_d| + c_f) (initialise to +inf bits); bad: device int counter
 hipError_t launch_newdt(const Geo& g, double gamma, const double* cons, const double* bface, int nb,
-                        unsigned long long* dt_bits, int* bad, hipStream_t s);
+                        unsigned long long* dt_bits, const Floors& fl, int* bad, hipStream_t s);
 
 // One stage of the unfused pipeline: out = g0*x + g1*un + bdt * L(x), where
 // x must have filled ghosts.  out must not alias x; un may alias out.
 hipError_t launch_stage_unfused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
                                 const double* xb, const double* unc, const double* unb, double* outc,
-                                double* outb, StageCoef coef, int nb, UnfusedScratch& scr, int* bad,
-                                hipStream_t s);
+                                double* outb, StageCoef coef, int nb, UnfusedScratch& scr, const Floors& fl,
+                                int* bad, hipStream_t s);
 
 // One stage in a single fused kernel (same contract as launch_stage_unfused);
 // kz = x3 planes per workgroup segment (0: default for the block size);
 // occ = register-allocation target in waves per SIMD (1 or 2).
 // dt_dev, if not NULL, supplies dt on the device (bdt = beta * dt).
+// bad[0] counts threads that met a non-physical cell, bad[1] floor activations.
 hipError_t launch_stage_fused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
                               const double* xb, const double* unc, const double* unb, double* outc, double* outb,
-                              StageCoef coef, const double* dt_dev, double beta, int nb, int kz, int occ, int* bad,
-                              hipStream_t s);
+                              StageCoef coef, const double* dt_dev, double beta, int nb, int kz, int occ, Floors fl,
+                              int* bad, hipStream_t s);
 int fused_default_kz(const Geo& g);
 
 // Batched blocks of uneven sizes.  One block descriptor per block: its
@@ -62,7 +63,7 @@ int batch_tile_threads(int shape);
 hipError_t launch_stage_batch(int shape, double gamma, int recon, int rs, double ct_eps, const BatchDesc* desc,
                               const WorkItem* items, int nitems, unsigned* queue, const double* xc,
                               const double* xb, const double* unc, const double* unb, double* outc, double* outb,
-                              StageCoef coef, const double* dt_dev, double beta, int grid, int* bad,
+                              StageCoef coef, const double* dt_dev, double beta, int grid, Floors fl, int* bad,
                               hipStream_t s);
 // Ghost fill, prim->cons and the CFL reduction over all blocks of a batch.
 hipError_t launch_fill_ghosts_batch(const BatchDesc* desc, int nblocks, int64_t max_shell, double* cons,
@@ -70,10 +71,18 @@ hipError_t launch_fill_ghosts_batch(const BatchDesc* desc, int nblocks, int64_t 
 hipError_t launch_prim2cons_batch(const BatchDesc* desc, int nblocks, int64_t max_cells, double gamma,
                                   const double* prim, const double* bface, double* cons, hipStream_t s);
 hipError_t launch_newdt_batch(const BatchDesc* desc, int nblocks, int64_t max_active, double gamma,
-                              const double* cons, const double* bface, unsigned long long* dt_bits, int* bad,
-                              hipStream_t s);
+                              const double* cons, const double* bface, unsigned long long* dt_bits,
+                              const Floors& fl, int* bad, hipStream_t s);
 
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
+
+// Floors on the conserved state of the active cells after a stage: rho raised
+// to fl.d, and E raised where the pressure implied by (U, B) is below fl.p
+// (face fields are read with periodic wrap).  Changed cells count in bad[1].
+hipError_t launch_floor_state(const Geo& g, double gamma, const Floors& fl, double* cons, const double* bface, int nb,
+                              int* bad, hipStream_t s);
+hipError_t launch_floor_state_batch(const BatchDesc* desc, int nblocks, double gamma, const Floors& fl, double* cons,
+                                    const double* bface, int* bad, hipStream_t s);
 
 // ---- reverse mode (periodic uniform blocks) ---------------------------------
 // Cotangent sets are 8 active-only arrays per block (5 conserved variables,
@@ -81,12 +90,13 @@ hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s)
 // stride 8 * n1 * n2 * n3 doubles.
 // Scratch doubles per block needed by launch_stage_vjp.
 int64_t adj_scratch_per_block(const Geo& g);
-// O += scale * J_L(X)^T V for the spatial operator L of one stage (recon DC or
-// PLM, HLLE or HLLD, CT weight eps), X in the padded layout.  V and O must not
-// alias.
+// One stage of the reverse sweep for the spatial operator L of a stage
+// (recon DC or PLM, HLLE or HLLD, CT weight eps), X in the padded layout:
+//   O = g0 V + scale J_L(X)^T V,  and if Z != NULL:  Z = (zfirst ? 0 : Z) + g1 V.
+// O must not alias V or Z.
 hipError_t launch_stage_vjp(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
-                            const double* xb, const double* V, double* O, double scale, double* scr, int nb,
-                            hipStream_t s);
+                            const double* xb, const double* V, double* O, double g0, double scale, double* Z,
+                            double g1, int zfirst, double* scr, int nb, hipStream_t s);
 hipError_t launch_adj_fill(double* p, double v, int64_t n, hipStream_t s);
 // out = xc * x + yc * y (elementwise; out may alias x or y)
 hipError_t launch_adj_axpby(double* out, double xc, const double* x, double yc, const double* y, int64_t n,

@@ -14,7 +14,7 @@
 // thread, in a fixed order), so the result is deterministic.  Pipeline:
 //   1. k_adj_prim       primitives W and cell EMFs -v x B of the stage input
 //   2. k_adj_face_fwd   per direction: face EMFs and CT upwind weights
-//   3. k_adj_edge       corner-EMF cotangents: transpose of the CT curl
+//   3. (in k_adj_prim)  corner-EMF cotangents: transpose of the CT curl
 //   4. k_adj_face_bwd   per direction: flux / face-EMF / weight cotangents
 //                       gathered from the neighbouring cells and edges, then
 //                       the Riemann solver's reverse sweep -> cotangents of
@@ -24,6 +24,8 @@
 //   6. k_adj_cell       cell-EMF cotangents and the reverse of cons -> prim
 //   7. k_adj_bface      face-field cotangents (normal field of the Riemann
 //                       problems and the two cell-centred averages)
+// Steps 6 and 7 write the stage's output cotangent O = g0 V + scale J^T V and
+// the running sum Z of the U^n terms (Z += g1 V) of the 2S scheme.
 #include "common.hpp"
 #include "kernels.hpp"
 #include "mhd_adjoint.hpp"
@@ -103,14 +105,27 @@ __device__ __forceinline__ int pf(const Adj& a, const Cell& c, int d, int o) {
 }
 
 // ---- 1. primitives and cell EMFs -------------------------------------------
+// (also step 3: the corner-EMF cotangents, which need only the cotangent V)
 __global__ void __launch_bounds__(kT) k_adj_prim(Adj a, const double* __restrict__ xc,
-                                                const double* __restrict__ xb, double* __restrict__ scr) {
+                                                const double* __restrict__ xb, const double* __restrict__ V,
+                                                double* __restrict__ scr) {
   const int t = blockIdx.x * kT + threadIdx.x;
   if (t >= (int)a.nc) return;
   const double* u = xc + blockIdx.y * a.g.cblock;
   const double* fb = xb + blockIdx.y * a.g.fblock;
   double* s = scr + blockIdx.y * (S_TOTAL * a.nc);
   const Cell c = cell_of(a, t);
+  {
+    const double* v = V + blockIdx.y * (8 * a.nc);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      const int ea = (e + 1) % 3, eb = (e + 2) % 3;
+      const double* va = v + (5 + ea) * a.nc;
+      const double* vb = v + (5 + eb) * a.nc;
+      s[(S_EB + e) * a.nc + t] =
+          (va[t] - va[at1(a, c, eb, -1)]) * a.idx[eb] - (vb[t] - vb[at1(a, c, ea, -1)]) * a.idx[ea];
+    }
+  }
   const int q = pc(a, c);
   double b[3];
 #pragma unroll
@@ -193,25 +208,11 @@ __global__ void __launch_bounds__(kT) k_adj_face_fwd(Adj a, const double* __rest
   s[(S_FE + 3 * D + 2) * a.nc + t] = ct_weight(F.rho, 0.5 * (L.rho + R.rho), smax, a.ct_eps);
 }
 
-// ---- 3. corner-EMF cotangents ----------------------------------------------
-// The CT update of the face field is dB_a/dt = -(dE_e/dx_b - dE_b/dx_e)...;
-// its transpose gives, for the edge of component e at the lower corner of c
+// ---- 3. corner-EMF cotangents (computed in k_adj_prim) ---------------------
+// The CT update of the face field is minus the curl of the corner EMFs; its
+// transpose gives, for the edge of component e at the lower corner of c
 // (a = e+1, b = e+2 cyclic):
 //   Ebar_e = (v_Ba[c] - v_Ba[c - b]) / dx_b - (v_Bb[c] - v_Bb[c - a]) / dx_a
-__global__ void __launch_bounds__(kT) k_adj_edge(Adj a, const double* __restrict__ V, double* __restrict__ scr) {
-  const int t = blockIdx.x * kT + threadIdx.x;
-  if (t >= (int)a.nc) return;
-  const double* v = V + blockIdx.y * (8 * a.nc);
-  double* s = scr + blockIdx.y * (S_TOTAL * a.nc);
-  const Cell c = cell_of(a, t);
-#pragma unroll
-  for (int e = 0; e < 3; ++e) {
-    const int ea = (e + 1) % 3, eb = (e + 2) % 3;
-    const double* va = v + (5 + ea) * a.nc;
-    const double* vb = v + (5 + eb) * a.nc;
-    s[(S_EB + e) * a.nc + t] = (va[t] - va[at1(a, c, eb, -1)]) * a.idx[eb] - (vb[t] - vb[at1(a, c, ea, -1)]) * a.idx[ea];
-  }
-}
 
 // ---- 4. face cotangents and the Riemann solver's reverse sweep ------------
 template <int D, int RECON, int RS>
@@ -312,6 +313,8 @@ __global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2))) k_
 // Cell c feeds the right state of its lower face (c) and the left state of
 // its upper face (c + D); with PLM it also enters the slopes of c - D, c and
 // c + D.
+// The first direction (D = 0) writes the primitive cotangents, the others
+// add to them; B1cc is not reconstructed along x1 and starts at zero.
 template <int D, int RECON>
 __global__ void __launch_bounds__(kT) k_adj_recon_bwd(Adj a, double* __restrict__ scr) {
   const int t = blockIdx.x * kT + threadIdx.x;
@@ -319,6 +322,7 @@ __global__ void __launch_bounds__(kT) k_adj_recon_bwd(Adj a, double* __restrict_
   double* s = scr + blockIdx.y * (S_TOTAL * a.nc);
   const Cell c = cell_of(a, t);
   const int cp = at1(a, c, D, 1);
+  if (D == 0) s[(S_WB + 5) * a.nc + t] = 0.0;
 #pragma unroll
   for (int m = 0; m < 7; ++m) {
     const double* lb = s + (S_LB + m) * a.nc;
@@ -342,17 +346,34 @@ __global__ void __launch_bounds__(kT) k_adj_recon_bwd(Adj a, double* __restrict_
       vl_slope_vjp(q0, qp, qp2, dbp, x0, x1, x2);  // c is the left point
       g += x0;
     }
-    s[(S_WB + wslot(D, m)) * a.nc + t] += g;
+    double& dst = s[(S_WB + wslot(D, m)) * a.nc + t];
+    dst = D == 0 ? g : dst + g;
   }
 }
 
 // ---- 6. cell EMFs and cons -> prim in reverse -------------------------------
-__global__ void __launch_bounds__(kT) k_adj_cell(Adj a, double* __restrict__ scr, double* __restrict__ O,
-                                                double scale) {
+// Output of the stage (per cotangent slot): O = g0 V + scale J^T V, and, when
+// Z is not NULL, Z = (zfirst ? 0 : Z) + g1 V.
+struct StageOut {
+  const double* V;
+  double* O;
+  double* Z;
+  double g0, g1, scale;
+  int zfirst;
+};
+
+__device__ __forceinline__ void stage_out(const StageOut& so, int64_t off, int m, int64_t nc, int t, double jt) {
+  const int64_t e = off + m * nc + t;
+  const double v = so.V[e];
+  so.O[e] = so.g0 * v + so.scale * jt;
+  if (so.Z) so.Z[e] = (so.zfirst ? 0.0 : so.Z[e]) + so.g1 * v;
+}
+
+__global__ void __launch_bounds__(kT) k_adj_cell(Adj a, double* __restrict__ scr, StageOut so) {
   const int t = blockIdx.x * kT + threadIdx.x;
   if (t >= (int)a.nc) return;
   double* s = scr + blockIdx.y * (S_TOTAL * a.nc);
-  double* o = O + blockIdx.y * (8 * a.nc);
+  const int64_t off = blockIdx.y * (8 * a.nc);
   const Cell c = cell_of(a, t);
   double wb[8], w[8];
 #pragma unroll
@@ -389,27 +410,26 @@ __global__ void __launch_bounds__(kT) k_adj_cell(Adj a, double* __restrict__ scr
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     urho -= wb[1 + d] * w[1 + d] * ir;
-    o[(1 + d) * a.nc + t] += scale * (wb[1 + d] * ir - gm1 * w[1 + d] * pb);
+    stage_out(so, off, 1 + d, a.nc, t, wb[1 + d] * ir - gm1 * w[1 + d] * pb);
     s[(S_BC + d) * a.nc + t] = wb[5 + d] - gm1 * w[5 + d] * pb;
   }
-  o[t] += scale * urho;
-  o[4 * a.nc + t] += scale * gm1 * pb;
+  stage_out(so, off, 0, a.nc, t, urho);
+  stage_out(so, off, 4, a.nc, t, gm1 * pb);
 }
 
 // ---- 7. face-field cotangents -----------------------------------------------
 // B_d at the lower face of c: normal field of that face's Riemann problem and
 // half of the cell-centred field of c and of c - d.
-__global__ void __launch_bounds__(kT) k_adj_bface(Adj a, const double* __restrict__ scr, double* __restrict__ O,
-                                                 double scale) {
+__global__ void __launch_bounds__(kT) k_adj_bface(Adj a, const double* __restrict__ scr, StageOut so) {
   const int t = blockIdx.x * kT + threadIdx.x;
   if (t >= (int)a.nc) return;
   const double* s = scr + blockIdx.y * (S_TOTAL * a.nc);
-  double* o = O + blockIdx.y * (8 * a.nc);
+  const int64_t off = blockIdx.y * (8 * a.nc);
   const Cell c = cell_of(a, t);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const double* bc = s + (S_BC + d) * a.nc;
-    o[(5 + d) * a.nc + t] += scale * (s[(S_BN + d) * a.nc + t] + 0.5 * (bc[t] + bc[at1(a, c, d, -1)]));
+    stage_out(so, off, 5 + d, a.nc, t, s[(S_BN + d) * a.nc + t] + 0.5 * (bc[t] + bc[at1(a, c, d, -1)]));
   }
 }
 
@@ -602,29 +622,24 @@ void recon_dir(const Adj& a, int recon, dim3 grid, double* scr, hipStream_t s) {
 int64_t adj_scratch_per_block(const Geo& g) { return (int64_t)S_TOTAL * g.n1 * g.n2 * g.n3; }
 
 hipError_t launch_stage_vjp(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
-                            const double* xb, const double* V, double* O, double scale, double* scr, int nb,
-                            hipStream_t s) {
+                            const double* xb, const double* V, double* O, double g0, double scale, double* Z,
+                            double g1, int zfirst, double* scr, int nb, hipStream_t s) {
   if (recon != 0 && recon != 1) return hipErrorInvalidValue;
   const Adj a = make_adj(g, gamma, ct_eps);
   const dim3 grid(grid_of(a.nc), nb);
-  hipLaunchKernelGGL(k_adj_prim, grid, dim3(kT), 0, s, a, xc, xb, scr);
+  hipLaunchKernelGGL(k_adj_prim, grid, dim3(kT), 0, s, a, xc, xb, V, scr);
   face_dir<0>(a, recon, rs, grid, xb, V, scr, s, false);
   face_dir<1>(a, recon, rs, grid, xb, V, scr, s, false);
   face_dir<2>(a, recon, rs, grid, xb, V, scr, s, false);
-  hipLaunchKernelGGL(k_adj_edge, grid, dim3(kT), 0, s, a, V, scr);
-  // primitive cotangents start at zero in every block
-  for (int b = 0; b < nb; ++b) {
-    double* wbp = scr + (int64_t)b * S_TOTAL * a.nc + (int64_t)S_WB * a.nc;
-    hipLaunchKernelGGL(k_adj_fill, dim3(grid_of(8 * a.nc)), dim3(kT), 0, s, wbp, 0.0, 8 * a.nc);
-  }
   face_dir<0>(a, recon, rs, grid, xb, V, scr, s, true);
   recon_dir<0>(a, recon, grid, scr, s);
   face_dir<1>(a, recon, rs, grid, xb, V, scr, s, true);
   recon_dir<1>(a, recon, grid, scr, s);
   face_dir<2>(a, recon, rs, grid, xb, V, scr, s, true);
   recon_dir<2>(a, recon, grid, scr, s);
-  hipLaunchKernelGGL(k_adj_cell, grid, dim3(kT), 0, s, a, scr, O, scale);
-  hipLaunchKernelGGL(k_adj_bface, grid, dim3(kT), 0, s, a, scr, O, scale);
+  const StageOut so{V, O, Z, g0, g1, scale, zfirst};
+  hipLaunchKernelGGL(k_adj_cell, grid, dim3(kT), 0, s, a, scr, so);
+  hipLaunchKernelGGL(k_adj_bface, grid, dim3(kT), 0, s, a, scr, so);
   return hipGetLastError();
 }
 

@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(kThreads) k_prim2cons(Geo g, double gamma, con
 // (non-negative doubles order like their bits).
 constexpr int kDtBlocks = 1024;
 
-__global__ void __launch_bounds__(kThreads) k_newdt(Geo g, double gamma, const double* __restrict__ cons,
+__global__ void __launch_bounds__(kThreads) k_newdt(Geo g, double gamma, Floors fl, const double* __restrict__ cons,
                                                    const double* __restrict__ bface,
                                                    unsigned long long* __restrict__ dt_bits,
                                                    int* __restrict__ bad) {
@@ -114,14 +114,14 @@ __global__ void __launch_bounds__(kThreads) k_newdt(Geo g, double gamma, const d
     const double b1 = 0.5 * (fb[f] + fb[f + 1]);
     const double b2 = 0.5 * (fb[g.fvar + f] + fb[g.fvar + f + g.F1]);
     const double b3 = 0.5 * (fb[2 * g.fvar + f] + fb[2 * g.fvar + f + g.F1 * g.F2]);
-    const double rho = u[q], ir = frcp(rho);
-    const double v1 = u[g.cvar + q] * ir, v2 = u[2 * g.cvar + q] * ir, v3 = u[3 * g.cvar + q] * ir;
-    const double p = (gamma - 1.0) * (u[4 * g.cvar + q] - 0.5 * rho * (v1 * v1 + v2 * v2 + v3 * v3) -
-                                      0.5 * (b1 * b1 + b2 * b2 + b3 * b3));
-    if (!(rho > 0.0) || !(p > 0.0)) {
+    const double uc[5] = {u[q], u[g.cvar + q], u[2 * g.cvar + q], u[3 * g.cvar + q], u[4 * g.cvar + q]};
+    const double bc[3] = {b1, b2, b3};
+    double w[5];
+    if (cell_prim(uc, bc, gamma - 1.0, fl, w) & 1) {
       ++nbad;
       continue;
     }
+    const double ir = frcp(w[0]), v1 = w[1], v2 = w[2], v3 = w[3], p = w[4];
     const double bs1 = b1 * b1, bs2 = b2 * b2, bs3 = b3 * b3;
     const double c1 = fast_speed(ir, p, bs1, bs2 + bs3, gamma);
     const double c2 = fast_speed(ir, p, bs2, bs3 + bs1, gamma);
@@ -141,6 +141,65 @@ __global__ void __launch_bounds__(kThreads) k_newdt(Geo g, double gamma, const d
     for (int w = 1; w < kThreads / 64; ++w) m = fmin(m, part[w]);
     if (m < DBL_MAX) atomicMin(dt_bits, (unsigned long long)__double_as_longlong(m));
   }
+}
+
+// Floors on the conserved state after a stage (floors enabled only): density
+// below the floor is raised to it, and where the pressure implied by (U, B)
+// is below the pressure floor the total energy is raised to give exactly that
+// pressure.  The cell-centred field uses the lower face and the periodic image
+// of the upper one.  Changed cells are counted in bad[1].
+__device__ __forceinline__ int floor_cell(const Geo& g, double gm1, const Floors& fl, double* u,
+                                          const double* fb, int i, int j, int k) {
+  const int q = g.c(i, j, k), f = g.f(i, j, k);
+  const int iu = wrap_index(i + 1, g.n1, g.ng), ju = wrap_index(j + 1, g.n2, g.ng), ku = wrap_index(k + 1, g.n3, g.ng);
+  const double b1 = 0.5 * (fb[f] + fb[g.f(iu, j, k)]);
+  const double b2 = 0.5 * (fb[g.fvar + f] + fb[g.fvar + g.f(i, ju, k)]);
+  const double b3 = 0.5 * (fb[2 * g.fvar + f] + fb[2 * g.fvar + g.f(i, j, ku)]);
+  int hit = 0;
+  double rho = u[q];
+  if (!(rho >= fl.d)) {
+    rho = fl.d;
+    u[q] = rho;
+    hit = 1;
+  }
+  const double m1 = u[g.cvar + q], m2 = u[2 * g.cvar + q], m3 = u[3 * g.cvar + q];
+  const double kin = 0.5 * (m1 * m1 + m2 * m2 + m3 * m3) / rho;
+  const double mag = 0.5 * (b1 * b1 + b2 * b2 + b3 * b3);
+  const double p = gm1 * (u[4 * g.cvar + q] - kin - mag);
+  if (!(p >= fl.p)) {
+    u[4 * g.cvar + q] = fl.p / gm1 + kin + mag;
+    hit = 1;
+  }
+  return hit;
+}
+
+__global__ void __launch_bounds__(kThreads) k_floor_state(Geo g, double gm1, Floors fl, double* __restrict__ cons,
+                                                         const double* __restrict__ bface, int* __restrict__ bad) {
+  const int64_t nact = (int64_t)g.n1 * g.n2 * g.n3;
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= nact) return;
+  const int i = g.ng + (int)(t % g.n1);
+  const int r = (int)(t / g.n1);
+  const int j = g.ng + r % g.n2, k = g.ng + r / g.n2;
+  if (floor_cell(g, gm1, fl, cons + blockIdx.y * g.cblock, bface + blockIdx.y * g.fblock, i, j, k))
+    atomicAdd(bad + 1, 1);
+}
+
+__global__ void __launch_bounds__(kThreads) k_floor_state_batch(const BatchDesc* __restrict__ desc, double gm1,
+                                                               Floors fl, double* __restrict__ cons,
+                                                               const double* __restrict__ bface,
+                                                               int* __restrict__ bad) {
+  const BatchDesc& d = desc[blockIdx.y];
+  const Geo& g = d.g;
+  const int64_t nact = (int64_t)g.n1 * g.n2 * g.n3;
+  int hits = 0;
+  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < nact; t += (int64_t)gridDim.x * kThreads) {
+    const int i = g.ng + (int)(t % g.n1);
+    const int r = (int)(t / g.n1);
+    const int j = g.ng + r % g.n2, k = g.ng + r / g.n2;
+    hits += floor_cell(g, gm1, fl, cons + d.coff, bface + d.foff, i, j, k);
+  }
+  if (hits) atomicAdd(bad + 1, hits);
 }
 
 __global__ void __launch_bounds__(kThreads) k_copy(double* __restrict__ dst, const double* __restrict__ src,
@@ -223,7 +282,7 @@ __global__ void __launch_bounds__(kThreads) k_prim2cons_batch(const BatchDesc* _
 // one workgroup per block: its minimum of dx_d/(|v_d| + c_f,d), then one
 // atomicMin per block
 __global__ void __launch_bounds__(kThreads) k_newdt_batch(const BatchDesc* __restrict__ desc, double gamma,
-                                                         const double* __restrict__ cons,
+                                                         Floors fl, const double* __restrict__ cons,
                                                          const double* __restrict__ bface,
                                                          unsigned long long* __restrict__ dt_bits,
                                                          int* __restrict__ bad) {
@@ -242,14 +301,14 @@ __global__ void __launch_bounds__(kThreads) k_newdt_batch(const BatchDesc* __res
     const double b1 = 0.5 * (fb[f] + fb[f + 1]);
     const double b2 = 0.5 * (fb[g.fvar + f] + fb[g.fvar + f + g.F1]);
     const double b3 = 0.5 * (fb[2 * g.fvar + f] + fb[2 * g.fvar + f + g.F1 * g.F2]);
-    const double rho = u[q], ir = frcp(rho);
-    const double v1 = u[g.cvar + q] * ir, v2 = u[2 * g.cvar + q] * ir, v3 = u[3 * g.cvar + q] * ir;
-    const double p = (gamma - 1.0) * (u[4 * g.cvar + q] - 0.5 * rho * (v1 * v1 + v2 * v2 + v3 * v3) -
-                                      0.5 * (b1 * b1 + b2 * b2 + b3 * b3));
-    if (!(rho > 0.0) || !(p > 0.0)) {
+    const double uc[5] = {u[q], u[g.cvar + q], u[2 * g.cvar + q], u[3 * g.cvar + q], u[4 * g.cvar + q]};
+    const double bc[3] = {b1, b2, b3};
+    double w[5];
+    if (cell_prim(uc, bc, gamma - 1.0, fl, w) & 1) {
       ++nbad;
       continue;
     }
+    const double ir = frcp(w[0]), v1 = w[1], v2 = w[2], v3 = w[3], p = w[4];
     const double bs1 = b1 * b1, bs2 = b2 * b2, bs3 = b3 * b3;
     const double c1 = fast_speed(ir, p, bs1, bs2 + bs3, gamma);
     const double c2 = fast_speed(ir, p, bs2, bs3 + bs1, gamma);
@@ -287,8 +346,24 @@ hipError_t launch_prim2cons_batch(const BatchDesc* desc, int nblocks, int64_t ma
 }
 
 hipError_t launch_newdt_batch(const BatchDesc* desc, int nblocks, int64_t, double gamma, const double* cons,
-                              const double* bface, unsigned long long* dt_bits, int* bad, hipStream_t s) {
-  hipLaunchKernelGGL(k_newdt_batch, dim3(nblocks), dim3(kThreads), 0, s, desc, gamma, cons, bface, dt_bits, bad);
+                              const double* bface, unsigned long long* dt_bits, const Floors& fl, int* bad,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_newdt_batch, dim3(nblocks), dim3(kThreads), 0, s, desc, gamma, fl, cons, bface, dt_bits, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_floor_state(const Geo& g, double gamma, const Floors& fl, double* cons, const double* bface, int nb,
+                              int* bad, hipStream_t s) {
+  const int64_t nact = (int64_t)g.n1 * g.n2 * g.n3;
+  hipLaunchKernelGGL(k_floor_state, dim3(grid_for(nact), nb), dim3(kThreads), 0, s, g, gamma - 1.0, fl, cons, bface,
+                     bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_floor_state_batch(const BatchDesc* desc, int nblocks, double gamma, const Floors& fl, double* cons,
+                                    const double* bface, int* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_floor_state_batch, dim3(16, nblocks), dim3(kThreads), 0, s, desc, gamma - 1.0, fl, cons,
+                     bface, bad);
   return hipGetLastError();
 }
 
@@ -304,10 +379,10 @@ hipError_t launch_prim2cons(const Geo& g, double gamma, const double* prim, cons
 }
 
 hipError_t launch_newdt(const Geo& g, double gamma, const double* cons, const double* bface, int nb,
-                        unsigned long long* dt_bits, int* bad, hipStream_t s) {
+                        unsigned long long* dt_bits, const Floors& fl, int* bad, hipStream_t s) {
   const int64_t nact = (int64_t)g.n1 * g.n2 * g.n3;
   const unsigned blocks = (unsigned)std::min<int64_t>(grid_for(nact), kDtBlocks);
-  hipLaunchKernelGGL(k_newdt, dim3(blocks, nb), dim3(kThreads), 0, s, g, gamma, cons, bface, dt_bits, bad);
+  hipLaunchKernelGGL(k_newdt, dim3(blocks, nb), dim3(kThreads), 0, s, g, gamma, fl, cons, bface, dt_bits, bad);
   return hipGetLastError();
 }
 

@@ -42,11 +42,13 @@ struct StageArgs {
   StageCoef cf;          // g0, g1 and (when dt_dev is NULL) beta * dt
   const double* dt_dev;  // optional device copy of dt: bdt = beta * (*dt_dev)
   double beta;
-  int* bad;
+  Floors fl;             // optional primitive floors
+  int* bad;              // [0]: threads that met a non-physical cell, [1]: floor activations
 };
 
-// Arrays of one block: stage input (ghosts filled), U^n (the u^(1) register),
-// stage output (active cells and their lower faces).
+// Arrays of one block: stage input (periodic images are read by index wrap,
+// ghost entries are not used), U^n (the u^(1) register), stage output (active
+// cells and their lower faces).
 struct BlockPtrs {
   const double* xc;
   const double* xb;
@@ -131,14 +133,27 @@ __device__ __forceinline__ void load_raw(const Geo& g, const double* __restrict_
   r.b3hi = xb[2 * g.fvar + g.f(c.i0, c.j0, k1)];
 }
 
-// cons -> prim: w = (rho, v1, v2, v3, P, B1cc, B2cc, B3cc)
-__device__ __forceinline__ bool to_prim(const Raw& r, double gm1, double* w) {
-  const double b1 = 0.5 * (r.b1lo + r.b1hi), b2 = 0.5 * (r.b2lo + r.b2hi), b3 = 0.5 * (r.b3lo + r.b3hi);
-  const double rho = r.u[0], ir = frcp(rho);
-  const double v1 = r.u[1] * ir, v2 = r.u[2] * ir, v3 = r.u[3] * ir;
-  const double p = gm1 * (r.u[4] - 0.5 * rho * (v1 * v1 + v2 * v2 + v3 * v3) - 0.5 * (b1 * b1 + b2 * b2 + b3 * b3));
-  w[0] = rho; w[1] = v1; w[2] = v2; w[3] = v3; w[4] = p; w[5] = b1; w[6] = b2; w[7] = b3;
-  return rho > 0.0 && p > 0.0;
+// cons -> prim: w = (rho, v1, v2, v3, P, B1cc, B2cc, B3cc); returns the flags
+// of cell_prim (bit 0 non-physical, bit 1 floored).  The same cell is
+// converted at several places (the register window along x3, the primitive
+// plane, the extra rings, and again by the neighbouring tile or x3 segment);
+// cell_prim computes without contraction, so all of them get the same bits.
+// Fluxes and EMFs on tile and segment boundaries are computed twice and must
+// agree exactly, or the CT update no longer preserves div B (reconstruction
+// limiters can turn an ulp of difference into an O(1) one).
+__device__ __forceinline__ int to_prim(const Raw& r, double gm1, const Floors& fl, double* w) {
+  double b[3];
+  {
+#pragma clang fp contract(off)
+    b[0] = 0.5 * (r.b1lo + r.b1hi);
+    b[1] = 0.5 * (r.b2lo + r.b2hi);
+    b[2] = 0.5 * (r.b3lo + r.b3hi);
+  }
+  const int flags = cell_prim(r.u, b, gm1, fl, w);
+  w[5] = b[0];
+  w[6] = b[1];
+  w[7] = b[2];
+  return flags;
 }
 
 __device__ __forceinline__ void to_zcell(const double* w, ZCell& z) {
@@ -174,8 +189,9 @@ __device__ __forceinline__ FaceState make_state(const double* q) {
 
 template <int RS>
 __device__ __forceinline__ void riemann(const double* ql, const double* qr, double bn, const Gas& gas, double ct_eps,
-                                        FaceFlux& F, double& w) {
+                                        const Floors& fl, int& nfl, FaceFlux& F, double& w) {
   FaceState L = make_state(ql), R = make_state(qr);
+  if (fl.on()) nfl += floor_state(L, fl) + floor_state(R, fl);
   double smax;
   if (RS == 1) hlld(L, R, bn, gas, F, smax);
   else hlle(L, R, bn, gas, F, smax);
@@ -248,7 +264,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
 
   const double i1 = 1.0 / g.dx1, i2 = 1.0 / g.dx2, i3 = 1.0 / g.dx3;
   const double gm1 = sa.gas.gm1;
-  int nbad = 0;
+  int nbad = 0, nfl = 0;
 
   // ---- z window: planes p-LA .. p+LA of the own column
   ZCell win[NW];
@@ -260,7 +276,9 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
 #pragma unroll
     for (int o = 0; o < NW - 1; ++o) {
       load_raw(g, xc, xb, own, k0 - 1 - LA + o, raw);
-      nbad += !to_prim(raw, gm1, w);
+      const int f = to_prim(raw, gm1, sa.fl, w);
+      nbad += f & 1;
+      nfl += f >> 1;
       to_zcell(w, win[o + 1]);
       if (o >= LA) {
         bnq[o - LA][0] = raw.b1lo;
@@ -287,7 +305,9 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
     for (int o = 0; o < NW - 1; ++o) win[o] = win[o + 1];
     {
       double w[8];
-      nbad += !to_prim(pre, gm1, w);
+      const int f = to_prim(pre, gm1, sa.fl, w);
+      nbad += f & 1;
+      nfl += f >> 1;
       to_zcell(w, win[NW - 1]);
       bnq[LA][0] = pre.b1lo;
       bnq[LA][1] = pre.b2lo;
@@ -322,7 +342,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
     // ---- 4. ring cells to LDS
     if (ring) {
       double w[8];
-      to_prim(rpre, gm1, w);
+      to_prim(rpre, gm1, sa.fl, w);
 #pragma unroll
       for (int v = 0; v < 8; ++v) sp[v * PL + rl] = w[v];
     }
@@ -347,7 +367,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
       if (zface) {
         const double bn3 = bnq[0][2];
         FaceFlux fz;
-        riemann<RS>(zl, zr, bn3, sa.gas, sa.ct_eps, fz, wz);
+        riemann<RS>(zl, zr, bn3, sa.gas, sa.ct_eps, sa.fl, nfl, fz, wz);
         // z-frame -> (rho, M1, M2, M3, E); x3-face E2 = -F(B1), E1 = +F(B2)
         fz_cons[0] = fz.rho; fz_cons[1] = fz.mt1; fz_cons[2] = fz.mt2; fz_cons[3] = fz.mn; fz_cons[4] = fz.e;
         e2z = -fz.bt1;
@@ -385,7 +405,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
         }
         const double bn1 = bnq[0][0];
         FaceFlux fx;
-        riemann<RS>(ql, qr, bn1, sa.gas, sa.ct_eps, fx, wx);
+        riemann<RS>(ql, qr, bn1, sa.gas, sa.ct_eps, sa.fl, nfl, fx, wx);
         sx[(X_FX + 0) * NT + tid] = fx.rho;
         sx[(X_FX + 1) * NT + tid] = fx.mn;   // M1
         sx[(X_FX + 2) * NT + tid] = fx.mt1;  // M2
@@ -422,7 +442,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
         }
         const double bn2 = bnq[0][1];
         FaceFlux fy;
-        riemann<RS>(ql, qr, bn2, sa.gas, sa.ct_eps, fy, wy);
+        riemann<RS>(ql, qr, bn2, sa.gas, sa.ct_eps, sa.fl, nfl, fy, wy);
         sx[(X_FY + 0) * NT + tid] = fy.rho;
         sx[(X_FY + 1) * NT + tid] = fy.mt2;  // M1
         sx[(X_FY + 2) * NT + tid] = fy.mn;   // M2
@@ -544,6 +564,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
     e2c_prev = e2c;
   }
   if (nbad && act) atomicAdd(sa.bad, 1);
+  if (nfl && act) atomicAdd(sa.bad + 1, nfl);
 }
 
 // Uniform blocks: one workgroup per (tile, x3 segment, block), XCD-aware:
@@ -633,8 +654,9 @@ hipError_t launch_batch_recon(int recon, int rs, const BatchArgs& ba, int grid, 
 int fused_default_kz(const Geo& g) { return g.n3 >= 64 ? 32 : (g.n3 >= 16 ? 16 : g.n3); }
 
 static StageArgs make_stage_args(double gamma, double ct_eps, StageCoef coef, const double* dt_dev, double beta,
-                                 int* bad) {
+                                 Floors fl, int* bad) {
   StageArgs sa;
+  sa.fl = fl;
   sa.gas = Gas{gamma, gamma - 1.0, 1.0 / (gamma - 1.0)};
   sa.ct_eps = ct_eps;
   sa.cf = coef;
@@ -646,11 +668,11 @@ static StageArgs make_stage_args(double gamma, double ct_eps, StageCoef coef, co
 
 hipError_t launch_stage_fused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
                               const double* xb, const double* unc, const double* unb, double* outc, double* outb,
-                              StageCoef coef, const double* dt_dev, double beta, int nb, int kz, int occ, int* bad,
-                              hipStream_t s) {
+                              StageCoef coef, const double* dt_dev, double beta, int nb, int kz, int occ, Floors fl,
+                              int* bad, hipStream_t s) {
   UniformArgs fa;
   fa.g = g;
-  fa.sa = make_stage_args(gamma, ct_eps, coef, dt_dev, beta, bad);
+  fa.sa = make_stage_args(gamma, ct_eps, coef, dt_dev, beta, fl, bad);
   fa.xc = xc; fa.xb = xb; fa.unc = unc; fa.unb = unb; fa.oc = outc; fa.ob = outb;
   fa.kz = kz > 0 ? kz : fused_default_kz(g);
   fa.ntx = (g.n1 + TileU::TX - 1) / TileU::TX;
@@ -680,7 +702,7 @@ int batch_tile_threads(int shape) {
 hipError_t launch_stage_batch(int shape, double gamma, int recon, int rs, double ct_eps, const BatchDesc* desc,
                               const WorkItem* items, int nitems, unsigned* queue, const double* xc,
                               const double* xb, const double* unc, const double* unb, double* outc, double* outb,
-                              StageCoef coef, const double* dt_dev, double beta, int grid, int* bad,
+                              StageCoef coef, const double* dt_dev, double beta, int grid, Floors fl, int* bad,
                               hipStream_t s) {
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, queue);
   hipError_t e = hipGetLastError();
@@ -690,7 +712,7 @@ hipError_t launch_stage_batch(int shape, double gamma, int recon, int rs, double
   ba.items = items;
   ba.nitems = nitems;
   ba.queue = queue;
-  ba.sa = make_stage_args(gamma, ct_eps, coef, dt_dev, beta, bad);
+  ba.sa = make_stage_args(gamma, ct_eps, coef, dt_dev, beta, fl, bad);
   ba.xc = xc; ba.xb = xb; ba.unc = unc; ba.unb = unb; ba.oc = outc; ba.ob = outb;
   switch (shape) {
     case 0: return launch_batch_recon<Tile<18, 10>>(recon, rs, ba, grid, s);

@@ -15,7 +15,7 @@ constexpr int kThreads = 256;
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 // cons -> prim on every stored cell; 8 output arrays (rho, v1..3, P, B1..3 cc)
-__global__ void __launch_bounds__(kThreads) k_prim(Geo g, double gamma, const double* __restrict__ cons,
+__global__ void __launch_bounds__(kThreads) k_prim(Geo g, double gamma, Floors fl, const double* __restrict__ cons,
                                                   const double* __restrict__ bface, double* __restrict__ w,
                                                   int* __restrict__ bad) {
   const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -29,19 +29,19 @@ __global__ void __launch_bounds__(kThreads) k_prim(Geo g, double gamma, const do
   const double b1 = 0.5 * (fb[g.f(i, j, k)] + fb[g.f(i + 1, j, k)]);
   const double b2 = 0.5 * (fb[g.fvar + g.f(i, j, k)] + fb[g.fvar + g.f(i, j + 1, k)]);
   const double b3 = 0.5 * (fb[2 * g.fvar + g.f(i, j, k)] + fb[2 * g.fvar + g.f(i, j, k + 1)]);
-  const double rho = u[t], ir = 1.0 / rho;
-  const double v1 = u[g.cvar + t] * ir, v2 = u[2 * g.cvar + t] * ir, v3 = u[3 * g.cvar + t] * ir;
-  const double p = (gamma - 1.0) * (u[4 * g.cvar + t] - 0.5 * rho * (v1 * v1 + v2 * v2 + v3 * v3) -
-                                    0.5 * (b1 * b1 + b2 * b2 + b3 * b3));
-  wb[t] = rho;
-  wb[g.cvar + t] = v1;
-  wb[2 * g.cvar + t] = v2;
-  wb[3 * g.cvar + t] = v3;
-  wb[4 * g.cvar + t] = p;
+  const double uc[5] = {u[t], u[g.cvar + t], u[2 * g.cvar + t], u[3 * g.cvar + t], u[4 * g.cvar + t]};
+  const double bc[3] = {b1, b2, b3};
+  double wc[5];
+  const int flags = cell_prim(uc, bc, gamma - 1.0, fl, wc);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) wb[v * g.cvar + t] = wc[v];
   wb[5 * g.cvar + t] = b1;
   wb[6 * g.cvar + t] = b2;
   wb[7 * g.cvar + t] = b3;
-  if (!(rho > 0.0) || !(p > 0.0)) atomicAdd(bad, 1);
+  // ghost cells are periodic images of active ones: count active cells only
+  const bool act = i >= g.ng && i < g.ng + g.n1 && j >= g.ng && j < g.ng + g.n2 && k >= g.ng && k < g.ng + g.n3;
+  if (act && (flags & 1)) atomicAdd(bad, 1);
+  if (act && (flags & 2)) atomicAdd(bad + 1, 1);
 }
 
 template <int RECON>
@@ -71,8 +71,9 @@ __device__ __forceinline__ void recon_pair(const double* __restrict__ q, int s, 
 // Fluxes through the faces normal to D: normal index [ng, ng+n_D], transverse
 // indices [ng-1, ng+n_t] (one extra ring for the corner EMFs).
 template <int D, int RECON, int RS>
-__global__ void __launch_bounds__(kThreads) k_flux(Geo g, Gas gas, double ct_eps, const double* __restrict__ w,
-                                                  const double* __restrict__ bface, double* __restrict__ fo) {
+__global__ void __launch_bounds__(kThreads) k_flux(Geo g, Gas gas, double ct_eps, Floors fl,
+                                                  const double* __restrict__ w, const double* __restrict__ bface,
+                                                  double* __restrict__ fo, int* __restrict__ bad) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   const int e1 = D == 0 ? g.n1 + 1 : g.n1 + 2;
   const int e2 = D == 1 ? g.n2 + 1 : g.n2 + 2;
@@ -98,6 +99,10 @@ __global__ void __launch_bounds__(kThreads) k_flux(Geo g, Gas gas, double ct_eps
   recon_pair<RECON>(wb + (5 + T2) * g.cvar + q, s, L.bt2, R.bt2);
   const int fi = g.f(i, j, k);
   const double bn = fb[D * g.fvar + fi];
+  if (fl.on()) {
+    const int n = floor_state(L, fl) + floor_state(R, fl);
+    if (n) atomicAdd(bad + 1, n);
+  }
   FaceFlux F;
   double smax;
   if (RS == 1) hlld(L, R, bn, gas, F, smax);
@@ -201,38 +206,40 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, StageCoef cf, const 
 }
 
 template <int D, int RECON>
-hipError_t flux_rs(const Geo& g, const Gas& gas, int rs, double ct_eps, const double* w, const double* xb,
-                   double* fo, int nb, hipStream_t s) {
+hipError_t flux_rs(const Geo& g, const Gas& gas, int rs, double ct_eps, const Floors& fl, const double* w,
+                   const double* xb, double* fo, int* bad, int nb, hipStream_t s) {
   const int64_t n = (int64_t)(D == 0 ? g.n1 + 1 : g.n1 + 2) * (D == 1 ? g.n2 + 1 : g.n2 + 2) *
                     (D == 2 ? g.n3 + 1 : g.n3 + 2);
   if (rs == 1)
-    hipLaunchKernelGGL((k_flux<D, RECON, 1>), dim3(grid_for(n), nb), dim3(kThreads), 0, s, g, gas, ct_eps, w, xb, fo);
+    hipLaunchKernelGGL((k_flux<D, RECON, 1>), dim3(grid_for(n), nb), dim3(kThreads), 0, s, g, gas, ct_eps, fl, w, xb,
+                       fo, bad);
   else
-    hipLaunchKernelGGL((k_flux<D, RECON, 0>), dim3(grid_for(n), nb), dim3(kThreads), 0, s, g, gas, ct_eps, w, xb, fo);
+    hipLaunchKernelGGL((k_flux<D, RECON, 0>), dim3(grid_for(n), nb), dim3(kThreads), 0, s, g, gas, ct_eps, fl, w, xb,
+                       fo, bad);
   return hipGetLastError();
 }
 
 template <int D>
-hipError_t flux_dir(const Geo& g, const Gas& gas, int recon, int rs, double ct_eps, const double* w,
-                    const double* xb, double* fo, int nb, hipStream_t s) {
-  if (recon == 0) return flux_rs<D, 0>(g, gas, rs, ct_eps, w, xb, fo, nb, s);
-  if (recon == 1) return flux_rs<D, 1>(g, gas, rs, ct_eps, w, xb, fo, nb, s);
-  return flux_rs<D, 2>(g, gas, rs, ct_eps, w, xb, fo, nb, s);
+hipError_t flux_dir(const Geo& g, const Gas& gas, int recon, int rs, double ct_eps, const Floors& fl, const double* w,
+                    const double* xb, double* fo, int* bad, int nb, hipStream_t s) {
+  if (recon == 0) return flux_rs<D, 0>(g, gas, rs, ct_eps, fl, w, xb, fo, bad, nb, s);
+  if (recon == 1) return flux_rs<D, 1>(g, gas, rs, ct_eps, fl, w, xb, fo, bad, nb, s);
+  return flux_rs<D, 2>(g, gas, rs, ct_eps, fl, w, xb, fo, bad, nb, s);
 }
 
 }  // namespace
 
 hipError_t launch_stage_unfused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
                                 const double* xb, const double* unc, const double* unb, double* outc,
-                                double* outb, StageCoef coef, int nb, UnfusedScratch& scr, int* bad,
-                                hipStream_t s) {
+                                double* outb, StageCoef coef, int nb, UnfusedScratch& scr, const Floors& fl,
+                                int* bad, hipStream_t s) {
   Gas gas{gamma, gamma - 1.0, 1.0 / (gamma - 1.0)};
-  hipLaunchKernelGGL(k_prim, dim3(grid_for(g.cvar), nb), dim3(kThreads), 0, s, g, gamma, xc, xb, scr.w, bad);
+  hipLaunchKernelGGL(k_prim, dim3(grid_for(g.cvar), nb), dim3(kThreads), 0, s, g, gamma, fl, xc, xb, scr.w, bad);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if ((e = flux_dir<0>(g, gas, recon, rs, ct_eps, scr.w, xb, scr.face[0], nb, s)) != hipSuccess) return e;
-  if ((e = flux_dir<1>(g, gas, recon, rs, ct_eps, scr.w, xb, scr.face[1], nb, s)) != hipSuccess) return e;
-  if ((e = flux_dir<2>(g, gas, recon, rs, ct_eps, scr.w, xb, scr.face[2], nb, s)) != hipSuccess) return e;
+  if ((e = flux_dir<0>(g, gas, recon, rs, ct_eps, fl, scr.w, xb, scr.face[0], bad, nb, s)) != hipSuccess) return e;
+  if ((e = flux_dir<1>(g, gas, recon, rs, ct_eps, fl, scr.w, xb, scr.face[1], bad, nb, s)) != hipSuccess) return e;
+  if ((e = flux_dir<2>(g, gas, recon, rs, ct_eps, fl, scr.w, xb, scr.face[2], bad, nb, s)) != hipSuccess) return e;
   const int64_t ne = (int64_t)(g.n1 + 1) * (g.n2 + 1) * (g.n3 + 1);
   hipLaunchKernelGGL(k_corner, dim3(grid_for(ne), nb), dim3(kThreads), 0, s, g, scr.w, scr.face[0], scr.face[1],
                      scr.face[2], scr.edge);

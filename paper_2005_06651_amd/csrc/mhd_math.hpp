@@ -11,6 +11,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "common.hpp"
+
 namespace athmhd {
 
 // Primitive state in the frame of a face: normal direction n, transverse t1, t2
@@ -72,6 +74,40 @@ __device__ __forceinline__ double fsqrt(double x) {
   const double d = fma(-g, g, x);
   g = fma(d, h, g);
   return x > 0.0 ? g : 0.0;
+}
+
+// cons -> prim of one cell: u = (rho, M1, M2, M3, E), b = cell-centred field;
+// w = (rho, v1, v2, v3, P).  Returns bit 0 set for a non-physical cell (rho <= 0,
+// P <= 0 or not finite; with floors on, only a non-finite input) and bit 1 set
+// when a floor acted (rho_W = max(rho, d), v = M / rho_W, P = max(P, p)).
+// Contraction into multiply-adds is off so that every place that converts a
+// cell gets the same bits.
+__device__ __forceinline__ int cell_prim(const double* u, const double* b, double gm1, const Floors& fl,
+                                         double* w) {
+#pragma clang fp contract(off)
+  double rho = u[0];
+  int flags = 0;
+  const bool finite_in = rho == rho && u[4] == u[4] && fabs(rho) < 1.0e300 && fabs(u[4]) < 1.0e300;
+  if (fl.on() && finite_in && !(rho >= fl.d)) {
+    rho = fl.d;
+    flags |= 2;
+  }
+  const double ir = frcp(rho);
+  const double v1 = u[1] * ir, v2 = u[2] * ir, v3 = u[3] * ir;
+  const double ke = v1 * v1 + v2 * v2 + v3 * v3;
+  const double me = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+  double p = gm1 * ((u[4] - 0.5 * rho * ke) - 0.5 * me);
+  if (fl.on() && finite_in && !(p >= fl.p)) {
+    p = fl.p;
+    flags |= 2;
+  }
+  if (!(rho > 0.0) || !(p > 0.0) || !(p < 1.0e300)) flags |= 1;
+  w[0] = rho;
+  w[1] = v1;
+  w[2] = v2;
+  w[3] = v3;
+  w[4] = p;
+  return flags;
 }
 
 // Fast magnetosonic speed along the normal:
@@ -316,6 +352,14 @@ __device__ __forceinline__ double corner_emf(double ea0, double ea1, double eb0,
   const double dap = wb0 * (cb - ea1) + (1.0 - wb0) * (c00 - ea0);
   const double dam = wb1 * (ea1 - cab) + (1.0 - wb1) * (ea0 - ca);
   return avg + 0.25 * (dbm - dbp) + 0.25 * (dam - dap);
+}
+
+// Floors on a reconstructed face state; returns 1 if one acted.
+__device__ __forceinline__ int floor_state(FaceState& s, const Floors& fl) {
+  int acted = 0;
+  if (!(s.rho >= fl.d)) { s.rho = fl.d; acted = 1; }
+  if (!(s.p >= fl.p)) { s.p = fl.p; acted = 1; }
+  return acted;
 }
 
 // upwind weight of a face from its mass flux

@@ -265,10 +265,12 @@ def turbulence(n: int = 256, seed: int = 1, mach: float = 1.0, brms: float = 0.1
 
 
 def blast(n: int = 512, seed: int = 1, gamma: float = 5.0 / 3.0, ng: int = 3, p_amb: float = 0.1,
-          p_in: float = 10.0, radius: float = 0.1) -> Block:
+          p_in: float = 10.0, radius: float = 0.1, edge: float = 0.0) -> Block:
     """MHD blast on the unit periodic cube: rho = 1, p = p_amb, p = p_in where
     the (periodic, minimum-image) distance to a seeded random centre is below
-    radius (sampled at cell centres); uniform B = (1/sqrt2, 1/sqrt2, 0)."""
+    radius (sampled at cell centres); uniform B = (1/sqrt2, 1/sqrt2, 0).
+    edge > 0 replaces the step by p_amb + (p_in - p_amb) (1 - tanh((r - radius)
+    / (edge dx))) / 2, a sphere whose surface is smoothed over ~edge cells."""
     rng = np.random.default_rng(seed)
     c = rng.random(3)
     nn = (n, n, n)
@@ -280,12 +282,15 @@ def blast(n: int = 512, seed: int = 1, gamma: float = 5.0 / 3.0, ng: int = 3, p_
     r2 = d1 ** 2 + d2 ** 2 + d3 ** 2
     prim = np.zeros((5,) + (n + 2 * ng,) * 3)
     prim[0] = 1.0
-    prim[4] = np.where(r2 < radius * radius, p_in, p_amb)
+    if edge > 0.0:
+        prim[4] = p_amb + (p_in - p_amb) * 0.5 * (1.0 - np.tanh((np.sqrt(r2) - radius) / (edge * h)))
+    else:
+        prim[4] = np.where(r2 < radius * radius, p_in, p_amb)
     bf = np.zeros((3,) + (n + 2 * ng + 1,) * 3)
     bf[0] = 1.0 / math.sqrt(2.0)
     bf[1] = 1.0 / math.sqrt(2.0)
     return Block(n=nn, ng=ng, dx=(h, h, h), gamma=gamma, bface=bf, prim=prim,
-                 meta=dict(workload="blast", seed=seed, centre=c.tolist(), cfl=0.3))
+                 meta=dict(workload="blast", seed=seed, centre=c.tolist(), cfl=0.3, edge=edge))
 
 
 def uniform(n=(8, 8, 8), ng=2, rho=1.0, v=(0.3, -0.2, 0.1), p=0.7, B=(0.5, -0.4, 0.3),

@@ -648,3 +648,66 @@ def test_step_jvp_is_derivative_of_step(orc, integ, recon, rs, eps):
     fb = (bp - bm) / (2 * h)
     for got, ref in ((jc[act], fc[act]), (jb[act], fb[act])):
         assert np.max(np.abs(got - ref)) <= 1e-6 * np.max(np.abs(ref))
+
+
+# ---------------------------------------------------------------------------
+# Optional floors act on the primitives only (never on U), so they cannot
+# break conservation, and they are invisible while no floor is reached.
+# ---------------------------------------------------------------------------
+def test_floors_inactive_are_invisible(orc):
+    blk = inputs.smooth_random(n=(10, 8, 6), seed=51, ng=2)
+    res = []
+    for fl in (0.0, 1e-12):
+        cfg = orc.cfg_for(blk, dfloor=fl, pfloor=fl)
+        c = orc.prim2cons(cfg, blk.prim, blk.bface)
+        b = blk.bface.copy()
+        orc.take_floor_count()
+        for _ in range(2):
+            dt, _ = orc.newdt(cfg, c, b)
+            assert orc.step(cfg, c, b, dt) == 0
+        assert orc.take_floor_count() == 0
+        res.append((c, b))
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+
+
+def test_floor_values_in_cons_to_prim(orc):
+    blk = inputs.uniform(n=(4, 4, 4), ng=2, p=0.7)
+    cfg = orc.cfg_for(blk, dfloor=0.5, pfloor=1e-3)
+    cons = orc.prim2cons(orc.cfg_for(blk), blk.prim, blk.bface)
+    g = blk.ng
+    cons[4, g, g, g] -= 10.0       # negative pressure in one cell
+    cons[0, g + 1, g, g] = 0.25    # density below the floor in another
+    cons_before = cons.copy()
+    orc.take_floor_count()
+    prim, _, bad = orc.cons2prim(cfg, cons, blk.bface)
+    assert bad == 0 and orc.take_floor_count() > 0
+    assert prim[4, g, g, g] == 1e-3
+    assert prim[0, g + 1, g, g] == 0.5
+    assert prim[1, g + 1, g, g] == cons[1, g + 1, g, g] / 0.5  # v = M / rho_W
+    assert np.array_equal(cons, cons_before)                    # U untouched
+
+
+def test_floors_keep_conservation_on_a_blast(orc):
+    """The sharp blast needs floors (without them this oracle reaches P <= 0
+    within a few RK3 + PPM steps).  With them, mass and momentum totals stay
+    constant (no density floor is reached here) and the energy total can only
+    grow, by what the pressure floor adds."""
+    blk = inputs.blast(n=24, seed=1)
+    cfg = orc.cfg_for(blk, integrator="rk3", recon="ppm", riemann="hlld", dfloor=1e-10, pfloor=1e-10)
+    c = orc.prim2cons(cfg, blk.prim, blk.bface)
+    b = blk.bface.copy()
+    g, n = blk.ng, 24
+    act = (slice(None), slice(g, g + n), slice(g, g + n), slice(g, g + n))
+    tot0 = c[act].sum(axis=(1, 2, 3))
+    orc.take_floor_count()
+    for _ in range(12):
+        dt, bad = orc.newdt(cfg, c, b)
+        assert bad == 0
+        assert orc.step(cfg, c, b, dt) == 0
+    assert orc.take_floor_count() > 0
+    scale = np.abs(c[act]).sum(axis=(1, 2, 3))
+    tot = c[act].sum(axis=(1, 2, 3))
+    assert np.all(np.abs(tot[:4] - tot0[:4]) <= 1e-13 * scale[:4])
+    assert tot[4] >= tot0[4] - 1e-13 * scale[4]
+    orc.fill_ghosts(cfg, c, b)
+    assert inputs.divb_metric(b, blk.n, blk.ng, blk.dx) <= 1e-13
