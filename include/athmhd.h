@@ -131,17 +131,29 @@ ATHMHD_API int athmhd_fill_ghosts(athmhd_t h, double* cons, double* bface, int n
  *     g_np1 there.
  *   - g_cons_n / g_bface_n may alias g_cons_np1 / g_bface_np1; they must not
  *     alias cons_n / bface_n.
- *   - The stage states are recomputed from (cons_n, bface_n); the library
- *     allocates its reverse-mode scratch on the first call (about 100 doubles
- *     per active cell and block, plus one state per stage beyond the first).
+ *   - stages: NULL, or the stage inputs recorded by athmhd_step_stages for
+ *     this step (cons_n, bface_n, dt); with NULL they are recomputed from
+ *     (cons_n, bface_n).  The library allocates its reverse-mode scratch on
+ *     the first call (about 95 doubles per active cell and block, plus one
+ *     state per stage beyond the first).
  *   - Supported: DC and PLM reconstruction, HLLE and HLLD, all integrators.
  *     The derivative of the CT weight is taken for ct_eps > 0; with ct_eps = 0
  *     the weight is piecewise constant and contributes nothing.  PPM and
  *     batched handles return ATHMHD_EUNSUP.
  * Asynchronous on `stream`. */
 ATHMHD_API int athmhd_step_vjp(athmhd_t h, const double* cons_n, const double* bface_n, double dt,
-                               const double* g_cons_np1, const double* g_bface_np1, double* g_cons_n,
-                               double* g_bface_n, int nblocks, void* stream);
+                               const double* stages, const double* g_cons_np1, const double* g_bface_np1,
+                               double* g_cons_n, double* g_bface_n, int nblocks, void* stream);
+
+/* One step exactly as athmhd_step, that also keeps the inputs of stages
+ * 1..S-1 of the 2S scheme (S = 1, 2, 2, 3 for RK1, VL2, RK2, RK3): they are
+ * written to `stages`, caller-owned device memory of (S-1) states, each the
+ * nblocks cons arrays followed by the nblocks bface arrays (only active cells
+ * and lower faces are defined).  Passing the same buffer as `stages` to
+ * athmhd_step_vjp for this step skips its recomputation of those states.
+ * Uniform handles only.  Asynchronous on `stream`. */
+ATHMHD_API int athmhd_step_stages(athmhd_t h, double* cons, double* bface, double dt, double* stages, int nblocks,
+                                  void* stream);
 
 /* Reverse mode of athmhd_prim2cons on every stored cell: with U = prim2cons(W, B),
  * writes g_prim = (dU/dW)^T g_cons and adds (dU/dB)^T g_cons to g_bface (the

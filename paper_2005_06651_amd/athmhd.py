@@ -8,6 +8,7 @@ library is missing or the device is not a HIP GPU, calls raise.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -20,7 +21,8 @@ INTEGRATOR = {"rk1": 0, "vl2": 1, "rk2": 2, "rk3": 3}
 EXPORTED = ["athmhd_version", "athmhd_create", "athmhd_create_batch", "athmhd_batch_info",
             "athmhd_batch_set_tile", "athmhd_batch_tune", "athmhd_set_graph", "athmhd_step", "athmhd_newdt",
             "athmhd_prim2cons", "athmhd_fill_ghosts", "athmhd_profile", "athmhd_last_error", "athmhd_destroy",
-            "athmhd_step_vjp", "athmhd_prim2cons_vjp", "athmhd_set_floors", "athmhd_floor_count"]
+            "athmhd_step_vjp", "athmhd_prim2cons_vjp", "athmhd_set_floors", "athmhd_floor_count",
+            "athmhd_step_stages"]
 BATCH_TILES = [(16, 8), (8, 16), (14, 14), (8, 8)]  # active columns of the batch tile candidates
 
 
@@ -66,7 +68,8 @@ def lib():
         L.athmhd_newdt.argtypes = [vp, vp, vp, C.c_int, C.POINTER(C.c_double), vp]
         L.athmhd_prim2cons.argtypes = [vp, vp, vp, vp, C.c_int, vp]
         L.athmhd_fill_ghosts.argtypes = [vp, vp, vp, C.c_int, vp]
-        L.athmhd_step_vjp.argtypes = [vp, vp, vp, C.c_double, vp, vp, vp, vp, C.c_int, vp]
+        L.athmhd_step_vjp.argtypes = [vp, vp, vp, C.c_double, vp, vp, vp, vp, vp, C.c_int, vp]
+        L.athmhd_step_stages.argtypes = [vp, vp, vp, C.c_double, vp, C.c_int, vp]
         L.athmhd_set_floors.argtypes = [vp, C.c_double, C.c_double]
         L.athmhd_floor_count.argtypes = [vp, C.POINTER(C.c_longlong), vp]
         L.athmhd_prim2cons_vjp.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int, vp]
@@ -176,12 +179,40 @@ class Solver:
         pc, pb, nb = self._pair(cons, bface)
         _check(lib().athmhd_fill_ghosts(self._h, pc, pb, nb, _stream(stream)), self._h)
 
-    def step_vjp(self, cons, bface, dt: float, g_cons, g_bface, out_cons=None, out_bface=None, stream=None):
+    @property
+    def extra_stages(self) -> int:
+        """Stages of the integrator beyond the first (S - 1)."""
+        return {0: 0, 1: 1, 2: 1, 3: 2}[self.cfg.integrator]
+
+    def stages_like(self, cons):
+        """A buffer for the stage inputs of one step (see step_stages)."""
+        import torch
+        nb = cons.shape[0] if cons.dim() == 5 else 1
+        n1 = 5 * math.prod(self.cell_shape) + 3 * math.prod(self.face_shape)
+        return torch.empty(max(self.extra_stages, 1) * nb * n1, dtype=torch.float64, device=cons.device)
+
+    def step_stages(self, cons, bface, dt: float, stages, stream=None) -> None:
+        """One step in place, also recording its stage inputs into `stages`
+        (from stages_like) for step_vjp."""
+        pc, pb, nb = self._pair(cons, bface)
+        ps = self._flat(stages)
+        _check(lib().athmhd_step_stages(self._h, pc, pb, float(dt), ps, nb, _stream(stream)), self._h)
+
+    def _flat(self, t):
+        import torch
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise TypeError("expected a contiguous float64 tensor in HIP device memory")
+        return C.c_void_p(t.data_ptr())
+
+    def step_vjp(self, cons, bface, dt: float, g_cons, g_bface, out_cons=None, out_bface=None, stages=None,
+                 stream=None):
         """Cotangents of (cons, bface) at the start of a step of size dt, given
         the cotangents (g_cons, g_bface) of its result; out_* may be g_* (in
-        place).  Returns (out_cons, out_bface)."""
+        place); stages: the buffer recorded by step_stages for this step, or
+        None to recompute.  Returns (out_cons, out_bface)."""
         import torch
         pc, pb, nb = self._pair(cons, bface)
+        ps = None if stages is None else self._flat(stages)
         gc, gb, nb2 = self._pair(g_cons, g_bface)
         if out_cons is None:
             out_cons = torch.empty_like(g_cons)
@@ -190,7 +221,7 @@ class Solver:
         oc, ob, nb3 = self._pair(out_cons, out_bface)
         if not nb == nb2 == nb3:
             raise ValueError("state and cotangents hold different block counts")
-        _check(lib().athmhd_step_vjp(self._h, pc, pb, float(dt), gc, gb, oc, ob, nb, _stream(stream)), self._h)
+        _check(lib().athmhd_step_vjp(self._h, pc, pb, float(dt), ps, gc, gb, oc, ob, nb, _stream(stream)), self._h)
         return out_cons, out_bface
 
     def prim2cons_vjp(self, prim, bface, g_cons, g_bface, out_prim=None, stream=None):

@@ -278,8 +278,11 @@ hipError_t fill_ghosts(athmhd_t h, double* cons, double* bface, int nblocks, hip
 
 // The launches of one full step (everything asynchronous on s).  With
 // dt_dev != NULL the stage kernels read dt from the device.
+// stages != NULL (uniform handles): the inputs of stages 1..S-1 are written
+// there (S-1 states, each all blocks' cons then all blocks' bface) instead of
+// the library's registers.
 int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const double* dt_dev, int nblocks,
-                 hipStream_t s) {
+                 hipStream_t s, double* stages = nullptr) {
   const Scheme sc = scheme_of(h->cfg.integrator);
   const double* xc = cons;
   const double* xb = bface;
@@ -296,6 +299,9 @@ int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const doubl
     if (last && xc != cons) {
       oc = cons;
       ob = bface;
+    } else if (stages && !last) {
+      oc = stages + (h->g.cblock + h->g.fblock) * (int64_t)nblocks * st;
+      ob = oc + h->g.cblock * (int64_t)nblocks;
     } else {
       double* r = h->reg[st % 2];
       oc = r;
@@ -694,8 +700,9 @@ int athmhd_step(athmhd_t h, double* cons, double* bface, double dt, int nblocks,
   return replay_step(h, dt, s);
 }
 
-int athmhd_step_vjp(athmhd_t h, const double* cons_n, const double* bface_n, double dt, const double* g_cons_np1,
-                    const double* g_bface_np1, double* g_cons_n, double* g_bface_n, int nblocks, void* stream) {
+int athmhd_step_vjp(athmhd_t h, const double* cons_n, const double* bface_n, double dt, const double* stages,
+                    const double* g_cons_np1, const double* g_bface_np1, double* g_cons_n, double* g_bface_n,
+                    int nblocks, void* stream) {
   int rc = check_call(h, cons_n, bface_n, nblocks);
   if (rc) return rc;
   if (h->batch) return fail(h, ATHMHD_EUNSUP, "reverse mode is available for uniform handles only");
@@ -717,7 +724,13 @@ int athmhd_step_vjp(athmhd_t h, const double* cons_n, const double* bface_n, dou
   // forward: stage inputs X_0 = (cons_n, bface_n), X_1, ..., X_{S-1}
   const double* xc[3] = {cons_n, nullptr, nullptr};
   const double* xb[3] = {bface_n, nullptr, nullptr};
-  for (int st = 0; st + 1 < sc.nstage; ++st) {
+  if (stages) {  // stage inputs recorded by athmhd_step_stages
+    for (int st = 0; st + 1 < sc.nstage; ++st) {
+      xc[st + 1] = stages + (g.cblock + g.fblock) * (int64_t)nblocks * st;
+      xb[st + 1] = xc[st + 1] + g.cblock * (int64_t)nblocks;
+    }
+  }
+  for (int st = 0; !stages && st + 1 < sc.nstage; ++st) {
     double* oc = h->adj_state[st];
     double* ob = oc + g.cblock * (int64_t)nblocks;
     const int recon = (h->cfg.integrator == ATHMHD_VL2 && st == 0) ? ATHMHD_RECON_DC : h->cfg.recon;
@@ -757,6 +770,16 @@ int athmhd_prim2cons_vjp(athmhd_t h, const double* prim, const double* bface, co
   hipError_t e = launch_prim2cons_vjp(h->g, h->cfg.gamma, prim, bface, g_cons, g_prim, g_bface, nblocks,
                                       (hipStream_t)stream);
   return e == hipSuccess ? ATHMHD_OK : hip_fail(h, e, "prim2cons vjp launch");
+}
+
+int athmhd_step_stages(athmhd_t h, double* cons, double* bface, double dt, double* stages, int nblocks,
+                       void* stream) {
+  int rc = check_call(h, cons, bface, nblocks);
+  if (rc) return rc;
+  if (h->batch) return fail(h, ATHMHD_EUNSUP, "stage recording is available for uniform handles only");
+  if (!stages) return fail(h, ATHMHD_EINVAL, "NULL stages");
+  if (!(std::isfinite(dt) && dt > 0.0)) return fail(h, ATHMHD_EINVAL, "dt must be finite and > 0 (got %g)", dt);
+  return enqueue_step(h, cons, bface, dt, nullptr, nblocks, (hipStream_t)stream, stages);
 }
 
 int athmhd_newdt(athmhd_t h, const double* cons, const double* bface, int nblocks, double* dt_host, void* stream) {

@@ -19,9 +19,9 @@
 //                       gathered from the neighbouring cells and edges, then
 //                       the Riemann solver's reverse sweep -> cotangents of
 //                       the reconstructed states and of the normal field
-//   5. k_adj_recon_bwd  per direction: reverse of the reconstruction into
-//                       the primitive cotangents
-//   6. k_adj_cell       cell-EMF cotangents and the reverse of cons -> prim
+//   5-6. k_adj_cell     per cell: reverse of the reconstruction along each
+//                       direction into the primitive cotangents, the
+//                       cell-EMF cotangents and the reverse of cons -> prim
 //   7. k_adj_bface      face-field cotangents (normal field of the Riemann
 //                       problems and the two cell-centred averages)
 // Steps 6 and 7 write the stage's output cotangent O = g0 V + scale J^T V and
@@ -43,12 +43,11 @@ enum : int {
   S_CE = 8,    // 3: cell EMF components
   S_FE = 11,   // 3 x 3: per face direction (EMF of component t1, of t2, weight)
   S_EB = 20,   // 3: corner-EMF cotangents
-  S_LB = 23,   // 7: cotangent of the left state of the faces of one direction
-  S_RB = 30,   // 7: of the right state
-  S_BN = 37,   // 3: cotangent of the normal field of the Riemann problems
-  S_WB = 40,   // 8: primitive cotangents
-  S_BC = 48,   // 3: cotangent of the cell-centred field
-  S_TOTAL = 51
+  S_LB = 23,   // 3 x 7: cotangents of the left states of the faces, per direction
+  S_RB = 44,   // 3 x 7: of the right states
+  S_BN = 65,   // 3: cotangent of the normal field of the Riemann problems
+  S_BC = 68,   // 3: cotangent of the cell-centred field
+  S_TOTAL = 71
 };
 
 struct Adj {
@@ -303,8 +302,8 @@ __global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2))) k_
   const double rb[7] = {Rb.rho, Rb.vn, Rb.vt1, Rb.vt2, Rb.p, Rb.bt1, Rb.bt2};
 #pragma unroll
   for (int m = 0; m < 7; ++m) {
-    s[(S_LB + m) * a.nc + t] = lb[m];
-    s[(S_RB + m) * a.nc + t] = rb[m];
+    s[(S_LB + 7 * D + m) * a.nc + t] = lb[m];
+    s[(S_RB + 7 * D + m) * a.nc + t] = rb[m];
   }
   s[(S_BN + D) * a.nc + t] = bn_b;
 }
@@ -312,25 +311,24 @@ __global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2))) k_
 // ---- 5. reverse of the reconstruction along D ------------------------------
 // Cell c feeds the right state of its lower face (c) and the left state of
 // its upper face (c + D); with PLM it also enters the slopes of c - D, c and
-// c + D.
-// The first direction (D = 0) writes the primitive cotangents, the others
-// add to them; B1cc is not reconstructed along x1 and starts at zero.
+// c + D.  Adds the contributions of direction D to the primitive cotangents.
 template <int D, int RECON>
-__global__ void __launch_bounds__(kT) k_adj_recon_bwd(Adj a, double* __restrict__ scr) {
-  const int t = blockIdx.x * kT + threadIdx.x;
-  if (t >= (int)a.nc) return;
-  double* s = scr + blockIdx.y * (S_TOTAL * a.nc);
-  const Cell c = cell_of(a, t);
+__device__ __forceinline__ void recon_bwd(const Adj& a, const double* __restrict__ s, const Cell& c, double* wb) {
+  const int t = c.t;
   const int cp = at1(a, c, D, 1);
-  if (D == 0) s[(S_WB + 5) * a.nc + t] = 0.0;
+  int cm = 0, cm2 = 0, cp2 = 0;
+  if (RECON == 1) {
+    cm = at1(a, c, D, -1);
+    cm2 = at1(a, c, D, -2);
+    cp2 = at1(a, c, D, 2);
+  }
 #pragma unroll
   for (int m = 0; m < 7; ++m) {
-    const double* lb = s + (S_LB + m) * a.nc;
-    const double* rb = s + (S_RB + m) * a.nc;
+    const double* lb = s + (S_LB + 7 * D + m) * a.nc;
+    const double* rb = s + (S_RB + 7 * D + m) * a.nc;
     double g = rb[t] + lb[cp];
     if (RECON == 1) {
       const double* q = s + (S_W + wslot(D, m)) * a.nc;
-      const int cm = at1(a, c, D, -1), cm2 = at1(a, c, D, -2), cp2 = at1(a, c, D, 2);
       // slope cotangents: delta(x) enters q_L(x + D) with +1/2, q_R(x) with -1/2
       const double dbm = 0.5 * (lb[t] - rb[cm]);    // slope of c - D
       const double db0 = 0.5 * (lb[cp] - rb[t]);    // slope of c
@@ -346,8 +344,8 @@ __global__ void __launch_bounds__(kT) k_adj_recon_bwd(Adj a, double* __restrict_
       vl_slope_vjp(q0, qp, qp2, dbp, x0, x1, x2);  // c is the left point
       g += x0;
     }
-    double& dst = s[(S_WB + wslot(D, m)) * a.nc + t];
-    dst = D == 0 ? g : dst + g;
+    wb[wslot(D, m)] += g;
+    if (RECON == 1) __builtin_amdgcn_sched_barrier(0);  // one variable's loads at a time
   }
 }
 
@@ -369,7 +367,10 @@ __device__ __forceinline__ void stage_out(const StageOut& so, int64_t off, int m
   if (so.Z) so.Z[e] = (so.zfirst ? 0.0 : so.Z[e]) + so.g1 * v;
 }
 
-__global__ void __launch_bounds__(kT) k_adj_cell(Adj a, double* __restrict__ scr, StageOut so) {
+template <int RECON>
+__global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2))) k_adj_cell(Adj a,
+                                                                                        double* __restrict__ scr,
+                                                                                        StageOut so) {
   const int t = blockIdx.x * kT + threadIdx.x;
   if (t >= (int)a.nc) return;
   double* s = scr + blockIdx.y * (S_TOTAL * a.nc);
@@ -378,9 +379,17 @@ __global__ void __launch_bounds__(kT) k_adj_cell(Adj a, double* __restrict__ scr
   double wb[8], w[8];
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
-    wb[m] = s[(S_WB + m) * a.nc + t];
+    wb[m] = 0.0;
     w[m] = s[(S_W + m) * a.nc + t];
   }
+  // one direction at a time: keeps the loads of the three directions from
+  // being hoisted together (register pressure)
+  recon_bwd<0, RECON>(a, s, c, wb);
+  __builtin_amdgcn_sched_barrier(0);
+  recon_bwd<1, RECON>(a, s, c, wb);
+  __builtin_amdgcn_sched_barrier(0);
+  recon_bwd<2, RECON>(a, s, c, wb);
+  __builtin_amdgcn_sched_barrier(0);
   // cell EMF of component e enters the four corner EMFs of component e
   // around it (as c00, ca, cb, cab of the edges at c, c+a, c+b, c+a+b)
 #pragma unroll
@@ -611,11 +620,6 @@ void face_dir(const Adj& a, int recon, int rs, dim3 grid, const double* xb, cons
   else face_pair<D, 1>(a, rs, grid, xb, V, scr, s, bwd);
 }
 
-template <int D>
-void recon_dir(const Adj& a, int recon, dim3 grid, double* scr, hipStream_t s) {
-  if (recon == 0) hipLaunchKernelGGL((k_adj_recon_bwd<D, 0>), grid, dim3(kT), 0, s, a, scr);
-  else hipLaunchKernelGGL((k_adj_recon_bwd<D, 1>), grid, dim3(kT), 0, s, a, scr);
-}
 
 }  // namespace
 
@@ -632,13 +636,11 @@ hipError_t launch_stage_vjp(const Geo& g, double gamma, int recon, int rs, doubl
   face_dir<1>(a, recon, rs, grid, xb, V, scr, s, false);
   face_dir<2>(a, recon, rs, grid, xb, V, scr, s, false);
   face_dir<0>(a, recon, rs, grid, xb, V, scr, s, true);
-  recon_dir<0>(a, recon, grid, scr, s);
   face_dir<1>(a, recon, rs, grid, xb, V, scr, s, true);
-  recon_dir<1>(a, recon, grid, scr, s);
   face_dir<2>(a, recon, rs, grid, xb, V, scr, s, true);
-  recon_dir<2>(a, recon, grid, scr, s);
   const StageOut so{V, O, Z, g0, g1, scale, zfirst};
-  hipLaunchKernelGGL(k_adj_cell, grid, dim3(kT), 0, s, a, scr, so);
+  if (recon == 0) hipLaunchKernelGGL((k_adj_cell<0>), grid, dim3(kT), 0, s, a, scr, so);
+  else hipLaunchKernelGGL((k_adj_cell<1>), grid, dim3(kT), 0, s, a, scr, so);
   hipLaunchKernelGGL(k_adj_bface, grid, dim3(kT), 0, s, a, scr, so);
   return hipGetLastError();
 }

@@ -6,8 +6,9 @@ reverse mode (athmhd_step_vjp) step by step from the last step to the first.
 Memory follows step checkpointing: the forward pass keeps the state at the
 start of every segment of `seg` steps (ceil(nsteps / ncheck) with ncheck
 checkpoints, sqrt(nsteps) by default); backward recomputes the states inside
-one segment at a time from its checkpoint, so at most ncheck + seg states are
-held.  `Prim2Cons` is prim -> cons with its reverse mode (athmhd_prim2cons_vjp),
+one segment at a time from its checkpoint (keeping each step's stage inputs,
+so the reverse steps do not recompute them), so at most ncheck + seg states
+(and their stage inputs) are held.  `Prim2Cons` is prim -> cons with its reverse mode (athmhd_prim2cons_vjp),
 so gradients can be taken with respect to primitive variables.
 
 Both functions only sequence library calls: every arithmetic step runs in
@@ -50,13 +51,22 @@ class Rollout(torch.autograd.Function):
         gb = torch.zeros_like(like_b) if g_bface is None else g_bface.detach().clone().contiguous()
         for s0, c0, b0 in reversed(ctx.checkpoints):
             s1 = min(s0 + seg, ctx.nsteps)
-            states = [(c0, b0)]
+            # recompute the segment, keeping every step's start state and its
+            # stage inputs (so the reverse step does not recompute them)
+            states = []
             c, b = c0.clone(), b0.clone()
-            for _ in range(s0, s1 - 1):
-                solver.step(c, b, dt)
-                states.append((c.clone(), b.clone()))
-            for cs, bs in reversed(states):
-                solver.step_vjp(cs, bs, dt, gc, gb, out_cons=gc, out_bface=gb)
+            for q in range(s0, s1):
+                cs, bs = c.clone(), b.clone()
+                st = None
+                if q < s1 - 1:  # the last step's stages are recomputed by step_vjp
+                    if solver.extra_stages:
+                        st = solver.stages_like(c)
+                        solver.step_stages(c, b, dt, st)
+                    else:
+                        solver.step(c, b, dt)
+                states.append((cs, bs, st))
+            for cs, bs, st in reversed(states):
+                solver.step_vjp(cs, bs, dt, gc, gb, out_cons=gc, out_bface=gb, stages=st)
             del states
         ctx.checkpoints = None
         return gc, gb, None, None, None, None

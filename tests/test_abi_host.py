@@ -77,7 +77,8 @@ def test_calls_reject_null_handle():
     assert L.athmhd_newdt(None, None, None, 1, C.byref(out), None) == athmhd.EINVAL
     assert L.athmhd_fill_ghosts(None, None, None, 1, None) == athmhd.EINVAL
     assert L.athmhd_prim2cons(None, None, None, None, 1, None) == athmhd.EINVAL
-    assert L.athmhd_step_vjp(None, None, None, 0.1, None, None, None, None, 1, None) == athmhd.EINVAL
+    assert L.athmhd_step_vjp(None, None, None, 0.1, None, None, None, None, None, 1, None) == athmhd.EINVAL
+    assert L.athmhd_step_stages(None, None, None, 0.1, None, 1, None) == athmhd.EINVAL
     assert L.athmhd_prim2cons_vjp(None, None, None, None, None, None, 1, None) == athmhd.EINVAL
     L.athmhd_destroy(None)
 

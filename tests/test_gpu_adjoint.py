@@ -158,6 +158,36 @@ def test_multi_block_vjp_equals_single_blocks(torch_dev, athmhd, orc):
     s1.close()
 
 
+@pytest.mark.parametrize("integ", ["vl2", "rk3", "rk1"])
+def test_recorded_stages_give_the_same_vjp(torch_dev, athmhd, orc, integ):
+    """step_stages records the stage inputs; step_vjp with them equals
+    step_vjp recomputing them, bitwise, and step_stages advances the state
+    exactly like step."""
+    torch, dev = torch_dev
+    blk = inputs.smooth_random(n=(20, 14, 9), seed=28, ng=2)
+    kw = dict(integrator=integ, recon="plm", riemann="hlld", ct_eps=1e-3)
+    cfg = orc.cfg_for(blk, **kw)
+    cons = orc.prim2cons(cfg, blk.prim, blk.bface)
+    s = athmhd.Solver(blk.n, blk.ng, blk.dx, blk.gamma, **kw)
+    tc = torch.from_numpy(cons).to(dev)
+    tb = torch.from_numpy(blk.bface).to(dev)
+    dt = s.newdt(tc, tb)
+    mc, mb = active_masks(blk.n, blk.ng)
+    rng = np.random.default_rng(13)
+    wc, wb = random_active(rng, mc, mb)
+    twc, twb = torch.from_numpy(wc).to(dev), torch.from_numpy(wb).to(dev)
+    g0 = s.step_vjp(tc, tb, dt, twc, twb)
+    st = s.stages_like(tc)
+    c2, b2 = tc.clone(), tb.clone()
+    s.step_stages(c2, b2, dt, st)
+    c3, b3 = tc.clone(), tb.clone()
+    s.step(c3, b3, dt)
+    assert torch.equal(c2, c3) and torch.equal(b2, b3)
+    g1 = s.step_vjp(tc, tb, dt, twc, twb, stages=st if s.extra_stages else None)
+    assert torch.equal(g0[0], g1[0]) and torch.equal(g0[1], g1[1])
+    s.close()
+
+
 def test_prim2cons_vjp_by_differences(torch_dev, athmhd, orc):
     """prim -> cons is a cubic polynomial along any line, so a central
     difference with a small step is exact up to rounding."""
