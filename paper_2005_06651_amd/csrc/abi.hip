@@ -47,7 +47,6 @@ struct athmhd_s {
   double* d_dtval = nullptr;              // dt of the step on the device (graph replay)
   void* h_pinned = nullptr;               // 16 bytes of pinned host memory for newdt
   int kz = 0;                             // x3 planes per fused workgroup (0: default)
-  int occ = 2;                            // register target of the fused kernel (waves per SIMD)
   // kernel timing
   bool profiling = false;
   std::vector<hipEvent_t> events;  // (start, stop) pairs around stage kernels
@@ -215,7 +214,6 @@ bool alloc_common(athmhd_t h) {
 
 void read_env(athmhd_t h) {
   if (const char* kz = getenv("ATHMHD_KZ")) h->kz = atoi(kz);
-  if (const char* oc = getenv("ATHMHD_OCC")) h->occ = atoi(oc) == 1 ? 1 : 2;
 }
 
 // ---- batched blocks: work items of one tile candidate ---------------------
@@ -266,7 +264,7 @@ hipError_t launch_stage(athmhd_t h, int recon, const double* xc, const double* x
                               h->d_bad, s);
   if (h->cfg.kernel_path == 0)
     return launch_stage_fused(h->g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc, xb, unc, unb, oc, ob, cf,
-                              dt_dev, beta, nblocks, h->kz, h->occ, h->floors, h->d_bad, s);
+                              dt_dev, beta, nblocks, h->kz, h->floors, h->d_bad, s);
   return launch_stage_unfused(h->g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc, xb, unc, unb, oc, ob,
                               cf, nblocks, h->scr, h->floors, h->d_bad, s);
 }
@@ -736,7 +734,7 @@ int athmhd_step_vjp(athmhd_t h, const double* cons_n, const double* bface_n, dou
     const int recon = (h->cfg.integrator == ATHMHD_VL2 && st == 0) ? ATHMHD_RECON_DC : h->cfg.recon;
     const StageCoef cf{sc.g0[st], sc.g1[st], sc.beta[st] * dt};
     e = launch_stage_fused(g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc[st], xb[st], cons_n, bface_n,
-                           oc, ob, cf, nullptr, sc.beta[st], nblocks, h->kz, h->occ, h->floors, h->d_bad, s);
+                           oc, ob, cf, nullptr, sc.beta[st], nblocks, h->kz, h->floors, h->d_bad, s);
     if (e != hipSuccess) return hip_fail(h, e, "vjp forward stage launch");
     xc[st + 1] = oc;
     xb[st + 1] = ob;

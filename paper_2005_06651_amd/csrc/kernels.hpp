@@ -34,14 +34,13 @@ hipError_t launch_stage_unfused(const Geo& g, double gamma, int recon, int rs, d
                                 int* bad, hipStream_t s);
 
 // One stage in a single fused kernel (same contract as launch_stage_unfused);
-// kz = x3 planes per workgroup segment (0: default for the block size);
-// occ = register-allocation target in waves per SIMD (1 or 2).
+// kz = x3 planes per workgroup segment (0: default for the block size).
 // dt_dev, if not NULL, supplies dt on the device (bdt = beta * dt).
 // bad[0] counts threads that met a non-physical cell, bad[1] floor activations.
 hipError_t launch_stage_fused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
                               const double* xb, const double* unc, const double* unb, double* outc, double* outb,
-                              StageCoef coef, const double* dt_dev, double beta, int nb, int kz, int occ, Floors fl,
-                              int* bad, hipStream_t s);
+                              StageCoef coef, const double* dt_dev, double beta, int nb, int kz, Floors fl, int* bad,
+                              hipStream_t s);
 int fused_default_kz(const Geo& g);
 
 // Batched blocks of uneven sizes.  One block descriptor per block: its

@@ -141,6 +141,7 @@ __device__ __forceinline__ void load_raw(const Geo& g, const double* __restrict_
 // Fluxes and EMFs on tile and segment boundaries are computed twice and must
 // agree exactly, or the CT update no longer preserves div B (reconstruction
 // limiters can turn an ulp of difference into an O(1) one).
+template <bool FL>
 __device__ __forceinline__ int to_prim(const Raw& r, double gm1, const Floors& fl, double* w) {
   double b[3];
   {
@@ -149,7 +150,7 @@ __device__ __forceinline__ int to_prim(const Raw& r, double gm1, const Floors& f
     b[1] = 0.5 * (r.b2lo + r.b2hi);
     b[2] = 0.5 * (r.b3lo + r.b3hi);
   }
-  const int flags = cell_prim(r.u, b, gm1, fl, w);
+  const int flags = cell_prim(r.u, b, gm1, FL ? fl : Floors{0.0, 0.0}, w);
   w[5] = b[0];
   w[6] = b[1];
   w[7] = b[2];
@@ -187,11 +188,11 @@ __device__ __forceinline__ FaceState make_state(const double* q) {
   return s;
 }
 
-template <int RS>
+template <int RS, bool FL>
 __device__ __forceinline__ void riemann(const double* ql, const double* qr, double bn, const Gas& gas, double ct_eps,
                                         const Floors& fl, int& nfl, FaceFlux& F, double& w) {
   FaceState L = make_state(ql), R = make_state(qr);
-  if (fl.on()) nfl += floor_state(L, fl) + floor_state(R, fl);
+  if (FL) nfl += floor_state(L, fl) + floor_state(R, fl);
   double smax;
   if (RS == 1) hlld(L, R, bn, gas, F, smax);
   else hlle(L, R, bn, gas, F, smax);
@@ -213,7 +214,7 @@ enum {
 };
 
 // One tile (tile_x, tile_y) of a block over the active planes [k0, kend).
-template <int RECON, int RS, class T>
+template <int RECON, int RS, class T, bool FL>
 __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, const StageArgs& sa, int tile_x,
                                            int tile_y, int k0, int kend, double* __restrict__ sp,
                                            double* __restrict__ sx, double* __restrict__ sc) {
@@ -276,7 +277,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
 #pragma unroll
     for (int o = 0; o < NW - 1; ++o) {
       load_raw(g, xc, xb, own, k0 - 1 - LA + o, raw);
-      const int f = to_prim(raw, gm1, sa.fl, w);
+      const int f = to_prim<FL>(raw, gm1, sa.fl, w);
       nbad += f & 1;
       nfl += f >> 1;
       to_zcell(w, win[o + 1]);
@@ -305,7 +306,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
     for (int o = 0; o < NW - 1; ++o) win[o] = win[o + 1];
     {
       double w[8];
-      const int f = to_prim(pre, gm1, sa.fl, w);
+      const int f = to_prim<FL>(pre, gm1, sa.fl, w);
       nbad += f & 1;
       nfl += f >> 1;
       to_zcell(w, win[NW - 1]);
@@ -342,7 +343,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
     // ---- 4. ring cells to LDS
     if (ring) {
       double w[8];
-      to_prim(rpre, gm1, sa.fl, w);
+      to_prim<FL>(rpre, gm1, sa.fl, w);
 #pragma unroll
       for (int v = 0; v < 8; ++v) sp[v * PL + rl] = w[v];
     }
@@ -367,7 +368,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
       if (zface) {
         const double bn3 = bnq[0][2];
         FaceFlux fz;
-        riemann<RS>(zl, zr, bn3, sa.gas, sa.ct_eps, sa.fl, nfl, fz, wz);
+        riemann<RS, FL>(zl, zr, bn3, sa.gas, sa.ct_eps, sa.fl, nfl, fz, wz);
         // z-frame -> (rho, M1, M2, M3, E); x3-face E2 = -F(B1), E1 = +F(B2)
         fz_cons[0] = fz.rho; fz_cons[1] = fz.mt1; fz_cons[2] = fz.mt2; fz_cons[3] = fz.mn; fz_cons[4] = fz.e;
         e2z = -fz.bt1;
@@ -405,7 +406,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
         }
         const double bn1 = bnq[0][0];
         FaceFlux fx;
-        riemann<RS>(ql, qr, bn1, sa.gas, sa.ct_eps, sa.fl, nfl, fx, wx);
+        riemann<RS, FL>(ql, qr, bn1, sa.gas, sa.ct_eps, sa.fl, nfl, fx, wx);
         sx[(X_FX + 0) * NT + tid] = fx.rho;
         sx[(X_FX + 1) * NT + tid] = fx.mn;   // M1
         sx[(X_FX + 2) * NT + tid] = fx.mt1;  // M2
@@ -442,7 +443,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
         }
         const double bn2 = bnq[0][1];
         FaceFlux fy;
-        riemann<RS>(ql, qr, bn2, sa.gas, sa.ct_eps, sa.fl, nfl, fy, wy);
+        riemann<RS, FL>(ql, qr, bn2, sa.gas, sa.ct_eps, sa.fl, nfl, fy, wy);
         sx[(X_FY + 0) * NT + tid] = fy.rho;
         sx[(X_FY + 1) * NT + tid] = fy.mt2;  // M1
         sx[(X_FY + 2) * NT + tid] = fy.mn;   // M2
@@ -570,8 +571,8 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
 // Uniform blocks: one workgroup per (tile, x3 segment, block), XCD-aware:
 // consecutive logical tiles land on the same XCD so that halo overlap hits its
 // L2.
-template <int RECON, int RS, int OCC>
-__global__ void __launch_bounds__(TileU::NT) __attribute__((amdgpu_waves_per_eu(OCC)))
+template <int RECON, int RS, bool FL>
+__global__ void __launch_bounds__(TileU::NT) __attribute__((amdgpu_waves_per_eu(2)))
 k_stage_fused(UniformArgs a) {
   using T = TileU;
   using S = Smem<RECON, T>;
@@ -591,12 +592,12 @@ k_stage_fused(UniformArgs a) {
                a.unb + blk * g.fblock, a.oc + blk * g.cblock, a.ob + blk * g.fblock};
   const int k0 = g.ng + seg * a.kz;
   const int kend = min(k0 + a.kz, g.ng + g.n3);
-  stage_tile<RECON, RS, T>(g, bp, a.sa, tile_x, tile_y, k0, kend, sp, sx, sc);
+  stage_tile<RECON, RS, T, FL>(g, bp, a.sa, tile_x, tile_y, k0, kend, sp, sx, sc);
 }
 
 // Batched blocks of uneven sizes: a persistent grid whose workgroups pull
 // (block, tile, x3 segment) items from a device queue until it is drained.
-template <int RECON, int RS, class T>
+template <int RECON, int RS, class T, bool FL>
 __global__ void __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(2))) k_stage_batch(BatchArgs a) {
   using S = Smem<RECON, T>;
   __shared__ double sp[8 * S::PL];
@@ -612,22 +613,20 @@ __global__ void __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(2)))
     const WorkItem w = a.items[it];
     const BatchDesc& d = a.desc[w.block];
     BlockPtrs bp{a.xc + d.coff, a.xb + d.foff, a.unc + d.coff, a.unb + d.foff, a.oc + d.coff, a.ob + d.foff};
-    stage_tile<RECON, RS, T>(d.g, bp, a.sa, w.tile_x, w.tile_y, w.k0, w.kend, sp, sx, sc);
+    stage_tile<RECON, RS, T, FL>(d.g, bp, a.sa, w.tile_x, w.tile_y, w.k0, w.kend, sp, sx, sc);
     __syncthreads();
   }
 }
 
 template <int RECON>
-hipError_t launch_rs(int rs, int occ, const UniformArgs& fa, hipStream_t s) {
+hipError_t launch_rs(int rs, const UniformArgs& fa, hipStream_t s) {
   const unsigned grid = (unsigned)(8 * fa.per_xcd);
   constexpr int NT = TileU::NT;
-  if (occ == 2) {
-    if (rs == 1) hipLaunchKernelGGL((k_stage_fused<RECON, 1, 2>), dim3(grid), dim3(NT), 0, s, fa);
-    else hipLaunchKernelGGL((k_stage_fused<RECON, 0, 2>), dim3(grid), dim3(NT), 0, s, fa);
-  } else {
-    if (rs == 1) hipLaunchKernelGGL((k_stage_fused<RECON, 1, 1>), dim3(grid), dim3(NT), 0, s, fa);
-    else hipLaunchKernelGGL((k_stage_fused<RECON, 0, 1>), dim3(grid), dim3(NT), 0, s, fa);
-  }
+  const bool fl = fa.sa.fl.on();
+  if (rs == 1 && fl) hipLaunchKernelGGL((k_stage_fused<RECON, 1, true>), dim3(grid), dim3(NT), 0, s, fa);
+  else if (rs == 1) hipLaunchKernelGGL((k_stage_fused<RECON, 1, false>), dim3(grid), dim3(NT), 0, s, fa);
+  else if (fl) hipLaunchKernelGGL((k_stage_fused<RECON, 0, true>), dim3(grid), dim3(NT), 0, s, fa);
+  else hipLaunchKernelGGL((k_stage_fused<RECON, 0, false>), dim3(grid), dim3(NT), 0, s, fa);
   return hipGetLastError();
 }
 
@@ -637,8 +636,11 @@ __global__ void k_zero_u32(unsigned* p) {
 
 template <class T, int RECON>
 hipError_t launch_batch_t(int rs, const BatchArgs& ba, int grid, hipStream_t s) {
-  if (rs == 1) hipLaunchKernelGGL((k_stage_batch<RECON, 1, T>), dim3(grid), dim3(T::NT), 0, s, ba);
-  else hipLaunchKernelGGL((k_stage_batch<RECON, 0, T>), dim3(grid), dim3(T::NT), 0, s, ba);
+  const bool fl = ba.sa.fl.on();
+  if (rs == 1 && fl) hipLaunchKernelGGL((k_stage_batch<RECON, 1, T, true>), dim3(grid), dim3(T::NT), 0, s, ba);
+  else if (rs == 1) hipLaunchKernelGGL((k_stage_batch<RECON, 1, T, false>), dim3(grid), dim3(T::NT), 0, s, ba);
+  else if (fl) hipLaunchKernelGGL((k_stage_batch<RECON, 0, T, true>), dim3(grid), dim3(T::NT), 0, s, ba);
+  else hipLaunchKernelGGL((k_stage_batch<RECON, 0, T, false>), dim3(grid), dim3(T::NT), 0, s, ba);
   return hipGetLastError();
 }
 
@@ -668,8 +670,8 @@ static StageArgs make_stage_args(double gamma, double ct_eps, StageCoef coef, co
 
 hipError_t launch_stage_fused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
                               const double* xb, const double* unc, const double* unb, double* outc, double* outb,
-                              StageCoef coef, const double* dt_dev, double beta, int nb, int kz, int occ, Floors fl,
-                              int* bad, hipStream_t s) {
+                              StageCoef coef, const double* dt_dev, double beta, int nb, int kz, Floors fl, int* bad,
+                              hipStream_t s) {
   UniformArgs fa;
   fa.g = g;
   fa.sa = make_stage_args(gamma, ct_eps, coef, dt_dev, beta, fl, bad);
@@ -680,9 +682,9 @@ hipError_t launch_stage_fused(const Geo& g, double gamma, int recon, int rs, dou
   fa.nseg = (g.n3 + fa.kz - 1) / fa.kz;
   fa.total = (int64_t)fa.ntx * fa.nty * fa.nseg * nb;
   fa.per_xcd = (fa.total + 7) / 8;
-  if (recon == 0) return launch_rs<0>(rs, occ, fa, s);
-  if (recon == 1) return launch_rs<1>(rs, occ, fa, s);
-  return launch_rs<2>(rs, occ, fa, s);
+  if (recon == 0) return launch_rs<0>(rs, fa, s);
+  if (recon == 1) return launch_rs<1>(rs, fa, s);
+  return launch_rs<2>(rs, fa, s);
 }
 
 int batch_tile_count() { return 4; }
