@@ -322,7 +322,15 @@ __device__ __forceinline__ void ppm_cell(double qa, double qb, double qc, double
     const double m = fmin(fabs(d2), fmin(C * fabs(d2l), fmin(C * fabs(d2r), C * fabs(d2c))));
     const double lim = pos ? m : (neg ? -m : 0.0);
     if (d2 != 0.0) {
-      const double r = lim * frcp(d2);
+      // lim and d2 share their sign and |lim| <= |d2|, so r is in [0, 1].  A
+      // tiny d2 (denormal, as in the decaying precursor ahead of a blast wave)
+      // has no finite reciprocal: scale both by a power of two first (exact).
+      double num = lim, den = d2;
+      if (fabs(den) < 0x1p-900) {
+        num *= 0x1p900;
+        den *= 0x1p900;
+      }
+      const double r = num * frcp(den);
       qm = qc + (qm - qc) * r;
       qp = qc + (qp - qc) * r;
     } else {

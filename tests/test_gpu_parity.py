@@ -471,3 +471,37 @@ def test_sharp_blast_runs_with_floors(torch_dev, athmhd, orc):
     s.fill_ghosts(tc, tb)
     assert inputs.divb_metric(tb.cpu().numpy(), b.n, b.ng, b.dx) <= 1e-13
     s.close()
+
+
+def test_ppm_with_denormal_precursor_matches_oracle(torch_dev, athmhd, orc):
+    """Velocities that decay across the block from O(1) to below the smallest
+    normal double (as in the numerical precursor ahead of a blast wave): the
+    PPM limiter meets second differences that are denormal, whose reciprocal
+    is not finite; the GPU must stay finite and match the oracle.  One RK1
+    step: after it the velocities are dominated by the new pressure-driven
+    flow, whose PPM stages are rounding sensitive in the oracle itself (the
+    oracle perturbed by 1e-15 moves by 1e-5, R-29); the first stage is not."""
+    torch, dev = torch_dev
+    b = inputs.smooth_random(n=(40, 12, 10), seed=29, ng=3, vmax=0.3)
+    g, n1 = b.ng, 40
+    x = np.arange(b.prim.shape[-1]) - g
+    # 1 down to ~1e-315 (denormal, never exactly 0: an exactly flat plateau
+    # would put ties into the PPM extremum test)
+    decay = np.exp(-np.clip(x, 0, n1 - 1) * (725.0 / (n1 - 1)))
+    prim = b.prim.copy()
+    prim[1:4] *= decay[None, None, None, :]
+    # where the velocity is tiny, PPM's accurate face states make the mass
+    # flux zero up to rounding: continuous CT weight, as in the blast test
+    kw = dict(integrator="rk1", recon="ppm", riemann="hlld", ct_eps=1e-8)
+    s, cfg = make_pair(athmhd, orc, b, **kw)
+    cons = orc.prim2cons(cfg, prim, b.bface)
+    tc, tb = to_dev(torch, dev, cons), to_dev(torch, dev, b.bface)
+    rc, rb = cons.copy(), b.bface.copy()
+    dt, bad = orc.newdt(cfg, rc, rb)
+    assert bad == 0
+    assert orc.step(cfg, rc, rb, dt) == 0
+    s.step(tc, tb, dt)
+    assert torch.isfinite(tc).all() and torch.isfinite(tb).all()
+    err = rel_l1(b, tc.cpu().numpy(), tb.cpu().numpy(), rc, rb)
+    assert err <= TOL, err
+    s.close()
