@@ -44,10 +44,11 @@ struct StageCoef {
   double g0, g1, bdt;
 };
 
-// Optional floors on the primitive variables (0 disables each).  They limit
-// density and pressure from below in the primitives only -- cell values and
-// reconstructed face states -- and never modify the conserved variables, so
-// the update stays conservative.
+// Optional density and pressure floors (0 disables each).  The primitives
+// taken from a cell or reconstructed on a face are limited from below, and a
+// separate pass after each stage raises the stored density and total energy
+// of a cell that fell below them; that pass is the only change the floors make
+// to the conserved variables.
 struct Floors {
   double d, p;
   __host__ __device__ bool on() const { return d > 0.0 || p > 0.0; }
