@@ -182,7 +182,7 @@ ATHMHD_API int athmhd_create_batch(const athmhd_config* base, const int32_t* dim
 ATHMHD_API int athmhd_batch_info(athmhd_t h, int64_t* cons_len, int64_t* bface_len, int64_t* offsets);
 
 /* Choose the thread tile of the batched stage kernel: shape indexes the
- * candidate tiles (0: 16x8, 1: 8x16, 2: 14x14, 3: 8x8 active columns) and
+ * candidate tiles (0: 16x12, 1: 12x16, 2: 14x14, 3: 16x8 active columns) and
  * split = 1 halves the x3 extent of each work item. */
 ATHMHD_API int athmhd_batch_set_tile(athmhd_t h, int shape, int split);
 

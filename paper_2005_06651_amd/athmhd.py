@@ -23,7 +23,7 @@ EXPORTED = ["athmhd_version", "athmhd_create", "athmhd_create_batch", "athmhd_ba
             "athmhd_prim2cons", "athmhd_fill_ghosts", "athmhd_profile", "athmhd_last_error", "athmhd_destroy",
             "athmhd_step_vjp", "athmhd_prim2cons_vjp", "athmhd_set_floors", "athmhd_floor_count",
             "athmhd_step_stages"]
-BATCH_TILES = [(16, 8), (8, 16), (14, 14), (8, 8)]  # active columns of the batch tile candidates
+BATCH_TILES = [(16, 12), (12, 16), (14, 14), (16, 8)]  # active columns of the batch tile candidates
 
 
 class AthmhdError(RuntimeError):
