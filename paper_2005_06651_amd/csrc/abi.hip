@@ -47,6 +47,7 @@ struct athmhd_s {
   double* d_dtval = nullptr;              // dt of the step on the device (graph replay)
   void* h_pinned = nullptr;               // 16 bytes of pinned host memory for newdt
   int kz = 0;                             // x3 planes per fused workgroup (0: default)
+  int cus = 0;                            // compute units of the device
   // kernel timing
   bool profiling = false;
   std::vector<hipEvent_t> events;  // (start, stop) pairs around stage kernels
@@ -254,6 +255,9 @@ int build_items(athmhd_t h, int shape, int split) {
   return ATHMHD_OK;
 }
 
+// x3 planes per workgroup of the fused stage kernel on nblocks uniform blocks
+int stage_kz(athmhd_t h, int nblocks) { return h->kz > 0 ? h->kz : fused_default_kz(h->g, nblocks, h->cus); }
+
 // One stage: uniform or batched, fused or unfused.
 hipError_t launch_stage(athmhd_t h, int recon, const double* xc, const double* xb, const double* unc,
                         const double* unb, double* oc, double* ob, StageCoef cf, double beta, const double* dt_dev,
@@ -264,7 +268,7 @@ hipError_t launch_stage(athmhd_t h, int recon, const double* xc, const double* x
                               h->d_bad, s);
   if (h->cfg.kernel_path == 0)
     return launch_stage_fused(h->g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc, xb, unc, unb, oc, ob, cf,
-                              dt_dev, beta, nblocks, h->kz, h->floors, h->d_bad, s);
+                              dt_dev, beta, nblocks, stage_kz(h, nblocks), h->floors, h->d_bad, s);
   return launch_stage_unfused(h->g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc, xb, unc, unb, oc, ob,
                               cf, nblocks, h->scr, h->floors, h->d_bad, s);
 }
@@ -431,8 +435,9 @@ int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
   h->nbmax = nblocks_max;
   read_env(h);
   hipError_t e = hipGetDevice(&h->device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, h->device);
   if (e != hipSuccess) {
-    rc = fail(nullptr, ATHMHD_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    rc = fail(nullptr, ATHMHD_EHIP, "device query: %s", hipGetErrorString(e));
     delete h;
     return rc;
   }
@@ -734,7 +739,7 @@ int athmhd_step_vjp(athmhd_t h, const double* cons_n, const double* bface_n, dou
     const int recon = (h->cfg.integrator == ATHMHD_VL2 && st == 0) ? ATHMHD_RECON_DC : h->cfg.recon;
     const StageCoef cf{sc.g0[st], sc.g1[st], sc.beta[st] * dt};
     e = launch_stage_fused(g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc[st], xb[st], cons_n, bface_n,
-                           oc, ob, cf, nullptr, sc.beta[st], nblocks, h->kz, h->floors, h->d_bad, s);
+                           oc, ob, cf, nullptr, sc.beta[st], nblocks, stage_kz(h, nblocks), h->floors, h->d_bad, s);
     if (e != hipSuccess) return hip_fail(h, e, "vjp forward stage launch");
     xc[st + 1] = oc;
     xb[st + 1] = ob;

@@ -40,8 +40,8 @@ hipError_t launch_stage_unfused(const Geo& g, double gamma, int recon, int rs, d
 hipError_t launch_stage_fused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
                               const double* xb, const double* unc, const double* unb, double* outc, double* outb,
                               StageCoef coef, const double* dt_dev, double beta, int nb, int kz, Floors fl, int* bad,
-                              hipStream_t s);
-int fused_default_kz(const Geo& g);
+                              hipStream_t s);  // kz > 0: x3 planes per workgroup
+int fused_default_kz(const Geo& g, int nb, int cus);
 
 // Batched blocks of uneven sizes.  One block descriptor per block: its
 // geometry and the offsets (in doubles) of its cons and bface in the

@@ -657,7 +657,15 @@ hipError_t launch_batch_recon(int recon, int rs, const BatchArgs& ba, int grid, 
 
 }  // namespace
 
-int fused_default_kz(const Geo& g) { return g.n3 >= 64 ? 32 : (g.n3 >= 16 ? 16 : g.n3); }
+int fused_default_kz(const Geo& g, int nb, int cus) {
+  // the longest x3 segment (32 planes down to 4) that still gives the launch
+  // at least 2.5 workgroups per CU: longer segments repeat less of the
+  // window start-up, more segments fill the chip on small blocks
+  const int64_t tiles = (int64_t)((g.n1 + TileU::TX - 1) / TileU::TX) * ((g.n2 + TileU::TY - 1) / TileU::TY) * nb;
+  int kz = 32;
+  while (kz > 4 && 2 * tiles * ((g.n3 + kz - 1) / kz) < 5 * (int64_t)cus) kz /= 2;
+  return kz < g.n3 ? kz : g.n3;
+}
 
 static StageArgs make_stage_args(double gamma, double ct_eps, StageCoef coef, const double* dt_dev, double beta,
                                  Floors fl, int* bad) {
@@ -680,7 +688,7 @@ hipError_t launch_stage_fused(const Geo& g, double gamma, int recon, int rs, dou
   fa.g = g;
   fa.sa = make_stage_args(gamma, ct_eps, coef, dt_dev, beta, fl, bad);
   fa.xc = xc; fa.xb = xb; fa.unc = unc; fa.unb = unb; fa.oc = outc; fa.ob = outb;
-  fa.kz = kz > 0 ? kz : fused_default_kz(g);
+  fa.kz = kz;
   fa.ntx = (g.n1 + TileU::TX - 1) / TileU::TX;
   fa.nty = (g.n2 + TileU::TY - 1) / TileU::TY;
   fa.nseg = (g.n3 + fa.kz - 1) / fa.kz;

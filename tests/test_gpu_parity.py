@@ -154,10 +154,14 @@ def test_steps_match_oracle(torch_dev, athmhd, orc, integ, recon, rs):
     s.close()
 
 
+@pytest.mark.parametrize("kz", [None, "16"])
 @pytest.mark.parametrize("integ,recon,rs", [("vl2", "plm", "hlld"), ("rk3", "ppm", "hlle"), ("rk1", "dc", "hlld")])
-def test_segmented_tiles_match_oracle(torch_dev, athmhd, orc, integ, recon, rs):
-    """Block split into several x3 segments (the last one ragged) and tiles
-    whose last row and column are partly outside the block."""
+def test_segmented_tiles_match_oracle(torch_dev, athmhd, orc, monkeypatch, integ, recon, rs, kz):
+    """Block split into several x3 segments (the default length, and 16
+    planes with the last segment ragged) and tiles whose last row and column
+    are partly outside the block."""
+    if kz is not None:
+        monkeypatch.setenv("ATHMHD_KZ", kz)
     torch, dev = torch_dev
     ng = 3 if recon == "ppm" else 2
     b = inputs.smooth_random(n=(30, 29, 40), seed=25, ng=ng)
