@@ -106,9 +106,10 @@ __global__ void __launch_bounds__(kThreads) k_newdt(Geo g, double gamma, Floors 
   const double* fb = bface + blockIdx.y * g.fblock;
   double best = DBL_MAX;
   int nbad = 0;
-  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < nact; t += (int64_t)gridDim.x * kThreads) {
-    const int i = g.ng + (int)(t % g.n1);
-    const int r = (int)(t / g.n1);
+  // a block holds fewer than 2^31 cells, so the cell index fits 32 bits
+  for (int t = blockIdx.x * kThreads + threadIdx.x; t < (int)nact; t += gridDim.x * kThreads) {
+    const int i = g.ng + t % g.n1;
+    const int r = t / g.n1;
     const int j = g.ng + r % g.n2, k = g.ng + r / g.n2;
     const int q = g.c(i, j, k), f = g.f(i, j, k);
     const double b1 = 0.5 * (fb[f] + fb[f + 1]);
@@ -286,16 +287,16 @@ __global__ void __launch_bounds__(kThreads) k_newdt_batch(const BatchDesc* __res
                                                          const double* __restrict__ bface,
                                                          unsigned long long* __restrict__ dt_bits,
                                                          int* __restrict__ bad) {
-  const BatchDesc& d = desc[blockIdx.x];
+  const BatchDesc& d = desc[blockIdx.y];
   const Geo& g = d.g;
   const double* u = cons + d.coff;
   const double* fb = bface + d.foff;
   const int64_t nact = (int64_t)g.n1 * g.n2 * g.n3;
   double best = DBL_MAX;
   int nbad = 0;
-  for (int64_t t = threadIdx.x; t < nact; t += kThreads) {
-    const int i = g.ng + (int)(t % g.n1);
-    const int r = (int)(t / g.n1);
+  for (int t = blockIdx.x * kThreads + threadIdx.x; t < (int)nact; t += gridDim.x * kThreads) {
+    const int i = g.ng + t % g.n1;
+    const int r = t / g.n1;
     const int j = g.ng + r % g.n2, k = g.ng + r / g.n2;
     const int q = g.c(i, j, k), f = g.f(i, j, k);
     const double b1 = 0.5 * (fb[f] + fb[f + 1]);
@@ -348,7 +349,9 @@ hipError_t launch_prim2cons_batch(const BatchDesc* desc, int nblocks, int64_t ma
 hipError_t launch_newdt_batch(const BatchDesc* desc, int nblocks, int64_t, double gamma, const double* cons,
                               const double* bface, unsigned long long* dt_bits, const Floors& fl, int* bad,
                               hipStream_t s) {
-  hipLaunchKernelGGL(k_newdt_batch, dim3(nblocks), dim3(kThreads), 0, s, desc, gamma, fl, cons, bface, dt_bits, bad);
+  // a few workgroups per block so that small blocks do not serialise
+  hipLaunchKernelGGL(k_newdt_batch, dim3(4, nblocks), dim3(kThreads), 0, s, desc, gamma, fl, cons, bface, dt_bits,
+                     bad);
   return hipGetLastError();
 }
 
