@@ -1,0 +1,211 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times (fused stage kernel with its default tile and x3 segment
+length; the batched kernel with the tuned tile).
+
+The oracle cannot step a 256^3 or 512^3 block within a test, but one step
+changes a cell only through cells a few cells away.  A window cut out of the
+full-size input and stepped by the oracle as a periodic block of its own is
+exact away from its edges (the margins are checked on the CPU by
+test_window_inner_cells_equal_full_grid), so sampled windows of the GPU's
+full-size step are compared with the oracle cell by cell, at the 1e-12 bar.
+Batched blocks are independent periodic blocks: sampled blocks are stepped by
+the oracle whole.  The rollout gradient is global: at full size it is checked
+against central differences, and checkpoint placement must not change it.
+"""
+import numpy as np
+import pytest
+
+import windows as W
+from paper_2005_06651_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def athmhd():
+    from paper_2005_06651_amd import athmhd as A
+    A.lib()
+    return A
+
+
+def check_windows(orc, kw, b, c0, b0, c1, b1, dt, origins, margin, mom_speed=0.0):
+    """oracle step of each window of c0/b0 against the same window of the
+    GPU's step c1/b1 (inner cells and their lower faces)"""
+    m = 16 + 2 * margin
+    worst = 0.0
+    for origin in origins:
+        wc, wb = W.extract(c0, b0, b.ng, b.n, origin, m)
+        wcfg = orc.make_cfg((m, m, m), b.ng, b.dx, b.gamma, **kw)
+        assert orc.step(wcfg, wc, wb, dt) == 0
+        ref = W.inner_of_window(wc, wb, b.ng, m, margin)
+        got = W.inner(c1, b1, b.ng, b.n, origin, m, margin)
+        errs = W.rel_l1_arrays(got[0], got[1], ref[0], ref[1], mom_speed)
+        err = max(errs)
+        print("window", origin, "rel L1 (rho, M1, M2, M3, E, B1, B2, B3)", " ".join(f"{e:.2e}" for e in errs),
+              flush=True)
+        worst = max(worst, err)
+    return worst
+
+
+def test_turbulence_256_sampled_windows(torch_dev, athmhd, orc):
+    """256^3 decaying turbulence, VL2 + PLM + HLLD: the CFL dt of the full
+    block against the oracle's, and one step on 10 windows of 16^3 inner
+    cells (seeded positions, one across the periodic corner)."""
+    torch, dev = torch_dev
+    b = inputs.turbulence(n=256, seed=1)
+    kw = dict(integrator="vl2", recon="plm", riemann="hlld", cfl=0.3)
+    s = athmhd.Solver(b.n, b.ng, b.dx, b.gamma, **kw)
+    tb = torch.from_numpy(b.bface).to(dev)
+    tc = s.prim2cons(torch.from_numpy(b.prim).to(dev), tb)
+    c0, b0 = tc.cpu().numpy(), tb.cpu().numpy()
+    dt = s.newdt(tc, tb)
+    odt, bad = orc.newdt(orc.cfg_for(b, **kw), c0, b0)
+    assert bad == 0 and abs(dt - odt) <= 1e-14 * odt, (dt, odt)
+    s.step(tc, tb, dt)
+    c1, b1 = tc.cpu().numpy(), tb.cpu().numpy()
+    rng = np.random.default_rng(41)
+    origins = [tuple(int(x) for x in rng.integers(0, 256, 3)) for _ in range(9)] + [(245, 250, 243)]
+    assert check_windows(orc, kw, b, c0, b0, c1, b1, dt, origins, 6) <= TOL
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def blast512():
+    # the benchmark's blast with its sphere's surface smoothed over ~2 cells
+    return inputs.blast(n=512, seed=1, edge=2.0)
+
+
+@pytest.mark.parametrize("rs", ["hlld", "hlle"])
+def test_blast_512_sampled_windows(torch_dev, athmhd, orc, blast512, rs):
+    """512^3 blast, RK3 + PPM with density and pressure floors at 1e-10 (the
+    benchmark's stage kernel): one step on windows across the sphere's
+    surface, at its centre and at seeded positions.  The gas starts at rest,
+    so momentum errors are relative to rho times the ambient sound speed.
+    The surface is smoothed over ~2 cells and the CT weight is the continuous
+    ramp of width 1e-8: with the sharp surface and the three-way switch the
+    method itself is rounding-sensitive (ties in the PPM extremum test, zero
+    mass fluxes), and the bar there is the oracle's own spread, checked at
+    40^3 elsewhere."""
+    torch, dev = torch_dev
+    b = blast512
+    n = 512
+    kw = dict(integrator="rk3", recon="ppm", riemann=rs, cfl=0.3, ct_eps=1e-8)
+    s = athmhd.Solver(b.n, b.ng, b.dx, b.gamma, **kw)
+    s.set_floors(1e-10, 1e-10)
+    tb = torch.from_numpy(b.bface).to(dev)
+    tc = s.prim2cons(torch.from_numpy(b.prim).to(dev), tb)
+    c0, b0 = tc.cpu().numpy(), tb.cpu().numpy()
+    dt = s.newdt(tc, tb)
+    s.step(tc, tb, dt)
+    assert s.floor_count() == 0
+    c1, b1 = tc.cpu().numpy(), tb.cpu().numpy()
+    # windows around the seeded centre of the sphere (radius 0.1)
+    ctr = tuple(int(x * n) for x in b.meta["centre"])
+    rad = int(round(0.1 * n))
+    m = 16 + 2 * 13
+    origins = [((ctr[0] - m // 2) % n, (ctr[1] - m // 2) % n, (ctr[2] - m // 2) % n),
+               ((ctr[0] + rad - m // 2) % n, (ctr[1] - m // 2) % n, (ctr[2] - m // 2) % n),
+               ((ctr[0] - m // 2) % n, (ctr[1] - rad - m // 2) % n, (ctr[2] - m // 2) % n),
+               ((ctr[0] - m // 2) % n, (ctr[1] - m // 2) % n, (ctr[2] + rad - m // 2) % n)]
+    rng = np.random.default_rng(43)
+    origins += [tuple(int(x) for x in rng.integers(0, n, 3)) for _ in range(2)]
+    okw = dict(kw, dfloor=1e-10, pfloor=1e-10)
+    # the gas starts at rest: momentum errors are measured against rho times
+    # the ambient sound speed
+    cs = (b.gamma * 0.1) ** 0.5
+    assert check_windows(orc, okw, b, c0, b0, c1, b1, dt, origins, 13, cs) <= TOL
+    s.close()
+
+
+def test_batch_1024_sampled_blocks(torch_dev, athmhd, orc):
+    """The 1024 uneven blocks of the batched workload with the tuned tile:
+    the global CFL dt against the oracle's minimum over every block, and one
+    step of 40 sampled blocks (all three sizes) against the oracle."""
+    torch, dev = torch_dev
+    blocks = inputs.amr_batch(1024, seed=1)
+    kw = dict(integrator="vl2", recon="plm", riemann="hlld", cfl=0.3)
+    s = athmhd.BatchSolver([x.n for x in blocks], [x.dx for x in blocks], 2, blocks[0].gamma, **kw)
+    tb = torch.from_numpy(inputs.pack([x.bface for x in blocks])).to(dev)
+    tc = s.prim2cons(torch.from_numpy(inputs.pack([x.prim for x in blocks])).to(dev), tb)
+    s.tune(tc, tb)
+    c0 = [x.cpu().numpy().copy() for x in s.views(tc, "cons")]
+    f0 = [x.cpu().numpy().copy() for x in s.views(tb, "bface")]
+    cfgs = [orc.cfg_for(x, **kw) for x in blocks]
+    dt = s.newdt(tc, tb)
+    odt = min(orc.newdt(c, x, y)[0] for c, x, y in zip(cfgs, c0, f0))
+    assert abs(dt - odt) <= 1e-14 * odt, (dt, odt)
+    s.step(tc, tb, dt)
+    c1 = s.views(tc, "cons")
+    f1 = s.views(tb, "bface")
+    rng = np.random.default_rng(44)
+    sample = sorted(set(rng.choice(len(blocks), 40, replace=False).tolist()))
+    assert len({blocks[i].n[0] for i in sample}) == 3
+    worst = 0.0
+    for i in sample:
+        x, y = c0[i].copy(), f0[i].copy()
+        assert orc.step(cfgs[i], x, y, dt) == 0
+        g, (n1, n2, n3) = blocks[i].ng, blocks[i].n
+        a = (slice(None), slice(g, g + n3), slice(g, g + n2), slice(g, g + n1))
+        err = W.max_rel_l1(c1[i].cpu().numpy()[a], f1[i].cpu().numpy()[a], x[a], y[a])
+        worst = max(worst, err)
+    print("worst block rel L1", worst, flush=True)
+    assert worst <= TOL
+    s.close()
+
+
+def test_rollout_128_gradient_at_full_size(torch_dev, athmhd, orc):
+    """The reverse-mode workload at its full size (128^3 at Mach 0.3, 64 VL2 +
+    PLM + HLLD steps with the continuous CT weight 1e-3, 8 checkpoints): the
+    gradient with respect to the initial velocity does not depend on the
+    checkpoint spacing (bitwise), and matches central differences of the loss
+    to 1e-6 on two smooth directions."""
+    torch, dev = torch_dev
+    from paper_2005_06651_amd.rollout import Prim2Cons, Rollout
+    n, nsteps = 128, 64
+    blk = inputs.turbulence(n=n, seed=1, mach=0.3)
+    s = athmhd.Solver(blk.n, blk.ng, blk.dx, blk.gamma, recon="plm", riemann="hlld", integrator="vl2", cfl=0.3,
+                      ct_eps=1e-3)
+    g = blk.ng
+    prim0 = torch.from_numpy(blk.prim).to(dev)
+    bf0 = torch.from_numpy(blk.bface).to(dev)
+    dt = s.newdt(s.prim2cons(prim0, bf0), bf0)
+    tgt = inputs.smooth_random(n=(n, n, n), seed=2001, ng=g, kmax=4.0, rho_range=(0.95, 1.05))
+    target = torch.from_numpy(np.ascontiguousarray(tgt.prim[0, g:g + n, g:g + n, g:g + n])).to(dev)
+    dV = blk.dx[0] * blk.dx[1] * blk.dx[2]
+
+    def loss_of(prim, ncheck):
+        cN, _ = Rollout.apply(Prim2Cons.apply(prim, bf0, s), bf0, s, dt, nsteps, ncheck)
+        return ((cN[0, g:g + n, g:g + n, g:g + n] - target) ** 2).sum() * dV
+
+    grads = []
+    for ncheck in (8, 5):
+        p = prim0.clone().requires_grad_(True)
+        loss_of(p, ncheck).backward()
+        grads.append(p.grad.detach().clone())
+    assert torch.equal(grads[0], grads[1])
+    grad_v = grads[0][1:4, g:g + n, g:g + n, g:g + n].cpu().numpy()
+    for q in range(2):
+        d = inputs.smooth_random(n=(n, n, n), seed=3001 + q, ng=g, kmax=4.0).prim[1:4, g:g + n, g:g + n,
+                                                                                  g:g + n].copy()
+        d /= np.linalg.norm(d)
+        ad = float(np.sum(grad_v * d))
+        best = None
+        for h in (1e-3, 1e-4):
+            dp = torch.zeros_like(prim0)
+            dp[1:4, g:g + n, g:g + n, g:g + n] = torch.from_numpy(h * d).to(dev)
+            with torch.no_grad():
+                fd = (loss_of(prim0 + dp, 8).item() - loss_of(prim0 - dp, 8).item()) / (2 * h)
+            err = abs(fd - ad) / max(abs(ad), 1e-300)
+            best = err if best is None else min(best, err)
+        print("direction", q, "<grad, d>", ad, "best FD rel err", best, flush=True)
+        assert best <= 1e-6, (best, ad)
+    s.close()

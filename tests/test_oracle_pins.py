@@ -711,3 +711,34 @@ def test_floors_keep_conservation_on_a_blast(orc):
     assert tot[4] >= tot0[4] - 1e-13 * scale[4]
     orc.fill_ghosts(cfg, c, b)
     assert inputs.divb_metric(b, blk.n, blk.ng, blk.dx) <= 1e-13
+
+
+@pytest.mark.parametrize("n,ng,margin,kw", [
+    (40, 2, 6, dict(integrator="vl2", recon="plm", riemann="hlld")),
+    (48, 3, 13, dict(integrator="rk3", recon="ppm", riemann="hlld", ct_eps=1e-8)),
+])
+def test_window_inner_cells_equal_full_grid(orc, n, ng, margin, kw):
+    """One step changes a cell only through cells within a few cells of it
+    (stencils of Sec. 3.2.1, faces and edges of Sec. 3.1, once per stage), so
+    a window cut out of a periodic grid and stepped as a periodic block of its
+    own reproduces the full grid's step bitwise away from its edges.  This
+    licenses the full-size GPU checks that compare sampled windows with the
+    oracle; the margins used there (6 cells for VL2 + PLM, 13 for RK3 + PPM)
+    are the ones checked here, from windows that also wrap across the grid's
+    periodic boundary."""
+    import windows as W
+    b = inputs.smooth_random(n=(n, n, n), seed=31, ng=ng)
+    cfg = orc.cfg_for(b, **kw)
+    cons = orc.prim2cons(cfg, b.prim, b.bface)
+    dt, _ = orc.newdt(cfg, cons, b.bface)
+    fc, fb = cons.copy(), b.bface.copy()
+    assert orc.step(cfg, fc, fb, dt) == 0
+    m = 16 + 2 * margin
+    for origin in [(n - 5, 3, n - 9), (7, n - 12, 1)]:
+        wc, wb = W.extract(cons, b.bface, ng, (n, n, n), origin, m)
+        wcfg = orc.make_cfg((m, m, m), ng, b.dx, b.gamma, **kw)
+        assert orc.step(wcfg, wc, wb, dt) == 0
+        got = W.inner_of_window(wc, wb, ng, m, margin)
+        ref = W.inner(fc, fb, ng, (n, n, n), origin, m, margin)
+        for x, y in zip(got, ref):
+            assert np.array_equal(x, y)
