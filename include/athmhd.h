@@ -30,9 +30,10 @@
  *
  * Errors: every function returns ATHMHD_OK (0) or a negative code.  Argument
  * errors are detected on the host before any HIP call.  Asynchronous HIP errors
- * and non-physical cells met by a step (rho <= 0, P <= 0 or not finite; no
- * floors are applied) surface at the next athmhd_newdt.  athmhd_last_error
- * returns a text description of the last failure of a handle.
+ * and non-physical cells met by a step (rho <= 0, P <= 0 or not finite, unless
+ * floors are enabled with athmhd_set_floors) surface at the next athmhd_newdt.
+ * athmhd_last_error returns a text description of the last failure of a
+ * handle.
  */
 #ifndef ATHMHD_H
 #define ATHMHD_H
@@ -89,7 +90,10 @@ ATHMHD_API int athmhd_version(void);
 /* Validate `cfg` on the host, then allocate the stage registers and scratch of
  * one block on the current device.  nblocks_max identical blocks may later be
  * advanced together (each periodic on its own).  On success *out receives a
- * handle owned by the caller (free with athmhd_destroy). */
+ * handle owned by the caller (free with athmhd_destroy).  The fused stage
+ * kernel marches each workgroup over a segment of x3 planes whose length is
+ * chosen per launch from the block size and the device's CU count; a positive
+ * integer in the environment variable ATHMHD_KZ, read here, fixes it instead. */
 ATHMHD_API int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out);
 
 /* One full time step of nblocks (<= nblocks_max) blocks, in place:
