@@ -56,12 +56,15 @@ def check_windows(orc, kw, b, c0, b0, c1, b1, dt, origins, margin, mom_speed=0.0
     return worst
 
 
-def test_turbulence_256_sampled_windows(torch_dev, athmhd, orc):
-    """256^3 decaying turbulence, VL2 + PLM + HLLD: the CFL dt of the full
-    block against the oracle's, and one step on 10 windows of 16^3 inner
-    cells (seeded positions, one across the periodic corner)."""
+@pytest.mark.parametrize("n", [256, 128])
+def test_turbulence_sampled_windows(torch_dev, athmhd, orc, n):
+    """Decaying turbulence, VL2 + PLM + HLLD, at the benchmark's 256^3 (x3
+    segments of 32 planes) and at 128^3 (segments of 8 planes, the reverse-mode
+    workload's size): the CFL dt of the full block against the oracle's, and
+    one step on 10 windows of 16^3 inner cells (seeded positions, one across
+    the periodic corner)."""
     torch, dev = torch_dev
-    b = inputs.turbulence(n=256, seed=1)
+    b = inputs.turbulence(n=n, seed=1)
     kw = dict(integrator="vl2", recon="plm", riemann="hlld", cfl=0.3)
     s = athmhd.Solver(b.n, b.ng, b.dx, b.gamma, **kw)
     tb = torch.from_numpy(b.bface).to(dev)
@@ -73,7 +76,7 @@ def test_turbulence_256_sampled_windows(torch_dev, athmhd, orc):
     s.step(tc, tb, dt)
     c1, b1 = tc.cpu().numpy(), tb.cpu().numpy()
     rng = np.random.default_rng(41)
-    origins = [tuple(int(x) for x in rng.integers(0, 256, 3)) for _ in range(9)] + [(245, 250, 243)]
+    origins = [tuple(int(x) for x in rng.integers(0, n, 3)) for _ in range(9)] + [(n - 11, n - 6, n - 13)]
     assert check_windows(orc, kw, b, c0, b0, c1, b1, dt, origins, 6) <= TOL
     s.close()
 
