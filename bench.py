@@ -59,7 +59,7 @@ def parse():
     p.add_argument("--riemann", default="hlld", choices=["hlld", "hlle"], help="blast: Riemann solver")
     p.add_argument("--blast-n", type=int, default=512, help="blast: cells per side")
     p.add_argument("--blast-steps", type=int, default=200, help="blast: timed steps")
-    p.add_argument("--floor", type=float, default=1e-10, help="blast: density and pressure floor on the primitives")
+    p.add_argument("--floor", type=float, default=1e-10, help="blast: density and pressure floor")
     p.add_argument("--adj-n", type=int, default=128, help="adjoint: cells per side")
     p.add_argument("--adj-steps", type=int, default=64, help="adjoint: rollout steps")
     p.add_argument("--adj-dirs", type=int, default=16, help="adjoint: finite-difference directions")
@@ -264,7 +264,8 @@ def bench_blast(args):
     """MHD blast on the 512^3 periodic unit cube (nghost 3, RK3 + PPM + HLLD or
     HLLE + CT, rho = 1, p = 0.1, p = 10 inside r < 0.1 around a seeded centre,
     B = (1/sqrt2, 1/sqrt2, 0), CFL 0.3): newdt + one RK3 step per timed step.
-    Density and pressure floors (1e-10 by default) act on the primitives only;
+    Density and pressure floors (1e-10 by default) limit the primitives and,
+    after each stage, raise the density and total energy of cells below them;
     their activations are counted and reported."""
     import torch
 
@@ -276,7 +277,7 @@ def bench_blast(args):
     s = athmhd.Solver(blk.n, blk.ng, blk.dx, blk.gamma, recon="ppm", riemann=args.riemann, integrator="rk3",
                       cfl=0.3)
     # without floors this blast reaches P <= 0 within a few steps (the CPU
-    # oracle does too); floors act on the primitives only and are counted
+    # oracle does too); every floor activation is counted
     s.set_floors(args.floor, args.floor)
     tb = torch.from_numpy(blk.bface).to(dev)
     tc = s.prim2cons(torch.from_numpy(blk.prim).to(dev), tb)
@@ -350,7 +351,8 @@ def bench_blast(args):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the MHD step runs on one GPU (sharding over several GPUs is designed, not built); "
+              "--gpus must be 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

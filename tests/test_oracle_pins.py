@@ -651,8 +651,10 @@ def test_step_jvp_is_derivative_of_step(orc, integ, recon, rs, eps):
 
 
 # ---------------------------------------------------------------------------
-# Optional floors act on the primitives only (never on U), so they cannot
-# break conservation, and they are invisible while no floor is reached.
+# Optional floors limit the primitives and, after each stage, raise the
+# density and total energy of cells below them: they are invisible while no
+# floor is reached, conversions to primitives leave U untouched, and they can
+# only add mass or energy.
 # ---------------------------------------------------------------------------
 def test_floors_inactive_are_invisible(orc):
     blk = inputs.smooth_random(n=(10, 8, 6), seed=51, ng=2)
