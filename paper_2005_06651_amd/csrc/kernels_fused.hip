@@ -17,6 +17,11 @@
 //   * the flux divergence and the CT curl accumulate in registers and the
 //     plane below is written out once its upper x3 fluxes / EMFs exist
 //     (2S stage update, Eq. (rk-2s)).
+// Two barriers per plane: after the primitives are in LDS, and after the face
+// results are.  The face-field update that reads a plane's corner EMFs runs
+// after the next plane's first barrier, and the exchange slots read by the
+// corner EMFs are written after that barrier too, so no third barrier is
+// needed to keep one plane's reads apart from the next plane's writes.
 // HBM traffic per stage is the input state (with the halo overlap of
 // neighbouring tiles), U^n where the stage needs it, and the output state.
 #include "common.hpp"
@@ -216,6 +221,35 @@ enum {
   X_FX = 0, X_FY = 5, X_E3X = 10, X_WX, X_E3Y, X_WY, X_E3C, X_E1Z, X_E2Z, X_WZ, X_E1C, X_E2C, X_E1CP, X_E2CP, X_N
 };
 
+// Face-field update of plane q from its corner EMFs in sc (E1, E2, E3 of the
+// own column's edges; the neighbours' at tid + 1 and tid + BX): completes B1
+// and B2 on the lower faces of cell q-1, writes B3 on the face q-1/2, and
+// leaves the partial B1, B2 of plane q in bacc[5], bacc[6].  pwb holds the
+// pointwise terms (g1 U^n + g0 X) of B1, B2 at q-1 and B3 at q.
+__device__ __forceinline__ void face_update(const Geo& g, const double* __restrict__ sc, int tid, int BX, int NT,
+                                            int gi, int gj, int q, int k0, int kend, double i1, double i2,
+                                            double i3, double bdt, const double* pwb, double* bacc,
+                                            double* __restrict__ ob) {
+  const int tE = tid + 1, tN = tid + BX;
+  const double e1 = sc[0 * NT + tid], e2 = sc[1 * NT + tid], e3 = sc[2 * NT + tid];
+  // B1(i-1/2, j): -(E3(j+1/2) - E3(j-1/2))/dx2 + (E2(k+1/2) - E2(k-1/2))/dx3
+  const double a5 = -(sc[2 * NT + tN] - e3) * i2 - e2 * i3;
+  bacc[5] += e2 * i3;
+  // B2(i, j-1/2): -(E1(k+1/2) - E1(k-1/2))/dx3 + (E3(i+1/2) - E3(i-1/2))/dx1
+  const double a6 = (sc[2 * NT + tE] - e3) * i1 + e1 * i3;
+  bacc[6] -= e1 * i3;
+  // B3(i, j, q-1/2): -(E2(i+1/2) - E2(i-1/2))/dx1 + (E1(j+1/2) - E1(j-1/2))/dx2
+  const double db3 = -(sc[1 * NT + tE] - e2) * i1 + (sc[0 * NT + tN] - e1) * i2;
+  if (q < kend) ob[2 * g.fvar + g.f(gi, gj, q)] = pwb[2] + bdt * db3;
+  if (q - 1 >= k0) {
+    const int f = g.f(gi, gj, q - 1);
+    ob[f] = pwb[0] + bdt * bacc[5];
+    ob[g.fvar + f] = pwb[1] + bdt * bacc[6];
+  }
+  bacc[5] = a5;
+  bacc[6] = a6;
+}
+
 // One tile (tile_x, tile_y) of a block over the active planes [k0, kend).
 template <int RECON, int RS, class T, bool FL>
 __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, const StageArgs& sa, int tile_x,
@@ -300,6 +334,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
   double qz_carry[7];  // left state of the next x3-face (right edge of the cell below)
   double e2x_prev = 0.0, wx_prev = 0.5, e1y_prev = 0.0, wy_prev = 0.5, e1c_prev = 0.0, e2c_prev = 0.0;
   double acc_prev[7];  // partial update of the plane below: 5 conserved, B1, B2
+  double pwb[3] = {0.0, 0.0, 0.0};  // pointwise terms of B1, B2 (plane below) and B3 of the last plane
 #pragma unroll
   for (int v = 0; v < 7; ++v) { acc_prev[v] = 0.0; qz_carry[v] = 0.0; }
 
@@ -319,8 +354,8 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
       bnq[LA][2] = pre.b3lo;
     }
 
-    // ---- 3. own cell of plane p: primitives to LDS, cell EMFs to the exchange
-    double e1c, e2c;
+    // ---- 3. own cell of plane p: primitives to LDS, cell EMFs
+    double e1c, e2c, e3c;
     {
       const ZCell& cur = win[LA];
       const int l = (ty + LA) * PW + tx + LA;
@@ -337,11 +372,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
       const double b1c = cur.q[5], b2c = cur.q[6], b3c = cur.b3;
       e1c = -(v2 * b3c - v3 * b2c);
       e2c = -(v3 * b1c - v1 * b3c);
-      sx[X_E3C * NT + tid] = -(v1 * b2c - v2 * b1c);
-      sx[X_E1C * NT + tid] = e1c;
-      sx[X_E2C * NT + tid] = e2c;
-      sx[X_E1CP * NT + tid] = e1c_prev;
-      sx[X_E2CP * NT + tid] = e2c_prev;
+      e3c = -(v1 * b2c - v2 * b1c);
     }
 
     // ---- 4. ring cells to LDS
@@ -355,6 +386,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
     // ---- 5. reconstruction along x3 and the Riemann problem on the lower
     // x3-face (p-1/2) of the own cell
     double fz_cons[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double wz = 0.5, e1z = 0.0, e2z = 0.0;
     {
       double zl[7], zr[7];
 #pragma unroll
@@ -368,7 +400,6 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
         zr[v] = left;
         qz_carry[v] = right;
       }
-      double wz = 0.5, e1z = 0.0, e2z = 0.0;
       if (zface) {
         const double bn3 = bnq[0][2];
         FaceFlux fz;
@@ -378,11 +409,23 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
         e2z = -fz.bt1;
         e1z = fz.bt2;
       }
-      sx[X_E1Z * NT + tid] = e1z;
-      sx[X_E2Z * NT + tid] = e2z;
-      sx[X_WZ * NT + tid] = wz;
     }
     __syncthreads();
+
+    // exchange values read only after the next barrier (writing them here, not
+    // before the barrier above, lets the previous plane's corner EMFs read the
+    // same slots without a third barrier per plane)
+    sx[X_E3C * NT + tid] = e3c;
+    sx[X_E1C * NT + tid] = e1c;
+    sx[X_E2C * NT + tid] = e2c;
+    sx[X_E1CP * NT + tid] = e1c_prev;
+    sx[X_E2CP * NT + tid] = e2c_prev;
+    sx[X_E1Z * NT + tid] = e1z;
+    sx[X_E2Z * NT + tid] = e2z;
+    sx[X_WZ * NT + tid] = wz;
+    // ---- 8 (of plane p-1). face-field updates from its corner EMFs
+    if (act && p - 1 >= k0)
+      face_update(g, sc, tid, BX, NT, gi, gj, p - 1, k0, kend, i1, i2, i3, bdt, pwb, acc_prev, ob);
 
     // ---- 6. Riemann problems on the lower x1-face and x2-face in plane p
     double e2x = 0.0, wx = 0.5, e1y = 0.0, wy = 0.5;
@@ -530,28 +573,12 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
 #pragma unroll
         for (int v = 0; v < 5; ++v) oc[v * g.cvar + q] = pw[v] + bdt * acc_prev[v];
       }
-    }
-    __syncthreads();
-
-    // ---- 8. face-field updates from the corner EMFs
-    if (act && zface) {
-      const double e1 = sc[0 * NT + tid], e2 = sc[1 * NT + tid], e3 = sc[2 * NT + tid];
-      // B1(i-1/2, j): -(E3(j+1/2) - E3(j-1/2))/dx2 + (E2(k+1/2) - E2(k-1/2))/dx3
-      acc[5] = -(sc[2 * NT + tN] - e3) * i2 - e2 * i3;
-      acc_prev[5] += e2 * i3;
-      // B2(i, j-1/2): -(E1(k+1/2) - E1(k-1/2))/dx3 + (E3(i+1/2) - E3(i-1/2))/dx1
-      acc[6] = (sc[2 * NT + tE] - e3) * i1 + e1 * i3;
-      acc_prev[6] -= e1 * i3;
-      // B3(i, j, p-1/2): -(E2(i+1/2) - E2(i-1/2))/dx1 + (E1(j+1/2) - E1(j-1/2))/dx2
-      const double db3 = -(sc[1 * NT + tE] - e2) * i1 + (sc[0 * NT + tN] - e1) * i2;
-      if (out_b3) ob[2 * g.fvar + g.f(gi, gj, p)] = pw[7] + bdt * db3;
-      if (out_cell) {
-        const int f = g.f(gi, gj, p - 1);
-        ob[f] = pw[5] + bdt * acc_prev[5];
-        ob[g.fvar + f] = pw[6] + bdt * acc_prev[6];
-      }
 #pragma unroll
-      for (int v = 0; v < 7; ++v) acc_prev[v] = acc[v];
+      for (int v = 0; v < 5; ++v) acc_prev[v] = acc[v];
+      // the face fields of this plane are updated after the next barrier
+      pwb[0] = pw[5];
+      pwb[1] = pw[6];
+      pwb[2] = pw[7];
     }
 
     // ---- 9. carry this plane's face EMFs / weights / cell EMFs upward
@@ -568,6 +595,9 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
     e1c_prev = e1c;
     e2c_prev = e2c;
   }
+  __syncthreads();
+  if (act && kend >= k0)
+    face_update(g, sc, tid, BX, NT, gi, gj, kend, k0, kend, i1, i2, i3, bdt, pwb, acc_prev, ob);
   if (nbad && act) atomicAdd(sa.bad, 1);
   if (nfl && act) atomicAdd(sa.bad + 1, nfl);
 }
