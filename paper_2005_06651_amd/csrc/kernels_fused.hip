@@ -423,7 +423,8 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
     sx[X_E1Z * NT + tid] = e1z;
     sx[X_E2Z * NT + tid] = e2z;
     sx[X_WZ * NT + tid] = wz;
-    // ---- 8 (of plane p-1). face-field updates from its corner EMFs
+    // ---- 8, for plane p-1: its face-field updates from the corner EMFs that
+    // the previous iteration left in sc
     if (act && p - 1 >= k0)
       face_update(g, sc, tid, BX, NT, gi, gj, p - 1, k0, kend, i1, i2, i3, bdt, pwb, acc_prev, ob);
 
