@@ -91,6 +91,19 @@ __global__ void __launch_bounds__(kThreads) k_prim2cons(Geo g, double gamma, con
   u[4 * g.cvar + t] = p / (gamma - 1.0) + 0.5 * rho * (v1 * v1 + v2 * v2 + v3 * v3) + 0.5 * (b1 * b1 + b2 * b2 + b3 * b3);
 }
 
+// Indices of the upper x1-, x2- and x3-faces of active cell (i, j, k).  The
+// block is its own periodic neighbour, so the upper faces on its boundary are
+// the periodic images of its lower boundary faces; they are read there, not
+// from the stored image entries, which a step does not refresh.
+__device__ __forceinline__ void upper_faces(const Geo& g, int i, int j, int k, int& f1, int& f2, int& f3) {
+  const int iu = i + 1 < g.ng + g.n1 ? i + 1 : g.ng;
+  const int ju = j + 1 < g.ng + g.n2 ? j + 1 : g.ng;
+  const int ku = k + 1 < g.ng + g.n3 ? k + 1 : g.ng;
+  f1 = g.f(iu, j, k);
+  f2 = g.f(i, ju, k);
+  f3 = g.f(i, j, ku);
+}
+
 // Smallest dx_d / (|v_d| + c_f,d) over the active cells (Sec. 2.1.6, Sec. 3.2.3).
 // Grid-stride loop per thread, wavefront min by cross-lane shuffles, LDS
 // across the workgroup, then one atomicMin per workgroup on the bit pattern
@@ -112,9 +125,11 @@ __global__ void __launch_bounds__(kThreads) k_newdt(Geo g, double gamma, Floors 
     const int r = t / g.n1;
     const int j = g.ng + r % g.n2, k = g.ng + r / g.n2;
     const int q = g.c(i, j, k), f = g.f(i, j, k);
-    const double b1 = 0.5 * (fb[f] + fb[f + 1]);
-    const double b2 = 0.5 * (fb[g.fvar + f] + fb[g.fvar + f + g.F1]);
-    const double b3 = 0.5 * (fb[2 * g.fvar + f] + fb[2 * g.fvar + f + g.F1 * g.F2]);
+    int f1, f2, f3;
+    upper_faces(g, i, j, k, f1, f2, f3);
+    const double b1 = 0.5 * (fb[f] + fb[f1]);
+    const double b2 = 0.5 * (fb[g.fvar + f] + fb[g.fvar + f2]);
+    const double b3 = 0.5 * (fb[2 * g.fvar + f] + fb[2 * g.fvar + f3]);
     const double uc[5] = {u[q], u[g.cvar + q], u[2 * g.cvar + q], u[3 * g.cvar + q], u[4 * g.cvar + q]};
     const double bc[3] = {b1, b2, b3};
     double w[5];
@@ -299,9 +314,11 @@ __global__ void __launch_bounds__(kThreads) k_newdt_batch(const BatchDesc* __res
     const int r = t / g.n1;
     const int j = g.ng + r % g.n2, k = g.ng + r / g.n2;
     const int q = g.c(i, j, k), f = g.f(i, j, k);
-    const double b1 = 0.5 * (fb[f] + fb[f + 1]);
-    const double b2 = 0.5 * (fb[g.fvar + f] + fb[g.fvar + f + g.F1]);
-    const double b3 = 0.5 * (fb[2 * g.fvar + f] + fb[2 * g.fvar + f + g.F1 * g.F2]);
+    int f1, f2, f3;
+    upper_faces(g, i, j, k, f1, f2, f3);
+    const double b1 = 0.5 * (fb[f] + fb[f1]);
+    const double b2 = 0.5 * (fb[g.fvar + f] + fb[g.fvar + f2]);
+    const double b3 = 0.5 * (fb[2 * g.fvar + f] + fb[2 * g.fvar + f3]);
     const double uc[5] = {u[q], u[g.cvar + q], u[2 * g.cvar + q], u[3 * g.cvar + q], u[4 * g.cvar + q]};
     const double bc[3] = {b1, b2, b3};
     double w[5];

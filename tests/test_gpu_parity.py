@@ -178,6 +178,37 @@ def test_segmented_tiles_match_oracle(torch_dev, athmhd, orc, monkeypatch, integ
     s.close()
 
 
+def test_newdt_after_steps_reads_no_image_entries(torch_dev, athmhd, orc):
+    """The CFL dt after fused steps (which leave ghost cells and periodic image
+    faces untouched) equals the oracle's, whose step refreshes them: the upper
+    face of a boundary cell is its periodic image.  Every stored entry outside
+    the active box is overwritten with a large field first, which would shrink
+    dt by orders of magnitude if it were read."""
+    torch, dev = torch_dev
+    b = inputs.smooth_random(n=(20, 12, 10), seed=29)
+    s, cfg = make_pair(athmhd, orc, b)
+    cons = orc.prim2cons(cfg, b.prim, b.bface)
+    tc, tb = to_dev(torch, dev, cons), to_dev(torch, dev, b.bface)
+    rc, rb = cons.copy(), b.bface.copy()
+    for _ in range(3):
+        dt, _ = orc.newdt(cfg, rc, rb)
+        assert orc.step(cfg, rc, rb, dt) == 0
+        s.step(tc, tb, dt)
+    g, (n1, n2, n3) = b.ng, b.n
+    gc, gb = tc.cpu().numpy(), tb.cpu().numpy()
+    junk_c, junk_b = np.full_like(gc, 1e3), np.full_like(gb, 1e3)
+    act_c = (slice(None), slice(g, g + n3), slice(g, g + n2), slice(g, g + n1))
+    junk_c[act_c] = gc[act_c]
+    junk_b[act_c] = gb[act_c]
+    tc.copy_(torch.from_numpy(junk_c))
+    tb.copy_(torch.from_numpy(junk_b))
+    odt, bad = orc.newdt(cfg, rc, rb)
+    assert bad == 0
+    gdt = s.newdt(tc, tb)
+    assert abs(gdt - odt) <= 1e-14 * odt, (gdt, odt)
+    s.close()
+
+
 def test_fused_and_unfused_paths_agree(torch_dev, athmhd, orc):
     """The single-kernel stage and the pipeline of simple kernels compute the
     same step (different summation orders only)."""
