@@ -52,10 +52,10 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle timing")
     p.add_argument("--cpu-steps", type=int, default=1, help="oracle steps in the CPU baseline sample")
     p.add_argument("--kernel-path", default="fused", choices=["fused", "unfused"])
-    p.add_argument("--workload", default="turbulence", choices=["turbulence", "batch", "adjoint", "blast"],
+    p.add_argument("--workload", default="turbulence", choices=["turbulence", "batch", "adjoint", "blast", "mesh"],
                    help="turbulence: the 256^3 block (default); batch: 1024 uneven AMR-shaped blocks; "
                         "adjoint: gradient of a 128^3 x 64-step rollout (cost ratio and finite differences); "
-                        "blast: 512^3 RK3+PPM MHD blast")
+                        "blast: 512^3 RK3+PPM MHD blast; mesh: the 256^3 domain as a coupled mesh of equal blocks")
     p.add_argument("--riemann", default="hlld", choices=["hlld", "hlle"], help="blast: Riemann solver")
     p.add_argument("--blast-n", type=int, default=512, help="blast: cells per side")
     p.add_argument("--blast-steps", type=int, default=200, help="blast: timed steps")
@@ -67,6 +67,7 @@ def parse():
     p.add_argument("--adj-no-fd", action="store_true", help="adjoint: skip the finite-difference check")
     p.add_argument("--adj-dir-kind", default="smooth", choices=["smooth", "white"],
                    help="adjoint: finite-difference directions: band-limited fields or white noise")
+    p.add_argument("--mesh-blocks", type=int, default=8, help="mesh: blocks per direction of the 256^3 domain")
     p.add_argument("--no-tune", action="store_true", help="batch: keep the default tile instead of autotuning")
     p.add_argument("--graph", action="store_true", help="replay each step from a hipGraph")
     p.add_argument("--copy-calibration", action="store_true",
@@ -260,6 +261,56 @@ def bench_adjoint(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_mesh(args):
+    """The 256^3 decaying turbulence as a coupled mesh of m^3 equal blocks
+    (default 8^3 blocks of 32^3): ghost cells and faces exchanged between the
+    blocks on the device before every stage, VL2+PLM+HLLD, newdt + one step
+    per timed step."""
+    import torch
+
+    from paper_2005_06651_amd import athmhd, inputs
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    m = args.mesh_blocks
+    blk = inputs.turbulence(n=args.n, seed=args.seed)
+    if args.n % m:
+        sys.exit(f"bench.py: {args.n} cells per side do not split into {m} blocks")
+    nb = args.n // m
+    single = athmhd.Solver(blk.n, blk.ng, blk.dx, blk.gamma)
+    tb = torch.from_numpy(blk.bface).to(dev)
+    cons = single.prim2cons(torch.from_numpy(blk.prim).to(dev), tb).cpu().numpy()
+    single.close()
+    del tb
+    mc, mf = inputs.split_mesh(cons, blk.bface, blk.ng, (nb, nb, nb), (m, m, m))
+    del cons
+    s = athmhd.MeshSolver((nb, nb, nb), (m, m, m), blk.ng, blk.dx, blk.gamma, recon="plm", riemann="hlld",
+                          integrator="vl2", cfl=0.3)
+    tc, tf = torch.from_numpy(mc).to(dev), torch.from_numpy(mf).to(dev)
+    del mc, mf
+    zones = args.n ** 3
+    for _ in range(args.warmup):
+        s.step(tc, tf, s.newdt(tc, tf))
+    torch.cuda.synchronize()
+    s.profile_start()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.step(tc, tf, s.newdt(tc, tf))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stage_ms, launches = s.profile_stop()
+    out = {
+        "metric": "zone-cycles/s, FP64 3D MHD VL2+PLM+HLLD, 1 MI355X, coupled mesh of equal blocks",
+        "value": zones * args.steps / elapsed, "unit": "zone-cycles/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"decaying MHD turbulence {args.n}^3 periodic as {m}^3 blocks of {nb}^3 (nghost 2), "
+                               "ghost exchange between blocks before every stage, VL2+PLM+HLLD+CT, CFL 0.3",
+                   "cells": zones, "blocks": m ** 3, "seed": args.seed},
+        "stage_ms_per_launch": stage_ms / max(launches, 1),
+    }
+    print(json.dumps(out))
+
+
 def bench_blast(args):
     """MHD blast on the 512^3 periodic unit cube (nghost 3, RK3 + PPM + HLLD or
     HLLE + CT, rho = 1, p = 0.1, p = 10 inside r < 0.1 around a seeded centre,
@@ -369,6 +420,9 @@ def main():
         return
     if args.workload == "blast":
         bench_blast(args)
+        return
+    if args.workload == "mesh":
+        bench_mesh(args)
         return
     if args.copy_calibration:
         a = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB

@@ -167,6 +167,28 @@ ATHMHD_API int athmhd_step_stages(athmhd_t h, double* cons, double* bface, doubl
 ATHMHD_API int athmhd_prim2cons_vjp(athmhd_t h, const double* prim, const double* bface, const double* g_cons,
                                     double* g_prim, double* g_bface, int nblocks, void* stream);
 
+/* Coupled mesh: nbx x nby x nbz equal blocks (the block shape of `cfg`)
+ * tiling one periodic domain of (nbx n1) x (nby n2) x (nbz n3) cells (Sec. 2.1:
+ * a Mesh of MeshBlocks; Sec. 2.1.1: neighbouring blocks exchange ghost cells
+ * and faces).  Block b = bx + nbx (by + nby bz) sits at (bx, by, bz); cons and
+ * bface hold the nbx nby nbz blocks one after the other as for athmhd_create,
+ * and nblocks in later calls must equal that count.
+ *   - Before every stage the library fills each block's ghost cells and every
+ *     face entry other than the lower faces of its active cells from the
+ *     block that owns that position (device kernel); each face is therefore
+ *     updated by exactly one block, and shared faces cannot drift apart.
+ *     athmhd_step thus writes the ghost entries of its input; after it they
+ *     hold the last stage's input (athmhd_fill_ghosts refreshes them).
+ *   - athmhd_newdt, athmhd_prim2cons and the floors read the upper faces of a
+ *     block's boundary cells from the neighbouring block, so they do not
+ *     depend on ghost entries.
+ *   - With one block per direction the result equals athmhd_create's
+ *     periodic block; split into several blocks it equals the single block
+ *     covering the whole domain.
+ * Fused kernel path only (kernel_path 0; else ATHMHD_EUNSUP).  Reverse mode and
+ * athmhd_step_stages return ATHMHD_EUNSUP on a mesh handle. */
+ATHMHD_API int athmhd_create_mesh(const athmhd_config* cfg, int nbx, int nby, int nbz, athmhd_t* out);
+
 /* Batched MeshBlocks of uneven sizes (Sec. 2.1: a Mesh of MeshBlocks, each
  * with its own cell count here, advanced with one global dt, Sec. 2.1.6).
  * `base` gives everything but the block shape (its n1..n3 and dx1..dx3 are

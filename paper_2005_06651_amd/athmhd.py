@@ -22,7 +22,7 @@ EXPORTED = ["athmhd_version", "athmhd_create", "athmhd_create_batch", "athmhd_ba
             "athmhd_batch_set_tile", "athmhd_batch_tune", "athmhd_set_graph", "athmhd_step", "athmhd_newdt",
             "athmhd_prim2cons", "athmhd_fill_ghosts", "athmhd_profile", "athmhd_last_error", "athmhd_destroy",
             "athmhd_step_vjp", "athmhd_prim2cons_vjp", "athmhd_set_floors", "athmhd_floor_count",
-            "athmhd_step_stages"]
+            "athmhd_step_stages", "athmhd_create_mesh"]
 BATCH_TILES = [(16, 12), (12, 16), (14, 14), (16, 8)]  # active columns of the batch tile candidates
 
 
@@ -57,6 +57,7 @@ def lib():
         vp = C.c_void_p
         L.athmhd_version.restype = C.c_int
         L.athmhd_create.argtypes = [C.POINTER(Config), C.c_int, C.POINTER(vp)]
+        L.athmhd_create_mesh.argtypes = [C.POINTER(Config), C.c_int, C.c_int, C.c_int, C.POINTER(vp)]
         L.athmhd_create_batch.argtypes = [C.POINTER(Config), C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int,
                                           C.POINTER(vp)]
         L.athmhd_batch_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
@@ -272,6 +273,27 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+class MeshSolver(Solver):
+    """A coupled mesh: mesh = (nbx, nby, nbz) equal blocks of n cells tiling one
+    periodic domain; block b = bx + nbx (by + nby bz).  Tensors hold all
+    blocks: cons (nb, 5, N3, N2, N1), bface (nb, 3, N3+1, N2+1, N1+1).  Before
+    every stage the library exchanges ghost cells and faces between the
+    blocks (see athmhd_create_mesh)."""
+
+    def __init__(self, n, mesh, nghost, dx, gamma, recon="plm", riemann="hlld", integrator="vl2", cfl=0.3,
+                 ct_eps=0.0):
+        self.n = tuple(int(x) for x in n)
+        self.mesh = tuple(int(x) for x in mesh)
+        self.ng = int(nghost)
+        self.nblocks = self.mesh[0] * self.mesh[1] * self.mesh[2]
+        self.cfg = make_config(n, nghost, dx, gamma, recon, riemann, integrator, cfl, ct_eps, "fused")
+        h = C.c_void_p()
+        rc = lib().athmhd_create_mesh(C.byref(self.cfg), self.mesh[0], self.mesh[1], self.mesh[2], C.byref(h))
+        if rc != OK:
+            raise AthmhdError(rc, lib().athmhd_last_error(None).decode(errors="replace"))
+        self._h = h
 
 
 class BatchSolver:

@@ -25,6 +25,9 @@ struct athmhd_s {
   // uniform handle: nbmax identical blocks of geometry g
   Geo g;
   int nbmax = 0;
+  // coupled mesh (athmhd_create_mesh): the nbmax blocks tile one periodic
+  // domain as g.mesh[0] x g.mesh[1] x g.mesh[2]
+  bool mesh = false;
   // batched handle: blocks of their own sizes, concatenated in the arrays
   bool batch = false;
   int nbatch = 0;
@@ -158,6 +161,9 @@ int check_call(athmhd_t h, const void* a, const void* b, int nb) {
   if (h->batch) {
     if (nb != h->nbatch)
       return fail(h, ATHMHD_EINVAL, "nblocks must equal the batch size %d (got %d)", h->nbatch, nb);
+  } else if (h->mesh) {
+    if (nb != h->nbmax)
+      return fail(h, ATHMHD_EINVAL, "nblocks must equal the mesh's block count %d (got %d)", h->nbmax, nb);
   } else if (nb < 1 || nb > h->nbmax) {
     return fail(h, ATHMHD_EINVAL, "nblocks %d outside [1, %d]", nb, h->nbmax);
   }
@@ -275,6 +281,7 @@ hipError_t launch_stage(athmhd_t h, int recon, const double* xc, const double* x
 
 hipError_t fill_ghosts(athmhd_t h, double* cons, double* bface, int nblocks, hipStream_t s) {
   if (h->batch) return launch_fill_ghosts_batch(h->d_desc, h->nbatch, h->max_shell, cons, bface, s);
+  if (h->mesh) return launch_mesh_ghosts(h->g, cons, bface, s);
   return launch_fill_ghosts(h->g, cons, bface, nblocks, s);
 }
 
@@ -290,8 +297,9 @@ int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const doubl
   const double* xb = bface;
   hipError_t e;
   // the fused kernels read periodic images directly; the unfused pipeline
-  // reads ghost entries, which are filled before each of its stages
-  const bool ghosts = h->cfg.kernel_path == 1 && !h->batch;
+  // and the blocks of a coupled mesh read ghost entries, which are filled
+  // (exchanged between the mesh's blocks) before each stage
+  const bool ghosts = (h->cfg.kernel_path == 1 && !h->batch) || h->mesh;
   for (int st = 0; st < sc.nstage; ++st) {
     if (ghosts && (e = fill_ghosts(h, const_cast<double*>(xc), const_cast<double*>(xb), nblocks, s)) != hipSuccess)
       return hip_fail(h, e, "fill_ghosts launch");
@@ -418,7 +426,7 @@ int alloc_adjoint(athmhd_t h) {
 
 extern "C" {
 
-int athmhd_version(void) { return 102; }
+int athmhd_version(void) { return 103; }
 
 int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
   if (!out) return fail(nullptr, ATHMHD_EINVAL, "out is NULL");
@@ -470,6 +478,24 @@ int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
     return fail(nullptr, ATHMHD_EHIP, "initialisation: %s", hipGetErrorString(e));
   }
   *out = h;
+  return ATHMHD_OK;
+}
+
+int athmhd_create_mesh(const athmhd_config* cfg, int nbx, int nby, int nbz, athmhd_t* out) {
+  if (!out) return fail(nullptr, ATHMHD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nbx < 1 || nby < 1 || nbz < 1)
+    return fail(nullptr, ATHMHD_EINVAL, "blocks per direction must be >= 1 (got %d %d %d)", nbx, nby, nbz);
+  const double nb = (double)nbx * nby * nbz;
+  if (nb > 1048576.0) return fail(nullptr, ATHMHD_EINVAL, "more than 2^20 blocks");
+  if (cfg && cfg->kernel_path != 0) return fail(nullptr, ATHMHD_EUNSUP, "a coupled mesh runs the fused kernels only");
+  int rc = athmhd_create(cfg, (int)nb, out);
+  if (rc != ATHMHD_OK) return rc;
+  athmhd_t h = *out;
+  h->mesh = true;
+  h->g.mesh[0] = nbx;
+  h->g.mesh[1] = nby;
+  h->g.mesh[2] = nbz;
   return ATHMHD_OK;
 }
 
@@ -708,7 +734,7 @@ int athmhd_step_vjp(athmhd_t h, const double* cons_n, const double* bface_n, dou
                     int nblocks, void* stream) {
   int rc = check_call(h, cons_n, bface_n, nblocks);
   if (rc) return rc;
-  if (h->batch) return fail(h, ATHMHD_EUNSUP, "reverse mode is available for uniform handles only");
+  if (h->batch || h->mesh) return fail(h, ATHMHD_EUNSUP, "reverse mode is available for uniform handles only");
   if (h->floors.on()) return fail(h, ATHMHD_EUNSUP, "reverse mode is not available with floors");
   if (!g_cons_np1 || !g_bface_np1 || !g_cons_n || !g_bface_n) return fail(h, ATHMHD_EINVAL, "NULL cotangent array");
   if (g_cons_n == cons_n || g_bface_n == bface_n || g_cons_n == (const double*)bface_n ||
@@ -767,7 +793,7 @@ int athmhd_prim2cons_vjp(athmhd_t h, const double* prim, const double* bface, co
                          double* g_bface, int nblocks, void* stream) {
   int rc = check_call(h, prim, bface, nblocks);
   if (rc) return rc;
-  if (h->batch) return fail(h, ATHMHD_EUNSUP, "reverse mode is available for uniform handles only");
+  if (h->batch || h->mesh) return fail(h, ATHMHD_EUNSUP, "reverse mode is available for uniform handles only");
   if (!g_cons || !g_prim || !g_bface) return fail(h, ATHMHD_EINVAL, "NULL cotangent array");
   if (g_prim == g_cons || g_prim == prim) return fail(h, ATHMHD_EINVAL, "g_prim must not alias g_cons or prim");
   hipError_t e = launch_prim2cons_vjp(h->g, h->cfg.gamma, prim, bface, g_cons, g_prim, g_bface, nblocks,
@@ -779,7 +805,7 @@ int athmhd_step_stages(athmhd_t h, double* cons, double* bface, double dt, doubl
                        void* stream) {
   int rc = check_call(h, cons, bface, nblocks);
   if (rc) return rc;
-  if (h->batch) return fail(h, ATHMHD_EUNSUP, "stage recording is available for uniform handles only");
+  if (h->batch || h->mesh) return fail(h, ATHMHD_EUNSUP, "stage recording is available for uniform handles only");
   if (!stages) return fail(h, ATHMHD_EINVAL, "NULL stages");
   if (!(std::isfinite(dt) && dt > 0.0)) return fail(h, ATHMHD_EINVAL, "dt must be finite and > 0 (got %g)", dt);
   return enqueue_step(h, cons, bface, dt, nullptr, nblocks, (hipStream_t)stream, stages);

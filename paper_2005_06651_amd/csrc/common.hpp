@@ -20,6 +20,11 @@ struct Geo {
   int64_t cblock;  // 5 * cvar: stride between blocks in cons
   int64_t fblock;  // 3 * fvar: stride between blocks in bface
   double dx1, dx2, dx3;
+  // Blocks per direction of a coupled mesh: equal blocks that tile one
+  // periodic domain, block b at (b mod m0, (b / m0) mod m1, b / (m0 m1)), each
+  // reading its neighbours' cells through its ghost entries (Sec. 2.1.1).
+  // All 0: every block is its own periodic neighbour.
+  int mesh[3];
 
   __host__ __device__ __forceinline__ int c(int i, int j, int k) const { return (k * N2 + j) * N1 + i; }
   __host__ __device__ __forceinline__ int f(int i, int j, int k) const { return (k * F2 + j) * F1 + i; }
@@ -35,6 +40,7 @@ inline Geo make_geo(int n1, int n2, int n3, int ng, double dx1, double dx2, doub
   g.cblock = 5 * g.cvar;
   g.fblock = 3 * g.fvar;
   g.dx1 = dx1; g.dx2 = dx2; g.dx3 = dx3;
+  g.mesh[0] = g.mesh[1] = g.mesh[2] = 0;
   return g;
 }
 
@@ -59,6 +65,18 @@ __host__ __device__ __forceinline__ int wrap_index(int idx, int n, int ng) {
   int r = (idx - ng) % n;
   if (r < 0) r += n;
   return ng + r;
+}
+
+// The next block (+1) along direction D from block b of a coupled mesh,
+// periodic over the mesh; b itself when blocks are their own periodic
+// neighbours.
+template <int D>
+__host__ __device__ __forceinline__ int next_block(const Geo& g, int b) {
+  const int m0 = g.mesh[0], m1 = g.mesh[1], m2 = g.mesh[2];
+  if (m0 <= 0 || m1 <= 0 || m2 <= 0) return b;
+  if (D == 0) return (b % m0 == m0 - 1) ? b - (m0 - 1) : b + 1;
+  if (D == 1) return ((b / m0) % m1 == m1 - 1) ? b - (m1 - 1) * m0 : b + m0;
+  return (b / (m0 * m1) == m2 - 1) ? b - (m2 - 1) * m0 * m1 : b + m0 * m1;
 }
 
 }  // namespace athmhd

@@ -61,9 +61,100 @@ __global__ void __launch_bounds__(kThreads) k_fill_ghosts(Geo g, double* __restr
   for (int c = 0; c < 3; ++c) fb[c * g.fvar + d] = fb[c * g.fvar + s];
 }
 
+// Ghost exchange of a coupled mesh (Sec. 2.1.1): every stored entry of block
+// b outside its active box (ghost cells, and faces other than the lower faces
+// of its active cells) takes the value of the active entry that owns that
+// position in the periodic domain tiled by the blocks: an active cell, or the
+// lower face of an active cell, of this or a neighbouring block.  The shell
+// enumeration is k_fill_ghosts'; sources are active entries only, so every
+// destination is written once from data this kernel does not change.
+__global__ void __launch_bounds__(kThreads) k_mesh_ghosts(Geo g, double* __restrict__ cons,
+                                                         double* __restrict__ bface) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t nz = (int64_t)(g.F3 - g.n3) * g.F2 * g.F1;
+  const int64_t ny = (int64_t)g.n3 * (g.F2 - g.n2) * g.F1;
+  const int64_t nx = (int64_t)g.n3 * g.n2 * (g.F1 - g.n1);
+  int x[3];
+  if (t < nz) {
+    x[0] = (int)(t % g.F1);
+    const int64_t r = t / g.F1;
+    x[1] = (int)(r % g.F2);
+    x[2] = ghost_index((int)(r / g.F2), g.n3, g.ng);
+  } else if (t < nz + ny) {
+    const int64_t u = t - nz;
+    x[0] = (int)(u % g.F1);
+    const int64_t r = u / g.F1;
+    x[1] = ghost_index((int)(r % (g.F2 - g.n2)), g.n2, g.ng);
+    x[2] = g.ng + (int)(r / (g.F2 - g.n2));
+  } else if (t < nz + ny + nx) {
+    const int64_t u = t - nz - ny;
+    x[0] = ghost_index((int)(u % (g.F1 - g.n1)), g.n1, g.ng);
+    const int64_t r = u / (g.F1 - g.n1);
+    x[1] = g.ng + (int)(r % g.n2);
+    x[2] = g.ng + (int)(r / g.n2);
+  } else {
+    return;
+  }
+  const int b = blockIdx.y;
+  const int bc[3] = {b % g.mesh[0], (b / g.mesh[0]) % g.mesh[1], b / (g.mesh[0] * g.mesh[1])};
+  const int n[3] = {g.n1, g.n2, g.n3};
+  int sx[3], sb[3];
+  for (int d = 0; d < 3; ++d) {
+    const int len = g.mesh[d] * n[d];  // domain cells along d
+    int p = bc[d] * n[d] + x[d] - g.ng;
+    p = ((p % len) + len) % len;
+    sb[d] = p / n[d];
+    sx[d] = g.ng + p % n[d];
+  }
+  const int src = sb[0] + g.mesh[0] * (sb[1] + g.mesh[1] * sb[2]);
+  const double* sc = cons + (int64_t)src * g.cblock;
+  const double* sf = bface + (int64_t)src * g.fblock;
+  double* dc = cons + (int64_t)b * g.cblock;
+  double* df = bface + (int64_t)b * g.fblock;
+  if (x[0] < g.N1 && x[1] < g.N2 && x[2] < g.N3) {
+    const int d = g.c(x[0], x[1], x[2]), s = g.c(sx[0], sx[1], sx[2]);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) dc[v * g.cvar + d] = sc[v * g.cvar + s];
+  }
+  const int d = g.f(x[0], x[1], x[2]), s = g.f(sx[0], sx[1], sx[2]);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) df[c * g.fvar + d] = sf[c * g.fvar + s];
+}
+
 inline int64_t ghost_count(const Geo& g) {
   return (int64_t)(g.F3 - g.n3) * g.F2 * g.F1 + (int64_t)g.n3 * (g.F2 - g.n2) * g.F1 +
          (int64_t)g.n3 * g.n2 * (g.F1 - g.n1);
+}
+
+// Cell-centred field of active cell (i, j, k) of block b: the mean of its
+// lower and upper faces.  An upper face on the block's upper boundary is the
+// lower boundary face of the next block along that direction (the block
+// itself when it is its own periodic neighbour) and is read there, not from
+// the stored image entries, which a step does not refresh.  fb: this block's
+// face arrays; all_fb: block 0's (read by coupled meshes only; other callers
+// pass fb).
+__device__ __forceinline__ void cell_field(const Geo& g, const double* fb, const double* all_fb, int b, int i, int j,
+                                           int k, double& b1, double& b2, double& b3) {
+  const int f = g.f(i, j, k);
+  const double* p1 = fb;
+  const double* p2 = fb;
+  const double* p3 = fb;
+  int iu = i + 1, ju = j + 1, ku = k + 1;
+  if (iu == g.ng + g.n1) {
+    iu = g.ng;
+    if (g.mesh[0]) p1 = all_fb + next_block<0>(g, b) * g.fblock;
+  }
+  if (ju == g.ng + g.n2) {
+    ju = g.ng;
+    if (g.mesh[0]) p2 = all_fb + next_block<1>(g, b) * g.fblock;
+  }
+  if (ku == g.ng + g.n3) {
+    ku = g.ng;
+    if (g.mesh[0]) p3 = all_fb + next_block<2>(g, b) * g.fblock;
+  }
+  b1 = 0.5 * (fb[f] + p1[g.f(iu, j, k)]);
+  b2 = 0.5 * (fb[g.fvar + f] + p2[g.fvar + g.f(i, ju, k)]);
+  b3 = 0.5 * (fb[2 * g.fvar + f] + p3[2 * g.fvar + g.f(i, j, ku)]);
 }
 
 // Conserved variables from primitives with the cell-centred field (mean of the
@@ -79,9 +170,14 @@ __global__ void __launch_bounds__(kThreads) k_prim2cons(Geo g, double gamma, con
   const double* w = prim + blockIdx.y * g.cblock;
   const double* fb = bface + blockIdx.y * g.fblock;
   double* u = cons + blockIdx.y * g.cblock;
-  const double b1 = 0.5 * (fb[g.f(i, j, k)] + fb[g.f(i + 1, j, k)]);
-  const double b2 = 0.5 * (fb[g.fvar + g.f(i, j, k)] + fb[g.fvar + g.f(i, j + 1, k)]);
-  const double b3 = 0.5 * (fb[2 * g.fvar + g.f(i, j, k)] + fb[2 * g.fvar + g.f(i, j, k + 1)]);
+  double b1, b2, b3;
+  if (i >= g.ng && i < g.ng + g.n1 && j >= g.ng && j < g.ng + g.n2 && k >= g.ng && k < g.ng + g.n3) {
+    cell_field(g, fb, bface, blockIdx.y, i, j, k, b1, b2, b3);
+  } else {  // ghost cells: their stored faces
+    b1 = 0.5 * (fb[g.f(i, j, k)] + fb[g.f(i + 1, j, k)]);
+    b2 = 0.5 * (fb[g.fvar + g.f(i, j, k)] + fb[g.fvar + g.f(i, j + 1, k)]);
+    b3 = 0.5 * (fb[2 * g.fvar + g.f(i, j, k)] + fb[2 * g.fvar + g.f(i, j, k + 1)]);
+  }
   const double rho = w[t], v1 = w[g.cvar + t], v2 = w[2 * g.cvar + t], v3 = w[3 * g.cvar + t];
   const double p = w[4 * g.cvar + t];
   u[t] = rho;
@@ -89,19 +185,6 @@ __global__ void __launch_bounds__(kThreads) k_prim2cons(Geo g, double gamma, con
   u[2 * g.cvar + t] = rho * v2;
   u[3 * g.cvar + t] = rho * v3;
   u[4 * g.cvar + t] = p / (gamma - 1.0) + 0.5 * rho * (v1 * v1 + v2 * v2 + v3 * v3) + 0.5 * (b1 * b1 + b2 * b2 + b3 * b3);
-}
-
-// Indices of the upper x1-, x2- and x3-faces of active cell (i, j, k).  The
-// block is its own periodic neighbour, so the upper faces on its boundary are
-// the periodic images of its lower boundary faces; they are read there, not
-// from the stored image entries, which a step does not refresh.
-__device__ __forceinline__ void upper_faces(const Geo& g, int i, int j, int k, int& f1, int& f2, int& f3) {
-  const int iu = i + 1 < g.ng + g.n1 ? i + 1 : g.ng;
-  const int ju = j + 1 < g.ng + g.n2 ? j + 1 : g.ng;
-  const int ku = k + 1 < g.ng + g.n3 ? k + 1 : g.ng;
-  f1 = g.f(iu, j, k);
-  f2 = g.f(i, ju, k);
-  f3 = g.f(i, j, ku);
 }
 
 // Smallest dx_d / (|v_d| + c_f,d) over the active cells (Sec. 2.1.6, Sec. 3.2.3).
@@ -124,12 +207,9 @@ __global__ void __launch_bounds__(kThreads) k_newdt(Geo g, double gamma, Floors 
     const int i = g.ng + t % g.n1;
     const int r = t / g.n1;
     const int j = g.ng + r % g.n2, k = g.ng + r / g.n2;
-    const int q = g.c(i, j, k), f = g.f(i, j, k);
-    int f1, f2, f3;
-    upper_faces(g, i, j, k, f1, f2, f3);
-    const double b1 = 0.5 * (fb[f] + fb[f1]);
-    const double b2 = 0.5 * (fb[g.fvar + f] + fb[g.fvar + f2]);
-    const double b3 = 0.5 * (fb[2 * g.fvar + f] + fb[2 * g.fvar + f3]);
+    const int q = g.c(i, j, k);
+    double b1, b2, b3;
+    cell_field(g, fb, bface, blockIdx.y, i, j, k, b1, b2, b3);
     const double uc[5] = {u[q], u[g.cvar + q], u[2 * g.cvar + q], u[3 * g.cvar + q], u[4 * g.cvar + q]};
     const double bc[3] = {b1, b2, b3};
     double w[5];
@@ -162,15 +242,13 @@ __global__ void __launch_bounds__(kThreads) k_newdt(Geo g, double gamma, Floors 
 // Floors on the conserved state after a stage (floors enabled only): density
 // below the floor is raised to it, and where the pressure implied by (U, B)
 // is below the pressure floor the total energy is raised to give exactly that
-// pressure.  The cell-centred field uses the lower face and the periodic image
-// of the upper one.  Changed cells are counted in bad[1].
+// pressure.  The cell-centred field is that of cell_field.  Changed cells are
+// counted in bad[1].
 __device__ __forceinline__ int floor_cell(const Geo& g, double gm1, const Floors& fl, double* u,
-                                          const double* fb, int i, int j, int k) {
-  const int q = g.c(i, j, k), f = g.f(i, j, k);
-  const int iu = wrap_index(i + 1, g.n1, g.ng), ju = wrap_index(j + 1, g.n2, g.ng), ku = wrap_index(k + 1, g.n3, g.ng);
-  const double b1 = 0.5 * (fb[f] + fb[g.f(iu, j, k)]);
-  const double b2 = 0.5 * (fb[g.fvar + f] + fb[g.fvar + g.f(i, ju, k)]);
-  const double b3 = 0.5 * (fb[2 * g.fvar + f] + fb[2 * g.fvar + g.f(i, j, ku)]);
+                                          const double* fb, const double* all_fb, int b, int i, int j, int k) {
+  const int q = g.c(i, j, k);
+  double b1, b2, b3;
+  cell_field(g, fb, all_fb, b, i, j, k, b1, b2, b3);
   int hit = 0;
   double rho = u[q];
   if (!(rho >= fl.d)) {
@@ -197,7 +275,7 @@ __global__ void __launch_bounds__(kThreads) k_floor_state(Geo g, double gm1, Flo
   const int i = g.ng + (int)(t % g.n1);
   const int r = (int)(t / g.n1);
   const int j = g.ng + r % g.n2, k = g.ng + r / g.n2;
-  if (floor_cell(g, gm1, fl, cons + blockIdx.y * g.cblock, bface + blockIdx.y * g.fblock, i, j, k))
+  if (floor_cell(g, gm1, fl, cons + blockIdx.y * g.cblock, bface + blockIdx.y * g.fblock, bface, blockIdx.y, i, j, k))
     atomicAdd(bad + 1, 1);
 }
 
@@ -213,7 +291,7 @@ __global__ void __launch_bounds__(kThreads) k_floor_state_batch(const BatchDesc*
     const int i = g.ng + (int)(t % g.n1);
     const int r = (int)(t / g.n1);
     const int j = g.ng + r % g.n2, k = g.ng + r / g.n2;
-    hits += floor_cell(g, gm1, fl, cons + d.coff, bface + d.foff, i, j, k);
+    hits += floor_cell(g, gm1, fl, cons + d.coff, bface + d.foff, bface + d.foff, 0, i, j, k);
   }
   if (hits) atomicAdd(bad + 1, hits);
 }
@@ -313,12 +391,9 @@ __global__ void __launch_bounds__(kThreads) k_newdt_batch(const BatchDesc* __res
     const int i = g.ng + t % g.n1;
     const int r = t / g.n1;
     const int j = g.ng + r % g.n2, k = g.ng + r / g.n2;
-    const int q = g.c(i, j, k), f = g.f(i, j, k);
-    int f1, f2, f3;
-    upper_faces(g, i, j, k, f1, f2, f3);
-    const double b1 = 0.5 * (fb[f] + fb[f1]);
-    const double b2 = 0.5 * (fb[g.fvar + f] + fb[g.fvar + f2]);
-    const double b3 = 0.5 * (fb[2 * g.fvar + f] + fb[2 * g.fvar + f3]);
+    const int q = g.c(i, j, k);
+    double b1, b2, b3;
+    cell_field(g, fb, fb, 0, i, j, k, b1, b2, b3);  // batched blocks: their own neighbours
     const double uc[5] = {u[q], u[g.cvar + q], u[2 * g.cvar + q], u[3 * g.cvar + q], u[4 * g.cvar + q]};
     const double bc[3] = {b1, b2, b3};
     double w[5];
@@ -389,6 +464,12 @@ hipError_t launch_floor_state_batch(const BatchDesc* desc, int nblocks, double g
 
 hipError_t launch_fill_ghosts(const Geo& g, double* cons, double* bface, int nb, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_ghosts, dim3(grid_for(ghost_count(g)), nb), dim3(kThreads), 0, s, g, cons, bface);
+  return hipGetLastError();
+}
+
+hipError_t launch_mesh_ghosts(const Geo& g, double* cons, double* bface, hipStream_t s) {
+  const int nb = g.mesh[0] * g.mesh[1] * g.mesh[2];
+  hipLaunchKernelGGL(k_mesh_ghosts, dim3(grid_for(ghost_count(g)), nb), dim3(kThreads), 0, s, g, cons, bface);
   return hipGetLastError();
 }
 

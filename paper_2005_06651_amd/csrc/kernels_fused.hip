@@ -107,20 +107,31 @@ struct Raw {
   double b1lo, b1hi, b2lo, b2hi, b3lo, b3hi;
 };
 
-// Periodic column of a block: wrapped indices of a column and of its upper
-// neighbours along x1 and x2.  Every block is its own periodic neighbour, so
-// the stage kernel reads the periodic images directly and never needs the
-// ghost entries of its input.
+// Column of a block: stored indices of a column and of its upper neighbours
+// along x1 and x2.  A block that is its own periodic neighbour is read at the
+// periodic images directly, so its ghost entries are never needed; the blocks
+// of a coupled mesh read their ghost entries, which the mesh exchange fills
+// before every stage.
 struct Col {
   int i0, i1, j0, j1;
 };
 
+// Stored index read for position idx (cell, or face when hi = N) along a
+// direction with n active cells: its periodic image when the block is its own
+// neighbour, else the stored entry itself (ghosts filled by the mesh
+// exchange), clamped into the array for the columns of a ragged tile past the
+// block edge, whose results are never written out.
+__device__ __forceinline__ int read_index(const Geo& g, int idx, int n, int hi) {
+  if (g.mesh[0] == 0) return wrap_index(idx, n, g.ng);
+  return idx < 0 ? 0 : (idx > hi ? hi : idx);
+}
+
 __device__ __forceinline__ Col make_col(const Geo& g, int i, int j) {
   Col c;
-  c.i0 = wrap_index(i, g.n1, g.ng);
-  c.i1 = wrap_index(i + 1, g.n1, g.ng);
-  c.j0 = wrap_index(j, g.n2, g.ng);
-  c.j1 = wrap_index(j + 1, g.n2, g.ng);
+  c.i0 = read_index(g, i, g.n1, g.N1 - 1);
+  c.i1 = read_index(g, i + 1, g.n1, g.N1);
+  c.j0 = read_index(g, j, g.n2, g.N2 - 1);
+  c.j1 = read_index(g, j + 1, g.n2, g.N2);
   return c;
 }
 
@@ -128,7 +139,7 @@ __device__ __forceinline__ Col make_col(const Geo& g, int i, int j) {
 // (unwrapped) plane k.
 __device__ __forceinline__ void load_raw(const Geo& g, const double* __restrict__ xc, const double* __restrict__ xb,
                                          const Col& c, int k, Raw& r) {
-  const int k0 = wrap_index(k, g.n3, g.ng), k1 = wrap_index(k + 1, g.n3, g.ng);
+  const int k0 = read_index(g, k, g.n3, g.N3 - 1), k1 = read_index(g, k + 1, g.n3, g.N3);
   const int q = g.c(c.i0, c.j0, k0);
 #pragma unroll
   for (int v = 0; v < 5; ++v) r.u[v] = xc[v * g.cvar + q];

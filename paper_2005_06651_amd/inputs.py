@@ -448,6 +448,50 @@ def amr_batch(nblocks: int = 1024, seed: int = 3, sizes=(16, 24, 32), fractions=
     return blocks
 
 
+def split_mesh(cells: np.ndarray, faces: np.ndarray, ng: int, n_block, mesh):
+    """Cut a periodic domain (one block of mesh[d] * n_block[d] cells, with ng
+    ghost layers: cells (nv, N3, N2, N1), faces (3, N3+1, N2+1, N1+1)) into the
+    blocks of a coupled mesh, block b = bx + nbx (by + nby bz), each with its
+    own ng ghost layers taken from the periodic domain.  Returns arrays of
+    shape (nb, nv, ...) and (nb, 3, ...).  Index arithmetic only."""
+    n1, n2, n3 = n_block
+    L = (mesh[0] * n1, mesh[1] * n2, mesh[2] * n3)
+    M = (n1 + 2 * ng, n2 + 2 * ng, n3 + 2 * ng)
+    out_c, out_f = [], []
+    for bz in range(mesh[2]):
+        for by in range(mesh[1]):
+            for bx in range(mesh[0]):
+                o = (bx * n1, by * n2, bz * n3)
+                ci = [ng + (np.arange(M[d]) + o[d] - ng) % L[d] for d in range(3)]
+                fi = [ng + (np.arange(M[d] + 1) + o[d] - ng) % L[d] for d in range(3)]
+                out_c.append(cells[:, ci[2][:, None, None], ci[1][None, :, None], ci[0][None, None, :]])
+                out_f.append(faces[:, fi[2][:, None, None], fi[1][None, :, None], fi[0][None, None, :]])
+    return np.ascontiguousarray(np.stack(out_c)), np.ascontiguousarray(np.stack(out_f))
+
+
+def join_mesh(cells: np.ndarray, faces: np.ndarray, ng: int, n_block, mesh):
+    """Inverse of split_mesh on the active entries: the blocks' active cells and
+    the lower faces of their active cells, placed into a periodic domain
+    block of (mesh[d] * n_block[d]) cells with ng ghost layers (ghost and image
+    entries left zero)."""
+    n1, n2, n3 = n_block
+    nb, nv = cells.shape[:2]
+    L = (mesh[0] * n1, mesh[1] * n2, mesh[2] * n3)
+    dc = np.zeros((nv, L[2] + 2 * ng, L[1] + 2 * ng, L[0] + 2 * ng))
+    df = np.zeros((3, L[2] + 2 * ng + 1, L[1] + 2 * ng + 1, L[0] + 2 * ng + 1))
+    a = (slice(ng, ng + n3), slice(ng, ng + n2), slice(ng, ng + n1))
+    b = 0
+    for bz in range(mesh[2]):
+        for by in range(mesh[1]):
+            for bx in range(mesh[0]):
+                d = (slice(ng + bz * n3, ng + (bz + 1) * n3), slice(ng + by * n2, ng + (by + 1) * n2),
+                     slice(ng + bx * n1, ng + (bx + 1) * n1))
+                dc[(slice(None),) + d] = cells[b][(slice(None),) + a]
+                df[(slice(None),) + d] = faces[b][(slice(None),) + a]
+                b += 1
+    return dc, df
+
+
 def pack(arrays) -> np.ndarray:
     """Concatenate per-block arrays into the flat batched layout."""
     return np.concatenate([np.ascontiguousarray(a).reshape(-1) for a in arrays])

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version():
-    assert athmhd.lib().athmhd_version() == 102
+    assert athmhd.lib().athmhd_version() == 103
 
 
 def _create(**over):
@@ -112,6 +112,23 @@ def test_create_batch_rejects_bad_blocks(dims, dxs, over, code, needle):
     rc, msg = _create_batch(dims, dxs, **over)
     assert rc == code
     assert needle in msg
+
+
+@pytest.mark.parametrize("blocks,over,code,needle", [
+    ((0, 2, 2), {}, athmhd.EINVAL, "blocks per direction"),
+    ((2, 2, 2), {"kernel_path": 1}, athmhd.EUNSUP, "fused"),
+    ((2, 2, 2), {"nghost": 1}, athmhd.EINVAL, "nghost"),
+    ((2, 2, 2), {"n1": 0}, athmhd.EINVAL, "block dims"),
+])
+def test_create_mesh_rejects_bad_arguments_before_any_hip_call(blocks, over, code, needle):
+    cfg = athmhd.make_config((8, 8, 8), 2, (0.1, 0.1, 0.1), 5.0 / 3.0)
+    for k, v in over.items():
+        setattr(cfg, k, v)
+    h = C.c_void_p()
+    rc = athmhd.lib().athmhd_create_mesh(C.byref(cfg), *blocks, C.byref(h))
+    assert rc == code
+    assert needle in athmhd.lib().athmhd_last_error(None).decode()
+    assert athmhd.lib().athmhd_create_mesh(C.byref(cfg), 1, 1, 1, None) == athmhd.EINVAL
 
 
 def test_batch_calls_reject_non_batch_use():

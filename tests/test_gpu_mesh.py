@@ -1,0 +1,158 @@
+"""Coupled mesh: equal blocks tiling one periodic domain, with the ghost
+cells and faces exchanged between blocks on the device before every stage
+(Sec. 2.1.1).  Split into blocks, the domain must step as the single block
+that covers it: the same kernels on the same values, so the dt agrees
+exactly and the state to 1e-14 (the x3 segments of the fused kernel fall on
+other planes, and the compiler's copies of the first and last plane of a
+segment may round the face-field update differently by an ulp), and as the
+oracle's single block within the 1e-12 bar, with div B at round-off.
+"""
+import numpy as np
+import pytest
+
+from paper_2005_06651_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def athmhd():
+    from paper_2005_06651_amd import athmhd as A
+    A.lib()
+    return A
+
+
+def to_dev(torch, dev, x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def active(ng, n):
+    return (slice(None), slice(ng, ng + n[2]), slice(ng, ng + n[1]), slice(ng, ng + n[0]))
+
+
+def rel_l1(a, b):
+    """worst relative L1 over the arrays of a (nv, ...) pair"""
+    return max(float(np.abs(a[v] - b[v]).sum() / max(np.abs(b[v]).sum(), 1e-300)) for v in range(a.shape[0]))
+
+
+@pytest.mark.parametrize("mesh,kw", [
+    ((2, 2, 2), dict(integrator="vl2", recon="plm", riemann="hlld")),
+    ((3, 1, 2), dict(integrator="rk3", recon="ppm", riemann="hlle")),
+    ((2, 1, 1), dict(integrator="rk2", recon="dc", riemann="hlld", ct_eps=1e-3)),
+    ((1, 1, 1), dict(integrator="vl2", recon="plm", riemann="hlld")),
+])
+def test_mesh_equals_single_block_and_oracle(torch_dev, athmhd, orc, mesh, kw):
+    """A 36 x 24 x 30 domain as a mesh of blocks: three steps with the CFL dt
+    of the mesh, which must equal the single block's exactly and the
+    oracle's; then the mesh's cells and faces agree with the single GPU
+    block's to 1e-14 and the oracle's within the bar, and div B stays at
+    round-off."""
+    torch, dev = torch_dev
+    ng = 3 if kw["recon"] == "ppm" else 2
+    b = inputs.smooth_random(n=(36, 24, 30), seed=41, ng=ng)
+    nblk = tuple(b.n[d] // mesh[d] for d in range(3))
+    single = athmhd.Solver(b.n, ng, b.dx, b.gamma, **kw)
+    ms = athmhd.MeshSolver(nblk, mesh, ng, b.dx, b.gamma, **kw)
+    cfg = orc.cfg_for(b, **kw)
+    cons = orc.prim2cons(cfg, b.prim, b.bface)
+    mc, mf = inputs.split_mesh(cons, b.bface, ng, nblk, mesh)
+    tmc, tmf = to_dev(torch, dev, mc), to_dev(torch, dev, mf)
+    tsc, tsf = to_dev(torch, dev, cons), to_dev(torch, dev, b.bface)
+    rc, rb = cons.copy(), b.bface.copy()
+    for _ in range(3):
+        dt, bad = orc.newdt(cfg, rc, rb)
+        assert bad == 0
+        mdt = ms.newdt(tmc, tmf)
+        assert mdt == single.newdt(tsc, tsf)
+        assert abs(mdt - dt) <= 1e-14 * dt
+        assert orc.step(cfg, rc, rb, dt) == 0
+        single.step(tsc, tsf, dt)
+        ms.step(tmc, tmf, dt)
+    jc, jf = inputs.join_mesh(tmc.cpu().numpy(), tmf.cpu().numpy(), ng, nblk, mesh)
+    a = active(ng, b.n)
+    sc, sf = tsc.cpu().numpy(), tsf.cpu().numpy()
+    assert max(rel_l1(jc[a], sc[a]), rel_l1(jf[a], sf[a])) <= 1e-14
+    assert max(rel_l1(jc[a], rc[a]), rel_l1(jf[a], rb[a])) <= TOL
+    orc.fill_ghosts(cfg, jc, jf)
+    assert inputs.divb_metric(jf, b.n, ng, b.dx) <= 1e-13
+    ms.close()
+    single.close()
+
+
+def test_mesh_ghost_exchange_is_the_periodic_domain(torch_dev, athmhd, orc):
+    """After the exchange every stored entry of every block (ghost cells, image
+    and ghost faces, padding) equals the entry at the same position of the
+    periodic domain, bitwise, also where a ghost layer is deeper than a
+    block (blocks of 2 cells along x3 with 2 ghost layers)."""
+    torch, dev = torch_dev
+    ng = 2
+    b = inputs.smooth_random(n=(20, 16, 6), seed=42, ng=ng)
+    mesh = (2, 4, 3)
+    nblk = (10, 4, 2)
+    cfg = orc.cfg_for(b)
+    cons = orc.prim2cons(cfg, b.prim, b.bface)
+    want_c, want_f = inputs.split_mesh(cons, b.bface, ng, nblk, mesh)
+    ms = athmhd.MeshSolver(nblk, mesh, ng, b.dx, b.gamma)
+    junk_c, junk_f = np.full_like(want_c, -7.0), np.full_like(want_f, -7.0)
+    a = active(ng, nblk)
+    for blk in range(want_c.shape[0]):
+        junk_c[blk][a] = want_c[blk][a]
+        junk_f[blk][a] = want_f[blk][a]
+    tc, tf = to_dev(torch, dev, junk_c), to_dev(torch, dev, junk_f)
+    ms.fill_ghosts(tc, tf)
+    assert np.array_equal(tc.cpu().numpy(), want_c)
+    assert np.array_equal(tf.cpu().numpy(), want_f)
+    ms.close()
+
+
+def test_mesh_256_as_8x8x8_blocks_of_32(torch_dev, athmhd, orc):
+    """The 256^3 turbulence split into 8^3 blocks of 32^3: two steps agree
+    with the single 256^3 block's to 1e-14, with equal dt, and div B stays at
+    round-off."""
+    torch, dev = torch_dev
+    b = inputs.turbulence(n=256, seed=1)
+    ng, mesh, nblk = b.ng, (8, 8, 8), (32, 32, 32)
+    single = athmhd.Solver(b.n, ng, b.dx, b.gamma)
+    tsf = to_dev(torch, dev, b.bface)
+    tsc = single.prim2cons(to_dev(torch, dev, b.prim), tsf)
+    mc, mf = inputs.split_mesh(tsc.cpu().numpy(), b.bface, ng, nblk, mesh)
+    ms = athmhd.MeshSolver(nblk, mesh, ng, b.dx, b.gamma)
+    tmc, tmf = to_dev(torch, dev, mc), to_dev(torch, dev, mf)
+    del mc, mf
+    for _ in range(2):
+        dt = single.newdt(tsc, tsf)
+        assert ms.newdt(tmc, tmf) == dt
+        single.step(tsc, tsf, dt)
+        ms.step(tmc, tmf, dt)
+    jc, jf = inputs.join_mesh(tmc.cpu().numpy(), tmf.cpu().numpy(), ng, nblk, mesh)
+    a = active(ng, b.n)
+    sc, sf = tsc.cpu().numpy(), tsf.cpu().numpy()
+    assert max(rel_l1(jc[a], sc[a]), rel_l1(jf[a], sf[a])) <= 1e-14
+    orc.fill_ghosts(orc.cfg_for(b), jc, jf)
+    assert inputs.divb_metric(jf, b.n, ng, b.dx) <= 1e-13
+    ms.close()
+    single.close()
+
+
+def test_mesh_rejects_reverse_mode_and_wrong_block_count(torch_dev, athmhd):
+    torch, dev = torch_dev
+    b = inputs.smooth_random(n=(8, 8, 8), seed=43)
+    ms = athmhd.MeshSolver((4, 4, 8), (2, 2, 1), b.ng, b.dx, b.gamma)
+    mc, mf = inputs.split_mesh(np.zeros((5,) + b.prim.shape[1:]), b.bface, b.ng, (4, 4, 8), (2, 2, 1))
+    tmc, tmf = to_dev(torch, dev, mc), to_dev(torch, dev, mf)
+    with pytest.raises(athmhd.AthmhdError) as e:
+        ms.step(tmc[:3].contiguous(), tmf[:3].contiguous(), 1e-3)
+    assert e.value.code == athmhd.EINVAL
+    with pytest.raises(athmhd.AthmhdError) as e:
+        ms.step_stages(tmc, tmf, 1e-3, ms.stages_like(tmc))
+    assert e.value.code == athmhd.EUNSUP
+    ms.close()
