@@ -279,9 +279,10 @@ hipError_t launch_stage(athmhd_t h, int recon, const double* xc, const double* x
                               cf, nblocks, h->scr, h->floors, h->d_bad, s);
 }
 
-hipError_t fill_ghosts(athmhd_t h, double* cons, double* bface, int nblocks, hipStream_t s) {
+// depth: ghost layers a mesh exchange fills (0: all); other handles fill all
+hipError_t fill_ghosts(athmhd_t h, double* cons, double* bface, int nblocks, hipStream_t s, int depth = 0) {
   if (h->batch) return launch_fill_ghosts_batch(h->d_desc, h->nbatch, h->max_shell, cons, bface, s);
-  if (h->mesh) return launch_mesh_ghosts(h->g, cons, bface, s);
+  if (h->mesh) return launch_mesh_ghosts(h->g, depth, cons, bface, s);
   return launch_fill_ghosts(h->g, cons, bface, nblocks, s);
 }
 
@@ -301,7 +302,13 @@ int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const doubl
   // (exchanged between the mesh's blocks) before each stage
   const bool ghosts = (h->cfg.kernel_path == 1 && !h->batch) || h->mesh;
   for (int st = 0; st < sc.nstage; ++st) {
-    if (ghosts && (e = fill_ghosts(h, const_cast<double*>(xc), const_cast<double*>(xb), nblocks, s)) != hipSuccess)
+    // the VL2 predictor always uses donor-cell fluxes (Sec. 3.2.3)
+    const int recon = (h->cfg.integrator == ATHMHD_VL2 && st == 0) ? ATHMHD_RECON_DC : h->cfg.recon;
+    // the fused stage reads recon + 1 cells past the block (the reconstruction
+    // stencil of the ring faces); the unfused pipeline reads every ghost layer
+    const int depth = h->cfg.kernel_path == 0 ? recon + 1 : 0;
+    if (ghosts &&
+        (e = fill_ghosts(h, const_cast<double*>(xc), const_cast<double*>(xb), nblocks, s, depth)) != hipSuccess)
       return hip_fail(h, e, "fill_ghosts launch");
     const bool last = st == sc.nstage - 1;
     double* oc;
@@ -317,8 +324,6 @@ int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const doubl
       oc = r;
       ob = r + h->reg_coff;
     }
-    // the VL2 predictor always uses donor-cell fluxes (Sec. 3.2.3)
-    const int recon = (h->cfg.integrator == ATHMHD_VL2 && st == 0) ? ATHMHD_RECON_DC : h->cfg.recon;
     StageCoef cf{sc.g0[st], sc.g1[st], sc.beta[st] * dt};
     if ((e = mark(h, s)) != hipSuccess) return hip_fail(h, e, "profiling event");
     e = launch_stage(h, recon, xc, xb, cons, bface, oc, ob, cf, sc.beta[st], dt_dev, nblocks, s);

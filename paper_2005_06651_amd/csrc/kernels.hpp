@@ -19,8 +19,9 @@ struct UnfusedScratch {
 };
 
 hipError_t launch_fill_ghosts(const Geo& g, double* cons, double* bface, int nb, hipStream_t s);
-// ghost exchange of the coupled mesh g.mesh[0] x g.mesh[1] x g.mesh[2]
-hipError_t launch_mesh_ghosts(const Geo& g, double* cons, double* bface, hipStream_t s);
+// ghost exchange of the coupled mesh g.mesh[0] x g.mesh[1] x g.mesh[2]: the w
+// ghost layers nearest each block's active box (w outside [1, ng]: all ng)
+hipError_t launch_mesh_ghosts(const Geo& g, int w, double* cons, double* bface, hipStream_t s);
 hipError_t launch_prim2cons(const Geo& g, double gamma, const double* prim, const double* bface, double* cons,
                             int nb, hipStream_t s);
 // dt_bits: device uint64 holding the bit pattern of the running minimum of

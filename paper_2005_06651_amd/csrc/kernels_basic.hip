@@ -67,51 +67,71 @@ __global__ void __launch_bounds__(kThreads) k_fill_ghosts(Geo g, double* __restr
 // position in the periodic domain tiled by the blocks: an active cell, or the
 // lower face of an active cell, of this or a neighbouring block.  The shell
 // enumeration is k_fill_ghosts'; sources are active entries only, so every
-// destination is written once from data this kernel does not change.
-__global__ void __launch_bounds__(kThreads) k_mesh_ghosts(Geo g, double* __restrict__ cons,
+// destination is written once from data this kernel does not change.  With
+// near = 1 (every block has more cells than ghost layers along each
+// direction) the owner is at most one block away and is found without
+// integer division.  Only the w ghost layers nearest the active box (and the
+// faces bounding them) are filled: a stage whose stencil reaches w cells past
+// the block needs no more.
+__global__ void __launch_bounds__(kThreads) k_mesh_ghosts(Geo g, int w, int near, double* __restrict__ cons,
                                                          double* __restrict__ bface) {
-  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const int64_t nz = (int64_t)(g.F3 - g.n3) * g.F2 * g.F1;
-  const int64_t ny = (int64_t)g.n3 * (g.F2 - g.n2) * g.F1;
-  const int64_t nx = (int64_t)g.n3 * g.n2 * (g.F1 - g.n1);
+  const int t = blockIdx.x * kThreads + threadIdx.x;
+  // the filled box: stored indices [ng - w, ng + n + w] (faces), cells below ng + n + w
+  const int E1 = g.n1 + 2 * w + 1, E2 = g.n2 + 2 * w + 1, E3 = g.n3 + 2 * w + 1;
+  const int lo = g.ng - w;
+  const int nz = (E3 - g.n3) * E2 * E1;
+  const int ny = g.n3 * (E2 - g.n2) * E1;
+  const int nx = g.n3 * g.n2 * (E1 - g.n1);
   int x[3];
   if (t < nz) {
-    x[0] = (int)(t % g.F1);
-    const int64_t r = t / g.F1;
-    x[1] = (int)(r % g.F2);
-    x[2] = ghost_index((int)(r / g.F2), g.n3, g.ng);
+    x[0] = lo + t % E1;
+    const int r = t / E1;
+    x[1] = lo + r % E2;
+    x[2] = lo + ghost_index(r / E2, g.n3, w);
   } else if (t < nz + ny) {
-    const int64_t u = t - nz;
-    x[0] = (int)(u % g.F1);
-    const int64_t r = u / g.F1;
-    x[1] = ghost_index((int)(r % (g.F2 - g.n2)), g.n2, g.ng);
-    x[2] = g.ng + (int)(r / (g.F2 - g.n2));
+    const int u = t - nz;
+    x[0] = lo + u % E1;
+    const int r = u / E1;
+    x[1] = lo + ghost_index(r % (E2 - g.n2), g.n2, w);
+    x[2] = g.ng + r / (E2 - g.n2);
   } else if (t < nz + ny + nx) {
-    const int64_t u = t - nz - ny;
-    x[0] = ghost_index((int)(u % (g.F1 - g.n1)), g.n1, g.ng);
-    const int64_t r = u / (g.F1 - g.n1);
-    x[1] = g.ng + (int)(r % g.n2);
-    x[2] = g.ng + (int)(r / g.n2);
+    const int u = t - nz - ny;
+    x[0] = lo + ghost_index(u % (E1 - g.n1), g.n1, w);
+    const int r = u / (E1 - g.n1);
+    x[1] = g.ng + r % g.n2;
+    x[2] = g.ng + r / g.n2;
   } else {
     return;
   }
   const int b = blockIdx.y;
-  const int bc[3] = {b % g.mesh[0], (b / g.mesh[0]) % g.mesh[1], b / (g.mesh[0] * g.mesh[1])};
+  const int m[3] = {g.mesh[0], g.mesh[1], g.mesh[2]};
+  const int bc[3] = {b % m[0], (b / m[0]) % m[1], b / (m[0] * m[1])};
   const int n[3] = {g.n1, g.n2, g.n3};
   int sx[3], sb[3];
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const int len = g.mesh[d] * n[d];  // domain cells along d
-    int p = bc[d] * n[d] + x[d] - g.ng;
-    p = ((p % len) + len) % len;
-    sb[d] = p / n[d];
-    sx[d] = g.ng + p % n[d];
+    const int o = x[d] - g.ng;  // position relative to the block's first active cell
+    if (near) {
+      const int q = o < 0 ? -1 : (o >= n[d] ? 1 : 0);
+      int c = bc[d] + q;
+      c = c < 0 ? c + m[d] : (c >= m[d] ? c - m[d] : c);
+      sb[d] = c;
+      sx[d] = g.ng + o - q * n[d];
+    } else {
+      const int len = m[d] * n[d];  // domain cells along d
+      int p = bc[d] * n[d] + o;
+      p = ((p % len) + len) % len;
+      sb[d] = p / n[d];
+      sx[d] = g.ng + p % n[d];
+    }
   }
-  const int src = sb[0] + g.mesh[0] * (sb[1] + g.mesh[1] * sb[2]);
+  const int src = sb[0] + m[0] * (sb[1] + m[1] * sb[2]);
   const double* sc = cons + (int64_t)src * g.cblock;
   const double* sf = bface + (int64_t)src * g.fblock;
   double* dc = cons + (int64_t)b * g.cblock;
   double* df = bface + (int64_t)b * g.fblock;
-  if (x[0] < g.N1 && x[1] < g.N2 && x[2] < g.N3) {
+  const int hi = g.ng + w;  // cells stop w layers past the active box, faces one entry further
+  if (x[0] < g.n1 + hi && x[1] < g.n2 + hi && x[2] < g.n3 + hi) {
     const int d = g.c(x[0], x[1], x[2]), s = g.c(sx[0], sx[1], sx[2]);
 #pragma unroll
     for (int v = 0; v < 5; ++v) dc[v * g.cvar + d] = sc[v * g.cvar + s];
@@ -467,9 +487,15 @@ hipError_t launch_fill_ghosts(const Geo& g, double* cons, double* bface, int nb,
   return hipGetLastError();
 }
 
-hipError_t launch_mesh_ghosts(const Geo& g, double* cons, double* bface, hipStream_t s) {
+hipError_t launch_mesh_ghosts(const Geo& g, int w, double* cons, double* bface, hipStream_t s) {
+  if (w < 1 || w > g.ng) w = g.ng;
   const int nb = g.mesh[0] * g.mesh[1] * g.mesh[2];
-  hipLaunchKernelGGL(k_mesh_ghosts, dim3(grid_for(ghost_count(g)), nb), dim3(kThreads), 0, s, g, cons, bface);
+  // the owner of a ghost entry is at most one block away when every block has
+  // more cells than the filled layers (the entries reach w + 1 past the block)
+  const int near = g.n1 > w && g.n2 > w && g.n3 > w;
+  const int64_t E1 = g.n1 + 2 * w + 1, E2 = g.n2 + 2 * w + 1, E3 = g.n3 + 2 * w + 1;
+  const int64_t count = (E3 - g.n3) * E2 * E1 + (int64_t)g.n3 * (E2 - g.n2) * E1 + (int64_t)g.n3 * g.n2 * (E1 - g.n1);
+  hipLaunchKernelGGL(k_mesh_ghosts, dim3(grid_for(count), nb), dim3(kThreads), 0, s, g, w, near, cons, bface);
   return hipGetLastError();
 }
 
@@ -482,7 +508,10 @@ hipError_t launch_prim2cons(const Geo& g, double gamma, const double* prim, cons
 hipError_t launch_newdt(const Geo& g, double gamma, const double* cons, const double* bface, int nb,
                         unsigned long long* dt_bits, const Floors& fl, int* bad, hipStream_t s) {
   const int64_t nact = (int64_t)g.n1 * g.n2 * g.n3;
-  const unsigned blocks = (unsigned)std::min<int64_t>(grid_for(nact), kDtBlocks);
+  // about kDtBlocks workgroups in all, so that many small blocks do not
+  // queue tens of thousands of atomics on the one result word
+  const int64_t per_block = std::max<int64_t>(1, kDtBlocks / std::max(nb, 1));
+  const unsigned blocks = (unsigned)std::min<int64_t>(grid_for(nact), per_block);
   hipLaunchKernelGGL(k_newdt, dim3(blocks, nb), dim3(kThreads), 0, s, g, gamma, fl, cons, bface, dt_bits, bad);
   return hipGetLastError();
 }
