@@ -105,7 +105,7 @@ ATHMHD_API int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t
 ATHMHD_API int athmhd_step(athmhd_t h, double* cons, double* bface, double dt, int nblocks, void* stream);
 
 /* Global time step dt = cfl * min over active cells and directions of
- * dx_d / (|v_d| + c_f,d) (Sec. 2.1.6, Sec. 3.2.3), written to *dt_host.
+ * dx_d / (|v_d| + c_f,d) (Sec. 2.1.7, Sec. 3.2.3), written to *dt_host.
  * Synchronises `stream`.  Returns ATHMHD_ENONPHYS if this state or any step
  * since the previous call met a non-physical cell (the flag is then cleared),
  * ATHMHD_EHIP if an asynchronous HIP error is pending. */
@@ -190,7 +190,7 @@ ATHMHD_API int athmhd_prim2cons_vjp(athmhd_t h, const double* prim, const double
 ATHMHD_API int athmhd_create_mesh(const athmhd_config* cfg, int nbx, int nby, int nbz, athmhd_t* out);
 
 /* Batched MeshBlocks of uneven sizes (Sec. 2.1: a Mesh of MeshBlocks, each
- * with its own cell count here, advanced with one global dt, Sec. 2.1.6).
+ * with its own cell count here, advanced with one global dt, Sec. 2.1.7).
  * `base` gives everything but the block shape (its n1..n3 and dx1..dx3 are
  * ignored); dims[3b..3b+2] and dx[3b..3b+2] give block b.  cons and bface of
  * a batched handle are the concatenations of the per-block arrays (block b's
@@ -229,7 +229,7 @@ ATHMHD_API int athmhd_batch_tune(athmhd_t h, const double* cons, const double* b
  *     rho_W = max(rho, dfloor), v = M / rho_W, P_W = max(P, pfloor).
  * Non-physical cells then no longer stop a run (only non-finite values are
  * reported by athmhd_newdt); every activation is counted instead.  The paper
- * names floors only for prolongation (Sec. 2.1.4); they are needed here by
+ * names floors only for prolongation (Sec. 2.1.5); they are needed here by
  * strong blasts in low-beta gas, whose pressure otherwise falls below zero.
  * dfloor and pfloor must be finite and >= 0.  Reverse mode is unavailable with
  * floors. */

@@ -34,7 +34,7 @@
 //   * corner EMFs: the upwind CT average of Gardiner & Stone (2005), with the
 //     upwind direction taken from the sign of the face mass flux; an optional
 //     continuous weight (ct_eps > 0) replaces the three-way switch;
-//   * time step: one global dt from |v| + c_f (Sec. 2.1.6), per direction min;
+//   * time step: one global dt from |v| + c_f (Sec. 2.1.7), per direction min;
 //   * face-B registers follow the same 2S weights as the conserved variables.
 #include <algorithm>
 #include <cmath>
@@ -794,7 +794,7 @@ template <class T> int step(const Cfg& cfg, T* cons, T* bf, double dt) {
 }
 
 // Global time step: C0 times the smallest dx_d / (|v_d| + c_f,d) over the
-// active cells (Sec. 2.1.6 and the CFL limits of Sec. 3.2.3).
+// active cells (Sec. 2.1.7 and the CFL limits of Sec. 3.2.3).
 inline int newdt(const Cfg& cfg, const double* cons, const double* bf, double* dt_out) {
   Geo g(cfg);
   const size_t nc = g.ncell();

@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(kThreads) k_prim2cons(Geo g, double gamma, con
   u[4 * g.cvar + t] = p / (gamma - 1.0) + 0.5 * rho * (v1 * v1 + v2 * v2 + v3 * v3) + 0.5 * (b1 * b1 + b2 * b2 + b3 * b3);
 }
 
-// Smallest dx_d / (|v_d| + c_f,d) over the active cells (Sec. 2.1.6, Sec. 3.2.3).
+// Smallest dx_d / (|v_d| + c_f,d) over the active cells (Sec. 2.1.7, Sec. 3.2.3).
 // Grid-stride loop per thread, wavefront min by cross-lane shuffles, LDS
 // across the workgroup, then one atomicMin per workgroup on the bit pattern
 // (non-negative doubles order like their bits).

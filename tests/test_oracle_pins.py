@@ -360,7 +360,7 @@ def test_conservation_and_flux_invariants(orc, integ, recon, rs):
 @pytest.mark.parametrize("integ,recon,rs", [("vl2", "plm", "hlld"), ("rk3", "ppm", "hlld")])
 def test_divb_preserved(orc, integ, recon, rs):
     """P3: the vector-potential initial field is divergence free to round-off
-    and CT keeps it so (Sec. 2.1.2 / Sec. 3.1)."""
+    and CT keeps it so (Sec. 2.1.4 / Sec. 3.1)."""
     ng = 3 if recon == "ppm" else 2
     b = inputs.smooth_random(n=(10, 12, 8), seed=4, ng=ng)
     assert inputs.divb_metric(b.bface, b.n, b.ng, b.dx) < 1e-15 * 4
