@@ -121,25 +121,28 @@ struct Col {
 // neighbour, else the stored entry itself (ghosts filled by the mesh
 // exchange), clamped into the array for the columns of a ragged tile past the
 // block edge, whose results are never written out.
+template <bool MESH>
 __device__ __forceinline__ int read_index(const Geo& g, int idx, int n, int hi) {
-  if (g.mesh[0] == 0) return wrap_index(idx, n, g.ng);
+  if (!MESH) return wrap_index(idx, n, g.ng);
   return idx < 0 ? 0 : (idx > hi ? hi : idx);
 }
 
+template <bool MESH>
 __device__ __forceinline__ Col make_col(const Geo& g, int i, int j) {
   Col c;
-  c.i0 = read_index(g, i, g.n1, g.N1 - 1);
-  c.i1 = read_index(g, i + 1, g.n1, g.N1);
-  c.j0 = read_index(g, j, g.n2, g.N2 - 1);
-  c.j1 = read_index(g, j + 1, g.n2, g.N2);
+  c.i0 = read_index<MESH>(g, i, g.n1, g.N1 - 1);
+  c.i1 = read_index<MESH>(g, i + 1, g.n1, g.N1);
+  c.j0 = read_index<MESH>(g, j, g.n2, g.N2 - 1);
+  c.j1 = read_index<MESH>(g, j + 1, g.n2, g.N2);
   return c;
 }
 
 // Conserved state and the six bounding face fields of the cell of column c in
 // (unwrapped) plane k.
+template <bool MESH>
 __device__ __forceinline__ void load_raw(const Geo& g, const double* __restrict__ xc, const double* __restrict__ xb,
                                          const Col& c, int k, Raw& r) {
-  const int k0 = read_index(g, k, g.n3, g.N3 - 1), k1 = read_index(g, k + 1, g.n3, g.N3);
+  const int k0 = read_index<MESH>(g, k, g.n3, g.N3 - 1), k1 = read_index<MESH>(g, k + 1, g.n3, g.N3);
   const int q = g.c(c.i0, c.j0, k0);
 #pragma unroll
   for (int v = 0; v < 5; ++v) r.u[v] = xc[v * g.cvar + q];
@@ -262,7 +265,7 @@ __device__ __forceinline__ void face_update(const Geo& g, const double* __restri
 }
 
 // One tile (tile_x, tile_y) of a block over the active planes [k0, kend).
-template <int RECON, int RS, class T, bool FL>
+template <int RECON, int RS, class T, bool FL, bool MESH = false>
 __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, const StageArgs& sa, int tile_x,
                                            int tile_y, int k0, int kend, double* __restrict__ sp,
                                            double* __restrict__ sx, double* __restrict__ sc) {
@@ -285,7 +288,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
   // own column (columns of a ragged tile past the block edge only feed values
   // that are never written out); reads use the periodic images
   const int gi = x0 - 1 + tx, gj = y0 - 1 + ty;
-  const Col own = make_col(g, gi, gj);
+  const Col own = make_col<MESH>(g, gi, gj);
   const bool act = tx >= 1 && tx <= TX && ty >= 1 && ty <= TY && gi < g.ng + g.n1 && gj < g.ng + g.n2;
 
   // ---- extra LDS rings (LA per side): left and right columns (BY cells per
@@ -309,7 +312,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
       rly = side == 0 ? LA - 1 - d : LA + BY + d;
     }
     rl = rly * PW + rlx;
-    rcol = make_col(g, x0 - 1 - LA + rlx, y0 - 1 - LA + rly);
+    rcol = make_col<MESH>(g, x0 - 1 - LA + rlx, y0 - 1 - LA + rly);
   }
 
   const double i1 = 1.0 / g.dx1, i2 = 1.0 / g.dx2, i3 = 1.0 / g.dx3;
@@ -325,7 +328,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
     Raw raw;
 #pragma unroll
     for (int o = 0; o < NW - 1; ++o) {
-      load_raw(g, xc, xb, own, k0 - 1 - LA + o, raw);
+      load_raw<MESH>(g, xc, xb, own, k0 - 1 - LA + o, raw);
       const int f = to_prim<FL>(raw, gm1, sa.fl, w);
       nbad += f & 1;
       nfl += f >> 1;
@@ -338,9 +341,9 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
     }
   }
   Raw pre;   // raw data of the next look-ahead plane
-  load_raw(g, xc, xb, own, k0 - 1 + LA, pre);
+  load_raw<MESH>(g, xc, xb, own, k0 - 1 + LA, pre);
   Raw rpre;  // raw data of this thread's ring cell in the next plane
-  if (ring) load_raw(g, xc, xb, rcol, k0 - 1, rpre);
+  if (ring) load_raw<MESH>(g, xc, xb, rcol, k0 - 1, rpre);
 
   double qz_carry[7];  // left state of the next x3-face (right edge of the cell below)
   double e2x_prev = 0.0, wx_prev = 0.5, e1y_prev = 0.0, wy_prev = 0.5, e1c_prev = 0.0, e2c_prev = 0.0;
@@ -519,8 +522,8 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
     // and the pointwise terms of this iteration's output (U^n, and the stage
     // input where g0 != 0)
     if (p + 1 <= kend) {
-      load_raw(g, xc, xb, own, p + 1 + LA, pre);
-      if (ring) load_raw(g, xc, xb, rcol, p + 1, rpre);
+      load_raw<MESH>(g, xc, xb, own, p + 1 + LA, pre);
+      if (ring) load_raw<MESH>(g, xc, xb, rcol, p + 1, rpre);
     }
     const bool out_cell = act && zface && p - 1 >= k0;
     const bool out_b3 = act && zface && p < kend;
@@ -617,7 +620,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
 // Uniform blocks: one workgroup per (tile, x3 segment, block), XCD-aware:
 // consecutive logical tiles land on the same XCD so that halo overlap hits its
 // L2.
-template <int RECON, int RS, bool FL>
+template <int RECON, int RS, bool FL, bool MESH>
 __global__ void __launch_bounds__(TileU::NT) __attribute__((amdgpu_waves_per_eu(2)))
 k_stage_fused(UniformArgs a) {
   using T = TileU;
@@ -638,7 +641,7 @@ k_stage_fused(UniformArgs a) {
                a.unb + blk * g.fblock, a.oc + blk * g.cblock, a.ob + blk * g.fblock};
   const int k0 = g.ng + seg * a.kz;
   const int kend = min(k0 + a.kz, g.ng + g.n3);
-  stage_tile<RECON, RS, T, FL>(g, bp, a.sa, tile_x, tile_y, k0, kend, sp, sx, sc);
+  stage_tile<RECON, RS, T, FL, MESH>(g, bp, a.sa, tile_x, tile_y, k0, kend, sp, sx, sc);
 }
 
 // Batched blocks of uneven sizes: a persistent grid whose workgroups pull
@@ -664,16 +667,23 @@ __global__ void __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(2)))
   }
 }
 
-template <int RECON>
-hipError_t launch_rs(int rs, const UniformArgs& fa, hipStream_t s) {
+// MESH: the blocks of a coupled mesh read their (exchanged) ghost entries; a
+// compile-time switch, so that the periodic-block kernels keep their code
+template <int RECON, bool MESH>
+hipError_t launch_rs_m(int rs, const UniformArgs& fa, hipStream_t s) {
   const unsigned grid = (unsigned)(8 * fa.per_xcd);
   constexpr int NT = TileU::NT;
   const bool fl = fa.sa.fl.on();
-  if (rs == 1 && fl) hipLaunchKernelGGL((k_stage_fused<RECON, 1, true>), dim3(grid), dim3(NT), 0, s, fa);
-  else if (rs == 1) hipLaunchKernelGGL((k_stage_fused<RECON, 1, false>), dim3(grid), dim3(NT), 0, s, fa);
-  else if (fl) hipLaunchKernelGGL((k_stage_fused<RECON, 0, true>), dim3(grid), dim3(NT), 0, s, fa);
-  else hipLaunchKernelGGL((k_stage_fused<RECON, 0, false>), dim3(grid), dim3(NT), 0, s, fa);
+  if (rs == 1 && fl) hipLaunchKernelGGL((k_stage_fused<RECON, 1, true, MESH>), dim3(grid), dim3(NT), 0, s, fa);
+  else if (rs == 1) hipLaunchKernelGGL((k_stage_fused<RECON, 1, false, MESH>), dim3(grid), dim3(NT), 0, s, fa);
+  else if (fl) hipLaunchKernelGGL((k_stage_fused<RECON, 0, true, MESH>), dim3(grid), dim3(NT), 0, s, fa);
+  else hipLaunchKernelGGL((k_stage_fused<RECON, 0, false, MESH>), dim3(grid), dim3(NT), 0, s, fa);
   return hipGetLastError();
+}
+
+template <int RECON>
+hipError_t launch_rs(int rs, const UniformArgs& fa, hipStream_t s) {
+  return fa.g.mesh[0] ? launch_rs_m<RECON, true>(rs, fa, s) : launch_rs_m<RECON, false>(rs, fa, s);
 }
 
 __global__ void k_zero_u32(unsigned* p) {
