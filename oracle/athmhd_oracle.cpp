@@ -35,7 +35,14 @@
 //     upwind direction taken from the sign of the face mass flux; an optional
 //     continuous weight (ct_eps > 0) replaces the three-way switch;
 //   * time step: one global dt from |v| + c_f (Sec. 2.1.7), per direction min;
-//   * face-B registers follow the same 2S weights as the conserved variables.
+//   * face-B registers follow the same 2S weights as the conserved variables;
+//   * passive scalars (Sec. 3.3.x "Additional Physics", Eq. (passive_scalars)):
+//     the conserved variable is rho C_i and the primitive C_i.  Readings: C_i
+//     is reconstructed like the other primitives, and the flux of rho C_i
+//     through a face is the face mass flux times C_i on the upwind side (the
+//     left state where the mass flux is >= 0, else the right state); with
+//     floors, C_i = (rho C_i) / rho_W with the floored density, and the floor
+//     pass after a stage leaves rho C_i alone.
 #include <algorithm>
 #include <cmath>
 #include <cstddef>
@@ -126,7 +133,8 @@ struct Cfg {
   int32_t n1, n2, n3, ng;       // active cells per direction, ghost layers
   double gamma;                 // adiabatic index, > 1
   double dx1, dx2, dx3;         // uniform Cartesian cell widths
-  int32_t recon, riemann, integrator, pad_;
+  int32_t recon, riemann, integrator;
+  int32_t nscalars;             // passive scalars rho C_i stored after the 5 MHD variables
   double cfl;                   // Courant number C0 used by newdt
   double ct_eps;                // 0: sign switch for the CT upwinding; >0: ramp width
   double dfloor, pfloor;        // optional density / pressure floors (0: off)
@@ -144,8 +152,10 @@ static long long g_floored = 0;
 // two directions transverse to e.
 struct Geo {
   int n[3], ng, N[3];
+  int nv;  // cell arrays of the state: 5 MHD variables, then the passive scalars
   explicit Geo(const Cfg& c) {
     n[0] = c.n1; n[1] = c.n2; n[2] = c.n3; ng = c.ng;
+    nv = 5 + c.nscalars;
     for (int d = 0; d < 3; ++d) N[d] = n[d] + 2 * ng;
   }
   size_t ncell() const { return (size_t)N[0] * N[1] * N[2]; }
@@ -165,7 +175,7 @@ struct Geo {
 // face is stored once.
 // ---------------------------------------------------------------------------
 template <class T> void fill_ghosts(const Geo& g, T* cons, T* bf) {
-  for (int v = 0; v < 5; ++v) {
+  for (int v = 0; v < g.nv; ++v) {
     T* a = cons + (size_t)v * g.ncell();
     for (int k = 0; k < g.N[2]; ++k)
       for (int j = 0; j < g.N[1]; ++j)
@@ -232,6 +242,8 @@ int cons_to_prim(const Geo& g, double gamma, const T* cons, const T* bf, T* w, T
         bcc[0 * nc + q] = b1;
         bcc[1 * nc + q] = b2;
         bcc[2 * nc + q] = b3;
+        // passive scalars: specific densities C_i from the masses rho C_i
+        for (int v = 5; v < g.nv; ++v) w[v * nc + q] = cons[v * nc + q] / rho;
         if (!(val(rho) > 0.0) || !(val(p) > 0.0) || !std::isfinite(val(rho)) || !std::isfinite(val(p)))
           ++bad;
       }
@@ -256,6 +268,7 @@ void prim_to_cons(const Geo& g, double gamma, const T* w, const T* bf, T* cons) 
         cons[3 * nc + q] = rho * v3;
         cons[4 * nc + q] = p / (gamma - 1.0) + 0.5 * rho * (v1 * v1 + v2 * v2 + v3 * v3) +
                            0.5 * (b1 * b1 + b2 * b2 + b3 * b3);
+        for (int v = 5; v < g.nv; ++v) cons[v * nc + q] = rho * w[v * nc + q];
       }
 }
 
@@ -512,7 +525,7 @@ template <class T> struct Work {
 template <class T>
 int spatial_operator(const Cfg& cfg, const Geo& g, int recon, const T* cons, const T* bf, T* du, T* db, Work<T>& wk) {
   const size_t nc = g.ncell(), nf = g.nface();
-  wk.w.assign(5 * nc, T(0.0));
+  wk.w.assign(g.nv * nc, T(0.0));
   wk.bcc.assign(3 * nc, T(0.0));
   int bad = cons_to_prim(g, cfg.gamma, cons, bf, wk.w.data(), wk.bcc.data(), cfg.dfloor, cfg.pfloor);
   const double dx[3] = {cfg.dx1, cfg.dx2, cfg.dx3};
@@ -522,7 +535,7 @@ int spatial_operator(const Cfg& cfg, const Geo& g, int recon, const T* cons, con
   // normal index [s, e+1], transverse indices [s-1, e+1]
   for (int d = 0; d < 3; ++d) {
     const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
-    wk.flux[d].assign(5 * nf, T(0.0));
+    wk.flux[d].assign(g.nv * nf, T(0.0));
     wk.emf_t1[d].assign(nf, T(0.0));
     wk.emf_t2[d].assign(nf, T(0.0));
     wk.wgt[d].assign(nf, T(0.0));
@@ -570,6 +583,19 @@ int spatial_operator(const Cfg& cfg, const Geo& g, int recon, const T* cons, con
           wk.flux[d][(1 + t1) * nf + fi] = fx[2];
           wk.flux[d][(1 + t2) * nf + fi] = fx[3];
           wk.flux[d][4 * nf + fi] = fx[4];
+          // passive scalars: C_i reconstructed on the face like the other
+          // primitives and carried by the mass flux from the upwind side
+          for (int v = 5; v < g.nv; ++v) {
+            T cline[6];
+            for (int o = -3; o <= 2; ++o) {
+              int idx[3] = {i, j, k};
+              idx[d] += o;
+              cline[o + 3] = (o < -sten || o > sten - 1) ? T(0.0) : wk.w[v * nc + g.c(idx[0], idx[1], idx[2])];
+            }
+            T cl, cr;
+            recon_face(recon, &cline[3], cl, cr);
+            wk.flux[d][v * nf + fi] = val(fx[0]) >= 0.0 ? fx[0] * cl : fx[0] * cr;
+          }
           // E = -v x B: the flux of B_t1 along d is -E_t2, that of B_t2 is +E_t1
           wk.emf_t2[d][fi] = -fx[5];
           wk.emf_t1[d][fi] = fx[6];
@@ -641,7 +667,7 @@ int spatial_operator(const Cfg& cfg, const Geo& g, int recon, const T* cons, con
     for (int j = g.s(1); j <= g.e(1); ++j)
       for (int i = g.s(0); i <= g.e(0); ++i) {
         size_t q = g.c(i, j, k);
-        for (int v = 0; v < 5; ++v) {
+        for (int v = 0; v < g.nv; ++v) {
           T sum(0.0);
           for (int d = 0; d < 3; ++d) {
             int up[3] = {i, j, k};
@@ -759,37 +785,38 @@ template <class T> int step(const Cfg& cfg, T* cons, T* bf, double dt) {
   Scheme sc;
   if (!scheme_for(cfg.integrator, sc)) return -1;
   const size_t nc = g.ncell(), nf = g.nface();
-  const size_t n = 5 * nc + 3 * nf;
+  const size_t ncv = g.nv * nc;  // cell part of the state: MHD variables and scalars
+  const size_t n = ncv + 3 * nf;
   std::vector<T> u(n);
-  std::copy(cons, cons + 5 * nc, u.begin());
-  std::copy(bf, bf + 3 * nf, u.begin() + 5 * nc);
+  std::copy(cons, cons + ncv, u.begin());
+  std::copy(bf, bf + 3 * nf, u.begin() + ncv);
   std::vector<unsigned char> mask(n, 0);
-  for (int v = 0; v < 5; ++v)
+  for (int v = 0; v < g.nv; ++v)
     for (int k = g.s(2); k <= g.e(2); ++k)
       for (int j = g.s(1); j <= g.e(1); ++j)
         for (int i = g.s(0); i <= g.e(0); ++i) mask[v * nc + g.c(i, j, k)] = 1;
   for (int d = 0; d < 3; ++d)
     for (int k = g.s(2); k <= g.e(2); ++k)
       for (int j = g.s(1); j <= g.e(1); ++j)
-        for (int i = g.s(0); i <= g.e(0); ++i) mask[5 * nc + d * nf + g.f(i, j, k)] = 1;
+        for (int i = g.s(0); i <= g.e(0); ++i) mask[ncv + d * nf + g.f(i, j, k)] = 1;
   Work<T> wk;
   auto rhs = [&](int s, T* state, T* L) -> int {
-    fill_ghosts(g, state, state + 5 * nc);
+    fill_ghosts(g, state, state + ncv);
     std::fill(L, L + n, T(0.0));
     // the VL2 predictor always uses donor-cell fluxes
     int recon = (cfg.integrator == INT_VL2 && s == 0) ? RECON_DC : cfg.recon;
-    return spatial_operator(cfg, g, recon, state, state + 5 * nc, L, L + 5 * nc, wk);
+    return spatial_operator(cfg, g, recon, state, state + ncv, L, L + ncv, wk);
   };
   int bad;
   if (cfg.dfloor > 0.0 || cfg.pfloor > 0.0)
     bad = drive_2s(sc, n, u.data(), mask.data(), dt, rhs,
-                   [&](T* state) { g_floored += floor_state(cfg, g, state, state + 5 * nc); });
+                   [&](T* state) { g_floored += floor_state(cfg, g, state, state + ncv); });
   else
     bad = drive_2s(sc, n, u.data(), mask.data(), dt, rhs);
   if (bad < 0) return bad;
-  fill_ghosts(g, u.data(), u.data() + 5 * nc);
-  std::copy(u.begin(), u.begin() + 5 * nc, cons);
-  std::copy(u.begin() + 5 * nc, u.end(), bf);
+  fill_ghosts(g, u.data(), u.data() + ncv);
+  std::copy(u.begin(), u.begin() + ncv, cons);
+  std::copy(u.begin() + ncv, u.end(), bf);
   return bad;
 }
 
@@ -798,7 +825,7 @@ template <class T> int step(const Cfg& cfg, T* cons, T* bf, double dt) {
 inline int newdt(const Cfg& cfg, const double* cons, const double* bf, double* dt_out) {
   Geo g(cfg);
   const size_t nc = g.ncell();
-  std::vector<double> w(5 * nc), bcc(3 * nc);
+  std::vector<double> w(g.nv * nc), bcc(3 * nc);
   int bad = cons_to_prim(g, cfg.gamma, cons, bf, w.data(), bcc.data(), cfg.dfloor, cfg.pfloor);
   const double dx[3] = {cfg.dx1, cfg.dx2, cfg.dx3};
   double best = INFINITY;
@@ -850,11 +877,12 @@ int orc_step(const orc::Cfg* c, double* cons, double* bface, double dt) {
 int orc_step_jvp(const orc::Cfg* c, double* cons, double* bface, double* dcons, double* dbface, double dt) {
   orc::Geo g(*c);
   const size_t nc = g.ncell(), nf = g.nface();
-  std::vector<orc::Dual> uc(5 * nc), ub(3 * nf);
-  for (size_t q = 0; q < 5 * nc; ++q) uc[q] = orc::Dual(cons[q], dcons[q]);
+  const size_t ncv = g.nv * nc;
+  std::vector<orc::Dual> uc(ncv), ub(3 * nf);
+  for (size_t q = 0; q < ncv; ++q) uc[q] = orc::Dual(cons[q], dcons[q]);
   for (size_t q = 0; q < 3 * nf; ++q) ub[q] = orc::Dual(bface[q], dbface[q]);
   int r = orc::step<orc::Dual>(*c, uc.data(), ub.data(), dt);
-  for (size_t q = 0; q < 5 * nc; ++q) { cons[q] = uc[q].v; dcons[q] = uc[q].d; }
+  for (size_t q = 0; q < ncv; ++q) { cons[q] = uc[q].v; dcons[q] = uc[q].d; }
   for (size_t q = 0; q < 3 * nf; ++q) { bface[q] = ub[q].v; dbface[q] = ub[q].d; }
   return r;
 }
@@ -865,7 +893,7 @@ int orc_step_jvp(const orc::Cfg* c, double* cons, double* bface, double* dcons, 
 int orc_count_ops(const orc::Cfg* c, const double* cons, const double* bface, double dt, unsigned long long* out) {
   orc::Geo g(*c);
   const size_t nc = g.ncell(), nf = g.nface();
-  std::vector<orc::Cnt> uc(cons, cons + 5 * nc), ub(bface, bface + 3 * nf);
+  std::vector<orc::Cnt> uc(cons, cons + g.nv * nc), ub(bface, bface + 3 * nf);
   orc::g_ops = {0, 0, 0, 0};
   int r = orc::step<orc::Cnt>(*c, uc.data(), ub.data(), dt);
   out[0] = orc::g_ops.add;

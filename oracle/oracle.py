@@ -34,7 +34,7 @@ def build(force: bool = False) -> str:
 class Cfg(C.Structure):
     _fields_ = [("n1", C.c_int32), ("n2", C.c_int32), ("n3", C.c_int32), ("ng", C.c_int32),
                 ("gamma", C.c_double), ("dx1", C.c_double), ("dx2", C.c_double), ("dx3", C.c_double),
-                ("recon", C.c_int32), ("riemann", C.c_int32), ("integrator", C.c_int32), ("pad_", C.c_int32),
+                ("recon", C.c_int32), ("riemann", C.c_int32), ("integrator", C.c_int32), ("nscalars", C.c_int32),
                 ("cfl", C.c_double), ("ct_eps", C.c_double), ("dfloor", C.c_double), ("pfloor", C.c_double)]
 
 
@@ -71,10 +71,20 @@ def _p(a: np.ndarray):
 
 
 def make_cfg(n, ng, dx, gamma, recon="plm", riemann="hlld", integrator="vl2", cfl=0.3, ct_eps=0.0,
-             dfloor=0.0, pfloor=0.0) -> Cfg:
+             dfloor=0.0, pfloor=0.0, nscalars=0) -> Cfg:
+    assert nscalars >= 0
     return Cfg(int(n[0]), int(n[1]), int(n[2]), int(ng), float(gamma), float(dx[0]), float(dx[1]),
-               float(dx[2]), RECON[recon], RIEMANN[riemann], INTEGRATOR[integrator], 0, float(cfl),
+               float(dx[2]), RECON[recon], RIEMANN[riemann], INTEGRATOR[integrator], int(nscalars), float(cfl),
                float(ct_eps), float(dfloor), float(pfloor))
+
+
+def _check(cfg: Cfg, cells: np.ndarray, bface: np.ndarray | None = None) -> None:
+    """The C routines index the arrays by the configuration alone: check their
+    shapes first (5 MHD variables plus the passive scalars, padded faces)."""
+    N = (cfg.n3 + 2 * cfg.ng, cfg.n2 + 2 * cfg.ng, cfg.n1 + 2 * cfg.ng)
+    assert cells.shape == (5 + cfg.nscalars,) + N, (cells.shape, cfg.nscalars, N)
+    if bface is not None:
+        assert bface.shape == (3,) + tuple(x + 1 for x in N), bface.shape
 
 
 def take_floor_count() -> int:
@@ -87,16 +97,19 @@ def cfg_for(block, **kw) -> Cfg:
 
 
 def fill_ghosts(cfg: Cfg, cons: np.ndarray, bface: np.ndarray) -> None:
+    _check(cfg, cons, bface)
     lib().orc_fill_ghosts(C.byref(cfg), _p(cons), _p(bface))
 
 
 def prim2cons(cfg: Cfg, prim: np.ndarray, bface: np.ndarray) -> np.ndarray:
+    _check(cfg, prim, bface)
     cons = np.empty_like(prim)
     lib().orc_prim2cons(C.byref(cfg), _p(prim), _p(bface), _p(cons))
     return cons
 
 
 def cons2prim(cfg: Cfg, cons: np.ndarray, bface: np.ndarray):
+    _check(cfg, cons, bface)
     prim = np.empty_like(cons)
     bcc = np.empty((3,) + cons.shape[1:])
     bad = lib().orc_cons2prim(C.byref(cfg), _p(cons), _p(bface), _p(prim), _p(bcc))
@@ -106,15 +119,19 @@ def cons2prim(cfg: Cfg, cons: np.ndarray, bface: np.ndarray):
 def step(cfg: Cfg, cons: np.ndarray, bface: np.ndarray, dt: float) -> int:
     """Advance (cons, bface) in place by one step; returns the count of
     non-physical cells met (0 normally), negative on a bad configuration."""
+    _check(cfg, cons, bface)
     return lib().orc_step(C.byref(cfg), _p(cons), _p(bface), float(dt))
 
 
 def step_jvp(cfg: Cfg, cons, bface, dcons, dbface, dt: float) -> int:
+    _check(cfg, cons, bface)
+    _check(cfg, dcons, dbface)
     return lib().orc_step_jvp(C.byref(cfg), _p(cons), _p(bface), _p(dcons), _p(dbface), float(dt))
 
 
 def count_ops(cfg: Cfg, cons: np.ndarray, bface: np.ndarray, dt: float):
     """(adds, multiplies, divides, square roots) of one step on this state."""
+    _check(cfg, cons, bface)
     out = (C.c_ulonglong * 4)()
     r = lib().orc_count_ops(C.byref(cfg), _p(cons), _p(bface), float(dt), out)
     assert r >= 0
@@ -122,6 +139,7 @@ def count_ops(cfg: Cfg, cons: np.ndarray, bface: np.ndarray, dt: float):
 
 
 def newdt(cfg: Cfg, cons: np.ndarray, bface: np.ndarray):
+    _check(cfg, cons, bface)
     out = np.zeros(1)
     bad = lib().orc_newdt(C.byref(cfg), _p(cons), _p(bface), _p(out))
     return float(out[0]), bad

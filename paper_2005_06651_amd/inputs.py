@@ -32,8 +32,8 @@ class Block:
     dx: tuple           # (dx1, dx2, dx3)
     gamma: float
     bface: np.ndarray   # (3, N3+1, N2+1, N1+1)
-    prim: np.ndarray | None = None   # (5, N3, N2, N1): rho, v1, v2, v3, p
-    cons: np.ndarray | None = None   # (5, N3, N2, N1): rho, M1, M2, M3, E
+    prim: np.ndarray | None = None   # (5 + ns, N3, N2, N1): rho, v1, v2, v3, p, then scalars C_i
+    cons: np.ndarray | None = None   # (5 + ns, N3, N2, N1): rho, M1, M2, M3, E, then rho C_i
     meta: dict = field(default_factory=dict)
 
     @property
@@ -351,6 +351,28 @@ def smooth_random(n=(16, 16, 16), seed=0, ng=2, gamma=5.0 / 3.0, vmax=0.9, kmax=
     prim[4] = _pad_periodic(pr, ng)
     return Block(n=(n1, n2, n3), ng=ng, dx=tuple(dx), gamma=gamma, bface=bf, prim=prim,
                  meta=dict(workload="smooth_random", seed=seed))
+
+
+def with_scalars(block: Block, nscalars: int, seed: int = 0, width: float = 0.1) -> Block:
+    """The block with nscalars passive-scalar rows appended to its primitives:
+    specific densities C_i of seeded tracer patterns on the block's periodic
+    box.  Scalar 0 is a dye, 0.5 + 0.5 tanh(f / width) of a smooth random level
+    function f scaled to max |f| = 1, so it is 0 or 1 away from fronts a few
+    cells wide; further scalars are smooth fields 1 + 0.9 f in [0.1, 1.9]."""
+    rng = np.random.default_rng(seed)
+    n1, n2, n3 = block.n
+    ng = block.ng
+    rows = []
+    for i in range(nscalars):
+        spec, _ = _band_modes(rng, (n1, n2, n3), 1.0, 3.0)
+        f = np.fft.irfftn(spec[0], s=(n3, n2, n1), axes=(0, 1, 2))
+        f /= np.abs(f).max()
+        c = 0.5 + 0.5 * np.tanh(f / width) if i == 0 else 1.0 + 0.9 * f
+        rows.append(_pad_periodic(c, ng))
+    prim = np.concatenate([block.prim[:5]] + [r[None] for r in rows], axis=0) if rows else block.prim[:5].copy()
+    meta = dict(block.meta, nscalars=nscalars, scalar_seed=seed)
+    return Block(n=block.n, ng=ng, dx=block.dx, gamma=block.gamma, bface=block.bface, prim=np.ascontiguousarray(prim),
+                 meta=meta)
 
 
 def divb_metric(bf: np.ndarray, n, ng, dx) -> float:
