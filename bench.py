@@ -70,6 +70,8 @@ def parse():
     p.add_argument("--mesh-blocks", type=int, default=8, help="mesh: blocks per direction of the 256^3 domain")
     p.add_argument("--no-tune", action="store_true", help="batch: keep the default tile instead of autotuning")
     p.add_argument("--graph", action="store_true", help="replay each step from a hipGraph")
+    p.add_argument("--scalars", type=int, default=0,
+                   help="turbulence: passive scalars carried along (a dye, then smooth fields)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain device copy of 1 GiB (for scaling PMC byte counters) and exit")
     return p.parse_args()
@@ -95,7 +97,8 @@ def cpu_baseline(block, steps: int):
     """The CPU oracle (single thread, as it stands) on a bounded sample of the
     same workload: `steps` VL2+PLM+HLLD steps of the same initial state."""
     from oracle import oracle as O
-    cfg = O.cfg_for(block, integrator="vl2", recon="plm", riemann="hlld", cfl=0.3)
+    cfg = O.cfg_for(block, integrator="vl2", recon="plm", riemann="hlld", cfl=0.3,
+                    nscalars=block.prim.shape[0] - 5)
     cons = O.prim2cons(cfg, block.prim, block.bface)
     bf = block.bface.copy()
     zones = block.n[0] * block.n[1] * block.n[2]
@@ -433,9 +436,12 @@ def main():
         print(json.dumps({"copy_bytes": a.numel() * 8, "launches": 3}))
         return
     n = args.n
+    ns = args.scalars
     block = inputs.turbulence(n=n, seed=args.seed)
+    if ns > 0:
+        block = inputs.with_scalars(block, ns, seed=args.seed + 100)
     solver = athmhd.Solver(block.n, block.ng, block.dx, block.gamma, recon="plm", riemann="hlld",
-                           integrator="vl2", cfl=0.3, kernel_path=args.kernel_path)
+                           integrator="vl2", cfl=0.3, kernel_path=args.kernel_path, nscalars=ns)
     tb = torch.from_numpy(block.bface).to(dev)
     tc = solver.prim2cons(torch.from_numpy(block.prim).to(dev), tb)
     torch.cuda.synchronize()
@@ -468,7 +474,7 @@ def main():
     achieved_gbs = alg_bytes / per_launch_s / 1e9
     traffic = None
     if STAGE_TRAFFIC and STAGE_TRAFFIC.get("source_hash") == stage_source_hash() and args.kernel_path == "fused" \
-            and n == 256:
+            and n == 256 and ns == 0:
         traffic = STAGE_TRAFFIC["bytes_per_launch"]
     # sanity of the final state
     solver.fill_ghosts(tc, tb)
@@ -482,7 +488,8 @@ def main():
     divb = div.abs().max().item() / bmax
 
     out = {
-        "metric": "zone-cycles/s, FP64 3D MHD VL2+PLM+HLLD, 1 MI355X",
+        "metric": "zone-cycles/s, FP64 3D MHD VL2+PLM+HLLD, 1 MI355X"
+                  + (f", with {ns} passive scalar(s)" if ns else ""),
         "value": value,
         "unit": "zone-cycles/s",
         "n_gpus": 1,
@@ -498,7 +505,7 @@ def main():
             "workload": f"decaying MHD turbulence {n}^3 periodic, VL2+PLM+HLLD+CT, gamma 5/3, rms Mach 1, "
                         f"B = 0.5 x + curl A (rms 0.1), CFL 0.3, dt from newdt every step",
             "cells": zones, "nghost": g, "integrator": "vl2", "recon": "plm", "riemann": "hlld",
-            "seed": args.seed, "kernel_path": args.kernel_path,
+            "seed": args.seed, "kernel_path": args.kernel_path, "nscalars": ns,
         },
         "roofline": {
             "bound": "alu",

@@ -22,6 +22,9 @@
  *           (k,j,i) along direction c (B1 at x1-faces, B2 at x2-faces, B3 at
  *           x3-faces, padded to a common shape).
  *   prim  : same shape as cons, v in (rho, v1, v2, v3, P).
+ * With nscalars = S > 0 passive scalars, cons holds 5 + S cell arrays per
+ * block, the masses rho C_1 .. rho C_S after E, and prim the specific
+ * densities C_1 .. C_S after P (see "Passive scalars" below).
  * Every block is its own periodic neighbour: ghost cells and the boundary
  * faces n_d+nghost are periodic images, filled by the library.
  *
@@ -82,7 +85,22 @@ typedef struct {
   double ct_eps;           /* 0: CT upwinding by the sign of the face mass flux    */
                            /* (Gardiner & Stone 2005); > 0: continuous weight      */
                            /* clamp(1/2 + (F_rho/rho_bar)/(2 ct_eps c_max), 0, 1)  */
+  int32_t nscalars;        /* passive scalars, in [0, 64] (Sec. 3.3.x, Eq.          */
+                           /* (passive_scalars)); see "Passive scalars" below      */
 } athmhd_config;
+
+/* Passive scalars (Sec. 3.3.x "Additional Physics", Eq. (passive_scalars)):
+ * each scalar obeys d(rho C)/dt + div(rho v C) = 0.  C is reconstructed with
+ * the configured method (DC in the VL2 predictor) like the other primitives,
+ * and the flux of rho C through a face is the face mass flux of the stage's
+ * Riemann solve times C on the upwind side (left state where the mass flux is
+ * >= 0).  With floors on, C = (rho C) / rho uses the floored density; the
+ * floor pass after a stage leaves rho C unchanged.  Available with
+ * athmhd_create and kernel_path 0: athmhd_create with kernel_path 1,
+ * athmhd_create_mesh and athmhd_create_batch return ATHMHD_EUNSUP for
+ * nscalars != 0, and so do athmhd_step_vjp and athmhd_prim2cons_vjp on a
+ * handle with scalars.  The MHD state of a step does not depend on the
+ * scalars. */
 
 /* Version of this ABI (major*100 + minor). */
 ATHMHD_API int athmhd_version(void);

@@ -41,7 +41,8 @@ class Config(C.Structure):
     _fields_ = [("n1", C.c_int32), ("n2", C.c_int32), ("n3", C.c_int32), ("nghost", C.c_int32),
                 ("gamma", C.c_double), ("dx1", C.c_double), ("dx2", C.c_double), ("dx3", C.c_double),
                 ("recon", C.c_int32), ("riemann", C.c_int32), ("integrator", C.c_int32),
-                ("kernel_path", C.c_int32), ("cfl", C.c_double), ("ct_eps", C.c_double)]
+                ("kernel_path", C.c_int32), ("cfl", C.c_double), ("ct_eps", C.c_double),
+                ("nscalars", C.c_int32)]
 
 
 _lib = None
@@ -87,10 +88,10 @@ KERNEL_PATH = {"fused": 0, "unfused": 1}
 
 
 def make_config(n, nghost, dx, gamma, recon="plm", riemann="hlld", integrator="vl2", cfl=0.3,
-                ct_eps=0.0, kernel_path="fused") -> Config:
+                ct_eps=0.0, kernel_path="fused", nscalars=0) -> Config:
     return Config(int(n[0]), int(n[1]), int(n[2]), int(nghost), float(gamma), float(dx[0]), float(dx[1]),
                   float(dx[2]), RECON[recon], RIEMANN[riemann], INTEGRATOR[integrator],
-                  KERNEL_PATH[kernel_path], float(cfl), float(ct_eps))
+                  KERNEL_PATH[kernel_path], float(cfl), float(ct_eps), int(nscalars))
 
 
 def _check(rc: int, h) -> None:
@@ -109,16 +110,18 @@ def _stream(stream):
 class Solver:
     """One handle of the library: nblocks identical periodic MeshBlocks.
 
-    Tensors: cons (nb, 5, N3, N2, N1) and bface (nb, 3, N3+1, N2+1, N1+1),
-    float64, contiguous, on the current HIP device (leading nb axis optional
-    when nb == 1)."""
+    Tensors: cons (nb, 5 + nscalars, N3, N2, N1) and bface (nb, 3, N3+1, N2+1,
+    N1+1), float64, contiguous, on the current HIP device (leading nb axis
+    optional when nb == 1).  Passive scalars rho C_i follow the 5 MHD
+    variables in cons, and C_i the 5 primitives in prim."""
 
     def __init__(self, n, nghost, dx, gamma, recon="plm", riemann="hlld", integrator="vl2", cfl=0.3,
-                 ct_eps=0.0, nblocks=1, kernel_path="fused"):
+                 ct_eps=0.0, nblocks=1, kernel_path="fused", nscalars=0):
         self.n = tuple(int(x) for x in n)
         self.ng = int(nghost)
         self.nblocks = int(nblocks)
-        self.cfg = make_config(n, nghost, dx, gamma, recon, riemann, integrator, cfl, ct_eps, kernel_path)
+        self.nv = 5 + int(nscalars)
+        self.cfg = make_config(n, nghost, dx, gamma, recon, riemann, integrator, cfl, ct_eps, kernel_path, nscalars)
         h = C.c_void_p()
         rc = lib().athmhd_create(C.byref(self.cfg), self.nblocks, C.byref(h))
         if rc != OK:
@@ -151,7 +154,7 @@ class Solver:
         return C.c_void_p(t.data_ptr()), nb
 
     def _pair(self, cons, bface):
-        pc, nb = self._arr(cons, 5, self.cell_shape)
+        pc, nb = self._arr(cons, self.nv, self.cell_shape)
         pb, nb2 = self._arr(bface, 3, self.face_shape)
         if nb != nb2:
             raise ValueError("cons and bface hold different block counts")
@@ -172,7 +175,7 @@ class Solver:
         pp, pb, nb = self._pair(prim, bface)
         if out is None:
             out = torch.empty_like(prim)
-        po, _ = self._arr(out, 5, self.cell_shape)
+        po, _ = self._arr(out, self.nv, self.cell_shape)
         _check(lib().athmhd_prim2cons(self._h, pp, pb, po, nb, _stream(stream)), self._h)
         return out
 
@@ -189,7 +192,7 @@ class Solver:
         """A buffer for the stage inputs of one step (see step_stages)."""
         import torch
         nb = cons.shape[0] if cons.dim() == 5 else 1
-        n1 = 5 * math.prod(self.cell_shape) + 3 * math.prod(self.face_shape)
+        n1 = self.nv * math.prod(self.cell_shape) + 3 * math.prod(self.face_shape)
         return torch.empty(max(self.extra_stages, 1) * nb * n1, dtype=torch.float64, device=cons.device)
 
     def step_stages(self, cons, bface, dt: float, stages, stream=None) -> None:
@@ -230,11 +233,11 @@ class Solver:
         part is added to g_bface in place.  Returns out_prim."""
         import torch
         pp, pb, nb = self._pair(prim, bface)
-        gc, _ = self._arr(g_cons, 5, self.cell_shape)
+        gc, _ = self._arr(g_cons, self.nv, self.cell_shape)
         gbp, _ = self._arr(g_bface, 3, self.face_shape)
         if out_prim is None:
             out_prim = torch.empty_like(prim)
-        op, _ = self._arr(out_prim, 5, self.cell_shape)
+        op, _ = self._arr(out_prim, self.nv, self.cell_shape)
         _check(lib().athmhd_prim2cons_vjp(self._h, pp, pb, gc, op, gbp, nb, _stream(stream)), self._h)
         return out_prim
 
@@ -288,6 +291,7 @@ class MeshSolver(Solver):
         self.mesh = tuple(int(x) for x in mesh)
         self.ng = int(nghost)
         self.nblocks = self.mesh[0] * self.mesh[1] * self.mesh[2]
+        self.nv = 5
         self.cfg = make_config(n, nghost, dx, gamma, recon, riemann, integrator, cfl, ct_eps, "fused")
         h = C.c_void_p()
         rc = lib().athmhd_create_mesh(C.byref(self.cfg), self.mesh[0], self.mesh[1], self.mesh[2], C.byref(h))

@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libathmhd.so")
-SOURCES = ["abi.hip", "kernels_basic.hip", "kernels_unfused.hip", "kernels_fused.hip", "kernels_adjoint.hip"]
+SOURCES = ["abi.hip", "kernels_basic.hip", "kernels_unfused.hip", "kernels_fused.hip", "kernels_adjoint.hip",
+           "kernels_scalar.hip"]
 OBJDIR = os.path.join(ROOT, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -44,6 +44,9 @@ struct athmhd_s {
   int64_t reg_coff = 0;                  // offset of bface inside a register
   UnfusedScratch scr{};
   double* scratch_base = nullptr;
+  // passive scalars (g.ns > 0): face mass fluxes of a stage and C_i
+  double* d_fm = nullptr;  // 3 face arrays per block
+  double* d_cs = nullptr;  // ns cell arrays per block
   unsigned long long* d_dtmin = nullptr;  // running min of dx/(|v|+cf), bit pattern
   int* d_bad = nullptr;                   // [0] non-physical cells met since the last newdt, [1] floor activations
   Floors floors{0.0, 0.0};                // optional primitive floors (off by default)
@@ -142,6 +145,8 @@ int validate_common(const athmhd_config* c) {
     return fail(nullptr, ATHMHD_EINVAL, "ct_eps must be finite and >= 0 (got %g)", c->ct_eps);
   if (c->kernel_path != 0 && c->kernel_path != 1)
     return fail(nullptr, ATHMHD_EINVAL, "kernel_path must be 0 (fused) or 1 (unfused)");
+  if (c->nscalars < 0 || c->nscalars > 64)
+    return fail(nullptr, ATHMHD_EINVAL, "nscalars must be in [0, 64] (got %d)", c->nscalars);
   return ATHMHD_OK;
 }
 
@@ -202,6 +207,8 @@ void free_all(athmhd_t h) {
   for (int r = 0; r < 2; ++r)
     if (h->reg[r]) (void)hipFree(h->reg[r]);
   if (h->scratch_base) (void)hipFree(h->scratch_base);
+  if (h->d_fm) (void)hipFree(h->d_fm);
+  if (h->d_cs) (void)hipFree(h->d_cs);
   if (h->d_dtmin) (void)hipFree(h->d_dtmin);
   if (h->d_bad) (void)hipFree(h->d_bad);
   if (h->d_dtval) (void)hipFree(h->d_dtval);
@@ -274,7 +281,8 @@ hipError_t launch_stage(athmhd_t h, int recon, const double* xc, const double* x
                               h->d_bad, s);
   if (h->cfg.kernel_path == 0)
     return launch_stage_fused(h->g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc, xb, unc, unb, oc, ob, cf,
-                              dt_dev, beta, nblocks, stage_kz(h, nblocks), h->floors, h->d_bad, s);
+                              dt_dev, beta, nblocks, stage_kz(h, nblocks), h->floors, h->d_bad,
+                              h->g.ns > 0 ? h->d_fm : nullptr, s);
   return launch_stage_unfused(h->g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc, xb, unc, unb, oc, ob,
                               cf, nblocks, h->scr, h->floors, h->d_bad, s);
 }
@@ -329,6 +337,12 @@ int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const doubl
     e = launch_stage(h, recon, xc, xb, cons, bface, oc, ob, cf, sc.beta[st], dt_dev, nblocks, s);
     if (e != hipSuccess) return hip_fail(h, e, "stage launch");
     if ((e = mark(h, s)) != hipSuccess) return hip_fail(h, e, "profiling event");
+    // passive scalars, carried by the mass fluxes the stage kernel stored
+    if (h->g.ns > 0) {
+      e = launch_scalar_stage(h->g, recon, xc, cons, oc, h->d_fm, h->d_cs, cf, dt_dev, sc.beta[st], nblocks,
+                              h->floors, s);
+      if (e != hipSuccess) return hip_fail(h, e, "scalar stage launch");
+    }
     if (h->floors.on()) {
       e = h->batch ? launch_floor_state_batch(h->d_desc, h->nbatch, h->cfg.gamma, h->floors, oc, ob, h->d_bad, s)
                    : launch_floor_state(h->g, h->cfg.gamma, h->floors, oc, ob, nblocks, h->d_bad, s);
@@ -431,7 +445,7 @@ int alloc_adjoint(athmhd_t h) {
 
 extern "C" {
 
-int athmhd_version(void) { return 103; }
+int athmhd_version(void) { return 104; }
 
 int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
   if (!out) return fail(nullptr, ATHMHD_EINVAL, "out is NULL");
@@ -441,10 +455,12 @@ int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
   rc = validate_block(cfg->n1, cfg->n2, cfg->n3, cfg->nghost, cfg->dx1, cfg->dx2, cfg->dx3);
   if (rc != ATHMHD_OK) return rc;
   if (nblocks_max < 1) return fail(nullptr, ATHMHD_EINVAL, "nblocks_max must be >= 1");
+  if (cfg->nscalars > 0 && cfg->kernel_path != 0)
+    return fail(nullptr, ATHMHD_EUNSUP, "passive scalars run with the fused kernels only");
   athmhd_t h = new (std::nothrow) athmhd_s();
   if (!h) return fail(nullptr, ATHMHD_ENOMEM, "host allocation failed");
   h->cfg = *cfg;
-  h->g = make_geo(cfg->n1, cfg->n2, cfg->n3, cfg->nghost, cfg->dx1, cfg->dx2, cfg->dx3);
+  h->g = make_geo(cfg->n1, cfg->n2, cfg->n3, cfg->nghost, cfg->dx1, cfg->dx2, cfg->dx3, cfg->nscalars);
   h->nbmax = nblocks_max;
   read_env(h);
   hipError_t e = hipGetDevice(&h->device);
@@ -458,14 +474,19 @@ int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
   const int64_t state = (h->g.cblock + h->g.fblock) * (int64_t)nblocks_max;
   const int64_t nscr =
       cfg->kernel_path == 1 ? (8 * h->g.cvar + 24 * h->g.fvar + 3 * h->g.fvar) * (int64_t)nblocks_max : 1;
+  const int64_t nfm = h->g.ns > 0 ? 3 * h->g.fvar * (int64_t)nblocks_max : 0;
+  const int64_t ncs = h->g.ns * h->g.cvar * (int64_t)nblocks_max;
   bool ok = hipMalloc(&h->reg[0], state * sizeof(double)) == hipSuccess &&
             hipMalloc(&h->reg[1], state * sizeof(double)) == hipSuccess &&
-            hipMalloc(&h->scratch_base, nscr * sizeof(double)) == hipSuccess && alloc_common(h);
+            hipMalloc(&h->scratch_base, nscr * sizeof(double)) == hipSuccess && alloc_common(h) &&
+            (nfm == 0 || (hipMalloc(&h->d_fm, nfm * sizeof(double)) == hipSuccess &&
+                          hipMalloc(&h->d_cs, ncs * sizeof(double)) == hipSuccess));
   if (!ok) {
     (void)hipGetLastError();
     free_all(h);
     delete h;
-    return fail(nullptr, ATHMHD_ENOMEM, "device allocation of %.3f GB failed", (2.0 * state + nscr) * 8.0 / 1e9);
+    return fail(nullptr, ATHMHD_ENOMEM, "device allocation of %.3f GB failed",
+                (2.0 * state + nscr + nfm + ncs) * 8.0 / 1e9);
   }
   double* p = h->scratch_base;
   h->scr.w = p;
@@ -494,6 +515,8 @@ int athmhd_create_mesh(const athmhd_config* cfg, int nbx, int nby, int nbz, athm
   const double nb = (double)nbx * nby * nbz;
   if (nb > 1048576.0) return fail(nullptr, ATHMHD_EINVAL, "more than 2^20 blocks");
   if (cfg && cfg->kernel_path != 0) return fail(nullptr, ATHMHD_EUNSUP, "a coupled mesh runs the fused kernels only");
+  if (cfg && cfg->nscalars != 0)
+    return fail(nullptr, ATHMHD_EUNSUP, "passive scalars are available on periodic blocks only");
   int rc = athmhd_create(cfg, (int)nb, out);
   if (rc != ATHMHD_OK) return rc;
   athmhd_t h = *out;
@@ -511,6 +534,7 @@ int athmhd_create_batch(const athmhd_config* base, const int32_t* dims, const do
   int rc = validate_common(base);
   if (rc != ATHMHD_OK) return rc;
   if (base->kernel_path != 0) return fail(nullptr, ATHMHD_EUNSUP, "batched blocks run on the fused kernel only");
+  if (base->nscalars != 0) return fail(nullptr, ATHMHD_EUNSUP, "passive scalars are available on periodic blocks only");
   if (!dims || !dx) return fail(nullptr, ATHMHD_EINVAL, "NULL dims or dx");
   if (nblocks < 1 || nblocks > 65535) return fail(nullptr, ATHMHD_EINVAL, "nblocks must be in [1, 65535]");
   for (int b = 0; b < nblocks; ++b) {
@@ -741,6 +765,7 @@ int athmhd_step_vjp(athmhd_t h, const double* cons_n, const double* bface_n, dou
   if (rc) return rc;
   if (h->batch || h->mesh) return fail(h, ATHMHD_EUNSUP, "reverse mode is available for uniform handles only");
   if (h->floors.on()) return fail(h, ATHMHD_EUNSUP, "reverse mode is not available with floors");
+  if (h->g.ns > 0) return fail(h, ATHMHD_EUNSUP, "reverse mode is not available with passive scalars");
   if (!g_cons_np1 || !g_bface_np1 || !g_cons_n || !g_bface_n) return fail(h, ATHMHD_EINVAL, "NULL cotangent array");
   if (g_cons_n == cons_n || g_bface_n == bface_n || g_cons_n == (const double*)bface_n ||
       g_bface_n == (const double*)cons_n)
@@ -770,7 +795,8 @@ int athmhd_step_vjp(athmhd_t h, const double* cons_n, const double* bface_n, dou
     const int recon = (h->cfg.integrator == ATHMHD_VL2 && st == 0) ? ATHMHD_RECON_DC : h->cfg.recon;
     const StageCoef cf{sc.g0[st], sc.g1[st], sc.beta[st] * dt};
     e = launch_stage_fused(g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc[st], xb[st], cons_n, bface_n,
-                           oc, ob, cf, nullptr, sc.beta[st], nblocks, stage_kz(h, nblocks), h->floors, h->d_bad, s);
+                           oc, ob, cf, nullptr, sc.beta[st], nblocks, stage_kz(h, nblocks), h->floors, h->d_bad,
+                           nullptr, s);
     if (e != hipSuccess) return hip_fail(h, e, "vjp forward stage launch");
     xc[st + 1] = oc;
     xb[st + 1] = ob;
@@ -799,6 +825,7 @@ int athmhd_prim2cons_vjp(athmhd_t h, const double* prim, const double* bface, co
   int rc = check_call(h, prim, bface, nblocks);
   if (rc) return rc;
   if (h->batch || h->mesh) return fail(h, ATHMHD_EUNSUP, "reverse mode is available for uniform handles only");
+  if (h->g.ns > 0) return fail(h, ATHMHD_EUNSUP, "reverse mode is not available with passive scalars");
   if (!g_cons || !g_prim || !g_bface) return fail(h, ATHMHD_EINVAL, "NULL cotangent array");
   if (g_prim == g_cons || g_prim == prim) return fail(h, ATHMHD_EINVAL, "g_prim must not alias g_cons or prim");
   hipError_t e = launch_prim2cons_vjp(h->g, h->cfg.gamma, prim, bface, g_cons, g_prim, g_bface, nblocks,

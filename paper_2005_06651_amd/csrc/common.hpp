@@ -13,11 +13,12 @@ namespace athmhd {
 // N_d + 1 in every direction.  i (direction 1) is fastest.
 struct Geo {
   int n1, n2, n3, ng;
+  int ns;          // passive scalars rho C_i, stored as cell arrays after the 5 MHD variables
   int N1, N2, N3;
   int F1, F2, F3;
   int64_t cvar;    // cells per variable (stride between cell arrays)
   int64_t fvar;    // faces per component (stride between face arrays)
-  int64_t cblock;  // 5 * cvar: stride between blocks in cons
+  int64_t cblock;  // (5 + ns) * cvar: stride between blocks in cons
   int64_t fblock;  // 3 * fvar: stride between blocks in bface
   double dx1, dx2, dx3;
   // Blocks per direction of a coupled mesh: equal blocks that tile one
@@ -30,14 +31,15 @@ struct Geo {
   __host__ __device__ __forceinline__ int f(int i, int j, int k) const { return (k * F2 + j) * F1 + i; }
 };
 
-inline Geo make_geo(int n1, int n2, int n3, int ng, double dx1, double dx2, double dx3) {
+inline Geo make_geo(int n1, int n2, int n3, int ng, double dx1, double dx2, double dx3, int ns = 0) {
   Geo g;
   g.n1 = n1; g.n2 = n2; g.n3 = n3; g.ng = ng;
+  g.ns = ns;
   g.N1 = n1 + 2 * ng; g.N2 = n2 + 2 * ng; g.N3 = n3 + 2 * ng;
   g.F1 = g.N1 + 1; g.F2 = g.N2 + 1; g.F3 = g.N3 + 1;
   g.cvar = (int64_t)g.N1 * g.N2 * g.N3;
   g.fvar = (int64_t)g.F1 * g.F2 * g.F3;
-  g.cblock = 5 * g.cvar;
+  g.cblock = (5 + ns) * g.cvar;
   g.fblock = 3 * g.fvar;
   g.dx1 = dx1; g.dx2 = dx2; g.dx3 = dx3;
   g.mesh[0] = g.mesh[1] = g.mesh[2] = 0;

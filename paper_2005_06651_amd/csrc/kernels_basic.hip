@@ -55,6 +55,7 @@ __global__ void __launch_bounds__(kThreads) k_fill_ghosts(Geo g, double* __restr
     const int d = g.c(i, j, k), s = g.c(ii, jj, kk);
 #pragma unroll
     for (int v = 0; v < 5; ++v) cb[v * g.cvar + d] = cb[v * g.cvar + s];
+    for (int v = 5; v < 5 + g.ns; ++v) cb[v * g.cvar + d] = cb[v * g.cvar + s];  // passive scalars
   }
   const int d = g.f(i, j, k), s = g.f(ii, jj, kk);
 #pragma unroll
@@ -205,6 +206,8 @@ __global__ void __launch_bounds__(kThreads) k_prim2cons(Geo g, double gamma, con
   u[2 * g.cvar + t] = rho * v2;
   u[3 * g.cvar + t] = rho * v3;
   u[4 * g.cvar + t] = p / (gamma - 1.0) + 0.5 * rho * (v1 * v1 + v2 * v2 + v3 * v3) + 0.5 * (b1 * b1 + b2 * b2 + b3 * b3);
+  // passive scalars: masses rho C_i from the specific densities C_i
+  for (int v = 5; v < 5 + g.ns; ++v) u[v * g.cvar + t] = rho * w[v * g.cvar + t];
 }
 
 // Smallest dx_d / (|v_d| + c_f,d) over the active cells (Sec. 2.1.7, Sec. 3.2.3).

@@ -64,6 +64,7 @@ struct BlockPtrs {
   const double* unb;
   double* oc;
   double* ob;
+  double* fm = nullptr;  // optional: mass fluxes through the lower faces of the active cells (3 face arrays)
 };
 
 struct UniformArgs {
@@ -75,6 +76,7 @@ struct UniformArgs {
   const double* unb;
   double* oc;
   double* ob;
+  double* fm;  // NULL, or the face mass-flux output of every block (3 face arrays per block)
   int ntx, nty, nseg, kz;
   int64_t total;    // workgroups doing work
   int64_t per_xcd;  // ceil(total / 8)
@@ -184,26 +186,6 @@ __device__ __forceinline__ void to_zcell(const double* w, ZCell& z) {
   z.b3 = w[7];
 }
 
-// Reconstruct the two edge values of cell c from a line of cells centred on
-// it: s[LA + o] = q_{c+o}, o in [-LA, LA]; returns (left edge, right edge).
-template <int RECON>
-__device__ __forceinline__ void cell_edges(const double* s, double& left, double& right) {
-  if (RECON == 0) {
-    left = s[0];
-    right = s[0];
-  } else if (RECON == 1) {
-    const double d = vl_slope(s[0], s[1], s[2]);
-    left = s[1] - 0.5 * d;
-    right = s[1] + 0.5 * d;
-  } else {
-    double qm = ppm_face(s[0], s[1], s[2], s[3]);
-    double qp = ppm_face(s[1], s[2], s[3], s[4]);
-    ppm_cell(s[0], s[1], s[2], s[3], s[4], qm, qp);
-    left = qm;
-    right = qp;
-  }
-}
-
 __device__ __forceinline__ FaceState make_state(const double* q) {
   FaceState s;
   s.rho = q[0]; s.vn = q[1]; s.vt1 = q[2]; s.vt2 = q[3]; s.p = q[4]; s.bt1 = q[5]; s.bt2 = q[6];
@@ -265,7 +247,9 @@ __device__ __forceinline__ void face_update(const Geo& g, const double* __restri
 }
 
 // One tile (tile_x, tile_y) of a block over the active planes [k0, kend).
-template <int RECON, int RS, class T, bool FL, bool MESH = false>
+// MF: also store the mass flux through the lower faces of the active cells,
+// which passive scalars are carried by.
+template <int RECON, int RS, class T, bool FL, bool MESH = false, bool MF = false>
 __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, const StageArgs& sa, int tile_x,
                                            int tile_y, int k0, int kend, double* __restrict__ sp,
                                            double* __restrict__ sx, double* __restrict__ sc) {
@@ -422,6 +406,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
         fz_cons[0] = fz.rho; fz_cons[1] = fz.mt1; fz_cons[2] = fz.mt2; fz_cons[3] = fz.mn; fz_cons[4] = fz.e;
         e2z = -fz.bt1;
         e1z = fz.bt2;
+        if (MF && act && p < kend) bp.fm[2 * g.fvar + g.f(gi, gj, p)] = fz.rho;
       }
     }
     __syncthreads();
@@ -469,6 +454,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
         const double bn1 = bnq[0][0];
         FaceFlux fx;
         riemann<RS, FL>(ql, qr, bn1, sa.gas, sa.ct_eps, sa.fl, nfl, fx, wx);
+        if (MF && act && p >= k0 && p < kend) bp.fm[g.f(gi, gj, p)] = fx.rho;
         sx[(X_FX + 0) * NT + tid] = fx.rho;
         sx[(X_FX + 1) * NT + tid] = fx.mn;   // M1
         sx[(X_FX + 2) * NT + tid] = fx.mt1;  // M2
@@ -506,6 +492,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
         const double bn2 = bnq[0][1];
         FaceFlux fy;
         riemann<RS, FL>(ql, qr, bn2, sa.gas, sa.ct_eps, sa.fl, nfl, fy, wy);
+        if (MF && act && p >= k0 && p < kend) bp.fm[g.fvar + g.f(gi, gj, p)] = fy.rho;
         sx[(X_FY + 0) * NT + tid] = fy.rho;
         sx[(X_FY + 1) * NT + tid] = fy.mt2;  // M1
         sx[(X_FY + 2) * NT + tid] = fy.mn;   // M2
@@ -620,7 +607,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
 // Uniform blocks: one workgroup per (tile, x3 segment, block), XCD-aware:
 // consecutive logical tiles land on the same XCD so that halo overlap hits its
 // L2.
-template <int RECON, int RS, bool FL, bool MESH>
+template <int RECON, int RS, bool FL, bool MESH, bool MF>
 __global__ void __launch_bounds__(TileU::NT) __attribute__((amdgpu_waves_per_eu(2)))
 k_stage_fused(UniformArgs a) {
   using T = TileU;
@@ -638,10 +625,11 @@ k_stage_fused(UniformArgs a) {
   const int seg = (int)(r % a.nseg); r /= a.nseg;
   const int64_t blk = r;
   BlockPtrs bp{a.xc + blk * g.cblock, a.xb + blk * g.fblock, a.unc + blk * g.cblock,
-               a.unb + blk * g.fblock, a.oc + blk * g.cblock, a.ob + blk * g.fblock};
+               a.unb + blk * g.fblock, a.oc + blk * g.cblock, a.ob + blk * g.fblock,
+               MF ? a.fm + blk * 3 * g.fvar : nullptr};
   const int k0 = g.ng + seg * a.kz;
   const int kend = min(k0 + a.kz, g.ng + g.n3);
-  stage_tile<RECON, RS, T, FL, MESH>(g, bp, a.sa, tile_x, tile_y, k0, kend, sp, sx, sc);
+  stage_tile<RECON, RS, T, FL, MESH, MF>(g, bp, a.sa, tile_x, tile_y, k0, kend, sp, sx, sc);
 }
 
 // Batched blocks of uneven sizes: a persistent grid whose workgroups pull
@@ -667,23 +655,25 @@ __global__ void __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(2)))
   }
 }
 
-// MESH: the blocks of a coupled mesh read their (exchanged) ghost entries; a
-// compile-time switch, so that the periodic-block kernels keep their code
-template <int RECON, bool MESH>
+// MESH: the blocks of a coupled mesh read their (exchanged) ghost entries; MF:
+// the face mass fluxes are stored for passive scalars.  Compile-time switches,
+// so that the plain periodic-block kernels keep their code.
+template <int RECON, bool MESH, bool MF>
 hipError_t launch_rs_m(int rs, const UniformArgs& fa, hipStream_t s) {
   const unsigned grid = (unsigned)(8 * fa.per_xcd);
   constexpr int NT = TileU::NT;
   const bool fl = fa.sa.fl.on();
-  if (rs == 1 && fl) hipLaunchKernelGGL((k_stage_fused<RECON, 1, true, MESH>), dim3(grid), dim3(NT), 0, s, fa);
-  else if (rs == 1) hipLaunchKernelGGL((k_stage_fused<RECON, 1, false, MESH>), dim3(grid), dim3(NT), 0, s, fa);
-  else if (fl) hipLaunchKernelGGL((k_stage_fused<RECON, 0, true, MESH>), dim3(grid), dim3(NT), 0, s, fa);
-  else hipLaunchKernelGGL((k_stage_fused<RECON, 0, false, MESH>), dim3(grid), dim3(NT), 0, s, fa);
+  if (rs == 1 && fl) hipLaunchKernelGGL((k_stage_fused<RECON, 1, true, MESH, MF>), dim3(grid), dim3(NT), 0, s, fa);
+  else if (rs == 1) hipLaunchKernelGGL((k_stage_fused<RECON, 1, false, MESH, MF>), dim3(grid), dim3(NT), 0, s, fa);
+  else if (fl) hipLaunchKernelGGL((k_stage_fused<RECON, 0, true, MESH, MF>), dim3(grid), dim3(NT), 0, s, fa);
+  else hipLaunchKernelGGL((k_stage_fused<RECON, 0, false, MESH, MF>), dim3(grid), dim3(NT), 0, s, fa);
   return hipGetLastError();
 }
 
 template <int RECON>
 hipError_t launch_rs(int rs, const UniformArgs& fa, hipStream_t s) {
-  return fa.g.mesh[0] ? launch_rs_m<RECON, true>(rs, fa, s) : launch_rs_m<RECON, false>(rs, fa, s);
+  if (fa.fm) return launch_rs_m<RECON, false, true>(rs, fa, s);  // scalars run on periodic blocks only
+  return fa.g.mesh[0] ? launch_rs_m<RECON, true, false>(rs, fa, s) : launch_rs_m<RECON, false, false>(rs, fa, s);
 }
 
 __global__ void k_zero_u32(unsigned* p) {
@@ -735,11 +725,12 @@ static StageArgs make_stage_args(double gamma, double ct_eps, StageCoef coef, co
 hipError_t launch_stage_fused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
                               const double* xb, const double* unc, const double* unb, double* outc, double* outb,
                               StageCoef coef, const double* dt_dev, double beta, int nb, int kz, Floors fl, int* bad,
-                              hipStream_t s) {
+                              double* fm, hipStream_t s) {
   UniformArgs fa;
   fa.g = g;
   fa.sa = make_stage_args(gamma, ct_eps, coef, dt_dev, beta, fl, bad);
   fa.xc = xc; fa.xb = xb; fa.unc = unc; fa.unb = unb; fa.oc = outc; fa.ob = outb;
+  fa.fm = fm;
   fa.kz = kz;
   fa.ntx = (g.n1 + TileU::TX - 1) / TileU::TX;
   fa.nty = (g.n2 + TileU::TY - 1) / TileU::TY;

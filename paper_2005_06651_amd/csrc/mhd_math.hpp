@@ -344,6 +344,27 @@ __device__ __forceinline__ void ppm_cell(double qa, double qb, double qc, double
   }
 }
 
+// Reconstruct the two edge values of cell c from a line of cells centred on
+// it (Sec. 3.2.1): s[LA + o] = q_{c+o}, o in [-LA, LA], with LA = 0, 1, 2 for
+// DC, PLM, PPM; returns (left edge, right edge).
+template <int RECON>
+__device__ __forceinline__ void cell_edges(const double* s, double& left, double& right) {
+  if (RECON == 0) {
+    left = s[0];
+    right = s[0];
+  } else if (RECON == 1) {
+    const double d = vl_slope(s[0], s[1], s[2]);
+    left = s[1] - 0.5 * d;
+    right = s[1] + 0.5 * d;
+  } else {
+    double qm = ppm_face(s[0], s[1], s[2], s[3]);
+    double qp = ppm_face(s[1], s[2], s[3], s[4]);
+    ppm_cell(s[0], s[1], s[2], s[3], s[4], qm, qp);
+    left = qm;
+    right = qp;
+  }
+}
+
 // Upwind CT corner EMF (Gardiner & Stone 2005) at the edge shared by four
 // cells.  Notation for component e with transverse directions a, b:
 //   ea0 = face-a EMF at (c), ea1 = at (c - b)   [faces normal to a]

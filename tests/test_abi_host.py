@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version():
-    assert athmhd.lib().athmhd_version() == 103
+    assert athmhd.lib().athmhd_version() == 104
 
 
 def _create(**over):
@@ -63,11 +63,19 @@ def _create(**over):
     (dict(ct_eps=-1.0), "ct_eps"),
     (dict(kernel_path=2), "kernel_path"),
     (dict(n=(2000, 2000, 2000)), "too large"),
+    (dict(nscalars=-1), "nscalars"),
+    (dict(nscalars=65), "nscalars"),
 ])
 def test_create_rejects_bad_config_before_any_hip_call(over, needle):
     rc, msg = _create(**over)
     assert rc == athmhd.EINVAL
     assert needle in msg
+
+
+def test_scalars_need_the_fused_kernels():
+    rc, msg = _create(nscalars=2, kernel_path=1)
+    assert rc == athmhd.EUNSUP
+    assert "scalars" in msg
 
 
 def test_calls_reject_null_handle():
@@ -107,6 +115,7 @@ def _create_batch(dims, dxs, **over):
     ([(16, 16, 16)], [(0.1, -1.0, 0.1)], {}, athmhd.EINVAL, "widths"),
     ([(16, 16, 16)], [(0.1,) * 3], {"kernel_path": 1}, athmhd.EUNSUP, "fused"),
     ([(16, 16, 16)], [(0.1,) * 3], {"nghost": 1}, athmhd.EINVAL, "nghost"),
+    ([(16, 16, 16)], [(0.1,) * 3], {"nscalars": 1}, athmhd.EUNSUP, "scalars"),
 ])
 def test_create_batch_rejects_bad_blocks(dims, dxs, over, code, needle):
     rc, msg = _create_batch(dims, dxs, **over)
@@ -119,6 +128,7 @@ def test_create_batch_rejects_bad_blocks(dims, dxs, over, code, needle):
     ((2, 2, 2), {"kernel_path": 1}, athmhd.EUNSUP, "fused"),
     ((2, 2, 2), {"nghost": 1}, athmhd.EINVAL, "nghost"),
     ((2, 2, 2), {"n1": 0}, athmhd.EINVAL, "block dims"),
+    ((2, 2, 2), {"nscalars": 1}, athmhd.EUNSUP, "scalars"),
 ])
 def test_create_mesh_rejects_bad_arguments_before_any_hip_call(blocks, over, code, needle):
     cfg = athmhd.make_config((8, 8, 8), 2, (0.1, 0.1, 0.1), 5.0 / 3.0)
