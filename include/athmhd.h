@@ -85,11 +85,11 @@ typedef struct {
   double ct_eps;           /* 0: CT upwinding by the sign of the face mass flux    */
                            /* (Gardiner & Stone 2005); > 0: continuous weight      */
                            /* clamp(1/2 + (F_rho/rho_bar)/(2 ct_eps c_max), 0, 1)  */
-  int32_t nscalars;        /* passive scalars, in [0, 64] (Sec. 3.3.x, Eq.          */
+  int32_t nscalars;        /* passive scalars, in [0, 64] (Sec. 3.2.6, Eq.          */
                            /* (passive_scalars)); see "Passive scalars" below      */
 } athmhd_config;
 
-/* Passive scalars (Sec. 3.3.x "Additional Physics", Eq. (passive_scalars)):
+/* Passive scalars (Sec. 3.2.6 "Additional Physics", Eq. (passive_scalars)):
  * each scalar obeys d(rho C)/dt + div(rho v C) = 0.  C is reconstructed with
  * the configured method (DC in the VL2 predictor) like the other primitives,
  * and the flux of rho C through a face is the face mass flux of the stage's

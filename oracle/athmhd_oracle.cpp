@@ -36,7 +36,7 @@
 //     continuous weight (ct_eps > 0) replaces the three-way switch;
 //   * time step: one global dt from |v| + c_f (Sec. 2.1.7), per direction min;
 //   * face-B registers follow the same 2S weights as the conserved variables;
-//   * passive scalars (Sec. 3.3.x "Additional Physics", Eq. (passive_scalars)):
+//   * passive scalars (Sec. 3.2.6 "Additional Physics", Eq. (passive_scalars)):
 //     the conserved variable is rho C_i and the primitive C_i.  Readings: C_i
 //     is reconstructed like the other primitives, and the flux of rho C_i
 //     through a face is the face mass flux times C_i on the upwind side (the

@@ -44,9 +44,8 @@ struct athmhd_s {
   int64_t reg_coff = 0;                  // offset of bface inside a register
   UnfusedScratch scr{};
   double* scratch_base = nullptr;
-  // passive scalars (g.ns > 0): face mass fluxes of a stage and C_i
-  double* d_fm = nullptr;  // 3 face arrays per block
-  double* d_cs = nullptr;  // ns cell arrays per block
+  // passive scalars (g.ns > 0): face mass fluxes of a stage, 3 face arrays per block
+  double* d_fm = nullptr;
   unsigned long long* d_dtmin = nullptr;  // running min of dx/(|v|+cf), bit pattern
   int* d_bad = nullptr;                   // [0] non-physical cells met since the last newdt, [1] floor activations
   Floors floors{0.0, 0.0};                // optional primitive floors (off by default)
@@ -208,7 +207,6 @@ void free_all(athmhd_t h) {
     if (h->reg[r]) (void)hipFree(h->reg[r]);
   if (h->scratch_base) (void)hipFree(h->scratch_base);
   if (h->d_fm) (void)hipFree(h->d_fm);
-  if (h->d_cs) (void)hipFree(h->d_cs);
   if (h->d_dtmin) (void)hipFree(h->d_dtmin);
   if (h->d_bad) (void)hipFree(h->d_bad);
   if (h->d_dtval) (void)hipFree(h->d_dtval);
@@ -339,8 +337,7 @@ int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const doubl
     if ((e = mark(h, s)) != hipSuccess) return hip_fail(h, e, "profiling event");
     // passive scalars, carried by the mass fluxes the stage kernel stored
     if (h->g.ns > 0) {
-      e = launch_scalar_stage(h->g, recon, xc, cons, oc, h->d_fm, h->d_cs, cf, dt_dev, sc.beta[st], nblocks,
-                              h->floors, s);
+      e = launch_scalar_stage(h->g, recon, xc, cons, oc, h->d_fm, cf, dt_dev, sc.beta[st], nblocks, h->floors, s);
       if (e != hipSuccess) return hip_fail(h, e, "scalar stage launch");
     }
     if (h->floors.on()) {
@@ -475,18 +472,16 @@ int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
   const int64_t nscr =
       cfg->kernel_path == 1 ? (8 * h->g.cvar + 24 * h->g.fvar + 3 * h->g.fvar) * (int64_t)nblocks_max : 1;
   const int64_t nfm = h->g.ns > 0 ? 3 * h->g.fvar * (int64_t)nblocks_max : 0;
-  const int64_t ncs = h->g.ns * h->g.cvar * (int64_t)nblocks_max;
   bool ok = hipMalloc(&h->reg[0], state * sizeof(double)) == hipSuccess &&
             hipMalloc(&h->reg[1], state * sizeof(double)) == hipSuccess &&
             hipMalloc(&h->scratch_base, nscr * sizeof(double)) == hipSuccess && alloc_common(h) &&
-            (nfm == 0 || (hipMalloc(&h->d_fm, nfm * sizeof(double)) == hipSuccess &&
-                          hipMalloc(&h->d_cs, ncs * sizeof(double)) == hipSuccess));
+            (nfm == 0 || hipMalloc(&h->d_fm, nfm * sizeof(double)) == hipSuccess);
   if (!ok) {
     (void)hipGetLastError();
     free_all(h);
     delete h;
     return fail(nullptr, ATHMHD_ENOMEM, "device allocation of %.3f GB failed",
-                (2.0 * state + nscr + nfm + ncs) * 8.0 / 1e9);
+                (2.0 * state + nscr + nfm) * 8.0 / 1e9);
   }
   double* p = h->scratch_base;
   h->scr.w = p;

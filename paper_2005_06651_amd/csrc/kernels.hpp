@@ -50,14 +50,14 @@ hipError_t launch_stage_fused(const Geo& g, double gamma, int recon, int rs, dou
 int fused_default_kz(const Geo& g, int nb, int cus);
 
 // Passive scalars of one stage (rows 5 .. 5+ns-1 of the cell arrays), after
-// the fused stage that stored the face mass fluxes fm: C_i = (rho C_i)/rho of
-// the stage input x into cs (ns cell arrays per block, active cells), then
+// the fused stage that stored the face mass fluxes fm:
 //   out_i = g0 * x_i + g1 * un_i + bdt * L_i,
-// L_i the difference of the mass fluxes times C_i reconstructed (recon) on the
-// upwind side.  Periodic blocks; out may alias un, not x.
+// L_i the difference of the mass fluxes times C_i = (rho C_i)/rho of the
+// stage input x, reconstructed (recon) on the upwind side.  Periodic blocks;
+// out may alias un, not x.
 hipError_t launch_scalar_stage(const Geo& g, int recon, const double* xc, const double* unc, double* outc,
-                               const double* fm, double* cs, StageCoef coef, const double* dt_dev, double beta,
-                               int nb, Floors fl, hipStream_t s);
+                               const double* fm, StageCoef coef, const double* dt_dev, double beta, int nb,
+                               Floors fl, hipStream_t s);
 
 // Batched blocks of uneven sizes.  One block descriptor per block: its
 // geometry and the offsets (in doubles) of its cons and bface in the

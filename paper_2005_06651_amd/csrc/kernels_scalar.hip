@@ -1,17 +1,20 @@
-// kernels_scalar.hip -- passive scalars (Sec. 3.3.x, Eq. (passive_scalars)):
+// kernels_scalar.hip -- passive scalars (Sec. 3.2.6, Eq. (passive_scalars)):
 // the mass rho C_i of each scalar obeys the continuity equation with the
 // specific density C_i carried along.  C_i is reconstructed like the other
 // primitives (DC / PLM / PPM, Sec. 3.2.1) and moves with the face mass flux
 // F_rho of the stage's Riemann solves, taken from the upwind side.  The fused
-// stage kernel stores F_rho on the lower faces of the active cells; two
-// HBM-bound kernels then finish the stage for any number of scalars:
-//   k_scalar_prim    C_i = (rho C_i) / rho of the stage input on the active
-//                    cells, rho floored as in the MHD primitives when floors
-//                    are on;
-//   k_scalar_update  flux difference of rho C_i and the 2S stage update
-//                    (Eq. (rk-2s)), one thread per active cell, x1 fastest so
-//                    that lines along x1 are coalesced and the x2 / x3
-//                    neighbours come from L2.
+// stage kernel stores F_rho on the lower faces of the active cells; one
+// HBM-bound kernel then finishes the stage for every scalar.
+//
+// k_scalar_stage: a workgroup of 64 x 8 threads owns a 64 x 8 tile of (x1,
+// x2) columns of one scalar and marches along x3 over a segment of planes.
+// Each plane of C = (rho C) / rho, with a halo of LA + 1 cells, is computed
+// once from the stage input and kept in a ring of 2 LA + 4 planes in LDS, so
+// that the lines of the reconstruction along x1, x2 and x3 all come from LDS;
+// the ring is one plane longer than the stencil, which lets one barrier per
+// plane separate every write of a slot from the reads of its previous plane.
+// Each thread then forms the upwinded fluxes through the six faces of its
+// cell and writes the 2S update (Eq. (rk-2s)).
 #include "common.hpp"
 #include "kernels.hpp"
 #include "mhd_math.hpp"
@@ -20,124 +23,155 @@ namespace athmhd {
 
 namespace {
 
-constexpr int kScThreads = 256;
-
-// Stored index of position idx along a direction of a periodic block with n
-// active cells.  NEAR: the stencil reaches less than a block past the active
-// range, so one correction step finds the periodic image.
-template <bool NEAR>
-__device__ __forceinline__ int wrap_sc(int idx, int n, int ng) {
-  if (!NEAR) return wrap_index(idx, n, ng);
-  return idx < ng ? idx + n : (idx >= ng + n ? idx - n : idx);
-}
-
-template <bool FL>
-__global__ void __launch_bounds__(kScThreads) k_scalar_prim(Geo g, Floors fl, const double* __restrict__ xc,
-                                                            double* __restrict__ cs) {
-  const int t = blockIdx.x * kScThreads + threadIdx.x;
-  if (t >= g.n1 * g.n2 * g.n3) return;
-  const int i = g.ng + t % g.n1, r = t / g.n1, j = g.ng + r % g.n2, k = g.ng + r / g.n2;
-  const int q = g.c(i, j, k);
-  const double* x = xc + (int64_t)blockIdx.y * g.cblock;
-  double* c = cs + (int64_t)blockIdx.y * g.ns * g.cvar;
-  double rho = x[q];
-  if (FL && isfinite(rho) && isfinite(x[4 * g.cvar + q]) && !(rho >= fl.d)) rho = fl.d;
-  for (int v = 0; v < g.ns; ++v) c[v * g.cvar + q] = x[(5 + v) * g.cvar + q] / rho;
-}
+constexpr int kSX = 64, kSY = 8, kST = kSX * kSY;
 
 struct ScalarArgs {
   Geo g;
   StageCoef cf;
   const double* dt_dev;  // optional device copy of dt: bdt = beta * (*dt_dev)
   double beta;
-  const double* xc;      // stage input (read where g0 != 0)
+  Floors fl;
+  const double* xc;      // stage input: rho, E and rho C_i are read
   const double* unc;     // U^n
   double* oc;            // stage output
   const double* fm;      // face mass fluxes, 3 face arrays per block
-  const double* cs;     // C_i on the active cells, ns cell arrays per block
+  int ntx, nty, nseg, kz;
 };
 
-template <int RECON, bool NEAR>
-__global__ void __launch_bounds__(kScThreads) k_scalar_update(ScalarArgs a) {
+// Stored index of position idx along a direction with n active cells, for a
+// periodic block.  NEAR: every position a stencil of an active cell reaches
+// is less than a block past the active range, so one correction step finds
+// its periodic image; positions past that (halo columns of a ragged tile,
+// never used by an active cell) are only kept inside the array.
+template <bool NEAR>
+__device__ __forceinline__ int wrap_sc(int idx, int n, int ng) {
+  if (!NEAR) return wrap_index(idx, n, ng);
+  idx = idx < ng ? idx + n : (idx >= ng + n ? idx - n : idx);
+  return (idx < ng || idx >= ng + n) ? ng : idx;
+}
+
+template <int RECON, bool FL, bool NEAR>
+__global__ void __launch_bounds__(kST) k_scalar_stage(ScalarArgs a) {
+  constexpr int LA = RECON;             // reconstruction half-width: DC 0, PLM 1, PPM 2
+  constexpr int H = LA + 1;             // halo: the edges of c-1, c, c+1 read c-H .. c+H
+  constexpr int NW = 2 * H + 1;
+  constexpr int R = 2 * H + 2;          // planes in the LDS ring
+  constexpr int PW = kSX + 2 * H, PH = kSY + 2 * H, PL = PW * PH;
+  __shared__ double ring[R * PL];
   const Geo& g = a.g;
-  constexpr int LA = RECON;       // reconstruction half-width: DC 0, PLM 1, PPM 2
-  constexpr int W = 2 * LA + 3;   // cells c-LA-1 .. c+LA+1: the edges of c-1, c, c+1
-  const int t = blockIdx.x * kScThreads + threadIdx.x;
-  if (t >= g.n1 * g.n2 * g.n3) return;
-  const int i = g.ng + t % g.n1, r = t / g.n1, j = g.ng + r % g.n2, k = g.ng + r / g.n2;
-  const int64_t b = blockIdx.y;
+  int64_t r = blockIdx.x;
+  const int tile_x = (int)(r % a.ntx); r /= a.ntx;
+  const int tile_y = (int)(r % a.nty); r /= a.nty;
+  const int seg = (int)(r % a.nseg); r /= a.nseg;
+  const int v = (int)(r % g.ns);
+  const int64_t b = r / g.ns;
+  const int x0 = g.ng + tile_x * kSX, y0 = g.ng + tile_y * kSY;
+  const int k0 = g.ng + seg * a.kz;
+  const int kend = min(k0 + a.kz, g.ng + g.n3);
+  const int tid = threadIdx.x, tx = tid % kSX, ty = tid / kSX;
+  const int i = x0 + tx, j = y0 + ty;
+  const bool act = i < g.ng + g.n1 && j < g.ng + g.n2;
+  const double* __restrict__ xb = a.xc + b * g.cblock;
+  const double* __restrict__ sv = xb + (5 + v) * g.cvar;
   const double* __restrict__ fm = a.fm + b * 3 * g.fvar;
-  const double* __restrict__ cs = a.cs + b * g.ns * g.cvar;
   const double bdt = a.dt_dev ? a.beta * *a.dt_dev : a.cf.bdt;
-  int si[W], sj[W], sk[W];
-#pragma unroll
-  for (int o = 0; o < W; ++o) {
-    si[o] = wrap_sc<NEAR>(i + o - LA - 1, g.n1, g.ng);
-    sj[o] = wrap_sc<NEAR>(j + o - LA - 1, g.n2, g.ng);
-    sk[o] = wrap_sc<NEAR>(k + o - LA - 1, g.n3, g.ng);
-  }
-  // mass fluxes through the lower and upper faces along each direction; the
-  // upper face of the last cell is the periodic image of the first lower face
-  double flo[3], fup[3];
-  flo[0] = fm[g.f(i, j, k)];
-  fup[0] = fm[g.f(si[LA + 2], j, k)];
-  flo[1] = fm[g.fvar + g.f(i, j, k)];
-  fup[1] = fm[g.fvar + g.f(i, sj[LA + 2], k)];
-  flo[2] = fm[2 * g.fvar + g.f(i, j, k)];
-  fup[2] = fm[2 * g.fvar + g.f(i, j, sk[LA + 2])];
-  const double inv[3] = {1.0 / g.dx1, 1.0 / g.dx2, 1.0 / g.dx3};
-  const int q = g.c(i, j, k);
-  for (int v = 0; v < g.ns; ++v) {
-    const double* __restrict__ c = cs + v * g.cvar;
-    double sum = 0.0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      double line[W];
-#pragma unroll
-      for (int o = 0; o < W; ++o)
-        line[o] = c[d == 0 ? g.c(si[o], j, k) : (d == 1 ? g.c(i, sj[o], k) : g.c(i, j, sk[o]))];
-      double lm, rm, l0, r0, lp, rp;
-      cell_edges<RECON>(line, lm, rm);      // cell c-1
-      cell_edges<RECON>(line + 1, l0, r0);  // cell c
-      cell_edges<RECON>(line + 2, lp, rp);  // cell c+1
-      // face c-1/2 has left state rm, right state l0; face c+1/2 has r0, lp
-      const double flux_lo = flo[d] >= 0.0 ? flo[d] * rm : flo[d] * l0;
-      const double flux_up = fup[d] >= 0.0 ? fup[d] * r0 : fup[d] * lp;
-      sum += (flux_up - flux_lo) * inv[d];
+  const double i1 = 1.0 / g.dx1, i2 = 1.0 / g.dx2, i3 = 1.0 / g.dx3;
+
+  // C of plane z (with its halo) into ring slot `slot`
+  auto load_plane = [&](int z, int slot) {
+    const int kk = wrap_sc<NEAR>(z, g.n3, g.ng);
+    for (int e = tid; e < PL; e += kST) {
+      const int ii = wrap_sc<NEAR>(x0 - H + e % PW, g.n1, g.ng);
+      const int jj = wrap_sc<NEAR>(y0 - H + e / PW, g.n2, g.ng);
+      const int q = g.c(ii, jj, kk);
+      double rho = xb[q];
+      // with floors, C uses the density of the floored primitives
+      if (FL && isfinite(rho) && isfinite(xb[4 * g.cvar + q]) && !(rho >= a.fl.d)) rho = a.fl.d;
+      ring[slot * PL + e] = sv[q] / rho;
     }
-    const int64_t e = b * g.cblock + (5 + v) * g.cvar + q;
-    double out = a.cf.g1 * a.unc[e];
-    if (a.cf.g0 != 0.0) out += a.cf.g0 * a.xc[e];
-    a.oc[e] = out - bdt * sum;
+  };
+
+#pragma unroll
+  for (int z = 0; z < 2 * H; ++z) load_plane(k0 - H + z, z);
+  const int ip = wrap_sc<NEAR>(i + 1, g.n1, g.ng), jp = wrap_sc<NEAR>(j + 1, g.n2, g.ng);
+  const int l = (ty + H) * PW + tx + H;
+  double f3lo = act ? fm[2 * g.fvar + g.f(i, j, k0)] : 0.0;
+  for (int p = k0; p < kend; ++p) {
+    const int base = p - k0;  // ring index of plane p - H
+    load_plane(p + H, (base + 2 * H) % R);
+    __syncthreads();
+    if (act) {
+      double lx[NW], ly[NW], lz[NW];
+      const double* pc = ring + ((base + H) % R) * PL;
+#pragma unroll
+      for (int o = 0; o < NW; ++o) {
+        lx[o] = pc[l + o - H];
+        ly[o] = pc[l + (o - H) * PW];
+        lz[o] = ring[((base + o) % R) * PL + l];
+      }
+      const double f1lo = fm[g.f(i, j, p)], f1up = fm[g.f(ip, j, p)];
+      const double f2lo = fm[g.fvar + g.f(i, j, p)], f2up = fm[g.fvar + g.f(i, jp, p)];
+      const double f3up = fm[2 * g.fvar + g.f(i, j, wrap_sc<NEAR>(p + 1, g.n3, g.ng))];
+      const double* lines[3] = {lx, ly, lz};
+      const double flo[3] = {f1lo, f2lo, f3lo}, fup[3] = {f1up, f2up, f3up}, inv[3] = {i1, i2, i3};
+      double sum = 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        double lm, rm, l0, r0, lp, rp;
+        cell_edges<RECON>(lines[d], lm, rm);      // cell c-1
+        cell_edges<RECON>(lines[d] + 1, l0, r0);  // cell c
+        cell_edges<RECON>(lines[d] + 2, lp, rp);  // cell c+1
+        // face c-1/2: left state rm, right state l0; face c+1/2: r0, lp
+        const double flux_lo = flo[d] >= 0.0 ? flo[d] * rm : flo[d] * l0;
+        const double flux_up = fup[d] >= 0.0 ? fup[d] * r0 : fup[d] * lp;
+        sum += (flux_up - flux_lo) * inv[d];
+      }
+      const int64_t e = b * g.cblock + (5 + v) * g.cvar + g.c(i, j, p);
+      double out = a.cf.g1 * a.unc[e];
+      if (a.cf.g0 != 0.0) out += a.cf.g0 * a.xc[e];
+      a.oc[e] = out - bdt * sum;
+      f3lo = f3up;
+    }
   }
 }
 
+template <int RECON, bool FL>
+void launch_r(const ScalarArgs& sa, bool near, unsigned grid, hipStream_t s) {
+  if (near) hipLaunchKernelGGL((k_scalar_stage<RECON, FL, true>), dim3(grid), dim3(kST), 0, s, sa);
+  else hipLaunchKernelGGL((k_scalar_stage<RECON, FL, false>), dim3(grid), dim3(kST), 0, s, sa);
+}
+
 template <int RECON>
-void launch_update(const ScalarArgs& sa, bool near, dim3 grid, hipStream_t s) {
-  if (near) hipLaunchKernelGGL((k_scalar_update<RECON, true>), grid, dim3(kScThreads), 0, s, sa);
-  else hipLaunchKernelGGL((k_scalar_update<RECON, false>), grid, dim3(kScThreads), 0, s, sa);
+void launch_f(const ScalarArgs& sa, bool near, unsigned grid, hipStream_t s) {
+  if (sa.fl.on()) launch_r<RECON, true>(sa, near, grid, s);
+  else launch_r<RECON, false>(sa, near, grid, s);
 }
 
 }  // namespace
 
 hipError_t launch_scalar_stage(const Geo& g, int recon, const double* xc, const double* unc, double* outc,
-                               const double* fm, double* cs, StageCoef coef, const double* dt_dev, double beta,
-                               int nb, Floors fl, hipStream_t s) {
+                               const double* fm, StageCoef coef, const double* dt_dev, double beta, int nb, Floors fl,
+                               hipStream_t s) {
   if (g.ns <= 0) return hipSuccess;
-  const int64_t na = (int64_t)g.n1 * g.n2 * g.n3;
-  const dim3 grid((unsigned)((na + kScThreads - 1) / kScThreads), (unsigned)nb);
-  if (fl.on()) hipLaunchKernelGGL((k_scalar_prim<true>), grid, dim3(kScThreads), 0, s, g, fl, xc, cs);
-  else hipLaunchKernelGGL((k_scalar_prim<false>), grid, dim3(kScThreads), 0, s, g, fl, xc, cs);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  ScalarArgs sa{g, coef, dt_dev, beta, xc, unc, outc, fm, cs};
-  // one correction step finds every periodic image when each direction has
-  // more active cells than the stencil reaches past the block
-  const int reach = recon + 2;
-  const bool near = g.n1 >= reach && g.n2 >= reach && g.n3 >= reach;
-  if (recon == 0) launch_update<0>(sa, near, grid, s);
-  else if (recon == 1) launch_update<1>(sa, near, grid, s);
-  else launch_update<2>(sa, near, grid, s);
+  ScalarArgs sa{g, coef, dt_dev, beta, fl, xc, unc, outc, fm, 0, 0, 0, 0};
+  sa.ntx = (g.n1 + kSX - 1) / kSX;
+  sa.nty = (g.n2 + kSY - 1) / kSY;
+  // x3 segments: the longest of 32 .. 4 planes that still gives about 1024
+  // workgroups (the ring's start-up costs 2 (LA + 1) planes per segment)
+  const int64_t cols = (int64_t)sa.ntx * sa.nty * g.ns * nb;
+  int kz = 32;
+  while (kz > 4 && cols * ((g.n3 + kz - 1) / kz) < 1024) kz /= 2;
+  sa.kz = kz < g.n3 ? kz : g.n3;
+  sa.nseg = (g.n3 + sa.kz - 1) / sa.kz;
+  const int64_t total = cols * sa.nseg;
+  if (total > 0x7fffffff) return hipErrorInvalidValue;
+  // one correction step finds every periodic image a stencil reaches when each
+  // direction has more active cells than the halo
+  const int h = recon + 1;
+  const bool near = g.n1 > h && g.n2 > h && g.n3 > h;
+  if (recon == 0) launch_f<0>(sa, near, (unsigned)total, s);
+  else if (recon == 1) launch_f<1>(sa, near, (unsigned)total, s);
+  else launch_f<2>(sa, near, (unsigned)total, s);
   return hipGetLastError();
 }
 

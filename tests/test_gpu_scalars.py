@@ -1,4 +1,4 @@
-"""Passive scalars on the GPU (Sec. 3.3.x, Eq. (passive_scalars)): the fused
+"""Passive scalars on the GPU (Sec. 3.2.6, Eq. (passive_scalars)): the fused
 stage kernel stores the face mass fluxes and the scalar kernels carry C_i with
 them.  Checked against the oracle element by element at the 1e-12 bar, on
 ragged blocks spanning several tiles and x3 segments, for every

@@ -1,4 +1,4 @@
-"""Pins of the oracle's passive scalars (Sec. 3.3.x, "Additional Physics":
+"""Pins of the oracle's passive scalars (Sec. 3.2.6, "Additional Physics":
 Eq. (passive_scalars), d(rho C_i)/dt + div(rho v C_i) = 0, with the specific
 density C_i as the primitive and rho C_i as the conserved variable).
 
