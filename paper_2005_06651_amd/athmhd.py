@@ -281,18 +281,18 @@ class Solver:
 class MeshSolver(Solver):
     """A coupled mesh: mesh = (nbx, nby, nbz) equal blocks of n cells tiling one
     periodic domain; block b = bx + nbx (by + nby bz).  Tensors hold all
-    blocks: cons (nb, 5, N3, N2, N1), bface (nb, 3, N3+1, N2+1, N1+1).  Before
+    blocks: cons (nb, 5 + nscalars, N3, N2, N1), bface (nb, 3, N3+1, N2+1, N1+1).  Before
     every stage the library exchanges ghost cells and faces between the
     blocks (see athmhd_create_mesh)."""
 
     def __init__(self, n, mesh, nghost, dx, gamma, recon="plm", riemann="hlld", integrator="vl2", cfl=0.3,
-                 ct_eps=0.0):
+                 ct_eps=0.0, nscalars=0):
         self.n = tuple(int(x) for x in n)
         self.mesh = tuple(int(x) for x in mesh)
         self.ng = int(nghost)
         self.nblocks = self.mesh[0] * self.mesh[1] * self.mesh[2]
-        self.nv = 5
-        self.cfg = make_config(n, nghost, dx, gamma, recon, riemann, integrator, cfl, ct_eps, "fused")
+        self.nv = 5 + int(nscalars)
+        self.cfg = make_config(n, nghost, dx, gamma, recon, riemann, integrator, cfl, ct_eps, "fused", nscalars)
         h = C.c_void_p()
         rc = lib().athmhd_create_mesh(C.byref(self.cfg), self.mesh[0], self.mesh[1], self.mesh[2], C.byref(h))
         if rc != OK:

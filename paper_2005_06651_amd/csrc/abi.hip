@@ -510,8 +510,6 @@ int athmhd_create_mesh(const athmhd_config* cfg, int nbx, int nby, int nbz, athm
   const double nb = (double)nbx * nby * nbz;
   if (nb > 1048576.0) return fail(nullptr, ATHMHD_EINVAL, "more than 2^20 blocks");
   if (cfg && cfg->kernel_path != 0) return fail(nullptr, ATHMHD_EUNSUP, "a coupled mesh runs the fused kernels only");
-  if (cfg && cfg->nscalars != 0)
-    return fail(nullptr, ATHMHD_EUNSUP, "passive scalars are available on periodic blocks only");
   int rc = athmhd_create(cfg, (int)nb, out);
   if (rc != ATHMHD_OK) return rc;
   athmhd_t h = *out;

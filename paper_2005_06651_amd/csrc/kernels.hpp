@@ -46,15 +46,16 @@ hipError_t launch_stage_fused(const Geo& g, double gamma, int recon, int rs, dou
                               double* fm, hipStream_t s);  // kz > 0: x3 planes per workgroup
 // fm: NULL, or the output of the mass flux through the lower face of every
 // active cell along each direction (3 face arrays per block), for the passive
-// scalars; periodic blocks only (g.mesh[0] == 0).
+// scalars.
 int fused_default_kz(const Geo& g, int nb, int cus);
 
 // Passive scalars of one stage (rows 5 .. 5+ns-1 of the cell arrays), after
 // the fused stage that stored the face mass fluxes fm:
 //   out_i = g0 * x_i + g1 * un_i + bdt * L_i,
 // L_i the difference of the mass fluxes times C_i = (rho C_i)/rho of the
-// stage input x, reconstructed (recon) on the upwind side.  Periodic blocks;
-// out may alias un, not x.
+// stage input x, reconstructed (recon) on the upwind side.  Blocks of a
+// coupled mesh read their exchanged ghost cells, and the mass flux through an
+// upper boundary face from the next block; out may alias un, not x.
 hipError_t launch_scalar_stage(const Geo& g, int recon, const double* xc, const double* unc, double* outc,
                                const double* fm, StageCoef coef, const double* dt_dev, double beta, int nb,
                                Floors fl, hipStream_t s);

@@ -136,6 +136,7 @@ __global__ void __launch_bounds__(kThreads) k_mesh_ghosts(Geo g, int w, int near
     const int d = g.c(x[0], x[1], x[2]), s = g.c(sx[0], sx[1], sx[2]);
 #pragma unroll
     for (int v = 0; v < 5; ++v) dc[v * g.cvar + d] = sc[v * g.cvar + s];
+    for (int v = 5; v < 5 + g.ns; ++v) dc[v * g.cvar + d] = sc[v * g.cvar + s];  // passive scalars
   }
   const int d = g.f(x[0], x[1], x[2]), s = g.f(sx[0], sx[1], sx[2]);
 #pragma unroll

@@ -672,7 +672,8 @@ hipError_t launch_rs_m(int rs, const UniformArgs& fa, hipStream_t s) {
 
 template <int RECON>
 hipError_t launch_rs(int rs, const UniformArgs& fa, hipStream_t s) {
-  if (fa.fm) return launch_rs_m<RECON, false, true>(rs, fa, s);  // scalars run on periodic blocks only
+  if (fa.fm)
+    return fa.g.mesh[0] ? launch_rs_m<RECON, true, true>(rs, fa, s) : launch_rs_m<RECON, false, true>(rs, fa, s);
   return fa.g.mesh[0] ? launch_rs_m<RECON, true, false>(rs, fa, s) : launch_rs_m<RECON, false, false>(rs, fa, s);
 }
 

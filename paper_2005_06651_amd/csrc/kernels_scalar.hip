@@ -14,7 +14,10 @@
 // the ring is one plane longer than the stencil, which lets one barrier per
 // plane separate every write of a slot from the reads of its previous plane.
 // Each thread then forms the upwinded fluxes through the six faces of its
-// cell and writes the 2S update (Eq. (rk-2s)).
+// cell and writes the 2S update (Eq. (rk-2s)).  A periodic block reads the
+// periodic images of its cells; the blocks of a coupled mesh read their ghost
+// cells (filled by the mesh exchange) and take the mass flux through an upper
+// boundary face from the next block, which owns that face.
 #include "common.hpp"
 #include "kernels.hpp"
 #include "mhd_math.hpp"
@@ -50,7 +53,17 @@ __device__ __forceinline__ int wrap_sc(int idx, int n, int ng) {
   return (idx < ng || idx >= ng + n) ? ng : idx;
 }
 
-template <int RECON, bool FL, bool NEAR>
+// Stored cell index read for position idx (0 .. N-1 with ghosts): the
+// periodic image on a self-periodic block, else the entry itself, clamped
+// into the array for halo columns of a ragged tile past the block.
+template <bool MESH, bool NEAR>
+__device__ __forceinline__ int read_sc(int idx, int n, int ng) {
+  if (!MESH) return wrap_sc<NEAR>(idx, n, ng);
+  const int hi = n + 2 * ng - 1;
+  return idx < 0 ? 0 : (idx > hi ? hi : idx);
+}
+
+template <int RECON, bool FL, bool NEAR, bool MESH>
 __global__ void __launch_bounds__(kST) k_scalar_stage(ScalarArgs a) {
   constexpr int LA = RECON;             // reconstruction half-width: DC 0, PLM 1, PPM 2
   constexpr int H = LA + 1;             // halo: the edges of c-1, c, c+1 read c-H .. c+H
@@ -79,10 +92,10 @@ __global__ void __launch_bounds__(kST) k_scalar_stage(ScalarArgs a) {
 
   // C of plane z (with its halo) into ring slot `slot`
   auto load_plane = [&](int z, int slot) {
-    const int kk = wrap_sc<NEAR>(z, g.n3, g.ng);
+    const int kk = read_sc<MESH, NEAR>(z, g.n3, g.ng);
     for (int e = tid; e < PL; e += kST) {
-      const int ii = wrap_sc<NEAR>(x0 - H + e % PW, g.n1, g.ng);
-      const int jj = wrap_sc<NEAR>(y0 - H + e / PW, g.n2, g.ng);
+      const int ii = read_sc<MESH, NEAR>(x0 - H + e % PW, g.n1, g.ng);
+      const int jj = read_sc<MESH, NEAR>(y0 - H + e / PW, g.n2, g.ng);
       const int q = g.c(ii, jj, kk);
       double rho = xb[q];
       // with floors, C uses the density of the floored primitives
@@ -93,7 +106,12 @@ __global__ void __launch_bounds__(kST) k_scalar_stage(ScalarArgs a) {
 
 #pragma unroll
   for (int z = 0; z < 2 * H; ++z) load_plane(k0 - H + z, z);
+  // upper faces: the block's own lower faces, or on the upper boundary the
+  // lower boundary face of the next block (the block itself when periodic)
   const int ip = wrap_sc<NEAR>(i + 1, g.n1, g.ng), jp = wrap_sc<NEAR>(j + 1, g.n2, g.ng);
+  const double* fm1 = (MESH && i + 1 == g.ng + g.n1) ? a.fm + next_block<0>(g, (int)b) * 3 * g.fvar : fm;
+  const double* fm2 = (MESH && j + 1 == g.ng + g.n2) ? a.fm + next_block<1>(g, (int)b) * 3 * g.fvar : fm;
+  const double* fm3 = MESH ? a.fm + next_block<2>(g, (int)b) * 3 * g.fvar : fm;
   const int l = (ty + H) * PW + tx + H;
   double f3lo = act ? fm[2 * g.fvar + g.f(i, j, k0)] : 0.0;
   for (int p = k0; p < kend; ++p) {
@@ -109,9 +127,9 @@ __global__ void __launch_bounds__(kST) k_scalar_stage(ScalarArgs a) {
         ly[o] = pc[l + (o - H) * PW];
         lz[o] = ring[((base + o) % R) * PL + l];
       }
-      const double f1lo = fm[g.f(i, j, p)], f1up = fm[g.f(ip, j, p)];
-      const double f2lo = fm[g.fvar + g.f(i, j, p)], f2up = fm[g.fvar + g.f(i, jp, p)];
-      const double f3up = fm[2 * g.fvar + g.f(i, j, wrap_sc<NEAR>(p + 1, g.n3, g.ng))];
+      const double f1lo = fm[g.f(i, j, p)], f1up = fm1[g.f(ip, j, p)];
+      const double f2lo = fm[g.fvar + g.f(i, j, p)], f2up = fm2[g.fvar + g.f(i, jp, p)];
+      const double f3up = (p + 1 == g.ng + g.n3 ? fm3 : fm)[2 * g.fvar + g.f(i, j, wrap_sc<NEAR>(p + 1, g.n3, g.ng))];
       const double* lines[3] = {lx, ly, lz};
       const double flo[3] = {f1lo, f2lo, f3lo}, fup[3] = {f1up, f2up, f3up}, inv[3] = {i1, i2, i3};
       double sum = 0.0;
@@ -137,8 +155,9 @@ __global__ void __launch_bounds__(kST) k_scalar_stage(ScalarArgs a) {
 
 template <int RECON, bool FL>
 void launch_r(const ScalarArgs& sa, bool near, unsigned grid, hipStream_t s) {
-  if (near) hipLaunchKernelGGL((k_scalar_stage<RECON, FL, true>), dim3(grid), dim3(kST), 0, s, sa);
-  else hipLaunchKernelGGL((k_scalar_stage<RECON, FL, false>), dim3(grid), dim3(kST), 0, s, sa);
+  if (sa.g.mesh[0]) hipLaunchKernelGGL((k_scalar_stage<RECON, FL, true, true>), dim3(grid), dim3(kST), 0, s, sa);
+  else if (near) hipLaunchKernelGGL((k_scalar_stage<RECON, FL, true, false>), dim3(grid), dim3(kST), 0, s, sa);
+  else hipLaunchKernelGGL((k_scalar_stage<RECON, FL, false, false>), dim3(grid), dim3(kST), 0, s, sa);
 }
 
 template <int RECON>

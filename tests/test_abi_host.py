@@ -128,7 +128,7 @@ def test_create_batch_rejects_bad_blocks(dims, dxs, over, code, needle):
     ((2, 2, 2), {"kernel_path": 1}, athmhd.EUNSUP, "fused"),
     ((2, 2, 2), {"nghost": 1}, athmhd.EINVAL, "nghost"),
     ((2, 2, 2), {"n1": 0}, athmhd.EINVAL, "block dims"),
-    ((2, 2, 2), {"nscalars": 1}, athmhd.EUNSUP, "scalars"),
+    ((2, 2, 2), {"nscalars": -1}, athmhd.EINVAL, "nscalars"),
 ])
 def test_create_mesh_rejects_bad_arguments_before_any_hip_call(blocks, over, code, needle):
     cfg = athmhd.make_config((8, 8, 8), 2, (0.1, 0.1, 0.1), 5.0 / 3.0)
