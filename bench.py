@@ -71,7 +71,7 @@ def parse():
     p.add_argument("--no-tune", action="store_true", help="batch: keep the default tile instead of autotuning")
     p.add_argument("--graph", action="store_true", help="replay each step from a hipGraph")
     p.add_argument("--scalars", type=int, default=0,
-                   help="turbulence: passive scalars carried along (a dye, then smooth fields)")
+                   help="turbulence, batch: passive scalars carried along (a dye, then smooth fields)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain device copy of 1 GiB (for scaling PMC byte counters) and exit")
     return p.parse_args()
@@ -183,8 +183,11 @@ def bench_batch(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     blocks = inputs.amr_batch(1024, seed=args.seed)
+    ns = args.scalars
+    if ns > 0:
+        blocks = [inputs.with_scalars(b, ns, seed=args.seed + 100 + i) for i, b in enumerate(blocks)]
     s = athmhd.BatchSolver([b.n for b in blocks], [b.dx for b in blocks], 2, blocks[0].gamma, recon="plm",
-                           riemann="hlld", integrator="vl2", cfl=0.3)
+                           riemann="hlld", integrator="vl2", cfl=0.3, nscalars=ns)
     tb = torch.from_numpy(inputs.pack([b.bface for b in blocks])).to(dev)
     tc = s.prim2cons(torch.from_numpy(inputs.pack([b.prim for b in blocks])).to(dev), tb)
     stream = torch.cuda.Stream() if args.graph else torch.cuda.current_stream()
@@ -207,7 +210,8 @@ def bench_batch(args):
         elapsed = time.perf_counter() - t0
         stage_ms, launches = (0.0, 0) if args.graph else s.profile_stop()
     out = {
-        "metric": "zone-cycles/s, FP64 3D MHD VL2+PLM+HLLD, 1 MI355X, batched uneven blocks",
+        "metric": "zone-cycles/s, FP64 3D MHD VL2+PLM+HLLD, 1 MI355X, batched uneven blocks"
+                  + (f", with {ns} passive scalar(s)" if ns else ""),
         "value": zones * args.steps / elapsed, "unit": "zone-cycles/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -215,7 +219,7 @@ def bench_batch(args):
                                "2:1-balanced octree, smooth periodic states, VL2+PLM+HLLD+CT, CFL 0.3",
                    "cells": zones, "tile": None if tuned is None else {"shape": athmhd.BATCH_TILES[tuned[0]],
                                                                         "split": tuned[1]},
-                   "graph": bool(args.graph)},
+                   "graph": bool(args.graph), "nscalars": ns},
         "stage_ms_per_launch": stage_ms / max(launches, 1) if launches else None,
     }
     s.close()

@@ -96,11 +96,11 @@ typedef struct {
  * Riemann solve times C on the upwind side (left state where the mass flux is
  * >= 0).  With floors on, C = (rho C) / rho uses the floored density; the
  * floor pass after a stage leaves rho C unchanged.  Available with
- * kernel_path 0 on athmhd_create and athmhd_create_mesh handles (the mesh
- * exchange then also fills the scalars' ghost cells): athmhd_create with
- * kernel_path 1 and athmhd_create_batch return ATHMHD_EUNSUP for
- * nscalars != 0, and so do athmhd_step_vjp and athmhd_prim2cons_vjp on a
- * handle with scalars.  The MHD state of a step does not depend on the
+ * kernel_path 0 on athmhd_create, athmhd_create_mesh (the mesh exchange then
+ * also fills the scalars' ghost cells) and athmhd_create_batch handles (each
+ * block holds 5 + nscalars cell arrays): athmhd_create with kernel_path 1
+ * returns ATHMHD_EUNSUP for nscalars != 0, and so do athmhd_step_vjp and
+ * athmhd_prim2cons_vjp on a handle with scalars.  The MHD state of a step does not depend on the
  * scalars. */
 
 /* Version of this ABI (major*100 + minor). */

@@ -303,15 +303,17 @@ class MeshSolver(Solver):
 class BatchSolver:
     """Blocks of uneven sizes advanced together (one persistent launch per
     stage).  cons / bface are flat float64 tensors: the concatenation of every
-    block's (5, N3, N2, N1) and (3, N3+1, N2+1, N1+1) arrays."""
+    block's (5 + nscalars, N3, N2, N1) and (3, N3+1, N2+1, N1+1) arrays."""
 
     def __init__(self, dims, dxs, nghost, gamma, recon="plm", riemann="hlld", integrator="vl2", cfl=0.3,
-                 ct_eps=0.0):
+                 ct_eps=0.0, nscalars=0):
         import numpy as np
         self.dims = [tuple(int(x) for x in d) for d in dims]
         self.ng = int(nghost)
         self.nblocks = len(self.dims)
-        self.cfg = make_config(self.dims[0], nghost, dxs[0], gamma, recon, riemann, integrator, cfl, ct_eps)
+        self.nv = 5 + int(nscalars)
+        self.cfg = make_config(self.dims[0], nghost, dxs[0], gamma, recon, riemann, integrator, cfl, ct_eps,
+                               "fused", nscalars)
         d = np.ascontiguousarray(np.array(self.dims, dtype=np.int32).reshape(-1))
         x = np.ascontiguousarray(np.array(dxs, dtype=np.float64).reshape(-1))
         h = C.c_void_p()
@@ -335,12 +337,12 @@ class BatchSolver:
         return tuple(x + 1 for x in self.cell_shape(b))
 
     def views(self, flat, kind):
-        """Per-block views (5, ...) of a flat cons-like array or (3, ...) of a
-        flat bface-like array (numpy or torch)."""
+        """Per-block views (5 + nscalars, ...) of a flat cons-like array or
+        (3, ...) of a flat bface-like array (numpy or torch)."""
         out = []
         for b in range(self.nblocks):
             if kind == "cons":
-                o, sh, nv = self.offsets[b][0], self.cell_shape(b), 5
+                o, sh, nv = self.offsets[b][0], self.cell_shape(b), self.nv
             else:
                 o, sh, nv = self.offsets[b][1], self.face_shape(b), 3
             n = nv * sh[0] * sh[1] * sh[2]

@@ -46,6 +46,9 @@ struct athmhd_s {
   double* scratch_base = nullptr;
   // passive scalars (g.ns > 0): face mass fluxes of a stage, 3 face arrays per block
   double* d_fm = nullptr;
+  WorkItem* d_sitems = nullptr;  // batched blocks: the scalar kernel's work items
+  int nsitems = 0;
+  int min_edge = 0;  // batched blocks: fewest active cells along any direction of any block
   unsigned long long* d_dtmin = nullptr;  // running min of dx/(|v|+cf), bit pattern
   int* d_bad = nullptr;                   // [0] non-physical cells met since the last newdt, [1] floor activations
   Floors floors{0.0, 0.0};                // optional primitive floors (off by default)
@@ -207,6 +210,7 @@ void free_all(athmhd_t h) {
     if (h->reg[r]) (void)hipFree(h->reg[r]);
   if (h->scratch_base) (void)hipFree(h->scratch_base);
   if (h->d_fm) (void)hipFree(h->d_fm);
+  if (h->d_sitems) (void)hipFree(h->d_sitems);
   if (h->d_dtmin) (void)hipFree(h->d_dtmin);
   if (h->d_bad) (void)hipFree(h->d_bad);
   if (h->d_dtval) (void)hipFree(h->d_dtval);
@@ -276,7 +280,7 @@ hipError_t launch_stage(athmhd_t h, int recon, const double* xc, const double* x
   if (h->batch)
     return launch_stage_batch(h->shape, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, h->d_desc, h->d_items,
                               h->nitems, h->d_queue, xc, xb, unc, unb, oc, ob, cf, dt_dev, beta, h->grid, h->floors,
-                              h->d_bad, s);
+                              h->d_bad, h->g.ns > 0 ? h->d_fm : nullptr, s);
   if (h->cfg.kernel_path == 0)
     return launch_stage_fused(h->g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc, xb, unc, unb, oc, ob, cf,
                               dt_dev, beta, nblocks, stage_kz(h, nblocks), h->floors, h->d_bad,
@@ -337,7 +341,12 @@ int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const doubl
     if ((e = mark(h, s)) != hipSuccess) return hip_fail(h, e, "profiling event");
     // passive scalars, carried by the mass fluxes the stage kernel stored
     if (h->g.ns > 0) {
-      e = launch_scalar_stage(h->g, recon, xc, cons, oc, h->d_fm, cf, dt_dev, sc.beta[st], nblocks, h->floors, s);
+      // one correction step finds the periodic images when every block has
+      // more active cells per direction than the stencil's halo
+      e = h->batch ? launch_scalar_stage_batch(h->d_desc, h->d_sitems, h->nsitems, h->g.ns, h->min_edge > recon + 1,
+                                               recon, xc, cons, oc, h->d_fm, cf, dt_dev, sc.beta[st], h->floors, s)
+                   : launch_scalar_stage(h->g, recon, xc, cons, oc, h->d_fm, cf, dt_dev, sc.beta[st], nblocks,
+                                         h->floors, s);
       if (e != hipSuccess) return hip_fail(h, e, "scalar stage launch");
     }
     if (h->floors.on()) {
@@ -527,7 +536,6 @@ int athmhd_create_batch(const athmhd_config* base, const int32_t* dims, const do
   int rc = validate_common(base);
   if (rc != ATHMHD_OK) return rc;
   if (base->kernel_path != 0) return fail(nullptr, ATHMHD_EUNSUP, "batched blocks run on the fused kernel only");
-  if (base->nscalars != 0) return fail(nullptr, ATHMHD_EUNSUP, "passive scalars are available on periodic blocks only");
   if (!dims || !dx) return fail(nullptr, ATHMHD_EINVAL, "NULL dims or dx");
   if (nblocks < 1 || nblocks > 65535) return fail(nullptr, ATHMHD_EINVAL, "nblocks must be in [1, 65535]");
   for (int b = 0; b < nblocks; ++b) {
@@ -547,7 +555,7 @@ int athmhd_create_batch(const athmhd_config* base, const int32_t* dims, const do
   for (int b = 0; b < nblocks; ++b) {
     BatchDesc& d = h->desc[b];
     d.g = make_geo(dims[3 * b], dims[3 * b + 1], dims[3 * b + 2], base->nghost, dx[3 * b], dx[3 * b + 1],
-                   dx[3 * b + 2]);
+                   dx[3 * b + 2], base->nscalars);
     d.coff = h->ctot;
     d.foff = h->ftot;
     h->ctot += d.g.cblock;
@@ -555,6 +563,8 @@ int athmhd_create_batch(const athmhd_config* base, const int32_t* dims, const do
     const Geo& g = d.g;
     h->max_shell = std::max<int64_t>(h->max_shell, g.fvar - (int64_t)g.n1 * g.n2 * g.n3);
     h->max_cells = std::max<int64_t>(h->max_cells, g.cvar);
+    const int edge = std::min(g.n1, std::min(g.n2, g.n3));
+    h->min_edge = b == 0 ? edge : std::min(h->min_edge, edge);
   }
   h->g = h->desc[0].g;
   h->nbmax = nblocks;
@@ -570,12 +580,34 @@ int athmhd_create_batch(const athmhd_config* base, const int32_t* dims, const do
   bool ok = hipMalloc(&h->reg[0], state * sizeof(double)) == hipSuccess &&
             hipMalloc(&h->reg[1], state * sizeof(double)) == hipSuccess &&
             hipMalloc(&h->d_desc, nblocks * sizeof(BatchDesc)) == hipSuccess &&
-            hipMalloc(&h->d_queue, sizeof(unsigned)) == hipSuccess && alloc_common(h);
+            hipMalloc(&h->d_queue, sizeof(unsigned)) == hipSuccess && alloc_common(h) &&
+            (base->nscalars == 0 || hipMalloc(&h->d_fm, h->ftot * sizeof(double)) == hipSuccess);
   if (!ok) {
     (void)hipGetLastError();
     free_all(h);
     delete h;
     return fail(nullptr, ATHMHD_ENOMEM, "device allocation of %.3f GB failed", 2.0 * state * 8.0 / 1e9);
+  }
+  if (base->nscalars > 0) {
+    // work items of the scalar kernel: tiles of T x T columns, x3 segments of
+    // at most 32 planes
+    const int T = scalar_batch_tile();
+    std::vector<WorkItem> si;
+    for (int b = 0; b < nblocks; ++b) {
+      const Geo& g = h->desc[b].g;
+      for (int k0 = g.ng; k0 < g.ng + g.n3; k0 += 32)
+        for (int ty = 0; ty < (g.n2 + T - 1) / T; ++ty)
+          for (int tx = 0; tx < (g.n1 + T - 1) / T; ++tx) si.push_back({b, tx, ty, k0, std::min(k0 + 32, g.ng + g.n3)});
+    }
+    h->nsitems = (int)si.size();
+    e = hipMalloc(&h->d_sitems, si.size() * sizeof(WorkItem));
+    if (e == hipSuccess) e = hipMemcpy(h->d_sitems, si.data(), si.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      free_all(h);
+      delete h;
+      return fail(nullptr, ATHMHD_ENOMEM, "scalar work items: %s", hipGetErrorString(e));
+    }
   }
   e = hipMemcpy(h->d_desc, h->desc.data(), nblocks * sizeof(BatchDesc), hipMemcpyHostToDevice);
   if (e != hipSuccess) {

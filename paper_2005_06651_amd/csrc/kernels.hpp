@@ -80,7 +80,14 @@ hipError_t launch_stage_batch(int shape, double gamma, int recon, int rs, double
                               const WorkItem* items, int nitems, unsigned* queue, const double* xc,
                               const double* xb, const double* unc, const double* unb, double* outc, double* outb,
                               StageCoef coef, const double* dt_dev, double beta, int grid, Floors fl, int* bad,
-                              hipStream_t s);
+                              double* fm, hipStream_t s);  // fm: NULL, or mass-flux output laid out like bface
+// Passive scalars of one stage of batched blocks (same contract as
+// launch_scalar_stage; fm laid out like bface).  items: one per (block, tile of
+// scalar_batch_tile() x scalar_batch_tile() columns, x3 segment).
+int scalar_batch_tile();
+hipError_t launch_scalar_stage_batch(const BatchDesc* desc, const WorkItem* items, int nitems, int ns, bool near,
+                                     int recon, const double* xc, const double* unc, double* outc, const double* fm,
+                                     StageCoef coef, const double* dt_dev, double beta, Floors fl, hipStream_t s);
 // Ghost fill, prim->cons and the CFL reduction over all blocks of a batch.
 hipError_t launch_fill_ghosts_batch(const BatchDesc* desc, int nblocks, int64_t max_shell, double* cons,
                                     double* bface, hipStream_t s);

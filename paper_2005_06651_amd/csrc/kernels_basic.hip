@@ -363,6 +363,7 @@ __global__ void __launch_bounds__(kThreads) k_fill_ghosts_batch(const BatchDesc*
       const int dd = g.c(i, j, k), ss = g.c(ii, jj, kk);
 #pragma unroll
       for (int v = 0; v < 5; ++v) cb[v * g.cvar + dd] = cb[v * g.cvar + ss];
+      for (int v = 5; v < 5 + g.ns; ++v) cb[v * g.cvar + dd] = cb[v * g.cvar + ss];  // passive scalars
     }
     const int dd = g.f(i, j, k), ss = g.f(ii, jj, kk);
 #pragma unroll
@@ -394,6 +395,7 @@ __global__ void __launch_bounds__(kThreads) k_prim2cons_batch(const BatchDesc* _
     u[3 * g.cvar + t] = rho * v3;
     u[4 * g.cvar + t] =
         p / (gamma - 1.0) + 0.5 * rho * (v1 * v1 + v2 * v2 + v3 * v3) + 0.5 * (b1 * b1 + b2 * b2 + b3 * b3);
+    for (int v = 5; v < 5 + g.ns; ++v) u[v * g.cvar + t] = rho * w[v * g.cvar + t];  // passive scalars
   }
 }
 

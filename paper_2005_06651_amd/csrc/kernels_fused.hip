@@ -94,6 +94,7 @@ struct BatchArgs {
   const double* unb;
   double* oc;
   double* ob;
+  double* fm;  // NULL, or the face mass-flux output, laid out like bface
 };
 
 // z-frame primitive vector of a cell: (rho, v3, v1, v2, P, B1cc, B2cc) plus
@@ -634,7 +635,7 @@ k_stage_fused(UniformArgs a) {
 
 // Batched blocks of uneven sizes: a persistent grid whose workgroups pull
 // (block, tile, x3 segment) items from a device queue until it is drained.
-template <int RECON, int RS, class T, bool FL>
+template <int RECON, int RS, class T, bool FL, bool MF>
 __global__ void __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(2))) k_stage_batch(BatchArgs a) {
   using S = Smem<RECON, T>;
   __shared__ double sp[8 * S::PL];
@@ -649,8 +650,9 @@ __global__ void __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(2)))
     if (it >= a.nitems) break;
     const WorkItem w = a.items[it];
     const BatchDesc& d = a.desc[w.block];
-    BlockPtrs bp{a.xc + d.coff, a.xb + d.foff, a.unc + d.coff, a.unb + d.foff, a.oc + d.coff, a.ob + d.foff};
-    stage_tile<RECON, RS, T, FL>(d.g, bp, a.sa, w.tile_x, w.tile_y, w.k0, w.kend, sp, sx, sc);
+    BlockPtrs bp{a.xc + d.coff, a.xb + d.foff, a.unc + d.coff, a.unb + d.foff, a.oc + d.coff, a.ob + d.foff,
+                 MF ? a.fm + d.foff : nullptr};
+    stage_tile<RECON, RS, T, FL, false, MF>(d.g, bp, a.sa, w.tile_x, w.tile_y, w.k0, w.kend, sp, sx, sc);
     __syncthreads();
   }
 }
@@ -681,14 +683,19 @@ __global__ void k_zero_u32(unsigned* p) {
   if (threadIdx.x == 0) *p = 0u;
 }
 
+template <class T, int RECON, bool MF>
+hipError_t launch_batch_m(int rs, const BatchArgs& ba, int grid, hipStream_t s) {
+  const bool fl = ba.sa.fl.on();
+  if (rs == 1 && fl) hipLaunchKernelGGL((k_stage_batch<RECON, 1, T, true, MF>), dim3(grid), dim3(T::NT), 0, s, ba);
+  else if (rs == 1) hipLaunchKernelGGL((k_stage_batch<RECON, 1, T, false, MF>), dim3(grid), dim3(T::NT), 0, s, ba);
+  else if (fl) hipLaunchKernelGGL((k_stage_batch<RECON, 0, T, true, MF>), dim3(grid), dim3(T::NT), 0, s, ba);
+  else hipLaunchKernelGGL((k_stage_batch<RECON, 0, T, false, MF>), dim3(grid), dim3(T::NT), 0, s, ba);
+  return hipGetLastError();
+}
+
 template <class T, int RECON>
 hipError_t launch_batch_t(int rs, const BatchArgs& ba, int grid, hipStream_t s) {
-  const bool fl = ba.sa.fl.on();
-  if (rs == 1 && fl) hipLaunchKernelGGL((k_stage_batch<RECON, 1, T, true>), dim3(grid), dim3(T::NT), 0, s, ba);
-  else if (rs == 1) hipLaunchKernelGGL((k_stage_batch<RECON, 1, T, false>), dim3(grid), dim3(T::NT), 0, s, ba);
-  else if (fl) hipLaunchKernelGGL((k_stage_batch<RECON, 0, T, true>), dim3(grid), dim3(T::NT), 0, s, ba);
-  else hipLaunchKernelGGL((k_stage_batch<RECON, 0, T, false>), dim3(grid), dim3(T::NT), 0, s, ba);
-  return hipGetLastError();
+  return ba.fm ? launch_batch_m<T, RECON, true>(rs, ba, grid, s) : launch_batch_m<T, RECON, false>(rs, ba, grid, s);
 }
 
 template <class T>
@@ -761,7 +768,7 @@ hipError_t launch_stage_batch(int shape, double gamma, int recon, int rs, double
                               const WorkItem* items, int nitems, unsigned* queue, const double* xc,
                               const double* xb, const double* unc, const double* unb, double* outc, double* outb,
                               StageCoef coef, const double* dt_dev, double beta, int grid, Floors fl, int* bad,
-                              hipStream_t s) {
+                              double* fm, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, queue);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -772,6 +779,7 @@ hipError_t launch_stage_batch(int shape, double gamma, int recon, int rs, double
   ba.queue = queue;
   ba.sa = make_stage_args(gamma, ct_eps, coef, dt_dev, beta, fl, bad);
   ba.xc = xc; ba.xb = xb; ba.unc = unc; ba.unb = unb; ba.oc = outc; ba.ob = outb;
+  ba.fm = fm;
   switch (shape) {
     case 0: return launch_batch_recon<Tile<18, 14>>(recon, rs, ba, grid, s);
     case 1: return launch_batch_recon<Tile<14, 18>>(recon, rs, ba, grid, s);

@@ -115,7 +115,7 @@ def _create_batch(dims, dxs, **over):
     ([(16, 16, 16)], [(0.1, -1.0, 0.1)], {}, athmhd.EINVAL, "widths"),
     ([(16, 16, 16)], [(0.1,) * 3], {"kernel_path": 1}, athmhd.EUNSUP, "fused"),
     ([(16, 16, 16)], [(0.1,) * 3], {"nghost": 1}, athmhd.EINVAL, "nghost"),
-    ([(16, 16, 16)], [(0.1,) * 3], {"nscalars": 1}, athmhd.EUNSUP, "scalars"),
+    ([(16, 16, 16)], [(0.1,) * 3], {"nscalars": 65}, athmhd.EINVAL, "nscalars"),
 ])
 def test_create_batch_rejects_bad_blocks(dims, dxs, over, code, needle):
     rc, msg = _create_batch(dims, dxs, **over)

@@ -161,3 +161,70 @@ def test_graph_replay_matches_eager(torch_dev, athmhd, orc):
                 assert torch.equal(ce, cg) and torch.equal(be, bg), (kind, it)
         eager.close()
         graph.close()
+
+
+@pytest.mark.parametrize("integ,recon,rs,ns,floors", [
+    ("vl2", "plm", "hlld", 2, None),
+    ("rk3", "ppm", "hlle", 1, None),
+    ("rk2", "dc", "hlld", 3, (0.8, 0.9)),
+])
+def test_batch_with_scalars_matches_oracle_per_block(torch_dev, athmhd, orc, integ, recon, rs, ns, floors):
+    """Passive scalars (Sec. 3.2.6) on batched blocks of several shapes, some
+    smaller than a scalar tile: two steps, every block's MHD arrays and
+    scalars against the oracle's within the 1e-12 bar."""
+    torch, dev = torch_dev
+    ng = 3 if recon == "ppm" else 2
+    blocks = [inputs.with_scalars(b, ns, seed=90 + i) for i, b in enumerate(small_batch(seed=9, ng=ng))]
+    kw = dict(integrator=integ, recon=recon, riemann=rs)
+    s = athmhd.BatchSolver([b.n for b in blocks], [b.dx for b in blocks], ng, blocks[0].gamma, nscalars=ns, **kw)
+    fl = floors or (0.0, 0.0)
+    if floors:
+        s.set_floors(*floors)
+    cfgs = [orc.cfg_for(b, nscalars=ns, dfloor=fl[0], pfloor=fl[1], **kw) for b in blocks]
+    cons = [orc.prim2cons(orc.cfg_for(b, nscalars=ns, **kw), b.prim, b.bface) for b in blocks]
+    tb = torch.from_numpy(inputs.pack([b.bface for b in blocks])).to(dev)
+    tc = s.prim2cons(torch.from_numpy(inputs.pack([b.prim for b in blocks])).to(dev), tb)
+    gc0 = s.views(tc.cpu().numpy(), "cons")
+    for b in range(len(blocks)):
+        assert np.array_equal(gc0[b][5:], cons[b][5:])
+    rc = [c.copy() for c in cons]
+    rb = [b.bface.copy() for b in blocks]
+    for _ in range(2):
+        dt = min(orc.newdt(c, x, y)[0] for c, x, y in zip(cfgs, rc, rb))
+        assert abs(s.newdt(tc, tb) - dt) <= 1e-13 * dt
+        for c, x, y in zip(cfgs, rc, rb):
+            assert orc.step(c, x, y, dt) == 0
+        s.step(tc, tb, dt)
+    gc = s.views(tc.cpu().numpy(), "cons")
+    gb = s.views(tb.cpu().numpy(), "bface")
+    for b, blk in enumerate(blocks):
+        g = blk.ng
+        a = (slice(None), slice(g, g + blk.n[2]), slice(g, g + blk.n[1]), slice(g, g + blk.n[0]))
+        for x, y in ((gc[b][a], rc[b][a]), (gb[b][a], rb[b][a])):
+            for v in range(x.shape[0]):
+                err = np.abs(x[v] - y[v]).sum() / max(np.abs(y[v]).sum(), 1e-300)
+                assert err <= TOL, (b, blk.n, v, err)
+    s.close()
+
+
+def test_batch_graph_replay_with_scalars(torch_dev, athmhd, orc):
+    """hipGraph replays of a batched step with scalars equal eager steps."""
+    torch, dev = torch_dev
+    stream = torch.cuda.Stream()
+    blocks = [inputs.with_scalars(b, 2, seed=95 + i) for i, b in enumerate(small_batch(seed=10))]
+    mk = lambda: athmhd.BatchSolver([x.n for x in blocks], [x.dx for x in blocks], 2, blocks[0].gamma, nscalars=2)
+    eager, graph = mk(), mk()
+    graph.set_graph(True)
+    b0 = torch.from_numpy(inputs.pack([x.bface for x in blocks])).to(dev)
+    c0 = eager.prim2cons(torch.from_numpy(inputs.pack([x.prim for x in blocks])).to(dev), b0)
+    ce, be, cg, bg = c0.clone(), b0.clone(), c0.clone(), b0.clone()
+    with torch.cuda.stream(stream):
+        for it in range(4):
+            dt = eager.newdt(ce, be, stream=stream) * (0.7 + 0.1 * it)
+            eager.step(ce, be, dt, stream=stream)
+            graph.step(cg, bg, dt, stream=stream)
+            stream.synchronize()
+            torch.ones(1000, device=dev).sum()
+            assert torch.equal(ce, cg) and torch.equal(be, bg), it
+    eager.close()
+    graph.close()
