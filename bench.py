@@ -38,8 +38,8 @@ ALG_FLOPS_PER_ZONE_CYCLE = 2560.0
 # of the stage-kernel sources they were measured on (traffic is reported only
 # while the sources are unchanged).
 STAGE_TRAFFIC = {"bytes_per_launch": 3.468e+09, "fetch_bytes_per_launch": 2.295e+09,
-                 "write_bytes_per_launch": 1.173e+09, "fetch_scale": 1.9999, "write_scale": 1.0000,
-                 "source_hash": "1a2bef9b697f5c3b"}
+                 "write_bytes_per_launch": 1.172e+09, "fetch_scale": 1.9999, "write_scale": 1.0000,
+                 "source_hash": "38a041e3236d4fb2"}
 
 
 def parse():
