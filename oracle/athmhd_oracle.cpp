@@ -42,7 +42,15 @@
 //     through a face is the face mass flux times C_i on the upwind side (the
 //     left state where the mass flux is >= 0, else the right state); with
 //     floors, C_i = (rho C_i) / rho_W with the floored density, and the floor
-//     pass after a stage leaves rho C_i alone.
+//     pass after a stage leaves rho C_i alone;
+//   * characteristic reconstruction (Sec. 3.2.1, C = L W, optional, PLM): the
+//     paper defers the projection steps to another paper.  Reading: for each
+//     cell the one-sided differences of the face-frame primitives are
+//     projected with the left eigenvectors of that cell's primitive system,
+//     limited component by component with the van Leer limiter, and projected
+//     back with the right eigenvectors; the edge values are W -/+ dW/2.  Right
+//     eigenvectors follow the Roe & Balsara (1996) normalisation; the left ones
+//     are their inverse.
 #include <algorithm>
 #include <cmath>
 #include <cstddef>
@@ -138,6 +146,8 @@ struct Cfg {
   double cfl;                   // Courant number C0 used by newdt
   double ct_eps;                // 0: sign switch for the CT upwinding; >0: ramp width
   double dfloor, pfloor;        // optional density / pressure floors (0: off)
+  int32_t charac;               // 1: PLM on characteristic variables (DC unchanged; PPM unsupported)
+  int32_t pad_;
 };
 
 // Number of primitive evaluations (cells and reconstructed face states) that a
@@ -345,6 +355,134 @@ template <class T> void ppm_cell(const T* q, T& left, T& right) {
 }
 
 // Left and right states at face c-1/2 from the cells around it.
+// ---------------------------------------------------------------------------
+// Characteristic variables (Sec. 3.2.1: C = L W).  Face frame, primitive
+// vector w = (rho, vn, vt1, vt2, P, Bt1, Bt2) with the normal field bn fixed.
+// The system W_t + A W_x = 0 has the waves vn - cf, vn - ca, vn - cs, vn,
+// vn + cs, vn + ca, vn + cf (fast, Alfven, slow magnetosonic and entropy).
+// Columns of R are the right eigenvectors in that order, normalised after
+// Roe & Balsara (1996): alpha_f^2 = (a^2 - cs^2)/(cf^2 - cs^2), alpha_s^2 =
+// (cf^2 - a^2)/(cf^2 - cs^2), (beta_1, beta_2) the direction of the
+// transverse field (1/sqrt2 each when it vanishes), and where cf = cs the
+// pair alpha_f = 1, alpha_s = 0.
+// ---------------------------------------------------------------------------
+template <class T> void prim_right_eigenvectors(const T* w, const T& bn, double gamma, T R[7][7]) {
+  const T rho = w[0], p = w[4], b1 = w[5], b2 = w[6];
+  const T a2 = gamma * p / rho;
+  const T ca2 = bn * bn / rho;
+  const T bt2 = b1 * b1 + b2 * b2;
+  const T bb2 = ca2 + bt2 / rho;
+  T disc2 = (a2 + bb2) * (a2 + bb2) - 4.0 * a2 * ca2;
+  if (!(val(disc2) > 0.0)) disc2 = T(0.0);
+  const T cf2 = 0.5 * (a2 + bb2 + sqrt(disc2));
+  const T cs2 = val(cf2) > 0.0 ? a2 * ca2 / cf2 : T(0.0);
+  T af(1.0), as(0.0);
+  if (val(cf2 - cs2) > 0.0) {
+    T af2 = (a2 - cs2) / (cf2 - cs2), as2 = (cf2 - a2) / (cf2 - cs2);
+    af2 = vmin(T(1.0), vmax(T(0.0), af2));
+    as2 = vmin(T(1.0), vmax(T(0.0), as2));
+    af = sqrt(af2);
+    as = sqrt(as2);
+  }
+  T be1(1.0 / std::sqrt(2.0)), be2(1.0 / std::sqrt(2.0));
+  if (val(bt2) > 0.0) {
+    const T bt = sqrt(bt2);
+    be1 = b1 / bt;
+    be2 = b2 / bt;
+  }
+  const double sg = val(bn) >= 0.0 ? 1.0 : -1.0;
+  const T a = sqrt(a2), cf = sqrt(cf2), cs = sqrt(cs2), sr = sqrt(rho);
+  const T gp = gamma * p;
+  for (int r = 0; r < 7; ++r)
+    for (int c = 0; c < 7; ++c) R[r][c] = T(0.0);
+  // fast waves, vn -/+ cf (columns 0 and 6)
+  for (int side = 0; side < 2; ++side) {
+    const int c = side == 0 ? 0 : 6;
+    const double m = side == 0 ? -1.0 : 1.0;  // sign of the wave speed relative to vn
+    R[0][c] = rho * af;
+    R[1][c] = m * cf * af;
+    R[2][c] = -m * as * cs * be1 * sg;
+    R[3][c] = -m * as * cs * be2 * sg;
+    R[4][c] = gp * af;
+    R[5][c] = as * sr * a * be1;
+    R[6][c] = as * sr * a * be2;
+  }
+  // Alfven waves, vn -/+ ca (columns 1 and 5)
+  for (int side = 0; side < 2; ++side) {
+    const int c = side == 0 ? 1 : 5;
+    const double m = side == 0 ? -1.0 : 1.0;
+    R[2][c] = m * be2;
+    R[3][c] = -m * be1;
+    R[5][c] = -be2 * sg * sr;
+    R[6][c] = be1 * sg * sr;
+  }
+  // slow waves, vn -/+ cs (columns 2 and 4)
+  for (int side = 0; side < 2; ++side) {
+    const int c = side == 0 ? 2 : 4;
+    const double m = side == 0 ? -1.0 : 1.0;
+    R[0][c] = rho * as;
+    R[1][c] = m * cs * as;
+    R[2][c] = m * af * cf * be1 * sg;
+    R[3][c] = m * af * cf * be2 * sg;
+    R[4][c] = gp * as;
+    R[5][c] = -af * sr * a * be1;
+    R[6][c] = -af * sr * a * be2;
+  }
+  // entropy wave, vn (column 3)
+  R[0][3] = T(1.0);
+}
+
+// Inverse of a 7 x 7 matrix by Gauss-Jordan elimination with partial
+// pivoting (pivots chosen by magnitude of the value part).
+template <class T> void invert7(const T A[7][7], T X[7][7]) {
+  T M[7][14];
+  for (int r = 0; r < 7; ++r)
+    for (int c = 0; c < 14; ++c) M[r][c] = c < 7 ? A[r][c] : T(c - 7 == r ? 1.0 : 0.0);
+  for (int c = 0; c < 7; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 7; ++r)
+      if (std::fabs(val(M[r][c])) > std::fabs(val(M[piv][c]))) piv = r;
+    if (piv != c)
+      for (int k = 0; k < 14; ++k) std::swap(M[c][k], M[piv][k]);
+    const T inv = 1.0 / M[c][c];
+    for (int k = 0; k < 14; ++k) M[c][k] = M[c][k] * inv;
+    for (int r = 0; r < 7; ++r) {
+      if (r == c) continue;
+      const T f = M[r][c];
+      for (int k = 0; k < 14; ++k) M[r][k] = M[r][k] - f * M[c][k];
+    }
+  }
+  for (int r = 0; r < 7; ++r)
+    for (int c = 0; c < 7; ++c) X[r][c] = M[r][c + 7];
+}
+
+// Characteristic PLM edges of cell c from its neighbours: wm = W_{c-1},
+// w0 = W_c, wp = W_{c+1} (7 face-frame primitives each), bn the cell-centred
+// normal field of c.  left = W_c - dW/2, right = W_c + dW/2 with dW = R lim(L
+// dW-, L dW+), lim the van Leer harmonic mean applied per wave family.
+template <class T>
+void char_plm_edges(const T* wm, const T* w0, const T* wp, const T& bn, double gamma, T* left, T* right) {
+  T R[7][7], L[7][7];
+  prim_right_eigenvectors(w0, bn, gamma, R);
+  invert7(R, L);
+  T dc[7];
+  for (int k = 0; k < 7; ++k) {
+    T dl(0.0), dr(0.0);
+    for (int j = 0; j < 7; ++j) {
+      dl = dl + L[k][j] * (w0[j] - wm[j]);
+      dr = dr + L[k][j] * (wp[j] - w0[j]);
+    }
+    const T prod = dl * dr;
+    dc[k] = val(prod) > 0.0 ? 2.0 * prod / (dl + dr) : T(0.0);
+  }
+  for (int j = 0; j < 7; ++j) {
+    T dw(0.0);
+    for (int k = 0; k < 7; ++k) dw = dw + R[j][k] * dc[k];
+    left[j] = w0[j] - 0.5 * dw;
+    right[j] = w0[j] + 0.5 * dw;
+  }
+}
+
 template <class T> void recon_face(int recon, const T* q, T& ql, T& qr) {
   if (recon == RECON_DC) {
     ql = q[-1];
@@ -563,7 +701,23 @@ int spatial_operator(const Cfg& cfg, const Geo& g, int recon, const T* cons, con
             line[6][o + 3] = wk.bcc[t2 * nc + q];
           }
           T wl[7], wr[7];
-          for (int n = 0; n < 7; ++n) recon_face(recon, &line[n][3], wl[n], wr[n]);
+          if (cfg.charac && recon == RECON_PLM) {
+            // characteristic PLM: right edge of cell c-1 and left edge of cell c,
+            // each with the eigenvectors of its own cell
+            T w[4][7], bnc[2];
+            for (int o = 0; o < 4; ++o)
+              for (int n = 0; n < 7; ++n) w[o][n] = line[n][o + 1];  // cells c-2 .. c+1
+            for (int o = 0; o < 2; ++o) {
+              int idx[3] = {i, j, k};
+              idx[d] += o - 1;
+              bnc[o] = wk.bcc[(size_t)d * nc + g.c(idx[0], idx[1], idx[2])];
+            }
+            T lft[7], rgt[7];
+            char_plm_edges(w[0], w[1], w[2], bnc[0], cfg.gamma, lft, wl);  // cell c-1
+            char_plm_edges(w[1], w[2], w[3], bnc[1], cfg.gamma, wr, rgt);  // cell c
+          } else {
+            for (int n = 0; n < 7; ++n) recon_face(recon, &line[n][3], wl[n], wr[n]);
+          }
           // floors, when enabled, also apply to the reconstructed face states
           if (cfg.dfloor > 0.0 || cfg.pfloor > 0.0) {
             T* st[2] = {wl, wr};
@@ -784,6 +938,7 @@ template <class T> int step(const Cfg& cfg, T* cons, T* bf, double dt) {
   Geo g(cfg);
   Scheme sc;
   if (!scheme_for(cfg.integrator, sc)) return -1;
+  if (cfg.charac && cfg.recon == RECON_PPM) return -1;  // characteristic PPM is not part of this oracle
   const size_t nc = g.ncell(), nf = g.nface();
   const size_t ncv = g.nv * nc;  // cell part of the state: MHD variables and scalars
   const size_t n = ncv + 3 * nf;
@@ -930,6 +1085,27 @@ int orc_phys_flux(double gamma, const double* w, double bn, double* u, double* f
 
 double orc_fast_speed(double rho, double p, double bn, double bt1, double bt2, double gamma) {
   return orc::fast_speed<double>(rho, p, bn, bt1, bt2, gamma);
+}
+
+// Right eigenvectors (columns, row-major 7 x 7) and their inverse for one
+// face-frame primitive state w (7 values) with normal field bn.
+int orc_prim_eigen(double gamma, const double* w, double bn, double* R, double* L) {
+  double r[7][7], l[7][7];
+  orc::prim_right_eigenvectors<double>(w, bn, gamma, r);
+  orc::invert7<double>(r, l);
+  for (int i = 0; i < 7; ++i)
+    for (int j = 0; j < 7; ++j) {
+      R[i * 7 + j] = r[i][j];
+      L[i * 7 + j] = l[i][j];
+    }
+  return 0;
+}
+
+// Characteristic PLM edges of one cell (w0) from its neighbours (wm, wp).
+int orc_char_plm(double gamma, const double* wm, const double* w0, const double* wp, double bn, double* left,
+                 double* right) {
+  orc::char_plm_edges<double>(wm, w0, wp, bn, gamma, left, right);
+  return 0;
 }
 
 // Reconstruct along a 1D line of n cells: for every face c-1/2 whose stencil

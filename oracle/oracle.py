@@ -35,7 +35,8 @@ class Cfg(C.Structure):
     _fields_ = [("n1", C.c_int32), ("n2", C.c_int32), ("n3", C.c_int32), ("ng", C.c_int32),
                 ("gamma", C.c_double), ("dx1", C.c_double), ("dx2", C.c_double), ("dx3", C.c_double),
                 ("recon", C.c_int32), ("riemann", C.c_int32), ("integrator", C.c_int32), ("nscalars", C.c_int32),
-                ("cfl", C.c_double), ("ct_eps", C.c_double), ("dfloor", C.c_double), ("pfloor", C.c_double)]
+                ("cfl", C.c_double), ("ct_eps", C.c_double), ("dfloor", C.c_double), ("pfloor", C.c_double),
+                ("charac", C.c_int32), ("pad_", C.c_int32)]
 
 
 _lib = None
@@ -59,6 +60,8 @@ def lib():
         _lib.orc_fast_speed.argtypes = [C.c_double] * 6
         _lib.orc_fast_speed.restype = C.c_double
         _lib.orc_recon_line.argtypes = [C.c_int, C.c_int, P, P, P]
+        _lib.orc_prim_eigen.argtypes = [C.c_double, P, C.c_double, P, P]
+        _lib.orc_char_plm.argtypes = [C.c_double, P, P, P, C.c_double, P, P]
         _lib.orc_drive_scalar.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_int,
                                           P, P]
         _lib.orc_take_floor_count.restype = C.c_longlong
@@ -71,11 +74,11 @@ def _p(a: np.ndarray):
 
 
 def make_cfg(n, ng, dx, gamma, recon="plm", riemann="hlld", integrator="vl2", cfl=0.3, ct_eps=0.0,
-             dfloor=0.0, pfloor=0.0, nscalars=0) -> Cfg:
+             dfloor=0.0, pfloor=0.0, nscalars=0, charac=False) -> Cfg:
     assert nscalars >= 0
     return Cfg(int(n[0]), int(n[1]), int(n[2]), int(ng), float(gamma), float(dx[0]), float(dx[1]),
                float(dx[2]), RECON[recon], RIEMANN[riemann], INTEGRATOR[integrator], int(nscalars), float(cfl),
-               float(ct_eps), float(dfloor), float(pfloor))
+               float(ct_eps), float(dfloor), float(pfloor), int(bool(charac)), 0)
 
 
 def _check(cfg: Cfg, cells: np.ndarray, bface: np.ndarray | None = None) -> None:
@@ -172,6 +175,24 @@ def recon_line(recon: str, q):
     qr = np.full_like(q, np.nan)
     lib().orc_recon_line(RECON[recon], len(q), _p(q), _p(ql), _p(qr))
     return ql, qr
+
+
+def prim_eigen(gamma: float, w, bn: float):
+    """(R, L): right eigenvectors as columns and their inverse, for the
+    face-frame primitive state w = (rho, vn, vt1, vt2, P, Bt1, Bt2)."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    R = np.zeros((7, 7))
+    L = np.zeros((7, 7))
+    lib().orc_prim_eigen(float(gamma), _p(w), float(bn), _p(R), _p(L))
+    return R, L
+
+
+def char_plm(gamma: float, wm, w0, wp, bn: float):
+    """Characteristic PLM (left, right) edge states of the cell w0."""
+    wm, w0, wp = (np.ascontiguousarray(x, dtype=np.float64) for x in (wm, w0, wp))
+    left, right = np.zeros(7), np.zeros(7)
+    lib().orc_char_plm(float(gamma), _p(wm), _p(w0), _p(wp), float(bn), _p(left), _p(right))
+    return left, right
 
 
 def drive_scalar(integrator: str, lam: complex, dt: float, nsteps: int) -> complex:
