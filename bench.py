@@ -70,6 +70,8 @@ def parse():
     p.add_argument("--mesh-blocks", type=int, default=8, help="mesh: blocks per direction of the 256^3 domain")
     p.add_argument("--no-tune", action="store_true", help="batch: keep the default tile instead of autotuning")
     p.add_argument("--graph", action="store_true", help="replay each step from a hipGraph")
+    p.add_argument("--charac", action="store_true",
+                   help="turbulence: PLM on characteristic variables (runs the unfused pipeline)")
     p.add_argument("--scalars", type=int, default=0,
                    help="turbulence, batch: passive scalars carried along (a dye, then smooth fields)")
     p.add_argument("--copy-calibration", action="store_true",
@@ -505,7 +507,8 @@ def main():
     if ns > 0:
         block = inputs.with_scalars(block, ns, seed=args.seed + 100)
     solver = athmhd.Solver(block.n, block.ng, block.dx, block.gamma, recon="plm", riemann="hlld",
-                           integrator="vl2", cfl=0.3, kernel_path=args.kernel_path, nscalars=ns)
+                           integrator="vl2", cfl=0.3, kernel_path=args.kernel_path, nscalars=ns,
+                           charac=args.charac)
     tb = torch.from_numpy(block.bface).to(dev)
     tc = solver.prim2cons(torch.from_numpy(block.prim).to(dev), tb)
     torch.cuda.synchronize()
@@ -538,7 +541,7 @@ def main():
     achieved_gbs = alg_bytes / per_launch_s / 1e9
     traffic = None
     if STAGE_TRAFFIC and STAGE_TRAFFIC.get("source_hash") == stage_source_hash() and args.kernel_path == "fused" \
-            and n == 256 and ns == 0:
+            and n == 256 and ns == 0 and not args.charac:
         traffic = STAGE_TRAFFIC["bytes_per_launch"]
     # sanity of the final state
     solver.fill_ghosts(tc, tb)
@@ -553,7 +556,7 @@ def main():
 
     out = {
         "metric": "zone-cycles/s, FP64 3D MHD VL2+PLM+HLLD, 1 MI355X"
-                  + (f", with {ns} passive scalar(s)" if ns else ""),
+                  + (f", with {ns} passive scalar(s)" if ns else "") + (", characteristic PLM" if args.charac else ""),
         "value": value,
         "unit": "zone-cycles/s",
         "n_gpus": 1,
@@ -569,7 +572,8 @@ def main():
             "workload": f"decaying MHD turbulence {n}^3 periodic, VL2+PLM+HLLD+CT, gamma 5/3, rms Mach 1, "
                         f"B = 0.5 x + curl A (rms 0.1), CFL 0.3, dt from newdt every step",
             "cells": zones, "nghost": g, "integrator": "vl2", "recon": "plm", "riemann": "hlld",
-            "seed": args.seed, "kernel_path": args.kernel_path, "nscalars": ns,
+            "seed": args.seed, "kernel_path": "unfused" if args.charac else args.kernel_path, "nscalars": ns,
+            "characteristic": bool(args.charac),
         },
         "roofline": {
             "bound": "alu",

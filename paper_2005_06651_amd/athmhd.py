@@ -42,7 +42,7 @@ class Config(C.Structure):
                 ("gamma", C.c_double), ("dx1", C.c_double), ("dx2", C.c_double), ("dx3", C.c_double),
                 ("recon", C.c_int32), ("riemann", C.c_int32), ("integrator", C.c_int32),
                 ("kernel_path", C.c_int32), ("cfl", C.c_double), ("ct_eps", C.c_double),
-                ("nscalars", C.c_int32)]
+                ("nscalars", C.c_int32), ("charac", C.c_int32)]
 
 
 _lib = None
@@ -88,10 +88,10 @@ KERNEL_PATH = {"fused": 0, "unfused": 1}
 
 
 def make_config(n, nghost, dx, gamma, recon="plm", riemann="hlld", integrator="vl2", cfl=0.3,
-                ct_eps=0.0, kernel_path="fused", nscalars=0) -> Config:
+                ct_eps=0.0, kernel_path="fused", nscalars=0, charac=False) -> Config:
     return Config(int(n[0]), int(n[1]), int(n[2]), int(nghost), float(gamma), float(dx[0]), float(dx[1]),
                   float(dx[2]), RECON[recon], RIEMANN[riemann], INTEGRATOR[integrator],
-                  KERNEL_PATH[kernel_path], float(cfl), float(ct_eps), int(nscalars))
+                  KERNEL_PATH[kernel_path], float(cfl), float(ct_eps), int(nscalars), int(bool(charac)))
 
 
 def _check(rc: int, h) -> None:
@@ -116,12 +116,13 @@ class Solver:
     variables in cons, and C_i the 5 primitives in prim."""
 
     def __init__(self, n, nghost, dx, gamma, recon="plm", riemann="hlld", integrator="vl2", cfl=0.3,
-                 ct_eps=0.0, nblocks=1, kernel_path="fused", nscalars=0):
+                 ct_eps=0.0, nblocks=1, kernel_path="fused", nscalars=0, charac=False):
         self.n = tuple(int(x) for x in n)
         self.ng = int(nghost)
         self.nblocks = int(nblocks)
         self.nv = 5 + int(nscalars)
-        self.cfg = make_config(n, nghost, dx, gamma, recon, riemann, integrator, cfl, ct_eps, kernel_path, nscalars)
+        self.cfg = make_config(n, nghost, dx, gamma, recon, riemann, integrator, cfl, ct_eps, kernel_path, nscalars,
+                               charac)
         h = C.c_void_p()
         rc = lib().athmhd_create(C.byref(self.cfg), self.nblocks, C.byref(h))
         if rc != OK:

@@ -28,6 +28,9 @@ struct athmhd_s {
   // coupled mesh (athmhd_create_mesh): the nbmax blocks tile one periodic
   // domain as g.mesh[0] x g.mesh[1] x g.mesh[2]
   bool mesh = false;
+  // the unfused pipeline runs the stages (kernel_path 1, or characteristic
+  // reconstruction, which only that pipeline implements)
+  bool unfused = false;
   // batched handle: blocks of their own sizes, concatenated in the arrays
   bool batch = false;
   int nbatch = 0;
@@ -149,6 +152,7 @@ int validate_common(const athmhd_config* c) {
     return fail(nullptr, ATHMHD_EINVAL, "kernel_path must be 0 (fused) or 1 (unfused)");
   if (c->nscalars < 0 || c->nscalars > 64)
     return fail(nullptr, ATHMHD_EINVAL, "nscalars must be in [0, 64] (got %d)", c->nscalars);
+  if (c->charac != 0 && c->charac != 1) return fail(nullptr, ATHMHD_EINVAL, "charac must be 0 or 1");
   return ATHMHD_OK;
 }
 
@@ -281,12 +285,12 @@ hipError_t launch_stage(athmhd_t h, int recon, const double* xc, const double* x
     return launch_stage_batch(h->shape, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, h->d_desc, h->d_items,
                               h->nitems, h->d_queue, xc, xb, unc, unb, oc, ob, cf, dt_dev, beta, h->grid, h->floors,
                               h->d_bad, h->g.ns > 0 ? h->d_fm : nullptr, s);
-  if (h->cfg.kernel_path == 0)
+  if (!h->unfused)
     return launch_stage_fused(h->g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc, xb, unc, unb, oc, ob, cf,
                               dt_dev, beta, nblocks, stage_kz(h, nblocks), h->floors, h->d_bad,
                               h->g.ns > 0 ? h->d_fm : nullptr, s);
   return launch_stage_unfused(h->g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc, xb, unc, unb, oc, ob,
-                              cf, nblocks, h->scr, h->floors, h->d_bad, s);
+                              cf, nblocks, h->scr, h->floors, h->d_bad, h->cfg.charac != 0, s);
 }
 
 // depth: ghost layers a mesh exchange fills (0: all); other handles fill all
@@ -310,13 +314,13 @@ int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const doubl
   // the fused kernels read periodic images directly; the unfused pipeline
   // and the blocks of a coupled mesh read ghost entries, which are filled
   // (exchanged between the mesh's blocks) before each stage
-  const bool ghosts = (h->cfg.kernel_path == 1 && !h->batch) || h->mesh;
+  const bool ghosts = (h->unfused && !h->batch) || h->mesh;
   for (int st = 0; st < sc.nstage; ++st) {
     // the VL2 predictor always uses donor-cell fluxes (Sec. 3.2.3)
     const int recon = (h->cfg.integrator == ATHMHD_VL2 && st == 0) ? ATHMHD_RECON_DC : h->cfg.recon;
     // the fused stage reads recon + 1 cells past the block (the reconstruction
     // stencil of the ring faces); the unfused pipeline reads every ghost layer
-    const int depth = h->cfg.kernel_path == 0 ? recon + 1 : 0;
+    const int depth = h->unfused ? 0 : recon + 1;
     if (ghosts &&
         (e = fill_ghosts(h, const_cast<double*>(xc), const_cast<double*>(xb), nblocks, s, depth)) != hipSuccess)
       return hip_fail(h, e, "fill_ghosts launch");
@@ -451,7 +455,7 @@ int alloc_adjoint(athmhd_t h) {
 
 extern "C" {
 
-int athmhd_version(void) { return 104; }
+int athmhd_version(void) { return 105; }
 
 int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
   if (!out) return fail(nullptr, ATHMHD_EINVAL, "out is NULL");
@@ -461,13 +465,16 @@ int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
   rc = validate_block(cfg->n1, cfg->n2, cfg->n3, cfg->nghost, cfg->dx1, cfg->dx2, cfg->dx3);
   if (rc != ATHMHD_OK) return rc;
   if (nblocks_max < 1) return fail(nullptr, ATHMHD_EINVAL, "nblocks_max must be >= 1");
-  if (cfg->nscalars > 0 && cfg->kernel_path != 0)
+  if (cfg->nscalars > 0 && (cfg->kernel_path != 0 || cfg->charac))
     return fail(nullptr, ATHMHD_EUNSUP, "passive scalars run with the fused kernels only");
+  if (cfg->charac && cfg->recon == ATHMHD_RECON_PPM)
+    return fail(nullptr, ATHMHD_EUNSUP, "characteristic reconstruction is available for PLM (and DC) only");
   athmhd_t h = new (std::nothrow) athmhd_s();
   if (!h) return fail(nullptr, ATHMHD_ENOMEM, "host allocation failed");
   h->cfg = *cfg;
   h->g = make_geo(cfg->n1, cfg->n2, cfg->n3, cfg->nghost, cfg->dx1, cfg->dx2, cfg->dx3, cfg->nscalars);
   h->nbmax = nblocks_max;
+  h->unfused = cfg->kernel_path == 1 || cfg->charac;
   read_env(h);
   hipError_t e = hipGetDevice(&h->device);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, h->device);
@@ -479,7 +486,7 @@ int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
   h->reg_coff = h->g.cblock * (int64_t)nblocks_max;
   const int64_t state = (h->g.cblock + h->g.fblock) * (int64_t)nblocks_max;
   const int64_t nscr =
-      cfg->kernel_path == 1 ? (8 * h->g.cvar + 24 * h->g.fvar + 3 * h->g.fvar) * (int64_t)nblocks_max : 1;
+      h->unfused ? (8 * h->g.cvar + 24 * h->g.fvar + 3 * h->g.fvar) * (int64_t)nblocks_max : 1;
   const int64_t nfm = h->g.ns > 0 ? 3 * h->g.fvar * (int64_t)nblocks_max : 0;
   bool ok = hipMalloc(&h->reg[0], state * sizeof(double)) == hipSuccess &&
             hipMalloc(&h->reg[1], state * sizeof(double)) == hipSuccess &&
@@ -518,7 +525,8 @@ int athmhd_create_mesh(const athmhd_config* cfg, int nbx, int nby, int nbz, athm
     return fail(nullptr, ATHMHD_EINVAL, "blocks per direction must be >= 1 (got %d %d %d)", nbx, nby, nbz);
   const double nb = (double)nbx * nby * nbz;
   if (nb > 1048576.0) return fail(nullptr, ATHMHD_EINVAL, "more than 2^20 blocks");
-  if (cfg && cfg->kernel_path != 0) return fail(nullptr, ATHMHD_EUNSUP, "a coupled mesh runs the fused kernels only");
+  if (cfg && (cfg->kernel_path != 0 || cfg->charac))
+    return fail(nullptr, ATHMHD_EUNSUP, "a coupled mesh runs the fused kernels only");
   int rc = athmhd_create(cfg, (int)nb, out);
   if (rc != ATHMHD_OK) return rc;
   athmhd_t h = *out;
@@ -535,7 +543,8 @@ int athmhd_create_batch(const athmhd_config* base, const int32_t* dims, const do
   *out = nullptr;
   int rc = validate_common(base);
   if (rc != ATHMHD_OK) return rc;
-  if (base->kernel_path != 0) return fail(nullptr, ATHMHD_EUNSUP, "batched blocks run on the fused kernel only");
+  if (base->kernel_path != 0 || base->charac)
+    return fail(nullptr, ATHMHD_EUNSUP, "batched blocks run on the fused kernel only");
   if (!dims || !dx) return fail(nullptr, ATHMHD_EINVAL, "NULL dims or dx");
   if (nblocks < 1 || nblocks > 65535) return fail(nullptr, ATHMHD_EINVAL, "nblocks must be in [1, 65535]");
   for (int b = 0; b < nblocks; ++b) {
@@ -791,6 +800,7 @@ int athmhd_step_vjp(athmhd_t h, const double* cons_n, const double* bface_n, dou
   if (h->batch || h->mesh) return fail(h, ATHMHD_EUNSUP, "reverse mode is available for uniform handles only");
   if (h->floors.on()) return fail(h, ATHMHD_EUNSUP, "reverse mode is not available with floors");
   if (h->g.ns > 0) return fail(h, ATHMHD_EUNSUP, "reverse mode is not available with passive scalars");
+  if (h->cfg.charac) return fail(h, ATHMHD_EUNSUP, "reverse mode is not available with characteristic reconstruction");
   if (!g_cons_np1 || !g_bface_np1 || !g_cons_n || !g_bface_n) return fail(h, ATHMHD_EINVAL, "NULL cotangent array");
   if (g_cons_n == cons_n || g_bface_n == bface_n || g_cons_n == (const double*)bface_n ||
       g_bface_n == (const double*)cons_n)

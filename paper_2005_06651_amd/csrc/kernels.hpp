@@ -34,7 +34,7 @@ hipError_t launch_newdt(const Geo& g, double gamma, const double* cons, const do
 hipError_t launch_stage_unfused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
                                 const double* xb, const double* unc, const double* unb, double* outc,
                                 double* outb, StageCoef coef, int nb, UnfusedScratch& scr, const Floors& fl,
-                                int* bad, hipStream_t s);
+                                int* bad, bool charac, hipStream_t s);  // charac: PLM on characteristic variables
 
 // One stage in a single fused kernel (same contract as launch_stage_unfused);
 // kz = x3 planes per workgroup segment (0: default for the block size).

@@ -68,9 +68,131 @@ __device__ __forceinline__ void recon_pair(const double* __restrict__ q, int s, 
   }
 }
 
+// ---- characteristic reconstruction (Sec. 3.2.1: C = L W) -------------------
+// Face frame, primitives w = (rho, vn, vt1, vt2, P, Bt1, Bt2), normal field bn.
+// Columns of R are the right eigenvectors of W_t + A W_x = 0 for the waves
+// vn - cf, vn - ca, vn - cs, vn, vn + cs, vn + ca, vn + cf, normalised after
+// Roe & Balsara (1996) (alpha_f, alpha_s from the fast and slow speeds, beta
+// along the transverse field, 1/sqrt2 each where it vanishes, alpha_f = 1 and
+// alpha_s = 0 where cf = cs), so they stay independent where speeds coincide.
+__device__ void char_right(const double* w, double bn, double gamma, double R[7][7]) {
+  const double rho = w[0], p = w[4], t1 = w[5], t2 = w[6];
+  const double a2 = gamma * p / rho, ca2 = bn * bn / rho, bt2 = t1 * t1 + t2 * t2;
+  const double sum = a2 + ca2 + bt2 / rho;
+  const double disc = fmax(sum * sum - 4.0 * a2 * ca2, 0.0);
+  const double cf2 = 0.5 * (sum + sqrt(disc));
+  const double cs2 = cf2 > 0.0 ? a2 * ca2 / cf2 : 0.0;
+  double af = 1.0, as = 0.0;
+  if (cf2 - cs2 > 0.0) {
+    af = sqrt(fmin(1.0, fmax(0.0, (a2 - cs2) / (cf2 - cs2))));
+    as = sqrt(fmin(1.0, fmax(0.0, (cf2 - a2) / (cf2 - cs2))));
+  }
+  double e1 = 0.70710678118654752440, e2 = 0.70710678118654752440;
+  if (bt2 > 0.0) {
+    const double bt = sqrt(bt2);
+    e1 = t1 / bt;
+    e2 = t2 / bt;
+  }
+  const double sg = bn >= 0.0 ? 1.0 : -1.0;
+  const double a = sqrt(a2), cf = sqrt(cf2), cs = sqrt(cs2), sr = sqrt(rho), gp = gamma * p;
+#pragma unroll
+  for (int r = 0; r < 7; ++r)
+#pragma unroll
+    for (int c = 0; c < 7; ++c) R[r][c] = 0.0;
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const double m = side == 0 ? -1.0 : 1.0;  // left- or right-going
+    const int f = side == 0 ? 0 : 6, al = side == 0 ? 1 : 5, sl = side == 0 ? 2 : 4;
+    R[0][f] = rho * af;  // fast
+    R[1][f] = m * cf * af;
+    R[2][f] = -m * as * cs * e1 * sg;
+    R[3][f] = -m * as * cs * e2 * sg;
+    R[4][f] = gp * af;
+    R[5][f] = as * sr * a * e1;
+    R[6][f] = as * sr * a * e2;
+    R[2][al] = m * e2;  // Alfven
+    R[3][al] = -m * e1;
+    R[5][al] = -e2 * sg * sr;
+    R[6][al] = e1 * sg * sr;
+    R[0][sl] = rho * as;  // slow
+    R[1][sl] = m * cs * as;
+    R[2][sl] = m * af * cf * e1 * sg;
+    R[3][sl] = m * af * cf * e2 * sg;
+    R[4][sl] = gp * as;
+    R[5][sl] = -af * sr * a * e1;
+    R[6][sl] = -af * sr * a * e2;
+  }
+  R[0][3] = 1.0;  // entropy
+}
+
+// L = R^{-1} by Gauss-Jordan elimination with partial pivoting.
+__device__ void char_left(const double R[7][7], double L[7][7]) {
+  double M[7][7];
+#pragma unroll
+  for (int r = 0; r < 7; ++r)
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+      M[r][c] = R[r][c];
+      L[r][c] = r == c ? 1.0 : 0.0;
+    }
+  for (int c = 0; c < 7; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 7; ++r)
+      if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
+    if (piv != c)
+      for (int k = 0; k < 7; ++k) {
+        double t = M[c][k];
+        M[c][k] = M[piv][k];
+        M[piv][k] = t;
+        t = L[c][k];
+        L[c][k] = L[piv][k];
+        L[piv][k] = t;
+      }
+    const double inv = 1.0 / M[c][c];
+    for (int k = 0; k < 7; ++k) {
+      M[c][k] *= inv;
+      L[c][k] *= inv;
+    }
+    for (int r = 0; r < 7; ++r) {
+      if (r == c) continue;
+      const double f = M[r][c];
+      for (int k = 0; k < 7; ++k) {
+        M[r][k] -= f * M[c][k];
+        L[r][k] -= f * L[c][k];
+      }
+    }
+  }
+}
+
+// PLM edges of cell w0 on characteristic variables: the one-sided differences
+// projected with L, van Leer-limited per wave family, projected back with R.
+__device__ void char_plm(const double* wm, const double* w0, const double* wp, double bn, double gamma,
+                         double* left, double* right) {
+  double R[7][7], L[7][7];
+  char_right(w0, bn, gamma, R);
+  char_left(R, L);
+  double dc[7];
+  for (int k = 0; k < 7; ++k) {
+    double dl = 0.0, dr = 0.0;
+    for (int j = 0; j < 7; ++j) {
+      dl += L[k][j] * (w0[j] - wm[j]);
+      dr += L[k][j] * (wp[j] - w0[j]);
+    }
+    const double pr = dl * dr;
+    dc[k] = pr > 0.0 ? 2.0 * pr / (dl + dr) : 0.0;
+  }
+  for (int j = 0; j < 7; ++j) {
+    double dw = 0.0;
+    for (int k = 0; k < 7; ++k) dw += R[j][k] * dc[k];
+    left[j] = w0[j] - 0.5 * dw;
+    right[j] = w0[j] + 0.5 * dw;
+  }
+}
+
 // Fluxes through the faces normal to D: normal index [ng, ng+n_D], transverse
-// indices [ng-1, ng+n_t] (one extra ring for the corner EMFs).
-template <int D, int RECON, int RS>
+// indices [ng-1, ng+n_t] (one extra ring for the corner EMFs).  CHAR: PLM on
+// characteristic variables (RECON == 1 only).
+template <int D, int RECON, int RS, bool CHAR>
 __global__ void __launch_bounds__(kThreads) k_flux(Geo g, Gas gas, double ct_eps, Floors fl,
                                                   const double* __restrict__ w, const double* __restrict__ bface,
                                                   double* __restrict__ fo, int* __restrict__ bad) {
@@ -90,13 +212,29 @@ __global__ void __launch_bounds__(kThreads) k_flux(Geo g, Gas gas, double ct_eps
   const int s = D == 0 ? 1 : (D == 1 ? g.N1 : g.N1 * g.N2);
   const int q = g.c(i, j, k);
   FaceState L, R;
-  recon_pair<RECON>(wb + q, s, L.rho, R.rho);
-  recon_pair<RECON>(wb + (1 + D) * g.cvar + q, s, L.vn, R.vn);
-  recon_pair<RECON>(wb + (1 + T1) * g.cvar + q, s, L.vt1, R.vt1);
-  recon_pair<RECON>(wb + (1 + T2) * g.cvar + q, s, L.vt2, R.vt2);
-  recon_pair<RECON>(wb + 4 * g.cvar + q, s, L.p, R.p);
-  recon_pair<RECON>(wb + (5 + T1) * g.cvar + q, s, L.bt1, R.bt1);
-  recon_pair<RECON>(wb + (5 + T2) * g.cvar + q, s, L.bt2, R.bt2);
+  if (CHAR && RECON == 1) {
+    // cells c-2 .. c+1 in the face frame; right edge of c-1, left edge of c
+    const int vi[7] = {0, 1 + D, 1 + T1, 1 + T2, 4, 5 + T1, 5 + T2};
+    double w[4][7];
+#pragma unroll
+    for (int o = 0; o < 4; ++o)
+#pragma unroll
+      for (int n = 0; n < 7; ++n) w[o][n] = wb[vi[n] * g.cvar + q + (o - 2) * s];
+    const double bnm = wb[(5 + D) * g.cvar + q - s], bn0 = wb[(5 + D) * g.cvar + q];
+    double lm[7], rm[7], l0[7], r0[7];
+    char_plm(w[0], w[1], w[2], bnm, gas.gamma, lm, rm);
+    char_plm(w[1], w[2], w[3], bn0, gas.gamma, l0, r0);
+    L = FaceState{rm[0], rm[1], rm[2], rm[3], rm[4], rm[5], rm[6]};
+    R = FaceState{l0[0], l0[1], l0[2], l0[3], l0[4], l0[5], l0[6]};
+  } else {
+    recon_pair<RECON>(wb + q, s, L.rho, R.rho);
+    recon_pair<RECON>(wb + (1 + D) * g.cvar + q, s, L.vn, R.vn);
+    recon_pair<RECON>(wb + (1 + T1) * g.cvar + q, s, L.vt1, R.vt1);
+    recon_pair<RECON>(wb + (1 + T2) * g.cvar + q, s, L.vt2, R.vt2);
+    recon_pair<RECON>(wb + 4 * g.cvar + q, s, L.p, R.p);
+    recon_pair<RECON>(wb + (5 + T1) * g.cvar + q, s, L.bt1, R.bt1);
+    recon_pair<RECON>(wb + (5 + T2) * g.cvar + q, s, L.bt2, R.bt2);
+  }
   const int fi = g.f(i, j, k);
   const double bn = fb[D * g.fvar + fi];
   if (fl.on()) {
@@ -205,26 +343,27 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, StageCoef cf, const 
   ob[2 * g.fvar + fc] = cf.g0 * xbb[2 * g.fvar + fc] + cf.g1 * unbb[2 * g.fvar + fc] - cf.bdt * c3;
 }
 
-template <int D, int RECON>
+template <int D, int RECON, bool CHAR>
 hipError_t flux_rs(const Geo& g, const Gas& gas, int rs, double ct_eps, const Floors& fl, const double* w,
                    const double* xb, double* fo, int* bad, int nb, hipStream_t s) {
   const int64_t n = (int64_t)(D == 0 ? g.n1 + 1 : g.n1 + 2) * (D == 1 ? g.n2 + 1 : g.n2 + 2) *
                     (D == 2 ? g.n3 + 1 : g.n3 + 2);
   if (rs == 1)
-    hipLaunchKernelGGL((k_flux<D, RECON, 1>), dim3(grid_for(n), nb), dim3(kThreads), 0, s, g, gas, ct_eps, fl, w, xb,
-                       fo, bad);
+    hipLaunchKernelGGL((k_flux<D, RECON, 1, CHAR>), dim3(grid_for(n), nb), dim3(kThreads), 0, s, g, gas, ct_eps, fl,
+                       w, xb, fo, bad);
   else
-    hipLaunchKernelGGL((k_flux<D, RECON, 0>), dim3(grid_for(n), nb), dim3(kThreads), 0, s, g, gas, ct_eps, fl, w, xb,
-                       fo, bad);
+    hipLaunchKernelGGL((k_flux<D, RECON, 0, CHAR>), dim3(grid_for(n), nb), dim3(kThreads), 0, s, g, gas, ct_eps, fl,
+                       w, xb, fo, bad);
   return hipGetLastError();
 }
 
 template <int D>
-hipError_t flux_dir(const Geo& g, const Gas& gas, int recon, int rs, double ct_eps, const Floors& fl, const double* w,
-                    const double* xb, double* fo, int* bad, int nb, hipStream_t s) {
-  if (recon == 0) return flux_rs<D, 0>(g, gas, rs, ct_eps, fl, w, xb, fo, bad, nb, s);
-  if (recon == 1) return flux_rs<D, 1>(g, gas, rs, ct_eps, fl, w, xb, fo, bad, nb, s);
-  return flux_rs<D, 2>(g, gas, rs, ct_eps, fl, w, xb, fo, bad, nb, s);
+hipError_t flux_dir(const Geo& g, const Gas& gas, int recon, bool charac, int rs, double ct_eps, const Floors& fl,
+                    const double* w, const double* xb, double* fo, int* bad, int nb, hipStream_t s) {
+  if (recon == 0) return flux_rs<D, 0, false>(g, gas, rs, ct_eps, fl, w, xb, fo, bad, nb, s);
+  if (recon == 1 && charac) return flux_rs<D, 1, true>(g, gas, rs, ct_eps, fl, w, xb, fo, bad, nb, s);
+  if (recon == 1) return flux_rs<D, 1, false>(g, gas, rs, ct_eps, fl, w, xb, fo, bad, nb, s);
+  return flux_rs<D, 2, false>(g, gas, rs, ct_eps, fl, w, xb, fo, bad, nb, s);
 }
 
 }  // namespace
@@ -232,14 +371,17 @@ hipError_t flux_dir(const Geo& g, const Gas& gas, int recon, int rs, double ct_e
 hipError_t launch_stage_unfused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
                                 const double* xb, const double* unc, const double* unb, double* outc,
                                 double* outb, StageCoef coef, int nb, UnfusedScratch& scr, const Floors& fl,
-                                int* bad, hipStream_t s) {
+                                int* bad, bool charac, hipStream_t s) {
   Gas gas{gamma, gamma - 1.0, 1.0 / (gamma - 1.0)};
   hipLaunchKernelGGL(k_prim, dim3(grid_for(g.cvar), nb), dim3(kThreads), 0, s, g, gamma, fl, xc, xb, scr.w, bad);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if ((e = flux_dir<0>(g, gas, recon, rs, ct_eps, fl, scr.w, xb, scr.face[0], bad, nb, s)) != hipSuccess) return e;
-  if ((e = flux_dir<1>(g, gas, recon, rs, ct_eps, fl, scr.w, xb, scr.face[1], bad, nb, s)) != hipSuccess) return e;
-  if ((e = flux_dir<2>(g, gas, recon, rs, ct_eps, fl, scr.w, xb, scr.face[2], bad, nb, s)) != hipSuccess) return e;
+  for (int d = 0; d < 3; ++d) {
+    e = d == 0   ? flux_dir<0>(g, gas, recon, charac, rs, ct_eps, fl, scr.w, xb, scr.face[0], bad, nb, s)
+        : d == 1 ? flux_dir<1>(g, gas, recon, charac, rs, ct_eps, fl, scr.w, xb, scr.face[1], bad, nb, s)
+                 : flux_dir<2>(g, gas, recon, charac, rs, ct_eps, fl, scr.w, xb, scr.face[2], bad, nb, s);
+    if (e != hipSuccess) return e;
+  }
   const int64_t ne = (int64_t)(g.n1 + 1) * (g.n2 + 1) * (g.n3 + 1);
   hipLaunchKernelGGL(k_corner, dim3(grid_for(ne), nb), dim3(kThreads), 0, s, g, scr.w, scr.face[0], scr.face[1],
                      scr.face[2], scr.edge);

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version():
-    assert athmhd.lib().athmhd_version() == 104
+    assert athmhd.lib().athmhd_version() == 105
 
 
 def _create(**over):
@@ -78,6 +78,17 @@ def test_scalars_need_the_fused_kernels():
     assert "scalars" in msg
 
 
+@pytest.mark.parametrize("over,code,needle", [
+    (dict(charac=2), athmhd.EINVAL, "charac"),
+    (dict(charac=1, recon=2, nghost=3), athmhd.EUNSUP, "PLM"),
+    (dict(charac=1, nscalars=1), athmhd.EUNSUP, "scalars"),
+])
+def test_characteristic_reconstruction_arguments(over, code, needle):
+    rc, msg = _create(**over)
+    assert rc == code
+    assert needle in msg
+
+
 def test_calls_reject_null_handle():
     L = athmhd.lib()
     out = C.c_double()
@@ -116,6 +127,7 @@ def _create_batch(dims, dxs, **over):
     ([(16, 16, 16)], [(0.1,) * 3], {"kernel_path": 1}, athmhd.EUNSUP, "fused"),
     ([(16, 16, 16)], [(0.1,) * 3], {"nghost": 1}, athmhd.EINVAL, "nghost"),
     ([(16, 16, 16)], [(0.1,) * 3], {"nscalars": 65}, athmhd.EINVAL, "nscalars"),
+    ([(16, 16, 16)], [(0.1,) * 3], {"charac": 1}, athmhd.EUNSUP, "fused"),
 ])
 def test_create_batch_rejects_bad_blocks(dims, dxs, over, code, needle):
     rc, msg = _create_batch(dims, dxs, **over)
@@ -129,6 +141,7 @@ def test_create_batch_rejects_bad_blocks(dims, dxs, over, code, needle):
     ((2, 2, 2), {"nghost": 1}, athmhd.EINVAL, "nghost"),
     ((2, 2, 2), {"n1": 0}, athmhd.EINVAL, "block dims"),
     ((2, 2, 2), {"nscalars": -1}, athmhd.EINVAL, "nscalars"),
+    ((2, 2, 2), {"charac": 1}, athmhd.EUNSUP, "fused"),
 ])
 def test_create_mesh_rejects_bad_arguments_before_any_hip_call(blocks, over, code, needle):
     cfg = athmhd.make_config((8, 8, 8), 2, (0.1, 0.1, 0.1), 5.0 / 3.0)

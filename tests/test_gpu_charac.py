@@ -1,0 +1,128 @@
+"""Characteristic reconstruction on the GPU (Sec. 3.2.1, C = L W; PLM):
+the unfused pipeline's flux kernels project onto the characteristic
+variables of each cell, limit per wave family and project back.  Checked
+against the oracle at the 1e-12 bar on ragged blocks and on Brio & Wu's
+shock tube, with donor cell unchanged and reverse mode refused.
+"""
+import numpy as np
+import pytest
+
+import windows as W
+from paper_2005_06651_amd import inputs
+from test_oracle_charac import _brio_wu
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def athmhd():
+    from paper_2005_06651_amd import athmhd as A
+    A.lib()
+    return A
+
+
+def to_dev(torch, dev, x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def rel_l1_all(gc, gb, rc, rb, ng, n):
+    a = (slice(None), slice(ng, ng + n[2]), slice(ng, ng + n[1]), slice(ng, ng + n[0]))
+    errs = []
+    for x, y in ((gc[a], rc[a]), (gb[a], rb[a])):
+        for v in range(x.shape[0]):
+            errs.append(float(np.abs(x[v] - y[v]).sum() / max(np.abs(y[v]).sum(), 1e-300)))
+    return errs
+
+
+@pytest.mark.parametrize("integ,rs,floors", [("vl2", "hlld", None), ("rk2", "hlle", None), ("rk3", "hlld", (0.8, 0.9)),
+                                             ("rk1", "hlld", None)])
+def test_characteristic_steps_match_oracle(torch_dev, athmhd, orc, integ, rs, floors):
+    """Three steps of a ragged 37 x 19 x 11 block of smooth random data."""
+    torch, dev = torch_dev
+    b = inputs.smooth_random(n=(37, 19, 11), seed=81)
+    kw = dict(integrator=integ, recon="plm", riemann=rs)
+    s = athmhd.Solver(b.n, b.ng, b.dx, b.gamma, charac=True, **kw)
+    fl = floors or (0.0, 0.0)
+    if floors:
+        s.set_floors(*floors)
+    cfg = orc.cfg_for(b, charac=True, dfloor=fl[0], pfloor=fl[1], **kw)
+    cons = orc.prim2cons(orc.cfg_for(b, **kw), b.prim, b.bface)
+    tc, tb = to_dev(torch, dev, cons), to_dev(torch, dev, b.bface)
+    rc, rb = cons.copy(), b.bface.copy()
+    for _ in range(3):
+        dt, bad = orc.newdt(cfg, rc, rb)
+        assert bad == 0
+        assert abs(s.newdt(tc, tb) - dt) <= 1e-13 * dt
+        assert orc.step(cfg, rc, rb, dt) == 0
+        s.step(tc, tb, dt)
+    errs = rel_l1_all(tc.cpu().numpy(), tb.cpu().numpy(), rc, rb, b.ng, b.n)
+    print("rel L1 per array", " ".join(f"{e:.1e}" for e in errs), flush=True)
+    assert max(errs) <= TOL
+    s.close()
+
+
+def test_characteristic_brio_wu_matches_oracle(torch_dev, athmhd, orc):
+    """Brio & Wu's tube (gamma 2) on 128 x 4 x 4 cells, VL2 + characteristic
+    PLM + HLLD, 40 steps of dt 2.5e-4 (discontinuities in every wave family).
+    v3 and B3 stay zero up to rounding, so momenta are measured against rho
+    times a unit speed and face fields against the mean of the three."""
+    torch, dev = torch_dev
+    n, g = 128, 2
+    dims, prim, bf = _brio_wu(n)
+    dx = (1.0 / n, 0.25, 0.25)
+    kw = dict(integrator="vl2", recon="plm", riemann="hlld")
+    cfg = orc.make_cfg(dims, g, dx, 2.0, charac=True, **kw)
+    cons = orc.prim2cons(cfg, prim, bf)
+    s = athmhd.Solver(dims, g, dx, 2.0, charac=True, **kw)
+    tc, tb = to_dev(torch, dev, cons), to_dev(torch, dev, bf)
+    rc, rb = cons.copy(), bf.copy()
+    for _ in range(40):
+        assert orc.step(cfg, rc, rb, 2.5e-4) == 0
+        s.step(tc, tb, 2.5e-4)
+    a = (slice(None), slice(g, g + dims[2]), slice(g, g + dims[1]), slice(g, g + dims[0]))
+    gc, gb = tc.cpu().numpy()[a], tb.cpu().numpy()[a]
+    errs = W.rel_l1_arrays(gc, gb, rc[a], rb[a], mom_speed=1.0)
+    print("rel L1 per array", " ".join(f"{e:.1e}" for e in errs), "max abs",
+          max(np.abs(gc - rc[a]).max(), np.abs(gb - rb[a]).max()), flush=True)
+    assert max(errs) <= TOL
+    s.close()
+
+
+def test_characteristic_donor_cell_is_unchanged(torch_dev, athmhd, orc):
+    """RK2 + DC: the characteristic handle gives the unfused primitive path's
+    result bitwise (the projection only applies to PLM)."""
+    torch, dev = torch_dev
+    b = inputs.smooth_random(n=(20, 12, 10), seed=82)
+    kw = dict(integrator="rk2", recon="dc", riemann="hlld")
+    s1 = athmhd.Solver(b.n, b.ng, b.dx, b.gamma, charac=True, **kw)
+    s0 = athmhd.Solver(b.n, b.ng, b.dx, b.gamma, kernel_path="unfused", **kw)
+    tb = to_dev(torch, dev, b.bface)
+    tc = s0.prim2cons(to_dev(torch, dev, b.prim), tb)
+    c0, b0, c1, b1 = tc.clone(), tb.clone(), tc.clone(), tb.clone()
+    for _ in range(2):
+        s0.step(c0, b0, 0.004)
+        s1.step(c1, b1, 0.004)
+    assert torch.equal(c0, c1) and torch.equal(b0, b1)
+    s0.close()
+    s1.close()
+
+
+def test_characteristic_rejects_reverse_mode(torch_dev, athmhd):
+    torch, dev = torch_dev
+    b = inputs.smooth_random(n=(8, 8, 8), seed=83)
+    s = athmhd.Solver(b.n, b.ng, b.dx, b.gamma, charac=True)
+    tb = to_dev(torch, dev, b.bface)
+    tc = s.prim2cons(to_dev(torch, dev, b.prim), tb)
+    with pytest.raises(athmhd.AthmhdError) as e:
+        s.step_vjp(tc, tb, 1e-3, tc.clone(), tb.clone())
+    assert e.value.code == athmhd.EUNSUP
+    s.close()
