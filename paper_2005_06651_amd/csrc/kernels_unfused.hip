@@ -125,64 +125,71 @@ __device__ void char_right(const double* w, double bn, double gamma, double R[7]
   R[0][3] = 1.0;  // entropy
 }
 
-// L = R^{-1} by Gauss-Jordan elimination with partial pivoting.
-__device__ void char_left(const double R[7][7], double L[7][7]) {
-  double M[7][7];
-#pragma unroll
-  for (int r = 0; r < 7; ++r)
-#pragma unroll
-    for (int c = 0; c < 7; ++c) {
-      M[r][c] = R[r][c];
-      L[r][c] = r == c ? 1.0 : 0.0;
-    }
-  for (int c = 0; c < 7; ++c) {
-    int piv = c;
-    for (int r = c + 1; r < 7; ++r)
-      if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
-    if (piv != c)
-      for (int k = 0; k < 7; ++k) {
-        double t = M[c][k];
-        M[c][k] = M[piv][k];
-        M[piv][k] = t;
-        t = L[c][k];
-        L[c][k] = L[piv][k];
-        L[piv][k] = t;
-      }
-    const double inv = 1.0 / M[c][c];
-    for (int k = 0; k < 7; ++k) {
-      M[c][k] *= inv;
-      L[c][k] *= inv;
-    }
-    for (int r = 0; r < 7; ++r) {
-      if (r == c) continue;
-      const double f = M[r][c];
-      for (int k = 0; k < 7; ++k) {
-        M[r][k] -= f * M[c][k];
-        L[r][k] -= f * L[c][k];
-      }
-    }
-  }
-}
-
 // PLM edges of cell w0 on characteristic variables: the one-sided differences
-// projected with L, van Leer-limited per wave family, projected back with R.
+// are projected with L = R^{-1} (solving R x = dW by Gaussian elimination with
+// partial pivoting, both differences at once; rows are exchanged by selects
+// so that every index is a compile-time constant and the system stays in
+// registers), van Leer-limited per wave family, and projected back with R.
 __device__ void char_plm(const double* wm, const double* w0, const double* wp, double bn, double gamma,
                          double* left, double* right) {
-  double R[7][7], L[7][7];
-  char_right(w0, bn, gamma, R);
-  char_left(R, L);
-  double dc[7];
-  for (int k = 0; k < 7; ++k) {
-    double dl = 0.0, dr = 0.0;
-    for (int j = 0; j < 7; ++j) {
-      dl += L[k][j] * (w0[j] - wm[j]);
-      dr += L[k][j] * (wp[j] - w0[j]);
+  double M[7][9];
+  {
+    double R[7][7];
+    char_right(w0, bn, gamma, R);
+#pragma unroll
+    for (int r = 0; r < 7; ++r) {
+#pragma unroll
+      for (int c = 0; c < 7; ++c) M[r][c] = R[r][c];
+      M[r][7] = w0[r] - wm[r];
+      M[r][8] = wp[r] - w0[r];
     }
-    const double pr = dl * dr;
-    dc[k] = pr > 0.0 ? 2.0 * pr / (dl + dr) : 0.0;
   }
+#pragma unroll
+  for (int c = 0; c < 7; ++c) {
+    // the largest entry of column c (rows c..6) to row c
+#pragma unroll
+    for (int r = c + 1; r < 7; ++r) {
+      const bool sw = fabs(M[r][c]) > fabs(M[c][c]);
+#pragma unroll
+      for (int k = c; k < 9; ++k) {
+        const double a = M[c][k], b = M[r][k];
+        M[c][k] = sw ? b : a;
+        M[r][k] = sw ? a : b;
+      }
+    }
+    const double inv = 1.0 / M[c][c];
+#pragma unroll
+    for (int r = c + 1; r < 7; ++r) {
+      const double f = M[r][c] * inv;
+#pragma unroll
+      for (int k = c + 1; k < 9; ++k) M[r][k] -= f * M[c][k];
+    }
+  }
+  double dl[7], dr[7];
+#pragma unroll
+  for (int c = 6; c >= 0; --c) {
+    double sl = M[c][7], sr = M[c][8];
+#pragma unroll
+    for (int k = c + 1; k < 7; ++k) {
+      sl -= M[c][k] * dl[k];
+      sr -= M[c][k] * dr[k];
+    }
+    const double inv = 1.0 / M[c][c];
+    dl[c] = sl * inv;
+    dr[c] = sr * inv;
+  }
+  double dc[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    const double pr = dl[k] * dr[k];
+    dc[k] = pr > 0.0 ? 2.0 * pr / (dl[k] + dr[k]) : 0.0;
+  }
+  double R[7][7];
+  char_right(w0, bn, gamma, R);
+#pragma unroll
   for (int j = 0; j < 7; ++j) {
     double dw = 0.0;
+#pragma unroll
     for (int k = 0; k < 7; ++k) dw += R[j][k] * dc[k];
     left[j] = w0[j] - 0.5 * dw;
     right[j] = w0[j] + 0.5 * dw;
