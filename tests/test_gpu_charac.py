@@ -126,3 +126,36 @@ def test_characteristic_rejects_reverse_mode(torch_dev, athmhd):
         s.step_vjp(tc, tb, 1e-3, tc.clone(), tb.clone())
     assert e.value.code == athmhd.EUNSUP
     s.close()
+
+
+def test_characteristic_turbulence_256_sampled_windows(torch_dev, athmhd, orc):
+    """The 256^3 turbulence with characteristic PLM (the --charac benchmark's
+    state and scheme, VL2 + HLLD): one step on 5 windows of 16^3 inner cells
+    against the oracle at the 1e-12 bar."""
+    torch, dev = torch_dev
+    n = 256
+    b = inputs.turbulence(n=n, seed=1)
+    kw = dict(integrator="vl2", recon="plm", riemann="hlld", cfl=0.3)
+    s = athmhd.Solver(b.n, b.ng, b.dx, b.gamma, charac=True, **kw)
+    tb = to_dev(torch, dev, b.bface)
+    tc = s.prim2cons(to_dev(torch, dev, b.prim), tb)
+    c0, b0 = tc.cpu().numpy(), tb.cpu().numpy()
+    dt = s.newdt(tc, tb)
+    s.step(tc, tb, dt)
+    c1, b1 = tc.cpu().numpy(), tb.cpu().numpy()
+    margin = 6
+    m = 16 + 2 * margin
+    rng = np.random.default_rng(84)
+    origins = [tuple(int(x) for x in rng.integers(0, n, 3)) for _ in range(4)] + [(n - 9, n - 4, n - 11)]
+    worst = 0.0
+    for origin in origins:
+        wc, wb = W.extract(c0, b0, b.ng, b.n, origin, m)
+        wcfg = orc.make_cfg((m, m, m), b.ng, b.dx, b.gamma, charac=True, **kw)
+        assert orc.step(wcfg, wc, wb, dt) == 0
+        ref = W.inner_of_window(wc, wb, b.ng, m, margin)
+        got = W.inner(c1, b1, b.ng, b.n, origin, m, margin)
+        errs = W.rel_l1_arrays(got[0], got[1], ref[0], ref[1])
+        print("window", origin, " ".join(f"{e:.1e}" for e in errs), flush=True)
+        worst = max(worst, max(errs))
+    assert worst <= TOL
+    s.close()
