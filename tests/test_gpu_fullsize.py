@@ -212,3 +212,37 @@ def test_rollout_128_gradient_at_full_size(torch_dev, athmhd, orc):
         print("direction", q, "<grad, d>", ad, "best FD rel err", best, flush=True)
         assert best <= 1e-6, (best, ad)
     s.close()
+
+
+def test_batch_1024_with_a_scalar_sampled_blocks(torch_dev, athmhd, orc):
+    """The batched workload with one passive scalar (Sec. 3.2.6; the
+    benchmark's --workload batch --scalars 1 state): one step of 24 sampled
+    blocks of all three sizes against the oracle, every array within the bar."""
+    torch, dev = torch_dev
+    blocks = [inputs.with_scalars(b, 1, seed=101 + i) for i, b in enumerate(inputs.amr_batch(1024, seed=1))]
+    kw = dict(integrator="vl2", recon="plm", riemann="hlld", cfl=0.3)
+    s = athmhd.BatchSolver([x.n for x in blocks], [x.dx for x in blocks], 2, blocks[0].gamma, nscalars=1, **kw)
+    tb = torch.from_numpy(inputs.pack([x.bface for x in blocks])).to(dev)
+    tc = s.prim2cons(torch.from_numpy(inputs.pack([x.prim for x in blocks])).to(dev), tb)
+    s.tune(tc, tb)
+    rng = np.random.default_rng(45)
+    sample = sorted(set(rng.choice(len(blocks), 24, replace=False).tolist()))
+    assert len({blocks[i].n[0] for i in sample}) == 3
+    c0 = [s.views(tc, "cons")[i].cpu().numpy().copy() for i in sample]
+    f0 = [s.views(tb, "bface")[i].cpu().numpy().copy() for i in sample]
+    dt = s.newdt(tc, tb)
+    s.step(tc, tb, dt)
+    c1 = s.views(tc, "cons")
+    f1 = s.views(tb, "bface")
+    worst = 0.0
+    for n_, i in enumerate(sample):
+        cfg = orc.cfg_for(blocks[i], nscalars=1, **kw)
+        x, y = c0[n_].copy(), f0[n_].copy()
+        assert orc.step(cfg, x, y, dt) == 0
+        g, (n1, n2, n3) = blocks[i].ng, blocks[i].n
+        a = (slice(None), slice(g, g + n3), slice(g, g + n2), slice(g, g + n1))
+        err = W.max_rel_l1(c1[i].cpu().numpy()[a], f1[i].cpu().numpy()[a], x[a], y[a])
+        worst = max(worst, err)
+    print("worst block rel L1", worst, flush=True)
+    assert worst <= TOL
+    s.close()
