@@ -43,14 +43,14 @@
 //     left state where the mass flux is >= 0, else the right state); with
 //     floors, C_i = (rho C_i) / rho_W with the floored density, and the floor
 //     pass after a stage leaves rho C_i alone;
-//   * characteristic reconstruction (Sec. 3.2.1, C = L W, optional, PLM): the
-//     paper defers the projection steps to another paper.  Reading: for each
-//     cell the one-sided differences of the face-frame primitives are
-//     projected with the left eigenvectors of that cell's primitive system,
-//     limited component by component with the van Leer limiter, and projected
-//     back with the right eigenvectors; the edge values are W -/+ dW/2.  Right
-//     eigenvectors follow the Roe & Balsara (1996) normalisation; the left ones
-//     are their inverse.
+//   * characteristic reconstruction (Sec. 3.2.1, C = L W, optional, PLM and
+//     PPM): the paper defers the projection steps to another paper.  Reading:
+//     for each cell the differences of the face-frame primitives of its
+//     stencil from the cell's own are projected with the left eigenvectors of
+//     that cell's primitive system, reconstructed per wave family (van Leer
+//     slope, or the limited PPM parabola), and the edge offsets projected
+//     back with the right eigenvectors.  Right eigenvectors follow the Roe &
+//     Balsara (1996) normalisation; the left ones are their inverse.
 #include <algorithm>
 #include <cmath>
 #include <cstddef>
@@ -146,7 +146,7 @@ struct Cfg {
   double cfl;                   // Courant number C0 used by newdt
   double ct_eps;                // 0: sign switch for the CT upwinding; >0: ramp width
   double dfloor, pfloor;        // optional density / pressure floors (0: off)
-  int32_t charac;               // 1: PLM on characteristic variables (DC unchanged; PPM unsupported)
+  int32_t charac;               // 1: PLM / PPM on characteristic variables (DC unchanged)
   int32_t pad_;
 };
 
@@ -483,6 +483,34 @@ void char_plm_edges(const T* wm, const T* w0, const T* wp, const T& bn, double g
   }
 }
 
+// Characteristic PPM edges of cell c from its five-cell stencil w[o] =
+// W_{c-2+o}: the differences from W_c in characteristic variables, the limited
+// parabola of Colella & Sekora per wave family, and the edge offsets projected
+// back.
+template <class T> void char_ppm_edges(const T w[5][7], const T& bn, double gamma, T* left, T* right) {
+  T R[7][7], L[7][7];
+  prim_right_eigenvectors(w[2], bn, gamma, R);
+  invert7(R, L);
+  T cl[7], cr[7];
+  for (int k = 0; k < 7; ++k) {
+    T q[5];
+    for (int o = 0; o < 5; ++o) {
+      q[o] = T(0.0);
+      for (int j = 0; j < 7; ++j) q[o] = q[o] + L[k][j] * (w[o][j] - w[2][j]);
+    }
+    ppm_cell(&q[2], cl[k], cr[k]);
+  }
+  for (int j = 0; j < 7; ++j) {
+    T dl(0.0), dr(0.0);
+    for (int k = 0; k < 7; ++k) {
+      dl = dl + R[j][k] * cl[k];
+      dr = dr + R[j][k] * cr[k];
+    }
+    left[j] = w[2][j] + dl;
+    right[j] = w[2][j] + dr;
+  }
+}
+
 template <class T> void recon_face(int recon, const T* q, T& ql, T& qr) {
   if (recon == RECON_DC) {
     ql = q[-1];
@@ -715,6 +743,20 @@ int spatial_operator(const Cfg& cfg, const Geo& g, int recon, const T* cons, con
             T lft[7], rgt[7];
             char_plm_edges(w[0], w[1], w[2], bnc[0], cfg.gamma, lft, wl);  // cell c-1
             char_plm_edges(w[1], w[2], w[3], bnc[1], cfg.gamma, wr, rgt);  // cell c
+          } else if (cfg.charac && recon == RECON_PPM) {
+            // characteristic PPM: right edge of cell c-1, left edge of cell c
+            T st[2][5][7], bnc[2];
+            for (int cell = 0; cell < 2; ++cell)
+              for (int o = 0; o < 5; ++o)
+                for (int n = 0; n < 7; ++n) st[cell][o][n] = line[n][cell + o];  // cells c-3+cell .. c+1+cell
+            for (int o = 0; o < 2; ++o) {
+              int idx[3] = {i, j, k};
+              idx[d] += o - 1;
+              bnc[o] = wk.bcc[(size_t)d * nc + g.c(idx[0], idx[1], idx[2])];
+            }
+            T lft[7], rgt[7];
+            char_ppm_edges(st[0], bnc[0], cfg.gamma, lft, wl);  // cell c-1
+            char_ppm_edges(st[1], bnc[1], cfg.gamma, wr, rgt);  // cell c
           } else {
             for (int n = 0; n < 7; ++n) recon_face(recon, &line[n][3], wl[n], wr[n]);
           }
@@ -938,7 +980,6 @@ template <class T> int step(const Cfg& cfg, T* cons, T* bf, double dt) {
   Geo g(cfg);
   Scheme sc;
   if (!scheme_for(cfg.integrator, sc)) return -1;
-  if (cfg.charac && cfg.recon == RECON_PPM) return -1;  // characteristic PPM is not part of this oracle
   const size_t nc = g.ncell(), nf = g.nface();
   const size_t ncv = g.nv * nc;  // cell part of the state: MHD variables and scalars
   const size_t n = ncv + 3 * nf;
@@ -1098,6 +1139,16 @@ int orc_prim_eigen(double gamma, const double* w, double bn, double* R, double* 
       R[i * 7 + j] = r[i][j];
       L[i * 7 + j] = l[i][j];
     }
+  return 0;
+}
+
+// Characteristic PPM edges of one cell from its five-cell stencil w (5 x 7,
+// row-major, cells c-2 .. c+2).
+int orc_char_ppm(double gamma, const double* w, double bn, double* left, double* right) {
+  double st[5][7];
+  for (int o = 0; o < 5; ++o)
+    for (int n = 0; n < 7; ++n) st[o][n] = w[o * 7 + n];
+  orc::char_ppm_edges<double>(st, bn, gamma, left, right);
   return 0;
 }
 

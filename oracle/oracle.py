@@ -62,6 +62,7 @@ def lib():
         _lib.orc_recon_line.argtypes = [C.c_int, C.c_int, P, P, P]
         _lib.orc_prim_eigen.argtypes = [C.c_double, P, C.c_double, P, P]
         _lib.orc_char_plm.argtypes = [C.c_double, P, P, P, C.c_double, P, P]
+        _lib.orc_char_ppm.argtypes = [C.c_double, P, C.c_double, P, P]
         _lib.orc_drive_scalar.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_int,
                                           P, P]
         _lib.orc_take_floor_count.restype = C.c_longlong
@@ -192,6 +193,16 @@ def char_plm(gamma: float, wm, w0, wp, bn: float):
     wm, w0, wp = (np.ascontiguousarray(x, dtype=np.float64) for x in (wm, w0, wp))
     left, right = np.zeros(7), np.zeros(7)
     lib().orc_char_plm(float(gamma), _p(wm), _p(w0), _p(wp), float(bn), _p(left), _p(right))
+    return left, right
+
+
+def char_ppm(gamma: float, stencil, bn: float):
+    """Characteristic PPM (left, right) edge states of the middle cell of a
+    five-cell stencil (5 x 7 face-frame primitives)."""
+    st = np.ascontiguousarray(stencil, dtype=np.float64)
+    assert st.shape == (5, 7)
+    left, right = np.zeros(7), np.zeros(7)
+    lib().orc_char_ppm(float(gamma), _p(st), float(bn), _p(left), _p(right))
     return left, right
 
 

@@ -1,5 +1,5 @@
-"""Pins of the oracle's characteristic reconstruction (Sec. 3.2.1: PLM on the
-characteristic variables C = L W of the primitive system).
+"""Pins of the oracle's characteristic reconstruction (Sec. 3.2.1: PLM and
+PPM on the characteristic variables C = L W of the primitive system).
 
 The eigenvectors are checked against the primitive-variable form of the ideal
 MHD equations (Eq. (cons) with the ideal-gas law), written out here as the
@@ -196,9 +196,88 @@ def test_characteristic_plm_oscillates_less_on_brio_wu(orc):
     assert tv[True][0] < tv[False][0] and tv[True][1] < tv[False][1], tv
 
 
-def test_characteristic_ppm_is_refused(orc):
+def _scalar_ppm_edges(orc, f):
+    """Left and right edges of the middle cell of the 5 values f by the
+    oracle's scalar PPM (pinned in test_oracle_pins)."""
+    line = np.concatenate([[2 * f[0] - f[1]], f, [2 * f[4] - f[3]]])  # cells -3 .. 3
+    ql, qr = orc.recon_line("ppm", line)
+    return qr[3], ql[4]
+
+
+@pytest.mark.parametrize("case", [0, 3, 6])
+def test_ppm_reconstructs_each_wave_family_on_its_own(orc, case):
+    """W = W_c + f r_a + g r_b with r_a, r_b two right eigenvectors of W_c and
+    f, g two profiles vanishing at the middle cell (one monotone, one with an
+    extremum): the characteristic PPM edges are W_c + ppm(f) r_a + ppm(g) r_b,
+    each family reconstructed by the scalar PPM."""
+    w0, bn = states()[case]
+    R, _ = orc.prim_eigen(G, w0, bn)
+    f = np.array([-0.03, -0.012, 0.0, 0.01, 0.025])     # monotone
+    h = np.array([0.02, 0.015, 0.0, 0.012, 0.03])       # minimum at the middle cell
+    ra, rb = R[:, 0], R[:, 4]
+    stencil = np.array([w0 + f[o] * ra + h[o] * rb for o in range(5)])
+    left, right = orc.char_ppm(G, stencil, bn)
+    fl, fr = _scalar_ppm_edges(orc, f)
+    hl, hr = _scalar_ppm_edges(orc, h)
+    assert np.allclose(left, w0 + fl * ra + hl * rb, rtol=0, atol=1e-14)
+    assert np.allclose(right, w0 + fr * ra + hr * rb, rtol=0, atol=1e-14)
+
+
+def test_ppm_of_one_profile_equals_primitive_ppm(orc):
+    """All components following one profile (W = W_c + f v): limiting is
+    homogeneous, so the characteristic edges equal PPM on each primitive."""
+    w0, bn = states()[0]
+    v = np.array([0.1, -0.2, 0.05, 0.3, -0.1, 0.2, 0.15])
+    f = np.array([-0.05, -0.02, 0.0, 0.03, 0.04])
+    left, right = orc.char_ppm(G, np.array([w0 + f[o] * v for o in range(5)]), bn)
+    fl, fr = _scalar_ppm_edges(orc, f)
+    assert np.allclose(left, w0 + fl * v, rtol=0, atol=1e-14)
+    assert np.allclose(right, w0 + fr * v, rtol=0, atol=1e-14)
+
+
+def test_characteristic_ppm_step_invariants_and_symmetry(orc):
     from paper_2005_06651_amd import inputs
-    b = inputs.smooth_random(n=(6, 6, 6), seed=22, ng=3)
+    u = inputs.uniform(n=(8, 6, 4), ng=3)
+    cfg = orc.cfg_for(u, recon="ppm", integrator="rk3", charac=True)
+    cons = orc.prim2cons(cfg, u.prim, u.bface)
+    c, _, _, _ = orc.run(cfg, cons, u.bface, 2, dt=0.01)
+    a = (slice(None),) + u.active
+    assert np.abs(c[a] - cons[a]).max() < 1e-14
+    b = inputs.smooth_random(n=(12, 10, 8), seed=23, ng=3)
     cfg = orc.cfg_for(b, recon="ppm", integrator="rk3", charac=True)
     cons = orc.prim2cons(cfg, b.prim, b.bface)
-    assert orc.step(cfg, cons, b.bface.copy(), 1e-3) < 0
+    c1, b1, _, _ = orc.run(cfg, cons, b.bface, 2)
+    for v in range(5):
+        t0, t1 = cons[v][b.active].sum(), c1[v][b.active].sum()
+        assert abs(t1 - t0) <= 1e-13 * max(abs(t0), 1.0)
+    orc.fill_ghosts(cfg, c1, b1)
+    assert inputs.divb_metric(b1, b.n, b.ng, b.dx) < 1e-13
+    n, ng = 24, 3
+    outs = []
+    for axis in range(3):
+        dims, prim, bf = _line_problem(n, axis, ng)
+        cfg = orc.make_cfg(dims, ng, (1.0 / n,) * 3, G, recon="ppm", riemann="hlld", integrator="rk3", charac=True)
+        c, bb, _, _ = orc.run(cfg, orc.prim2cons(cfg, prim, bf), bf, 4, dt=0.004)
+        t1 = (axis + 1) % 3
+        sl = [slice(ng + 1, ng + 2)] * 3
+        sl[2 - axis] = slice(ng, ng + n)
+        sl = tuple(sl)
+        outs.append(np.stack([c[0][sl].ravel(), c[1 + axis][sl].ravel(), c[1 + t1][sl].ravel(), c[4][sl].ravel(),
+                              bb[t1][sl].ravel()]))
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def test_characteristic_ppm_oscillates_less_on_brio_wu(orc):
+    """As for PLM: RK3 + characteristic PPM on Brio & Wu's tube has lower
+    total variation of rho and v_t at t = 0.08 than PPM on the primitives."""
+    n, g = 256, 3
+    dims, prim, bf = _brio_wu(n, ng=g)
+    tv = {}
+    for ch in (False, True):
+        cfg = orc.make_cfg(dims, g, (1.0 / n, 0.25, 0.25), 2.0, recon="ppm", riemann="hlld", integrator="rk3",
+                           cfl=0.4, charac=ch)
+        c, _, _, _ = orc.run(cfg, orc.prim2cons(cfg, prim, bf), bf, 0, t_end=0.08)
+        rho = c[0][g, g, g:g + n]
+        vt = c[2][g, g, g:g + n] / rho
+        tv[ch] = (np.abs(np.diff(rho)).sum(), np.abs(np.diff(vt)).sum())
+    assert tv[True][0] < tv[False][0] and tv[True][1] < tv[False][1], tv
