@@ -87,7 +87,7 @@ typedef struct {
                            /* clamp(1/2 + (F_rho/rho_bar)/(2 ct_eps c_max), 0, 1)  */
   int32_t nscalars;        /* passive scalars, in [0, 64] (Sec. 3.2.6, Eq.          */
                            /* (passive_scalars)); see "Passive scalars" below      */
-  int32_t charac;          /* 0 or 1: PLM on characteristic variables C = L W      */
+  int32_t charac;          /* 0 or 1: PLM / PPM on characteristic variables C = LW  */
                            /* (Sec. 3.2.1); see "Characteristic reconstruction"    */
 } athmhd_config;
 
@@ -106,16 +106,16 @@ typedef struct {
  * scalars. */
 
 /* Characteristic reconstruction (Sec. 3.2.1, C = L W): with charac = 1 the
- * PLM states at each face are formed on the characteristic variables of the
- * primitive system in the face frame: for each cell the one-sided
- * differences of (rho, vn, vt1, vt2, P, Bt1, Bt2) are projected with the left
- * eigenvectors of that cell's state (normal field: the cell-centred one),
- * limited per wave family with the van Leer limiter and projected back with
- * the right eigenvectors (normalised after Roe & Balsara 1996).  DC (the VL2
- * predictor) is unchanged.  Such a handle runs the stages on the unfused
- * kernel pipeline whatever kernel_path says.  ATHMHD_EUNSUP for PPM, with
- * passive scalars, on athmhd_create_mesh and athmhd_create_batch, and from
- * athmhd_step_vjp. */
+ * PLM or PPM states at each face are formed on the characteristic variables
+ * of the primitive system in the face frame: for each cell the differences
+ * of (rho, vn, vt1, vt2, P, Bt1, Bt2) across its stencil are projected with
+ * the left eigenvectors of that cell's state (normal field: the cell-centred
+ * one), reconstructed per wave family (van Leer slope, or the limited PPM
+ * parabola) and projected back with the right eigenvectors (normalised after
+ * Roe & Balsara 1996).  DC (the VL2 predictor) is unchanged.  Such a handle
+ * runs the stages on the unfused kernel pipeline whatever kernel_path says.
+ * ATHMHD_EUNSUP with passive scalars, on athmhd_create_mesh and
+ * athmhd_create_batch, and from athmhd_step_vjp. */
 
 /* Version of this ABI (major*100 + minor). */
 ATHMHD_API int athmhd_version(void);

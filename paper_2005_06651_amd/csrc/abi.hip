@@ -467,8 +467,6 @@ int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
   if (nblocks_max < 1) return fail(nullptr, ATHMHD_EINVAL, "nblocks_max must be >= 1");
   if (cfg->nscalars > 0 && (cfg->kernel_path != 0 || cfg->charac))
     return fail(nullptr, ATHMHD_EUNSUP, "passive scalars run with the fused kernels only");
-  if (cfg->charac && cfg->recon == ATHMHD_RECON_PPM)
-    return fail(nullptr, ATHMHD_EUNSUP, "characteristic reconstruction is available for PLM (and DC) only");
   athmhd_t h = new (std::nothrow) athmhd_s();
   if (!h) return fail(nullptr, ATHMHD_ENOMEM, "host allocation failed");
   h->cfg = *cfg;

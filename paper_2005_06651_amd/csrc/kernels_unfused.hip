@@ -125,14 +125,14 @@ __device__ void char_right(const double* w, double bn, double gamma, double R[7]
   R[0][3] = 1.0;  // entropy
 }
 
-// PLM edges of cell w0 on characteristic variables: the one-sided differences
-// are projected with L = R^{-1} (solving R x = dW by Gaussian elimination with
-// partial pivoting, both differences at once; rows are exchanged by selects
+// Projection onto the characteristic variables of the state w0: solves
+// R x = B for NR right-hand sides (rows of B, replaced by the solutions) by
+// Gaussian elimination with partial pivoting.  Rows are exchanged by selects
 // so that every index is a compile-time constant and the system stays in
-// registers), van Leer-limited per wave family, and projected back with R.
-__device__ void char_plm(const double* wm, const double* w0, const double* wp, double bn, double gamma,
-                         double* left, double* right) {
-  double M[7][9];
+// registers.
+template <int NR>
+__device__ __forceinline__ void char_project(const double* w0, double bn, double gamma, double (&B)[NR][7]) {
+  double M[7][7 + NR];
   {
     double R[7][7];
     char_right(w0, bn, gamma, R);
@@ -140,8 +140,8 @@ __device__ void char_plm(const double* wm, const double* w0, const double* wp, d
     for (int r = 0; r < 7; ++r) {
 #pragma unroll
       for (int c = 0; c < 7; ++c) M[r][c] = R[r][c];
-      M[r][7] = w0[r] - wm[r];
-      M[r][8] = wp[r] - w0[r];
+#pragma unroll
+      for (int n = 0; n < NR; ++n) M[r][7 + n] = B[n][r];
     }
   }
 #pragma unroll
@@ -151,7 +151,7 @@ __device__ void char_plm(const double* wm, const double* w0, const double* wp, d
     for (int r = c + 1; r < 7; ++r) {
       const bool sw = fabs(M[r][c]) > fabs(M[c][c]);
 #pragma unroll
-      for (int k = c; k < 9; ++k) {
+      for (int k = c; k < 7 + NR; ++k) {
         const double a = M[c][k], b = M[r][k];
         M[c][k] = sw ? b : a;
         M[r][k] = sw ? a : b;
@@ -162,43 +162,84 @@ __device__ void char_plm(const double* wm, const double* w0, const double* wp, d
     for (int r = c + 1; r < 7; ++r) {
       const double f = M[r][c] * inv;
 #pragma unroll
-      for (int k = c + 1; k < 9; ++k) M[r][k] -= f * M[c][k];
+      for (int k = c + 1; k < 7 + NR; ++k) M[r][k] -= f * M[c][k];
     }
   }
-  double dl[7], dr[7];
 #pragma unroll
   for (int c = 6; c >= 0; --c) {
-    double sl = M[c][7], sr = M[c][8];
-#pragma unroll
-    for (int k = c + 1; k < 7; ++k) {
-      sl -= M[c][k] * dl[k];
-      sr -= M[c][k] * dr[k];
-    }
     const double inv = 1.0 / M[c][c];
-    dl[c] = sl * inv;
-    dr[c] = sr * inv;
-  }
-  double dc[7];
 #pragma unroll
-  for (int k = 0; k < 7; ++k) {
-    const double pr = dl[k] * dr[k];
-    dc[k] = pr > 0.0 ? 2.0 * pr / (dl[k] + dr[k]) : 0.0;
+    for (int n = 0; n < NR; ++n) {
+      double v = M[c][7 + n];
+#pragma unroll
+      for (int k = c + 1; k < 7; ++k) v -= M[c][k] * B[n][k];
+      B[n][c] = v * inv;
+    }
   }
+}
+
+// w0 + R d for the characteristic offset d
+__device__ __forceinline__ void char_back(const double* w0, double bn, double gamma, const double* d, double* out) {
   double R[7][7];
   char_right(w0, bn, gamma, R);
 #pragma unroll
   for (int j = 0; j < 7; ++j) {
-    double dw = 0.0;
+    double v = 0.0;
 #pragma unroll
-    for (int k = 0; k < 7; ++k) dw += R[j][k] * dc[k];
-    left[j] = w0[j] - 0.5 * dw;
-    right[j] = w0[j] + 0.5 * dw;
+    for (int k = 0; k < 7; ++k) v += R[j][k] * d[k];
+    out[j] = w0[j] + v;
   }
 }
 
+// PLM edges of cell w0 on characteristic variables: the one-sided differences
+// projected with L, van Leer-limited per wave family, projected back with R.
+__device__ void char_plm(const double* wm, const double* w0, const double* wp, double bn, double gamma,
+                         double* left, double* right) {
+  double B[2][7];
+#pragma unroll
+  for (int r = 0; r < 7; ++r) {
+    B[0][r] = w0[r] - wm[r];
+    B[1][r] = wp[r] - w0[r];
+  }
+  char_project<2>(w0, bn, gamma, B);
+  double dl[7], dr[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    const double pr = B[0][k] * B[1][k];
+    const double dc = pr > 0.0 ? 2.0 * pr / (B[0][k] + B[1][k]) : 0.0;
+    dl[k] = -0.5 * dc;
+    dr[k] = 0.5 * dc;
+  }
+  char_back(w0, bn, gamma, dl, left);
+  char_back(w0, bn, gamma, dr, right);
+}
+
+// PPM edges of the middle cell of the stencil st[0..4] on characteristic
+// variables: the differences from the middle cell projected with L, the
+// limited parabola per wave family, the edge offsets projected back with R.
+__device__ void char_ppm(const double (&st)[5][7], double bn, double gamma, double* left, double* right) {
+  double B[4][7];
+#pragma unroll
+  for (int r = 0; r < 7; ++r) {
+    B[0][r] = st[0][r] - st[2][r];
+    B[1][r] = st[1][r] - st[2][r];
+    B[2][r] = st[3][r] - st[2][r];
+    B[3][r] = st[4][r] - st[2][r];
+  }
+  char_project<4>(st[2], bn, gamma, B);
+  double cl[7], cr[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    const double q[5] = {B[0][k], B[1][k], 0.0, B[2][k], B[3][k]};
+    cell_edges<2>(q, cl[k], cr[k]);
+  }
+  char_back(st[2], bn, gamma, cl, left);
+  char_back(st[2], bn, gamma, cr, right);
+}
+
 // Fluxes through the faces normal to D: normal index [ng, ng+n_D], transverse
-// indices [ng-1, ng+n_t] (one extra ring for the corner EMFs).  CHAR: PLM on
-// characteristic variables (RECON == 1 only).
+// indices [ng-1, ng+n_t] (one extra ring for the corner EMFs).  CHAR: PLM or
+// PPM on characteristic variables.
 template <int D, int RECON, int RS, bool CHAR>
 __global__ void __launch_bounds__(kThreads) k_flux(Geo g, Gas gas, double ct_eps, Floors fl,
                                                   const double* __restrict__ w, const double* __restrict__ bface,
@@ -231,6 +272,28 @@ __global__ void __launch_bounds__(kThreads) k_flux(Geo g, Gas gas, double ct_eps
     double lm[7], rm[7], l0[7], r0[7];
     char_plm(w[0], w[1], w[2], bnm, gas.gamma, lm, rm);
     char_plm(w[1], w[2], w[3], bn0, gas.gamma, l0, r0);
+    L = FaceState{rm[0], rm[1], rm[2], rm[3], rm[4], rm[5], rm[6]};
+    R = FaceState{l0[0], l0[1], l0[2], l0[3], l0[4], l0[5], l0[6]};
+  } else if (CHAR && RECON == 2) {
+    // cells c-3 .. c+2; right edge of c-1 (stencil c-3 .. c+1), left edge of c
+    const int vi[7] = {0, 1 + D, 1 + T1, 1 + T2, 4, 5 + T1, 5 + T2};
+    double lm[7], rm[7], l0[7], r0[7];
+    {
+      double st[5][7];
+#pragma unroll
+      for (int o = 0; o < 5; ++o)
+#pragma unroll
+        for (int n = 0; n < 7; ++n) st[o][n] = wb[vi[n] * g.cvar + q + (o - 3) * s];
+      char_ppm(st, wb[(5 + D) * g.cvar + q - s], gas.gamma, lm, rm);
+    }
+    {
+      double st[5][7];
+#pragma unroll
+      for (int o = 0; o < 5; ++o)
+#pragma unroll
+        for (int n = 0; n < 7; ++n) st[o][n] = wb[vi[n] * g.cvar + q + (o - 2) * s];
+      char_ppm(st, wb[(5 + D) * g.cvar + q], gas.gamma, l0, r0);
+    }
     L = FaceState{rm[0], rm[1], rm[2], rm[3], rm[4], rm[5], rm[6]};
     R = FaceState{l0[0], l0[1], l0[2], l0[3], l0[4], l0[5], l0[6]};
   } else {
@@ -370,6 +433,7 @@ hipError_t flux_dir(const Geo& g, const Gas& gas, int recon, bool charac, int rs
   if (recon == 0) return flux_rs<D, 0, false>(g, gas, rs, ct_eps, fl, w, xb, fo, bad, nb, s);
   if (recon == 1 && charac) return flux_rs<D, 1, true>(g, gas, rs, ct_eps, fl, w, xb, fo, bad, nb, s);
   if (recon == 1) return flux_rs<D, 1, false>(g, gas, rs, ct_eps, fl, w, xb, fo, bad, nb, s);
+  if (charac) return flux_rs<D, 2, true>(g, gas, rs, ct_eps, fl, w, xb, fo, bad, nb, s);
   return flux_rs<D, 2, false>(g, gas, rs, ct_eps, fl, w, xb, fo, bad, nb, s);
 }
 

@@ -80,7 +80,6 @@ def test_scalars_need_the_fused_kernels():
 
 @pytest.mark.parametrize("over,code,needle", [
     (dict(charac=2), athmhd.EINVAL, "charac"),
-    (dict(charac=1, recon=2, nghost=3), athmhd.EUNSUP, "PLM"),
     (dict(charac=1, nscalars=1), athmhd.EUNSUP, "scalars"),
 ])
 def test_characteristic_reconstruction_arguments(over, code, needle):

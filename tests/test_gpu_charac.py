@@ -1,4 +1,4 @@
-"""Characteristic reconstruction on the GPU (Sec. 3.2.1, C = L W; PLM):
+"""Characteristic reconstruction on the GPU (Sec. 3.2.1, C = L W; PLM, PPM):
 the unfused pipeline's flux kernels project onto the characteristic
 variables of each cell, limit per wave family and project back.  Checked
 against the oracle at the 1e-12 bar on ragged blocks and on Brio & Wu's
@@ -65,6 +65,52 @@ def test_characteristic_steps_match_oracle(torch_dev, athmhd, orc, integ, rs, fl
         assert orc.step(cfg, rc, rb, dt) == 0
         s.step(tc, tb, dt)
     errs = rel_l1_all(tc.cpu().numpy(), tb.cpu().numpy(), rc, rb, b.ng, b.n)
+    print("rel L1 per array", " ".join(f"{e:.1e}" for e in errs), flush=True)
+    assert max(errs) <= TOL
+    s.close()
+
+
+@pytest.mark.parametrize("integ,rs", [("rk3", "hlld"), ("rk3", "hlle"), ("vl2", "hlld")])
+def test_characteristic_ppm_steps_match_oracle(torch_dev, athmhd, orc, integ, rs):
+    """PPM on characteristic variables: three steps of a ragged 37 x 19 x 11
+    block (3 ghost layers) against the oracle."""
+    torch, dev = torch_dev
+    b = inputs.smooth_random(n=(37, 19, 11), seed=85, ng=3)
+    kw = dict(integrator=integ, recon="ppm", riemann=rs)
+    s = athmhd.Solver(b.n, b.ng, b.dx, b.gamma, charac=True, **kw)
+    cfg = orc.cfg_for(b, charac=True, **kw)
+    cons = orc.prim2cons(cfg, b.prim, b.bface)
+    tc, tb = to_dev(torch, dev, cons), to_dev(torch, dev, b.bface)
+    rc, rb = cons.copy(), b.bface.copy()
+    for _ in range(3):
+        dt, bad = orc.newdt(cfg, rc, rb)
+        assert bad == 0
+        assert orc.step(cfg, rc, rb, dt) == 0
+        s.step(tc, tb, dt)
+    errs = rel_l1_all(tc.cpu().numpy(), tb.cpu().numpy(), rc, rb, b.ng, b.n)
+    print("rel L1 per array", " ".join(f"{e:.1e}" for e in errs), flush=True)
+    assert max(errs) <= TOL
+    s.close()
+
+
+def test_characteristic_ppm_brio_wu_matches_oracle(torch_dev, athmhd, orc):
+    """Brio & Wu's tube with RK3 + characteristic PPM + HLLD, 40 steps."""
+    torch, dev = torch_dev
+    n, g = 128, 3
+    dims, prim, bf = _brio_wu(n, ng=g)
+    dx = (1.0 / n, 0.25, 0.25)
+    kw = dict(integrator="rk3", recon="ppm", riemann="hlld")
+    cfg = orc.make_cfg(dims, g, dx, 2.0, charac=True, **kw)
+    cons = orc.prim2cons(cfg, prim, bf)
+    s = athmhd.Solver(dims, g, dx, 2.0, charac=True, **kw)
+    tc, tb = to_dev(torch, dev, cons), to_dev(torch, dev, bf)
+    rc, rb = cons.copy(), bf.copy()
+    for _ in range(40):
+        assert orc.step(cfg, rc, rb, 2.5e-4) == 0
+        s.step(tc, tb, 2.5e-4)
+    a = (slice(None), slice(g, g + dims[2]), slice(g, g + dims[1]), slice(g, g + dims[0]))
+    gc, gb = tc.cpu().numpy()[a], tb.cpu().numpy()[a]
+    errs = W.rel_l1_arrays(gc, gb, rc[a], rb[a], mom_speed=1.0)
     print("rel L1 per array", " ".join(f"{e:.1e}" for e in errs), flush=True)
     assert max(errs) <= TOL
     s.close()
