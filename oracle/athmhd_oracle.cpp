@@ -52,6 +52,7 @@
 //     back with the right eigenvectors.  Right eigenvectors follow the Roe &
 //     Balsara (1996) normalisation; the left ones are their inverse.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstddef>
 #include <cstdint>
@@ -1040,6 +1041,251 @@ inline int newdt(const Cfg& cfg, const double* cons, const double* bf, double* d
   return bad;
 }
 
+// ---------------------------------------------------------------------------
+// Restriction and prolongation between a coarse block and the fine block that
+// refines one octant of it (Sec. 2.1.5), for block refinement / derefinement.
+// Both blocks have the geometry of cfg (n cells per side, even; ng ghosts;
+// the fine cells half as wide).  (ox, oy, oz): the octant's first active
+// coarse cell, 0 or n/2 along each direction.
+//   restriction: volume average of the 8 fine cells (all nv cell arrays);
+//     area average of the 4 fine faces on each coarse face of the octant
+//     (the octant's upper faces read the fine block's image faces);
+//   prolongation of cells: U_C + the minmod-limited slopes along each
+//     direction times the offsets +-1/4 (coarse cell units) of the children;
+//   prolongation of faces (Toth & Roe 2002): each coarse face of the octant
+//     (and its upper neighbours) split into 4 fine faces by the 2D
+//     minmod-limited linear profile on the face; the 12 faces inside each
+//     coarse cell from the conditions that every fine cell has the coarse
+//     cell's divergence and that the curl at each of the 6 interior edges
+//     equals its estimate from the outer faces (the mean of the tangential
+//     differences on the two outer faces parallel to the edge's planes) --
+//     14 equations of rank 12, solved here by least squares (normal
+//     equations), consistent when the outer values are.
+// ---------------------------------------------------------------------------
+template <class T> T minmod(const T& a, const T& b) {
+  if (val(a) > 0.0 && val(b) > 0.0) return vmin(a, b);
+  if (val(a) < 0.0 && val(b) < 0.0) return vmax(a, b);
+  return T(0.0);
+}
+
+inline void restrict_octant(const Geo& g, const double* fc, const double* fb, double* cc, double* cb, const int o[3]) {
+  const size_t nc = g.ncell(), nf = g.nface();
+  const int h[3] = {g.n[0] / 2, g.n[1] / 2, g.n[2] / 2};
+  for (int v = 0; v < g.nv; ++v)
+    for (int c = 0; c < h[2]; ++c)
+      for (int b = 0; b < h[1]; ++b)
+        for (int a = 0; a < h[0]; ++a) {
+          double sum = 0.0;
+          for (int s3 = 0; s3 < 2; ++s3)
+            for (int s2 = 0; s2 < 2; ++s2)
+              for (int s1 = 0; s1 < 2; ++s1)
+                sum += fc[v * nc + g.c(g.ng + 2 * a + s1, g.ng + 2 * b + s2, g.ng + 2 * c + s3)];
+          cc[v * nc + g.c(g.ng + o[0] + a, g.ng + o[1] + b, g.ng + o[2] + c)] = sum / 8.0;
+        }
+  for (int d = 0; d < 3; ++d) {
+    const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+    int lim[3] = {h[0], h[1], h[2]};
+    lim[d] = h[d] + 1;  // the octant's upper faces too
+    for (int c = 0; c < lim[2]; ++c)
+      for (int b = 0; b < lim[1]; ++b)
+        for (int a = 0; a < lim[0]; ++a) {
+          const int q[3] = {a, b, c};
+          double sum = 0.0;
+          for (int u = 0; u < 2; ++u)
+            for (int w = 0; w < 2; ++w) {
+              int f[3];
+              f[d] = g.ng + 2 * q[d];
+              f[t1] = g.ng + 2 * q[t1] + u;
+              f[t2] = g.ng + 2 * q[t2] + w;
+              sum += fb[d * nf + g.f(f[0], f[1], f[2])];
+            }
+          cb[d * nf + g.f(g.ng + o[0] + a, g.ng + o[1] + b, g.ng + o[2] + c)] = sum / 4.0;
+        }
+  }
+}
+
+// Solve the least-squares problem min |A x - r| (rows x 12) by the normal
+// equations with Gaussian elimination (partial pivoting).
+inline void lsq12(const std::vector<std::array<double, 12>>& A, const std::vector<double>& r, double* x) {
+  double N[12][13];
+  for (int i = 0; i < 12; ++i) {
+    for (int j = 0; j < 12; ++j) {
+      double s = 0.0;
+      for (size_t k = 0; k < A.size(); ++k) s += A[k][i] * A[k][j];
+      N[i][j] = s;
+    }
+    double s = 0.0;
+    for (size_t k = 0; k < A.size(); ++k) s += A[k][i] * r[k];
+    N[i][12] = s;
+  }
+  for (int c = 0; c < 12; ++c) {
+    int piv = c;
+    for (int i = c + 1; i < 12; ++i)
+      if (std::fabs(N[i][c]) > std::fabs(N[piv][c])) piv = i;
+    for (int k = 0; k < 13; ++k) std::swap(N[c][k], N[piv][k]);
+    for (int i = c + 1; i < 12; ++i) {
+      const double f = N[i][c] / N[c][c];
+      for (int k = c; k < 13; ++k) N[i][k] -= f * N[c][k];
+    }
+  }
+  for (int c = 11; c >= 0; --c) {
+    double s = N[c][12];
+    for (int k = c + 1; k < 12; ++k) s -= N[c][k] * x[k];
+    x[c] = s / N[c][c];
+  }
+}
+
+inline void prolong_octant(const Geo& g, const double* cc, const double* cb, double* fc, double* fb, const int o[3]) {
+  const size_t nc = g.ncell(), nf = g.nface();
+  const int h[3] = {g.n[0] / 2, g.n[1] / 2, g.n[2] / 2};
+  // cells: U_C + sum_d minmod slope_d * (+-1/4)
+  for (int v = 0; v < g.nv; ++v)
+    for (int c = 0; c < h[2]; ++c)
+      for (int b = 0; b < h[1]; ++b)
+        for (int a = 0; a < h[0]; ++a) {
+          const int C[3] = {g.ng + o[0] + a, g.ng + o[1] + b, g.ng + o[2] + c};
+          const double u0 = cc[v * nc + g.c(C[0], C[1], C[2])];
+          double sl[3];
+          for (int d = 0; d < 3; ++d) {
+            int m[3] = {C[0], C[1], C[2]}, p[3] = {C[0], C[1], C[2]};
+            m[d] -= 1;
+            p[d] += 1;
+            sl[d] = minmod(u0 - cc[v * nc + g.c(m[0], m[1], m[2])], cc[v * nc + g.c(p[0], p[1], p[2])] - u0);
+          }
+          for (int s3 = 0; s3 < 2; ++s3)
+            for (int s2 = 0; s2 < 2; ++s2)
+              for (int s1 = 0; s1 < 2; ++s1)
+                fc[v * nc + g.c(g.ng + 2 * a + s1, g.ng + 2 * b + s2, g.ng + 2 * c + s3)] =
+                    u0 + 0.25 * ((2 * s1 - 1) * sl[0] + (2 * s2 - 1) * sl[1] + (2 * s3 - 1) * sl[2]);
+        }
+  // outer fine faces: each coarse face of the octant (upper ones included)
+  // split by the minmod-limited linear profile along its two transverse
+  // directions
+  for (int d = 0; d < 3; ++d) {
+    const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+    int lim[3] = {h[0], h[1], h[2]};
+    lim[d] = h[d] + 1;
+    for (int c = 0; c < lim[2]; ++c)
+      for (int b = 0; b < lim[1]; ++b)
+        for (int a = 0; a < lim[0]; ++a) {
+          const int q[3] = {a, b, c};
+          const int C[3] = {g.ng + o[0] + a, g.ng + o[1] + b, g.ng + o[2] + c};
+          const double B = cb[d * nf + g.f(C[0], C[1], C[2])];
+          double sl[2];
+          for (int e = 0; e < 2; ++e) {
+            const int t = e == 0 ? t1 : t2;
+            int m[3] = {C[0], C[1], C[2]}, p[3] = {C[0], C[1], C[2]};
+            m[t] -= 1;
+            p[t] += 1;
+            sl[e] = minmod(B - cb[d * nf + g.f(m[0], m[1], m[2])], cb[d * nf + g.f(p[0], p[1], p[2])] - B);
+          }
+          for (int u = 0; u < 2; ++u)
+            for (int w = 0; w < 2; ++w) {
+              int f[3];
+              f[d] = g.ng + 2 * q[d];
+              f[t1] = g.ng + 2 * q[t1] + u;
+              f[t2] = g.ng + 2 * q[t2] + w;
+              fb[d * nf + g.f(f[0], f[1], f[2])] = B + 0.25 * ((2 * u - 1) * sl[0] + (2 * w - 1) * sl[1]);
+            }
+        }
+  }
+  // interior fine faces of each coarse cell
+  for (int c = 0; c < h[2]; ++c)
+    for (int b = 0; b < h[1]; ++b)
+      for (int a = 0; a < h[0]; ++a) {
+        const int base[3] = {g.ng + 2 * a, g.ng + 2 * b, g.ng + 2 * c};
+        // face value of component d at fine offset (x, y, z) in {0, 1, 2} from base
+        auto face = [&](int d, int x, int y, int z) -> double& {
+          return fb[d * nf + g.f(base[0] + x, base[1] + y, base[2] + z)];
+        };
+        // unknown numbering: component d, halves (p, q) of its transverse
+        // directions (t1, t2) in {0, 1}: 4 d + 2 p + q
+        auto unk = [](int d, int p, int q) { return 4 * d + 2 * p + q; };
+        // offset of the interior face of component d with its t1-half p and t2-half q
+        auto at = [](int d, int mid, int p, int q, int* x) {
+          x[d] = mid;
+          x[(d + 1) % 3] = p;
+          x[(d + 2) % 3] = q;
+        };
+        std::vector<std::array<double, 12>> A;
+        std::vector<double> r;
+        // coarse divergence density (unit fine spacing): sum over directions
+        // of (mean upper outer value - mean lower outer value) / 2
+        double dc = 0.0;
+        for (int d = 0; d < 3; ++d) {
+          double up = 0.0, lo = 0.0;
+          for (int p = 0; p < 2; ++p)
+            for (int q = 0; q < 2; ++q) {
+              int x[3];
+              at(d, 2, p, q, x);
+              up += face(d, x[0], x[1], x[2]);
+              at(d, 0, p, q, x);
+              lo += face(d, x[0], x[1], x[2]);
+            }
+          dc += (up - lo) / 4.0 / 2.0;
+        }
+        // every fine cell (s1, s2, s3): its divergence equals dc
+        for (int s3 = 0; s3 < 2; ++s3)
+          for (int s2 = 0; s2 < 2; ++s2)
+            for (int s1 = 0; s1 < 2; ++s1) {
+              const int s[3] = {s1, s2, s3};
+              std::array<double, 12> row{};
+              double rhs = dc;
+              for (int d = 0; d < 3; ++d) {
+                const int p = s[(d + 1) % 3], q = s[(d + 2) % 3];
+                int x[3];
+                at(d, 2 * s[d], p, q, x);  // outer face of this cell along d
+                const double outer = face(d, x[0], x[1], x[2]);
+                const double sg = s[d] == 1 ? 1.0 : -1.0;  // upper cell: outer - inner, lower: inner - outer
+                rhs -= sg * outer;
+                row[unk(d, p, q)] -= sg;
+              }
+              A.push_back(row);
+              r.push_back(rhs);
+            }
+        // interior edges along e, at half h of direction e: curl_e =
+        // d(B_b)/d(a) - d(B_a)/d(b) with (a, b) = (e+1, e+2)
+        for (int e = 0; e < 3; ++e) {
+          const int ea = (e + 1) % 3, eb = (e + 2) % 3;
+          for (int hh = 0; hh < 2; ++hh) {
+            std::array<double, 12> row{};
+            // interior faces of component eb (normal to eb) at the two halves
+            // of ea; of component ea at the two halves of eb
+            // unknown halves of component eb: (t1, t2) = (e, ea)
+            row[unk(eb, hh, 1)] += 1.0;
+            row[unk(eb, hh, 0)] -= 1.0;
+            // component ea: (t1, t2) = (eb, e)
+            row[unk(ea, 1, hh)] -= 1.0;
+            row[unk(ea, 0, hh)] += 1.0;
+            // estimate from the outer faces: means over the two outer planes
+            double est = 0.0;
+            for (int side = 0; side < 2; ++side) {
+              int x[3];
+              at(eb, 2 * side, hh, 1, x);
+              est += 0.5 * face(eb, x[0], x[1], x[2]);
+              at(eb, 2 * side, hh, 0, x);
+              est -= 0.5 * face(eb, x[0], x[1], x[2]);
+              at(ea, 2 * side, 1, hh, x);
+              est -= 0.5 * face(ea, x[0], x[1], x[2]);
+              at(ea, 2 * side, 0, hh, x);
+              est += 0.5 * face(ea, x[0], x[1], x[2]);
+            }
+            A.push_back(row);
+            r.push_back(est);
+          }
+        }
+        double xs[12];
+        lsq12(A, r, xs);
+        for (int d = 0; d < 3; ++d)
+          for (int p = 0; p < 2; ++p)
+            for (int q = 0; q < 2; ++q) {
+              int x[3];
+              at(d, 1, p, q, x);
+              face(d, x[0], x[1], x[2]) = xs[unk(d, p, q)];
+            }
+      }
+}
+
 }  // namespace orc
 
 // ---------------------------------------------------------------------------
@@ -1139,6 +1385,24 @@ int orc_prim_eigen(double gamma, const double* w, double bn, double* R, double* 
       R[i * 7 + j] = r[i][j];
       L[i * 7 + j] = l[i][j];
     }
+  return 0;
+}
+
+// Restriction of the fine block (fcons, fbface) into the octant (ox, oy, oz)
+// of the coarse block, and prolongation of that octant into the fine block.
+int orc_restrict(const orc::Cfg* c, const double* fcons, const double* fbface, double* ccons, double* cbface, int ox,
+                 int oy, int oz) {
+  orc::Geo g(*c);
+  const int o[3] = {ox, oy, oz};
+  orc::restrict_octant(g, fcons, fbface, ccons, cbface, o);
+  return 0;
+}
+
+int orc_prolong(const orc::Cfg* c, const double* ccons, const double* cbface, double* fcons, double* fbface, int ox,
+                int oy, int oz) {
+  orc::Geo g(*c);
+  const int o[3] = {ox, oy, oz};
+  orc::prolong_octant(g, ccons, cbface, fcons, fbface, o);
   return 0;
 }
 

@@ -1,0 +1,294 @@
+"""Pins of the oracle's level operators for block refinement (Sec. 2.1.5):
+restriction (volume averages of cells, area averages of faces) and
+prolongation (minmod-limited linear cells; faces split on the coarse faces by
+the 2D minmod profile, the interior faces from Toth & Roe's divergence and
+curl conditions).
+
+None of these re-types the operators.  They check what the definitions and the
+mathematics fix:
+  * restriction after prolongation is the identity (the children's offsets
+    cancel in the average, for cells and for the 4 faces of each coarse face);
+  * a linear cell field is prolonged to the exact fine averages, and restriction
+    of a linear fine field gives the exact coarse averages;
+  * a cell at a local extremum has flat children (minmod);
+  * any linear face field with zero divergence, whatever its curl, is prolonged
+    to the exact fine face averages, interior faces included (the field then
+    satisfies every condition, and the conditions have one solution);
+  * every fine cell has its parent's divergence, for arbitrary face data;
+    restricted faces have the mean divergence of the children;
+  * the operators commute with mirroring an axis and with cycling the axes
+    (a wrong weighting of the two outer planes in the curl estimate, or a
+    transposed index, breaks one of them);
+  * only the named octant of the coarse block is written by restriction.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+OCTANTS = list(itertools.product((0, 1), repeat=3))
+
+
+def geom(orc, n=(8, 6, 4), ng=2, ns=0):
+    cfg = orc.make_cfg(n, ng, (0.1, 0.1, 0.1), 5.0 / 3.0, nscalars=ns)
+    N = (n[2] + 2 * ng, n[1] + 2 * ng, n[0] + 2 * ng)
+    return cfg, N
+
+
+def random_block(N, nv, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((nv,) + N), rng.standard_normal((3,) + tuple(x + 1 for x in N))
+
+
+def oct_origin(n, o):
+    return tuple(o[d] * n[d] // 2 for d in range(3))
+
+
+def prolong(orc, cfg, cc, cb, o):
+    fc, fb = np.zeros_like(cc), np.zeros_like(cb)
+    orc.prolong(cfg, cc, cb, fc, fb, o)
+    return fc, fb
+
+
+def divergence(bf, ng, n, h):
+    """Flux divergence of every active cell of a face field (unit-free h)."""
+    a = bf[0][ng:ng + n[2], ng:ng + n[1], ng:ng + n[0] + 1]
+    b = bf[1][ng:ng + n[2], ng:ng + n[1] + 1, ng:ng + n[0]]
+    c = bf[2][ng:ng + n[2] + 1, ng:ng + n[1], ng:ng + n[0]]
+    return (np.diff(a, axis=2) + np.diff(b, axis=1) + np.diff(c, axis=0)) / h
+
+
+def octant_slices(n, ng, o, extra=(0, 0, 0)):
+    """(k, j, i) slices of octant o of the coarse block, with `extra` entries
+    appended along (x, y, z)."""
+    h = [n[d] // 2 for d in range(3)]
+    s = [slice(ng + o[d] * h[d], ng + o[d] * h[d] + h[d] + extra[d]) for d in range(3)]
+    return (s[2], s[1], s[0])
+
+
+@pytest.mark.parametrize("o", OCTANTS)
+def test_restriction_undoes_prolongation(orc, o):
+    n = (8, 6, 4)
+    cfg, N = geom(orc, n, ns=1)
+    cc, cb = random_block(N, 6, seed=11)
+    org = oct_origin(n, o)
+    fc, fb = prolong(orc, cfg, cc, cb, org)
+    rc, rb = np.full_like(cc, np.nan), np.full_like(cb, np.nan)
+    orc.restrict(cfg, fc, fb, rc, rb, org)
+    s = octant_slices(n, 2, o)
+    assert np.abs(rc[(slice(None),) + s] - cc[(slice(None),) + s]).max() <= 4e-15
+    for d in range(3):
+        e = [0, 0, 0]
+        e[d] = 1
+        sf = octant_slices(n, 2, o, e)
+        assert np.abs(rb[d][sf] - cb[d][sf]).max() <= 4e-15, d
+
+
+def test_restriction_writes_only_its_octant(orc):
+    n = (8, 6, 4)
+    cfg, N = geom(orc, n)
+    fc, fb = random_block(N, 5, seed=2)
+    rc, rb = np.full((5,) + N, 7.0), np.full((3,) + tuple(x + 1 for x in N), 7.0)
+    o = (1, 0, 1)
+    orc.restrict(cfg, fc, fb, rc, rb, oct_origin(n, o))
+    mask = np.zeros(N, bool)
+    mask[octant_slices(n, 2, o)] = True
+    assert np.all(rc[:, ~mask] == 7.0) and not np.any(rc[:, mask] == 7.0)
+    for d in range(3):
+        e = [0, 0, 0]
+        e[d] = 1
+        m = np.zeros(rb.shape[1:], bool)
+        m[octant_slices(n, 2, o, e)] = True
+        assert np.all(rb[d][~m] == 7.0) and not np.any(rb[d][m] == 7.0)
+
+
+def cell_centres(N, ng, h):
+    z, y, x = np.meshgrid(*[(np.arange(m) - ng + 0.5) * h for m in N], indexing="ij")
+    return x, y, z
+
+
+@pytest.mark.parametrize("o", OCTANTS)
+def test_linear_cells_prolong_exactly(orc, o):
+    """U = a + b.x: cell averages are centre values; both minmod arguments are
+    the same slope, so the children get U at their own centres."""
+    n = (8, 6, 4)
+    cfg, N = geom(orc, n)
+    coef = np.array([[0.3, 1.5, -2.0, 0.7], [-1.0, 0.2, 0.9, -0.4], [2.0, -0.3, 0.0, 1.1], [0.5, 0.0, 0.0, 0.0],
+                     [1.0, 3.0, 2.0, 1.0]])
+    xc, yc, zc = cell_centres(N, 2, 1.0)           # coarse spacing 1
+    cc = np.stack([c[0] + c[1] * xc + c[2] * yc + c[3] * zc for c in coef])
+    _, cb = random_block(N, 5, seed=1)
+    org = oct_origin(n, o)
+    fc, _ = prolong(orc, cfg, cc, cb, org)
+    xf, yf, zf = cell_centres(N, 2, 0.5)           # fine spacing 1/2 ...
+    off = [org[d] for d in range(3)]               # ... starting at the octant's corner
+    want = np.stack([c[0] + c[1] * (xf + off[0]) + c[2] * (yf + off[1]) + c[3] * (zf + off[2]) for c in coef])
+    a = (slice(None), slice(2, 2 + n[2]), slice(2, 2 + n[1]), slice(2, 2 + n[0]))
+    assert np.abs(fc[a] - want[a]).max() <= 1e-13
+
+
+def test_extremum_cell_has_flat_children(orc):
+    n = (8, 8, 8)
+    cfg, N = geom(orc, n)
+    cc = np.zeros((5,) + N)
+    cc[:, 4, 4, 4] = 1.0      # a peak in every variable, inside octant (0, 0, 0)
+    cc[:, 5, 4, 4] = 0.5      # one side rising, the other falling in z: minmod is 0
+    _, cb = random_block(N, 5, seed=1)
+    fc, _ = prolong(orc, cfg, cc, cb, (0, 0, 0))
+    # coarse cell (4, 4, 4) is active cell (2, 2, 2): fine cells 4..5 + ng
+    kids = fc[:, 6:8, 6:8, 6:8]
+    assert np.all(kids == 1.0)
+
+
+def linear_faces(N, ng, h, M, b0, shift=(0, 0, 0)):
+    """Face averages of the linear field B = b0 + M x (trace M = 0), with x
+    measured from the block's first active corner plus `shift`."""
+    F = tuple(m + 1 for m in N)
+    out = np.empty((3,) + F)
+    for d in range(3):
+        idx = np.meshgrid(*[np.arange(m) for m in F], indexing="ij")   # (k, j, i)
+        x = [(idx[2] - ng) * h, (idx[1] - ng) * h, (idx[0] - ng) * h]
+        x = [x[e] + (0.0 if e == d else 0.5 * h) + shift[e] for e in range(3)]   # face centres
+        out[d] = b0[d] + M[d][0] * x[0] + M[d][1] * x[1] + M[d][2] * x[2]
+    return out
+
+
+@pytest.mark.parametrize("o", OCTANTS)
+def test_divergence_free_linear_field_prolongs_exactly(orc, o):
+    n = (8, 6, 4)
+    cfg, N = geom(orc, n)
+    M = np.array([[0.7, -1.3, 0.4], [2.1, -0.2, 0.9], [-0.6, 1.7, -0.5]])   # curl != 0, trace 0
+    b0 = np.array([0.3, -0.8, 1.2])
+    cb = linear_faces(N, 2, 1.0, M, b0)
+    cc, _ = random_block(N, 5, seed=4)
+    org = oct_origin(n, o)
+    _, fb = prolong(orc, cfg, cc, cb, org)
+    want = linear_faces(N, 2, 0.5, M, b0, shift=org)
+    for d in range(3):
+        e = [0, 0, 0]
+        e[d] = 1
+        s = (slice(2, 2 + n[2] + e[2]), slice(2, 2 + n[1] + e[1]), slice(2, 2 + n[0] + e[0]))
+        assert np.abs(fb[d][s] - want[d][s]).max() <= 2e-14, d
+
+
+@pytest.mark.parametrize("o", OCTANTS[::3])
+def test_fine_cells_keep_the_parent_divergence(orc, o):
+    n = (8, 6, 4)
+    cfg, N = geom(orc, n)
+    cc, cb = random_block(N, 5, seed=8)     # arbitrary faces: nonzero divergence
+    org = oct_origin(n, o)
+    _, fb = prolong(orc, cfg, cc, cb, org)
+    df = divergence(fb, 2, n, 0.5)
+    dc = divergence(cb, 2, n, 1.0)
+    h = [n[d] // 2 for d in range(3)]
+    parent = dc[org[2]:org[2] + h[2], org[1]:org[1] + h[1], org[0]:org[0] + h[0]]
+    want = np.repeat(np.repeat(np.repeat(parent, 2, 0), 2, 1), 2, 2)
+    assert np.abs(df - want).max() <= 1e-13 * np.abs(dc).max()
+
+
+def test_divergence_free_smooth_field_stays_divergence_free(orc):
+    from paper_2005_06651_amd import inputs
+    b = inputs.smooth_random(n=(8, 8, 8), seed=6, ng=2)
+    cfg = orc.cfg_for(b)
+    cc = orc.prim2cons(cfg, b.prim, b.bface)
+    scale = np.abs(b.bface).max() / b.dx[0]
+    for o in OCTANTS:
+        _, fb = prolong(orc, cfg, cc, b.bface, oct_origin(b.n, o))
+        assert np.abs(divergence(fb, 2, b.n, b.dx[0] / 2)).max() <= 1e-12 * scale
+
+
+def test_restricted_faces_carry_the_mean_child_divergence(orc):
+    n = (8, 6, 4)
+    cfg, N = geom(orc, n)
+    fc, fb = random_block(N, 5, seed=9)
+    cc, cb = random_block(N, 5, seed=10)
+    o = (1, 1, 0)
+    org = oct_origin(n, o)
+    orc.restrict(cfg, fc, fb, cc, cb, org)
+    df = divergence(fb, 2, n, 0.5)
+    mean = df.reshape(n[2] // 2, 2, n[1] // 2, 2, n[0] // 2, 2).mean(axis=(1, 3, 5))
+    h = [n[d] // 2 for d in range(3)]
+    dc = divergence(cb, 2, n, 1.0)[org[2]:org[2] + h[2], org[1]:org[1] + h[1], org[0]:org[0] + h[0]]
+    assert np.abs(dc - mean).max() <= 1e-13 * np.abs(mean).max()
+
+
+def test_linear_fine_field_restricts_exactly(orc):
+    n = (8, 8, 8)
+    cfg, N = geom(orc, n)
+    M = np.array([[0.7, -1.3, 0.4], [2.1, -0.2, 0.9], [-0.6, 1.7, -0.5]])
+    b0 = np.array([0.3, -0.8, 1.2])
+    o = (0, 1, 1)
+    org = oct_origin(n, o)
+    fb = linear_faces(N, 2, 0.5, M, b0, shift=org)
+    xf, yf, zf = cell_centres(N, 2, 0.5)
+    fc = np.stack([1.0 + 0.5 * (xf + org[0]) - 2.0 * (yf + org[1]) + 0.25 * (zf + org[2])] * 5)
+    cc, cb = np.zeros((5,) + N), np.zeros((3,) + tuple(m + 1 for m in N))
+    orc.restrict(cfg, fc, fb, cc, cb, org)
+    xc, yc, zc = cell_centres(N, 2, 1.0)
+    wantc = 1.0 + 0.5 * xc - 2.0 * yc + 0.25 * zc
+    s = octant_slices(n, 2, o)
+    assert np.abs(cc[0][s] - wantc[s]).max() <= 1e-13
+    wantb = linear_faces(N, 2, 1.0, M, b0)
+    for d in range(3):
+        e = [0, 0, 0]
+        e[d] = 1
+        sf = octant_slices(n, 2, o, e)
+        assert np.abs(cb[d][sf] - wantb[d][sf]).max() <= 1e-13
+
+
+def mirror_x(cells, faces):
+    """Reflect x -> L - x: cells reverse along i; the x faces reverse over all
+    N1 + 1 entries and change sign; the y and z faces reverse like cells."""
+    c = cells[..., ::-1].copy()
+    f = np.zeros_like(faces)
+    f[0] = -faces[0][..., ::-1]
+    f[1][..., :-1] = faces[1][..., :-1][..., ::-1]
+    f[2][..., :-1] = faces[2][..., :-1][..., ::-1]
+    return c, f
+
+
+@pytest.mark.parametrize("o", [(0, 0, 0), (1, 0, 1)])
+def test_prolongation_commutes_with_a_mirror(orc, o):
+    n = (8, 6, 4)
+    cfg, N = geom(orc, n)
+    cc, cb = random_block(N, 5, seed=12)
+    org = oct_origin(n, o)
+    fc, fb = prolong(orc, cfg, cc, cb, org)
+    mc, mb = mirror_x(cc, cb)
+    morg = (n[0] // 2 - org[0],) + org[1:]
+    gc, gb = prolong(orc, cfg, mc, mb, morg)
+    wc, wb = mirror_x(fc, fb)
+    a = (slice(None), slice(2, 2 + n[2]), slice(2, 2 + n[1]), slice(2, 2 + n[0]))
+    assert np.abs(gc[a] - wc[a]).max() <= 1e-14
+    for d in range(3):
+        e = [0, 0, 0]
+        e[d] = 1
+        s = (slice(2, 2 + n[2] + e[2]), slice(2, 2 + n[1] + e[1]), slice(2, 2 + n[0] + e[0]))
+        assert np.abs(gb[d][s] - wb[d][s]).max() <= 1e-13, d
+
+
+def cycle(cells, faces):
+    """Relabel axes (x, y, z) -> (z, x, y): the new x is the old y, the new y
+    the old z, the new z the old x."""
+    c = np.ascontiguousarray(cells.transpose(0, 3, 1, 2))
+    f = np.stack([faces[1].transpose(2, 0, 1), faces[2].transpose(2, 0, 1), faces[0].transpose(2, 0, 1)])
+    return c, np.ascontiguousarray(f)
+
+
+@pytest.mark.parametrize("o", [(0, 0, 0), (1, 0, 1), (0, 1, 1)])
+def test_prolongation_commutes_with_cycling_the_axes(orc, o):
+    n = (8, 8, 8)
+    cfg, N = geom(orc, n)
+    cc, cb = random_block(N, 5, seed=13)
+    org = oct_origin(n, o)
+    fc, fb = prolong(orc, cfg, cc, cb, org)
+    rc, rb = cycle(cc, cb)
+    gc, gb = prolong(orc, cfg, rc, rb, (org[1], org[2], org[0]))
+    wc, wb = cycle(fc, fb)
+    a = (slice(None), slice(2, 10), slice(2, 10), slice(2, 10))
+    assert np.abs(gc[a] - wc[a]).max() <= 1e-14
+    for d in range(3):
+        e = [0, 0, 0]
+        e[d] = 1
+        s = (slice(2, 10 + e[2]), slice(2, 10 + e[1]), slice(2, 10 + e[0]))
+        assert np.abs(gb[d][s] - wb[d][s]).max() <= 1e-13, d
