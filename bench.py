@@ -52,10 +52,12 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle timing")
     p.add_argument("--cpu-steps", type=int, default=1, help="oracle steps in the CPU baseline sample")
     p.add_argument("--kernel-path", default="fused", choices=["fused", "unfused"])
-    p.add_argument("--workload", default="turbulence", choices=["turbulence", "batch", "adjoint", "blast", "mesh"],
+    p.add_argument("--workload", default="turbulence",
+                   choices=["turbulence", "batch", "adjoint", "blast", "mesh", "levels"],
                    help="turbulence: the 256^3 block (default); batch: 1024 uneven AMR-shaped blocks; "
                         "adjoint: gradient of a 128^3 x 64-step rollout (cost ratio and finite differences); "
-                        "blast: 512^3 RK3+PPM MHD blast; mesh: the 256^3 domain as a coupled mesh of equal blocks")
+                        "blast: 512^3 RK3+PPM MHD blast; mesh: the 256^3 domain as a coupled mesh of equal blocks; "
+                        "levels: restriction and prolongation of a 256^3 block")
     p.add_argument("--riemann", default="hlld", choices=["hlld", "hlle"], help="blast: Riemann solver")
     p.add_argument("--blast-n", type=int, default=512, help="blast: cells per side")
     p.add_argument("--blast-steps", type=int, default=200, help="blast: timed steps")
@@ -67,6 +69,7 @@ def parse():
     p.add_argument("--adj-no-fd", action="store_true", help="adjoint: skip the finite-difference check")
     p.add_argument("--adj-dir-kind", default="smooth", choices=["smooth", "white"],
                    help="adjoint: finite-difference directions: band-limited fields or white noise")
+    p.add_argument("--levels-n", type=int, default=256, help="levels: cells per side of the block")
     p.add_argument("--mesh-blocks", type=int, default=8, help="mesh: blocks per direction of the 256^3 domain")
     p.add_argument("--no-tune", action="store_true", help="batch: keep the default tile instead of autotuning")
     p.add_argument("--graph", action="store_true", help="replay each step from a hipGraph")
@@ -376,6 +379,70 @@ def bench_mesh(args):
     print(json.dumps(out))
 
 
+def bench_levels(args):
+    """Level operators of block refinement on one 256^3 block (the largest
+    single block; nghost 2, 5 conserved arrays): prolongation of each of the 8
+    octants of a coarse block onto a fine block, then restriction of the fine
+    block back onto each octant, timed with HIP events on the launch stream.
+    Algorithmic bytes per coarse cell of an octant (nv = 5 cell arrays, 3 face
+    components): prolongation reads nv cells and 3 faces and writes 8 nv fine
+    cells and 24 fine faces (12 on the coarse faces it owns, 12 inside), i.e.
+    (9 nv + 27) x 8 = 576 B; restriction reads 8 nv fine cells and 12 fine
+    faces and writes nv cells and 3 faces, (9 nv + 15) x 8 = 480 B."""
+    import torch
+
+    from paper_2005_06651_amd import athmhd
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n, ng, nv = args.levels_n, 2, 5
+    N = n + 2 * ng
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(args.seed)
+    cc = torch.randn((nv, N, N, N), dtype=torch.float64, device=dev, generator=gen)
+    cb = torch.randn((3, N + 1, N + 1, N + 1), dtype=torch.float64, device=dev, generator=gen)
+    fc, fb = torch.zeros_like(cc), torch.zeros_like(cb)
+    s = athmhd.Solver((n, n, n), ng, (1.0 / n,) * 3, 5.0 / 3.0)
+    octs = [(i & 1, (i >> 1) & 1, i >> 2) for i in range(8)]
+    stream = torch.cuda.current_stream()
+
+    def run(op, src, dst):
+        for o in octs:
+            op(*src, *dst, o, stream=stream)
+
+    for _ in range(args.warmup):
+        run(s.prolong, (cc, cb), (fc, fb))
+        run(s.restrict, (fc, fb), (cc, cb))
+    torch.cuda.synchronize()
+    ms = {}
+    t0 = time.perf_counter()
+    for name, op, src, dst in (("prolong", s.prolong, (cc, cb), (fc, fb)), ("restrict", s.restrict, (fc, fb), (cc, cb))):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            run(op, src, dst)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms[name] = e0.elapsed_time(e1) / (args.steps * 8)   # per launch (one octant)
+    elapsed = time.perf_counter() - t0
+    coarse = (n // 2) ** 3                                   # coarse cells per octant
+    bytes_p, bytes_r = coarse * (9 * nv + 27) * 8, coarse * (9 * nv + 15) * 8
+    gbs_p, gbs_r = bytes_p / (ms["prolong"] * 1e-3) / 1e9, bytes_r / (ms["restrict"] * 1e-3) / 1e9
+    out = {
+        "metric": "fine cells prolonged per second, FP64 MHD level operators (Sec. 2.1.5), 1 MI355X",
+        "value": 8 * coarse / (ms["prolong"] * 1e-3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"prolongation of the 8 octants of a {n}^3 block (nghost 2, 5 cell arrays, "
+                               "face field) onto a fine block, then restriction back, seeded normal values",
+                   "octant_coarse_cells": coarse, "seed": args.seed},
+        "roofline": {"bound": "hbm", "achieved": gbs_p, "peak": 8000.0, "unit": "GB/s", "frac": gbs_p / 8000.0,
+                     "traffic": None, "kernel": "k_prolong", "ms_per_launch": ms["prolong"]},
+        "restrict": {"ms_per_launch": ms["restrict"], "GB/s": gbs_r, "frac": gbs_r / 8000.0,
+                     "cells_per_s": coarse / (ms["restrict"] * 1e-3)},
+    }
+    print(json.dumps(out))
+
+
 def bench_blast(args):
     """MHD blast on the 512^3 periodic unit cube (nghost 3, RK3 + PPM + HLLD or
     HLLE + CT, rho = 1, p = 0.1, p = 10 inside r < 0.1 around a seeded centre,
@@ -492,6 +559,9 @@ def main():
         return
     if args.workload == "mesh":
         bench_mesh(args)
+        return
+    if args.workload == "levels":
+        bench_levels(args)
         return
     if args.copy_calibration:
         a = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB

@@ -287,6 +287,40 @@ ATHMHD_API int athmhd_set_graph(athmhd_t h, int enable);
  * may be NULL). */
 ATHMHD_API int athmhd_profile(athmhd_t h, int enable, double* total_ms, int* launches);
 
+/* Level operators of block refinement (Sec. 2.1.5), between a coarse block
+ * and the fine block that refines its octant (o1, o2, o3) (each 0 or 1: the
+ * lower or upper half of the active cells along that direction).  Both are
+ * single blocks of this handle's shape (athmhd_create handles only, else
+ * ATHMHD_EUNSUP; n1, n2, n3 even, else ATHMHD_EINVAL), laid out as for
+ * athmhd_step, device arrays, all four distinct; the fine block's cells are
+ * half as wide.  Every cell array (5 + nscalars) is treated alike; for new
+ * blocks these are the conserved variables, as the method prescribes.
+ *
+ * athmhd_restrict: writes the octant's active coarse cells with the volume
+ * average of their 8 fine cells, and every coarse face of the octant (its
+ * upper boundary faces included) with the area average of its 4 fine faces.
+ * Nothing else of the coarse block is touched; ghost entries of the fine
+ * block are not read.
+ *
+ * athmhd_prolong: writes every active fine cell and face (upper boundary
+ * faces included); fine ghost entries are not touched.  Reads the octant's
+ * coarse cells and faces and one layer of their neighbours, ghosts included,
+ * so fill the coarse block's ghosts first.  Cells: the coarse value plus the
+ * minmod-limited slope along each direction times the child's offset of
+ * 1/4 coarse cell.  Faces (Toth & Roe 2002): each coarse face split into 4 by
+ * its 2D minmod-limited linear profile, then the 12 faces inside each coarse
+ * cell such that every fine cell has the coarse cell's divergence and the
+ * curl at each interior edge equals the mean tangential difference over the
+ * two outer faces parallel to it.  The fine field of a divergence-free coarse
+ * field is then divergence-free, and linear fields are reproduced exactly.
+ * Needs cubic cells (dx1 = dx2 = dx3, else ATHMHD_EUNSUP).
+ *
+ * Asynchronous on `stream`. */
+ATHMHD_API int athmhd_restrict(athmhd_t h, const double* fine_cons, const double* fine_bface, double* coarse_cons,
+                               double* coarse_bface, int o1, int o2, int o3, void* stream);
+ATHMHD_API int athmhd_prolong(athmhd_t h, const double* coarse_cons, const double* coarse_bface, double* fine_cons,
+                              double* fine_bface, int o1, int o2, int o3, void* stream);
+
 /* Text of the last error recorded on `h` (or of the last failed create when
  * h is NULL).  Valid until the next call on the same handle. */
 ATHMHD_API const char* athmhd_last_error(athmhd_t h);

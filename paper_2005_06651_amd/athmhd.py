@@ -22,7 +22,7 @@ EXPORTED = ["athmhd_version", "athmhd_create", "athmhd_create_batch", "athmhd_ba
             "athmhd_batch_set_tile", "athmhd_batch_tune", "athmhd_set_graph", "athmhd_step", "athmhd_newdt",
             "athmhd_prim2cons", "athmhd_fill_ghosts", "athmhd_profile", "athmhd_last_error", "athmhd_destroy",
             "athmhd_step_vjp", "athmhd_prim2cons_vjp", "athmhd_set_floors", "athmhd_floor_count",
-            "athmhd_step_stages", "athmhd_create_mesh"]
+            "athmhd_step_stages", "athmhd_create_mesh", "athmhd_restrict", "athmhd_prolong"]
 BATCH_TILES = [(16, 12), (12, 16), (14, 14), (16, 8)]  # active columns of the batch tile candidates
 
 
@@ -76,6 +76,8 @@ def lib():
         L.athmhd_floor_count.argtypes = [vp, C.POINTER(C.c_longlong), vp]
         L.athmhd_prim2cons_vjp.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int, vp]
         L.athmhd_profile.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]
+        L.athmhd_restrict.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_int, C.c_int, vp]
+        L.athmhd_prolong.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_int, C.c_int, vp]
         L.athmhd_last_error.argtypes = [vp]
         L.athmhd_last_error.restype = C.c_char_p
         L.athmhd_destroy.argtypes = [vp]
@@ -183,6 +185,26 @@ class Solver:
     def fill_ghosts(self, cons, bface, stream=None) -> None:
         pc, pb, nb = self._pair(cons, bface)
         _check(lib().athmhd_fill_ghosts(self._h, pc, pb, nb, _stream(stream)), self._h)
+
+    def _one_block(self, cons, bface):
+        pc, pb, nb = self._pair(cons, bface)
+        if nb != 1:
+            raise ValueError("level operators take one block")
+        return pc, pb
+
+    def restrict(self, fine_cons, fine_bface, coarse_cons, coarse_bface, octant, stream=None) -> None:
+        """Restrict the fine block onto octant (o1, o2, o3) of the coarse block, in place."""
+        fc, fb = self._one_block(fine_cons, fine_bface)
+        cc, cb = self._one_block(coarse_cons, coarse_bface)
+        o = [int(x) for x in octant]
+        _check(lib().athmhd_restrict(self._h, fc, fb, cc, cb, *o, _stream(stream)), self._h)
+
+    def prolong(self, coarse_cons, coarse_bface, fine_cons, fine_bface, octant, stream=None) -> None:
+        """Prolong octant (o1, o2, o3) of the coarse block onto the fine block's active cells and faces."""
+        cc, cb = self._one_block(coarse_cons, coarse_bface)
+        fc, fb = self._one_block(fine_cons, fine_bface)
+        o = [int(x) for x in octant]
+        _check(lib().athmhd_prolong(self._h, cc, cb, fc, fb, *o, _stream(stream)), self._h)
 
     @property
     def extra_stages(self) -> int:

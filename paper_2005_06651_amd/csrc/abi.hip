@@ -455,7 +455,7 @@ int alloc_adjoint(athmhd_t h) {
 
 extern "C" {
 
-int athmhd_version(void) { return 105; }
+int athmhd_version(void) { return 106; }
 
 int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
   if (!out) return fail(nullptr, ATHMHD_EINVAL, "out is NULL");
@@ -851,6 +851,51 @@ int athmhd_step_vjp(athmhd_t h, const double* cons_n, const double* bface_n, dou
   }
   e = launch_adj_scatter(g, A, Z, g_cons_np1, g_bface_np1, g_cons_n, g_bface_n, nblocks, s);
   return e == hipSuccess ? ATHMHD_OK : hip_fail(h, e, "vjp scatter launch");
+}
+
+namespace {
+
+// Shared checks of the two level operators: a uniform handle, even block
+// sizes, an octant of 0/1 flags and four distinct arrays.
+int check_level(athmhd_t h, const void* a, const void* b, const void* c, const void* d, const int oct[3],
+                bool cubic) {
+  if (!h) return ATHMHD_EINVAL;
+  if (h->batch || h->mesh) return fail(h, ATHMHD_EUNSUP, "level operators act on athmhd_create handles");
+  if (!a || !b || !c || !d) return fail(h, ATHMHD_EINVAL, "NULL array argument");
+  const void* p[4] = {a, b, c, d};
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j)
+      if (p[i] == p[j]) return fail(h, ATHMHD_EINVAL, "the four arrays must be distinct");
+  const Geo& g = h->g;
+  if (g.n1 % 2 || g.n2 % 2 || g.n3 % 2)
+    return fail(h, ATHMHD_EINVAL, "block sizes must be even (got %d x %d x %d)", g.n1, g.n2, g.n3);
+  for (int k = 0; k < 3; ++k)
+    if (oct[k] != 0 && oct[k] != 1) return fail(h, ATHMHD_EINVAL, "octant flags must be 0 or 1 (got %d)", oct[k]);
+  if (cubic) {
+    const double lo = std::min(g.dx1, std::min(g.dx2, g.dx3)), hi = std::max(g.dx1, std::max(g.dx2, g.dx3));
+    if (hi - lo > 1e-12 * hi) return fail(h, ATHMHD_EUNSUP, "face prolongation needs cubic cells (dx1 = dx2 = dx3)");
+  }
+  return ATHMHD_OK;
+}
+
+}  // namespace
+
+int athmhd_restrict(athmhd_t h, const double* fine_cons, const double* fine_bface, double* coarse_cons,
+                    double* coarse_bface, int o1, int o2, int o3, void* stream) {
+  const int oct[3] = {o1, o2, o3};
+  int rc = check_level(h, fine_cons, fine_bface, coarse_cons, coarse_bface, oct, false);
+  if (rc) return rc;
+  hipError_t e = launch_restrict(h->g, oct, fine_cons, fine_bface, coarse_cons, coarse_bface, (hipStream_t)stream);
+  return e == hipSuccess ? ATHMHD_OK : hip_fail(h, e, "restrict launch");
+}
+
+int athmhd_prolong(athmhd_t h, const double* coarse_cons, const double* coarse_bface, double* fine_cons,
+                   double* fine_bface, int o1, int o2, int o3, void* stream) {
+  const int oct[3] = {o1, o2, o3};
+  int rc = check_level(h, coarse_cons, coarse_bface, fine_cons, fine_bface, oct, true);
+  if (rc) return rc;
+  hipError_t e = launch_prolong(h->g, oct, coarse_cons, coarse_bface, fine_cons, fine_bface, (hipStream_t)stream);
+  return e == hipSuccess ? ATHMHD_OK : hip_fail(h, e, "prolong launch");
 }
 
 int athmhd_prim2cons_vjp(athmhd_t h, const double* prim, const double* bface, const double* g_cons, double* g_prim,

@@ -1,0 +1,247 @@
+// Level operators of block refinement (Sec. 2.1.5): restriction of a fine
+// block onto one octant of its coarse parent, and prolongation of that octant
+// onto the fine block.  Both blocks have the same shape (n1 x n2 x n3 active
+// cells, ng ghosts, 5 + ns cell arrays); the fine cells are half as wide, and
+// octant (o1, o2, o3) of the coarse block covers active coarse cells
+// [o_d n_d / 2, (o_d + 1) n_d / 2) along each direction d.
+//
+// One thread per coarse cell of the octant (plus one layer beyond its upper
+// side for the faces there).  These run once per refinement or derefinement
+// of a block, not per step: plain HBM-bound kernels, rows of threads along x1
+// so that the fine reads and writes of neighbouring threads are contiguous.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace athmhd {
+namespace {
+
+constexpr int kAmrThreads = 256;
+
+struct OctArgs {
+  Geo g;
+  int h[3];  // octant extent n_d / 2
+  int o[3];  // first active coarse cell of the octant, o_d n_d / 2
+};
+
+__device__ __forceinline__ double minmod(double a, double b) {
+  if (a > 0.0 && b > 0.0) return fmin(a, b);
+  if (a < 0.0 && b < 0.0) return fmax(a, b);
+  return 0.0;
+}
+
+// flat index of the cell / face at p = (x1, x2, x3)
+__device__ __forceinline__ int cidx(const Geo& g, const int p[3]) { return g.c(p[0], p[1], p[2]); }
+__device__ __forceinline__ int fidx(const Geo& g, const int p[3]) { return g.f(p[0], p[1], p[2]); }
+
+// Restriction: volume average of the 8 fine cells of each coarse cell (every
+// cell array), area average of the 4 fine faces on each coarse face of the
+// octant, upper faces included.
+__global__ void __launch_bounds__(kAmrThreads)
+    k_restrict(OctArgs A, const double* __restrict__ fc, const double* __restrict__ fb, double* __restrict__ cc,
+               double* __restrict__ cb) {
+  const Geo& g = A.g;
+  const int e1 = A.h[0] + 1, e2 = A.h[1] + 1, e3 = A.h[2] + 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= e1 * e2 * e3) return;
+  const int q[3] = {t % e1, (t / e1) % e2, t / (e1 * e2)};
+  const int ng = g.ng;
+  const bool cell = q[0] < A.h[0] && q[1] < A.h[1] && q[2] < A.h[2];
+  const int C[3] = {ng + A.o[0] + q[0], ng + A.o[1] + q[1], ng + A.o[2] + q[2]};
+  const int F[3] = {ng + 2 * q[0], ng + 2 * q[1], ng + 2 * q[2]};
+  if (cell) {
+    const int nv = 5 + g.ns;
+    for (int v = 0; v < nv; ++v) {
+      const double* src = fc + v * g.cvar;
+      double s = 0.0;
+      for (int s3 = 0; s3 < 2; ++s3)
+        for (int s2 = 0; s2 < 2; ++s2)
+          for (int s1 = 0; s1 < 2; ++s1) s += src[g.c(F[0] + s1, F[1] + s2, F[2] + s3)];
+      cc[v * g.cvar + cidx(g, C)] = s / 8.0;
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+    if (q[t1] >= A.h[t1] || q[t2] >= A.h[t2]) continue;
+    const double* src = fb + d * g.fvar;
+    double s = 0.0;
+    for (int u = 0; u < 2; ++u)
+      for (int w = 0; w < 2; ++w) {
+        int p[3];
+        p[d] = F[d];
+        p[t1] = F[t1] + u;
+        p[t2] = F[t2] + w;
+        s += src[fidx(g, p)];
+      }
+    cb[d * g.fvar + fidx(g, C)] = s / 4.0;
+  }
+}
+
+// The 4 fine values of the coarse face of component d at coarse index C:
+// the face value plus the minmod-limited slopes along its two transverse
+// directions (t1, t2) = (d + 1, d + 2) times the quarter offsets, out[p][q]
+// with p the half along t1, q the half along t2.
+__device__ __forceinline__ void split_face(const Geo& g, const double* cb, int d, const int C[3], double out[2][2]) {
+  const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  const double* b = cb + d * g.fvar;
+  const double B = b[fidx(g, C)];
+  double sl[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int t = e == 0 ? t1 : t2;
+    int m[3] = {C[0], C[1], C[2]}, p[3] = {C[0], C[1], C[2]};
+    m[t] -= 1;
+    p[t] += 1;
+    sl[e] = minmod(B - b[fidx(g, m)], b[fidx(g, p)] - B);
+  }
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) out[p][q] = B + 0.25 * ((2 * p - 1) * sl[0] + (2 * q - 1) * sl[1]);
+}
+
+// Prolongation.  Cells: U_C plus the minmod-limited slope along each
+// direction times the child's offset +-1/4.  Faces: every coarse face of the
+// octant split into 4 by split_face; the 12 faces inside each coarse cell in
+// closed form.  Those are the one solution of Toth & Roe's conditions (every
+// fine cell has the coarse cell's divergence; the curl at each of the 6
+// interior edges equals the mean of the tangential differences on the two
+// outer faces parallel to it).  Solved once by hand, with O_d[S][p][q] the
+// outer fine value of component d on side S in {0, 1} and halves (p, q) along
+// (d + 1, d + 2), s(x) = 2 x - 1, and w = 3/16 for r equal to the face's own
+// half, 1/16 otherwise:
+//   B_d(p, q) = (O_d[0][p][q] + O_d[1][p][q]) / 2
+//             + sum_{S,i,r} s(S) s(i) [ w(r, q) O_{d+1}[S][r][i] + w(r, p) O_{d+2}[S][i][r] ]
+// (component d + 1 has halves along (d + 2, d), component d + 2 along
+// (d, d + 1); i is the half along d).  Each cell thread recomputes the
+// splits of its upper faces; only the thread that owns a face as its lower
+// face writes it, so every fine face is written once.
+__global__ void __launch_bounds__(kAmrThreads)
+    k_prolong(OctArgs A, const double* __restrict__ cc, const double* __restrict__ cb, double* __restrict__ fc,
+              double* __restrict__ fb) {
+  const Geo& g = A.g;
+  const int e1 = A.h[0] + 1, e2 = A.h[1] + 1, e3 = A.h[2] + 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= e1 * e2 * e3) return;
+  const int q[3] = {t % e1, (t / e1) % e2, t / (e1 * e2)};
+  const int ng = g.ng;
+  const bool cell = q[0] < A.h[0] && q[1] < A.h[1] && q[2] < A.h[2];
+  const int C[3] = {ng + A.o[0] + q[0], ng + A.o[1] + q[1], ng + A.o[2] + q[2]};
+  const int F[3] = {ng + 2 * q[0], ng + 2 * q[1], ng + 2 * q[2]};
+
+  if (cell) {
+    const int nv = 5 + g.ns;
+    for (int v = 0; v < nv; ++v) {
+      const double* src = cc + v * g.cvar;
+      const double u0 = src[cidx(g, C)];
+      double sl[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        int m[3] = {C[0], C[1], C[2]}, p[3] = {C[0], C[1], C[2]};
+        m[d] -= 1;
+        p[d] += 1;
+        sl[d] = minmod(u0 - src[cidx(g, m)], src[cidx(g, p)] - u0);
+      }
+      double* dst = fc + v * g.cvar;
+#pragma unroll
+      for (int s3 = 0; s3 < 2; ++s3)
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+          for (int s1 = 0; s1 < 2; ++s1)
+            dst[g.c(F[0] + s1, F[1] + s2, F[2] + s3)] =
+                u0 + 0.25 * ((2 * s1 - 1) * sl[0] + (2 * s2 - 1) * sl[1] + (2 * s3 - 1) * sl[2]);
+    }
+  }
+
+  // outer faces: O[d][S][p][q]; the lower one (S = 0) is this thread's own
+  double O[3][2][2][2];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+    if (q[t1] >= A.h[t1] || q[t2] >= A.h[t2]) continue;
+    split_face(g, cb, d, C, O[d][0]);
+    double* dst = fb + d * g.fvar;
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        int x[3];
+        x[d] = F[d];
+        x[t1] = F[t1] + p;
+        x[t2] = F[t2] + r;
+        dst[fidx(g, x)] = O[d][0][p][r];
+      }
+    if (cell) {
+      int Cu[3] = {C[0], C[1], C[2]};
+      Cu[d] += 1;
+      split_face(g, cb, d, Cu, O[d][1]);
+    }
+  }
+  if (!cell) return;
+
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+    double* dst = fb + d * g.fvar;
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        double v = 0.5 * (O[d][0][p][r] + O[d][1][p][r]);
+        double cross = 0.0;
+#pragma unroll
+        for (int S = 0; S < 2; ++S)
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            const double sg = (S == i) ? 1.0 : -1.0;  // s(S) s(i)
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+              const double w1 = (k == r) ? 0.1875 : 0.0625;
+              const double w2 = (k == p) ? 0.1875 : 0.0625;
+              cross += sg * (w1 * O[d1][S][k][i] + w2 * O[d2][S][i][k]);
+            }
+          }
+        int x[3];
+        x[d] = F[d] + 1;
+        x[d1] = F[d1] + p;
+        x[d2] = F[d2] + r;
+        dst[fidx(g, x)] = v + cross;
+      }
+  }
+}
+
+OctArgs oct_args(const Geo& g, const int oct[3]) {
+  OctArgs A;
+  A.g = g;
+  const int n[3] = {g.n1, g.n2, g.n3};
+  for (int d = 0; d < 3; ++d) {
+    A.h[d] = n[d] / 2;
+    A.o[d] = oct[d] * A.h[d];
+  }
+  return A;
+}
+
+int grid_of(const OctArgs& A) {
+  const long pts = (long)(A.h[0] + 1) * (A.h[1] + 1) * (A.h[2] + 1);
+  return (int)((pts + kAmrThreads - 1) / kAmrThreads);
+}
+
+}  // namespace
+
+hipError_t launch_restrict(const Geo& g, const int oct[3], const double* fc, const double* fb, double* cc, double* cb,
+                           hipStream_t s) {
+  const OctArgs A = oct_args(g, oct);
+  hipLaunchKernelGGL(k_restrict, dim3(grid_of(A)), dim3(kAmrThreads), 0, s, A, fc, fb, cc, cb);
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong(const Geo& g, const int oct[3], const double* cc, const double* cb, double* fc, double* fb,
+                          hipStream_t s) {
+  const OctArgs A = oct_args(g, oct);
+  hipLaunchKernelGGL(k_prolong, dim3(grid_of(A)), dim3(kAmrThreads), 0, s, A, cc, cb, fc, fb);
+  return hipGetLastError();
+}
+
+}  // namespace athmhd

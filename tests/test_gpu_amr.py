@@ -1,0 +1,241 @@
+"""Level operators of block refinement on the GPU (Sec. 2.1.5):
+athmhd_restrict and athmhd_prolong against the oracle, element by element.
+
+Restriction and the cell and outer-face prolongation add the same values in
+the same order on both sides, so they must agree bitwise; the faces inside
+each coarse cell come from a closed form on the GPU and from a least-squares
+solve of Toth & Roe's conditions in the oracle, so those agree to a tolerance
+of 1e-14 of the field's scale (a few roundings of sums of 25 terms with
+weights up to 1/2).  Every octant, several block shapes (ragged: unequal and
+non-multiple-of-tile sizes, 2 and 3 ghosts, scalar rows), the entries that
+must stay untouched, round trip and divergence properties on the device, a
+128^3 block, and the error paths.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from paper_2005_06651_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+OCTANTS = list(itertools.product((0, 1), repeat=3))
+FACE_TOL = 1e-14
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def athmhd():
+    from paper_2005_06651_amd import athmhd as A
+    A.lib()
+    return A
+
+
+def shapes(n, ng):
+    N = (n[2] + 2 * ng, n[1] + 2 * ng, n[0] + 2 * ng)
+    return N, tuple(x + 1 for x in N)
+
+
+def random_pair(N, F, nv, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((nv,) + N), rng.standard_normal((3,) + F)
+
+
+def solver(athmhd, n, ng, ns=0, dx=0.1):
+    return athmhd.Solver(n, ng, (dx, dx, dx), 5.0 / 3.0, nscalars=ns)
+
+
+def dev(torch, d, x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(d)
+
+
+def active_faces(n, ng, d):
+    e = [0, 0, 0]
+    e[d] = 1
+    return (slice(ng, ng + n[2] + e[2]), slice(ng, ng + n[1] + e[1]), slice(ng, ng + n[0] + e[0]))
+
+
+def octant_mask_cells(N, n, ng, o):
+    m = np.zeros(N, bool)
+    h = [x // 2 for x in n]
+    m[tuple(slice(ng + o[d] * h[d], ng + (o[d] + 1) * h[d]) for d in (2, 1, 0))] = True
+    return m
+
+
+def octant_mask_faces(F, n, ng, o, d):
+    m = np.zeros(F, bool)
+    h = [x // 2 for x in n]
+    e = [0, 0, 0]
+    e[d] = 1
+    m[tuple(slice(ng + o[k] * h[k], ng + (o[k] + 1) * h[k] + e[k]) for k in (2, 1, 0))] = True
+    return m
+
+
+CASES = [((8, 6, 4), 2, 0), ((10, 14, 6), 3, 1), ((32, 24, 16), 2, 2)]
+
+
+@pytest.mark.parametrize("n,ng,ns", CASES)
+@pytest.mark.parametrize("o", OCTANTS)
+def test_restrict_matches_the_oracle_bitwise(torch_dev, athmhd, orc, n, ng, ns, o):
+    torch, d = torch_dev
+    nv = 5 + ns
+    N, F = shapes(n, ng)
+    fc, fb = random_pair(N, F, nv, seed=21)
+    cc, cb = random_pair(N, F, nv, seed=22)
+    cfg = orc.make_cfg(n, ng, (0.1,) * 3, 5.0 / 3.0, nscalars=ns)
+    want_c, want_b = cc.copy(), cb.copy()
+    orc.restrict(cfg, fc, fb, want_c, want_b, tuple(o[k] * n[k] // 2 for k in range(3)))
+    s = solver(athmhd, n, ng, ns)
+    gc, gb = dev(torch, d, cc), dev(torch, d, cb)
+    s.restrict(dev(torch, d, fc), dev(torch, d, fb), gc, gb, o)
+    torch.cuda.synchronize()
+    got_c, got_b = gc.cpu().numpy(), gb.cpu().numpy()
+    assert np.array_equal(got_c, want_c)
+    assert np.array_equal(got_b, want_b)
+    # and only the octant changed
+    m = octant_mask_cells(N, n, ng, o)
+    assert np.array_equal(got_c[:, ~m], cc[:, ~m])
+    for k in range(3):
+        mf = octant_mask_faces(F, n, ng, o, k)
+        assert np.array_equal(got_b[k][~mf], cb[k][~mf])
+
+
+def check_prolong(got_c, got_b, want_c, want_b, fc0, fb0, n, ng):
+    """Cells bitwise everywhere (ghosts untouched); faces: the outer ones
+    (even offsets along their own direction) bitwise, interior ones within
+    FACE_TOL of the field scale, ghost entries untouched."""
+    assert np.array_equal(got_c, want_c)
+    scale = np.abs(want_b).max()
+    for k in range(3):
+        a = active_faces(n, ng, k)
+        g, w = got_b[k][a], want_b[k][a]
+        idx = [slice(None)] * 3
+        idx[2 - k] = slice(0, None, 2)          # outer faces: even fine index along k
+        assert np.array_equal(g[tuple(idx)], w[tuple(idx)]), k
+        assert np.abs(g - w).max() <= FACE_TOL * scale, (k, np.abs(g - w).max())
+        mask = np.ones(got_b.shape[1:], bool)
+        mask[a] = False
+        assert np.array_equal(got_b[k][mask], fb0[k][mask])
+
+
+@pytest.mark.parametrize("n,ng,ns", CASES)
+@pytest.mark.parametrize("o", OCTANTS)
+def test_prolong_matches_the_oracle(torch_dev, athmhd, orc, n, ng, ns, o):
+    torch, d = torch_dev
+    nv = 5 + ns
+    N, F = shapes(n, ng)
+    cc, cb = random_pair(N, F, nv, seed=31)
+    fc0, fb0 = random_pair(N, F, nv, seed=32)
+    cfg = orc.make_cfg(n, ng, (0.1,) * 3, 5.0 / 3.0, nscalars=ns)
+    want_c, want_b = fc0.copy(), fb0.copy()
+    orc.prolong(cfg, cc, cb, want_c, want_b, tuple(o[k] * n[k] // 2 for k in range(3)))
+    s = solver(athmhd, n, ng, ns)
+    gc, gb = dev(torch, d, fc0), dev(torch, d, fb0)
+    s.prolong(dev(torch, d, cc), dev(torch, d, cb), gc, gb, o)
+    torch.cuda.synchronize()
+    check_prolong(gc.cpu().numpy(), gb.cpu().numpy(), want_c, want_b, fc0, fb0, n, ng)
+
+
+def test_prolong_of_a_smooth_state_matches_the_oracle(torch_dev, athmhd, orc):
+    """A physical state (divergence-free faces from a vector potential,
+    conserved variables): the limiter takes both branches and zero slopes."""
+    torch, d = torch_dev
+    b = inputs.smooth_random(n=(16, 16, 16), seed=4, ng=2)
+    cfg = orc.cfg_for(b)
+    cc = orc.prim2cons(cfg, b.prim, b.bface)
+    s = athmhd.Solver(b.n, b.ng, b.dx, b.gamma)
+    for o in OCTANTS:
+        want_c, want_b = np.zeros_like(cc), np.zeros_like(b.bface)
+        orc.prolong(cfg, cc, b.bface, want_c, want_b, tuple(o[k] * 8 for k in range(3)))
+        gc, gb = torch.zeros_like(dev(torch, d, cc)), torch.zeros_like(dev(torch, d, b.bface))
+        s.prolong(dev(torch, d, cc), dev(torch, d, b.bface), gc, gb, o)
+        torch.cuda.synchronize()
+        check_prolong(gc.cpu().numpy(), gb.cpu().numpy(), want_c, want_b, want_c, want_b, b.n, b.ng)
+        div = inputs.divb_metric(gb.cpu().numpy(), b.n, b.ng, tuple(x / 2 for x in b.dx))
+        assert div <= 1e-12, div
+
+
+def test_round_trip_on_the_device(torch_dev, athmhd):
+    """restrict(prolong(U)) gives back the octant of U, to rounding."""
+    torch, d = torch_dev
+    n, ng = (24, 16, 12), 2
+    N, F = shapes(n, ng)
+    cc, cb = random_pair(N, F, 6, seed=41)
+    s = solver(athmhd, n, ng, 1)
+    gcc, gcb = dev(torch, d, cc), dev(torch, d, cb)
+    for o in OCTANTS:
+        fc, fb = torch.zeros_like(gcc), torch.zeros_like(gcb)
+        back_c, back_b = torch.full_like(gcc, np.nan), torch.full_like(gcb, np.nan)
+        s.prolong(gcc, gcb, fc, fb, o)
+        s.restrict(fc, fb, back_c, back_b, o)
+        torch.cuda.synchronize()
+        m = octant_mask_cells(N, n, ng, o)
+        bc = back_c.cpu().numpy()
+        assert np.abs(bc[:, m] - cc[:, m]).max() <= 4e-15
+        bb = back_b.cpu().numpy()
+        for k in range(3):
+            mf = octant_mask_faces(F, n, ng, o, k)
+            assert np.abs(bb[k][mf] - cb[k][mf]).max() <= 4e-15
+
+
+def test_large_block_prolong_and_restrict(torch_dev, athmhd, orc):
+    """A 128^3 block (the size of one octant of the 256^3 domain): full
+    comparison against the oracle for one octant of each operator."""
+    torch, d = torch_dev
+    n, ng = (128, 128, 128), 2
+    N, F = shapes(n, ng)
+    cc, cb = random_pair(N, F, 5, seed=51)
+    cfg = orc.make_cfg(n, ng, (0.1,) * 3, 5.0 / 3.0)
+    o = (1, 0, 1)
+    org = tuple(o[k] * 64 for k in range(3))
+    want_c, want_b = np.zeros_like(cc), np.zeros_like(cb)
+    orc.prolong(cfg, cc, cb, want_c, want_b, org)
+    s = solver(athmhd, n, ng)
+    gc, gb = torch.zeros(cc.shape, dtype=torch.float64, device=d), torch.zeros(cb.shape, dtype=torch.float64, device=d)
+    s.prolong(dev(torch, d, cc), dev(torch, d, cb), gc, gb, o)
+    torch.cuda.synchronize()
+    check_prolong(gc.cpu().numpy(), gb.cpu().numpy(), want_c, want_b, want_c, want_b, n, ng)
+    rc, rb = cc.copy(), cb.copy()
+    orc.restrict(cfg, want_c, want_b, rc, rb, org)
+    g2c, g2b = dev(torch, d, cc), dev(torch, d, cb)
+    s.restrict(gc, gb, g2c, g2b, o)
+    torch.cuda.synchronize()
+    # restriction of slightly different interior faces is not read: cells and
+    # the coarse faces come from outer faces only, which agree bitwise
+    assert np.array_equal(g2c.cpu().numpy(), rc)
+    assert np.array_equal(g2b.cpu().numpy(), rb)
+
+
+def test_level_operator_errors(torch_dev, athmhd):
+    torch, d = torch_dev
+    n, ng = (8, 8, 8), 2
+    N, F = shapes(n, ng)
+    a = [torch.zeros((5,) + N, dtype=torch.float64, device=d) for _ in range(2)]
+    b = [torch.zeros((3,) + F, dtype=torch.float64, device=d) for _ in range(2)]
+    s = solver(athmhd, n, ng)
+    with pytest.raises(athmhd.AthmhdError) as e:
+        s.prolong(a[0], b[0], a[1], b[1], (0, 2, 0))
+    assert e.value.code == athmhd.EINVAL
+    with pytest.raises(athmhd.AthmhdError) as e:
+        s.restrict(a[0], b[0], a[0], b[1], (0, 0, 0))
+    assert e.value.code == athmhd.EINVAL
+    odd = athmhd.Solver((8, 7, 8), ng, (0.1,) * 3, 5.0 / 3.0)
+    No, Fo = shapes((8, 7, 8), ng)
+    ao = [torch.zeros((5,) + No, dtype=torch.float64, device=d) for _ in range(2)]
+    bo = [torch.zeros((3,) + Fo, dtype=torch.float64, device=d) for _ in range(2)]
+    with pytest.raises(athmhd.AthmhdError) as e:
+        odd.restrict(ao[0], bo[0], ao[1], bo[1], (0, 0, 0))
+    assert e.value.code == athmhd.EINVAL
+    slab = athmhd.Solver(n, ng, (0.1, 0.2, 0.1), 5.0 / 3.0)
+    with pytest.raises(athmhd.AthmhdError) as e:
+        slab.prolong(a[0], b[0], a[1], b[1], (0, 0, 0))
+    assert e.value.code == athmhd.EUNSUP
+    slab.restrict(a[0], b[0], a[1], b[1], (0, 0, 0))   # restriction needs no cubic cells
+    torch.cuda.synchronize()
