@@ -40,6 +40,13 @@ ALG_FLOPS_PER_ZONE_CYCLE = 2560.0
 STAGE_TRAFFIC = {"bytes_per_launch": 3.468e+09, "fetch_bytes_per_launch": 2.295e+09,
                  "write_bytes_per_launch": 1.172e+09, "fetch_scale": 1.9999, "write_scale": 1.0000,
                  "source_hash": "38a041e3236d4fb2"}
+# The same for the level operators on the 256^3 block (per octant launch).
+LEVELS_SOURCES = ("kernels_amr.hip", "common.hpp")
+LEVELS_TRAFFIC = {"prolong": {"bytes_per_launch": 1.643e+09, "fetch_bytes_per_launch": 4.022e+08,
+                              "write_bytes_per_launch": 1.2409e+09},
+                  "restrict": {"bytes_per_launch": 1.112e+09, "fetch_bytes_per_launch": 9.693e+08,
+                               "write_bytes_per_launch": 1.423e+08},
+                  "fetch_scale": 1.9999, "write_scale": 1.0000, "source_hash": "c1ae33ea82ff0478"}
 
 
 def parse():
@@ -82,14 +89,15 @@ def parse():
     return p.parse_args()
 
 
-def stage_source_hash() -> str:
-    """Hash of the stage kernels' code with comments and blank lines removed,
-    so that a comment edit does not invalidate the stored PMC traffic."""
+def stage_source_hash(names=("kernels_fused.hip", "mhd_math.hpp", "common.hpp")) -> str:
+    """Hash of the kernels' code (the named sources) with comments and blank
+    lines removed, so that a comment edit does not invalidate the stored PMC
+    traffic."""
     import hashlib
     import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2005_06651_amd", "csrc")
-    for name in ("kernels_fused.hip", "mhd_math.hpp", "common.hpp"):
+    for name in names:
         with open(os.path.join(csrc, name), encoding="utf-8") as f:
             text = f.read()
         text = re.sub(r"/\*.*?\*/", "", re.sub(r"//[^\n]*", "", text), flags=re.S)
@@ -427,6 +435,8 @@ def bench_levels(args):
     coarse = (n // 2) ** 3                                   # coarse cells per octant
     bytes_p, bytes_r = coarse * (9 * nv + 27) * 8, coarse * (9 * nv + 15) * 8
     gbs_p, gbs_r = bytes_p / (ms["prolong"] * 1e-3) / 1e9, bytes_r / (ms["restrict"] * 1e-3) / 1e9
+    measured = LEVELS_TRAFFIC.get("source_hash") == stage_source_hash(LEVELS_SOURCES) and n == 256
+    traffic = {k: (LEVELS_TRAFFIC[k]["bytes_per_launch"] if measured else None) for k in ("prolong", "restrict")}
     out = {
         "metric": "fine cells prolonged per second, FP64 MHD level operators (Sec. 2.1.5), 1 MI355X",
         "value": 8 * coarse / (ms["prolong"] * 1e-3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
@@ -436,8 +446,10 @@ def bench_levels(args):
                                "face field) onto a fine block, then restriction back, seeded normal values",
                    "octant_coarse_cells": coarse, "seed": args.seed},
         "roofline": {"bound": "hbm", "achieved": gbs_p, "peak": 8000.0, "unit": "GB/s", "frac": gbs_p / 8000.0,
-                     "traffic": None, "kernel": "k_prolong", "ms_per_launch": ms["prolong"]},
+                     "traffic": traffic["prolong"], "kernel": "k_prolong", "ms_per_launch": ms["prolong"],
+                     "alg_bytes_per_launch": bytes_p},
         "restrict": {"ms_per_launch": ms["restrict"], "GB/s": gbs_r, "frac": gbs_r / 8000.0,
+                     "traffic": traffic["restrict"], "alg_bytes_per_launch": bytes_r,
                      "cells_per_s": coarse / (ms["restrict"] * 1e-3)},
     }
     print(json.dumps(out))

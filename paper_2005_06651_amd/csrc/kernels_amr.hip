@@ -20,9 +20,19 @@ constexpr int kAmrThreads = 256;
 
 struct OctArgs {
   Geo g;
-  int h[3];  // octant extent n_d / 2
-  int o[3];  // first active coarse cell of the octant, o_d n_d / 2
+  int h[3];     // octant extent n_d / 2
+  int o[3];     // first active coarse cell of the octant, o_d n_d / 2
+  int per_xcd;  // workgroups per XCD: ceil(workgroups / 8)
 };
+
+// Thread index in the octant's point order, XCD-aware: workgroup b runs on
+// XCD b mod 8, so logical workgroup (b mod 8) per_xcd + b / 8 gives each XCD
+// one contiguous run of rows and planes, and the neighbour rows and planes a
+// thread reads sit in that XCD's L2.  Launched with 8 per_xcd workgroups.
+__device__ __forceinline__ int oct_thread(const OctArgs& A) {
+  const int b = blockIdx.x;
+  return ((b % 8) * A.per_xcd + b / 8) * kAmrThreads + threadIdx.x;
+}
 
 __device__ __forceinline__ double minmod(double a, double b) {
   if (a > 0.0 && b > 0.0) return fmin(a, b);
@@ -42,7 +52,7 @@ __global__ void __launch_bounds__(kAmrThreads)
                double* __restrict__ cb) {
   const Geo& g = A.g;
   const int e1 = A.h[0] + 1, e2 = A.h[1] + 1, e3 = A.h[2] + 1;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = oct_thread(A);
   if (t >= e1 * e2 * e3) return;
   const int q[3] = {t % e1, (t / e1) % e2, t / (e1 * e2)};
   const int ng = g.ng;
@@ -122,7 +132,7 @@ __global__ void __launch_bounds__(kAmrThreads)
               double* __restrict__ fb) {
   const Geo& g = A.g;
   const int e1 = A.h[0] + 1, e2 = A.h[1] + 1, e3 = A.h[2] + 1;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = oct_thread(A);
   if (t >= e1 * e2 * e3) return;
   const int q[3] = {t % e1, (t / e1) % e2, t / (e1 * e2)};
   const int ng = g.ng;
@@ -220,13 +230,13 @@ OctArgs oct_args(const Geo& g, const int oct[3]) {
     A.h[d] = n[d] / 2;
     A.o[d] = oct[d] * A.h[d];
   }
+  const long pts = (long)(A.h[0] + 1) * (A.h[1] + 1) * (A.h[2] + 1);
+  const long wgs = (pts + kAmrThreads - 1) / kAmrThreads;
+  A.per_xcd = (int)((wgs + 7) / 8);
   return A;
 }
 
-int grid_of(const OctArgs& A) {
-  const long pts = (long)(A.h[0] + 1) * (A.h[1] + 1) * (A.h[2] + 1);
-  return (int)((pts + kAmrThreads - 1) / kAmrThreads);
-}
+int grid_of(const OctArgs& A) { return 8 * A.per_xcd; }
 
 }  // namespace
 
