@@ -42,11 +42,11 @@ STAGE_TRAFFIC = {"bytes_per_launch": 3.468e+09, "fetch_bytes_per_launch": 2.295e
                  "source_hash": "38a041e3236d4fb2"}
 # The same for the level operators on the 256^3 block (per octant launch).
 LEVELS_SOURCES = ("kernels_amr.hip", "common.hpp")
-LEVELS_TRAFFIC = {"prolong": {"bytes_per_launch": 1.643e+09, "fetch_bytes_per_launch": 4.022e+08,
-                              "write_bytes_per_launch": 1.2409e+09},
-                  "restrict": {"bytes_per_launch": 1.112e+09, "fetch_bytes_per_launch": 9.693e+08,
+LEVELS_TRAFFIC = {"prolong": {"bytes_per_launch": 1.644e+09, "fetch_bytes_per_launch": 4.028e+08,
+                              "write_bytes_per_launch": 1.241e+09},
+                  "restrict": {"bytes_per_launch": 1.112e+09, "fetch_bytes_per_launch": 9.695e+08,
                                "write_bytes_per_launch": 1.423e+08},
-                  "fetch_scale": 1.9999, "write_scale": 1.0000, "source_hash": "c1ae33ea82ff0478"}
+                  "fetch_scale": 1.9999, "write_scale": 1.0000, "source_hash": "39539a05d0c3f29f"}
 
 
 def parse():

@@ -313,6 +313,11 @@ ATHMHD_API int athmhd_profile(athmhd_t h, int enable, double* total_ms, int* lau
  * curl at each interior edge equals the mean tangential difference over the
  * two outer faces parallel to it.  The fine field of a divergence-free coarse
  * field is then divergence-free, and linear fields are reproduced exactly.
+ * With a pressure floor set (athmhd_set_floors, pfloor > 0), a refined cell
+ * whose pressure (from its U and the mean of its two bounding fine faces) is
+ * below pfloor gets E raised to give pfloor, with rho and M unchanged (the
+ * method applies such a floor to refined cells; mass and momentum stay
+ * conserved); activations count in athmhd_floor_count.
  * Needs cubic cells (dx1 = dx2 = dx3, else ATHMHD_EUNSUP).
  *
  * Asynchronous on `stream`. */

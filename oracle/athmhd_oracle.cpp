@@ -1135,7 +1135,8 @@ inline void lsq12(const std::vector<std::array<double, 12>>& A, const std::vecto
   }
 }
 
-inline void prolong_octant(const Geo& g, const double* cc, const double* cb, double* fc, double* fb, const int o[3]) {
+inline void prolong_octant(const Geo& g, const double* cc, const double* cb, double* fc, double* fb, const int o[3],
+                           double gamma, double pfloor) {
   const size_t nc = g.ncell(), nf = g.nface();
   const int h[3] = {g.n[0] / 2, g.n[1] / 2, g.n[2] / 2};
   // cells: U_C + sum_d minmod slope_d * (+-1/4)
@@ -1284,6 +1285,29 @@ inline void prolong_octant(const Geo& g, const double* cc, const double* cb, dou
               face(d, x[0], x[1], x[2]) = xs[unk(d, p, q)];
             }
       }
+  // Pressure floor on the refined cells (pfloor > 0 only; Sec. 2.1.5 applies
+  // one when prolonged conserved variables give a negative pressure): where
+  // the pressure implied by the fine U and the cell-centred field of the fine
+  // faces (mean of the two bounding faces) is below pfloor, E is raised to
+  // give pfloor; rho and M, hence mass and momentum, are unchanged.
+  if (pfloor > 0.0)
+    for (int k = g.ng; k < g.ng + g.n[2]; ++k)
+      for (int j = g.ng; j < g.ng + g.n[1]; ++j)
+        for (int i = g.ng; i < g.ng + g.n[0]; ++i) {
+          const size_t q = g.c(i, j, k);
+          double b[3];
+          for (int d = 0; d < 3; ++d) {
+            int up[3] = {i, j, k};
+            up[d] += 1;
+            b[d] = 0.5 * (fb[d * nf + g.f(i, j, k)] + fb[d * nf + g.f(up[0], up[1], up[2])]);
+          }
+          const double rho = fc[q];
+          const double kin = 0.5 * (fc[nc + q] * fc[nc + q] + fc[2 * nc + q] * fc[2 * nc + q] +
+                                    fc[3 * nc + q] * fc[3 * nc + q]) / rho;
+          const double mag = 0.5 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+          const double p = (gamma - 1.0) * (fc[4 * nc + q] - kin - mag);
+          if (!(p >= pfloor)) fc[4 * nc + q] = pfloor / (gamma - 1.0) + kin + mag;
+        }
 }
 
 }  // namespace orc
@@ -1402,7 +1426,7 @@ int orc_prolong(const orc::Cfg* c, const double* ccons, const double* cbface, do
                 int oy, int oz) {
   orc::Geo g(*c);
   const int o[3] = {ox, oy, oz};
-  orc::prolong_octant(g, ccons, cbface, fcons, fbface, o);
+  orc::prolong_octant(g, ccons, cbface, fcons, fbface, o, c->gamma, c->pfloor);
   return 0;
 }
 

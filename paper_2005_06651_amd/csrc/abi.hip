@@ -894,7 +894,8 @@ int athmhd_prolong(athmhd_t h, const double* coarse_cons, const double* coarse_b
   const int oct[3] = {o1, o2, o3};
   int rc = check_level(h, coarse_cons, coarse_bface, fine_cons, fine_bface, oct, true);
   if (rc) return rc;
-  hipError_t e = launch_prolong(h->g, oct, coarse_cons, coarse_bface, fine_cons, fine_bface, (hipStream_t)stream);
+  hipError_t e = launch_prolong(h->g, oct, coarse_cons, coarse_bface, fine_cons, fine_bface, h->cfg.gamma, h->floors.p,
+                                h->d_bad, (hipStream_t)stream);
   return e == hipSuccess ? ATHMHD_OK : hip_fail(h, e, "prolong launch");
 }
 

@@ -23,6 +23,9 @@ struct OctArgs {
   int h[3];     // octant extent n_d / 2
   int o[3];     // first active coarse cell of the octant, o_d n_d / 2
   int per_xcd;  // workgroups per XCD: ceil(workgroups / 8)
+  double gm1;     // gamma - 1
+  double pfloor;  // pressure floor of the refined cells (prolongation; 0: off)
+  int* bad;       // bad[1] counts floor activations
 };
 
 // Thread index in the octant's point order, XCD-aware: workgroup b runs on
@@ -127,6 +130,10 @@ __device__ __forceinline__ void split_face(const Geo& g, const double* cb, int d
 // (d, d + 1); i is the half along d).  Each cell thread recomputes the
 // splits of its upper faces; only the thread that owns a face as its lower
 // face writes it, so every fine face is written once.
+// With a pressure floor, every child whose pressure (from its prolonged U and
+// the mean of its two bounding fine faces, all in this thread's registers) is
+// below it gets E raised to give the floor; rho and M are unchanged.
+template <bool FLOOR>
 __global__ void __launch_bounds__(kAmrThreads)
     k_prolong(OctArgs A, const double* __restrict__ cc, const double* __restrict__ cb, double* __restrict__ fc,
               double* __restrict__ fb) {
@@ -191,6 +198,7 @@ __global__ void __launch_bounds__(kAmrThreads)
   }
   if (!cell) return;
 
+  double Bi[3][2][2];  // interior faces, halves as for O
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
@@ -217,14 +225,44 @@ __global__ void __launch_bounds__(kAmrThreads)
         x[d] = F[d] + 1;
         x[d1] = F[d1] + p;
         x[d2] = F[d2] + r;
-        dst[fidx(g, x)] = v + cross;
+        Bi[d][p][r] = v + cross;
+        dst[fidx(g, x)] = Bi[d][p][r];
       }
   }
+  if (!FLOOR) return;
+
+  const int64_t cv = g.cvar;
+  int hits = 0;
+#pragma unroll
+  for (int s3 = 0; s3 < 2; ++s3)
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+      for (int s1 = 0; s1 < 2; ++s1) {
+        // bounding faces of child (s1, s2, s3): component d's halves run
+        // along (d + 1, d + 2)
+        const double bx = 0.5 * ((s1 ? Bi[0][s2][s3] : O[0][0][s2][s3]) + (s1 ? O[0][1][s2][s3] : Bi[0][s2][s3]));
+        const double by = 0.5 * ((s2 ? Bi[1][s3][s1] : O[1][0][s3][s1]) + (s2 ? O[1][1][s3][s1] : Bi[1][s3][s1]));
+        const double bz = 0.5 * ((s3 ? Bi[2][s1][s2] : O[2][0][s1][s2]) + (s3 ? O[2][1][s1][s2] : Bi[2][s1][s2]));
+        const int q0 = g.c(F[0] + s1, F[1] + s2, F[2] + s3);
+        const double rho = fc[q0], m1 = fc[cv + q0], m2 = fc[2 * cv + q0], m3 = fc[3 * cv + q0];
+        const double e = fc[4 * cv + q0];
+        const double kin = 0.5 * (m1 * m1 + m2 * m2 + m3 * m3) / rho;
+        const double mag = 0.5 * (bx * bx + by * by + bz * bz);
+        if (!(A.gm1 * (e - kin - mag) >= A.pfloor)) {
+          fc[4 * cv + q0] = A.pfloor / A.gm1 + kin + mag;
+          ++hits;
+        }
+      }
+  if (hits) atomicAdd(A.bad + 1, hits);
 }
 
 OctArgs oct_args(const Geo& g, const int oct[3]) {
   OctArgs A;
   A.g = g;
+  A.gm1 = 0.0;
+  A.pfloor = 0.0;
+  A.bad = nullptr;
   const int n[3] = {g.n1, g.n2, g.n3};
   for (int d = 0; d < 3; ++d) {
     A.h[d] = n[d] / 2;
@@ -248,9 +286,17 @@ hipError_t launch_restrict(const Geo& g, const int oct[3], const double* fc, con
 }
 
 hipError_t launch_prolong(const Geo& g, const int oct[3], const double* cc, const double* cb, double* fc, double* fb,
-                          hipStream_t s) {
-  const OctArgs A = oct_args(g, oct);
-  hipLaunchKernelGGL(k_prolong, dim3(grid_of(A)), dim3(kAmrThreads), 0, s, A, cc, cb, fc, fb);
+                          double gamma, double pfloor, int* bad, hipStream_t s) {
+  OctArgs A = oct_args(g, oct);
+  if (pfloor > 0.0 && bad) {
+    A.gm1 = gamma - 1.0;
+    A.pfloor = pfloor;
+    A.bad = bad;
+  }
+  if (A.pfloor > 0.0)
+    hipLaunchKernelGGL(k_prolong<true>, dim3(grid_of(A)), dim3(kAmrThreads), 0, s, A, cc, cb, fc, fb);
+  else
+    hipLaunchKernelGGL(k_prolong<false>, dim3(grid_of(A)), dim3(kAmrThreads), 0, s, A, cc, cb, fc, fb);
   return hipGetLastError();
 }
 

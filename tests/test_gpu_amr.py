@@ -9,7 +9,8 @@ of 1e-14 of the field's scale (a few roundings of sums of 25 terms with
 weights up to 1/2).  Every octant, several block shapes (ragged: unequal and
 non-multiple-of-tile sizes, 2 and 3 ghosts, scalar rows), the entries that
 must stay untouched, round trip and divergence properties on the device, a
-128^3 block, and the error paths.
+128^3 block, the pressure floor on refined cells (E within 1e-14 of the
+oracle, activations counted), and the error paths.
 """
 import itertools
 
@@ -239,3 +240,61 @@ def test_level_operator_errors(torch_dev, athmhd):
     assert e.value.code == athmhd.EUNSUP
     slab.restrict(a[0], b[0], a[1], b[1], (0, 0, 0))   # restriction needs no cubic cells
     torch.cuda.synchronize()
+
+
+def cold_block(N, F, seed, p0=1e-4, gamma=5.0 / 3.0):
+    """rho near 1, momenta of order 1 from cell to cell, weak faces, pressure
+    p0: prolonging E and M separately leaves some children below p0."""
+    rng = np.random.default_rng(seed)
+    cells = np.empty((5,) + N)
+    cells[0] = 1.0 + 0.2 * rng.random(N)
+    cells[1:4] = rng.standard_normal((3,) + N)
+    faces = 0.05 * rng.standard_normal((3,) + F)
+    b1 = 0.5 * (faces[0][:-1, :-1, :-1] + faces[0][:-1, :-1, 1:])
+    b2 = 0.5 * (faces[1][:-1, :-1, :-1] + faces[1][:-1, 1:, :-1])
+    b3 = 0.5 * (faces[2][:-1, :-1, :-1] + faces[2][1:, :-1, :-1])
+    kin = 0.5 * (cells[1] ** 2 + cells[2] ** 2 + cells[3] ** 2) / cells[0]
+    cells[4] = p0 / (gamma - 1.0) + kin + 0.5 * (b1 ** 2 + b2 ** 2 + b3 ** 2)
+    return cells, faces
+
+
+def fine_pressure(cells, faces, n, ng, gamma=5.0 / 3.0):
+    a = (slice(ng, ng + n[2]), slice(ng, ng + n[1]), slice(ng, ng + n[0]))
+    b1 = faces[0][a[0], a[1], ng:ng + n[0] + 1]
+    b2 = faces[1][a[0], ng:ng + n[1] + 1, a[2]]
+    b3 = faces[2][ng:ng + n[2] + 1, a[1], a[2]]
+    mag = 0.5 * ((0.5 * (b1[..., :-1] + b1[..., 1:])) ** 2 + (0.5 * (b2[:, :-1] + b2[:, 1:])) ** 2
+                 + (0.5 * (b3[:-1] + b3[1:])) ** 2)
+    kin = 0.5 * (cells[1][a] ** 2 + cells[2][a] ** 2 + cells[3][a] ** 2) / cells[0][a]
+    return (gamma - 1.0) * (cells[4][a] - kin - mag)
+
+
+@pytest.mark.parametrize("o", [(0, 0, 0), (1, 0, 1), (1, 1, 1)])
+def test_prolong_with_a_pressure_floor_matches_the_oracle(torch_dev, athmhd, orc, o):
+    """Refined cells below the handle's pressure floor get E raised: rho, M
+    and the faces bitwise as without the floor, E within 1e-14 of the oracle,
+    and one counted activation per floored cell."""
+    torch, d = torch_dev
+    n, ng, pf = (16, 12, 10), 2, 1e-5
+    N, F = shapes(n, ng)
+    cc, cb = cold_block(N, F, seed=71)
+    org = tuple(o[k] * n[k] // 2 for k in range(3))
+    cfg0 = orc.make_cfg(n, ng, (0.1,) * 3, 5.0 / 3.0)
+    cfg1 = orc.make_cfg(n, ng, (0.1,) * 3, 5.0 / 3.0, pfloor=pf)
+    c0, b0 = np.zeros_like(cc), np.zeros_like(cb)
+    orc.prolong(cfg0, cc, cb, c0, b0, org)
+    want_c, want_b = np.zeros_like(cc), np.zeros_like(cb)
+    orc.prolong(cfg1, cc, cb, want_c, want_b, org)
+    expected = int((fine_pressure(c0, b0, n, ng) < pf).sum())
+    assert expected >= 3
+    s = solver(athmhd, n, ng)
+    s.set_floors(0.0, pf)
+    assert s.floor_count() == 0
+    gc, gb = torch.zeros(cc.shape, dtype=torch.float64, device=d), torch.zeros(cb.shape, dtype=torch.float64, device=d)
+    s.prolong(dev(torch, d, cc), dev(torch, d, cb), gc, gb, o)
+    got_c, got_b = gc.cpu().numpy(), gb.cpu().numpy()
+    assert s.floor_count() == expected
+    assert np.array_equal(got_c[:4], want_c[:4])
+    assert np.abs(got_c[4] - want_c[4]).max() <= 1e-14 * np.abs(want_c[4]).max()
+    check_prolong(got_c[:4], got_b, want_c[:4], want_b, want_c[:4], want_b, n, ng)
+    assert fine_pressure(got_c, got_b, n, ng).min() >= pf * (1 - 1e-9)

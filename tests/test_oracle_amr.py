@@ -19,7 +19,10 @@ mathematics fix:
   * the operators commute with mirroring an axis and with cycling the axes
     (a wrong weighting of the two outer planes in the curl estimate, or a
     transposed index, breaks one of them);
-  * only the named octant of the coarse block is written by restriction.
+  * only the named octant of the coarse block is written by restriction;
+  * with a pressure floor, every refined cell ends at or above it, and only E
+    of the cells below it changes (mass, momentum and faces bitwise as
+    without the floor).
 """
 import itertools
 
@@ -292,3 +295,58 @@ def test_prolongation_commutes_with_cycling_the_axes(orc, o):
         e[d] = 1
         s = (slice(2, 10 + e[2]), slice(2, 10 + e[1]), slice(2, 10 + e[0]))
         assert np.abs(gb[d][s] - wb[d][s]).max() <= 1e-13, d
+
+
+def pressure(cells, faces, n, ng, gamma):
+    """Pressure of every active cell from U and the mean of its two bounding faces."""
+    a = (slice(ng, ng + n[2]), slice(ng, ng + n[1]), slice(ng, ng + n[0]))
+    b1 = faces[0][a[0], a[1], ng:ng + n[0] + 1]
+    b2 = faces[1][a[0], ng:ng + n[1] + 1, a[2]]
+    b3 = faces[2][ng:ng + n[2] + 1, a[1], a[2]]
+    bc = [0.5 * (b1[..., :-1] + b1[..., 1:]), 0.5 * (b2[:, :-1] + b2[:, 1:]), 0.5 * (b3[:-1] + b3[1:])]
+    rho = cells[0][a]
+    kin = 0.5 * (cells[1][a] ** 2 + cells[2][a] ** 2 + cells[3][a] ** 2) / rho
+    return (gamma - 1.0) * (cells[4][a] - kin - 0.5 * (bc[0] ** 2 + bc[1] ** 2 + bc[2] ** 2))
+
+
+def cold_state(N, F, seed):
+    """rho near 1, momenta of order 1 varying from cell to cell, pressure 1e-4:
+    linear interpolation of E and M separately then leaves some children with
+    less E than their kinetic energy (M^2 / 2 rho is convex)."""
+    rng = np.random.default_rng(seed)
+    cells = np.empty((5,) + N)
+    cells[0] = 1.0 + 0.2 * rng.random(N)
+    cells[1:4] = rng.standard_normal((3,) + N)
+    faces = 0.05 * rng.standard_normal((3,) + F)
+    bc = [0.5 * (faces[0][..., :-1][:, :-1, :] + faces[0][..., 1:][:, :-1, :])[:-1],
+          0.5 * (faces[1][:, :-1][..., :-1] + faces[1][:, 1:][..., :-1])[:-1],
+          0.5 * (faces[2][:-1][:, :-1, :-1] + faces[2][1:][:, :-1, :-1])]
+    kin = 0.5 * (cells[1] ** 2 + cells[2] ** 2 + cells[3] ** 2) / cells[0]
+    cells[4] = 1e-4 / (5.0 / 3.0 - 1.0) + kin + 0.5 * sum(b ** 2 for b in bc)
+    return cells, faces
+
+
+@pytest.mark.parametrize("o", [(0, 0, 0), (1, 1, 0)])
+def test_pressure_floor_on_refined_cells(orc, o):
+    """With a pressure floor, every refined cell has P >= pfloor; only E of the
+    cells below it changes (upwards), and mass, momentum and faces are those
+    of the prolongation without the floor, bitwise."""
+    n, ng, pf = (8, 6, 4), 2, 1e-5
+    N = (n[2] + 2 * ng, n[1] + 2 * ng, n[0] + 2 * ng)
+    F = tuple(x + 1 for x in N)
+    cc, cb = cold_state(N, F, seed=61)
+    org = oct_origin(n, o)
+    cfg0 = orc.make_cfg(n, ng, (0.1,) * 3, 5.0 / 3.0)
+    cfg1 = orc.make_cfg(n, ng, (0.1,) * 3, 5.0 / 3.0, pfloor=pf)
+    c0, b0 = prolong(orc, cfg0, cc, cb, org)
+    c1, b1 = prolong(orc, cfg1, cc, cb, org)
+    p0 = pressure(c0, b0, n, ng, 5.0 / 3.0)
+    p1 = pressure(c1, b1, n, ng, 5.0 / 3.0)
+    low = p0 < pf
+    assert low.sum() >= 3                          # the floor is exercised
+    assert np.array_equal(c1[:4], c0[:4]) and np.array_equal(b1, b0)
+    a = (slice(ng, ng + n[2]), slice(ng, ng + n[1]), slice(ng, ng + n[0]))
+    assert np.array_equal(c1[4][a][~low], c0[4][a][~low])
+    assert np.all(c1[4][a][low] > c0[4][a][low])
+    assert np.all(p1 >= pf * (1 - 1e-9)), p1.min()
+    assert np.abs(p1[low] - pf).max() <= 1e-9 * np.abs(c1[4][a]).max()
