@@ -391,7 +391,9 @@ def bench_levels(args):
     """Level operators of block refinement on one 256^3 block (the largest
     single block; nghost 2, 5 conserved arrays): prolongation of each of the 8
     octants of a coarse block onto a fine block, then restriction of the fine
-    block back onto each octant, timed with HIP events on the launch stream.
+    block back onto each octant, and prolongation in primitive variables of a
+    physical copy of the coarse block, timed with HIP events on the launch
+    stream.
     Algorithmic bytes per coarse cell of an octant (nv = 5 cell arrays, 3 face
     components): prolongation reads nv cells and 3 faces and writes 8 nv fine
     cells and 24 fine faces (12 on the coarse faces it owns, 12 inside), i.e.
@@ -417,13 +419,22 @@ def bench_levels(args):
         for o in octs:
             op(*src, *dst, o, stream=stream)
 
+    def prolong_prim(*a, **k):
+        s.prolong(*a, primitive=True, **k)
+
+    # primitive prolongation needs a physical coarse state: rho and P positive
+    cp = cc.clone()
+    cp[0] = 1.0 + 0.1 * cp[0].abs()
+    cp[4] = 50.0 + cp[4].abs()
     for _ in range(args.warmup):
         run(s.prolong, (cc, cb), (fc, fb))
         run(s.restrict, (fc, fb), (cc, cb))
+        run(prolong_prim, (cp, cb), (fc, fb))
     torch.cuda.synchronize()
     ms = {}
     t0 = time.perf_counter()
-    for name, op, src, dst in (("prolong", s.prolong, (cc, cb), (fc, fb)), ("restrict", s.restrict, (fc, fb), (cc, cb))):
+    for name, op, src, dst in (("prolong", s.prolong, (cc, cb), (fc, fb)), ("restrict", s.restrict, (fc, fb), (cc, cb)),
+                               ("prolong_primitive", prolong_prim, (cp, cb), (fc, fb))):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(args.steps):
@@ -451,6 +462,9 @@ def bench_levels(args):
         "restrict": {"ms_per_launch": ms["restrict"], "GB/s": gbs_r, "frac": gbs_r / 8000.0,
                      "traffic": traffic["restrict"], "alg_bytes_per_launch": bytes_r,
                      "cells_per_s": coarse / (ms["restrict"] * 1e-3)},
+        "prolong_primitive": {"ms_per_launch": ms["prolong_primitive"],
+                              "GB/s": bytes_p / (ms["prolong_primitive"] * 1e-3) / 1e9,
+                              "frac": bytes_p / (ms["prolong_primitive"] * 1e-3) / 1e9 / 8000.0},
     }
     print(json.dumps(out))
 

@@ -313,18 +313,25 @@ ATHMHD_API int athmhd_profile(athmhd_t h, int enable, double* total_ms, int* lau
  * curl at each interior edge equals the mean tangential difference over the
  * two outer faces parallel to it.  The fine field of a divergence-free coarse
  * field is then divergence-free, and linear fields are reproduced exactly.
- * With a pressure floor set (athmhd_set_floors, pfloor > 0), a refined cell
- * whose pressure (from its U and the mean of its two bounding fine faces) is
- * below pfloor gets E raised to give pfloor, with rho and M unchanged (the
- * method applies such a floor to refined cells; mass and momentum stay
+ * primitive = 0 (new blocks: conserved variables, as the method prescribes):
+ * the cell arrays themselves are prolonged; with a pressure floor set
+ * (athmhd_set_floors, pfloor > 0), a refined cell whose pressure (from its U
+ * and the mean of its two bounding fine faces) is below pfloor gets E raised
+ * to give pfloor, with rho and M unchanged (mass and momentum stay
  * conserved); activations count in athmhd_floor_count.
+ * primitive = 1 (ghost zones between levels, where the method prolongs
+ * primitives): the coarse cells read are converted to (rho, v, P, C_i) with
+ * their cell-centred fields (mean of the two stored bounding faces), those
+ * are prolonged as above, and each fine cell is converted back with the
+ * cell-centred field of the prolonged fine faces; no floor is applied (P is
+ * prolonged directly).  Other values: ATHMHD_EINVAL.
  * Needs cubic cells (dx1 = dx2 = dx3, else ATHMHD_EUNSUP).
  *
  * Asynchronous on `stream`. */
 ATHMHD_API int athmhd_restrict(athmhd_t h, const double* fine_cons, const double* fine_bface, double* coarse_cons,
                                double* coarse_bface, int o1, int o2, int o3, void* stream);
 ATHMHD_API int athmhd_prolong(athmhd_t h, const double* coarse_cons, const double* coarse_bface, double* fine_cons,
-                              double* fine_bface, int o1, int o2, int o3, void* stream);
+                              double* fine_bface, int o1, int o2, int o3, int primitive, void* stream);
 
 /* Text of the last error recorded on `h` (or of the last failed create when
  * h is NULL).  Valid until the next call on the same handle. */

@@ -1135,28 +1135,71 @@ inline void lsq12(const std::vector<std::array<double, 12>>& A, const std::vecto
   }
 }
 
+// Cell-centred field of cell (i, j, k) from the stored faces: the mean of the
+// two faces that bound it along each direction (no periodic wrap).
+inline void cell_field_stored(const Geo& g, const double* bf, int i, int j, int k, double b[3]) {
+  const size_t nf = g.nface();
+  for (int d = 0; d < 3; ++d) {
+    int up[3] = {i, j, k};
+    up[d] += 1;
+    b[d] = 0.5 * (bf[d * nf + g.f(i, j, k)] + bf[d * nf + g.f(up[0], up[1], up[2])]);
+  }
+}
+
+// primitive = false: the cell arrays prolonged are the conserved variables
+// themselves (new blocks); with pfloor > 0 the pressure floor follows.
+// primitive = true: the coarse cells the octant reads (the octant and one
+// layer around it) are converted to primitives (rho, v, P, C_i) with their
+// cell-centred field, the primitives are prolonged, and each fine cell is
+// converted back to conserved variables with the cell-centred field of the
+// prolonged fine faces (Sec. 2.1.5 uses this between levels: conserved
+// values are exchanged, prolongation acts on primitives).
 inline void prolong_octant(const Geo& g, const double* cc, const double* cb, double* fc, double* fb, const int o[3],
-                           double gamma, double pfloor) {
+                           double gamma, double pfloor, bool primitive) {
   const size_t nc = g.ncell(), nf = g.nface();
   const int h[3] = {g.n[0] / 2, g.n[1] / 2, g.n[2] / 2};
+  std::vector<double> wc, wf;
+  if (primitive) {
+    wc.assign(g.nv * nc, 0.0);
+    wf.assign(g.nv * nc, 0.0);
+    for (int k = g.ng + o[2] - 1; k <= g.ng + o[2] + h[2]; ++k)
+      for (int j = g.ng + o[1] - 1; j <= g.ng + o[1] + h[1]; ++j)
+        for (int i = g.ng + o[0] - 1; i <= g.ng + o[0] + h[0]; ++i) {
+          const size_t q = g.c(i, j, k);
+          double b[3];
+          cell_field_stored(g, cb, i, j, k, b);
+          const double rho = cc[q];
+          const double v1 = cc[nc + q] / rho, v2 = cc[2 * nc + q] / rho, v3 = cc[3 * nc + q] / rho;
+          const double kin = 0.5 * rho * (v1 * v1 + v2 * v2 + v3 * v3);
+          const double mag = 0.5 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+          wc[q] = rho;
+          wc[nc + q] = v1;
+          wc[2 * nc + q] = v2;
+          wc[3 * nc + q] = v3;
+          wc[4 * nc + q] = (gamma - 1.0) * (cc[4 * nc + q] - kin - mag);
+          for (int v = 5; v < g.nv; ++v) wc[v * nc + q] = cc[v * nc + q] / rho;
+        }
+  }
+  const double* src = primitive ? wc.data() : cc;
+  double* dst = primitive ? wf.data() : fc;
   // cells: U_C + sum_d minmod slope_d * (+-1/4)
   for (int v = 0; v < g.nv; ++v)
     for (int c = 0; c < h[2]; ++c)
       for (int b = 0; b < h[1]; ++b)
         for (int a = 0; a < h[0]; ++a) {
           const int C[3] = {g.ng + o[0] + a, g.ng + o[1] + b, g.ng + o[2] + c};
-          const double u0 = cc[v * nc + g.c(C[0], C[1], C[2])];
+          const double u0 = src[v * nc + g.c(C[0], C[1], C[2])];
           double sl[3];
           for (int d = 0; d < 3; ++d) {
             int m[3] = {C[0], C[1], C[2]}, p[3] = {C[0], C[1], C[2]};
             m[d] -= 1;
             p[d] += 1;
-            sl[d] = minmod(u0 - cc[v * nc + g.c(m[0], m[1], m[2])], cc[v * nc + g.c(p[0], p[1], p[2])] - u0);
+            sl[d] = minmod(u0 - src[v * nc + g.c(m[0], m[1], m[2])], src[v * nc + g.c(p[0], p[1], p[2])] - u0);
           }
           for (int s3 = 0; s3 < 2; ++s3)
             for (int s2 = 0; s2 < 2; ++s2)
               for (int s1 = 0; s1 < 2; ++s1)
-                fc[v * nc + g.c(g.ng + 2 * a + s1, g.ng + 2 * b + s2, g.ng + 2 * c + s3)] =
+                dst[v * nc + g.c(g.ng + 2 * a + s1, g.ng + 2 * b + s2, g.ng + 2 * c + s3)] =
                     u0 + 0.25 * ((2 * s1 - 1) * sl[0] + (2 * s2 - 1) * sl[1] + (2 * s3 - 1) * sl[2]);
         }
   // outer fine faces: each coarse face of the octant (upper ones included)
@@ -1285,12 +1328,30 @@ inline void prolong_octant(const Geo& g, const double* cc, const double* cb, dou
               face(d, x[0], x[1], x[2]) = xs[unk(d, p, q)];
             }
       }
+  // primitive prolongation: back to conserved variables with the fine
+  // cell-centred field
+  if (primitive)
+    for (int k = g.ng; k < g.ng + g.n[2]; ++k)
+      for (int j = g.ng; j < g.ng + g.n[1]; ++j)
+        for (int i = g.ng; i < g.ng + g.n[0]; ++i) {
+          const size_t q = g.c(i, j, k);
+          double b[3];
+          cell_field_stored(g, fb, i, j, k, b);
+          const double rho = wf[q], v1 = wf[nc + q], v2 = wf[2 * nc + q], v3 = wf[3 * nc + q];
+          fc[q] = rho;
+          fc[nc + q] = rho * v1;
+          fc[2 * nc + q] = rho * v2;
+          fc[3 * nc + q] = rho * v3;
+          fc[4 * nc + q] = wf[4 * nc + q] / (gamma - 1.0) + 0.5 * rho * (v1 * v1 + v2 * v2 + v3 * v3) +
+                           0.5 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+          for (int v = 5; v < g.nv; ++v) fc[v * nc + q] = rho * wf[v * nc + q];
+        }
   // Pressure floor on the refined cells (pfloor > 0 only; Sec. 2.1.5 applies
   // one when prolonged conserved variables give a negative pressure): where
   // the pressure implied by the fine U and the cell-centred field of the fine
   // faces (mean of the two bounding faces) is below pfloor, E is raised to
   // give pfloor; rho and M, hence mass and momentum, are unchanged.
-  if (pfloor > 0.0)
+  if (pfloor > 0.0 && !primitive)
     for (int k = g.ng; k < g.ng + g.n[2]; ++k)
       for (int j = g.ng; j < g.ng + g.n[1]; ++j)
         for (int i = g.ng; i < g.ng + g.n[0]; ++i) {
@@ -1423,10 +1484,10 @@ int orc_restrict(const orc::Cfg* c, const double* fcons, const double* fbface, d
 }
 
 int orc_prolong(const orc::Cfg* c, const double* ccons, const double* cbface, double* fcons, double* fbface, int ox,
-                int oy, int oz) {
+                int oy, int oz, int primitive) {
   orc::Geo g(*c);
   const int o[3] = {ox, oy, oz};
-  orc::prolong_octant(g, ccons, cbface, fcons, fbface, o, c->gamma, c->pfloor);
+  orc::prolong_octant(g, ccons, cbface, fcons, fbface, o, c->gamma, c->pfloor, primitive != 0);
   return 0;
 }
 

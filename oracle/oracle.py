@@ -64,7 +64,7 @@ def lib():
         _lib.orc_char_plm.argtypes = [C.c_double, P, P, P, C.c_double, P, P]
         _lib.orc_char_ppm.argtypes = [C.c_double, P, C.c_double, P, P]
         _lib.orc_restrict.argtypes = [cp, P, P, P, P, C.c_int, C.c_int, C.c_int]
-        _lib.orc_prolong.argtypes = [cp, P, P, P, P, C.c_int, C.c_int, C.c_int]
+        _lib.orc_prolong.argtypes = [cp, P, P, P, P, C.c_int, C.c_int, C.c_int, C.c_int]
         _lib.orc_drive_scalar.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_int,
                                           P, P]
         _lib.orc_take_floor_count.restype = C.c_longlong
@@ -216,12 +216,14 @@ def restrict(cfg: Cfg, fcons, fbface, ccons, cbface, octant) -> None:
     lib().orc_restrict(C.byref(cfg), _p(fcons), _p(fbface), _p(ccons), _p(cbface), *[int(v) for v in octant])
 
 
-def prolong(cfg: Cfg, ccons, cbface, fcons, fbface, octant) -> None:
+def prolong(cfg: Cfg, ccons, cbface, fcons, fbface, octant, primitive: bool = False) -> None:
     """Prolong octant (ox, oy, oz) of the coarse block into the fine block (in
-    place in fcons, fbface)."""
+    place in fcons, fbface); primitive=True prolongs the primitives and
+    converts back."""
     for x, y in ((fcons, fbface), (ccons, cbface)):
         _check(cfg, x, y)
-    lib().orc_prolong(C.byref(cfg), _p(ccons), _p(cbface), _p(fcons), _p(fbface), *[int(v) for v in octant])
+    lib().orc_prolong(C.byref(cfg), _p(ccons), _p(cbface), _p(fcons), _p(fbface), *[int(v) for v in octant],
+                      int(bool(primitive)))
 
 
 def drive_scalar(integrator: str, lam: complex, dt: float, nsteps: int) -> complex:

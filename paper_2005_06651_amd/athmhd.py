@@ -77,7 +77,7 @@ def lib():
         L.athmhd_prim2cons_vjp.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int, vp]
         L.athmhd_profile.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]
         L.athmhd_restrict.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_int, C.c_int, vp]
-        L.athmhd_prolong.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_int, C.c_int, vp]
+        L.athmhd_prolong.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, vp]
         L.athmhd_last_error.argtypes = [vp]
         L.athmhd_last_error.restype = C.c_char_p
         L.athmhd_destroy.argtypes = [vp]
@@ -199,12 +199,14 @@ class Solver:
         o = [int(x) for x in octant]
         _check(lib().athmhd_restrict(self._h, fc, fb, cc, cb, *o, _stream(stream)), self._h)
 
-    def prolong(self, coarse_cons, coarse_bface, fine_cons, fine_bface, octant, stream=None) -> None:
-        """Prolong octant (o1, o2, o3) of the coarse block onto the fine block's active cells and faces."""
+    def prolong(self, coarse_cons, coarse_bface, fine_cons, fine_bface, octant, primitive=False,
+                stream=None) -> None:
+        """Prolong octant (o1, o2, o3) of the coarse block onto the fine block's
+        active cells and faces (primitive=True: in primitive variables)."""
         cc, cb = self._one_block(coarse_cons, coarse_bface)
         fc, fb = self._one_block(fine_cons, fine_bface)
         o = [int(x) for x in octant]
-        _check(lib().athmhd_prolong(self._h, cc, cb, fc, fb, *o, _stream(stream)), self._h)
+        _check(lib().athmhd_prolong(self._h, cc, cb, fc, fb, *o, int(bool(primitive)), _stream(stream)), self._h)
 
     @property
     def extra_stages(self) -> int:

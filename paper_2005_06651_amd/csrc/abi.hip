@@ -890,12 +890,13 @@ int athmhd_restrict(athmhd_t h, const double* fine_cons, const double* fine_bfac
 }
 
 int athmhd_prolong(athmhd_t h, const double* coarse_cons, const double* coarse_bface, double* fine_cons,
-                   double* fine_bface, int o1, int o2, int o3, void* stream) {
+                   double* fine_bface, int o1, int o2, int o3, int primitive, void* stream) {
   const int oct[3] = {o1, o2, o3};
   int rc = check_level(h, coarse_cons, coarse_bface, fine_cons, fine_bface, oct, true);
   if (rc) return rc;
-  hipError_t e = launch_prolong(h->g, oct, coarse_cons, coarse_bface, fine_cons, fine_bface, h->cfg.gamma, h->floors.p,
-                                h->d_bad, (hipStream_t)stream);
+  if (primitive != 0 && primitive != 1) return fail(h, ATHMHD_EINVAL, "primitive must be 0 or 1 (got %d)", primitive);
+  hipError_t e = launch_prolong(h->g, oct, coarse_cons, coarse_bface, fine_cons, fine_bface, primitive == 1,
+                                h->cfg.gamma, h->floors.p, h->d_bad, (hipStream_t)stream);
   return e == hipSuccess ? ATHMHD_OK : hip_fail(h, e, "prolong launch");
 }
 

@@ -25,9 +25,10 @@ hipError_t launch_mesh_ghosts(const Geo& g, int w, double* cons, double* bface, 
 // Level operators of block refinement on one octant (0 or 1 per direction).
 hipError_t launch_restrict(const Geo& g, const int oct[3], const double* fc, const double* fb, double* cc, double* cb,
                            hipStream_t s);
-// pfloor > 0: pressure floor on the refined cells, activations in bad[1].
+// primitive: prolong (rho, v, P, C_i) instead of U; otherwise pfloor > 0
+// applies the pressure floor to the refined cells, activations in bad[1].
 hipError_t launch_prolong(const Geo& g, const int oct[3], const double* cc, const double* cb, double* fc, double* fb,
-                          double gamma, double pfloor, int* bad, hipStream_t s);
+                          bool primitive, double gamma, double pfloor, int* bad, hipStream_t s);
 hipError_t launch_prim2cons(const Geo& g, double gamma, const double* prim, const double* bface, double* cons,
                             int nb, hipStream_t s);
 // dt_bits: device uint64 holding the bit pattern of the running minimum of

@@ -133,7 +133,46 @@ __device__ __forceinline__ void split_face(const Geo& g, const double* cb, int d
 // With a pressure floor, every child whose pressure (from its prolonged U and
 // the mean of its two bounding fine faces, all in this thread's registers) is
 // below it gets E raised to give the floor; rho and M are unchanged.
-template <bool FLOOR>
+// PRIM: the cells are prolonged in primitive variables instead -- the coarse
+// cell and its 6 neighbours converted to (rho, v, P, C_i) with their own
+// cell-centred fields, the primitives prolonged, each child converted back
+// with the cell-centred field of its fine faces (no floor then: P itself is
+// prolonged, so it stays positive).
+
+// Primitives (rho, v1, v2, v3, P) of coarse cell P from its U and the mean of
+// its two stored bounding faces along each direction.
+__device__ __forceinline__ void coarse_prim(const Geo& g, double gm1, const double* cc, const double* cb,
+                                            const int P[3], double w[5]) {
+  const int q = cidx(g, P);
+  double b[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int up[3] = {P[0], P[1], P[2]};
+    up[d] += 1;
+    b[d] = 0.5 * (cb[d * g.fvar + fidx(g, P)] + cb[d * g.fvar + fidx(g, up)]);
+  }
+  const double rho = cc[q];
+  const double v1 = cc[g.cvar + q] / rho, v2 = cc[2 * g.cvar + q] / rho, v3 = cc[3 * g.cvar + q] / rho;
+  const double kin = 0.5 * rho * (v1 * v1 + v2 * v2 + v3 * v3);
+  const double mag = 0.5 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+  w[0] = rho;
+  w[1] = v1;
+  w[2] = v2;
+  w[3] = v3;
+  w[4] = gm1 * (cc[4 * g.cvar + q] - kin - mag);
+}
+
+// Cell-centred field of child (s1, s2, s3) from the outer (O) and interior
+// (Bi) fine faces of its coarse cell; component d's halves run along
+// (d + 1, d + 2).
+__device__ __forceinline__ void child_field(const double (&O)[3][2][2][2], const double (&Bi)[3][2][2], int s1,
+                                            int s2, int s3, double b[3]) {
+  b[0] = 0.5 * ((s1 ? Bi[0][s2][s3] : O[0][0][s2][s3]) + (s1 ? O[0][1][s2][s3] : Bi[0][s2][s3]));
+  b[1] = 0.5 * ((s2 ? Bi[1][s3][s1] : O[1][0][s3][s1]) + (s2 ? O[1][1][s3][s1] : Bi[1][s3][s1]));
+  b[2] = 0.5 * ((s3 ? Bi[2][s1][s2] : O[2][0][s1][s2]) + (s3 ? O[2][1][s1][s2] : Bi[2][s1][s2]));
+}
+
+template <bool FLOOR, bool PRIM>
 __global__ void __launch_bounds__(kAmrThreads)
     k_prolong(OctArgs A, const double* __restrict__ cc, const double* __restrict__ cb, double* __restrict__ fc,
               double* __restrict__ fb) {
@@ -147,7 +186,7 @@ __global__ void __launch_bounds__(kAmrThreads)
   const int C[3] = {ng + A.o[0] + q[0], ng + A.o[1] + q[1], ng + A.o[2] + q[2]};
   const int F[3] = {ng + 2 * q[0], ng + 2 * q[1], ng + 2 * q[2]};
 
-  if (cell) {
+  if (cell && !PRIM) {
     const int nv = 5 + g.ns;
     for (int v = 0; v < nv; ++v) {
       const double* src = cc + v * g.cvar;
@@ -229,9 +268,72 @@ __global__ void __launch_bounds__(kAmrThreads)
         dst[fidx(g, x)] = Bi[d][p][r];
       }
   }
+  const int64_t cv = g.cvar;
+  if (PRIM) {
+    // slopes of the 5 MHD primitives, one direction at a time
+    double w0[5], sl[5][3];
+    coarse_prim(g, A.gm1, cc, cb, C, w0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int m[3] = {C[0], C[1], C[2]}, p[3] = {C[0], C[1], C[2]};
+      m[d] -= 1;
+      p[d] += 1;
+      double wm[5], wp[5];
+      coarse_prim(g, A.gm1, cc, cb, m, wm);
+      coarse_prim(g, A.gm1, cc, cb, p, wp);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sl[v][d] = minmod(w0[v] - wm[v], wp[v] - w0[v]);
+    }
+    double rho_c[8];
+#pragma unroll
+    for (int s3 = 0; s3 < 2; ++s3)
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int s1 = 0; s1 < 2; ++s1) {
+          double w[5];
+#pragma unroll
+          for (int v = 0; v < 5; ++v)
+            w[v] = w0[v] + 0.25 * ((2 * s1 - 1) * sl[v][0] + (2 * s2 - 1) * sl[v][1] + (2 * s3 - 1) * sl[v][2]);
+          double b[3];
+          child_field(O, Bi, s1, s2, s3, b);
+          const int q0 = g.c(F[0] + s1, F[1] + s2, F[2] + s3);
+          fc[q0] = w[0];
+          fc[cv + q0] = w[0] * w[1];
+          fc[2 * cv + q0] = w[0] * w[2];
+          fc[3 * cv + q0] = w[0] * w[3];
+          fc[4 * cv + q0] = w[4] / A.gm1 + 0.5 * w[0] * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) +
+                            0.5 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+          rho_c[(s3 * 2 + s2) * 2 + s1] = w[0];
+        }
+    // passive scalars: C = (rho C) / rho prolonged, back as rho_child C
+    const int nv = 5 + g.ns;
+    const double r0 = cc[cidx(g, C)];
+    for (int v = 5; v < nv; ++v) {
+      const double* src = cc + v * cv;
+      const double c0 = src[cidx(g, C)] / r0;
+      double s[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        int m[3] = {C[0], C[1], C[2]}, p[3] = {C[0], C[1], C[2]};
+        m[d] -= 1;
+        p[d] += 1;
+        const double cm = src[cidx(g, m)] / cc[cidx(g, m)], cp = src[cidx(g, p)] / cc[cidx(g, p)];
+        s[d] = minmod(c0 - cm, cp - c0);
+      }
+#pragma unroll
+      for (int s3 = 0; s3 < 2; ++s3)
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+          for (int s1 = 0; s1 < 2; ++s1)
+            fc[v * cv + g.c(F[0] + s1, F[1] + s2, F[2] + s3)] =
+                rho_c[(s3 * 2 + s2) * 2 + s1] *
+                (c0 + 0.25 * ((2 * s1 - 1) * s[0] + (2 * s2 - 1) * s[1] + (2 * s3 - 1) * s[2]));
+    }
+  }
   if (!FLOOR) return;
 
-  const int64_t cv = g.cvar;
   int hits = 0;
 #pragma unroll
   for (int s3 = 0; s3 < 2; ++s3)
@@ -239,11 +341,9 @@ __global__ void __launch_bounds__(kAmrThreads)
     for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
       for (int s1 = 0; s1 < 2; ++s1) {
-        // bounding faces of child (s1, s2, s3): component d's halves run
-        // along (d + 1, d + 2)
-        const double bx = 0.5 * ((s1 ? Bi[0][s2][s3] : O[0][0][s2][s3]) + (s1 ? O[0][1][s2][s3] : Bi[0][s2][s3]));
-        const double by = 0.5 * ((s2 ? Bi[1][s3][s1] : O[1][0][s3][s1]) + (s2 ? O[1][1][s3][s1] : Bi[1][s3][s1]));
-        const double bz = 0.5 * ((s3 ? Bi[2][s1][s2] : O[2][0][s1][s2]) + (s3 ? O[2][1][s1][s2] : Bi[2][s1][s2]));
+        double bc[3];
+        child_field(O, Bi, s1, s2, s3, bc);
+        const double bx = bc[0], by = bc[1], bz = bc[2];
         const int q0 = g.c(F[0] + s1, F[1] + s2, F[2] + s3);
         const double rho = fc[q0], m1 = fc[cv + q0], m2 = fc[2 * cv + q0], m3 = fc[3 * cv + q0];
         const double e = fc[4 * cv + q0];
@@ -286,17 +386,20 @@ hipError_t launch_restrict(const Geo& g, const int oct[3], const double* fc, con
 }
 
 hipError_t launch_prolong(const Geo& g, const int oct[3], const double* cc, const double* cb, double* fc, double* fb,
-                          double gamma, double pfloor, int* bad, hipStream_t s) {
+                          bool primitive, double gamma, double pfloor, int* bad, hipStream_t s) {
   OctArgs A = oct_args(g, oct);
-  if (pfloor > 0.0 && bad) {
-    A.gm1 = gamma - 1.0;
+  A.gm1 = gamma - 1.0;
+  if (!primitive && pfloor > 0.0 && bad) {
     A.pfloor = pfloor;
     A.bad = bad;
   }
-  if (A.pfloor > 0.0)
-    hipLaunchKernelGGL(k_prolong<true>, dim3(grid_of(A)), dim3(kAmrThreads), 0, s, A, cc, cb, fc, fb);
+  const dim3 grid(grid_of(A)), block(kAmrThreads);
+  if (primitive)
+    hipLaunchKernelGGL((k_prolong<false, true>), grid, block, 0, s, A, cc, cb, fc, fb);
+  else if (A.pfloor > 0.0)
+    hipLaunchKernelGGL((k_prolong<true, false>), grid, block, 0, s, A, cc, cb, fc, fb);
   else
-    hipLaunchKernelGGL(k_prolong<false>, dim3(grid_of(A)), dim3(kAmrThreads), 0, s, A, cc, cb, fc, fb);
+    hipLaunchKernelGGL((k_prolong<false, false>), grid, block, 0, s, A, cc, cb, fc, fb);
   return hipGetLastError();
 }
 

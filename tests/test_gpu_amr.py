@@ -9,8 +9,9 @@ of 1e-14 of the field's scale (a few roundings of sums of 25 terms with
 weights up to 1/2).  Every octant, several block shapes (ragged: unequal and
 non-multiple-of-tile sizes, 2 and 3 ghosts, scalar rows), the entries that
 must stay untouched, round trip and divergence properties on the device, a
-128^3 block, the pressure floor on refined cells (E within 1e-14 of the
-oracle, activations counted), and the error paths.
+128^3 block, prolongation in primitive variables (1e-13), the pressure floor
+on refined cells (E within 1e-14 of the oracle, activations counted), and the
+error paths.
 """
 import itertools
 
@@ -298,3 +299,74 @@ def test_prolong_with_a_pressure_floor_matches_the_oracle(torch_dev, athmhd, orc
     assert np.abs(got_c[4] - want_c[4]).max() <= 1e-14 * np.abs(want_c[4]).max()
     check_prolong(got_c[:4], got_b, want_c[:4], want_b, want_c[:4], want_b, n, ng)
     assert fine_pressure(got_c, got_b, n, ng).min() >= pf * (1 - 1e-9)
+
+
+PRIM_TOL = 1e-13
+
+
+@pytest.mark.parametrize("n,ng,ns", [((10, 14, 6), 3, 1), ((32, 24, 16), 2, 2), ((16, 16, 16), 2, 0)])
+@pytest.mark.parametrize("o", [(0, 0, 0), (1, 0, 0), (0, 1, 1), (1, 1, 1)])
+def test_primitive_prolong_matches_the_oracle(torch_dev, athmhd, orc, n, ng, ns, o):
+    """Prolongation in primitive variables of a smooth physical state with
+    scalars: rho and the faces as in the bitwise cases, every other array
+    within 1e-13 of its scale (divisions and the pressure formula round
+    differently with FMA contraction)."""
+    torch, d = torch_dev
+    b = inputs.smooth_random(n=n, seed=9, ng=ng)
+    if ns:
+        b = inputs.with_scalars(b, ns, seed=19)
+    cfg = orc.cfg_for(b, nscalars=ns)
+    cc = orc.prim2cons(cfg, b.prim, b.bface)
+    org = tuple(o[k] * n[k] // 2 for k in range(3))
+    want_c, want_b = np.zeros_like(cc), np.zeros_like(b.bface)
+    orc.prolong(cfg, cc, b.bface, want_c, want_b, org, primitive=True)
+    s = athmhd.Solver(b.n, b.ng, (0.1,) * 3, b.gamma, nscalars=ns)   # the operators do not read dx
+    gc = torch.zeros(cc.shape, dtype=torch.float64, device=d)
+    gb = torch.zeros(b.bface.shape, dtype=torch.float64, device=d)
+    s.prolong(dev(torch, d, cc), dev(torch, d, b.bface), gc, gb, o, primitive=True)
+    got_c, got_b = gc.cpu().numpy(), gb.cpu().numpy()
+    assert np.array_equal(got_c[0], want_c[0])
+    for v in range(1, cc.shape[0]):
+        err = np.abs(got_c[v] - want_c[v]).max() / np.abs(want_c[v]).max()
+        assert err <= PRIM_TOL, (v, err)
+    check_prolong(got_c[:1], got_b, want_c[:1], want_b, want_c[:1], want_b, n, ng)
+
+
+def test_primitive_prolong_of_a_cold_state(torch_dev, athmhd, orc):
+    """The cold state that conserved prolongation drives negative: positive
+    pressure everywhere, and parity with the oracle; the floor counter stays
+    at zero with a floor set (primitive prolongation applies none)."""
+    torch, d = torch_dev
+    n, ng = (16, 12, 10), 2
+    N, F = shapes(n, ng)
+    cc, cb = cold_block(N, F, seed=73)
+    cfg = orc.make_cfg(n, ng, (0.1,) * 3, 5.0 / 3.0)
+    s = solver(athmhd, n, ng)
+    s.set_floors(0.0, 1e-5)
+    s.floor_count()
+    for o in [(0, 0, 0), (1, 1, 0)]:
+        org = tuple(o[k] * n[k] // 2 for k in range(3))
+        want_c, want_b = np.zeros_like(cc), np.zeros_like(cb)
+        orc.prolong(cfg, cc, cb, want_c, want_b, org, primitive=True)
+        gc = torch.zeros(cc.shape, dtype=torch.float64, device=d)
+        gb = torch.zeros(cb.shape, dtype=torch.float64, device=d)
+        s.prolong(dev(torch, d, cc), dev(torch, d, cb), gc, gb, o, primitive=True)
+        got_c, got_b = gc.cpu().numpy(), gb.cpu().numpy()
+        assert fine_pressure(got_c, got_b, n, ng).min() > 0
+        for v in range(5):
+            err = np.abs(got_c[v] - want_c[v]).max() / np.abs(want_c[v]).max()
+            assert err <= PRIM_TOL, (v, err)
+    assert s.floor_count() == 0
+
+
+def test_primitive_flag_is_checked(torch_dev, athmhd):
+    torch, d = torch_dev
+    import ctypes
+    n, ng = (8, 8, 8), 2
+    N, F = shapes(n, ng)
+    a = [torch.zeros((5,) + N, dtype=torch.float64, device=d) for _ in range(2)]
+    b = [torch.zeros((3,) + F, dtype=torch.float64, device=d) for _ in range(2)]
+    s = solver(athmhd, n, ng)
+    p = [ctypes.c_void_p(x.data_ptr()) for x in (a[0], b[0], a[1], b[1])]
+    rc = athmhd.lib().athmhd_prolong(s._h, *p, 0, 0, 0, 2, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == athmhd.EINVAL

@@ -350,3 +350,77 @@ def test_pressure_floor_on_refined_cells(orc, o):
     assert np.all(c1[4][a][low] > c0[4][a][low])
     assert np.all(p1 >= pf * (1 - 1e-9)), p1.min()
     assert np.abs(p1[low] - pf).max() <= 1e-9 * np.abs(c1[4][a]).max()
+
+
+def prims_of(cells, faces, n, ng, gamma=5.0 / 3.0):
+    """(rho, v1, v2, v3, P, C...) of every active cell from U and its
+    bounding faces."""
+    a = (slice(ng, ng + n[2]), slice(ng, ng + n[1]), slice(ng, ng + n[0]))
+    rho = cells[0][a]
+    out = [rho] + [cells[k][a] / rho for k in (1, 2, 3)]
+    out.append(pressure(cells, faces, n, ng, gamma))
+    out += [cells[k][a] / rho for k in range(5, cells.shape[0])]
+    return np.stack(out)
+
+
+def linear_prims(N, ng, h, coef, shift=(0, 0, 0)):
+    x, y, z = cell_centres(N, ng, h)
+    return np.stack([c[0] + c[1] * (x + shift[0]) + c[2] * (y + shift[1]) + c[3] * (z + shift[2]) for c in coef])
+
+
+PRIM_COEF = np.array([[1.0, 0.05, -0.03, 0.02], [0.3, 0.02, 0.01, -0.04], [-0.2, 0.01, 0.03, 0.02],
+                      [0.1, -0.02, 0.02, 0.01], [0.8, 0.03, 0.01, -0.02], [0.5, 0.04, -0.01, 0.03]])
+
+
+def cons_from_prims(w, faces, gamma=5.0 / 3.0):
+    """Conserved variables of every stored cell (ghosts included) from
+    primitives and the mean of the two stored faces bounding the cell."""
+    b1 = 0.5 * (faces[0][:-1, :-1, :-1] + faces[0][:-1, :-1, 1:])
+    b2 = 0.5 * (faces[1][:-1, :-1, :-1] + faces[1][:-1, 1:, :-1])
+    b3 = 0.5 * (faces[2][:-1, :-1, :-1] + faces[2][1:, :-1, :-1])
+    rho, v = w[0], w[1:4]
+    u = np.empty_like(w)
+    u[0] = rho
+    u[1:4] = rho * v
+    u[4] = w[4] / (gamma - 1.0) + 0.5 * rho * (v ** 2).sum(0) + 0.5 * (b1 ** 2 + b2 ** 2 + b3 ** 2)
+    u[5:] = rho * w[5:]
+    return u
+
+
+@pytest.mark.parametrize("o", [(0, 0, 0), (1, 0, 1), (0, 1, 1), (1, 1, 1)])
+def test_primitive_prolongation_of_linear_primitives_is_exact(orc, o):
+    """Linear rho, v, P and C with a linear divergence-free field: the
+    primitives of the fine cells (recovered from their U and fine faces) are
+    the linear fields at the fine centres."""
+    n, ng = (8, 6, 4), 2
+    cfg, N = geom(orc, n, ns=1)
+    M = np.array([[0.07, -0.13, 0.04], [0.21, -0.02, 0.09], [-0.06, 0.17, -0.05]])
+    b0 = np.array([0.3, -0.2, 0.25])
+    cb = linear_faces(N, ng, 1.0, M, b0)
+    cc = cons_from_prims(linear_prims(N, ng, 1.0, PRIM_COEF), cb)
+    org = oct_origin(n, o)
+    fc, fb = np.zeros_like(cc), np.zeros_like(cb)
+    orc.prolong(cfg, cc, cb, fc, fb, org, primitive=True)
+    got = prims_of(fc, fb, n, ng)
+    a = (slice(None), slice(ng, ng + n[2]), slice(ng, ng + n[1]), slice(ng, ng + n[0]))
+    want = linear_prims(N, ng, 0.5, PRIM_COEF, shift=org)[a]
+    assert np.abs(got - want).max() <= 1e-13
+
+
+def test_primitive_prolongation_keeps_pressure_positive(orc):
+    """The cold state whose conserved prolongation gives negative pressure:
+    prolonging P itself (minmod) keeps every refined cell positive; density
+    and faces are bitwise those of the conserved prolongation."""
+    n, ng = (8, 6, 4), 2
+    N = (n[2] + 2 * ng, n[1] + 2 * ng, n[0] + 2 * ng)
+    F = tuple(x + 1 for x in N)
+    cc, cb = cold_state(N, F, seed=61)
+    cfg = orc.make_cfg(n, ng, (0.1,) * 3, 5.0 / 3.0)
+    for o in [(0, 0, 0), (1, 1, 0)]:
+        org = oct_origin(n, o)
+        c0, b0 = prolong(orc, cfg, cc, cb, org)
+        c1, b1 = np.zeros_like(cc), np.zeros_like(cb)
+        orc.prolong(cfg, cc, cb, c1, b1, org, primitive=True)
+        assert (pressure(c0, b0, n, ng, 5.0 / 3.0) < 0).any()
+        assert pressure(c1, b1, n, ng, 5.0 / 3.0).min() > 0
+        assert np.array_equal(c1[0], c0[0]) and np.array_equal(b1, b0)
