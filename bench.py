@@ -42,11 +42,13 @@ STAGE_TRAFFIC = {"bytes_per_launch": 3.468e+09, "fetch_bytes_per_launch": 2.295e
                  "source_hash": "38a041e3236d4fb2"}
 # The same for the level operators on the 256^3 block (per octant launch).
 LEVELS_SOURCES = ("kernels_amr.hip", "common.hpp")
-LEVELS_TRAFFIC = {"prolong": {"bytes_per_launch": 1.644e+09, "fetch_bytes_per_launch": 4.028e+08,
+LEVELS_TRAFFIC = {"prolong": {"bytes_per_launch": 1.642e+09, "fetch_bytes_per_launch": 4.015e+08,
                               "write_bytes_per_launch": 1.241e+09},
                   "restrict": {"bytes_per_launch": 1.112e+09, "fetch_bytes_per_launch": 9.695e+08,
                                "write_bytes_per_launch": 1.423e+08},
-                  "fetch_scale": 1.9999, "write_scale": 1.0000, "source_hash": "39539a05d0c3f29f"}
+                  "prolong_primitive": {"bytes_per_launch": 1.798e+09, "fetch_bytes_per_launch": 5.611e+08,
+                                        "write_bytes_per_launch": 1.237e+09},
+                  "fetch_scale": 1.9999, "write_scale": 1.0000, "source_hash": "baae95cf55fecd72"}
 
 
 def parse():
@@ -447,7 +449,8 @@ def bench_levels(args):
     bytes_p, bytes_r = coarse * (9 * nv + 27) * 8, coarse * (9 * nv + 15) * 8
     gbs_p, gbs_r = bytes_p / (ms["prolong"] * 1e-3) / 1e9, bytes_r / (ms["restrict"] * 1e-3) / 1e9
     measured = LEVELS_TRAFFIC.get("source_hash") == stage_source_hash(LEVELS_SOURCES) and n == 256
-    traffic = {k: (LEVELS_TRAFFIC[k]["bytes_per_launch"] if measured else None) for k in ("prolong", "restrict")}
+    traffic = {k: (LEVELS_TRAFFIC[k]["bytes_per_launch"] if measured else None)
+               for k in ("prolong", "restrict", "prolong_primitive")}
     out = {
         "metric": "fine cells prolonged per second, FP64 MHD level operators (Sec. 2.1.5), 1 MI355X",
         "value": 8 * coarse / (ms["prolong"] * 1e-3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
@@ -464,7 +467,8 @@ def bench_levels(args):
                      "cells_per_s": coarse / (ms["restrict"] * 1e-3)},
         "prolong_primitive": {"ms_per_launch": ms["prolong_primitive"],
                               "GB/s": bytes_p / (ms["prolong_primitive"] * 1e-3) / 1e9,
-                              "frac": bytes_p / (ms["prolong_primitive"] * 1e-3) / 1e9 / 8000.0},
+                              "frac": bytes_p / (ms["prolong_primitive"] * 1e-3) / 1e9 / 8000.0,
+                              "traffic": traffic["prolong_primitive"], "alg_bytes_per_launch": bytes_p},
     }
     print(json.dumps(out))
 
