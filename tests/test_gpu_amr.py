@@ -370,3 +370,35 @@ def test_primitive_flag_is_checked(torch_dev, athmhd):
     p = [ctypes.c_void_p(x.data_ptr()) for x in (a[0], b[0], a[1], b[1])]
     rc = athmhd.lib().athmhd_prolong(s._h, *p, 0, 0, 0, 2, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
     assert rc == athmhd.EINVAL
+
+
+def test_level_operators_with_the_maximum_number_of_scalars(torch_dev, athmhd, orc):
+    """64 scalar rows: restriction and conserved prolongation bitwise, and
+    primitive prolongation within 1e-13, against the oracle."""
+    torch, d = torch_dev
+    n, ng, ns = (8, 6, 4), 2, 64
+    b = inputs.with_scalars(inputs.smooth_random(n=n, seed=81, ng=ng), ns, seed=82)
+    cfg = orc.cfg_for(b, nscalars=ns)
+    cc = orc.prim2cons(cfg, b.prim, b.bface)
+    s = athmhd.Solver(b.n, b.ng, (0.1,) * 3, b.gamma, nscalars=ns)
+    o = (1, 0, 1)
+    org = tuple(o[k] * n[k] // 2 for k in range(3))
+    for primitive in (False, True):
+        want_c, want_b = np.zeros_like(cc), np.zeros_like(b.bface)
+        orc.prolong(cfg, cc, b.bface, want_c, want_b, org, primitive=primitive)
+        gc = torch.zeros(cc.shape, dtype=torch.float64, device=d)
+        gb = torch.zeros(b.bface.shape, dtype=torch.float64, device=d)
+        s.prolong(dev(torch, d, cc), dev(torch, d, b.bface), gc, gb, o, primitive=primitive)
+        got_c, got_b = gc.cpu().numpy(), gb.cpu().numpy()
+        if primitive:
+            assert np.array_equal(got_c[0], want_c[0])
+            for v in range(1, cc.shape[0]):
+                assert np.abs(got_c[v] - want_c[v]).max() <= PRIM_TOL * np.abs(want_c[v]).max(), v
+            check_prolong(got_c[:1], got_b, want_c[:1], want_b, want_c[:1], want_b, n, ng)
+        else:
+            check_prolong(got_c, got_b, want_c, want_b, want_c, want_b, n, ng)
+    rc, rb = cc.copy(), b.bface.copy()
+    orc.restrict(cfg, want_c, want_b, rc, rb, org)
+    g2c, g2b = dev(torch, d, cc), dev(torch, d, b.bface)
+    s.restrict(dev(torch, d, want_c), dev(torch, d, want_b), g2c, g2b, o)
+    assert np.array_equal(g2c.cpu().numpy(), rc) and np.array_equal(g2b.cpu().numpy(), rb)

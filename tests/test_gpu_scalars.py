@@ -232,3 +232,29 @@ def test_turbulence_256_with_scalars_sampled_windows(torch_dev, athmhd, orc):
         worst = max(worst, max(errs))
     assert worst <= TOL
     s.close()
+
+
+@pytest.mark.parametrize("recon,integ", [("plm", "vl2"), ("ppm", "rk3")])
+def test_the_maximum_number_of_scalars(torch_dev, athmhd, orc, recon, integ):
+    """64 scalars, the largest count the library accepts, on a ragged block:
+    two steps against the oracle, every array at the 1e-12 bar."""
+    torch, dev = torch_dev
+    ng = 3 if recon == "ppm" else 2
+    ns = 64
+    b = inputs.with_scalars(inputs.smooth_random(n=(20, 12, 10), seed=67, ng=ng), ns, seed=68)
+    kw = dict(integrator=integ, recon=recon, riemann="hlld")
+    s = athmhd.Solver(b.n, b.ng, b.dx, b.gamma, nscalars=ns, **kw)
+    cfg = orc.cfg_for(b, nscalars=ns, **kw)
+    cons = orc.prim2cons(cfg, b.prim, b.bface)
+    tc, tb = to_dev(torch, dev, cons), to_dev(torch, dev, b.bface)
+    rc, rb = cons.copy(), b.bface.copy()
+    for _ in range(2):
+        dt, bad = orc.newdt(cfg, rc, rb)
+        assert bad == 0
+        assert orc.step(cfg, rc, rb, dt) == 0
+        s.step(tc, tb, dt)
+    a = act(b)
+    errs = rel_l1_each(tc.cpu().numpy()[a], rc[a]) + rel_l1_each(tb.cpu().numpy()[a], rb[a])
+    print("worst rel L1 over", len(errs), "arrays", max(errs), flush=True)
+    assert max(errs) <= TOL
+    s.close()
