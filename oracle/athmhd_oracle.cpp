@@ -1068,9 +1068,26 @@ template <class T> T minmod(const T& a, const T& b) {
   return T(0.0);
 }
 
-inline void restrict_octant(const Geo& g, const double* fc, const double* fb, double* cc, double* cb, const int o[3]) {
+// A box of the level operators: fine cells [f, f + 2 h) and coarse cells
+// [c, c + h) along each direction (stored indices, ghosts included); an
+// octant is f = ng, c = ng + o_d n_d / 2, h = n / 2.
+struct LevelBox {
+  int f[3], c[3], h[3];
+};
+
+inline LevelBox octant_box(const Geo& g, const int o[3]) {
+  LevelBox B;
+  for (int d = 0; d < 3; ++d) {
+    B.f[d] = g.ng;
+    B.c[d] = g.ng + o[d];
+    B.h[d] = g.n[d] / 2;
+  }
+  return B;
+}
+
+inline void restrict_box(const Geo& g, const double* fc, const double* fb, double* cc, double* cb, const LevelBox& B) {
   const size_t nc = g.ncell(), nf = g.nface();
-  const int h[3] = {g.n[0] / 2, g.n[1] / 2, g.n[2] / 2};
+  const int* h = B.h;
   for (int v = 0; v < g.nv; ++v)
     for (int c = 0; c < h[2]; ++c)
       for (int b = 0; b < h[1]; ++b)
@@ -1079,13 +1096,13 @@ inline void restrict_octant(const Geo& g, const double* fc, const double* fb, do
           for (int s3 = 0; s3 < 2; ++s3)
             for (int s2 = 0; s2 < 2; ++s2)
               for (int s1 = 0; s1 < 2; ++s1)
-                sum += fc[v * nc + g.c(g.ng + 2 * a + s1, g.ng + 2 * b + s2, g.ng + 2 * c + s3)];
-          cc[v * nc + g.c(g.ng + o[0] + a, g.ng + o[1] + b, g.ng + o[2] + c)] = sum / 8.0;
+                sum += fc[v * nc + g.c(B.f[0] + 2 * a + s1, B.f[1] + 2 * b + s2, B.f[2] + 2 * c + s3)];
+          cc[v * nc + g.c(B.c[0] + a, B.c[1] + b, B.c[2] + c)] = sum / 8.0;
         }
   for (int d = 0; d < 3; ++d) {
     const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
     int lim[3] = {h[0], h[1], h[2]};
-    lim[d] = h[d] + 1;  // the octant's upper faces too
+    lim[d] = h[d] + 1;  // the box's upper faces too
     for (int c = 0; c < lim[2]; ++c)
       for (int b = 0; b < lim[1]; ++b)
         for (int a = 0; a < lim[0]; ++a) {
@@ -1094,12 +1111,12 @@ inline void restrict_octant(const Geo& g, const double* fc, const double* fb, do
           for (int u = 0; u < 2; ++u)
             for (int w = 0; w < 2; ++w) {
               int f[3];
-              f[d] = g.ng + 2 * q[d];
-              f[t1] = g.ng + 2 * q[t1] + u;
-              f[t2] = g.ng + 2 * q[t2] + w;
+              f[d] = B.f[d] + 2 * q[d];
+              f[t1] = B.f[t1] + 2 * q[t1] + u;
+              f[t2] = B.f[t2] + 2 * q[t2] + w;
               sum += fb[d * nf + g.f(f[0], f[1], f[2])];
             }
-          cb[d * nf + g.f(g.ng + o[0] + a, g.ng + o[1] + b, g.ng + o[2] + c)] = sum / 4.0;
+          cb[d * nf + g.f(B.c[0] + a, B.c[1] + b, B.c[2] + c)] = sum / 4.0;
         }
   }
 }
@@ -1154,17 +1171,17 @@ inline void cell_field_stored(const Geo& g, const double* bf, int i, int j, int 
 // converted back to conserved variables with the cell-centred field of the
 // prolonged fine faces (Sec. 2.1.5 uses this between levels: conserved
 // values are exchanged, prolongation acts on primitives).
-inline void prolong_octant(const Geo& g, const double* cc, const double* cb, double* fc, double* fb, const int o[3],
-                           double gamma, double pfloor, bool primitive) {
+inline void prolong_box(const Geo& g, const double* cc, const double* cb, double* fc, double* fb, const LevelBox& B,
+                        double gamma, double pfloor, bool primitive) {
   const size_t nc = g.ncell(), nf = g.nface();
-  const int h[3] = {g.n[0] / 2, g.n[1] / 2, g.n[2] / 2};
+  const int* h = B.h;
   std::vector<double> wc, wf;
   if (primitive) {
     wc.assign(g.nv * nc, 0.0);
     wf.assign(g.nv * nc, 0.0);
-    for (int k = g.ng + o[2] - 1; k <= g.ng + o[2] + h[2]; ++k)
-      for (int j = g.ng + o[1] - 1; j <= g.ng + o[1] + h[1]; ++j)
-        for (int i = g.ng + o[0] - 1; i <= g.ng + o[0] + h[0]; ++i) {
+    for (int k = B.c[2] - 1; k <= B.c[2] + h[2]; ++k)
+      for (int j = B.c[1] - 1; j <= B.c[1] + h[1]; ++j)
+        for (int i = B.c[0] - 1; i <= B.c[0] + h[0]; ++i) {
           const size_t q = g.c(i, j, k);
           double b[3];
           cell_field_stored(g, cb, i, j, k, b);
@@ -1187,7 +1204,7 @@ inline void prolong_octant(const Geo& g, const double* cc, const double* cb, dou
     for (int c = 0; c < h[2]; ++c)
       for (int b = 0; b < h[1]; ++b)
         for (int a = 0; a < h[0]; ++a) {
-          const int C[3] = {g.ng + o[0] + a, g.ng + o[1] + b, g.ng + o[2] + c};
+          const int C[3] = {B.c[0] + a, B.c[1] + b, B.c[2] + c};
           const double u0 = src[v * nc + g.c(C[0], C[1], C[2])];
           double sl[3];
           for (int d = 0; d < 3; ++d) {
@@ -1199,7 +1216,7 @@ inline void prolong_octant(const Geo& g, const double* cc, const double* cb, dou
           for (int s3 = 0; s3 < 2; ++s3)
             for (int s2 = 0; s2 < 2; ++s2)
               for (int s1 = 0; s1 < 2; ++s1)
-                dst[v * nc + g.c(g.ng + 2 * a + s1, g.ng + 2 * b + s2, g.ng + 2 * c + s3)] =
+                dst[v * nc + g.c(B.f[0] + 2 * a + s1, B.f[1] + 2 * b + s2, B.f[2] + 2 * c + s3)] =
                     u0 + 0.25 * ((2 * s1 - 1) * sl[0] + (2 * s2 - 1) * sl[1] + (2 * s3 - 1) * sl[2]);
         }
   // outer fine faces: each coarse face of the octant (upper ones included)
@@ -1213,23 +1230,23 @@ inline void prolong_octant(const Geo& g, const double* cc, const double* cb, dou
       for (int b = 0; b < lim[1]; ++b)
         for (int a = 0; a < lim[0]; ++a) {
           const int q[3] = {a, b, c};
-          const int C[3] = {g.ng + o[0] + a, g.ng + o[1] + b, g.ng + o[2] + c};
-          const double B = cb[d * nf + g.f(C[0], C[1], C[2])];
+          const int C[3] = {B.c[0] + a, B.c[1] + b, B.c[2] + c};
+          const double b0 = cb[d * nf + g.f(C[0], C[1], C[2])];
           double sl[2];
           for (int e = 0; e < 2; ++e) {
             const int t = e == 0 ? t1 : t2;
             int m[3] = {C[0], C[1], C[2]}, p[3] = {C[0], C[1], C[2]};
             m[t] -= 1;
             p[t] += 1;
-            sl[e] = minmod(B - cb[d * nf + g.f(m[0], m[1], m[2])], cb[d * nf + g.f(p[0], p[1], p[2])] - B);
+            sl[e] = minmod(b0 - cb[d * nf + g.f(m[0], m[1], m[2])], cb[d * nf + g.f(p[0], p[1], p[2])] - b0);
           }
           for (int u = 0; u < 2; ++u)
             for (int w = 0; w < 2; ++w) {
               int f[3];
-              f[d] = g.ng + 2 * q[d];
-              f[t1] = g.ng + 2 * q[t1] + u;
-              f[t2] = g.ng + 2 * q[t2] + w;
-              fb[d * nf + g.f(f[0], f[1], f[2])] = B + 0.25 * ((2 * u - 1) * sl[0] + (2 * w - 1) * sl[1]);
+              f[d] = B.f[d] + 2 * q[d];
+              f[t1] = B.f[t1] + 2 * q[t1] + u;
+              f[t2] = B.f[t2] + 2 * q[t2] + w;
+              fb[d * nf + g.f(f[0], f[1], f[2])] = b0 + 0.25 * ((2 * u - 1) * sl[0] + (2 * w - 1) * sl[1]);
             }
         }
   }
@@ -1237,7 +1254,7 @@ inline void prolong_octant(const Geo& g, const double* cc, const double* cb, dou
   for (int c = 0; c < h[2]; ++c)
     for (int b = 0; b < h[1]; ++b)
       for (int a = 0; a < h[0]; ++a) {
-        const int base[3] = {g.ng + 2 * a, g.ng + 2 * b, g.ng + 2 * c};
+        const int base[3] = {B.f[0] + 2 * a, B.f[1] + 2 * b, B.f[2] + 2 * c};
         // face value of component d at fine offset (x, y, z) in {0, 1, 2} from base
         auto face = [&](int d, int x, int y, int z) -> double& {
           return fb[d * nf + g.f(base[0] + x, base[1] + y, base[2] + z)];
@@ -1331,9 +1348,9 @@ inline void prolong_octant(const Geo& g, const double* cc, const double* cb, dou
   // primitive prolongation: back to conserved variables with the fine
   // cell-centred field
   if (primitive)
-    for (int k = g.ng; k < g.ng + g.n[2]; ++k)
-      for (int j = g.ng; j < g.ng + g.n[1]; ++j)
-        for (int i = g.ng; i < g.ng + g.n[0]; ++i) {
+    for (int k = B.f[2]; k < B.f[2] + 2 * h[2]; ++k)
+      for (int j = B.f[1]; j < B.f[1] + 2 * h[1]; ++j)
+        for (int i = B.f[0]; i < B.f[0] + 2 * h[0]; ++i) {
           const size_t q = g.c(i, j, k);
           double b[3];
           cell_field_stored(g, fb, i, j, k, b);
@@ -1352,9 +1369,9 @@ inline void prolong_octant(const Geo& g, const double* cc, const double* cb, dou
   // faces (mean of the two bounding faces) is below pfloor, E is raised to
   // give pfloor; rho and M, hence mass and momentum, are unchanged.
   if (pfloor > 0.0 && !primitive)
-    for (int k = g.ng; k < g.ng + g.n[2]; ++k)
-      for (int j = g.ng; j < g.ng + g.n[1]; ++j)
-        for (int i = g.ng; i < g.ng + g.n[0]; ++i) {
+    for (int k = B.f[2]; k < B.f[2] + 2 * h[2]; ++k)
+      for (int j = B.f[1]; j < B.f[1] + 2 * h[1]; ++j)
+        for (int i = B.f[0]; i < B.f[0] + 2 * h[0]; ++i) {
           const size_t q = g.c(i, j, k);
           double b[3];
           for (int d = 0; d < 3; ++d) {
@@ -1479,7 +1496,21 @@ int orc_restrict(const orc::Cfg* c, const double* fcons, const double* fbface, d
                  int oy, int oz) {
   orc::Geo g(*c);
   const int o[3] = {ox, oy, oz};
-  orc::restrict_octant(g, fcons, fbface, ccons, cbface, o);
+  orc::restrict_box(g, fcons, fbface, ccons, cbface, orc::octant_box(g, o));
+  return 0;
+}
+
+// The same on a box: fine cells [flo, flo + 2 ext), coarse cells [clo, clo + ext).
+int orc_restrict_box(const orc::Cfg* c, const double* fcons, const double* fbface, double* ccons, double* cbface,
+                     const int* flo, const int* clo, const int* ext) {
+  orc::Geo g(*c);
+  orc::LevelBox B;
+  for (int d = 0; d < 3; ++d) {
+    B.f[d] = flo[d];
+    B.c[d] = clo[d];
+    B.h[d] = ext[d];
+  }
+  orc::restrict_box(g, fcons, fbface, ccons, cbface, B);
   return 0;
 }
 
@@ -1487,7 +1518,20 @@ int orc_prolong(const orc::Cfg* c, const double* ccons, const double* cbface, do
                 int oy, int oz, int primitive) {
   orc::Geo g(*c);
   const int o[3] = {ox, oy, oz};
-  orc::prolong_octant(g, ccons, cbface, fcons, fbface, o, c->gamma, c->pfloor, primitive != 0);
+  orc::prolong_box(g, ccons, cbface, fcons, fbface, orc::octant_box(g, o), c->gamma, c->pfloor, primitive != 0);
+  return 0;
+}
+
+int orc_prolong_box(const orc::Cfg* c, const double* ccons, const double* cbface, double* fcons, double* fbface,
+                    const int* flo, const int* clo, const int* ext, int primitive) {
+  orc::Geo g(*c);
+  orc::LevelBox B;
+  for (int d = 0; d < 3; ++d) {
+    B.f[d] = flo[d];
+    B.c[d] = clo[d];
+    B.h[d] = ext[d];
+  }
+  orc::prolong_box(g, ccons, cbface, fcons, fbface, B, c->gamma, c->pfloor, primitive != 0);
   return 0;
 }
 

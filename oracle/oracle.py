@@ -65,6 +65,9 @@ def lib():
         _lib.orc_char_ppm.argtypes = [C.c_double, P, C.c_double, P, P]
         _lib.orc_restrict.argtypes = [cp, P, P, P, P, C.c_int, C.c_int, C.c_int]
         _lib.orc_prolong.argtypes = [cp, P, P, P, P, C.c_int, C.c_int, C.c_int, C.c_int]
+        I3 = C.POINTER(C.c_int)
+        _lib.orc_restrict_box.argtypes = [cp, P, P, P, P, I3, I3, I3]
+        _lib.orc_prolong_box.argtypes = [cp, P, P, P, P, I3, I3, I3, C.c_int]
         _lib.orc_drive_scalar.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_int,
                                           P, P]
         _lib.orc_take_floor_count.restype = C.c_longlong
@@ -224,6 +227,27 @@ def prolong(cfg: Cfg, ccons, cbface, fcons, fbface, octant, primitive: bool = Fa
         _check(cfg, x, y)
     lib().orc_prolong(C.byref(cfg), _p(ccons), _p(cbface), _p(fcons), _p(fbface), *[int(v) for v in octant],
                       int(bool(primitive)))
+
+
+def _box(flo, clo, ext):
+    return [(C.c_int * 3)(*[int(x) for x in v]) for v in (flo, clo, ext)]
+
+
+def restrict_box(cfg: Cfg, fcons, fbface, ccons, cbface, flo, clo, ext) -> None:
+    """Restrict fine cells [flo, flo + 2 ext) (stored (x1, x2, x3) indices,
+    ghosts included) onto coarse cells [clo, clo + ext), in place."""
+    for x, y in ((fcons, fbface), (ccons, cbface)):
+        _check(cfg, x, y)
+    lib().orc_restrict_box(C.byref(cfg), _p(fcons), _p(fbface), _p(ccons), _p(cbface), *_box(flo, clo, ext))
+
+
+def prolong_box(cfg: Cfg, ccons, cbface, fcons, fbface, flo, clo, ext, primitive: bool = False) -> None:
+    """Prolong coarse cells [clo, clo + ext) onto fine cells [flo, flo + 2 ext)
+    and their faces, in place."""
+    for x, y in ((fcons, fbface), (ccons, cbface)):
+        _check(cfg, x, y)
+    lib().orc_prolong_box(C.byref(cfg), _p(ccons), _p(cbface), _p(fcons), _p(fbface), *_box(flo, clo, ext),
+                          int(bool(primitive)))
 
 
 def drive_scalar(integrator: str, lam: complex, dt: float, nsteps: int) -> complex:

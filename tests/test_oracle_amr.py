@@ -424,3 +424,96 @@ def test_primitive_prolongation_keeps_pressure_positive(orc):
         assert (pressure(c0, b0, n, ng, 5.0 / 3.0) < 0).any()
         assert pressure(c1, b1, n, ng, 5.0 / 3.0).min() > 0
         assert np.array_equal(c1[0], c0[0]) and np.array_equal(b1, b0)
+
+
+# ---- boxes: the same operators between any even-aligned fine box and a
+# coarse box, ghost zones included (coarse buffers, ghost-zone prolongation)
+
+def test_octant_calls_are_boxes(orc):
+    n, ng = (8, 6, 4), 2
+    cfg, N = geom(orc, n, ns=1)
+    cc, cb = random_block(N, 6, seed=91)
+    o = (1, 0, 1)
+    org = oct_origin(n, o)
+    a = prolong(orc, cfg, cc, cb, org)
+    fc, fb = np.zeros_like(cc), np.zeros_like(cb)
+    orc.prolong_box(cfg, cc, cb, fc, fb, (ng,) * 3, tuple(ng + x for x in org), tuple(x // 2 for x in n))
+    assert np.array_equal(fc, a[0]) and np.array_equal(fb, a[1])
+    r1c, r1b = cc.copy(), cb.copy()
+    r2c, r2b = cc.copy(), cb.copy()
+    orc.restrict(cfg, a[0], a[1], r1c, r1b, org)
+    orc.restrict_box(cfg, a[0], a[1], r2c, r2b, (ng,) * 3, tuple(ng + x for x in org), tuple(x // 2 for x in n))
+    assert np.array_equal(r1c, r2c) and np.array_equal(r1b, r2b)
+
+
+def coarse_linear(N, coef):
+    """Linear cell fields of the stored index (coarse cell C has centre C + 1/2)."""
+    z, y, x = np.meshgrid(*[np.arange(m) + 0.5 for m in N], indexing="ij")
+    return np.stack([c[0] + c[1] * x + c[2] * y + c[3] * z for c in coef])
+
+
+def test_restriction_into_the_coarse_ghost_zone(orc):
+    """A fine boundary layer (4 fine cells thick) restricted into the coarse
+    block's upper x1 ghost zone (2 cells), as for a coarse buffer: linear
+    fields exact, nothing outside the box written."""
+    n, ng = (8, 8, 8), 4
+    cfg, N = geom(orc, n, ng=ng)
+    coef = [[0.3, 1.5, -2.0, 0.7], [1.0, 0.2, 0.9, -0.4], [2.0, -0.3, 0.1, 1.1], [0.5, 0.0, 0.3, 0.0],
+            [1.0, 3.0, 2.0, 1.0]]
+    flo, clo, ext = (ng + n[0] - 4, ng, ng), (ng + n[0], ng + 2, ng), (2, 4, 4)
+    # fine fields: linear in the coarse coordinate of each fine centre
+    z, y, x = np.meshgrid(*[np.arange(m) for m in N], indexing="ij")
+    xf = [clo[d] + ([x, y, z][d] - flo[d]) / 2.0 + 0.25 for d in range(3)]
+    fc = np.stack([c[0] + c[1] * xf[0] + c[2] * xf[1] + c[3] * xf[2] for c in coef])
+    _, fb = random_block(N, 5, seed=92)
+    cc = np.full((5,) + N, 7.0)
+    cb = np.full((3,) + tuple(m + 1 for m in N), 7.0)
+    orc.restrict_box(cfg, fc, fb, cc, cb, flo, clo, ext)
+    want = coarse_linear(N, coef)
+    s = (slice(clo[2], clo[2] + ext[2]), slice(clo[1], clo[1] + ext[1]), slice(clo[0], clo[0] + ext[0]))
+    assert np.abs(cc[(slice(None),) + s] - want[(slice(None),) + s]).max() <= 1e-13
+    mask = np.zeros(N, bool)
+    mask[s] = True
+    assert np.all(cc[:, ~mask] == 7.0)
+
+
+def test_prolongation_into_the_fine_ghost_zone(orc):
+    """Coarse cells (ghosts of the coarse neighbour included) prolonged into
+    the fine block's lower x1 ghost zone: linear cells and divergence-free
+    linear faces exact, each fine cell with its parent's divergence, nothing
+    outside the box written."""
+    n, ng = (8, 8, 8), 4
+    cfg, N = geom(orc, n, ng=ng)
+    F = tuple(m + 1 for m in N)
+    coef = [[0.3, 1.5, -2.0, 0.7], [1.0, 0.2, 0.9, -0.4], [2.0, -0.3, 0.1, 1.1], [0.5, 0.0, 0.3, 0.0],
+            [1.0, 3.0, 2.0, 1.0]]
+    cc = coarse_linear(N, coef)
+    M = np.array([[0.7, -1.3, 0.4], [2.1, -0.2, 0.9], [-0.6, 1.7, -0.5]])
+    b0 = np.array([0.3, -0.8, 1.2])
+    cb = linear_faces(N, 0, 1.0, M, b0)          # coarse face positions: stored index
+    flo, clo, ext = (0, ng, ng), (5, 3, 6), (2, 4, 3)
+    fc = np.full((5,) + N, 7.0)
+    fb = np.full((3,) + F, 7.0)
+    orc.prolong_box(cfg, cc, cb, fc, fb, flo, clo, ext)
+    s = tuple(slice(flo[d], flo[d] + 2 * ext[d]) for d in (2, 1, 0))
+    z, y, x = np.meshgrid(*[np.arange(m) for m in N], indexing="ij")
+    xf = [clo[d] + ([x, y, z][d] - flo[d]) / 2.0 + 0.25 for d in range(3)]
+    want = np.stack([c[0] + c[1] * xf[0] + c[2] * xf[1] + c[3] * xf[2] for c in coef])
+    assert np.abs(fc[(slice(None),) + s] - want[(slice(None),) + s]).max() <= 1e-13
+    mask = np.zeros(N, bool)
+    mask[s] = True
+    assert np.all(fc[:, ~mask] == 7.0)
+    # faces: the fine face at fine index i along d sits at coarse coordinate
+    # clo_d + (i - flo_d) / 2; transverse centres as for cells
+    zf, yf, xf_ = np.meshgrid(*[np.arange(m) for m in F], indexing="ij")
+    idx = [xf_, yf, zf]
+    for d in range(3):
+        pos = [clo[e] + (idx[e] - flo[e]) / 2.0 + (0.0 if e == d else 0.25) for e in range(3)]
+        wantd = b0[d] + M[d][0] * pos[0] + M[d][1] * pos[1] + M[d][2] * pos[2]
+        e = [0, 0, 0]
+        e[d] = 1
+        sf = tuple(slice(flo[k], flo[k] + 2 * ext[k] + e[k]) for k in (2, 1, 0))
+        assert np.abs(fb[d][sf] - wantd[sf]).max() <= 2e-14, d
+        m = np.zeros(F, bool)
+        m[sf] = True
+        assert np.all(fb[d][~m] == 7.0)
