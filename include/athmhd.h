@@ -333,6 +333,30 @@ ATHMHD_API int athmhd_restrict(athmhd_t h, const double* fine_cons, const double
 ATHMHD_API int athmhd_prolong(athmhd_t h, const double* coarse_cons, const double* coarse_bface, double* fine_cons,
                               double* fine_bface, int o1, int o2, int o3, int primitive, void* stream);
 
+/* The same operators on a box, for the coarse buffers and ghost zones of
+ * blocks at different levels (Sec. 2.1.2, 2.1.5).  fine_lo, coarse_lo and
+ * extent are host arrays of 3 ints (x1, x2, x3): fine cells
+ * [fine_lo, fine_lo + 2 extent) correspond to coarse cells
+ * [coarse_lo, coarse_lo + extent), in stored indices with the ghost zones
+ * included (index ng is the first active cell).  athmhd_restrict_box writes
+ * those coarse cells and the coarse faces of the box (upper ones included);
+ * athmhd_prolong_box writes those fine cells and their faces (upper ones
+ * included) and reads the coarse box plus one cell on each side.  Everything
+ * touched must lie in the stored arrays, else ATHMHD_EINVAL: extent >= 1,
+ * 0 <= fine_lo, fine_lo + 2 extent <= N_d (N_d = n_d + 2 nghost); for
+ * restriction 0 <= coarse_lo, coarse_lo + extent <= N_d; for prolongation
+ * 1 <= coarse_lo, coarse_lo + extent <= N_d - 1.  Block sizes need not be
+ * even.  The octant calls above are the box fine_lo = nghost,
+ * coarse_lo = nghost + o_d n_d / 2, extent = n_d / 2.  Other rules (handles,
+ * distinct arrays, cubic cells for prolongation, primitive, the pressure
+ * floor) as above. */
+ATHMHD_API int athmhd_restrict_box(athmhd_t h, const double* fine_cons, const double* fine_bface, double* coarse_cons,
+                                   double* coarse_bface, const int* fine_lo, const int* coarse_lo, const int* extent,
+                                   void* stream);
+ATHMHD_API int athmhd_prolong_box(athmhd_t h, const double* coarse_cons, const double* coarse_bface, double* fine_cons,
+                                  double* fine_bface, const int* fine_lo, const int* coarse_lo, const int* extent,
+                                  int primitive, void* stream);
+
 /* Text of the last error recorded on `h` (or of the last failed create when
  * h is NULL).  Valid until the next call on the same handle. */
 ATHMHD_API const char* athmhd_last_error(athmhd_t h);

@@ -22,7 +22,8 @@ EXPORTED = ["athmhd_version", "athmhd_create", "athmhd_create_batch", "athmhd_ba
             "athmhd_batch_set_tile", "athmhd_batch_tune", "athmhd_set_graph", "athmhd_step", "athmhd_newdt",
             "athmhd_prim2cons", "athmhd_fill_ghosts", "athmhd_profile", "athmhd_last_error", "athmhd_destroy",
             "athmhd_step_vjp", "athmhd_prim2cons_vjp", "athmhd_set_floors", "athmhd_floor_count",
-            "athmhd_step_stages", "athmhd_create_mesh", "athmhd_restrict", "athmhd_prolong"]
+            "athmhd_step_stages", "athmhd_create_mesh", "athmhd_restrict", "athmhd_prolong",
+            "athmhd_restrict_box", "athmhd_prolong_box"]
 BATCH_TILES = [(16, 12), (12, 16), (14, 14), (16, 8)]  # active columns of the batch tile candidates
 
 
@@ -78,6 +79,9 @@ def lib():
         L.athmhd_profile.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]
         L.athmhd_restrict.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_int, C.c_int, vp]
         L.athmhd_prolong.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, vp]
+        I3 = C.POINTER(C.c_int)
+        L.athmhd_restrict_box.argtypes = [vp, vp, vp, vp, vp, I3, I3, I3, vp]
+        L.athmhd_prolong_box.argtypes = [vp, vp, vp, vp, vp, I3, I3, I3, C.c_int, vp]
         L.athmhd_last_error.argtypes = [vp]
         L.athmhd_last_error.restype = C.c_char_p
         L.athmhd_destroy.argtypes = [vp]
@@ -207,6 +211,28 @@ class Solver:
         fc, fb = self._one_block(fine_cons, fine_bface)
         o = [int(x) for x in octant]
         _check(lib().athmhd_prolong(self._h, cc, cb, fc, fb, *o, int(bool(primitive)), _stream(stream)), self._h)
+
+    @staticmethod
+    def _box(fine_lo, coarse_lo, extent):
+        return [(C.c_int * 3)(*[int(x) for x in v]) for v in (fine_lo, coarse_lo, extent)]
+
+    def restrict_box(self, fine_cons, fine_bface, coarse_cons, coarse_bface, fine_lo, coarse_lo, extent,
+                     stream=None) -> None:
+        """Restrict fine cells [fine_lo, fine_lo + 2 extent) onto coarse cells
+        [coarse_lo, coarse_lo + extent) (stored (x1, x2, x3) indices, ghosts included)."""
+        fc, fb = self._one_block(fine_cons, fine_bface)
+        cc, cb = self._one_block(coarse_cons, coarse_bface)
+        _check(lib().athmhd_restrict_box(self._h, fc, fb, cc, cb, *self._box(fine_lo, coarse_lo, extent),
+                                         _stream(stream)), self._h)
+
+    def prolong_box(self, coarse_cons, coarse_bface, fine_cons, fine_bface, fine_lo, coarse_lo, extent,
+                    primitive=False, stream=None) -> None:
+        """Prolong coarse cells [coarse_lo, coarse_lo + extent) onto fine cells
+        [fine_lo, fine_lo + 2 extent) and their faces."""
+        cc, cb = self._one_block(coarse_cons, coarse_bface)
+        fc, fb = self._one_block(fine_cons, fine_bface)
+        _check(lib().athmhd_prolong_box(self._h, cc, cb, fc, fb, *self._box(fine_lo, coarse_lo, extent),
+                                        int(bool(primitive)), _stream(stream)), self._h)
 
     @property
     def extra_stages(self) -> int:

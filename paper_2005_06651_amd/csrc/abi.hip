@@ -455,7 +455,7 @@ int alloc_adjoint(athmhd_t h) {
 
 extern "C" {
 
-int athmhd_version(void) { return 106; }
+int athmhd_version(void) { return 107; }
 
 int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
   if (!out) return fail(nullptr, ATHMHD_EINVAL, "out is NULL");
@@ -855,10 +855,9 @@ int athmhd_step_vjp(athmhd_t h, const double* cons_n, const double* bface_n, dou
 
 namespace {
 
-// Shared checks of the two level operators: a uniform handle, even block
-// sizes, an octant of 0/1 flags and four distinct arrays.
-int check_level(athmhd_t h, const void* a, const void* b, const void* c, const void* d, const int oct[3],
-                bool cubic) {
+// Shared checks of the level operators: a uniform handle, four distinct
+// arrays, and (prolongation) cubic cells.
+int check_level_arrays(athmhd_t h, const void* a, const void* b, const void* c, const void* d, bool cubic) {
   if (!h) return ATHMHD_EINVAL;
   if (h->batch || h->mesh) return fail(h, ATHMHD_EUNSUP, "level operators act on athmhd_create handles");
   if (!a || !b || !c || !d) return fail(h, ATHMHD_EINVAL, "NULL array argument");
@@ -866,38 +865,108 @@ int check_level(athmhd_t h, const void* a, const void* b, const void* c, const v
   for (int i = 0; i < 4; ++i)
     for (int j = i + 1; j < 4; ++j)
       if (p[i] == p[j]) return fail(h, ATHMHD_EINVAL, "the four arrays must be distinct");
-  const Geo& g = h->g;
-  if (g.n1 % 2 || g.n2 % 2 || g.n3 % 2)
-    return fail(h, ATHMHD_EINVAL, "block sizes must be even (got %d x %d x %d)", g.n1, g.n2, g.n3);
-  for (int k = 0; k < 3; ++k)
-    if (oct[k] != 0 && oct[k] != 1) return fail(h, ATHMHD_EINVAL, "octant flags must be 0 or 1 (got %d)", oct[k]);
   if (cubic) {
+    const Geo& g = h->g;
     const double lo = std::min(g.dx1, std::min(g.dx2, g.dx3)), hi = std::max(g.dx1, std::max(g.dx2, g.dx3));
     if (hi - lo > 1e-12 * hi) return fail(h, ATHMHD_EUNSUP, "face prolongation needs cubic cells (dx1 = dx2 = dx3)");
   }
   return ATHMHD_OK;
 }
 
+// Every index a box operator touches lies in the stored arrays: fine cells
+// [flo, flo + 2 ext) and their faces up to flo + 2 ext; coarse cells
+// [clo, clo + ext) and faces up to clo + ext, and for prolongation one more
+// cell (with its upper faces) on each side.
+int check_level_box(athmhd_t h, const int* flo, const int* clo, const int* ext, bool prolong) {
+  if (!flo || !clo || !ext) return fail(h, ATHMHD_EINVAL, "NULL box argument");
+  const Geo& g = h->g;
+  const int N[3] = {g.N1, g.N2, g.N3};
+  for (int d = 0; d < 3; ++d) {
+    if (ext[d] < 1) return fail(h, ATHMHD_EINVAL, "box extent must be >= 1 (got %d along x%d)", ext[d], d + 1);
+    if (flo[d] < 0 || (long)flo[d] + 2L * ext[d] > N[d])
+      return fail(h, ATHMHD_EINVAL, "fine box [%d, %ld) outside the %d stored cells along x%d", flo[d],
+                  (long)flo[d] + 2L * ext[d], N[d], d + 1);
+    const int lo = prolong ? 1 : 0, hi = prolong ? N[d] - 1 : N[d];
+    if (clo[d] < lo || (long)clo[d] + ext[d] > hi)
+      return fail(h, ATHMHD_EINVAL, "coarse box [%d, %ld) along x%d needs [%d, %d]%s", clo[d], (long)clo[d] + ext[d],
+                  d + 1, lo, hi, prolong ? " (prolongation reads one neighbour on each side)" : "");
+  }
+  return ATHMHD_OK;
+}
+
+// The box of octant oct: fine active cells onto coarse active cells
+// [ng + o_d n_d / 2, ng + (o_d + 1) n_d / 2).
+int octant_box(athmhd_t h, const int oct[3], int flo[3], int clo[3], int ext[3]) {
+  const Geo& g = h->g;
+  if (g.n1 % 2 || g.n2 % 2 || g.n3 % 2)
+    return fail(h, ATHMHD_EINVAL, "block sizes must be even (got %d x %d x %d)", g.n1, g.n2, g.n3);
+  const int n[3] = {g.n1, g.n2, g.n3};
+  for (int k = 0; k < 3; ++k) {
+    if (oct[k] != 0 && oct[k] != 1) return fail(h, ATHMHD_EINVAL, "octant flags must be 0 or 1 (got %d)", oct[k]);
+    ext[k] = n[k] / 2;
+    flo[k] = g.ng;
+    clo[k] = g.ng + oct[k] * ext[k];
+  }
+  return ATHMHD_OK;
+}
+
+int restrict_box(athmhd_t h, const double* fc, const double* fb, double* cc, double* cb, const int* flo,
+                 const int* clo, const int* ext, void* stream) {
+  int rc = check_level_box(h, flo, clo, ext, false);
+  if (rc) return rc;
+  hipError_t e = launch_restrict(h->g, flo, clo, ext, fc, fb, cc, cb, (hipStream_t)stream);
+  return e == hipSuccess ? ATHMHD_OK : hip_fail(h, e, "restrict launch");
+}
+
+int prolong_box(athmhd_t h, const double* cc, const double* cb, double* fc, double* fb, const int* flo,
+                const int* clo, const int* ext, int primitive, void* stream) {
+  if (primitive != 0 && primitive != 1) return fail(h, ATHMHD_EINVAL, "primitive must be 0 or 1 (got %d)", primitive);
+  int rc = check_level_box(h, flo, clo, ext, true);
+  if (rc) return rc;
+  hipError_t e = launch_prolong(h->g, flo, clo, ext, cc, cb, fc, fb, primitive == 1, h->cfg.gamma, h->floors.p,
+                                h->d_bad, (hipStream_t)stream);
+  return e == hipSuccess ? ATHMHD_OK : hip_fail(h, e, "prolong launch");
+}
+
 }  // namespace
 
 int athmhd_restrict(athmhd_t h, const double* fine_cons, const double* fine_bface, double* coarse_cons,
                     double* coarse_bface, int o1, int o2, int o3, void* stream) {
-  const int oct[3] = {o1, o2, o3};
-  int rc = check_level(h, fine_cons, fine_bface, coarse_cons, coarse_bface, oct, false);
+  int rc = check_level_arrays(h, fine_cons, fine_bface, coarse_cons, coarse_bface, false);
   if (rc) return rc;
-  hipError_t e = launch_restrict(h->g, oct, fine_cons, fine_bface, coarse_cons, coarse_bface, (hipStream_t)stream);
-  return e == hipSuccess ? ATHMHD_OK : hip_fail(h, e, "restrict launch");
+  const int oct[3] = {o1, o2, o3};
+  int flo[3], clo[3], ext[3];
+  rc = octant_box(h, oct, flo, clo, ext);
+  if (rc) return rc;
+  return restrict_box(h, fine_cons, fine_bface, coarse_cons, coarse_bface, flo, clo, ext, stream);
 }
 
 int athmhd_prolong(athmhd_t h, const double* coarse_cons, const double* coarse_bface, double* fine_cons,
                    double* fine_bface, int o1, int o2, int o3, int primitive, void* stream) {
-  const int oct[3] = {o1, o2, o3};
-  int rc = check_level(h, coarse_cons, coarse_bface, fine_cons, fine_bface, oct, true);
+  int rc = check_level_arrays(h, coarse_cons, coarse_bface, fine_cons, fine_bface, true);
   if (rc) return rc;
-  if (primitive != 0 && primitive != 1) return fail(h, ATHMHD_EINVAL, "primitive must be 0 or 1 (got %d)", primitive);
-  hipError_t e = launch_prolong(h->g, oct, coarse_cons, coarse_bface, fine_cons, fine_bface, primitive == 1,
-                                h->cfg.gamma, h->floors.p, h->d_bad, (hipStream_t)stream);
-  return e == hipSuccess ? ATHMHD_OK : hip_fail(h, e, "prolong launch");
+  const int oct[3] = {o1, o2, o3};
+  int flo[3], clo[3], ext[3];
+  rc = octant_box(h, oct, flo, clo, ext);
+  if (rc) return rc;
+  return prolong_box(h, coarse_cons, coarse_bface, fine_cons, fine_bface, flo, clo, ext, primitive, stream);
+}
+
+int athmhd_restrict_box(athmhd_t h, const double* fine_cons, const double* fine_bface, double* coarse_cons,
+                        double* coarse_bface, const int* fine_lo, const int* coarse_lo, const int* extent,
+                        void* stream) {
+  int rc = check_level_arrays(h, fine_cons, fine_bface, coarse_cons, coarse_bface, false);
+  if (rc) return rc;
+  return restrict_box(h, fine_cons, fine_bface, coarse_cons, coarse_bface, fine_lo, coarse_lo, extent, stream);
+}
+
+int athmhd_prolong_box(athmhd_t h, const double* coarse_cons, const double* coarse_bface, double* fine_cons,
+                       double* fine_bface, const int* fine_lo, const int* coarse_lo, const int* extent, int primitive,
+                       void* stream) {
+  int rc = check_level_arrays(h, coarse_cons, coarse_bface, fine_cons, fine_bface, true);
+  if (rc) return rc;
+  return prolong_box(h, coarse_cons, coarse_bface, fine_cons, fine_bface, fine_lo, coarse_lo, extent, primitive,
+                     stream);
 }
 
 int athmhd_prim2cons_vjp(athmhd_t h, const double* prim, const double* bface, const double* g_cons, double* g_prim,

@@ -22,13 +22,15 @@ hipError_t launch_fill_ghosts(const Geo& g, double* cons, double* bface, int nb,
 // ghost exchange of the coupled mesh g.mesh[0] x g.mesh[1] x g.mesh[2]: the w
 // ghost layers nearest each block's active box (w outside [1, ng]: all ng)
 hipError_t launch_mesh_ghosts(const Geo& g, int w, double* cons, double* bface, hipStream_t s);
-// Level operators of block refinement on one octant (0 or 1 per direction).
-hipError_t launch_restrict(const Geo& g, const int oct[3], const double* fc, const double* fb, double* cc, double* cb,
-                           hipStream_t s);
+// Level operators of block refinement on a box: fine cells [flo, flo + 2 ext)
+// <-> coarse cells [clo, clo + ext) (stored indices, checked by the caller).
+hipError_t launch_restrict(const Geo& g, const int flo[3], const int clo[3], const int ext[3], const double* fc,
+                           const double* fb, double* cc, double* cb, hipStream_t s);
 // primitive: prolong (rho, v, P, C_i) instead of U; otherwise pfloor > 0
 // applies the pressure floor to the refined cells, activations in bad[1].
-hipError_t launch_prolong(const Geo& g, const int oct[3], const double* cc, const double* cb, double* fc, double* fb,
-                          bool primitive, double gamma, double pfloor, int* bad, hipStream_t s);
+hipError_t launch_prolong(const Geo& g, const int flo[3], const int clo[3], const int ext[3], const double* cc,
+                          const double* cb, double* fc, double* fb, bool primitive, double gamma, double pfloor, int* bad,
+                          hipStream_t s);
 hipError_t launch_prim2cons(const Geo& g, double gamma, const double* prim, const double* bface, double* cons,
                             int nb, hipStream_t s);
 // dt_bits: device uint64 holding the bit pattern of the running minimum of

@@ -1,11 +1,14 @@
-// Level operators of block refinement (Sec. 2.1.5): restriction of a fine
-// block onto one octant of its coarse parent, and prolongation of that octant
-// onto the fine block.  Both blocks have the same shape (n1 x n2 x n3 active
-// cells, ng ghosts, 5 + ns cell arrays); the fine cells are half as wide, and
-// octant (o1, o2, o3) of the coarse block covers active coarse cells
-// [o_d n_d / 2, (o_d + 1) n_d / 2) along each direction d.
+// Level operators of block refinement (Sec. 2.1.5) on a box: restriction of
+// fine cells [f, f + 2 h) of a fine block onto coarse cells [c, c + h) of a
+// coarse block, and prolongation the other way (stored indices, ghost zones
+// included).  Both blocks have the same shape (n1 x n2 x n3 active cells, ng
+// ghosts, 5 + ns cell arrays); the fine cells are half as wide.  An octant
+// (o1, o2, o3) of a coarse parent is the box f = ng, c = ng + o_d n_d / 2,
+// h = n / 2; boxes in ghost zones serve the coarse buffers and ghost-zone
+// prolongation between levels.  The host checks every box against the
+// stored ranges before a launch.
 //
-// One thread per coarse cell of the octant (plus one layer beyond its upper
+// One thread per coarse cell of the box (plus one layer beyond its upper
 // side for the faces there).  These run once per refinement or derefinement
 // of a block, not per step: plain HBM-bound kernels, rows of threads along x1
 // so that the fine reads and writes of neighbouring threads are contiguous.
@@ -20,15 +23,16 @@ constexpr int kAmrThreads = 256;
 
 struct OctArgs {
   Geo g;
-  int h[3];     // octant extent n_d / 2
-  int o[3];     // first active coarse cell of the octant, o_d n_d / 2
+  int h[3];     // box extent in coarse cells
+  int cl[3];    // first coarse cell of the box (stored index)
+  int fl[3];    // first fine cell of the box (stored index)
   int per_xcd;  // workgroups per XCD: ceil(workgroups / 8)
   double gm1;     // gamma - 1
   double pfloor;  // pressure floor of the refined cells (prolongation; 0: off)
   int* bad;       // bad[1] counts floor activations
 };
 
-// Thread index in the octant's point order, XCD-aware: workgroup b runs on
+// Thread index in the box's point order, XCD-aware: workgroup b runs on
 // XCD b mod 8, so logical workgroup (b mod 8) per_xcd + b / 8 gives each XCD
 // one contiguous run of rows and planes, and the neighbour rows and planes a
 // thread reads sit in that XCD's L2.  Launched with 8 per_xcd workgroups.
@@ -49,7 +53,7 @@ __device__ __forceinline__ int fidx(const Geo& g, const int p[3]) { return g.f(p
 
 // Restriction: volume average of the 8 fine cells of each coarse cell (every
 // cell array), area average of the 4 fine faces on each coarse face of the
-// octant, upper faces included.
+// box, upper faces included.
 __global__ void __launch_bounds__(kAmrThreads)
     k_restrict(OctArgs A, const double* __restrict__ fc, const double* __restrict__ fb, double* __restrict__ cc,
                double* __restrict__ cb) {
@@ -58,10 +62,9 @@ __global__ void __launch_bounds__(kAmrThreads)
   const int t = oct_thread(A);
   if (t >= e1 * e2 * e3) return;
   const int q[3] = {t % e1, (t / e1) % e2, t / (e1 * e2)};
-  const int ng = g.ng;
   const bool cell = q[0] < A.h[0] && q[1] < A.h[1] && q[2] < A.h[2];
-  const int C[3] = {ng + A.o[0] + q[0], ng + A.o[1] + q[1], ng + A.o[2] + q[2]};
-  const int F[3] = {ng + 2 * q[0], ng + 2 * q[1], ng + 2 * q[2]};
+  const int C[3] = {A.cl[0] + q[0], A.cl[1] + q[1], A.cl[2] + q[2]};
+  const int F[3] = {A.fl[0] + 2 * q[0], A.fl[1] + 2 * q[1], A.fl[2] + 2 * q[2]};
   if (cell) {
     const int nv = 5 + g.ns;
     for (int v = 0; v < nv; ++v) {
@@ -116,7 +119,7 @@ __device__ __forceinline__ void split_face(const Geo& g, const double* cb, int d
 
 // Prolongation.  Cells: U_C plus the minmod-limited slope along each
 // direction times the child's offset +-1/4.  Faces: every coarse face of the
-// octant split into 4 by split_face; the 12 faces inside each coarse cell in
+// box split into 4 by split_face; the 12 faces inside each coarse cell in
 // closed form.  Those are the one solution of Toth & Roe's conditions (every
 // fine cell has the coarse cell's divergence; the curl at each of the 6
 // interior edges equals the mean of the tangential differences on the two
@@ -181,10 +184,9 @@ __global__ void __launch_bounds__(kAmrThreads)
   const int t = oct_thread(A);
   if (t >= e1 * e2 * e3) return;
   const int q[3] = {t % e1, (t / e1) % e2, t / (e1 * e2)};
-  const int ng = g.ng;
   const bool cell = q[0] < A.h[0] && q[1] < A.h[1] && q[2] < A.h[2];
-  const int C[3] = {ng + A.o[0] + q[0], ng + A.o[1] + q[1], ng + A.o[2] + q[2]};
-  const int F[3] = {ng + 2 * q[0], ng + 2 * q[1], ng + 2 * q[2]};
+  const int C[3] = {A.cl[0] + q[0], A.cl[1] + q[1], A.cl[2] + q[2]};
+  const int F[3] = {A.fl[0] + 2 * q[0], A.fl[1] + 2 * q[1], A.fl[2] + 2 * q[2]};
 
   if (cell && !PRIM) {
     const int nv = 5 + g.ns;
@@ -357,16 +359,16 @@ __global__ void __launch_bounds__(kAmrThreads)
   if (hits) atomicAdd(A.bad + 1, hits);
 }
 
-OctArgs oct_args(const Geo& g, const int oct[3]) {
+OctArgs box_args(const Geo& g, const int flo[3], const int clo[3], const int ext[3]) {
   OctArgs A;
   A.g = g;
   A.gm1 = 0.0;
   A.pfloor = 0.0;
   A.bad = nullptr;
-  const int n[3] = {g.n1, g.n2, g.n3};
   for (int d = 0; d < 3; ++d) {
-    A.h[d] = n[d] / 2;
-    A.o[d] = oct[d] * A.h[d];
+    A.h[d] = ext[d];
+    A.cl[d] = clo[d];
+    A.fl[d] = flo[d];
   }
   const long pts = (long)(A.h[0] + 1) * (A.h[1] + 1) * (A.h[2] + 1);
   const long wgs = (pts + kAmrThreads - 1) / kAmrThreads;
@@ -378,16 +380,17 @@ int grid_of(const OctArgs& A) { return 8 * A.per_xcd; }
 
 }  // namespace
 
-hipError_t launch_restrict(const Geo& g, const int oct[3], const double* fc, const double* fb, double* cc, double* cb,
-                           hipStream_t s) {
-  const OctArgs A = oct_args(g, oct);
+hipError_t launch_restrict(const Geo& g, const int flo[3], const int clo[3], const int ext[3], const double* fc,
+                           const double* fb, double* cc, double* cb, hipStream_t s) {
+  const OctArgs A = box_args(g, flo, clo, ext);
   hipLaunchKernelGGL(k_restrict, dim3(grid_of(A)), dim3(kAmrThreads), 0, s, A, fc, fb, cc, cb);
   return hipGetLastError();
 }
 
-hipError_t launch_prolong(const Geo& g, const int oct[3], const double* cc, const double* cb, double* fc, double* fb,
-                          bool primitive, double gamma, double pfloor, int* bad, hipStream_t s) {
-  OctArgs A = oct_args(g, oct);
+hipError_t launch_prolong(const Geo& g, const int flo[3], const int clo[3], const int ext[3], const double* cc,
+                          const double* cb, double* fc, double* fb, bool primitive, double gamma, double pfloor, int* bad,
+                          hipStream_t s) {
+  OctArgs A = box_args(g, flo, clo, ext);
   A.gm1 = gamma - 1.0;
   if (!primitive && pfloor > 0.0 && bad) {
     A.pfloor = pfloor;

@@ -402,3 +402,124 @@ def test_level_operators_with_the_maximum_number_of_scalars(torch_dev, athmhd, o
     g2c, g2b = dev(torch, d, cc), dev(torch, d, b.bface)
     s.restrict(dev(torch, d, want_c), dev(torch, d, want_b), g2c, g2b, o)
     assert np.array_equal(g2c.cpu().numpy(), rc) and np.array_equal(g2b.cpu().numpy(), rb)
+
+
+# ---- boxes (coarse buffers and ghost zones between levels)
+
+def box_face_slices(flo, ext, d, extra):
+    e = [0, 0, 0]
+    e[d] = 1
+    return tuple(slice(flo[k], flo[k] + extra * ext[k] + e[k]) for k in (2, 1, 0))
+
+
+def check_box(got_c, got_b, want_c, want_b, init_b, flo, ext, fine, bitwise_faces):
+    """Cells bitwise (every entry: outside the box both sides are the initial
+    values); faces inside the box bitwise on the outer ones (or all, for
+    restriction) and within FACE_TOL elsewhere, outside the box untouched."""
+    assert np.array_equal(got_c, want_c)
+    scale = np.abs(want_b).max()
+    for d in range(3):
+        sf = box_face_slices(flo, ext, d, 2 if fine else 1)
+        m = np.zeros(got_b.shape[1:], bool)
+        m[sf] = True
+        assert np.array_equal(got_b[d][~m], init_b[d][~m]), d
+        g, w = got_b[d][sf], want_b[d][sf]
+        if bitwise_faces:
+            assert np.array_equal(g, w), d
+        else:
+            idx = [slice(None)] * 3
+            idx[2 - d] = slice(0, None, 2)
+            assert np.array_equal(g[tuple(idx)], w[tuple(idx)]), d
+            assert np.abs(g - w).max() <= FACE_TOL * scale, d
+
+
+N_BOX, NG_BOX = (12, 10, 8), 4
+RESTRICT_BOXES = [((12, 4, 4), (16, 5, 4), (2, 5, 4)),     # fine boundary layer -> coarse upper x1 ghosts
+                  ((0, 0, 0), (0, 0, 0), (2, 2, 2)),       # ghost corner onto ghost corner
+                  ((1, 3, 2), (5, 2, 3), (3, 2, 2)),       # odd offsets
+                  ((4, 4, 4), (18, 16, 14), (2, 2, 2))]    # coarse box ending at the last stored cell
+PROLONG_BOXES = [((0, 4, 4), (5, 3, 6), (2, 4, 3)),        # coarse cells -> fine lower x1 ghosts
+                 ((16, 0, 2), (3, 4, 2), (2, 3, 3)),       # fine upper x1 ghosts, ghost rows
+                 ((1, 3, 2), (1, 1, 1), (3, 2, 2)),        # coarse box from the first readable cell
+                 ((4, 4, 4), (16, 14, 12), (3, 3, 3))]     # coarse box ending at N - 1
+
+
+@pytest.mark.parametrize("box", RESTRICT_BOXES)
+def test_restrict_box_matches_the_oracle(torch_dev, athmhd, orc, box):
+    torch, d = torch_dev
+    n, ng, ns = N_BOX, NG_BOX, 1
+    N, F = shapes(n, ng)
+    fc, fb = random_pair(N, F, 6, seed=101)
+    cc, cb = random_pair(N, F, 6, seed=102)
+    cfg = orc.make_cfg(n, ng, (0.1,) * 3, 5.0 / 3.0, nscalars=ns)
+    want_c, want_b = cc.copy(), cb.copy()
+    orc.restrict_box(cfg, fc, fb, want_c, want_b, *box)
+    s = solver(athmhd, n, ng, ns)
+    gc, gb = dev(torch, d, cc), dev(torch, d, cb)
+    s.restrict_box(dev(torch, d, fc), dev(torch, d, fb), gc, gb, *box)
+    check_box(gc.cpu().numpy(), gb.cpu().numpy(), want_c, want_b, cb, box[1], box[2], fine=False,
+              bitwise_faces=True)
+
+
+@pytest.mark.parametrize("primitive", [False, True])
+@pytest.mark.parametrize("box", PROLONG_BOXES)
+def test_prolong_box_matches_the_oracle(torch_dev, athmhd, orc, box, primitive):
+    torch, d = torch_dev
+    n, ng, ns = N_BOX, NG_BOX, 1
+    N, F = shapes(n, ng)
+    if primitive:      # a physical state: positive density and pressure everywhere, ghosts included
+        b = inputs.with_scalars(inputs.smooth_random(n=n, seed=103, ng=ng), ns, seed=104)
+        cfg = orc.make_cfg(n, ng, (0.1,) * 3, b.gamma, nscalars=ns)
+        cc, cb = orc.prim2cons(cfg, b.prim, b.bface), b.bface
+    else:
+        cc, cb = random_pair(N, F, 6, seed=105)
+        cfg = orc.make_cfg(n, ng, (0.1,) * 3, 5.0 / 3.0, nscalars=ns)
+    fc0, fb0 = random_pair(N, F, 6, seed=106)
+    want_c, want_b = fc0.copy(), fb0.copy()
+    orc.prolong_box(cfg, cc, cb, want_c, want_b, *box, primitive=primitive)
+    s = solver(athmhd, n, ng, ns)
+    gc, gb = dev(torch, d, fc0), dev(torch, d, fb0)
+    s.prolong_box(dev(torch, d, cc), dev(torch, d, cb), gc, gb, *box, primitive=primitive)
+    got_c, got_b = gc.cpu().numpy(), gb.cpu().numpy()
+    if primitive:
+        sc = tuple(slice(box[0][k], box[0][k] + 2 * box[2][k]) for k in (2, 1, 0))
+        mask = np.zeros(N, bool)
+        mask[sc] = True
+        assert np.array_equal(got_c[:, ~mask], fc0[:, ~mask])
+        assert np.array_equal(got_c[0], want_c[0])
+        for v in range(1, 6):
+            assert np.abs(got_c[v] - want_c[v]).max() <= PRIM_TOL * np.abs(want_c[v][mask]).max(), v
+        check_box(got_c[:1], got_b, want_c[:1], want_b, fb0, box[0], box[2], fine=True, bitwise_faces=False)
+    else:
+        check_box(got_c, got_b, want_c, want_b, fb0, box[0], box[2], fine=True, bitwise_faces=False)
+
+
+def test_box_bounds_are_checked(torch_dev, athmhd):
+    """Boxes reaching outside the stored arrays are refused before any launch."""
+    torch, d = torch_dev
+    n, ng = N_BOX, NG_BOX
+    N, F = shapes(n, ng)
+    Nx = N[::-1]                                    # stored cells along (x1, x2, x3)
+    a = [torch.zeros((5,) + N, dtype=torch.float64, device=d) for _ in range(2)]
+    b = [torch.zeros((3,) + F, dtype=torch.float64, device=d) for _ in range(2)]
+    s = solver(athmhd, n, ng)
+    bad_restrict = [((0, 0, 0), (0, 0, 0), (0, 1, 1)),                       # empty extent
+                    ((Nx[0] - 3, 0, 0), (0, 0, 0), (2, 1, 1)),              # fine box past the end
+                    ((-1, 0, 0), (0, 0, 0), (1, 1, 1)),                     # negative start
+                    ((0, 0, 0), (Nx[0] - 1, 0, 0), (2, 1, 1))]              # coarse box past the end
+    for box in bad_restrict:
+        with pytest.raises(athmhd.AthmhdError) as e:
+            s.restrict_box(a[0], b[0], a[1], b[1], *box)
+        assert e.value.code == athmhd.EINVAL, box
+    bad_prolong = [((0, 0, 0), (0, 1, 1), (1, 1, 1)),                       # no lower neighbour
+                   ((0, 0, 0), (1, 1, Nx[2] - 1), (1, 1, 1)),               # no upper neighbour
+                   ((0, 0, Nx[2] - 1), (1, 1, 1), (1, 1, 1))]               # fine box past the end
+    for box in bad_prolong:
+        with pytest.raises(athmhd.AthmhdError) as e:
+            s.prolong_box(a[0], b[0], a[1], b[1], *box)
+        assert e.value.code == athmhd.EINVAL, box
+    # the largest boxes allowed run
+    s.restrict_box(a[0], b[0], a[1], b[1], (0, 0, 0), (Nx[0] // 2, Nx[1] // 2, Nx[2] // 2),
+                   (Nx[0] // 2, Nx[1] // 2, Nx[2] // 2))
+    s.prolong_box(a[0], b[0], a[1], b[1], (0, 0, 0), (1, 1, 1), (Nx[0] // 2 - 1, Nx[1] // 2 - 1, Nx[2] // 2 - 1))
+    torch.cuda.synchronize()
