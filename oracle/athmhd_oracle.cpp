@@ -1171,8 +1171,13 @@ inline void cell_field_stored(const Geo& g, const double* bf, int i, int j, int 
 // converted back to conserved variables with the cell-centred field of the
 // prolonged fine faces (Sec. 2.1.5 uses this between levels: conserved
 // values are exchanged, prolongation acts on primitives).
+// keep: bit 2 d + S set -> the fine faces of component d on side S (0 lower,
+// 1 upper) of the box already hold fine-level values; they are neither
+// overwritten nor recomputed, and the interior faces are solved with them
+// (Sec. 2.1.5: fine faces that exist at the fine level are used instead of
+// prolonged ones).
 inline void prolong_box(const Geo& g, const double* cc, const double* cb, double* fc, double* fb, const LevelBox& B,
-                        double gamma, double pfloor, bool primitive) {
+                        double gamma, double pfloor, bool primitive, int keep = 0) {
   const size_t nc = g.ncell(), nf = g.nface();
   const int* h = B.h;
   std::vector<double> wc, wf;
@@ -1230,6 +1235,7 @@ inline void prolong_box(const Geo& g, const double* cc, const double* cb, double
       for (int b = 0; b < lim[1]; ++b)
         for (int a = 0; a < lim[0]; ++a) {
           const int q[3] = {a, b, c};
+          if ((q[d] == 0 && ((keep >> (2 * d)) & 1)) || (q[d] == h[d] && ((keep >> (2 * d + 1)) & 1))) continue;
           const int C[3] = {B.c[0] + a, B.c[1] + b, B.c[2] + c};
           const double b0 = cb[d * nf + g.f(C[0], C[1], C[2])];
           double sl[2];
@@ -1523,7 +1529,7 @@ int orc_prolong(const orc::Cfg* c, const double* ccons, const double* cbface, do
 }
 
 int orc_prolong_box(const orc::Cfg* c, const double* ccons, const double* cbface, double* fcons, double* fbface,
-                    const int* flo, const int* clo, const int* ext, int primitive) {
+                    const int* flo, const int* clo, const int* ext, int primitive, int keep) {
   orc::Geo g(*c);
   orc::LevelBox B;
   for (int d = 0; d < 3; ++d) {
@@ -1531,7 +1537,7 @@ int orc_prolong_box(const orc::Cfg* c, const double* ccons, const double* cbface
     B.c[d] = clo[d];
     B.h[d] = ext[d];
   }
-  orc::prolong_box(g, ccons, cbface, fcons, fbface, B, c->gamma, c->pfloor, primitive != 0);
+  orc::prolong_box(g, ccons, cbface, fcons, fbface, B, c->gamma, c->pfloor, primitive != 0, keep);
   return 0;
 }
 

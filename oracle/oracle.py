@@ -67,7 +67,7 @@ def lib():
         _lib.orc_prolong.argtypes = [cp, P, P, P, P, C.c_int, C.c_int, C.c_int, C.c_int]
         I3 = C.POINTER(C.c_int)
         _lib.orc_restrict_box.argtypes = [cp, P, P, P, P, I3, I3, I3]
-        _lib.orc_prolong_box.argtypes = [cp, P, P, P, P, I3, I3, I3, C.c_int]
+        _lib.orc_prolong_box.argtypes = [cp, P, P, P, P, I3, I3, I3, C.c_int, C.c_int]
         _lib.orc_drive_scalar.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_int,
                                           P, P]
         _lib.orc_take_floor_count.restype = C.c_longlong
@@ -241,13 +241,15 @@ def restrict_box(cfg: Cfg, fcons, fbface, ccons, cbface, flo, clo, ext) -> None:
     lib().orc_restrict_box(C.byref(cfg), _p(fcons), _p(fbface), _p(ccons), _p(cbface), *_box(flo, clo, ext))
 
 
-def prolong_box(cfg: Cfg, ccons, cbface, fcons, fbface, flo, clo, ext, primitive: bool = False) -> None:
+def prolong_box(cfg: Cfg, ccons, cbface, fcons, fbface, flo, clo, ext, primitive: bool = False,
+                keep: int = 0) -> None:
     """Prolong coarse cells [clo, clo + ext) onto fine cells [flo, flo + 2 ext)
-    and their faces, in place."""
+    and their faces, in place; keep bit 2 d + S keeps the fine faces already
+    on side S of the box along direction d."""
     for x, y in ((fcons, fbface), (ccons, cbface)):
         _check(cfg, x, y)
     lib().orc_prolong_box(C.byref(cfg), _p(ccons), _p(cbface), _p(fcons), _p(fbface), *_box(flo, clo, ext),
-                          int(bool(primitive)))
+                          int(bool(primitive)), int(keep))
 
 
 def drive_scalar(integrator: str, lam: complex, dt: float, nsteps: int) -> complex:

@@ -552,3 +552,47 @@ def test_cell_prolongation_is_second_order_on_smooth_data(orc):
     e = [_prolong_l1_error(orc, n) for n in (8, 16, 32)]
     rates = [np.log2(e[i] / e[i + 1]) for i in range(2)]
     assert min(rates) >= 1.9, (e, rates)
+
+
+def curl_faces(N, seed, scale=1.0):
+    """A face field with zero discrete divergence: the discrete curl of a
+    random edge potential (forward differences commute)."""
+    rng = np.random.default_rng(seed)
+    ax, ay, az = scale * rng.standard_normal((3,) + tuple(m + 2 for m in N))
+    s = slice(0, -1)
+    bx = (az[s, 1:, s] - az[s, s, s]) - (ay[1:, s, s] - ay[s, s, s])
+    by = (ax[1:, s, s] - ax[s, s, s]) - (az[s, s, 1:] - az[s, s, s])
+    bz = (ay[s, s, 1:] - ay[s, s, s]) - (ax[s, 1:, s] - ax[s, s, s])
+    return np.ascontiguousarray(np.stack([bx, by, bz]))
+
+
+@pytest.mark.parametrize("o", [(0, 0, 0), (1, 0, 1)])
+def test_kept_fine_faces_are_used_and_keep_the_field_divergence_free(orc, o):
+    """Fine faces that already exist on the box's sides are kept (bitwise)
+    and the interior faces are solved with them: a divergence-free fine field,
+    restricted to the coarse level and prolonged back with all 6 sides kept,
+    stays divergence-free; without keeping, the sides change."""
+    n, ng = (8, 6, 4), 2
+    cfg, N = geom(orc, n)
+    fb_true = curl_faces(N, seed=111)
+    assert np.abs(divergence(fb_true, ng, n, 1.0)).max() <= 1e-13
+    cc, cb = random_block(N, 5, seed=112)
+    org = oct_origin(n, o)
+    orc.restrict(cfg, np.zeros_like(cc), fb_true, cc, cb, org)      # coarse faces of the octant
+    box = ((ng,) * 3, tuple(ng + x for x in org), tuple(x // 2 for x in n))
+    sides = np.zeros((3,) + fb_true.shape[1:], bool)                 # faces on the box's 6 sides
+    for d in range(3):
+        idx = [slice(ng, ng + n[k] + (1 if k == d else 0)) for k in range(3)]
+        for side in (ng, ng + n[d]):
+            sl = list(idx)
+            sl[d] = side
+            sides[d][sl[2], sl[1], sl[0]] = True
+    fc = np.zeros_like(cc)
+    fb = np.where(sides, fb_true, 7.0)
+    orc.prolong_box(cfg, cc, cb, fc, fb, *box, keep=63)
+    assert np.array_equal(fb[sides], fb_true[sides])
+    assert np.abs(divergence(fb, ng, n, 1.0)).max() <= 1e-12 * np.abs(fb_true).max()
+    fb0 = np.where(sides, fb_true, 7.0)
+    orc.prolong_box(cfg, cc, cb, np.zeros_like(cc), fb0, *box, keep=0)
+    assert not np.array_equal(fb0[sides], fb_true[sides])
+    assert np.abs(divergence(fb0, ng, n, 1.0)).max() <= 1e-12 * np.abs(fb_true).max()
