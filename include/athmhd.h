@@ -347,15 +347,21 @@ ATHMHD_API int athmhd_prolong(athmhd_t h, const double* coarse_cons, const doubl
  * restriction 0 <= coarse_lo, coarse_lo + extent <= N_d; for prolongation
  * 1 <= coarse_lo, coarse_lo + extent <= N_d - 1.  Block sizes need not be
  * even.  The octant calls above are the box fine_lo = nghost,
- * coarse_lo = nghost + o_d n_d / 2, extent = n_d / 2.  Other rules (handles,
- * distinct arrays, cubic cells for prolongation, primitive, the pressure
- * floor) as above. */
+ * coarse_lo = nghost + o_d n_d / 2, extent = n_d / 2.  keep (prolongation;
+ * 0 to 63, else ATHMHD_EINVAL): bit 2 d + S set (d = 0, 1, 2 for x1, x2, x3;
+ * S = 0 lower, 1 upper side) means the fine faces of component d on that side
+ * of the box already hold fine-level values, as where the fine block shares
+ * the face with a fine neighbour; they are read, not overwritten, and the
+ * faces inside the box are solved with them (Sec. 2.1.5), so a fine field
+ * whose kept faces restrict to the coarse faces keeps the coarse divergence.
+ * Other rules (handles, distinct arrays, cubic cells for prolongation,
+ * primitive, the pressure floor) as above. */
 ATHMHD_API int athmhd_restrict_box(athmhd_t h, const double* fine_cons, const double* fine_bface, double* coarse_cons,
                                    double* coarse_bface, const int* fine_lo, const int* coarse_lo, const int* extent,
                                    void* stream);
 ATHMHD_API int athmhd_prolong_box(athmhd_t h, const double* coarse_cons, const double* coarse_bface, double* fine_cons,
                                   double* fine_bface, const int* fine_lo, const int* coarse_lo, const int* extent,
-                                  int primitive, void* stream);
+                                  int primitive, int keep, void* stream);
 
 /* Text of the last error recorded on `h` (or of the last failed create when
  * h is NULL).  Valid until the next call on the same handle. */

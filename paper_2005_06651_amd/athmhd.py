@@ -81,7 +81,7 @@ def lib():
         L.athmhd_prolong.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, vp]
         I3 = C.POINTER(C.c_int)
         L.athmhd_restrict_box.argtypes = [vp, vp, vp, vp, vp, I3, I3, I3, vp]
-        L.athmhd_prolong_box.argtypes = [vp, vp, vp, vp, vp, I3, I3, I3, C.c_int, vp]
+        L.athmhd_prolong_box.argtypes = [vp, vp, vp, vp, vp, I3, I3, I3, C.c_int, C.c_int, vp]
         L.athmhd_last_error.argtypes = [vp]
         L.athmhd_last_error.restype = C.c_char_p
         L.athmhd_destroy.argtypes = [vp]
@@ -226,13 +226,14 @@ class Solver:
                                          _stream(stream)), self._h)
 
     def prolong_box(self, coarse_cons, coarse_bface, fine_cons, fine_bface, fine_lo, coarse_lo, extent,
-                    primitive=False, stream=None) -> None:
+                    primitive=False, keep=0, stream=None) -> None:
         """Prolong coarse cells [coarse_lo, coarse_lo + extent) onto fine cells
-        [fine_lo, fine_lo + 2 extent) and their faces."""
+        [fine_lo, fine_lo + 2 extent) and their faces; keep bit 2 d + S keeps
+        the fine faces already on side S of the box along direction d."""
         cc, cb = self._one_block(coarse_cons, coarse_bface)
         fc, fb = self._one_block(fine_cons, fine_bface)
         _check(lib().athmhd_prolong_box(self._h, cc, cb, fc, fb, *self._box(fine_lo, coarse_lo, extent),
-                                        int(bool(primitive)), _stream(stream)), self._h)
+                                        int(bool(primitive)), int(keep), _stream(stream)), self._h)
 
     @property
     def extra_stages(self) -> int:

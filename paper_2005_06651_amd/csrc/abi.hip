@@ -455,7 +455,7 @@ int alloc_adjoint(athmhd_t h) {
 
 extern "C" {
 
-int athmhd_version(void) { return 107; }
+int athmhd_version(void) { return 108; }
 
 int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
   if (!out) return fail(nullptr, ATHMHD_EINVAL, "out is NULL");
@@ -919,11 +919,12 @@ int restrict_box(athmhd_t h, const double* fc, const double* fb, double* cc, dou
 }
 
 int prolong_box(athmhd_t h, const double* cc, const double* cb, double* fc, double* fb, const int* flo,
-                const int* clo, const int* ext, int primitive, void* stream) {
+                const int* clo, const int* ext, int primitive, int keep, void* stream) {
   if (primitive != 0 && primitive != 1) return fail(h, ATHMHD_EINVAL, "primitive must be 0 or 1 (got %d)", primitive);
+  if (keep < 0 || keep > 63) return fail(h, ATHMHD_EINVAL, "keep must be a 6-bit mask (got %d)", keep);
   int rc = check_level_box(h, flo, clo, ext, true);
   if (rc) return rc;
-  hipError_t e = launch_prolong(h->g, flo, clo, ext, cc, cb, fc, fb, primitive == 1, h->cfg.gamma, h->floors.p,
+  hipError_t e = launch_prolong(h->g, flo, clo, ext, cc, cb, fc, fb, primitive == 1, keep, h->cfg.gamma, h->floors.p,
                                 h->d_bad, (hipStream_t)stream);
   return e == hipSuccess ? ATHMHD_OK : hip_fail(h, e, "prolong launch");
 }
@@ -949,7 +950,7 @@ int athmhd_prolong(athmhd_t h, const double* coarse_cons, const double* coarse_b
   int flo[3], clo[3], ext[3];
   rc = octant_box(h, oct, flo, clo, ext);
   if (rc) return rc;
-  return prolong_box(h, coarse_cons, coarse_bface, fine_cons, fine_bface, flo, clo, ext, primitive, stream);
+  return prolong_box(h, coarse_cons, coarse_bface, fine_cons, fine_bface, flo, clo, ext, primitive, 0, stream);
 }
 
 int athmhd_restrict_box(athmhd_t h, const double* fine_cons, const double* fine_bface, double* coarse_cons,
@@ -962,11 +963,11 @@ int athmhd_restrict_box(athmhd_t h, const double* fine_cons, const double* fine_
 
 int athmhd_prolong_box(athmhd_t h, const double* coarse_cons, const double* coarse_bface, double* fine_cons,
                        double* fine_bface, const int* fine_lo, const int* coarse_lo, const int* extent, int primitive,
-                       void* stream) {
+                       int keep, void* stream) {
   int rc = check_level_arrays(h, coarse_cons, coarse_bface, fine_cons, fine_bface, true);
   if (rc) return rc;
   return prolong_box(h, coarse_cons, coarse_bface, fine_cons, fine_bface, fine_lo, coarse_lo, extent, primitive,
-                     stream);
+                     keep, stream);
 }
 
 int athmhd_prim2cons_vjp(athmhd_t h, const double* prim, const double* bface, const double* g_cons, double* g_prim,

@@ -28,9 +28,10 @@ hipError_t launch_restrict(const Geo& g, const int flo[3], const int clo[3], con
                            const double* fb, double* cc, double* cb, hipStream_t s);
 // primitive: prolong (rho, v, P, C_i) instead of U; otherwise pfloor > 0
 // applies the pressure floor to the refined cells, activations in bad[1].
+// keep: bit 2 d + S keeps the fine faces already on side S of the box along d.
 hipError_t launch_prolong(const Geo& g, const int flo[3], const int clo[3], const int ext[3], const double* cc,
-                          const double* cb, double* fc, double* fb, bool primitive, double gamma, double pfloor, int* bad,
-                          hipStream_t s);
+                          const double* cb, double* fc, double* fb, bool primitive, int keep, double gamma,
+                          double pfloor, int* bad, hipStream_t s);
 hipError_t launch_prim2cons(const Geo& g, double gamma, const double* prim, const double* bface, double* cons,
                             int nb, hipStream_t s);
 // dt_bits: device uint64 holding the bit pattern of the running minimum of

@@ -27,6 +27,7 @@ struct OctArgs {
   int cl[3];    // first coarse cell of the box (stored index)
   int fl[3];    // first fine cell of the box (stored index)
   int per_xcd;  // workgroups per XCD: ceil(workgroups / 8)
+  int keep;     // prolongation: bit 2 d + S keeps the fine faces on side S of the box along d
   double gm1;     // gamma - 1
   double pfloor;  // pressure floor of the refined cells (prolongation; 0: off)
   int* bad;       // bad[1] counts floor activations
@@ -213,28 +214,57 @@ __global__ void __launch_bounds__(kAmrThreads)
     }
   }
 
-  // outer faces: O[d][S][p][q]; the lower one (S = 0) is this thread's own
+  // outer faces: O[d][S][p][q]; the lower one (S = 0) is this thread's own.
+  // Faces on a kept side of the box are read, never written; all others are
+  // split from the coarse face, and only their owner writes them.
   double O[3][2][2][2];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
     if (q[t1] >= A.h[t1] || q[t2] >= A.h[t2]) continue;
-    split_face(g, cb, d, C, O[d][0]);
     double* dst = fb + d * g.fvar;
+    const bool keep_lo = (q[d] == 0 && ((A.keep >> (2 * d)) & 1)) || (q[d] == A.h[d] && ((A.keep >> (2 * d + 1)) & 1));
+    if (keep_lo) {
 #pragma unroll
-    for (int p = 0; p < 2; ++p)
+      for (int p = 0; p < 2; ++p)
 #pragma unroll
-      for (int r = 0; r < 2; ++r) {
-        int x[3];
-        x[d] = F[d];
-        x[t1] = F[t1] + p;
-        x[t2] = F[t2] + r;
-        dst[fidx(g, x)] = O[d][0][p][r];
-      }
+        for (int r = 0; r < 2; ++r) {
+          int x[3];
+          x[d] = F[d];
+          x[t1] = F[t1] + p;
+          x[t2] = F[t2] + r;
+          O[d][0][p][r] = dst[fidx(g, x)];
+        }
+    } else {
+      split_face(g, cb, d, C, O[d][0]);
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          int x[3];
+          x[d] = F[d];
+          x[t1] = F[t1] + p;
+          x[t2] = F[t2] + r;
+          dst[fidx(g, x)] = O[d][0][p][r];
+        }
+    }
     if (cell) {
-      int Cu[3] = {C[0], C[1], C[2]};
-      Cu[d] += 1;
-      split_face(g, cb, d, Cu, O[d][1]);
+      if (q[d] == A.h[d] - 1 && ((A.keep >> (2 * d + 1)) & 1)) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+          for (int r = 0; r < 2; ++r) {
+            int x[3];
+            x[d] = F[d] + 2;
+            x[t1] = F[t1] + p;
+            x[t2] = F[t2] + r;
+            O[d][1][p][r] = dst[fidx(g, x)];
+          }
+      } else {
+        int Cu[3] = {C[0], C[1], C[2]};
+        Cu[d] += 1;
+        split_face(g, cb, d, Cu, O[d][1]);
+      }
     }
   }
   if (!cell) return;
@@ -365,6 +395,7 @@ OctArgs box_args(const Geo& g, const int flo[3], const int clo[3], const int ext
   A.gm1 = 0.0;
   A.pfloor = 0.0;
   A.bad = nullptr;
+  A.keep = 0;
   for (int d = 0; d < 3; ++d) {
     A.h[d] = ext[d];
     A.cl[d] = clo[d];
@@ -388,9 +419,10 @@ hipError_t launch_restrict(const Geo& g, const int flo[3], const int clo[3], con
 }
 
 hipError_t launch_prolong(const Geo& g, const int flo[3], const int clo[3], const int ext[3], const double* cc,
-                          const double* cb, double* fc, double* fb, bool primitive, double gamma, double pfloor, int* bad,
-                          hipStream_t s) {
+                          const double* cb, double* fc, double* fb, bool primitive, int keep, double gamma, double pfloor,
+                          int* bad, hipStream_t s) {
   OctArgs A = box_args(g, flo, clo, ext);
+  A.keep = keep;
   A.gm1 = gamma - 1.0;
   if (!primitive && pfloor > 0.0 && bad) {
     A.pfloor = pfloor;

@@ -523,3 +523,72 @@ def test_box_bounds_are_checked(torch_dev, athmhd):
                    (Nx[0] // 2, Nx[1] // 2, Nx[2] // 2))
     s.prolong_box(a[0], b[0], a[1], b[1], (0, 0, 0), (1, 1, 1), (Nx[0] // 2 - 1, Nx[1] // 2 - 1, Nx[2] // 2 - 1))
     torch.cuda.synchronize()
+
+
+def curl_faces(N, seed):
+    """A face field with zero discrete divergence (curl of an edge potential)."""
+    rng = np.random.default_rng(seed)
+    ax, ay, az = rng.standard_normal((3,) + tuple(m + 2 for m in N))
+    s = slice(0, -1)
+    bx = (az[s, 1:, s] - az[s, s, s]) - (ay[1:, s, s] - ay[s, s, s])
+    by = (ax[1:, s, s] - ax[s, s, s]) - (az[s, s, 1:] - az[s, s, s])
+    bz = (ay[s, s, 1:] - ay[s, s, s]) - (ax[s, 1:, s] - ax[s, s, s])
+    return np.ascontiguousarray(np.stack([bx, by, bz]))
+
+
+@pytest.mark.parametrize("keep", [63, 5, 42, 16])
+@pytest.mark.parametrize("box", [PROLONG_BOXES[0], ((4, 4, 4), (4, 4, 4), (6, 5, 4))])
+def test_prolong_box_with_kept_faces_matches_the_oracle(torch_dev, athmhd, orc, box, keep):
+    """Kept sides are read, not written (bitwise the initial fine values on
+    both sides), and the interior faces are solved with them."""
+    torch, d = torch_dev
+    n, ng = N_BOX, NG_BOX
+    N, F = shapes(n, ng)
+    cc, cb = random_pair(N, F, 5, seed=121)
+    fc0, fb0 = random_pair(N, F, 5, seed=122)
+    cfg = orc.make_cfg(n, ng, (0.1,) * 3, 5.0 / 3.0)
+    want_c, want_b = fc0.copy(), fb0.copy()
+    orc.prolong_box(cfg, cc, cb, want_c, want_b, *box, keep=keep)
+    s = solver(athmhd, n, ng)
+    gc, gb = dev(torch, d, fc0), dev(torch, d, fb0)
+    s.prolong_box(dev(torch, d, cc), dev(torch, d, cb), gc, gb, *box, keep=keep)
+    check_box(gc.cpu().numpy(), gb.cpu().numpy(), want_c, want_b, fb0, box[0], box[2], fine=True,
+              bitwise_faces=False)
+
+
+def test_kept_faces_keep_a_divergence_free_field_on_the_device(torch_dev, athmhd, orc):
+    """A divergence-free fine field restricted onto its parent octant and
+    prolonged back with its 6 sides kept stays divergence-free."""
+    torch, d = torch_dev
+    n, ng = (16, 12, 8), 2
+    N, F = shapes(n, ng)
+    fb_true = curl_faces(N, seed=123)
+    cc, cb = random_pair(N, F, 5, seed=124)
+    s = solver(athmhd, n, ng)
+    gcc, gcb = dev(torch, d, cc), dev(torch, d, cb)
+    s.restrict(torch.zeros_like(gcc), dev(torch, d, fb_true), gcc, gcb, (1, 0, 1))
+    box = ((ng,) * 3, (ng + 8, ng, ng + 4), (8, 6, 4))
+    gf = dev(torch, d, fb_true)
+    s.prolong_box(gcc, gcb, torch.zeros_like(gcc), gf, *box, keep=63)
+    got = gf.cpu().numpy()
+    div = inputs.divb_metric(got, n, ng, (1.0, 1.0, 1.0))
+    assert div <= 1e-13, div
+    for k in range(3):       # the 6 sides are the original values
+        e = [slice(ng, ng + n[2]), slice(ng, ng + n[1]), slice(ng, ng + n[0])]
+        for side in (ng, ng + n[k]):
+            sl = list(e)
+            sl[2 - k] = side
+            assert np.array_equal(got[k][tuple(sl)], fb_true[k][tuple(sl)])
+
+
+def test_keep_mask_is_checked(torch_dev, athmhd):
+    torch, d = torch_dev
+    n, ng = N_BOX, NG_BOX
+    N, F = shapes(n, ng)
+    a = [torch.zeros((5,) + N, dtype=torch.float64, device=d) for _ in range(2)]
+    b = [torch.zeros((3,) + F, dtype=torch.float64, device=d) for _ in range(2)]
+    s = solver(athmhd, n, ng)
+    for keep in (64, -1):
+        with pytest.raises(athmhd.AthmhdError) as e:
+            s.prolong_box(a[0], b[0], a[1], b[1], (4, 4, 4), (4, 4, 4), (2, 2, 2), keep=keep)
+        assert e.value.code == athmhd.EINVAL
