@@ -229,7 +229,15 @@ def prolong(cfg: Cfg, ccons, cbface, fcons, fbface, octant, primitive: bool = Fa
                       int(bool(primitive)))
 
 
-def _box(flo, clo, ext):
+def _box(flo, clo, ext, cfg=None, prolong=False):
+    """The three boxes as C arrays, after checking that every index the C
+    routine touches lies in the stored arrays (the C code does not check)."""
+    if cfg is not None:
+        N = (cfg.n1 + 2 * cfg.ng, cfg.n2 + 2 * cfg.ng, cfg.n3 + 2 * cfg.ng)
+        for d in range(3):
+            assert ext[d] >= 1 and flo[d] >= 0 and flo[d] + 2 * ext[d] <= N[d], (flo, ext, N)
+            lo, hi = (1, N[d] - 1) if prolong else (0, N[d])
+            assert clo[d] >= lo and clo[d] + ext[d] <= hi, (clo, ext, N, prolong)
     return [(C.c_int * 3)(*[int(x) for x in v]) for v in (flo, clo, ext)]
 
 
@@ -238,7 +246,7 @@ def restrict_box(cfg: Cfg, fcons, fbface, ccons, cbface, flo, clo, ext) -> None:
     ghosts included) onto coarse cells [clo, clo + ext), in place."""
     for x, y in ((fcons, fbface), (ccons, cbface)):
         _check(cfg, x, y)
-    lib().orc_restrict_box(C.byref(cfg), _p(fcons), _p(fbface), _p(ccons), _p(cbface), *_box(flo, clo, ext))
+    lib().orc_restrict_box(C.byref(cfg), _p(fcons), _p(fbface), _p(ccons), _p(cbface), *_box(flo, clo, ext, cfg))
 
 
 def prolong_box(cfg: Cfg, ccons, cbface, fcons, fbface, flo, clo, ext, primitive: bool = False,
@@ -248,8 +256,9 @@ def prolong_box(cfg: Cfg, ccons, cbface, fcons, fbface, flo, clo, ext, primitive
     on side S of the box along direction d."""
     for x, y in ((fcons, fbface), (ccons, cbface)):
         _check(cfg, x, y)
-    lib().orc_prolong_box(C.byref(cfg), _p(ccons), _p(cbface), _p(fcons), _p(fbface), *_box(flo, clo, ext),
-                          int(bool(primitive)), int(keep))
+    assert 0 <= keep <= 63, keep
+    lib().orc_prolong_box(C.byref(cfg), _p(ccons), _p(cbface), _p(fcons), _p(fbface),
+                          *_box(flo, clo, ext, cfg, prolong=True), int(bool(primitive)), int(keep))
 
 
 def drive_scalar(integrator: str, lam: complex, dt: float, nsteps: int) -> complex:
