@@ -592,3 +592,47 @@ def test_keep_mask_is_checked(torch_dev, athmhd):
         with pytest.raises(athmhd.AthmhdError) as e:
             s.prolong_box(a[0], b[0], a[1], b[1], (4, 4, 4), (4, 4, 4), (2, 2, 2), keep=keep)
         assert e.value.code == athmhd.EINVAL
+
+
+def test_level_operators_replay_from_a_graph(torch_dev, athmhd):
+    """The level operators allocate nothing and record no memset, so a
+    refinement (8 octant prolongations) and a derefinement (8 restrictions)
+    can be captured once in a graph: three replays, with eager updates of the
+    input between them, each bitwise equal to eager calls on the same data."""
+    torch, d = torch_dev
+    n, ng = (16, 12, 8), 2
+    N, F = shapes(n, ng)
+    cc0, cb0 = random_pair(N, F, 5, seed=131)
+    cc, cb = dev(torch, d, cc0), dev(torch, d, cb0)
+    fcs = [torch.zeros_like(cc) for _ in range(8)]
+    fbs = [torch.zeros_like(cb) for _ in range(8)]
+    rc, rb = torch.zeros_like(cc), torch.zeros_like(cb)
+    s = solver(athmhd, n, ng)
+
+    def refine_and_back():
+        for i, o in enumerate(OCTANTS):
+            s.prolong(cc, cb, fcs[i], fbs[i], o)
+        for i, o in enumerate(OCTANTS):
+            s.restrict(fcs[i], fbs[i], rc, rb, o)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        refine_and_back()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        refine_and_back()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        cc.mul_(1.0 + 0.1 * rep)
+        cb.add_(0.05)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        got = [x.clone() for x in fcs + fbs] + [rc.clone(), rb.clone()]
+        refine_and_back()
+        torch.cuda.synchronize()
+        want = fcs + fbs + [rc, rb]
+        assert all(torch.equal(a, b) for a, b in zip(got, want)), rep
