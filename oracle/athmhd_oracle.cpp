@@ -575,7 +575,47 @@ template <class T> void hlle(const T* wl, const T* wr, const T& bn, double gamma
 // HLLD: five-wave solver of Miyoshi & Kusano (2005).
 const double kHlldSmall = 1.0e-8;
 
-template <class T> void hlld(const T* wl, const T* wr, const T& bx, double gamma, T* flux, T& smax) {
+// The states of the HLLD fan that are not the outer states: speeds
+// S_L < S*_L <= S_M <= S*_R < S_R, the total pressure p_T* of the fan, and
+// the conserved single-star (U*_L, U*_R) and double-star (U**_L, U**_R)
+// states in the face frame.  Filled on request only (a test hook); the flux
+// itself does not need every state.
+template <class T> struct HlldFan {
+  T sl, ssl, sm, ssr, sr, pts;
+  T us_l[7], uss_l[7], uss_r[7], us_r[7];
+};
+
+// Double-star states from the single-star ones (rotational discontinuities
+// at S*_L, S*_R; transverse velocity and field continuous across S_M).
+// Identical to the single-star states when Bx is negligible against p_T*.
+template <class T>
+void hlld_double_star(const T& bx, const T& sm, const T& pts, const T* us_l, const T* us_r, const T* vys,
+                      const T* vzs, const T* bys, const T* bzs, const T* rhos, const T* vdbs, const T& sqrl,
+                      const T& sqrr, T* uss_l, T* uss_r) {
+  if (val(0.5 * bx * bx) < kHlldSmall * val(pts)) {
+    for (int n = 0; n < 7; ++n) { uss_l[n] = us_l[n]; uss_r[n] = us_r[n]; }
+    return;
+  }
+  double sb = sgn(bx);
+  T isum = 1.0 / (sqrl + sqrr);
+  T vyss = (sqrl * vys[0] + sqrr * vys[1] + (bys[1] - bys[0]) * sb) * isum;
+  T vzss = (sqrl * vzs[0] + sqrr * vzs[1] + (bzs[1] - bzs[0]) * sb) * isum;
+  T byss = (sqrl * bys[1] + sqrr * bys[0] + sqrl * sqrr * (vys[1] - vys[0]) * sb) * isum;
+  T bzss = (sqrl * bzs[1] + sqrr * bzs[0] + sqrl * sqrr * (vzs[1] - vzs[0]) * sb) * isum;
+  T vdbss = sm * bx + vyss * byss + vzss * bzss;
+  T ess_l = us_l[4] - sqrl * (vdbs[0] - vdbss) * sb;
+  T ess_r = us_r[4] + sqrr * (vdbs[1] - vdbss) * sb;
+  uss_l[0] = rhos[0]; uss_l[1] = rhos[0] * sm; uss_l[2] = rhos[0] * vyss; uss_l[3] = rhos[0] * vzss;
+  uss_l[4] = ess_l; uss_l[5] = byss; uss_l[6] = bzss;
+  uss_r[0] = rhos[1]; uss_r[1] = rhos[1] * sm; uss_r[2] = rhos[1] * vyss; uss_r[3] = rhos[1] * vzss;
+  uss_r[4] = ess_r; uss_r[5] = byss; uss_r[6] = bzss;
+}
+
+// fan != NULL: also record every intermediate state (the flux is unchanged);
+// returns false when an outer state is upwind (S_L > 0 or S_R < 0) and no
+// fan is formed.
+template <class T>
+bool hlld(const T* wl, const T* wr, const T& bx, double gamma, T* flux, T& smax, HlldFan<T>* fan = nullptr) {
   T ul[7], fl[7], ur[7], fr[7];
   phys_flux(wl, bx, gamma, ul, fl);
   phys_flux(wr, bx, gamma, ur, fr);
@@ -592,8 +632,8 @@ template <class T> void hlld(const T* wl, const T* wr, const T& bx, double gamma
   T sl = vmin(vxl, vxr) - cmax;
   T sr = vmax(vxl, vxr) + cmax;
   smax = vmax(fabs(sl), fabs(sr));
-  if (val(sl) > 0.0) { for (int n = 0; n < 7; ++n) flux[n] = fl[n]; return; }
-  if (val(sr) < 0.0) { for (int n = 0; n < 7; ++n) flux[n] = fr[n]; return; }
+  if (val(sl) > 0.0) { for (int n = 0; n < 7; ++n) flux[n] = fl[n]; return false; }
+  if (val(sr) < 0.0) { for (int n = 0; n < 7; ++n) flux[n] = fr[n]; return false; }
 
   // contact speed and star total pressure
   T sdl = sl - vxl, sdr = sr - vxr;
@@ -636,39 +676,28 @@ template <class T> void hlld(const T* wl, const T* wr, const T& bx, double gamma
   T sqrl = sqrt(rhos[0]), sqrr = sqrt(rhos[1]);
   T ssl = sm - fabs(bx) / sqrl;
   T ssr = sm + fabs(bx) / sqrr;
+  if (fan) {
+    fan->sl = sl; fan->ssl = ssl; fan->sm = sm; fan->ssr = ssr; fan->sr = sr; fan->pts = pts;
+    for (int n = 0; n < 7; ++n) { fan->us_l[n] = us_l[n]; fan->us_r[n] = us_r[n]; }
+    hlld_double_star(bx, sm, pts, us_l, us_r, vys, vzs, bys, bzs, rhos, vdbs, sqrl, sqrr, fan->uss_l, fan->uss_r);
+  }
 
   if (val(ssl) >= 0.0) {
     for (int n = 0; n < 7; ++n) flux[n] = fl[n] + sl * (us_l[n] - ul[n]);
-    return;
+    return true;
   }
   if (val(ssr) <= 0.0) {
     for (int n = 0; n < 7; ++n) flux[n] = fr[n] + sr * (us_r[n] - ur[n]);
-    return;
+    return true;
   }
-  // double-star states (identical to the single-star states when Bx ~ 0)
   T uss_l[7], uss_r[7];
-  if (val(0.5 * bx * bx) < kHlldSmall * val(pts)) {
-    for (int n = 0; n < 7; ++n) { uss_l[n] = us_l[n]; uss_r[n] = us_r[n]; }
-  } else {
-    double sb = sgn(bx);
-    T isum = 1.0 / (sqrl + sqrr);
-    T vyss = (sqrl * vys[0] + sqrr * vys[1] + (bys[1] - bys[0]) * sb) * isum;
-    T vzss = (sqrl * vzs[0] + sqrr * vzs[1] + (bzs[1] - bzs[0]) * sb) * isum;
-    T byss = (sqrl * bys[1] + sqrr * bys[0] + sqrl * sqrr * (vys[1] - vys[0]) * sb) * isum;
-    T bzss = (sqrl * bzs[1] + sqrr * bzs[0] + sqrl * sqrr * (vzs[1] - vzs[0]) * sb) * isum;
-    T vdbss = sm * bx + vyss * byss + vzss * bzss;
-    T ess_l = us_l[4] - sqrl * (vdbs[0] - vdbss) * sb;
-    T ess_r = us_r[4] + sqrr * (vdbs[1] - vdbss) * sb;
-    uss_l[0] = rhos[0]; uss_l[1] = rhos[0] * sm; uss_l[2] = rhos[0] * vyss; uss_l[3] = rhos[0] * vzss;
-    uss_l[4] = ess_l; uss_l[5] = byss; uss_l[6] = bzss;
-    uss_r[0] = rhos[1]; uss_r[1] = rhos[1] * sm; uss_r[2] = rhos[1] * vyss; uss_r[3] = rhos[1] * vzss;
-    uss_r[4] = ess_r; uss_r[5] = byss; uss_r[6] = bzss;
-  }
+  hlld_double_star(bx, sm, pts, us_l, us_r, vys, vzs, bys, bzs, rhos, vdbs, sqrl, sqrr, uss_l, uss_r);
   if (val(sm) >= 0.0) {
     for (int n = 0; n < 7; ++n) flux[n] = fl[n] + sl * (us_l[n] - ul[n]) + ssl * (uss_l[n] - us_l[n]);
   } else {
     for (int n = 0; n < 7; ++n) flux[n] = fr[n] + sr * (us_r[n] - ur[n]) + ssr * (uss_r[n] - us_r[n]);
   }
+  return true;
 }
 
 template <class T> void riemann(int rs, const T* wl, const T* wr, const T& bn, double gamma, T* flux, T& smax) {
@@ -1469,6 +1498,24 @@ int orc_riemann(int rs, double gamma, const double* wl, const double* wr, double
   double s;
   orc::riemann<double>(rs, wl, wr, bn, gamma, flux, s);
   if (smax) *smax = s;
+  return 0;
+}
+
+// HLLD fan of one face (test hook): out[0..5] = S_L, S*_L, S_M, S*_R, S_R,
+// p_T*; out[6..33] = U*_L, U**_L, U**_R, U*_R (7 each, face frame); flux as
+// orc_riemann.  Returns 1 when an outer state is upwind (out not written).
+int orc_hlld_fan(double gamma, const double* wl, const double* wr, double bn, double* flux, double* out) {
+  double s;
+  orc::HlldFan<double> fan;
+  if (!orc::hlld<double>(wl, wr, bn, gamma, flux, s, &fan)) return 1;
+  const double head[6] = {fan.sl, fan.ssl, fan.sm, fan.ssr, fan.sr, fan.pts};
+  for (int n = 0; n < 6; ++n) out[n] = head[n];
+  for (int n = 0; n < 7; ++n) {
+    out[6 + n] = fan.us_l[n];
+    out[13 + n] = fan.uss_l[n];
+    out[20 + n] = fan.uss_r[n];
+    out[27 + n] = fan.us_r[n];
+  }
   return 0;
 }
 

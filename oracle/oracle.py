@@ -57,6 +57,7 @@ def lib():
         _lib.orc_count_ops.argtypes = [cp, P, P, C.c_double, C.POINTER(C.c_ulonglong)]
         _lib.orc_riemann.argtypes = [C.c_int, C.c_double, P, P, C.c_double, P, P]
         _lib.orc_phys_flux.argtypes = [C.c_double, P, C.c_double, P, P]
+        _lib.orc_hlld_fan.argtypes = [C.c_double, P, P, C.c_double, P, P]
         _lib.orc_fast_speed.argtypes = [C.c_double] * 6
         _lib.orc_fast_speed.restype = C.c_double
         _lib.orc_recon_line.argtypes = [C.c_int, C.c_int, P, P, P]
@@ -161,6 +162,20 @@ def riemann(rs: str, gamma: float, wl, wr, bn: float):
     smax = np.zeros(1)
     lib().orc_riemann(RIEMANN[rs], float(gamma), _p(wl), _p(wr), float(bn), _p(f), _p(smax))
     return f, float(smax[0])
+
+
+def hlld_fan(gamma: float, wl, wr, bn: float):
+    """HLLD flux and its fan: (flux, speeds, states) with speeds = (S_L, S*_L,
+    S_M, S*_R, S_R, p_T*) and states = (U*_L, U**_L, U**_R, U*_R) in the face
+    frame; speeds and states are None when an outer state is upwind."""
+    wl = np.ascontiguousarray(wl, dtype=np.float64)
+    wr = np.ascontiguousarray(wr, dtype=np.float64)
+    f = np.zeros(7)
+    out = np.zeros(34)
+    rc = lib().orc_hlld_fan(float(gamma), _p(wl), _p(wr), float(bn), _p(f), _p(out))
+    if rc:
+        return f, None, None
+    return f, out[:6].copy(), out[6:].reshape(4, 7).copy()
 
 
 def phys_flux(gamma: float, w, bn: float):
