@@ -53,7 +53,7 @@ struct athmhd_s {
   int nsitems = 0;
   int min_edge = 0;  // batched blocks: fewest active cells along any direction of any block
   unsigned long long* d_dtmin = nullptr;  // running min of dx/(|v|+cf), bit pattern
-  int* d_bad = nullptr;                   // [0] non-physical cells met since the last newdt, [1] floor activations
+  int* d_bad = nullptr;                   // counters of add_floor_count: [0] non-physical cells, [2, 4) floors (64-bit)
   Floors floors{0.0, 0.0};                // optional primitive floors (off by default)
   double* d_dtval = nullptr;              // dt of the step on the device (graph replay)
   void* h_pinned = nullptr;               // 16 bytes of pinned host memory for newdt
@@ -121,7 +121,7 @@ __global__ void k_set_u64(unsigned long long* p, unsigned long long v, int* bad,
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     *p = v;
     if (clear_bad & 1) bad[0] = 0;
-    if (clear_bad & 2) bad[1] = 0;
+    if (clear_bad & 2) *reinterpret_cast<unsigned long long*>(bad + 2) = 0ull;
   }
 }
 
@@ -228,7 +228,7 @@ void free_all(athmhd_t h) {
 // Small device buffers every handle has.
 bool alloc_common(athmhd_t h) {
   return hipMalloc(&h->d_dtmin, sizeof(unsigned long long)) == hipSuccess &&
-         hipMalloc(&h->d_bad, 2 * sizeof(int)) == hipSuccess && hipMalloc(&h->d_dtval, sizeof(double)) == hipSuccess &&
+         hipMalloc(&h->d_bad, 4 * sizeof(int)) == hipSuccess && hipMalloc(&h->d_dtval, sizeof(double)) == hipSuccess &&
          hipHostMalloc(&h->h_pinned, 16, hipHostMallocDefault) == hipSuccess;
 }
 
@@ -290,7 +290,7 @@ hipError_t launch_stage(athmhd_t h, int recon, const double* xc, const double* x
                               dt_dev, beta, nblocks, stage_kz(h, nblocks), h->floors, h->d_bad,
                               h->g.ns > 0 ? h->d_fm : nullptr, s);
   return launch_stage_unfused(h->g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc, xb, unc, unb, oc, ob,
-                              cf, nblocks, h->scr, h->floors, h->d_bad, h->cfg.charac != 0, s);
+                              cf, dt_dev, beta, nblocks, h->scr, h->floors, h->d_bad, h->cfg.charac != 0, s);
 }
 
 // depth: ghost layers a mesh exchange fills (0: all); other handles fill all
@@ -315,6 +315,17 @@ int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const doubl
   // and the blocks of a coupled mesh read ghost entries, which are filled
   // (exchanged between the mesh's blocks) before each stage
   const bool ghosts = (h->unfused && !h->batch) || h->mesh;
+  const int64_t ncell = h->batch ? h->ctot : h->g.cblock * nblocks;
+  const int64_t nface = h->batch ? h->ftot : h->g.fblock * nblocks;
+  if (sc.nstage == 1) {
+    // a single-stage scheme cannot update in place: its stage writes the
+    // active entries of a register, which is copied back whole afterwards;
+    // seed the register with the input so that the copy leaves ghost cells
+    // and periodic-image faces as they were (they are not part of a step)
+    if ((e = launch_copy(h->reg[0], cons, ncell, s)) != hipSuccess) return hip_fail(h, e, "copy launch");
+    if ((e = launch_copy(h->reg[0] + h->reg_coff, bface, nface, s)) != hipSuccess)
+      return hip_fail(h, e, "copy launch");
+  }
   for (int st = 0; st < sc.nstage; ++st) {
     // the VL2 predictor always uses donor-cell fluxes (Sec. 3.2.3)
     const int recon = (h->cfg.integrator == ATHMHD_VL2 && st == 0) ? ATHMHD_RECON_DC : h->cfg.recon;
@@ -362,10 +373,8 @@ int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const doubl
     xb = ob;
   }
   if (xc != cons) {  // single-stage scheme: the result sits in a register
-    const int64_t nc = h->batch ? h->ctot : h->g.cblock * nblocks;
-    const int64_t nf = h->batch ? h->ftot : h->g.fblock * nblocks;
-    if ((e = launch_copy(cons, xc, nc, s)) != hipSuccess) return hip_fail(h, e, "copy launch");
-    if ((e = launch_copy(bface, xb, nf, s)) != hipSuccess) return hip_fail(h, e, "copy launch");
+    if ((e = launch_copy(cons, xc, ncell, s)) != hipSuccess) return hip_fail(h, e, "copy launch");
+    if ((e = launch_copy(bface, xb, nface, s)) != hipSuccess) return hip_fail(h, e, "copy launch");
   }
   return ATHMHD_OK;
 }
@@ -731,14 +740,14 @@ int athmhd_floor_count(athmhd_t h, long long* count, void* stream) {
   if (!count) return fail(h, ATHMHD_EINVAL, "NULL count");
   hipStream_t s = (hipStream_t)stream;
   char* hp = (char*)h->h_pinned;
-  hipError_t e = hipMemcpyAsync(hp + 12, h->d_bad + 1, 4, hipMemcpyDeviceToHost, s);
+  hipError_t e = hipMemcpyAsync(hp, h->d_bad + 2, 8, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, h->d_dtmin, 0ull, h->d_bad, 2);
   if (e == hipSuccess) e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(h, e, "floor count");
-  int n;
-  std::memcpy(&n, hp + 12, 4);
-  *count = n;
+  unsigned long long n;
+  std::memcpy(&n, hp, 8);
+  *count = (long long)n;
   return ATHMHD_OK;
 }
 

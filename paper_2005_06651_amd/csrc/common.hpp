@@ -62,6 +62,13 @@ struct Floors {
   __host__ __device__ bool on() const { return d > 0.0 || p > 0.0; }
 };
 
+// Event counters of a handle, one device array of four ints: [0] counts
+// non-physical cells met since the last newdt; ints [2, 4) hold the 64-bit
+// count of floor activations, which a long run with floors can take past 2^31.
+__device__ __forceinline__ void add_floor_count(int* bad, unsigned long long n) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(bad + 2), n);
+}
+
 // Periodic image of a stored index along a direction with n active cells.
 __host__ __device__ __forceinline__ int wrap_index(int idx, int n, int ng) {
   int r = (idx - ng) % n;

@@ -27,7 +27,7 @@ hipError_t launch_mesh_ghosts(const Geo& g, int w, double* cons, double* bface, 
 hipError_t launch_restrict(const Geo& g, const int flo[3], const int clo[3], const int ext[3], const double* fc,
                            const double* fb, double* cc, double* cb, hipStream_t s);
 // primitive: prolong (rho, v, P, C_i) instead of U; otherwise pfloor > 0
-// applies the pressure floor to the refined cells, activations in bad[1].
+// applies the pressure floor to the refined cells, activations counted in bad.
 // keep: bit 2 d + S keeps the fine faces already on side S of the box along d.
 hipError_t launch_prolong(const Geo& g, const int flo[3], const int clo[3], const int ext[3], const double* cc,
                           const double* cb, double* fc, double* fb, bool primitive, int keep, double gamma,
@@ -39,17 +39,21 @@ hipError_t launch_prim2cons(const Geo& g, double gamma, const double* prim, cons
 hipError_t launch_newdt(const Geo& g, double gamma, const double* cons, const double* bface, int nb,
                         unsigned long long* dt_bits, const Floors& fl, int* bad, hipStream_t s);
 
+
 // One stage of the unfused pipeline: out = g0*x + g1*un + bdt * L(x), where
 // x must have filled ghosts.  out must not alias x; un may alias out.
+// dt_dev, if not NULL, supplies dt on the device (bdt = beta * dt).
 hipError_t launch_stage_unfused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
                                 const double* xb, const double* unc, const double* unb, double* outc,
-                                double* outb, StageCoef coef, int nb, UnfusedScratch& scr, const Floors& fl,
-                                int* bad, bool charac, hipStream_t s);  // charac: PLM on characteristic variables
+                                double* outb, StageCoef coef, const double* dt_dev, double beta, int nb,
+                                UnfusedScratch& scr, const Floors& fl, int* bad,
+                                bool charac, hipStream_t s);  // charac: PLM on characteristic variables
 
 // One stage in a single fused kernel (same contract as launch_stage_unfused);
 // kz = x3 planes per workgroup segment (0: default for the block size).
 // dt_dev, if not NULL, supplies dt on the device (bdt = beta * dt).
-// bad[0] counts threads that met a non-physical cell, bad[1] floor activations.
+// bad[0] counts threads that met a non-physical cell; floor activations go to
+// the 64-bit counter of add_floor_count.
 hipError_t launch_stage_fused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
                               const double* xb, const double* unc, const double* unb, double* outc, double* outb,
                               StageCoef coef, const double* dt_dev, double beta, int nb, int kz, Floors fl, int* bad,
@@ -111,7 +115,7 @@ hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s)
 
 // Floors on the conserved state of the active cells after a stage: rho raised
 // to fl.d, and E raised where the pressure implied by (U, B) is below fl.p
-// (face fields are read with periodic wrap).  Changed cells count in bad[1].
+// (face fields are read with periodic wrap).  Changed cells are counted in bad.
 hipError_t launch_floor_state(const Geo& g, double gamma, const Floors& fl, double* cons, const double* bface, int nb,
                               int* bad, hipStream_t s);
 hipError_t launch_floor_state_batch(const BatchDesc* desc, int nblocks, double gamma, const Floors& fl, double* cons,

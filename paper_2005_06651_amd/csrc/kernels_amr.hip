@@ -30,7 +30,7 @@ struct OctArgs {
   int keep;     // prolongation: bit 2 d + S keeps the fine faces on side S of the box along d
   double gm1;     // gamma - 1
   double pfloor;  // pressure floor of the refined cells (prolongation; 0: off)
-  int* bad;       // bad[1] counts floor activations
+  int* bad;       // floor activations counted with add_floor_count
 };
 
 // Thread index in the box's point order, XCD-aware: workgroup b runs on
@@ -386,7 +386,7 @@ __global__ void __launch_bounds__(kAmrThreads)
           ++hits;
         }
       }
-  if (hits) atomicAdd(A.bad + 1, hits);
+  if (hits) add_floor_count(A.bad, (unsigned long long)hits);
 }
 
 OctArgs box_args(const Geo& g, const int flo[3], const int clo[3], const int ext[3]) {

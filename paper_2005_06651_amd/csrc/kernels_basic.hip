@@ -267,7 +267,7 @@ __global__ void __launch_bounds__(kThreads) k_newdt(Geo g, double gamma, Floors 
 // below the floor is raised to it, and where the pressure implied by (U, B)
 // is below the pressure floor the total energy is raised to give exactly that
 // pressure.  The cell-centred field is that of cell_field.  Changed cells are
-// counted in bad[1].
+// counted with add_floor_count.
 __device__ __forceinline__ int floor_cell(const Geo& g, double gm1, const Floors& fl, double* u,
                                           const double* fb, const double* all_fb, int b, int i, int j, int k) {
   const int q = g.c(i, j, k);
@@ -300,7 +300,7 @@ __global__ void __launch_bounds__(kThreads) k_floor_state(Geo g, double gm1, Flo
   const int r = (int)(t / g.n1);
   const int j = g.ng + r % g.n2, k = g.ng + r / g.n2;
   if (floor_cell(g, gm1, fl, cons + blockIdx.y * g.cblock, bface + blockIdx.y * g.fblock, bface, blockIdx.y, i, j, k))
-    atomicAdd(bad + 1, 1);
+    add_floor_count(bad, 1ull);
 }
 
 __global__ void __launch_bounds__(kThreads) k_floor_state_batch(const BatchDesc* __restrict__ desc, double gm1,
@@ -317,7 +317,7 @@ __global__ void __launch_bounds__(kThreads) k_floor_state_batch(const BatchDesc*
     const int j = g.ng + r % g.n2, k = g.ng + r / g.n2;
     hits += floor_cell(g, gm1, fl, cons + d.coff, bface + d.foff, bface + d.foff, 0, i, j, k);
   }
-  if (hits) atomicAdd(bad + 1, hits);
+  if (hits) add_floor_count(bad, (unsigned long long)hits);
 }
 
 __global__ void __launch_bounds__(kThreads) k_copy(double* __restrict__ dst, const double* __restrict__ src,

@@ -51,7 +51,7 @@ struct StageArgs {
   const double* dt_dev;  // optional device copy of dt: bdt = beta * (*dt_dev)
   double beta;
   Floors fl;             // optional primitive floors
-  int* bad;              // [0]: threads that met a non-physical cell, [1]: floor activations
+  int* bad;              // [0]: threads that met a non-physical cell; floor activations (add_floor_count)
 };
 
 // Arrays of one block: stage input (periodic images are read by index wrap,
@@ -602,7 +602,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
   if (act && kend >= k0)
     face_update(g, sc, tid, BX, NT, gi, gj, kend, k0, kend, i1, i2, i3, bdt, pwb, acc_prev, ob);
   if (nbad && act) atomicAdd(sa.bad, 1);
-  if (nfl && act) atomicAdd(sa.bad + 1, nfl);
+  if (nfl && act) add_floor_count(sa.bad, (unsigned long long)nfl);
 }
 
 // Uniform blocks: one workgroup per (tile, x3 segment, block), XCD-aware:

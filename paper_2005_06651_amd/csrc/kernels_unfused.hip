@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(kThreads) k_prim(Geo g, double gamma, Floors f
   // ghost cells are periodic images of active ones: count active cells only
   const bool act = i >= g.ng && i < g.ng + g.n1 && j >= g.ng && j < g.ng + g.n2 && k >= g.ng && k < g.ng + g.n3;
   if (act && (flags & 1)) atomicAdd(bad, 1);
-  if (act && (flags & 2)) atomicAdd(bad + 1, 1);
+  if (act && (flags & 2)) add_floor_count(bad, 1ull);
 }
 
 template <int RECON>
@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(kThreads) k_flux(Geo g, Gas gas, double ct_eps
   const double bn = fb[D * g.fvar + fi];
   if (fl.on()) {
     const int n = floor_state(L, fl) + floor_state(R, fl);
-    if (n) atomicAdd(bad + 1, n);
+    if (n) add_floor_count(bad, (unsigned long long)n);
   }
   FaceFlux F;
   double smax;
@@ -367,8 +367,11 @@ __global__ void __launch_bounds__(kThreads) k_corner(Geo g, const double* __rest
   }
 }
 
-// out = g0 x + g1 un + bdt L(x) on the active cells and their lower faces.
-__global__ void __launch_bounds__(kThreads) k_update(Geo g, StageCoef cf, const double* __restrict__ xc,
+// out = g0 x + g1 un + bdt L(x) on the active cells and their lower faces;
+// bdt = beta * (*dt_dev) when dt_dev is not NULL (a step replayed from a
+// graph reads its dt on the device), else cf.bdt.
+__global__ void __launch_bounds__(kThreads) k_update(Geo g, StageCoef cf, const double* dt_dev, double beta,
+                                                    const double* __restrict__ xc,
                                                     const double* __restrict__ xb, const double* unc,
                                                     const double* unb, const double* __restrict__ f0,
                                                     const double* __restrict__ f1, const double* __restrict__ f2,
@@ -381,6 +384,7 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, StageCoef cf, const 
   const int b = blockIdx.y;
   const int q = g.c(i, j, k), fc = g.f(i, j, k);
   const int s2 = g.F1, s3 = g.F1 * g.F2;
+  const double bdt = dt_dev ? beta * *dt_dev : cf.bdt;
   const double* F0 = f0 + b * 8 * g.fvar;
   const double* F1 = f1 + b * 8 * g.fvar;
   const double* F2 = f2 + b * 8 * g.fvar;
@@ -393,7 +397,7 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, StageCoef cf, const 
     const int64_t fv = v * g.fvar + fc;
     const double div = (F0[fv + 1] - F0[fv]) * i1 + (F1[fv + s2] - F1[fv]) * i2 + (F2[fv + s3] - F2[fv]) * i3;
     const int64_t cv = v * g.cvar + q;
-    o[cv] = cf.g0 * x[cv] + cf.g1 * un[cv] - cf.bdt * div;
+    o[cv] = cf.g0 * x[cv] + cf.g1 * un[cv] - bdt * div;
   }
   const double* E = edge + b * 3 * g.fvar;
   const double* xbb = xb + b * g.fblock;
@@ -408,9 +412,9 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, StageCoef cf, const 
   const double c2 = (E1[fc + s3] - E1[fc]) * i3 - (E3[fc + 1] - E3[fc]) * i1;
   // dB3 = -[(E2(i+1) - E2(i))/dx1 - (E1(j+1) - E1(j))/dx2]
   const double c3 = (E2[fc + 1] - E2[fc]) * i1 - (E1[fc + s2] - E1[fc]) * i2;
-  ob[fc] = cf.g0 * xbb[fc] + cf.g1 * unbb[fc] - cf.bdt * c1;
-  ob[g.fvar + fc] = cf.g0 * xbb[g.fvar + fc] + cf.g1 * unbb[g.fvar + fc] - cf.bdt * c2;
-  ob[2 * g.fvar + fc] = cf.g0 * xbb[2 * g.fvar + fc] + cf.g1 * unbb[2 * g.fvar + fc] - cf.bdt * c3;
+  ob[fc] = cf.g0 * xbb[fc] + cf.g1 * unbb[fc] - bdt * c1;
+  ob[g.fvar + fc] = cf.g0 * xbb[g.fvar + fc] + cf.g1 * unbb[g.fvar + fc] - bdt * c2;
+  ob[2 * g.fvar + fc] = cf.g0 * xbb[2 * g.fvar + fc] + cf.g1 * unbb[2 * g.fvar + fc] - bdt * c3;
 }
 
 template <int D, int RECON, bool CHAR>
@@ -441,8 +445,8 @@ hipError_t flux_dir(const Geo& g, const Gas& gas, int recon, bool charac, int rs
 
 hipError_t launch_stage_unfused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
                                 const double* xb, const double* unc, const double* unb, double* outc,
-                                double* outb, StageCoef coef, int nb, UnfusedScratch& scr, const Floors& fl,
-                                int* bad, bool charac, hipStream_t s) {
+                                double* outb, StageCoef coef, const double* dt_dev, double beta, int nb,
+                                UnfusedScratch& scr, const Floors& fl, int* bad, bool charac, hipStream_t s) {
   Gas gas{gamma, gamma - 1.0, 1.0 / (gamma - 1.0)};
   hipLaunchKernelGGL(k_prim, dim3(grid_for(g.cvar), nb), dim3(kThreads), 0, s, g, gamma, fl, xc, xb, scr.w, bad);
   hipError_t e = hipGetLastError();
@@ -458,7 +462,7 @@ hipError_t launch_stage_unfused(const Geo& g, double gamma, int recon, int rs, d
                      scr.face[2], scr.edge);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int64_t na = (int64_t)g.n1 * g.n2 * g.n3;
-  hipLaunchKernelGGL(k_update, dim3(grid_for(na), nb), dim3(kThreads), 0, s, g, coef, xc, xb, unc, unb,
+  hipLaunchKernelGGL(k_update, dim3(grid_for(na), nb), dim3(kThreads), 0, s, g, coef, dt_dev, beta, xc, xb, unc, unb,
                      scr.face[0], scr.face[1], scr.face[2], scr.edge, outc, outb);
   return hipGetLastError();
 }

@@ -353,6 +353,38 @@ def smooth_random(n=(16, 16, 16), seed=0, ng=2, gamma=5.0 / 3.0, vmax=0.9, kmax=
                  meta=dict(workload="smooth_random", seed=seed))
 
 
+def x1_profile(n=(32, 6, 5), seed=0, ng=2, gamma=5.0 / 3.0, base=(1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0),
+               amp=(0.0, 0.0, 0.3, 0.3, 0.0, 0.0, 0.0), b1=1.0, dx=None) -> Block:
+    """State that varies along x1 only: each of (rho, v1, v2, v3, P, B2, B3) is
+    base + amp * f(x1), f a seeded smooth periodic profile (modes 1..3, max
+    |f| = 1) sampled at cell centres, and B1 = b1 everywhere.  B2 and B3 are
+    the same on every face of a column, so the discrete div B is zero."""
+    rng = np.random.default_rng(seed)
+    n1, n2, n3 = n
+    if dx is None:
+        dx = (1.0 / n1, 1.0 / n1, 1.0 / n1)
+    L = dx[0] * n1
+    xs = (np.arange(n1) + 0.5) * dx[0]
+    prof = []
+    for q in range(7):
+        f = np.zeros(n1)
+        for m in range(1, 4):
+            f += rng.normal() * np.sin(2 * math.pi * m * xs / L + rng.uniform(0, 2 * math.pi))
+        prof.append(base[q] + amp[q] * f / np.abs(f).max())
+    shape = (n3 + 2 * ng, n2 + 2 * ng, n1 + 2 * ng)
+    cells = _wrapped_index(shape[2], n1, ng) - ng        # active column of every stored x1 index
+    faces = _wrapped_index(shape[2] + 1, n1, ng) - ng    # same for the padded face arrays
+    prim = np.empty((5,) + shape)
+    for q in range(5):
+        prim[q] = prof[q][cells][None, None, :]
+    bf = np.zeros((3, shape[0] + 1, shape[1] + 1, shape[2] + 1))
+    bf[0] = b1
+    bf[1] = prof[5][faces][None, None, :]
+    bf[2] = prof[6][faces][None, None, :]
+    return Block(n=(n1, n2, n3), ng=ng, dx=tuple(dx), gamma=gamma, bface=bf, prim=prim,
+                 meta=dict(workload="x1_profile", seed=seed))
+
+
 def with_scalars(block: Block, nscalars: int, seed: int = 0, width: float = 0.1) -> Block:
     """The block with nscalars passive-scalar rows appended to its primitives:
     specific densities C_i of seeded tracer patterns on the block's periodic

@@ -205,3 +205,37 @@ def test_characteristic_turbulence_256_sampled_windows(torch_dev, athmhd, orc):
         worst = max(worst, max(errs))
     assert worst <= TOL
     s.close()
+
+
+@pytest.mark.parametrize("charac,kernel_path,integ", [(True, "fused", "vl2"), (False, "unfused", "rk3"),
+                                                       (True, "fused", "rk1")])
+def test_unfused_graph_replay_matches_eager(torch_dev, athmhd, orc, charac, kernel_path, integ):
+    """Steps replayed from a hipGraph on handles that run the unfused pipeline
+    (characteristic reconstruction, or kernel_path 1) equal eager steps
+    bitwise; the replayed stages read each step's dt on the device, so a
+    replay that ignored it would leave the state unchanged.  Eager work and
+    synchronisations run between the replays, and dt changes every step."""
+    torch, dev = torch_dev
+    stream = torch.cuda.Stream()
+    recon = "ppm" if integ == "rk3" else "plm"
+    b = inputs.smooth_random(n=(21, 14, 9), seed=84, ng=3 if recon == "ppm" else 2)
+    kw = dict(integrator=integ, recon=recon, riemann="hlld", kernel_path=kernel_path, charac=charac)
+    cfg = orc.cfg_for(b, recon=recon)
+    c0 = to_dev(torch, dev, orc.prim2cons(cfg, b.prim, b.bface))
+    b0 = to_dev(torch, dev, b.bface)
+    eager = athmhd.Solver(b.n, b.ng, b.dx, b.gamma, **kw)
+    graph = athmhd.Solver(b.n, b.ng, b.dx, b.gamma, **kw)
+    graph.set_graph(True)
+    ce, be, cg, bg = c0.clone(), b0.clone(), c0.clone(), b0.clone()
+    with torch.cuda.stream(stream):
+        for it in range(3):
+            before = cg.clone()
+            dt = eager.newdt(ce, be, stream=stream) * (0.7 + 0.1 * it)
+            eager.step(ce, be, dt, stream=stream)
+            graph.step(cg, bg, dt, stream=stream)
+            stream.synchronize()
+            torch.ones(1000, device=dev).sum()
+            assert not torch.equal(before, cg), it
+            assert torch.equal(ce, cg) and torch.equal(be, bg), it
+    eager.close()
+    graph.close()
