@@ -145,6 +145,35 @@ ATHMHD_API int athmhd_step(athmhd_t h, double* cons, double* bface, double dt, i
 ATHMHD_API int athmhd_newdt(athmhd_t h, const double* cons, const double* bface, int nblocks, double* dt_host,
                  void* stream);
 
+/* Most blocks one call of athmhd_newdt_noalloc accepts. */
+#define ATHMHD_NOALLOC_MAX_BLOCKS 65536
+
+/* Allocation-free athmhd_newdt, for callers that cannot allocate device or
+ * pinned host memory or synchronise: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  The same reduction over the
+ * same cells, with its results left in caller-owned device memory instead of
+ * host memory:
+ *   dt_dev[0]   = cfl * min over active cells and directions of
+ *                 dx_d / (|v_d| + c_f,d), the value athmhd_newdt returns
+ *                 (+inf when no cell is physical; the minimum over the
+ *                 physical cells otherwise);
+ *   nbad_dev[0] = non-physical cells met by this reduction plus those met by
+ *                 steps since the previous newdt call; the handle's counter
+ *                 is then cleared, as athmhd_newdt clears it.  A caller
+ *                 checks nbad_dev[0] == 0 where athmhd_newdt would return
+ *                 ATHMHD_ENONPHYS.
+ * The call allocates nothing, copies nothing to the host and never
+ * synchronises; it only enqueues two kernels on `stream`.  Its partial results
+ * (one per workgroup, at most ATHMHD_NOALLOC_MAX_BLOCKS of 16 bytes, 1 MiB)
+ * live in a fixed device array of the library, one per GPU, kept until the
+ * process ends and fully rewritten by every call, so nothing needs clearing.
+ * Calls that overlap on one GPU (several streams, or host threads) share that
+ * array and race: serialise them.  The handle's device must be current.
+ * ATHMHD_EINVAL for NULL outputs or nblocks > ATHMHD_NOALLOC_MAX_BLOCKS, and
+ * as athmhd_newdt for the other arguments. */
+ATHMHD_API int athmhd_newdt_noalloc(athmhd_t h, const double* cons, const double* bface, int nblocks, double* dt_dev,
+                                    int32_t* nbad_dev, void* stream);
+
 /* cons <- conserved variables of (prim, bface) on every stored cell, using the
  * cell-centred field (mean of the two bounding faces).  Asynchronous. */
 ATHMHD_API int athmhd_prim2cons(athmhd_t h, const double* prim, const double* bface, double* cons, int nblocks,

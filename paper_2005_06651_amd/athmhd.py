@@ -23,7 +23,7 @@ EXPORTED = ["athmhd_version", "athmhd_create", "athmhd_create_batch", "athmhd_ba
             "athmhd_prim2cons", "athmhd_fill_ghosts", "athmhd_profile", "athmhd_last_error", "athmhd_destroy",
             "athmhd_step_vjp", "athmhd_prim2cons_vjp", "athmhd_set_floors", "athmhd_floor_count",
             "athmhd_step_stages", "athmhd_create_mesh", "athmhd_restrict", "athmhd_prolong",
-            "athmhd_restrict_box", "athmhd_prolong_box"]
+            "athmhd_restrict_box", "athmhd_prolong_box", "athmhd_newdt_noalloc"]
 BATCH_TILES = [(16, 12), (12, 16), (14, 14), (16, 8)]  # active columns of the batch tile candidates
 
 
@@ -69,6 +69,7 @@ def lib():
         L.athmhd_set_graph.argtypes = [vp, C.c_int]
         L.athmhd_step.argtypes = [vp, vp, vp, C.c_double, C.c_int, vp]
         L.athmhd_newdt.argtypes = [vp, vp, vp, C.c_int, C.POINTER(C.c_double), vp]
+        L.athmhd_newdt_noalloc.argtypes = [vp, vp, vp, C.c_int, vp, vp, vp]
         L.athmhd_prim2cons.argtypes = [vp, vp, vp, vp, C.c_int, vp]
         L.athmhd_fill_ghosts.argtypes = [vp, vp, vp, C.c_int, vp]
         L.athmhd_step_vjp.argtypes = [vp, vp, vp, C.c_double, vp, vp, vp, vp, vp, C.c_int, vp]
@@ -104,6 +105,16 @@ def _check(rc: int, h) -> None:
     if rc != OK:
         msg = lib().athmhd_last_error(h).decode(errors="replace")
         raise (NonPhysicalState if rc == ENONPHYS else AthmhdError)(rc, msg)
+
+
+def _scalar_out(t, dtype: str):
+    """Device address of a one-element (or longer) contiguous output tensor."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or str(t.dtype) != "torch." + dtype:
+        raise TypeError(f"expected a {dtype} tensor in HIP device memory")
+    if t.numel() < 1 or not t.is_contiguous():
+        raise ValueError("output tensor must be contiguous with at least one element")
+    return C.c_void_p(t.data_ptr())
 
 
 def _stream(stream):
@@ -176,6 +187,14 @@ class Solver:
         out = C.c_double()
         _check(lib().athmhd_newdt(self._h, pc, pb, nb, C.byref(out), _stream(stream)), self._h)
         return out.value
+
+    def newdt_noalloc(self, cons, bface, dt_out, nbad_out, stream=None) -> None:
+        """athmhd_newdt_noalloc: dt into dt_out[0] (float64) and the
+        non-physical count into nbad_out[0] (int32), both device tensors;
+        asynchronous, allocates nothing."""
+        pc, pb, nb = self._pair(cons, bface)
+        _check(lib().athmhd_newdt_noalloc(self._h, pc, pb, nb, _scalar_out(dt_out, "float64"),
+                                          _scalar_out(nbad_out, "int32"), _stream(stream)), self._h)
 
     def prim2cons(self, prim, bface, out=None, stream=None):
         import torch
@@ -421,6 +440,11 @@ class BatchSolver:
         out = C.c_double()
         _check(lib().athmhd_newdt(self._h, pc, pb, self.nblocks, C.byref(out), _stream(stream)), self._h)
         return out.value
+
+    def newdt_noalloc(self, cons, bface, dt_out, nbad_out, stream=None) -> None:
+        pc, pb = self._pair(cons, bface)
+        _check(lib().athmhd_newdt_noalloc(self._h, pc, pb, self.nblocks, _scalar_out(dt_out, "float64"),
+                                          _scalar_out(nbad_out, "int32"), _stream(stream)), self._h)
 
     def prim2cons(self, prim, bface, out=None, stream=None):
         import torch

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -460,11 +461,40 @@ int alloc_adjoint(athmhd_t h) {
   return ATHMHD_OK;
 }
 
+// ---- allocation-free CFL reduction (athmhd_newdt_noalloc) -----------------
+// One partial result per workgroup of the reduction, in a fixed array of the
+// library: each GPU the library runs on holds its own copy until the process
+// ends.  In host code `scratch` is only a stand-in for the symbol; its device
+// address on each device is found once, with that device current, and only
+// that address is passed to kernels.
+static __device__ __align__(256) DtPart scratch[ATHMHD_NOALLOC_MAX_BLOCKS];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+DtPart* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of scratch on device dev, which must be current.
+int noalloc_scratch(athmhd_t h, int dev, DtPart** out) {
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(h, ATHMHD_EUNSUP, "device %d: the library keeps scratch addresses for devices 0..%d", dev,
+                kMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(h, e, "address of the newdt scratch array");
+    if (!p) return fail(h, ATHMHD_EHIP, "address of the newdt scratch array is NULL");
+    g_scratch_ptr[dev] = static_cast<DtPart*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return ATHMHD_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-int athmhd_version(void) { return 108; }
+int athmhd_version(void) { return 109; }
 
 int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
   if (!out) return fail(nullptr, ATHMHD_EINVAL, "out is NULL");
@@ -1035,6 +1065,31 @@ int athmhd_newdt(athmhd_t h, const double* cons, const double* bface, int nblock
     return fail(h, ATHMHD_ENONPHYS, "%d non-physical cell evaluations (rho <= 0, P <= 0 or not finite)", bad);
   }
   return ATHMHD_OK;
+}
+
+int athmhd_newdt_noalloc(athmhd_t h, const double* cons, const double* bface, int nblocks, double* dt_dev,
+                         int32_t* nbad_dev, void* stream) {
+  int rc = check_call(h, cons, bface, nblocks);
+  if (rc) return rc;
+  if (!dt_dev || !nbad_dev) return fail(h, ATHMHD_EINVAL, "NULL dt_dev or nbad_dev");
+  if (nblocks > ATHMHD_NOALLOC_MAX_BLOCKS)
+    return fail(h, ATHMHD_EINVAL, "athmhd_newdt_noalloc takes at most %d blocks per call (got %d)",
+                ATHMHD_NOALLOC_MAX_BLOCKS, nblocks);
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(h, e, "hipGetDevice");
+  if (dev != h->device) return fail(h, ATHMHD_EINVAL, "current device %d is not the handle's device %d", dev, h->device);
+  DtPart* parts = nullptr;
+  if ((rc = noalloc_scratch(h, dev, &parts)) != ATHMHD_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  int nparts = 0;
+  e = h->batch ? launch_newdt_parts_batch(h->d_desc, h->nbatch, h->cfg.gamma, cons, bface, h->floors, parts,
+                                          ATHMHD_NOALLOC_MAX_BLOCKS, &nparts, s)
+               : launch_newdt_parts(h->g, h->cfg.gamma, cons, bface, nblocks, h->floors, parts,
+                                    ATHMHD_NOALLOC_MAX_BLOCKS, &nparts, s);
+  if (e != hipSuccess) return hip_fail(h, e, "newdt launch");
+  e = launch_newdt_finish(parts, nparts, h->cfg.cfl, h->d_bad, dt_dev, nbad_dev, s);
+  return e == hipSuccess ? ATHMHD_OK : hip_fail(h, e, "newdt reduction launch");
 }
 
 int athmhd_profile(athmhd_t h, int enable, double* total_ms, int* launches) {

@@ -7,6 +7,7 @@
 namespace athmhd {
 
 struct Gas;
+struct BatchDesc;
 
 // Scratch of the unfused pipeline for nb blocks: cell primitives (8 arrays:
 // rho, v1, v2, v3, p, B1cc, B2cc, B3cc), per-direction face data (8 arrays:
@@ -39,6 +40,25 @@ hipError_t launch_prim2cons(const Geo& g, double gamma, const double* prim, cons
 hipError_t launch_newdt(const Geo& g, double gamma, const double* cons, const double* bface, int nb,
                         unsigned long long* dt_bits, const Floors& fl, int* bad, hipStream_t s);
 
+// The same CFL reduction in two launches that use no atomics and need no
+// cleared memory: one partial result per workgroup (minimum of
+// dx_d/(|v_d| + c_f,d), DBL_MAX if the workgroup met no physical cell, and
+// its count of non-physical cells), then one workgroup that reduces them.
+struct DtPart {
+  double m;
+  int nbad, pad;
+};
+// At most max_parts partials are written (one launch over every block;
+// *nparts receives the count); hipErrorInvalidValue when nb > max_parts.
+hipError_t launch_newdt_parts(const Geo& g, double gamma, const double* cons, const double* bface, int nb,
+                              const Floors& fl, DtPart* parts, int max_parts, int* nparts, hipStream_t s);
+hipError_t launch_newdt_parts_batch(const BatchDesc* desc, int nblocks, double gamma, const double* cons,
+                                    const double* bface, const Floors& fl, DtPart* parts, int max_parts, int* nparts,
+                                    hipStream_t s);
+// dt_out = cfl * min of the partials (+inf if none is finite); nbad_out = their
+// counts plus *step_bad, which is then cleared.
+hipError_t launch_newdt_finish(const DtPart* parts, int nparts, double cfl, int* step_bad, double* dt_out,
+                               int* nbad_out, hipStream_t s);
 
 // One stage of the unfused pipeline: out = g0*x + g1*un + bdt * L(x), where
 // x must have filled ghosts.  out must not alias x; un may alias out.

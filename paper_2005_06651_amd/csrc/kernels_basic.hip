@@ -217,10 +217,47 @@ __global__ void __launch_bounds__(kThreads) k_prim2cons(Geo g, double gamma, con
 // (non-negative doubles order like their bits).
 constexpr int kDtBlocks = 1024;
 
+// End of a CFL workgroup: its minimum and non-physical count, either merged
+// into the global result word and counter with atomics (PARTS = false) or
+// written as the workgroup's partial result parts[wg] (PARTS = true; a later
+// reduction reads them, so nothing needs clearing before the launch).
+template <bool PARTS>
+__device__ __forceinline__ void dt_workgroup_end(double best, int nbad, unsigned long long* dt_bits, int* bad,
+                                                 DtPart* parts, int64_t wg) {
+  if (!PARTS && nbad) atomicAdd(bad, nbad);
+  // wavefront minimum (and count)
+  for (int off = 32; off > 0; off >>= 1) {
+    best = fmin(best, __shfl_xor(best, off, 64));
+    if (PARTS) nbad += __shfl_xor(nbad, off, 64);
+  }
+  __shared__ double part[kThreads / 64];
+  __shared__ int pbad[kThreads / 64];
+  if ((threadIdx.x & 63) == 0) {
+    part[threadIdx.x >> 6] = best;
+    pbad[threadIdx.x >> 6] = nbad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = part[0];
+    int nb = pbad[0];
+    for (int w = 1; w < kThreads / 64; ++w) {
+      m = fmin(m, part[w]);
+      nb += pbad[w];
+    }
+    if (PARTS) {
+      parts[wg].m = m;
+      parts[wg].nbad = nb;
+    } else if (m < DBL_MAX) {
+      atomicMin(dt_bits, (unsigned long long)__double_as_longlong(m));
+    }
+  }
+}
+
+template <bool PARTS>
 __global__ void __launch_bounds__(kThreads) k_newdt(Geo g, double gamma, Floors fl, const double* __restrict__ cons,
                                                    const double* __restrict__ bface,
                                                    unsigned long long* __restrict__ dt_bits,
-                                                   int* __restrict__ bad) {
+                                                   int* __restrict__ bad, DtPart* __restrict__ parts) {
   const int64_t nact = (int64_t)g.n1 * g.n2 * g.n3;
   const double* u = cons + blockIdx.y * g.cblock;
   const double* fb = bface + blockIdx.y * g.fblock;
@@ -250,17 +287,7 @@ __global__ void __launch_bounds__(kThreads) k_newdt(Geo g, double gamma, Floors 
     if (!(d > 0.0) || !(d < DBL_MAX)) ++nbad;
     else best = fmin(best, d);
   }
-  if (nbad) atomicAdd(bad, nbad);
-  // wavefront minimum
-  for (int off = 32; off > 0; off >>= 1) best = fmin(best, __shfl_xor(best, off, 64));
-  __shared__ double part[kThreads / 64];
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = best;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = part[0];
-    for (int w = 1; w < kThreads / 64; ++w) m = fmin(m, part[w]);
-    if (m < DBL_MAX) atomicMin(dt_bits, (unsigned long long)__double_as_longlong(m));
-  }
+  dt_workgroup_end<PARTS>(best, nbad, dt_bits, bad, parts, (int64_t)blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 // Floors on the conserved state after a stage (floors enabled only): density
@@ -399,13 +426,14 @@ __global__ void __launch_bounds__(kThreads) k_prim2cons_batch(const BatchDesc* _
   }
 }
 
-// one workgroup per block: its minimum of dx_d/(|v_d| + c_f,d), then one
-// atomicMin per block
+// a few workgroups per block: their minima of dx_d/(|v_d| + c_f,d), then one
+// atomicMin per workgroup (or one partial result, PARTS)
+template <bool PARTS>
 __global__ void __launch_bounds__(kThreads) k_newdt_batch(const BatchDesc* __restrict__ desc, double gamma,
                                                          Floors fl, const double* __restrict__ cons,
                                                          const double* __restrict__ bface,
                                                          unsigned long long* __restrict__ dt_bits,
-                                                         int* __restrict__ bad) {
+                                                         int* __restrict__ bad, DtPart* __restrict__ parts) {
   const BatchDesc& d = desc[blockIdx.y];
   const Geo& g = d.g;
   const double* u = cons + d.coff;
@@ -436,15 +464,45 @@ __global__ void __launch_bounds__(kThreads) k_newdt_batch(const BatchDesc* __res
     if (!(dd > 0.0) || !(dd < DBL_MAX)) ++nbad;
     else best = fmin(best, dd);
   }
-  if (nbad) atomicAdd(bad, nbad);
-  for (int off = 32; off > 0; off >>= 1) best = fmin(best, __shfl_xor(best, off, 64));
+  dt_workgroup_end<PARTS>(best, nbad, dt_bits, bad, parts, (int64_t)blockIdx.y * gridDim.x + blockIdx.x);
+}
+
+// Reduction of nparts partial CFL results in one workgroup, in a fixed order
+// (the result does not depend on the scheduling of the partial launch):
+// dt_out = cfl * min (+inf when no cell was physical); nbad_out = the
+// partial counts plus step_bad[0] (non-physical cells met by steps since the
+// last newdt), and step_bad[0] is cleared.
+__global__ void __launch_bounds__(kThreads) k_newdt_finish(const DtPart* __restrict__ parts, int nparts, double cfl,
+                                                          int* __restrict__ step_bad, double* __restrict__ dt_out,
+                                                          int* __restrict__ nbad_out) {
+  double best = DBL_MAX;
+  int nbad = 0;
+  for (int t = threadIdx.x; t < nparts; t += kThreads) {
+    best = fmin(best, parts[t].m);
+    nbad += parts[t].nbad;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    best = fmin(best, __shfl_xor(best, off, 64));
+    nbad += __shfl_xor(nbad, off, 64);
+  }
   __shared__ double part[kThreads / 64];
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = best;
+  __shared__ int pbad[kThreads / 64];
+  if ((threadIdx.x & 63) == 0) {
+    part[threadIdx.x >> 6] = best;
+    pbad[threadIdx.x >> 6] = nbad;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     double m = part[0];
-    for (int w = 1; w < kThreads / 64; ++w) m = fmin(m, part[w]);
-    if (m < DBL_MAX) atomicMin(dt_bits, (unsigned long long)__double_as_longlong(m));
+    int nb = pbad[0];
+    for (int w = 1; w < kThreads / 64; ++w) {
+      m = fmin(m, part[w]);
+      nb += pbad[w];
+    }
+    nb += step_bad[0];
+    step_bad[0] = 0;
+    *dt_out = cfl * (m < DBL_MAX ? m : (double)INFINITY);
+    *nbad_out = nb;
   }
 }
 
@@ -468,8 +526,25 @@ hipError_t launch_newdt_batch(const BatchDesc* desc, int nblocks, int64_t, doubl
                               const double* bface, unsigned long long* dt_bits, const Floors& fl, int* bad,
                               hipStream_t s) {
   // a few workgroups per block so that small blocks do not serialise
-  hipLaunchKernelGGL(k_newdt_batch, dim3(4, nblocks), dim3(kThreads), 0, s, desc, gamma, fl, cons, bface, dt_bits,
-                     bad);
+  hipLaunchKernelGGL(k_newdt_batch<false>, dim3(4, nblocks), dim3(kThreads), 0, s, desc, gamma, fl, cons, bface,
+                     dt_bits, bad, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_newdt_parts_batch(const BatchDesc* desc, int nblocks, double gamma, const double* cons,
+                                    const double* bface, const Floors& fl, DtPart* parts, int max_parts, int* nparts,
+                                    hipStream_t s) {
+  if (nblocks < 1 || nblocks > max_parts) return hipErrorInvalidValue;
+  const int gx = std::max(1, std::min(4, max_parts / nblocks));
+  *nparts = gx * nblocks;
+  hipLaunchKernelGGL(k_newdt_batch<true>, dim3(gx, nblocks), dim3(kThreads), 0, s, desc, gamma, fl, cons, bface,
+                     nullptr, nullptr, parts);
+  return hipGetLastError();
+}
+
+hipError_t launch_newdt_finish(const DtPart* parts, int nparts, double cfl, int* step_bad, double* dt_out,
+                               int* nbad_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_newdt_finish, dim3(1), dim3(kThreads), 0, s, parts, nparts, cfl, step_bad, dt_out, nbad_out);
   return hipGetLastError();
 }
 
@@ -518,7 +593,20 @@ hipError_t launch_newdt(const Geo& g, double gamma, const double* cons, const do
   // queue tens of thousands of atomics on the one result word
   const int64_t per_block = std::max<int64_t>(1, kDtBlocks / std::max(nb, 1));
   const unsigned blocks = (unsigned)std::min<int64_t>(grid_for(nact), per_block);
-  hipLaunchKernelGGL(k_newdt, dim3(blocks, nb), dim3(kThreads), 0, s, g, gamma, fl, cons, bface, dt_bits, bad);
+  hipLaunchKernelGGL(k_newdt<false>, dim3(blocks, nb), dim3(kThreads), 0, s, g, gamma, fl, cons, bface, dt_bits, bad,
+                     nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_newdt_parts(const Geo& g, double gamma, const double* cons, const double* bface, int nb,
+                              const Floors& fl, DtPart* parts, int max_parts, int* nparts, hipStream_t s) {
+  if (nb < 1 || nb > max_parts) return hipErrorInvalidValue;
+  const int64_t nact = (int64_t)g.n1 * g.n2 * g.n3;
+  const int64_t per_block = std::max<int64_t>(1, std::min<int64_t>(kDtBlocks, max_parts / nb));
+  const unsigned blocks = (unsigned)std::min<int64_t>(grid_for(nact), per_block);
+  *nparts = (int)blocks * nb;
+  hipLaunchKernelGGL(k_newdt<true>, dim3(blocks, nb), dim3(kThreads), 0, s, g, gamma, fl, cons, bface, nullptr,
+                     nullptr, parts);
   return hipGetLastError();
 }
 
