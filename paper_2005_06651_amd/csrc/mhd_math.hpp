@@ -191,28 +191,30 @@ __device__ __forceinline__ void hlld(const FaceState& L, const FaceState& R, dou
 
   // transverse velocity and field of the single-star states (both sides are
   // needed by the double-star state)
+  // (degenerate: the correction factors c1 = 0, c2 = 1 leave the transverse
+  // state unchanged)
   double vt1sl, vt2sl, bt1sl, bt2sl, vt1sr, vt2sr, bt1sr, bt2sr;
   {
     const double d = ml * (sl - sm) - bnsq;
     const bool degen = fabs(d) < kSmall * pts;
     const double id = frcp(degen ? 1.0 : d);
-    const double c1 = bn * (sm - L.vn) * id;
-    const double c2 = (ml * (sl - L.vn) - bnsq) * id;
-    vt1sl = degen ? L.vt1 : L.vt1 - L.bt1 * c1;
-    vt2sl = degen ? L.vt2 : L.vt2 - L.bt2 * c1;
-    bt1sl = degen ? L.bt1 : L.bt1 * c2;
-    bt2sl = degen ? L.bt2 : L.bt2 * c2;
+    const double c1 = degen ? 0.0 : bn * (sm - L.vn) * id;
+    const double c2 = degen ? 1.0 : (ml * (sl - L.vn) - bnsq) * id;
+    vt1sl = L.vt1 - L.bt1 * c1;
+    vt2sl = L.vt2 - L.bt2 * c1;
+    bt1sl = L.bt1 * c2;
+    bt2sl = L.bt2 * c2;
   }
   {
     const double d = mr * (sr - sm) - bnsq;
     const bool degen = fabs(d) < kSmall * pts;
     const double id = frcp(degen ? 1.0 : d);
-    const double c1 = bn * (sm - R.vn) * id;
-    const double c2 = (mr * (sr - R.vn) - bnsq) * id;
-    vt1sr = degen ? R.vt1 : R.vt1 - R.bt1 * c1;
-    vt2sr = degen ? R.vt2 : R.vt2 - R.bt2 * c1;
-    bt1sr = degen ? R.bt1 : R.bt1 * c2;
-    bt2sr = degen ? R.bt2 : R.bt2 * c2;
+    const double c1 = degen ? 0.0 : bn * (sm - R.vn) * id;
+    const double c2 = degen ? 1.0 : (mr * (sr - R.vn) - bnsq) * id;
+    vt1sr = R.vt1 - R.bt1 * c1;
+    vt2sr = R.vt2 - R.bt2 * c1;
+    bt1sr = R.bt1 * c2;
+    bt2sr = R.bt2 * c2;
   }
 
   // double-star state (shared velocity and field)
