@@ -135,7 +135,7 @@ template <class T> inline double sgn(const T& a) { return val(a) > 0.0 ? 1.0 : (
 // Problem description.  Mirrored field by field by a ctypes Structure.
 // ---------------------------------------------------------------------------
 enum { RECON_DC = 0, RECON_PLM = 1, RECON_PPM = 2 };
-enum { RS_HLLE = 0, RS_HLLD = 1 };
+enum { RS_HLLE = 0, RS_HLLD = 1, RS_ROE = 2 };
 enum { INT_RK1 = 0, INT_VL2 = 1, INT_RK2 = 2, INT_RK3 = 3 };
 
 struct Cfg {
@@ -700,8 +700,174 @@ bool hlld(const T* wl, const T* wr, const T& bx, double gamma, T* flux, T& smax,
   return true;
 }
 
+// ---------------------------------------------------------------------------
+// Roe's linearised solver (Sec. 3.2.2 names it beside HLLE and HLLD and
+// prints no formula).  Reading R-34: the Roe matrix A of the pair is the
+// matrix with A (U_R - U_L) = F_R - F_L built from exact identities for
+// differences, with the averages
+//   s_a = sqrt(rho_a),  D = s_L + s_R,  rho_bar = s_L s_R,
+//   q_bar = (s_L q_L + s_R q_R) / D      for q = v (3 components), H,
+//   Bt_bar = (s_R Bt_L + s_L Bt_R) / D   (weights swapped),
+//   X = |Bt_R - Bt_L|^2 / (2 D^2),
+// where H = (E + p + B^2/2) / rho.  For these,
+//   d(rho q) = rho_bar dq + q_bar d rho,   d(rho q r) = rho_bar (q_bar dr +
+//   r_bar dq) + q_bar r_bar d rho,   d(q Bt) = q_bar dBt + Bt_bar dq,
+//   d(B^2 / 2) = Bt_bar . dBt + X d rho
+// hold exactly (d = right minus left).  Writing every difference of U and
+// of the flux F through the primitive differences dW = (d rho, dv, dp, dBt)
+// gives dU = M dW and dF = G dW with M, G built from the averages below, and
+// A = G M^{-1}.  The flux is F = (F_L + F_R)/2 - |A| (U_R - U_L) / 2 with
+// |A| = A sign(A), sign(A) from Newton's iteration S <- (S + S^{-1}) / 2.
+// No entropy fix is applied.
+// ---------------------------------------------------------------------------
+template <class T> void roe_matrix(const T* wl, const T* wr, const T& bx, double gamma, T A[7][7]) {
+  const T sl = sqrt(wl[0]), sr = sqrt(wr[0]);
+  const T D = sl + sr;
+  const T rho = sl * sr;
+  const T u = (sl * wl[1] + sr * wr[1]) / D;
+  const T v = (sl * wl[2] + sr * wr[2]) / D;
+  const T w = (sl * wl[3] + sr * wr[3]) / D;
+  T ul[7], fl[7], ur[7], fr[7];
+  phys_flux(wl, bx, gamma, ul, fl);
+  phys_flux(wr, bx, gamma, ur, fr);
+  const T hl = (ul[4] + wl[4] + 0.5 * (bx * bx + wl[5] * wl[5] + wl[6] * wl[6])) / wl[0];
+  const T hr = (ur[4] + wr[4] + 0.5 * (bx * bx + wr[5] * wr[5] + wr[6] * wr[6])) / wr[0];
+  const T H = (sl * hl + sr * hr) / D;
+  const T by = (sr * wl[5] + sl * wr[5]) / D;
+  const T bz = (sr * wl[6] + sl * wr[6]) / D;
+  const T dby = wr[5] - wl[5], dbz = wr[6] - wl[6];
+  const T X = (dby * dby + dbz * dbz) / (2.0 * D * D);
+  const T ke = 0.5 * (u * u + v * v + w * w);
+  const T z(0.0);
+  // dU = M dW, dW = (d rho, du, dv, dw, dp, dBy, dBz)
+  const T M[7][7] = {
+      {T(1.0), z, z, z, z, z, z},
+      {u, rho, z, z, z, z, z},
+      {v, z, rho, z, z, z, z},
+      {w, z, z, rho, z, z, z},
+      {ke + X, rho * u, rho * v, rho * w, T(1.0 / (gamma - 1.0)), by, bz},
+      {z, z, z, z, z, T(1.0), z},
+      {z, z, z, z, z, z, T(1.0)},
+  };
+  // d(rho H) = dE + dp + d(B^2/2)
+  T drh[7];
+  for (int c = 0; c < 7; ++c) drh[c] = M[4][c];
+  drh[0] = drh[0] + X;
+  drh[4] = drh[4] + 1.0;
+  drh[5] = drh[5] + by;
+  drh[6] = drh[6] + bz;
+  // dF = G dW
+  T G[7][7] = {
+      {u, rho, z, z, z, z, z},
+      {u * u + X, 2.0 * rho * u, z, z, T(1.0), by, bz},
+      {u * v, rho * v, rho * u, z, z, -bx, z},
+      {u * w, rho * w, z, rho * u, z, z, -bx},
+      {z, H * rho - bx * bx, -bx * by, -bx * bz, z, -bx * v, -bx * w},
+      {z, by, -bx, z, z, u, z},
+      {z, bz, z, -bx, z, z, u},
+  };
+  for (int c = 0; c < 7; ++c) G[4][c] = G[4][c] + u * drh[c];
+  T Mi[7][7];
+  invert7(M, Mi);
+  for (int r = 0; r < 7; ++r)
+    for (int c = 0; c < 7; ++c) {
+      T acc(0.0);
+      for (int k = 0; k < 7; ++k) acc = acc + G[r][k] * Mi[k][c];
+      A[r][c] = acc;
+    }
+}
+
+// sign(A) by Newton's iteration; false if it did not converge (A singular
+// or nearly so).
+template <class T> bool matrix_sign(const T A[7][7], T S[7][7]) {
+  for (int r = 0; r < 7; ++r)
+    for (int c = 0; c < 7; ++c) S[r][c] = A[r][c];
+  for (int it = 0; it < 200; ++it) {
+    T Si[7][7];
+    invert7(S, Si);
+    double change = 0.0, size = 0.0;
+    bool finite = true;
+    for (int r = 0; r < 7; ++r)
+      for (int c = 0; c < 7; ++c) {
+        const T nx = 0.5 * (S[r][c] + Si[r][c]);
+        if (!std::isfinite(val(nx))) finite = false;
+        change = std::max(change, std::fabs(val(nx) - val(S[r][c])));
+        size = std::max(size, std::fabs(val(nx)));
+        S[r][c] = nx;
+      }
+    if (!finite) return false;
+    if (change <= 1e-15 * size) return true;
+  }
+  return false;
+}
+
+// y = |A| x = A sign(A) x.  With an eigenvalue at (or within rounding of)
+// zero the iteration fails; |A| is then taken as (|A + d I| + |A - d I|)/2,
+// which differs from |A| only for eigenvalues below d = 1e-14 max|A_ij|.
+template <class T> void abs_apply(const T A[7][7], const T* x, T* y) {
+  T S[7][7];
+  double amax = 0.0;
+  for (int r = 0; r < 7; ++r)
+    for (int c = 0; c < 7; ++c) amax = std::max(amax, std::fabs(val(A[r][c])));
+  if (matrix_sign(A, S)) {
+    T sx[7];
+    for (int r = 0; r < 7; ++r) {
+      sx[r] = T(0.0);
+      for (int c = 0; c < 7; ++c) sx[r] = sx[r] + S[r][c] * x[c];
+    }
+    for (int r = 0; r < 7; ++r) {
+      y[r] = T(0.0);
+      for (int c = 0; c < 7; ++c) y[r] = y[r] + A[r][c] * sx[c];
+    }
+    return;
+  }
+  const double d = 1e-14 * amax;
+  for (int r = 0; r < 7; ++r) y[r] = T(0.0);
+  for (int side = -1; side <= 1; side += 2) {
+    T B[7][7];
+    for (int r = 0; r < 7; ++r)
+      for (int c = 0; c < 7; ++c) B[r][c] = A[r][c] + (r == c ? side * d : 0.0);
+    if (!matrix_sign(B, S)) {
+      for (int r = 0; r < 7; ++r) y[r] = T(NAN);
+      return;
+    }
+    T sx[7];
+    for (int r = 0; r < 7; ++r) {
+      sx[r] = T(0.0);
+      for (int c = 0; c < 7; ++c) sx[r] = sx[r] + S[r][c] * x[c];
+    }
+    for (int r = 0; r < 7; ++r)
+      for (int c = 0; c < 7; ++c) y[r] = y[r] + 0.5 * (B[r][c] * sx[c]);
+  }
+}
+
+template <class T> void roe(const T* wl, const T* wr, const T& bx, double gamma, T* flux, T& smax) {
+  T ul[7], fl[7], ur[7], fr[7];
+  phys_flux(wl, bx, gamma, ul, fl);
+  phys_flux(wr, bx, gamma, ur, fr);
+  // wave-speed bound for the CT weight: the larger |u| + c_f of the two states
+  const T cfl = fast_speed(wl[0], wl[4], bx, wl[5], wl[6], gamma);
+  const T cfr = fast_speed(wr[0], wr[4], bx, wr[5], wr[6], gamma);
+  smax = vmax(fabs(wl[1]) + cfl, fabs(wr[1]) + cfr);
+  T du[7];
+  bool same = true;
+  for (int n = 0; n < 7; ++n) {
+    du[n] = ur[n] - ul[n];
+    if (val(du[n]) != 0.0) same = false;
+  }
+  if (same) {
+    for (int n = 0; n < 7; ++n) flux[n] = fl[n];
+    return;
+  }
+  T A[7][7], d[7];
+  roe_matrix(wl, wr, bx, gamma, A);
+  abs_apply(A, du, d);
+  for (int n = 0; n < 7; ++n) flux[n] = 0.5 * (fl[n] + fr[n]) - 0.5 * d[n];
+}
+
 template <class T> void riemann(int rs, const T* wl, const T* wr, const T& bn, double gamma, T* flux, T& smax) {
   if (rs == RS_HLLD) hlld(wl, wr, bn, gamma, flux, smax);
+  else if (rs == RS_ROE) roe(wl, wr, bn, gamma, flux, smax);
   else hlle(wl, wr, bn, gamma, flux, smax);
 }
 
@@ -1516,6 +1682,15 @@ int orc_hlld_fan(double gamma, const double* wl, const double* wr, double bn, do
     out[20 + n] = fan.uss_r[n];
     out[27 + n] = fan.us_r[n];
   }
+  return 0;
+}
+
+// Roe matrix of a pair (test hook): A (7 x 7, row-major, face frame).
+int orc_roe_matrix(double gamma, const double* wl, const double* wr, double bn, double* A) {
+  double M[7][7];
+  orc::roe_matrix<double>(wl, wr, bn, gamma, M);
+  for (int r = 0; r < 7; ++r)
+    for (int c = 0; c < 7; ++c) A[7 * r + c] = M[r][c];
   return 0;
 }
 

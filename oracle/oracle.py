@@ -17,7 +17,7 @@ SRC = os.path.join(HERE, "athmhd_oracle.cpp")
 LIB = os.path.join(HERE, "liboracle.so")
 
 RECON = {"dc": 0, "plm": 1, "ppm": 2}
-RIEMANN = {"hlle": 0, "hlld": 1}
+RIEMANN = {"hlle": 0, "hlld": 1, "roe": 2}
 INTEGRATOR = {"rk1": 0, "vl2": 1, "rk2": 2, "rk3": 3}
 
 
@@ -58,6 +58,7 @@ def lib():
         _lib.orc_riemann.argtypes = [C.c_int, C.c_double, P, P, C.c_double, P, P]
         _lib.orc_phys_flux.argtypes = [C.c_double, P, C.c_double, P, P]
         _lib.orc_hlld_fan.argtypes = [C.c_double, P, P, C.c_double, P, P]
+        _lib.orc_roe_matrix.argtypes = [C.c_double, P, P, C.c_double, P]
         _lib.orc_fast_speed.argtypes = [C.c_double] * 6
         _lib.orc_fast_speed.restype = C.c_double
         _lib.orc_recon_line.argtypes = [C.c_int, C.c_int, P, P, P]
@@ -176,6 +177,15 @@ def hlld_fan(gamma: float, wl, wr, bn: float):
     if rc:
         return f, None, None
     return f, out[:6].copy(), out[6:].reshape(4, 7).copy()
+
+
+def roe_matrix(gamma: float, wl, wr, bn: float):
+    """Roe matrix of the pair (7 x 7, face frame)."""
+    wl = np.ascontiguousarray(wl, dtype=np.float64)
+    wr = np.ascontiguousarray(wr, dtype=np.float64)
+    a = np.zeros(49)
+    lib().orc_roe_matrix(float(gamma), _p(wl), _p(wr), float(bn), _p(a))
+    return a.reshape(7, 7)
 
 
 def phys_flux(gamma: float, w, bn: float):
