@@ -66,8 +66,12 @@ enum athmhd_status {
 
 /* Reconstruction (Sec. 3.2.1).  The VL2 predictor always uses DC. */
 enum { ATHMHD_RECON_DC = 0, ATHMHD_RECON_PLM = 1, ATHMHD_RECON_PPM = 2 };
-/* Riemann solver (Sec. 3.2.2). */
-enum { ATHMHD_RS_HLLE = 0, ATHMHD_RS_HLLD = 1 };
+/* Riemann solver (Sec. 3.2.2).  Roe's linearised solver uses the Roe matrix
+ * built from exact jump identities with s-weighted velocity and enthalpy
+ * averages and a swapped-weight transverse field average (see roe() in the
+ * library source); no entropy fix.  athmhd_create_batch and athmhd_step_vjp
+ * return ATHMHD_EUNSUP for it. */
+enum { ATHMHD_RS_HLLE = 0, ATHMHD_RS_HLLD = 1, ATHMHD_RS_ROE = 2 };
 /* Time integrator (Sec. 3.2.3). */
 enum { ATHMHD_RK1 = 0, ATHMHD_VL2 = 1, ATHMHD_RK2 = 2, ATHMHD_RK3 = 3 };
 

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libathmhd.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENONPHYS, EUNSUP = 0, -1, -2, -3, -4, -5
 RECON = {"dc": 0, "plm": 1, "ppm": 2}
-RIEMANN = {"hlle": 0, "hlld": 1}
+RIEMANN = {"hlle": 0, "hlld": 1, "roe": 2}
 INTEGRATOR = {"rk1": 0, "vl2": 1, "rk2": 2, "rk3": 3}
 EXPORTED = ["athmhd_version", "athmhd_create", "athmhd_create_batch", "athmhd_batch_info",
             "athmhd_batch_set_tile", "athmhd_batch_tune", "athmhd_set_graph", "athmhd_step", "athmhd_newdt",

@@ -135,7 +135,7 @@ int validate_common(const athmhd_config* c) {
   if (!c) return fail(nullptr, ATHMHD_EINVAL, "config is NULL");
   if (c->recon < ATHMHD_RECON_DC || c->recon > ATHMHD_RECON_PPM)
     return fail(nullptr, ATHMHD_EINVAL, "unknown reconstruction %d", c->recon);
-  if (c->riemann != ATHMHD_RS_HLLE && c->riemann != ATHMHD_RS_HLLD)
+  if (c->riemann != ATHMHD_RS_HLLE && c->riemann != ATHMHD_RS_HLLD && c->riemann != ATHMHD_RS_ROE)
     return fail(nullptr, ATHMHD_EINVAL, "unknown Riemann solver %d", c->riemann);
   if (c->integrator < ATHMHD_RK1 || c->integrator > ATHMHD_RK3)
     return fail(nullptr, ATHMHD_EINVAL, "unknown integrator %d", c->integrator);
@@ -582,6 +582,8 @@ int athmhd_create_batch(const athmhd_config* base, const int32_t* dims, const do
   if (rc != ATHMHD_OK) return rc;
   if (base->kernel_path != 0 || base->charac)
     return fail(nullptr, ATHMHD_EUNSUP, "batched blocks run on the fused kernel only");
+  if (base->riemann == ATHMHD_RS_ROE)
+    return fail(nullptr, ATHMHD_EUNSUP, "batched blocks take HLLE or HLLD");
   if (!dims || !dx) return fail(nullptr, ATHMHD_EINVAL, "NULL dims or dx");
   if (nblocks < 1 || nblocks > 65535) return fail(nullptr, ATHMHD_EINVAL, "nblocks must be in [1, 65535]");
   for (int b = 0; b < nblocks; ++b) {
@@ -838,6 +840,7 @@ int athmhd_step_vjp(athmhd_t h, const double* cons_n, const double* bface_n, dou
   if (h->floors.on()) return fail(h, ATHMHD_EUNSUP, "reverse mode is not available with floors");
   if (h->g.ns > 0) return fail(h, ATHMHD_EUNSUP, "reverse mode is not available with passive scalars");
   if (h->cfg.charac) return fail(h, ATHMHD_EUNSUP, "reverse mode is not available with characteristic reconstruction");
+  if (h->cfg.riemann == ATHMHD_RS_ROE) return fail(h, ATHMHD_EUNSUP, "reverse mode takes HLLE or HLLD");
   if (!g_cons_np1 || !g_bface_np1 || !g_cons_n || !g_bface_n) return fail(h, ATHMHD_EINVAL, "NULL cotangent array");
   if (g_cons_n == cons_n || g_bface_n == bface_n || g_cons_n == (const double*)bface_n ||
       g_bface_n == (const double*)cons_n)

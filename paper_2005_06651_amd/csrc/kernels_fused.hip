@@ -199,8 +199,7 @@ __device__ __forceinline__ void riemann(const double* ql, const double* qr, doub
   FaceState L = make_state(ql), R = make_state(qr);
   if (FL) nfl += floor_state(L, fl) + floor_state(R, fl);
   double smax;
-  if (RS == 1) hlld(L, R, bn, gas, F, smax);
-  else hlle(L, R, bn, gas, F, smax);
+  riemann_flux<RS>(L, R, bn, gas, F, smax);
   w = ct_weight(F.rho, 0.5 * (L.rho + R.rho), smax, ct_eps);
 }
 
@@ -660,16 +659,20 @@ __global__ void __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(2)))
 // MESH: the blocks of a coupled mesh read their (exchanged) ghost entries; MF:
 // the face mass fluxes are stored for passive scalars.  Compile-time switches,
 // so that the plain periodic-block kernels keep their code.
-template <int RECON, bool MESH, bool MF>
-hipError_t launch_rs_m(int rs, const UniformArgs& fa, hipStream_t s) {
+template <int RECON, int RS, bool MESH, bool MF>
+hipError_t launch_fl(const UniformArgs& fa, hipStream_t s) {
   const unsigned grid = (unsigned)(8 * fa.per_xcd);
   constexpr int NT = TileU::NT;
-  const bool fl = fa.sa.fl.on();
-  if (rs == 1 && fl) hipLaunchKernelGGL((k_stage_fused<RECON, 1, true, MESH, MF>), dim3(grid), dim3(NT), 0, s, fa);
-  else if (rs == 1) hipLaunchKernelGGL((k_stage_fused<RECON, 1, false, MESH, MF>), dim3(grid), dim3(NT), 0, s, fa);
-  else if (fl) hipLaunchKernelGGL((k_stage_fused<RECON, 0, true, MESH, MF>), dim3(grid), dim3(NT), 0, s, fa);
-  else hipLaunchKernelGGL((k_stage_fused<RECON, 0, false, MESH, MF>), dim3(grid), dim3(NT), 0, s, fa);
+  if (fa.sa.fl.on()) hipLaunchKernelGGL((k_stage_fused<RECON, RS, true, MESH, MF>), dim3(grid), dim3(NT), 0, s, fa);
+  else hipLaunchKernelGGL((k_stage_fused<RECON, RS, false, MESH, MF>), dim3(grid), dim3(NT), 0, s, fa);
   return hipGetLastError();
+}
+
+template <int RECON, bool MESH, bool MF>
+hipError_t launch_rs_m(int rs, const UniformArgs& fa, hipStream_t s) {
+  if (rs == 1) return launch_fl<RECON, 1, MESH, MF>(fa, s);
+  if (rs == 2) return launch_fl<RECON, 2, MESH, MF>(fa, s);
+  return launch_fl<RECON, 0, MESH, MF>(fa, s);
 }
 
 template <int RECON>

@@ -313,8 +313,7 @@ __global__ void __launch_bounds__(kThreads) k_flux(Geo g, Gas gas, double ct_eps
   }
   FaceFlux F;
   double smax;
-  if (RS == 1) hlld(L, R, bn, gas, F, smax);
-  else hlle(L, R, bn, gas, F, smax);
+  riemann_flux<RS>(L, R, bn, gas, F, smax);
   ob[fi] = F.rho;
   ob[(1 + D) * g.fvar + fi] = F.mn;
   ob[(1 + T1) * g.fvar + fi] = F.mt1;
@@ -424,6 +423,9 @@ hipError_t flux_rs(const Geo& g, const Gas& gas, int rs, double ct_eps, const Fl
                     (D == 2 ? g.n3 + 1 : g.n3 + 2);
   if (rs == 1)
     hipLaunchKernelGGL((k_flux<D, RECON, 1, CHAR>), dim3(grid_for(n), nb), dim3(kThreads), 0, s, g, gas, ct_eps, fl,
+                       w, xb, fo, bad);
+  else if (rs == 2)
+    hipLaunchKernelGGL((k_flux<D, RECON, 2, CHAR>), dim3(grid_for(n), nb), dim3(kThreads), 0, s, g, gas, ct_eps, fl,
                        w, xb, fo, bad);
   else
     hipLaunchKernelGGL((k_flux<D, RECON, 0, CHAR>), dim3(grid_for(n), nb), dim3(kThreads), 0, s, g, gas, ct_eps, fl,

@@ -277,6 +277,128 @@ __device__ __forceinline__ void hlld(const FaceState& L, const FaceState& R, dou
   }
 }
 
+// Roe's linearised solver (Sec. 3.2.2) with the Roe matrix of our own
+// derivation: s = sqrt(rho), s-weighted velocity and total enthalpy
+// H = (E + P_T) / rho, the transverse field averaged with swapped weights
+// (s_R B_L + s_L B_R) / (s_L + s_R), and X = |dB_t|^2 / (2 (s_L + s_R)^2).
+// With these every jump of U and of the flux is linear in the primitive jumps
+// dW = (d rho, du_n, du_t1, du_t2, dP, dB_t1, dB_t2), and the matrix has seven
+// waves: u, u -+ b_n (Alfven), u -+ c_f, u -+ c_s, for the sound speed
+// a^2 = (gamma-1)(H - v^2/2 - B^2/rho) - (gamma-2) X.  The flux is
+// (F_L + F_R)/2 - M D / 2, where dW is split into the waves' right
+// eigenvectors (closed form in the frame of the averaged transverse field,
+// normalised with alpha_f, alpha_s as for characteristic reconstruction),
+// D = sum |lambda_k| a_k R_k, and M maps primitive onto conserved jumps at the
+// averaged state.  The entropy wave carries dP = -X d rho.  No entropy fix.
+// smax (for the CT weight) is the larger |u_n| + c_f of the two states.
+__device__ __forceinline__ void roe(const FaceState& L, const FaceState& R, double bn, const Gas& g, FaceFlux& F,
+                                    double& smax) {
+  const double bnsq = bn * bn;
+  const double irl = frcp(L.rho), irr = frcp(R.rho);
+  const double btl = L.bt1 * L.bt1 + L.bt2 * L.bt2, btr = R.bt1 * R.bt1 + R.bt2 * R.bt2;
+  smax = fmax(fabs(L.vn) + fast_speed(irl, L.p, bnsq, btl, g.gamma), fabs(R.vn) + fast_speed(irr, R.p, bnsq, btr, g.gamma));
+
+  // physical fluxes of the two states
+  const double pml = 0.5 * (bnsq + btl), pmr = 0.5 * (bnsq + btr);
+  const double ptl = L.p + pml, ptr = R.p + pmr;
+  const double el = L.p * g.igm1 + 0.5 * L.rho * (L.vn * L.vn + L.vt1 * L.vt1 + L.vt2 * L.vt2) + pml;
+  const double er = R.p * g.igm1 + 0.5 * R.rho * (R.vn * R.vn + R.vt1 * R.vt1 + R.vt2 * R.vt2) + pmr;
+  const double mnl = L.rho * L.vn, mnr = R.rho * R.vn;
+  const double vbl = L.vn * bn + L.vt1 * L.bt1 + L.vt2 * L.bt2;
+  const double vbr = R.vn * bn + R.vt1 * R.bt1 + R.vt2 * R.bt2;
+
+  // averaged state
+  const double sl = L.rho * frsq(L.rho), sr = R.rho * frsq(R.rho);
+  const double iD = frcp(sl + sr);
+  const double wl = sl * iD, wr = sr * iD;
+  const double rho = sl * sr, irho = frcp(rho);
+  const double S = fsqrt(rho), iS = frcp(S);
+  const double u = wl * L.vn + wr * R.vn, v1 = wl * L.vt1 + wr * R.vt1, v2 = wl * L.vt2 + wr * R.vt2;
+  const double H = wl * ((el + ptl) * irl) + wr * ((er + ptr) * irr);
+  const double b1 = wr * L.bt1 + wl * R.bt1, b2 = wr * L.bt2 + wl * R.bt2;
+  const double db1 = R.bt1 - L.bt1, db2 = R.bt2 - L.bt2;
+  const double X = 0.5 * (db1 * db1 + db2 * db2) * iD * iD;
+  const double vsq = u * u + v1 * v1 + v2 * v2;
+  const double btsum = b1 * b1 + b2 * b2;
+  const double ah2 = g.gm1 * (H - 0.5 * vsq - (bnsq + btsum) * irho - X);  // a^2 - X
+  const double a2 = ah2 + X;
+  const double bx2 = bnsq * irho, bt2 = btsum * irho, b2sum = bx2 + bt2;
+  const double dab = a2 - b2sum;
+  const double disc = fsqrt(dab * dab + 4.0 * a2 * bt2);
+  const double cf2 = 0.5 * (a2 + b2sum + disc);
+  const double cs2 = a2 * bx2 * frcp(cf2);
+  const double cf = fsqrt(cf2), cs = fsqrt(cs2), ca = fabs(bn) * iS, a = fsqrt(a2);
+  // alpha_f^2 = (a^2 - c_s^2) / (c_f^2 - c_s^2), alpha_s^2 = (c_f^2 - a^2) / (c_f^2 - c_s^2),
+  // each numerator in a form without cancellation; (1, 0) when c_f = c_s
+  const bool split = disc > 0.0;
+  const double idisc = frcp(split ? disc : 1.0);
+  const double t4 = 2.0 * a2 * bt2;
+  const double cfa = dab <= 0.0 ? 0.5 * (disc - dab) : t4 * frcp(split ? disc + dab : 1.0);
+  const double acs = dab >= 0.0 ? 0.5 * (disc + dab) : t4 * frcp(split ? disc - dab : 1.0);
+  const double af = split ? fsqrt(acs * idisc) : 1.0;
+  const double as = split ? fsqrt(cfa * idisc) : 0.0;
+  // direction of the averaged transverse field ((1, 1)/sqrt2 when it vanishes)
+  const bool hasbt = btsum > 0.0;
+  const double ib = frsq(hasbt ? btsum : 2.0);
+  const double be1 = hasbt ? b1 * ib : ib, be2 = hasbt ? b2 * ib : ib;
+  const double sg = bn >= 0.0 ? 1.0 : -1.0;
+
+  // primitive jumps, transverse parts along and across the field direction
+  const double drho = R.rho - L.rho, du = R.vn - L.vn, dp = R.p - L.p;
+  const double dv1 = R.vt1 - L.vt1, dv2 = R.vt2 - L.vt2;
+  const double dvpar = be1 * dv1 + be2 * dv2, dvper = be1 * dv2 - be2 * dv1;
+  const double dbpar = be1 * db1 + be2 * db2, dbper = be1 * db2 - be2 * db1;
+
+  // wave strengths
+  const double aAp = 0.5 * (dvper - sg * dbper * iS), aAm = 0.5 * (dvper + sg * dbper * iS);
+  const double iQ = frcp(cf2 * af * af + cs2 * as * as);
+  const double dF = (af * cf * du - sg * as * cs * dvpar) * iQ;
+  const double dS = (as * cs * du + sg * af * cf * dvpar) * iQ;
+  const double P = (dp + X * drho) * frcp(rho * a2);
+  const double Qp = dbpar * frcp(S * a);
+  const double sF = af * P + as * Qp, sS = as * P - af * Qp;
+  const double aE = drho - rho * P;
+
+  // |lambda| a for every wave
+  const double wE = fabs(u) * aE;
+  const double wAp = fabs(u + ca) * aAp, wAm = fabs(u - ca) * aAm;
+  const double wFp = fabs(u + cf) * 0.5 * (sF + dF), wFm = fabs(u - cf) * 0.5 * (sF - dF);
+  const double wSp = fabs(u + cs) * 0.5 * (sS + dS), wSm = fabs(u - cs) * 0.5 * (sS - dS);
+
+  // D = sum |lambda| a R in primitive jumps
+  const double fs = wFp + wFm, fd = wFp - wFm, ss = wSp + wSm, sd = wSp - wSm;
+  const double Drho = wE + rho * (af * fs + as * ss);
+  const double Du = cf * af * fd + cs * as * sd;
+  const double Dvpar = sg * (af * cf * sd - as * cs * fd);
+  const double Dvper = wAp + wAm;
+  const double Dp = rho * ah2 * (af * fs + as * ss) - X * wE;
+  const double Dbpar = S * a * (as * fs - af * ss);
+  const double Dbper = -sg * S * (wAp - wAm);
+  const double Dv1 = be1 * Dvpar - be2 * Dvper, Dv2 = be2 * Dvpar + be1 * Dvper;
+  const double Db1 = be1 * Dbpar - be2 * Dbper, Db2 = be2 * Dbpar + be1 * Dbper;
+
+  // conserved form of D at the averaged state, and the flux
+  const double Umn = rho * Du + u * Drho;
+  const double Um1 = rho * Dv1 + v1 * Drho, Um2 = rho * Dv2 + v2 * Drho;
+  const double UE = Dp * g.igm1 + rho * (u * Du + v1 * Dv1 + v2 * Dv2) + (0.5 * vsq + X) * Drho + b1 * Db1 + b2 * Db2;
+  F.rho = 0.5 * (mnl + mnr - Drho);
+  F.mn = 0.5 * (mnl * L.vn + ptl - bnsq + mnr * R.vn + ptr - bnsq - Umn);
+  F.mt1 = 0.5 * (mnl * L.vt1 - bn * L.bt1 + mnr * R.vt1 - bn * R.bt1 - Um1);
+  F.mt2 = 0.5 * (mnl * L.vt2 - bn * L.bt2 + mnr * R.vt2 - bn * R.bt2 - Um2);
+  F.e = 0.5 * ((el + ptl) * L.vn - bn * vbl + (er + ptr) * R.vn - bn * vbr - UE);
+  F.bt1 = 0.5 * (L.bt1 * L.vn - bn * L.vt1 + R.bt1 * R.vn - bn * R.vt1 - Db1);
+  F.bt2 = 0.5 * (L.bt2 * L.vn - bn * L.vt2 + R.bt2 * R.vn - bn * R.vt2 - Db2);
+}
+
+// Riemann solver of a kernel's compile-time choice: 0 HLLE, 1 HLLD, 2 Roe.
+template <int RS>
+__device__ __forceinline__ void riemann_flux(const FaceState& L, const FaceState& R, double bn, const Gas& g,
+                                             FaceFlux& F, double& smax) {
+  if (RS == 1) hlld(L, R, bn, g, F, smax);
+  else if (RS == 2) roe(L, R, bn, g, F, smax);
+  else hlle(L, R, bn, g, F, smax);
+}
+
 // van Leer (1974) slope: harmonic mean of the one-sided differences when they
 // share a sign, else zero.
 __device__ __forceinline__ double vl_slope(double qm, double q0, double qp) {
