@@ -884,13 +884,15 @@ template <class T> struct Work {
   std::vector<T> edge;              // 3 edge arrays: corner EMFs
 };
 
+// Face fluxes, face EMFs, upwind weights, cell EMFs and corner EMFs of a
+// block whose ghosts are filled (steps 2-6 of the stage); returns the count
+// of non-physical cells.
 template <class T>
-int spatial_operator(const Cfg& cfg, const Geo& g, int recon, const T* cons, const T* bf, T* du, T* db, Work<T>& wk) {
+int compute_fluxes(const Cfg& cfg, const Geo& g, int recon, const T* cons, const T* bf, Work<T>& wk) {
   const size_t nc = g.ncell(), nf = g.nface();
   wk.w.assign(g.nv * nc, T(0.0));
   wk.bcc.assign(3 * nc, T(0.0));
   int bad = cons_to_prim(g, cfg.gamma, cons, bf, wk.w.data(), wk.bcc.data(), cfg.dfloor, cfg.pfloor);
-  const double dx[3] = {cfg.dx1, cfg.dx2, cfg.dx3};
   const int sten = recon == RECON_PPM ? 3 : (recon == RECON_PLM ? 2 : 1);
 
   // fluxes on every face that the update or the corner EMFs need:
@@ -1053,7 +1055,26 @@ int spatial_operator(const Cfg& cfg, const Geo& g, int recon, const T* cons, con
           wk.edge[(size_t)e * nf + g.f(i, j, k)] = avg + 0.25 * (db_m - db_p) + 0.25 * (da_m - da_p);
         }
   }
+  return bad;
+}
 
+// -(curl E)_d on face (i, j, k) normal to d, from the corner EMFs of wk.
+template <class T> T face_curl(const Geo& g, const double* dx, const Work<T>& wk, int d, int i, int j, int k) {
+  const size_t nf = g.nface();
+  const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  int p1[3] = {i, j, k}; p1[t1] += 1;
+  int p2[3] = {i, j, k}; p2[t2] += 1;
+  size_t f0 = g.f(i, j, k);
+  T curl = (wk.edge[(size_t)t2 * nf + g.f(p1[0], p1[1], p1[2])] - wk.edge[(size_t)t2 * nf + f0]) / dx[t1] -
+           (wk.edge[(size_t)t1 * nf + g.f(p2[0], p2[1], p2[2])] - wk.edge[(size_t)t1 * nf + f0]) / dx[t2];
+  return -curl;
+}
+
+// Flux divergence on the active cells and the CT update rate of the active
+// faces (step 7 without the 2S weights) from the fluxes and EMFs of wk.
+template <class T> void apply_operator(const Cfg& cfg, const Geo& g, const Work<T>& wk, T* du, T* db) {
+  const size_t nc = g.ncell(), nf = g.nface();
+  const double dx[3] = {cfg.dx1, cfg.dx2, cfg.dx3};
   // flux divergence on the active cells
   for (int k = g.s(2); k <= g.e(2); ++k)
     for (int j = g.s(1); j <= g.e(1); ++j)
@@ -1071,19 +1092,16 @@ int spatial_operator(const Cfg& cfg, const Geo& g, int recon, const T* cons, con
       }
   // CT: dB_d/dt = -(curl E)_d on the active faces (index [s, e] in every
   // direction; the periodic image face is set by the ghost fill)
-  for (int d = 0; d < 3; ++d) {
-    const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  for (int d = 0; d < 3; ++d)
     for (int k = g.s(2); k <= g.e(2); ++k)
       for (int j = g.s(1); j <= g.e(1); ++j)
-        for (int i = g.s(0); i <= g.e(0); ++i) {
-          int p1[3] = {i, j, k}; p1[t1] += 1;
-          int p2[3] = {i, j, k}; p2[t2] += 1;
-          size_t f0 = g.f(i, j, k);
-          T curl = (wk.edge[(size_t)t2 * nf + g.f(p1[0], p1[1], p1[2])] - wk.edge[(size_t)t2 * nf + f0]) / dx[t1] -
-                   (wk.edge[(size_t)t1 * nf + g.f(p2[0], p2[1], p2[2])] - wk.edge[(size_t)t1 * nf + f0]) / dx[t2];
-          db[(size_t)d * nf + f0] = -curl;
-        }
-  }
+        for (int i = g.s(0); i <= g.e(0); ++i) db[(size_t)d * nf + g.f(i, j, k)] = face_curl(g, dx, wk, d, i, j, k);
+}
+
+template <class T>
+int spatial_operator(const Cfg& cfg, const Geo& g, int recon, const T* cons, const T* bf, T* du, T* db, Work<T>& wk) {
+  const int bad = compute_fluxes(cfg, g, recon, cons, bf, wk);
+  apply_operator(cfg, g, wk, du, db);
   return bad;
 }
 
@@ -1589,6 +1607,308 @@ inline void prolong_box(const Geo& g, const double* cc, const double* cb, double
         }
 }
 
+
+// ---------------------------------------------------------------------------
+// Two-level composite (Sec. 2.1.3: communication between levels; Sec. 2.1.4:
+// flux and EMF correction; reading R-35).  Nine blocks of one shape (n cells
+// per direction, ng ghosts).  Block 0 is coarse (widths dx of cfg) and covers
+// [X, 2X) x [0, Y) x [0, Z) with X = n1 dx1, Y = n2 dx2, Z = n3 dx3; block
+// 1 + a + 2b + 4c (a, b, c in {0, 1}) is fine (widths dx / 2) and covers the
+// octant (a, b, c) of [0, X) x [0, Y) x [0, Z).  The domain
+// [0, 2X) x [0, Y) x [0, Z) is periodic.  n1, n2, n3 are even and at least
+// 2 ng, and ng is even.
+//
+// Faces: a block owns the lower faces of its active cells.  Both coarse-fine
+// interfaces (x1 = X and x1 = 2X = 0) are owned by the fine side: the fine
+// blocks with a = 1 also own their upper x1 faces, and the coarse block's two
+// x1 boundary faces are area averages of the fine faces there (restriction),
+// which the EMF correction keeps equal to what the coarse CT update would
+// give.
+// ---------------------------------------------------------------------------
+struct TwoLevel {
+  Cfg cc, cf;  // coarse and fine configuration (fine: dx / 2)
+  Geo g;
+  size_t ncv, nf, bs;  // cell part, face array, doubles per block
+  explicit TwoLevel(const Cfg& c) : cc(c), cf(c), g(c) {
+    cf.dx1 = 0.5 * c.dx1;
+    cf.dx2 = 0.5 * c.dx2;
+    cf.dx3 = 0.5 * c.dx3;
+    ncv = g.nv * g.ncell();
+    nf = g.nface();
+    bs = ncv + 3 * nf;
+  }
+  const Cfg& cfg(int b) const { return b == 0 ? cc : cf; }
+};
+
+inline bool two_level_ok(const Cfg& c) {
+  return c.ng % 2 == 0 && c.n1 % 2 == 0 && c.n2 % 2 == 0 && c.n3 % 2 == 0 && c.n1 >= 2 * c.ng &&
+         c.n2 >= 2 * c.ng && c.n3 >= 2 * c.ng && c.nscalars == 0;
+}
+
+// Same-level ghosts of the fine blocks: every stored cell or face of a fine
+// block that lies inside the fine region (periodic along x2 and x3) and is
+// not owned by that block is copied from the fine block that owns it.
+// Entries beyond the region along x1 are left to prolongation.
+inline void two_level_fine_exchange(const TwoLevel& L, std::vector<double*>& cons, std::vector<double*>& bf) {
+  const Geo& g = L.g;
+  const int n[3] = {g.n[0], g.n[1], g.n[2]}, ng = g.ng;
+  for (int blk = 1; blk <= 8; ++blk) {
+    const int pos[3] = {(blk - 1) & 1, ((blk - 1) >> 1) & 1, ((blk - 1) >> 2) & 1};
+    // cells
+    for (int k = 0; k < g.N[2]; ++k)
+      for (int j = 0; j < g.N[1]; ++j)
+        for (int i = 0; i < g.N[0]; ++i) {
+          const int idx[3] = {i, j, k};
+          bool act = true;
+          int src[3], sb[3];
+          bool inside = true;
+          for (int d = 0; d < 3; ++d) {
+            int gl = pos[d] * n[d] + idx[d] - ng;  // index in the fine region
+            if (idx[d] < ng || idx[d] >= ng + n[d]) act = false;
+            if (d == 0) {
+              if (gl < 0 || gl >= 2 * n[0]) inside = false;
+            } else {
+              gl = ((gl % (2 * n[d])) + 2 * n[d]) % (2 * n[d]);
+            }
+            sb[d] = gl / n[d];
+            src[d] = ng + gl - sb[d] * n[d];
+          }
+          if (act || !inside) continue;
+          const int sblk = 1 + sb[0] + 2 * sb[1] + 4 * sb[2];
+          for (int v = 0; v < g.nv; ++v)
+            cons[blk][v * g.ncell() + g.c(i, j, k)] = cons[sblk][v * g.ncell() + g.c(src[0], src[1], src[2])];
+        }
+    // faces of component d
+    for (int d = 0; d < 3; ++d)
+      for (int k = 0; k <= g.N[2]; ++k)
+        for (int j = 0; j <= g.N[1]; ++j)
+          for (int i = 0; i <= g.N[0]; ++i) {
+            const int idx[3] = {i, j, k};
+            // owned: lower faces of active cells, and for a = 1 the upper x1 faces
+            bool owned = true;
+            for (int e = 0; e < 3; ++e) {
+              const int hi = (e == 0 && d == 0 && pos[0] == 1) ? ng + n[0] : ng + n[e] - 1;
+              if (idx[e] < ng || idx[e] > hi) owned = false;
+            }
+            if (owned) continue;
+            int src[3], sb[3];
+            bool inside = true;
+            for (int e = 0; e < 3; ++e) {
+              int gl = pos[e] * n[e] + idx[e] - ng;
+              if (e == 0) {
+                // x1 faces up to the interface x1 = X (index 2 n1) are in the region
+                const int top = d == 0 ? 2 * n[0] : 2 * n[0] - 1;
+                if (gl < 0 || gl > top) inside = false;
+                sb[e] = std::min(gl / n[e], 1);
+              } else {
+                gl = ((gl % (2 * n[e])) + 2 * n[e]) % (2 * n[e]);
+                sb[e] = gl / n[e];
+              }
+              src[e] = ng + gl - sb[e] * n[e];
+            }
+            if (!inside) continue;
+            const int sblk = 1 + sb[0] + 2 * sb[1] + 4 * sb[2];
+            bf[blk][d * L.nf + g.f(i, j, k)] = bf[sblk][d * L.nf + g.f(src[0], src[1], src[2])];
+          }
+  }
+}
+
+// Ghosts of the whole composite: fine same-level exchange; the coarse block's
+// periodic images along x2 and x3, with its x1 ghost slabs and x1 boundary
+// faces restricted from the fine blocks; the fine blocks' x1 ghost slabs
+// beyond the fine region prolongated from the coarse block (keeping the fine
+// interface faces).
+inline void two_level_ghosts(const TwoLevel& L, double* cons, double* bf) {
+  const Geo& g = L.g;
+  const int n1 = g.n[0], n2 = g.n[1], n3 = g.n[2], ng = g.ng;
+  std::vector<double*> cb(9), bb(9);
+  for (int b = 0; b < 9; ++b) {
+    cb[b] = cons + b * L.ncv;
+    bb[b] = bf + b * 3 * L.nf;
+  }
+  two_level_fine_exchange(L, cb, bb);
+  fill_ghosts(g, cb[0], bb[0]);
+  // coarse x1 slabs: segments of coarse stored indices along x2 (x3) and the
+  // fine block and fine start index they restrict from
+  struct Seg { int c, h, fb, f; };
+  const Seg sj[4] = {{0, ng, 1, n2 - ng}, {ng, n2 / 2, 0, ng}, {ng + n2 / 2, n2 / 2, 1, ng}, {ng + n2, ng, 0, ng}};
+  const Seg sk[4] = {{0, ng, 1, n3 - ng}, {ng, n3 / 2, 0, ng}, {ng + n3 / 2, n3 / 2, 1, ng}, {ng + n3, ng, 0, ng}};
+  for (int side = 0; side < 2; ++side)
+    for (int a = 0; a < 4; ++a)
+      for (int c = 0; c < 4; ++c) {
+        LevelBox B;
+        B.c[0] = side == 0 ? 0 : ng + n1;
+        B.h[0] = ng;
+        B.f[0] = side == 0 ? n1 - ng : ng;
+        const int fa = side == 0 ? 1 : 0;
+        B.c[1] = sj[a].c; B.h[1] = sj[a].h; B.f[1] = sj[a].f;
+        B.c[2] = sk[c].c; B.h[2] = sk[c].h; B.f[2] = sk[c].f;
+        const int fblk = 1 + fa + 2 * sj[a].fb + 4 * sk[c].fb;
+        restrict_box(g, cb[fblk], bb[fblk], cb[0], bb[0], B);
+      }
+  // fine x1 slabs beyond the fine region, prolongated from the coarse block
+  for (int blk = 1; blk <= 8; ++blk) {
+    const int a = (blk - 1) & 1, b = ((blk - 1) >> 1) & 1, c = ((blk - 1) >> 2) & 1;
+    LevelBox B;
+    B.h[0] = ng / 2;
+    B.f[0] = a == 1 ? ng + n1 : 0;
+    B.c[0] = a == 1 ? ng : ng + n1 - ng / 2;
+    B.f[1] = 0; B.h[1] = g.N[1] / 2; B.c[1] = ng + b * n2 / 2 - ng / 2;
+    B.f[2] = 0; B.h[2] = g.N[2] / 2; B.c[2] = ng + c * n3 / 2 - ng / 2;
+    const int keep = a == 1 ? 1 : 2;  // the interface face: lower x1 side (a = 1), upper (a = 0)
+    prolong_box(g, cb[0], bb[0], cb[blk], bb[blk], B, L.cc.gamma, L.cc.pfloor, false, keep);
+  }
+}
+
+// Fine block and stored index of global fine index gl (periodic over 2 n)
+// along a direction with n cells per block.
+inline void fine_pos(int gl, int n, int ng, int& blk, int& idx) {
+  gl = ((gl % (2 * n)) + 2 * n) % (2 * n);
+  blk = gl / n;
+  idx = ng + gl - blk * n;
+}
+
+// Flux correction (the coarse fluxes through both interfaces replaced by the
+// area average of the four fine fluxes) and EMF correction (Eq. emfcorr: the
+// coarse E2, E3 on the interface planes replaced by the mean of the two fine
+// edges along them).
+inline void two_level_correct(const TwoLevel& L, std::vector<Work<double>>& wk) {
+  const Geo& g = L.g;
+  const int n1 = g.n[0], n2 = g.n[1], n3 = g.n[2], ng = g.ng;
+  const size_t nf = L.nf;
+  for (int side = 0; side < 2; ++side) {
+    const int ci = side == 0 ? ng : ng + n1;  // coarse x1 face / edge plane
+    const int fi = side == 0 ? ng + n1 : ng;  // the same plane in the fine blocks
+    const int fa = side == 0 ? 1 : 0;
+    for (int k = ng; k < ng + n3; ++k)
+      for (int j = ng; j < ng + n2; ++j)
+        for (int v = 0; v < g.nv; ++v) {
+          double sum = 0.0;
+          for (int dk = 0; dk < 2; ++dk)
+            for (int dj = 0; dj < 2; ++dj) {
+              int bj, jj, bk, kk;
+              fine_pos(2 * (j - ng) + dj, n2, ng, bj, jj);
+              fine_pos(2 * (k - ng) + dk, n3, ng, bk, kk);
+              sum += wk[1 + fa + 2 * bj + 4 * bk].flux[0][v * nf + g.f(fi, jj, kk)];
+            }
+          wk[0].flux[0][v * nf + g.f(ci, j, k)] = 0.25 * sum;
+        }
+    // E2: along x2 over coarse cell j, at the lower x3 face k (k up to ng + n3)
+    for (int k = ng; k <= ng + n3; ++k)
+      for (int j = ng; j < ng + n2; ++j) {
+        double sum = 0.0;
+        for (int dj = 0; dj < 2; ++dj) {
+          int bj, jj, bk, kk;
+          fine_pos(2 * (j - ng) + dj, n2, ng, bj, jj);
+          fine_pos(2 * (k - ng), n3, ng, bk, kk);
+          sum += wk[1 + fa + 2 * bj + 4 * bk].edge[1 * nf + g.f(fi, jj, kk)];
+        }
+        wk[0].edge[1 * nf + g.f(ci, j, k)] = 0.5 * sum;
+      }
+    // E3: along x3 over coarse cell k, at the lower x2 face j (j up to ng + n2)
+    for (int k = ng; k < ng + n3; ++k)
+      for (int j = ng; j <= ng + n2; ++j) {
+        double sum = 0.0;
+        for (int dk = 0; dk < 2; ++dk) {
+          int bj, jj, bk, kk;
+          fine_pos(2 * (j - ng), n2, ng, bj, jj);
+          fine_pos(2 * (k - ng) + dk, n3, ng, bk, kk);
+          sum += wk[1 + fa + 2 * bj + 4 * bk].edge[2 * nf + g.f(fi, jj, kk)];
+        }
+        wk[0].edge[2 * nf + g.f(ci, j, k)] = 0.5 * sum;
+      }
+  }
+}
+
+inline int two_level_step(const Cfg& cfg, double* cons, double* bf, double dt) {
+  if (!two_level_ok(cfg)) return -1;
+  TwoLevel L(cfg);
+  const Geo& g = L.g;
+  Scheme sc;
+  if (!scheme_for(cfg.integrator, sc)) return -1;
+  const size_t n = 9 * L.bs;
+  // state: block b's cells then its faces
+  std::vector<double> u(n);
+  for (int b = 0; b < 9; ++b) {
+    std::copy(cons + b * L.ncv, cons + (b + 1) * L.ncv, u.begin() + b * L.bs);
+    std::copy(bf + b * 3 * L.nf, bf + (b + 1) * 3 * L.nf, u.begin() + b * L.bs + L.ncv);
+  }
+  std::vector<unsigned char> mask(n, 0);
+  const int ng = g.ng;
+  for (int b = 0; b < 9; ++b) {
+    const size_t o = b * L.bs;
+    for (int v = 0; v < g.nv; ++v)
+      for (int k = ng; k <= g.e(2); ++k)
+        for (int j = ng; j <= g.e(1); ++j)
+          for (int i = ng; i <= g.e(0); ++i) mask[o + v * g.ncell() + g.c(i, j, k)] = 1;
+    for (int d = 0; d < 3; ++d)
+      for (int k = ng; k <= g.e(2); ++k)
+        for (int j = ng; j <= g.e(1); ++j) {
+          const int ilo = (b == 0 && d == 0) ? ng + 1 : ng;  // coarse x1 boundary faces: fine-owned
+          const int ihi = (b != 0 && d == 0 && ((b - 1) & 1) == 1) ? g.e(0) + 1 : g.e(0);
+          for (int i = ilo; i <= ihi; ++i) mask[o + L.ncv + d * L.nf + g.f(i, j, k)] = 1;
+        }
+  }
+  std::vector<Work<double>> wk(9);
+  // state in the two-array layout for the ghost fill
+  std::vector<double> sc_(9 * L.ncv), sb_(9 * 3 * L.nf);
+  auto split = [&](const double* st) {
+    for (int b = 0; b < 9; ++b) {
+      std::copy(st + b * L.bs, st + b * L.bs + L.ncv, sc_.begin() + b * L.ncv);
+      std::copy(st + b * L.bs + L.ncv, st + (b + 1) * L.bs, sb_.begin() + b * 3 * L.nf);
+    }
+  };
+  auto join = [&](double* st) {
+    for (int b = 0; b < 9; ++b) {
+      std::copy(sc_.begin() + b * L.ncv, sc_.begin() + (b + 1) * L.ncv, st + b * L.bs);
+      std::copy(sb_.begin() + b * 3 * L.nf, sb_.begin() + (b + 1) * 3 * L.nf, st + b * L.bs + L.ncv);
+    }
+  };
+  auto rhs = [&](int s, double* state, double* R) -> int {
+    split(state);
+    two_level_ghosts(L, sc_.data(), sb_.data());
+    join(state);
+    std::fill(R, R + n, 0.0);
+    const int recon = (cfg.integrator == INT_VL2 && s == 0) ? RECON_DC : cfg.recon;
+    int bad = 0;
+    for (int b = 0; b < 9; ++b)
+      bad += compute_fluxes(L.cfg(b), g, recon, state + b * L.bs, state + b * L.bs + L.ncv, wk[b]);
+    two_level_correct(L, wk);
+    for (int b = 0; b < 9; ++b) {
+      double* du = R + b * L.bs;
+      double* db = du + L.ncv;
+      apply_operator(L.cfg(b), g, wk[b], du, db);
+      if (b != 0 && ((b - 1) & 1) == 1) {  // a = 1: the interface faces x1 = X
+        const double dx[3] = {L.cf.dx1, L.cf.dx2, L.cf.dx3};
+        for (int k = ng; k <= g.e(2); ++k)
+          for (int j = ng; j <= g.e(1); ++j) db[g.f(g.e(0) + 1, j, k)] = face_curl(g, dx, wk[b], 0, g.e(0) + 1, j, k);
+      }
+    }
+    return bad;
+  };
+  const int bad = drive_2s(sc, n, u.data(), mask.data(), dt, rhs);
+  if (bad < 0) return bad;
+  split(u.data());
+  two_level_ghosts(L, sc_.data(), sb_.data());
+  std::copy(sc_.begin(), sc_.end(), cons);
+  std::copy(sb_.begin(), sb_.end(), bf);
+  return bad;
+}
+
+inline int two_level_newdt(const Cfg& cfg, const double* cons, const double* bf, double* dt_out) {
+  if (!two_level_ok(cfg)) return -1;
+  TwoLevel L(cfg);
+  double best = INFINITY;
+  int bad = 0;
+  for (int b = 0; b < 9; ++b) {
+    double dt;
+    bad += newdt(L.cfg(b), cons + b * L.ncv, bf + b * 3 * L.nf, &dt);
+    best = std::min(best, dt);
+  }
+  *dt_out = best;
+  return bad;
+}
+
 }  // namespace orc
 
 // ---------------------------------------------------------------------------
@@ -1653,6 +1973,24 @@ long long orc_take_floor_count(void) {
   const long long n = orc::g_floored;
   orc::g_floored = 0;
   return n;
+}
+
+// Two-level composite of nine blocks (block 0 coarse, 1..8 fine; see
+// TwoLevel): one step, the ghost fill, and the CFL time step.  -1 when the
+// geometry does not satisfy two_level_ok.
+int orc_two_level_step(const orc::Cfg* c, double* cons, double* bface, double dt) {
+  return orc::two_level_step(*c, cons, bface, dt);
+}
+
+int orc_two_level_fill(const orc::Cfg* c, double* cons, double* bface) {
+  if (!orc::two_level_ok(*c)) return -1;
+  orc::TwoLevel L(*c);
+  orc::two_level_ghosts(L, cons, bface);
+  return 0;
+}
+
+int orc_two_level_newdt(const orc::Cfg* c, const double* cons, const double* bface, double* dt_out) {
+  return orc::two_level_newdt(*c, cons, bface, dt_out);
 }
 
 int orc_newdt(const orc::Cfg* c, const double* cons, const double* bface, double* dt_out) {

@@ -59,6 +59,9 @@ def lib():
         _lib.orc_phys_flux.argtypes = [C.c_double, P, C.c_double, P, P]
         _lib.orc_hlld_fan.argtypes = [C.c_double, P, P, C.c_double, P, P]
         _lib.orc_roe_matrix.argtypes = [C.c_double, P, P, C.c_double, P]
+        _lib.orc_two_level_step.argtypes = [cp, P, P, C.c_double]
+        _lib.orc_two_level_fill.argtypes = [cp, P, P]
+        _lib.orc_two_level_newdt.argtypes = [cp, P, P, P]
         _lib.orc_fast_speed.argtypes = [C.c_double] * 6
         _lib.orc_fast_speed.restype = C.c_double
         _lib.orc_recon_line.argtypes = [C.c_int, C.c_int, P, P, P]
@@ -177,6 +180,23 @@ def hlld_fan(gamma: float, wl, wr, bn: float):
     if rc:
         return f, None, None
     return f, out[:6].copy(), out[6:].reshape(4, 7).copy()
+
+
+def two_level_step(cfg: Cfg, cons, bface, dt: float) -> int:
+    """One step of the two-level composite (nine blocks, in place); cfg is the
+    coarse block's configuration."""
+    assert cons.flags.c_contiguous and bface.flags.c_contiguous
+    return lib().orc_two_level_step(C.byref(cfg), _p(cons), _p(bface), float(dt))
+
+
+def two_level_fill(cfg: Cfg, cons, bface) -> int:
+    return lib().orc_two_level_fill(C.byref(cfg), _p(cons), _p(bface))
+
+
+def two_level_newdt(cfg: Cfg, cons, bface):
+    out = np.zeros(1)
+    bad = lib().orc_two_level_newdt(C.byref(cfg), _p(cons), _p(bface), _p(out))
+    return float(out[0]), bad
 
 
 def roe_matrix(gamma: float, wl, wr, bn: float):

@@ -546,6 +546,73 @@ def join_mesh(cells: np.ndarray, faces: np.ndarray, ng: int, n_block, mesh):
     return dc, df
 
 
+def analytic_state(n, ng=2, box=(2.0, 1.0, 1.0), seed=0, gamma=5.0 / 3.0, amp=0.2, vamp=0.4, bamp=0.15,
+                   B0=(0.6, 0.3, -0.2), modes=3) -> Block:
+    """Smooth periodic state on an n-cell uniform grid of the given box, from
+    seeded analytic Fourier modes, so that grids of different resolution over
+    the same box sample the same continuous fields: rho, p = 1 + amp f, v =
+    vamp g (cell-centre values), B = B0 + curl A with A a sum of modes (face
+    values from exact edge integrals).  Wave vectors are integer multiples of
+    2 pi / box along each direction."""
+    rng = np.random.default_rng(seed)
+    dx = tuple(box[d] / n[d] for d in range(3))
+    x = [_cell_centres(n[d], ng, dx[d]) for d in range(3)]
+    X1, X2, X3 = x[0][None, None, :], x[1][None, :, None], x[2][:, None, None]
+
+    def field():
+        f = 0.0
+        for _ in range(modes):
+            k = [2 * math.pi * rng.integers(-2, 3) / box[d] for d in range(3)]
+            f = f + rng.normal() * np.cos(k[0] * X1 + k[1] * X2 + k[2] * X3 + rng.uniform(0, 2 * math.pi))
+        return f
+
+    shape = (n[2] + 2 * ng, n[1] + 2 * ng, n[0] + 2 * ng)
+    prim = np.empty((5,) + shape)
+    f = field() + np.zeros(shape)
+    prim[0] = 1.0 + amp * f / max(np.abs(f).max(), 1e-300)
+    for c in range(3):
+        g = field() + np.zeros(shape)
+        prim[1 + c] = vamp * g / max(np.abs(g).max(), 1e-300)
+    f = field() + np.zeros(shape)
+    prim[4] = 1.0 + amp * f / max(np.abs(f).max(), 1e-300)
+    amodes = []
+    for _ in range(modes):
+        k = [2 * math.pi * rng.integers(-2, 3) / box[d] for d in range(3)]
+        if k[0] == k[1] == k[2] == 0.0:
+            continue
+        a = tuple(bamp * rng.normal(size=3) / math.sqrt(k[0] ** 2 + k[1] ** 2 + k[2] ** 2))
+        amodes.append((tuple(k), a, rng.uniform(0, 2 * math.pi)))
+    bf = faces_from_modes(tuple(n), ng, dx, amodes) if amodes else np.zeros((3,) + tuple(s + 1 for s in shape))
+    for c in range(3):
+        bf[c] += B0[c]
+    return Block(n=tuple(n), ng=ng, dx=dx, gamma=gamma, bface=bf, prim=prim,
+                 meta=dict(workload="analytic_state", seed=seed, box=box))
+
+
+def two_level(coarse: Block, fine: Block, n):
+    """The nine blocks of a two-level composite from two uniform periodic grids
+    of the same box: coarse with (2 n1, n2, n3) cells, fine with
+    (4 n1, 2 n2, 2 n3).  Block 0 is the coarse grid's upper half along x1;
+    block 1 + a + 2 b + 4 c is the fine grid's block (a, b, c) of n cells in
+    its lower half along x1.  Returns (cells, faces) of shape (9, nv, ...),
+    (9, 3, ...), from the grids' prim (or cons when prim is None).  Index
+    arithmetic only."""
+    ng = coarse.ng
+    cc = coarse.prim if coarse.prim is not None else coarse.cons
+    fc = fine.prim if fine.prim is not None else fine.cons
+    c_cells, c_faces = split_mesh(cc, coarse.bface, ng, n, (2, 1, 1))
+    f_cells, f_faces = split_mesh(fc, fine.bface, ng, n, (4, 2, 2))
+    cells = [c_cells[1]]
+    faces = [c_faces[1]]
+    for c in range(2):
+        for b in range(2):
+            for a in range(2):
+                q = a + 4 * (b + 2 * c)
+                cells.append(f_cells[q])
+                faces.append(f_faces[q])
+    return np.ascontiguousarray(np.stack(cells)), np.ascontiguousarray(np.stack(faces))
+
+
 def pack(arrays) -> np.ndarray:
     """Concatenate per-block arrays into the flat batched layout."""
     return np.concatenate([np.ascontiguousarray(a).reshape(-1) for a in arrays])
