@@ -149,6 +149,29 @@ ATHMHD_API int athmhd_step(athmhd_t h, double* cons, double* bface, double dt, i
 ATHMHD_API int athmhd_newdt(athmhd_t h, const double* cons, const double* bface, int nblocks, double* dt_host,
                  void* stream);
 
+/* Two-level composite (Sec. 2.1.3 communication between levels, Sec. 2.1.4
+ * flux and EMF correction, Sec. 2.1.5 restriction and prolongation): nine
+ * blocks of the shape of cfg (n1 x n2 x n3 active cells, nghost ghosts) on a
+ * periodic box [0, 2X) x [0, Y) x [0, Z), X = n1 dx1, Y = n2 dx2, Z = n3 dx3.
+ * Block 0 is coarse (widths dx of cfg) and covers [X, 2X) x [0, Y) x [0, Z);
+ * block 1 + a + 2b + 4c (a, b, c in {0, 1}) is fine (widths dx / 2) and
+ * covers the octant (a, b, c) of [0, X) x [0, Y) x [0, Z).  cons and bface
+ * hold the nine blocks one after the other in the layout above (nblocks = 9
+ * in every call).  Each stage exchanges ghosts within the fine level, fills
+ * the coarse block's x1 ghost slabs and x1 boundary faces by restriction of
+ * the fine blocks, prolongates the fine blocks' x1 ghost slabs beyond the
+ * fine region from the coarse block, computes fluxes and corner EMFs on both
+ * levels, replaces the coarse fluxes through the two interfaces by the mean
+ * of the four fine fluxes and the coarse E2, E3 on the interface planes by
+ * the mean of the two fine EMFs along them, and updates.  The interface
+ * faces belong to the fine blocks.  Unlike other handles, a step ends with
+ * this ghost fill, so the ghost entries of cons and bface are current after
+ * it.  Needs an even nghost, even n_d >= 2 nghost, cubic cells and no
+ * passive scalars; runs the unfused kernels (kernel_path is ignored).
+ * ATHMHD_EUNSUP from athmhd_step with floors, and from the reverse-mode,
+ * stage-recording, level-operator and allocation-free calls. */
+ATHMHD_API int athmhd_create_levels(const athmhd_config* cfg, athmhd_t* out);
+
 /* Most blocks one call of athmhd_newdt_noalloc accepts. */
 #define ATHMHD_NOALLOC_MAX_BLOCKS 65536
 

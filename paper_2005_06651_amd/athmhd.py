@@ -23,7 +23,7 @@ EXPORTED = ["athmhd_version", "athmhd_create", "athmhd_create_batch", "athmhd_ba
             "athmhd_prim2cons", "athmhd_fill_ghosts", "athmhd_profile", "athmhd_last_error", "athmhd_destroy",
             "athmhd_step_vjp", "athmhd_prim2cons_vjp", "athmhd_set_floors", "athmhd_floor_count",
             "athmhd_step_stages", "athmhd_create_mesh", "athmhd_restrict", "athmhd_prolong",
-            "athmhd_restrict_box", "athmhd_prolong_box", "athmhd_newdt_noalloc"]
+            "athmhd_restrict_box", "athmhd_prolong_box", "athmhd_newdt_noalloc", "athmhd_create_levels"]
 BATCH_TILES = [(16, 12), (12, 16), (14, 14), (16, 8)]  # active columns of the batch tile candidates
 
 
@@ -60,6 +60,7 @@ def lib():
         L.athmhd_version.restype = C.c_int
         L.athmhd_create.argtypes = [C.POINTER(Config), C.c_int, C.POINTER(vp)]
         L.athmhd_create_mesh.argtypes = [C.POINTER(Config), C.c_int, C.c_int, C.c_int, C.POINTER(vp)]
+        L.athmhd_create_levels.argtypes = [C.POINTER(Config), C.POINTER(vp)]
         L.athmhd_create_batch.argtypes = [C.POINTER(Config), C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int,
                                           C.POINTER(vp)]
         L.athmhd_batch_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
@@ -366,6 +367,26 @@ class MeshSolver(Solver):
         self.cfg = make_config(n, nghost, dx, gamma, recon, riemann, integrator, cfl, ct_eps, "fused", nscalars)
         h = C.c_void_p()
         rc = lib().athmhd_create_mesh(C.byref(self.cfg), self.mesh[0], self.mesh[1], self.mesh[2], C.byref(h))
+        if rc != OK:
+            raise AthmhdError(rc, lib().athmhd_last_error(None).decode(errors="replace"))
+        self._h = h
+
+
+class TwoLevelSolver(Solver):
+    """A two-level composite (see athmhd_create_levels): block 0 coarse with
+    widths dx, blocks 1 + a + 2b + 4c fine with widths dx / 2, all of n
+    cells.  Tensors hold the nine blocks: cons (9, 5, N3, N2, N1), bface
+    (9, 3, N3+1, N2+1, N1+1)."""
+
+    def __init__(self, n, nghost, dx, gamma, recon="plm", riemann="hlld", integrator="vl2", cfl=0.3, ct_eps=0.0,
+                 charac=False):
+        self.n = tuple(int(x) for x in n)
+        self.ng = int(nghost)
+        self.nblocks = 9
+        self.nv = 5
+        self.cfg = make_config(n, nghost, dx, gamma, recon, riemann, integrator, cfl, ct_eps, "unfused", 0, charac)
+        h = C.c_void_p()
+        rc = lib().athmhd_create_levels(C.byref(self.cfg), C.byref(h))
         if rc != OK:
             raise AthmhdError(rc, lib().athmhd_last_error(None).decode(errors="replace"))
         self._h = h

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libathmhd.so")
 SOURCES = ["abi.hip", "kernels_basic.hip", "kernels_unfused.hip", "kernels_fused.hip", "kernels_adjoint.hip",
-           "kernels_scalar.hip", "kernels_amr.hip"]
+           "kernels_scalar.hip", "kernels_amr.hip", "kernels_levels.hip"]
 OBJDIR = os.path.join(ROOT, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -32,6 +32,10 @@ struct athmhd_s {
   // the unfused pipeline runs the stages (kernel_path 1, or characteristic
   // reconstruction, which only that pipeline implements)
   bool unfused = false;
+  // two-level composite (athmhd_create_levels): block 0 coarse (geometry g,
+  // with mesh[0] = -1), blocks 1..8 fine (geometry gf, widths dx / 2)
+  bool levels = false;
+  Geo gf{};
   // batched handle: blocks of their own sizes, concatenated in the arrays
   bool batch = false;
   int nbatch = 0;
@@ -170,7 +174,9 @@ int validate_block(int n1, int n2, int n3, int ng, double dx1, double dx2, doubl
 int check_call(athmhd_t h, const void* a, const void* b, int nb) {
   if (!h) return ATHMHD_EINVAL;
   if (!a || !b) return fail(h, ATHMHD_EINVAL, "NULL array argument");
-  if (h->batch) {
+  if (h->levels) {
+    if (nb != 9) return fail(h, ATHMHD_EINVAL, "a two-level composite has 9 blocks (got %d)", nb);
+  } else if (h->batch) {
     if (nb != h->nbatch)
       return fail(h, ATHMHD_EINVAL, "nblocks must equal the batch size %d (got %d)", h->nbatch, nb);
   } else if (h->mesh) {
@@ -275,6 +281,82 @@ int build_items(athmhd_t h, int shape, int split) {
   return ATHMHD_OK;
 }
 
+// ---- two-level composite ----------------------------------------------------
+// Unfused scratch of the fine blocks (the coarse block's is h->scr itself).
+UnfusedScratch fine_scratch(athmhd_t h) {
+  UnfusedScratch f = h->scr;
+  f.w += 8 * h->g.cvar;
+  for (int d = 0; d < 3; ++d) f.face[d] += 8 * h->g.fvar;
+  f.edge += 3 * h->g.fvar;
+  return f;
+}
+
+// Ghosts of the composite (Sec. 2.1.3): the fine blocks' same-level exchange
+// (a 2 x 2 x 2 mesh, open along x1); the coarse block's periodic images, then
+// its x1 ghost slabs and x1 boundary faces restricted from the fine blocks
+// (Sec. 2.1.5), in boxes split where the fine block or the periodic image
+// changes; the fine blocks' x1 ghost slabs beyond the fine region
+// prolongated from the coarse block, keeping the fine interface faces.
+hipError_t levels_ghosts(athmhd_t h, double* cons, double* bface, hipStream_t s) {
+  const Geo& g = h->g;
+  const int n1 = g.n1, n2 = g.n2, n3 = g.n3, ng = g.ng;
+  double* fc = cons + g.cblock;
+  double* fb = bface + g.fblock;
+  Geo gm = h->gf;
+  gm.mesh[0] = gm.mesh[1] = gm.mesh[2] = 2;
+  hipError_t e = launch_mesh_ghosts(gm, 0, fc, fb, s, true);
+  if (e == hipSuccess) e = launch_fill_ghosts(g, cons, bface, 1, s);
+  // (first coarse stored index, extent, fine block along the direction, first fine stored index)
+  struct Seg {
+    int c, h, fb, f;
+  };
+  const Seg sj[4] = {{0, ng, 1, n2 - ng}, {ng, n2 / 2, 0, ng}, {ng + n2 / 2, n2 / 2, 1, ng}, {ng + n2, ng, 0, ng}};
+  const Seg sk[4] = {{0, ng, 1, n3 - ng}, {ng, n3 / 2, 0, ng}, {ng + n3 / 2, n3 / 2, 1, ng}, {ng + n3, ng, 0, ng}};
+  for (int side = 0; side < 2 && e == hipSuccess; ++side)
+    for (int a = 0; a < 4 && e == hipSuccess; ++a)
+      for (int c = 0; c < 4 && e == hipSuccess; ++c) {
+        const int fa = side == 0 ? 1 : 0;
+        const int flo[3] = {side == 0 ? n1 - ng : ng, sj[a].f, sk[c].f};
+        const int clo[3] = {side == 0 ? 0 : ng + n1, sj[a].c, sk[c].c};
+        const int ext[3] = {ng, sj[a].h, sk[c].h};
+        const int q = fa + 2 * sj[a].fb + 4 * sk[c].fb;
+        e = launch_restrict(g, flo, clo, ext, fc + q * g.cblock, fb + q * g.fblock, cons, bface, s);
+      }
+  for (int q = 0; q < 8 && e == hipSuccess; ++q) {
+    const int a = q & 1, b = (q >> 1) & 1, c = q >> 2;
+    const int flo[3] = {a == 1 ? ng + n1 : 0, 0, 0};
+    const int clo[3] = {a == 1 ? ng : ng + n1 - ng / 2, ng + b * n2 / 2 - ng / 2, ng + c * n3 / 2 - ng / 2};
+    const int ext[3] = {ng / 2, g.N2 / 2, g.N3 / 2};
+    e = launch_prolong(g, flo, clo, ext, cons, bface, fc + q * g.cblock, fb + q * g.fblock, false, a == 1 ? 1 : 2,
+                       h->cfg.gamma, h->floors.p, h->d_bad, s);
+  }
+  return e;
+}
+
+// One stage of the composite: fluxes and EMFs of both levels, flux and EMF
+// correction (Sec. 2.1.4), the updates, and the fine-owned interface faces.
+hipError_t levels_stage(athmhd_t h, int recon, const double* xc, const double* xb, const double* unc,
+                        const double* unb, double* oc, double* ob, StageCoef cf, double beta, const double* dt_dev,
+                        hipStream_t s) {
+  const Geo& g = h->g;
+  UnfusedScratch fs = fine_scratch(h);
+  const bool ch = h->cfg.charac != 0;
+  hipError_t e = launch_fluxes_unfused(g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc, xb, 1, h->scr,
+                                       h->floors, h->d_bad, ch, s);
+  if (e == hipSuccess)
+    e = launch_fluxes_unfused(h->gf, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc + g.cblock, xb + g.fblock,
+                              8, fs, h->floors, h->d_bad, ch, s);
+  if (e == hipSuccess) e = launch_level_correct(g, h->scr, fs, s);
+  // the coarse x1 boundary faces are the fine blocks' (restricted at each fill)
+  if (e == hipSuccess) e = launch_update_unfused(g, xc, xb, unc, unb, oc, ob, cf, dt_dev, beta, 1, h->scr, s, true);
+  if (e == hipSuccess)
+    e = launch_update_unfused(h->gf, xc + g.cblock, xb + g.fblock, unc + g.cblock, unb + g.fblock, oc + g.cblock,
+                              ob + g.fblock, cf, dt_dev, beta, 8, fs, s);
+  if (e == hipSuccess)
+    e = launch_level_fine_faces(h->gf, xb + g.fblock, unb + g.fblock, ob + g.fblock, cf, dt_dev, beta, fs, s);
+  return e;
+}
+
 // x3 planes per workgroup of the fused stage kernel on nblocks uniform blocks
 int stage_kz(athmhd_t h, int nblocks) { return h->kz > 0 ? h->kz : fused_default_kz(h->g, nblocks, h->cus); }
 
@@ -282,6 +364,7 @@ int stage_kz(athmhd_t h, int nblocks) { return h->kz > 0 ? h->kz : fused_default
 hipError_t launch_stage(athmhd_t h, int recon, const double* xc, const double* xb, const double* unc,
                         const double* unb, double* oc, double* ob, StageCoef cf, double beta, const double* dt_dev,
                         int nblocks, hipStream_t s) {
+  if (h->levels) return levels_stage(h, recon, xc, xb, unc, unb, oc, ob, cf, beta, dt_dev, s);
   if (h->batch)
     return launch_stage_batch(h->shape, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, h->d_desc, h->d_items,
                               h->nitems, h->d_queue, xc, xb, unc, unb, oc, ob, cf, dt_dev, beta, h->grid, h->floors,
@@ -296,6 +379,7 @@ hipError_t launch_stage(athmhd_t h, int recon, const double* xc, const double* x
 
 // depth: ghost layers a mesh exchange fills (0: all); other handles fill all
 hipError_t fill_ghosts(athmhd_t h, double* cons, double* bface, int nblocks, hipStream_t s, int depth = 0) {
+  if (h->levels) return levels_ghosts(h, cons, bface, s);
   if (h->batch) return launch_fill_ghosts_batch(h->d_desc, h->nbatch, h->max_shell, cons, bface, s);
   if (h->mesh) return launch_mesh_ghosts(h->g, depth, cons, bface, s);
   return launch_fill_ghosts(h->g, cons, bface, nblocks, s);
@@ -377,6 +461,9 @@ int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const doubl
     if ((e = launch_copy(cons, xc, ncell, s)) != hipSuccess) return hip_fail(h, e, "copy launch");
     if ((e = launch_copy(bface, xb, nface, s)) != hipSuccess) return hip_fail(h, e, "copy launch");
   }
+  // a composite leaves its ghosts and restricted coarse faces filled, which
+  // its newdt reads
+  if (h->levels && (e = levels_ghosts(h, cons, bface, s)) != hipSuccess) return hip_fail(h, e, "level ghost launch");
   return ATHMHD_OK;
 }
 
@@ -494,7 +581,7 @@ int noalloc_scratch(athmhd_t h, int dev, DtPart** out) {
 
 extern "C" {
 
-int athmhd_version(void) { return 109; }
+int athmhd_version(void) { return 110; }
 
 int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
   if (!out) return fail(nullptr, ATHMHD_EINVAL, "out is NULL");
@@ -571,6 +658,33 @@ int athmhd_create_mesh(const athmhd_config* cfg, int nbx, int nby, int nbz, athm
   h->g.mesh[0] = nbx;
   h->g.mesh[1] = nby;
   h->g.mesh[2] = nbz;
+  return ATHMHD_OK;
+}
+
+int athmhd_create_levels(const athmhd_config* cfg, athmhd_t* out) {
+  if (!out) return fail(nullptr, ATHMHD_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate_common(cfg);
+  if (rc != ATHMHD_OK) return rc;
+  if (cfg->nscalars != 0) return fail(nullptr, ATHMHD_EUNSUP, "a two-level composite carries no passive scalars");
+  if (cfg->nghost % 2 != 0)
+    return fail(nullptr, ATHMHD_EINVAL, "a two-level composite needs an even nghost (got %d)", cfg->nghost);
+  const int n[3] = {cfg->n1, cfg->n2, cfg->n3};
+  for (int d = 0; d < 3; ++d)
+    if (n[d] % 2 != 0 || n[d] < 2 * cfg->nghost)
+      return fail(nullptr, ATHMHD_EINVAL, "block sizes must be even and >= 2 nghost (got %d x %d x %d, nghost %d)",
+                  cfg->n1, cfg->n2, cfg->n3, cfg->nghost);
+  const double lo = std::min(cfg->dx1, std::min(cfg->dx2, cfg->dx3)), hi = std::max(cfg->dx1, std::max(cfg->dx2, cfg->dx3));
+  if (!(hi - lo <= 1e-12 * hi)) return fail(nullptr, ATHMHD_EUNSUP, "face prolongation needs cubic cells (dx1 = dx2 = dx3)");
+  athmhd_config c = *cfg;
+  c.kernel_path = 1;  // the levels are coupled between flux computation and update
+  rc = athmhd_create(&c, 9, out);
+  if (rc != ATHMHD_OK) return rc;
+  athmhd_t h = *out;
+  h->levels = true;
+  h->g.mesh[0] = -1;  // the stored upper faces are current after a step
+  h->gf = make_geo(cfg->n1, cfg->n2, cfg->n3, cfg->nghost, 0.5 * cfg->dx1, 0.5 * cfg->dx2, 0.5 * cfg->dx3);
+  h->gf.mesh[0] = -1;
   return ATHMHD_OK;
 }
 
@@ -820,6 +934,7 @@ int athmhd_prim2cons(athmhd_t h, const double* prim, const double* bface, double
 int athmhd_step(athmhd_t h, double* cons, double* bface, double dt, int nblocks, void* stream) {
   int rc = check_call(h, cons, bface, nblocks);
   if (rc) return rc;
+  if (h->levels && h->floors.on()) return fail(h, ATHMHD_EUNSUP, "a two-level composite runs without floors");
   if (!(std::isfinite(dt) && dt > 0.0)) return fail(h, ATHMHD_EINVAL, "dt must be finite and > 0 (got %g)", dt);
   hipStream_t s = (hipStream_t)stream;
   if (!h->use_graph || h->profiling) return enqueue_step(h, cons, bface, dt, nullptr, nblocks, s);
@@ -836,7 +951,8 @@ int athmhd_step_vjp(athmhd_t h, const double* cons_n, const double* bface_n, dou
                     int nblocks, void* stream) {
   int rc = check_call(h, cons_n, bface_n, nblocks);
   if (rc) return rc;
-  if (h->batch || h->mesh) return fail(h, ATHMHD_EUNSUP, "reverse mode is available for uniform handles only");
+  if (h->batch || h->mesh || h->levels)
+    return fail(h, ATHMHD_EUNSUP, "reverse mode is available for uniform handles only");
   if (h->floors.on()) return fail(h, ATHMHD_EUNSUP, "reverse mode is not available with floors");
   if (h->g.ns > 0) return fail(h, ATHMHD_EUNSUP, "reverse mode is not available with passive scalars");
   if (h->cfg.charac) return fail(h, ATHMHD_EUNSUP, "reverse mode is not available with characteristic reconstruction");
@@ -901,7 +1017,7 @@ namespace {
 // arrays, and (prolongation) cubic cells.
 int check_level_arrays(athmhd_t h, const void* a, const void* b, const void* c, const void* d, bool cubic) {
   if (!h) return ATHMHD_EINVAL;
-  if (h->batch || h->mesh) return fail(h, ATHMHD_EUNSUP, "level operators act on athmhd_create handles");
+  if (h->batch || h->mesh || h->levels) return fail(h, ATHMHD_EUNSUP, "level operators act on athmhd_create handles");
   if (!a || !b || !c || !d) return fail(h, ATHMHD_EINVAL, "NULL array argument");
   const void* p[4] = {a, b, c, d};
   for (int i = 0; i < 4; ++i)
@@ -1016,7 +1132,8 @@ int athmhd_prim2cons_vjp(athmhd_t h, const double* prim, const double* bface, co
                          double* g_bface, int nblocks, void* stream) {
   int rc = check_call(h, prim, bface, nblocks);
   if (rc) return rc;
-  if (h->batch || h->mesh) return fail(h, ATHMHD_EUNSUP, "reverse mode is available for uniform handles only");
+  if (h->batch || h->mesh || h->levels)
+    return fail(h, ATHMHD_EUNSUP, "reverse mode is available for uniform handles only");
   if (h->g.ns > 0) return fail(h, ATHMHD_EUNSUP, "reverse mode is not available with passive scalars");
   if (!g_cons || !g_prim || !g_bface) return fail(h, ATHMHD_EINVAL, "NULL cotangent array");
   if (g_prim == g_cons || g_prim == prim) return fail(h, ATHMHD_EINVAL, "g_prim must not alias g_cons or prim");
@@ -1029,7 +1146,8 @@ int athmhd_step_stages(athmhd_t h, double* cons, double* bface, double dt, doubl
                        void* stream) {
   int rc = check_call(h, cons, bface, nblocks);
   if (rc) return rc;
-  if (h->batch || h->mesh) return fail(h, ATHMHD_EUNSUP, "stage recording is available for uniform handles only");
+  if (h->batch || h->mesh || h->levels)
+    return fail(h, ATHMHD_EUNSUP, "stage recording is available for uniform handles only");
   if (!stages) return fail(h, ATHMHD_EINVAL, "NULL stages");
   if (!(std::isfinite(dt) && dt > 0.0)) return fail(h, ATHMHD_EINVAL, "dt must be finite and > 0 (got %g)", dt);
   return enqueue_step(h, cons, bface, dt, nullptr, nblocks, (hipStream_t)stream, stages);
@@ -1046,9 +1164,16 @@ int athmhd_newdt(athmhd_t h, const double* cons, const double* bface, int nblock
   hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, h->d_dtmin, inf_bits, h->d_bad, 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(h, e, "newdt init launch");
-  e = h->batch ? launch_newdt_batch(h->d_desc, h->nbatch, 0, h->cfg.gamma, cons, bface, h->d_dtmin, h->floors,
-                                    h->d_bad, s)
-               : launch_newdt(h->g, h->cfg.gamma, cons, bface, nblocks, h->d_dtmin, h->floors, h->d_bad, s);
+  if (h->levels) {
+    e = launch_newdt(h->g, h->cfg.gamma, cons, bface, 1, h->d_dtmin, h->floors, h->d_bad, s);
+    if (e == hipSuccess)
+      e = launch_newdt(h->gf, h->cfg.gamma, cons + h->g.cblock, bface + h->g.fblock, 8, h->d_dtmin, h->floors,
+                       h->d_bad, s);
+  } else {
+    e = h->batch ? launch_newdt_batch(h->d_desc, h->nbatch, 0, h->cfg.gamma, cons, bface, h->d_dtmin, h->floors,
+                                      h->d_bad, s)
+                 : launch_newdt(h->g, h->cfg.gamma, cons, bface, nblocks, h->d_dtmin, h->floors, h->d_bad, s);
+  }
   if (e != hipSuccess) return hip_fail(h, e, "newdt launch");
   char* hp = (char*)h->h_pinned;
   if ((e = hipMemcpyAsync(hp, h->d_dtmin, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
@@ -1075,6 +1200,7 @@ int athmhd_newdt_noalloc(athmhd_t h, const double* cons, const double* bface, in
   int rc = check_call(h, cons, bface, nblocks);
   if (rc) return rc;
   if (!dt_dev || !nbad_dev) return fail(h, ATHMHD_EINVAL, "NULL dt_dev or nbad_dev");
+  if (h->levels) return fail(h, ATHMHD_EUNSUP, "athmhd_newdt_noalloc takes uniform, mesh and batched handles");
   if (nblocks > ATHMHD_NOALLOC_MAX_BLOCKS)
     return fail(h, ATHMHD_EINVAL, "athmhd_newdt_noalloc takes at most %d blocks per call (got %d)",
                 ATHMHD_NOALLOC_MAX_BLOCKS, nblocks);

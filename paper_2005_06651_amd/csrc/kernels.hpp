@@ -22,7 +22,10 @@ struct UnfusedScratch {
 hipError_t launch_fill_ghosts(const Geo& g, double* cons, double* bface, int nb, hipStream_t s);
 // ghost exchange of the coupled mesh g.mesh[0] x g.mesh[1] x g.mesh[2]: the w
 // ghost layers nearest each block's active box (w outside [1, ng]: all ng)
-hipError_t launch_mesh_ghosts(const Geo& g, int w, double* cons, double* bface, hipStream_t s);
+hipError_t launch_mesh_ghosts(const Geo& g, int w, double* cons, double* bface, hipStream_t s, bool open_x1 = false);
+// (open_x1: the mesh is not periodic along x1; entries whose owner along x1
+// lies beyond the mesh are left as they are, except the B1 faces on the
+// mesh's upper x1 boundary plane, owned by the last blocks along x1)
 // Level operators of block refinement on a box: fine cells [flo, flo + 2 ext)
 // <-> coarse cells [clo, clo + ext) (stored indices, checked by the caller).
 hipError_t launch_restrict(const Geo& g, const int flo[3], const int clo[3], const int ext[3], const double* fc,
@@ -68,6 +71,28 @@ hipError_t launch_stage_unfused(const Geo& g, double gamma, int recon, int rs, d
                                 double* outb, StageCoef coef, const double* dt_dev, double beta, int nb,
                                 UnfusedScratch& scr, const Floors& fl, int* bad,
                                 bool charac, hipStream_t s);  // charac: PLM on characteristic variables
+
+// The two halves of launch_stage_unfused: primitives, face fluxes and corner
+// EMFs into scr; then the 2S update from them (between the two, a caller may
+// correct the fluxes and EMFs in scr).
+hipError_t launch_fluxes_unfused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
+                                 const double* xb, int nb, UnfusedScratch& scr, const Floors& fl, int* bad,
+                                 bool charac, hipStream_t s);
+hipError_t launch_update_unfused(const Geo& g, const double* xc, const double* xb, const double* unc,
+                                 const double* unb, double* outc, double* outb, StageCoef coef, const double* dt_dev,
+                                 double beta, int nb, const UnfusedScratch& scr, hipStream_t s,
+                                 bool keep_x1_lower = false);
+
+// Two-level composite (block 0 coarse, blocks 1..8 fine; the unfused scratch
+// of the coarse block and of the first fine block): flux correction of the
+// coarse x1 boundary faces from the mean of the four fine fluxes, and EMF
+// correction of the coarse E2, E3 on the two interface planes from the mean
+// of the two fine EMFs along them.  gc: the coarse geometry (n, ng).
+hipError_t launch_level_correct(const Geo& gc, UnfusedScratch& coarse, const UnfusedScratch& fine, hipStream_t s);
+// The x1 faces on the interface x1 = X, owned by the fine blocks with a = 1:
+// out = g0 x + g1 un + bdt (-curl E) from the fine blocks' corner EMFs.
+hipError_t launch_level_fine_faces(const Geo& gf, const double* xb, const double* unb, double* outb, StageCoef coef,
+                                   const double* dt_dev, double beta, const UnfusedScratch& fine, hipStream_t s);
 
 // One stage in a single fused kernel (same contract as launch_stage_unfused);
 // kz = x3 planes per workgroup segment (0: default for the block size).

@@ -74,8 +74,8 @@ __global__ void __launch_bounds__(kThreads) k_fill_ghosts(Geo g, double* __restr
 // integer division.  Only the w ghost layers nearest the active box (and the
 // faces bounding them) are filled: a stage whose stencil reaches w cells past
 // the block needs no more.
-__global__ void __launch_bounds__(kThreads) k_mesh_ghosts(Geo g, int w, int near, double* __restrict__ cons,
-                                                         double* __restrict__ bface) {
+__global__ void __launch_bounds__(kThreads) k_mesh_ghosts(Geo g, int w, int near, int open_x1,
+                                                         double* __restrict__ cons, double* __restrict__ bface) {
   const int t = blockIdx.x * kThreads + threadIdx.x;
   // the filled box: stored indices [ng - w, ng + n + w] (faces), cells below ng + n + w
   const int E1 = g.n1 + 2 * w + 1, E2 = g.n2 + 2 * w + 1, E3 = g.n3 + 2 * w + 1;
@@ -109,18 +109,36 @@ __global__ void __launch_bounds__(kThreads) k_mesh_ghosts(Geo g, int w, int near
   const int bc[3] = {b % m[0], (b / m[0]) % m[1], b / (m[0] * m[1])};
   const int n[3] = {g.n1, g.n2, g.n3};
   int sx[3], sb[3];
+  // open_x1: entries beyond the mesh along x1 belong to another level and are
+  // left alone, except the B1 faces on the mesh's upper x1 boundary plane,
+  // which the last blocks along x1 own (copied here from the owner along x2, x3)
+  bool plane = false;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int o = x[d] - g.ng;  // position relative to the block's first active cell
     if (near) {
       const int q = o < 0 ? -1 : (o >= n[d] ? 1 : 0);
       int c = bc[d] + q;
+      if (d == 0 && open_x1 && (c < 0 || c >= m[0])) {
+        if (c < 0 || o != n[0]) return;
+        plane = true;
+        sb[0] = bc[0];
+        sx[0] = x[0];
+        continue;
+      }
       c = c < 0 ? c + m[d] : (c >= m[d] ? c - m[d] : c);
       sb[d] = c;
       sx[d] = g.ng + o - q * n[d];
     } else {
       const int len = m[d] * n[d];  // domain cells along d
       int p = bc[d] * n[d] + o;
+      if (d == 0 && open_x1 && (p < 0 || p >= len)) {
+        if (p != len) return;
+        plane = true;
+        sb[0] = bc[0];
+        sx[0] = x[0];
+        continue;
+      }
       p = ((p % len) + len) % len;
       sb[d] = p / n[d];
       sx[d] = g.ng + p % n[d];
@@ -131,6 +149,10 @@ __global__ void __launch_bounds__(kThreads) k_mesh_ghosts(Geo g, int w, int near
   const double* sf = bface + (int64_t)src * g.fblock;
   double* dc = cons + (int64_t)b * g.cblock;
   double* df = bface + (int64_t)b * g.fblock;
+  if (plane) {  // the block's own plane faces (src == b) are active
+    if (src != b) df[g.f(x[0], x[1], x[2])] = sf[g.f(sx[0], sx[1], sx[2])];
+    return;
+  }
   const int hi = g.ng + w;  // cells stop w layers past the active box, faces one entry further
   if (x[0] < g.n1 + hi && x[1] < g.n2 + hi && x[2] < g.n3 + hi) {
     const int d = g.c(x[0], x[1], x[2]), s = g.c(sx[0], sx[1], sx[2]);
@@ -154,10 +176,18 @@ inline int64_t ghost_count(const Geo& g) {
 // itself when it is its own periodic neighbour) and is read there, not from
 // the stored image entries, which a step does not refresh.  fb: this block's
 // face arrays; all_fb: block 0's (read by coupled meshes only; other callers
-// pass fb).
+// pass fb).  Geometries with mesh[0] < 0 (the blocks of a two-level
+// composite, whose ghosts are filled after every step) read the stored upper
+// faces.
 __device__ __forceinline__ void cell_field(const Geo& g, const double* fb, const double* all_fb, int b, int i, int j,
                                            int k, double& b1, double& b2, double& b3) {
   const int f = g.f(i, j, k);
+  if (g.mesh[0] < 0) {  // blocks whose upper boundary faces are stored (filled ghosts)
+    b1 = 0.5 * (fb[f] + fb[g.f(i + 1, j, k)]);
+    b2 = 0.5 * (fb[g.fvar + f] + fb[g.fvar + g.f(i, j + 1, k)]);
+    b3 = 0.5 * (fb[2 * g.fvar + f] + fb[2 * g.fvar + g.f(i, j, k + 1)]);
+    return;
+  }
   const double* p1 = fb;
   const double* p2 = fb;
   const double* p3 = fb;
@@ -568,7 +598,7 @@ hipError_t launch_fill_ghosts(const Geo& g, double* cons, double* bface, int nb,
   return hipGetLastError();
 }
 
-hipError_t launch_mesh_ghosts(const Geo& g, int w, double* cons, double* bface, hipStream_t s) {
+hipError_t launch_mesh_ghosts(const Geo& g, int w, double* cons, double* bface, hipStream_t s, bool open_x1) {
   if (w < 1 || w > g.ng) w = g.ng;
   const int nb = g.mesh[0] * g.mesh[1] * g.mesh[2];
   // the owner of a ghost entry is at most one block away when every block has
@@ -576,7 +606,8 @@ hipError_t launch_mesh_ghosts(const Geo& g, int w, double* cons, double* bface, 
   const int near = g.n1 > w && g.n2 > w && g.n3 > w;
   const int64_t E1 = g.n1 + 2 * w + 1, E2 = g.n2 + 2 * w + 1, E3 = g.n3 + 2 * w + 1;
   const int64_t count = (E3 - g.n3) * E2 * E1 + (int64_t)g.n3 * (E2 - g.n2) * E1 + (int64_t)g.n3 * g.n2 * (E1 - g.n1);
-  hipLaunchKernelGGL(k_mesh_ghosts, dim3(grid_for(count), nb), dim3(kThreads), 0, s, g, w, near, cons, bface);
+  hipLaunchKernelGGL(k_mesh_ghosts, dim3(grid_for(count), nb), dim3(kThreads), 0, s, g, w, near, open_x1 ? 1 : 0,
+                     cons, bface);
   return hipGetLastError();
 }
 

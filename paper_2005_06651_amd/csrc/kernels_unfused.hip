@@ -368,8 +368,10 @@ __global__ void __launch_bounds__(kThreads) k_corner(Geo g, const double* __rest
 
 // out = g0 x + g1 un + bdt L(x) on the active cells and their lower faces;
 // bdt = beta * (*dt_dev) when dt_dev is not NULL (a step replayed from a
-// graph reads its dt on the device), else cf.bdt.
-__global__ void __launch_bounds__(kThreads) k_update(Geo g, StageCoef cf, const double* dt_dev, double beta,
+// graph reads its dt on the device), else cf.bdt.  b1_lo: the first x1 index
+// whose B1 face is written (ng, or ng + 1 for a block whose lower x1 boundary
+// faces another block owns).
+__global__ void __launch_bounds__(kThreads) k_update(Geo g, StageCoef cf, const double* dt_dev, double beta, int b1_lo,
                                                     const double* __restrict__ xc,
                                                     const double* __restrict__ xb, const double* unc,
                                                     const double* unb, const double* __restrict__ f0,
@@ -411,7 +413,7 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, StageCoef cf, const 
   const double c2 = (E1[fc + s3] - E1[fc]) * i3 - (E3[fc + 1] - E3[fc]) * i1;
   // dB3 = -[(E2(i+1) - E2(i))/dx1 - (E1(j+1) - E1(j))/dx2]
   const double c3 = (E2[fc + 1] - E2[fc]) * i1 - (E1[fc + s2] - E1[fc]) * i2;
-  ob[fc] = cf.g0 * xbb[fc] + cf.g1 * unbb[fc] - bdt * c1;
+  if (i >= b1_lo) ob[fc] = cf.g0 * xbb[fc] + cf.g1 * unbb[fc] - bdt * c1;
   ob[g.fvar + fc] = cf.g0 * xbb[g.fvar + fc] + cf.g1 * unbb[g.fvar + fc] - bdt * c2;
   ob[2 * g.fvar + fc] = cf.g0 * xbb[2 * g.fvar + fc] + cf.g1 * unbb[2 * g.fvar + fc] - bdt * c3;
 }
@@ -445,10 +447,9 @@ hipError_t flux_dir(const Geo& g, const Gas& gas, int recon, bool charac, int rs
 
 }  // namespace
 
-hipError_t launch_stage_unfused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
-                                const double* xb, const double* unc, const double* unb, double* outc,
-                                double* outb, StageCoef coef, const double* dt_dev, double beta, int nb,
-                                UnfusedScratch& scr, const Floors& fl, int* bad, bool charac, hipStream_t s) {
+hipError_t launch_fluxes_unfused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
+                                 const double* xb, int nb, UnfusedScratch& scr, const Floors& fl, int* bad,
+                                 bool charac, hipStream_t s) {
   Gas gas{gamma, gamma - 1.0, 1.0 / (gamma - 1.0)};
   hipLaunchKernelGGL(k_prim, dim3(grid_for(g.cvar), nb), dim3(kThreads), 0, s, g, gamma, fl, xc, xb, scr.w, bad);
   hipError_t e = hipGetLastError();
@@ -462,11 +463,26 @@ hipError_t launch_stage_unfused(const Geo& g, double gamma, int recon, int rs, d
   const int64_t ne = (int64_t)(g.n1 + 1) * (g.n2 + 1) * (g.n3 + 1);
   hipLaunchKernelGGL(k_corner, dim3(grid_for(ne), nb), dim3(kThreads), 0, s, g, scr.w, scr.face[0], scr.face[1],
                      scr.face[2], scr.edge);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int64_t na = (int64_t)g.n1 * g.n2 * g.n3;
-  hipLaunchKernelGGL(k_update, dim3(grid_for(na), nb), dim3(kThreads), 0, s, g, coef, dt_dev, beta, xc, xb, unc, unb,
-                     scr.face[0], scr.face[1], scr.face[2], scr.edge, outc, outb);
   return hipGetLastError();
+}
+
+hipError_t launch_update_unfused(const Geo& g, const double* xc, const double* xb, const double* unc,
+                                 const double* unb, double* outc, double* outb, StageCoef coef, const double* dt_dev,
+                                 double beta, int nb, const UnfusedScratch& scr, hipStream_t s, bool keep_x1_lower) {
+  const int64_t na = (int64_t)g.n1 * g.n2 * g.n3;
+  const int b1_lo = keep_x1_lower ? g.ng + 1 : g.ng;
+  hipLaunchKernelGGL(k_update, dim3(grid_for(na), nb), dim3(kThreads), 0, s, g, coef, dt_dev, beta, b1_lo, xc, xb,
+                     unc, unb, scr.face[0], scr.face[1], scr.face[2], scr.edge, outc, outb);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_unfused(const Geo& g, double gamma, int recon, int rs, double ct_eps, const double* xc,
+                                const double* xb, const double* unc, const double* unb, double* outc,
+                                double* outb, StageCoef coef, const double* dt_dev, double beta, int nb,
+                                UnfusedScratch& scr, const Floors& fl, int* bad, bool charac, hipStream_t s) {
+  hipError_t e = launch_fluxes_unfused(g, gamma, recon, rs, ct_eps, xc, xb, nb, scr, fl, bad, charac, s);
+  if (e != hipSuccess) return e;
+  return launch_update_unfused(g, xc, xb, unc, unb, outc, outb, coef, dt_dev, beta, nb, scr, s);
 }
 
 }  // namespace athmhd

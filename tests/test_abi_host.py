@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version():
-    assert athmhd.lib().athmhd_version() == 109
+    assert athmhd.lib().athmhd_version() == 110
 
 
 def _create(**over):
