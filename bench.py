@@ -5,11 +5,12 @@ MI355X, in zone-cycles per second.
 Workload: decaying MHD turbulence on a 256^3 periodic block (nghost 2,
 gamma 5/3, rho = 1, p = 1, solenoidal velocity on 1 <= |k| <= 4 at rms Mach 1,
 B = 0.5 x + curl A with rms(curl A) = 0.1), CFL 0.3.  One timed step is the
-whole hot path: the CFL time step (athmhd_newdt) followed by one full VL2 step
-(two fused stages of cons->prim, reconstruction, HLLD fluxes, CT corner EMFs
-and the conservative + face-field update; periodic images are read in place,
-so no ghost-fill pass is needed).  Inputs are resident in HBM before the
-timed region.
+whole hot path (athmhd_step_chain): one full VL2 step (two fused stages of
+cons->prim, reconstruction, HLLD fluxes, CT corner EMFs and the conservative
++ face-field update; periodic images are read in place, so no ghost-fill pass
+is needed) with dt read on the device, then the CFL reduction of the new
+state, which leaves the next step's dt on the device.  Inputs are resident in
+HBM before the timed region.
 
 Prints one JSON line.  Only one GPU is supported: --gpus N with N > 1 exits.
 """
@@ -192,7 +193,8 @@ def cpu_baseline(block, steps: int):
 def bench_batch(args):
     """1024 MeshBlocks of uneven sizes (40% 16^3, 40% 24^3, 20% 32^3, nghost 2)
     from a seeded 2:1-balanced octree, each with a smooth periodic state, one
-    persistent launch per stage, VL2+PLM+HLLD, dt from newdt every step."""
+    persistent launch per stage, VL2+PLM+HLLD, dt from the CFL reduction of
+    every step's new state."""
     import torch
 
     from paper_2005_06651_amd import athmhd, inputs
@@ -214,17 +216,28 @@ def bench_batch(args):
         s.set_graph(True)
     zones = sum(b.n[0] * b.n[1] * b.n[2] for b in blocks)
     with torch.cuda.stream(stream):
+        # eager: chained steps (dt stays on the device); graph mode replays
+        # athmhd_step with the dt of newdt
+        dt_dev = torch.tensor([s.newdt(tc, tb, stream=stream)], dtype=torch.float64, device=dev)
+
+        def one_step():
+            if args.graph:
+                s.step(tc, tb, s.newdt(tc, tb, stream=stream), stream=stream)
+            else:
+                s.step_chain(tc, tb, dt_dev, stream=stream)
+
         for _ in range(args.warmup):
-            s.step(tc, tb, s.newdt(tc, tb, stream=stream), stream=stream)
+            one_step()
         stream.synchronize()
         if not args.graph:
             s.profile_start()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            s.step(tc, tb, s.newdt(tc, tb, stream=stream), stream=stream)
+            one_step()
         stream.synchronize()
         elapsed = time.perf_counter() - t0
         stage_ms, launches = (0.0, 0) if args.graph else s.profile_stop()
+        s.newdt(tc, tb, stream=stream)  # raises if any step met a non-physical cell
     out = {
         "metric": "zone-cycles/s, FP64 3D MHD VL2+PLM+HLLD, 1 MI355X, batched uneven blocks"
                   + (f", with {ns} passive scalar(s)" if ns else ""),
@@ -343,8 +356,9 @@ def bench_adjoint(args):
 def bench_mesh(args):
     """The 256^3 decaying turbulence as a coupled mesh of m^3 equal blocks
     (default 8^3 blocks of 32^3): ghost cells and faces exchanged between the
-    blocks on the device before every stage, VL2+PLM+HLLD, newdt + one step
-    per timed step."""
+    blocks on the device before every stage, VL2+PLM+HLLD, one chained step
+    (step, then the CFL reduction for the next dt, on the device) per timed
+    step."""
     import torch
 
     from paper_2005_06651_amd import athmhd, inputs
@@ -367,16 +381,18 @@ def bench_mesh(args):
     tc, tf = torch.from_numpy(mc).to(dev), torch.from_numpy(mf).to(dev)
     del mc, mf
     zones = args.n ** 3
+    dt_dev = torch.tensor([s.newdt(tc, tf)], dtype=torch.float64, device=dev)
     for _ in range(args.warmup):
-        s.step(tc, tf, s.newdt(tc, tf))
+        s.step_chain(tc, tf, dt_dev)
     torch.cuda.synchronize()
     s.profile_start()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        s.step(tc, tf, s.newdt(tc, tf))
+        s.step_chain(tc, tf, dt_dev)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     stage_ms, launches = s.profile_stop()
+    s.newdt(tc, tf)  # raises if any step met a non-physical cell
     out = {
         "metric": "zone-cycles/s, FP64 3D MHD VL2+PLM+HLLD, 1 MI355X, coupled mesh of equal blocks",
         "value": zones * args.steps / elapsed, "unit": "zone-cycles/s", "n_gpus": 1, "steps": args.steps,
@@ -477,7 +493,8 @@ def bench_levels(args):
 def bench_blast(args):
     """MHD blast on the 512^3 periodic unit cube (nghost 3, RK3 + PPM + HLLD or
     HLLE + CT, rho = 1, p = 0.1, p = 10 inside r < 0.1 around a seeded centre,
-    B = (1/sqrt2, 1/sqrt2, 0), CFL 0.3): newdt + one RK3 step per timed step.
+    B = (1/sqrt2, 1/sqrt2, 0), CFL 0.3): one chained RK3 step (step, then the
+    CFL reduction for the next dt, on the device) per timed step.
     Density and pressure floors (1e-10 by default) limit the primitives and,
     after each stage, raise the density and total energy of cells below them;
     their activations are counted and reported."""
@@ -496,31 +513,32 @@ def bench_blast(args):
     tb = torch.from_numpy(blk.bface).to(dev)
     tc = s.prim2cons(torch.from_numpy(blk.prim).to(dev), tb)
     del blk.prim
-    nonphys = 0
+    # chained steps: dt read on the device, the CFL reduction of the new state
+    # writes the next one there; the simulated time accumulates on the device
+    dt_dev = torch.tensor([s.newdt(tc, tb)], dtype=torch.float64, device=dev)
+    t_dev = torch.zeros(1, dtype=torch.float64, device=dev)
 
     def one_step():
-        nonlocal nonphys
-        try:
-            dt = s.newdt(tc, tb)
-        except athmhd.NonPhysicalState:
-            nonphys += 1
-            raise
-        s.step(tc, tb, dt)
-        return dt
+        t_dev.add_(dt_dev)
+        s.step_chain(tc, tb, dt_dev)
 
-    t_sim = 0.0
     s.floor_count()
     for _ in range(args.warmup):
-        t_sim += one_step()
+        one_step()
     torch.cuda.synchronize()
     s.profile_start()
     t0 = time.perf_counter()
     for _ in range(args.blast_steps):
-        t_sim += one_step()
+        one_step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     stage_ms, launches = s.profile_stop()
-    s.newdt(tc, tb)  # reports any non-finite value met by the last step
+    nonphys = 0
+    try:
+        s.newdt(tc, tb)  # reports any non-physical cell met since the warmup
+    except athmhd.NonPhysicalState:
+        nonphys = 1
+    t_sim = t_dev.item()
     floored = s.floor_count()
     s.fill_ghosts(tc, tb)
     torch.cuda.synchronize()
@@ -538,7 +556,7 @@ def bench_blast(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"MHD blast {n}^3 periodic unit cube, nghost 3, RK3+PPM+{args.riemann.upper()}+CT, "
                                "rho 1, p 0.1 / 10 inside r < 0.1 (seeded centre), B = (1,1,0)/sqrt2, CFL 0.3, "
-                               "dt from newdt every step",
+                               "dt from the CFL reduction of every step's new state, kept on the device",
                    "cells": zones, "seed": args.seed, "riemann": args.riemann},
         "stage_ms_per_launch": stage_ms / max(launches, 1),
         "t_simulated": t_sim, "nonphysical_reports": nonphys,
@@ -614,19 +632,22 @@ def main():
     tc = solver.prim2cons(torch.from_numpy(block.prim).to(dev), tb)
     torch.cuda.synchronize()
 
+    # each step: the VL2 step with dt read on the device, then the CFL
+    # reduction of the new state writing the next step's dt there
+    # (athmhd_step_chain); no host round trip between steps
+    dt_dev = torch.tensor([solver.newdt(tc, tb)], dtype=torch.float64, device=dev)
     for _ in range(args.warmup):
-        dt = solver.newdt(tc, tb)
-        solver.step(tc, tb, dt)
+        solver.step_chain(tc, tb, dt_dev)
     torch.cuda.synchronize()
 
     solver.profile_start()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        dt = solver.newdt(tc, tb)
-        solver.step(tc, tb, dt)
+        solver.step_chain(tc, tb, dt_dev)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     stage_ms, launches = solver.profile_stop()
+    solver.newdt(tc, tb)  # raises if any step met a non-physical cell
 
     zones = n ** 3
     value = zones * args.steps / elapsed
@@ -671,7 +692,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"decaying MHD turbulence {n}^3 periodic, VL2+PLM+HLLD+CT, gamma 5/3, rms Mach 1, "
-                        f"B = 0.5 x + curl A (rms 0.1), CFL 0.3, dt from newdt every step",
+                        f"B = 0.5 x + curl A (rms 0.1), CFL 0.3, dt from the CFL reduction of every step's "
+                        f"new state, kept on the device",
             "cells": zones, "nghost": g, "integrator": "vl2", "recon": "plm", "riemann": "hlld",
             "seed": args.seed, "kernel_path": "unfused" if args.charac else args.kernel_path, "nscalars": ns,
             "characteristic": bool(args.charac),

@@ -141,6 +141,22 @@ ATHMHD_API int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t
  * dt > 0 and finite.  Asynchronous on `stream`. */
 ATHMHD_API int athmhd_step(athmhd_t h, double* cons, double* bface, double dt, int nblocks, void* stream);
 
+/* One full time step (as athmhd_step) whose dt comes from the device and
+ * which also yields the next one (Sec. 2.1.7: the time step of the next cycle
+ * is the CFL limit of the state the cycle leaves).  *dt_dev (device memory,
+ * owned by the caller) holds this step's dt on entry; in stream order after
+ * the step it holds cfl * min over the new state's active cells of
+ * dx_d / (|v_d| + c_f,d), the value athmhd_newdt would return for it (+inf
+ * when no cell gives a finite limit), computed by the CFL reduction of
+ * athmhd_newdt queued after the step.  nbad_dev (device int, or NULL): the
+ * number of non-physical cells met by the step and the reduction, after which
+ * the handle's counter is cleared; with NULL the count stays in the handle
+ * and the next athmhd_newdt reports it.  No host synchronisation: a run of
+ * steps is queued without waiting.  Graph mode (athmhd_set_graph) does not
+ * apply.  Asynchronous on `stream`. */
+ATHMHD_API int athmhd_step_chain(athmhd_t h, double* cons, double* bface, int nblocks, double* dt_dev,
+                                 int32_t* nbad_dev, void* stream);
+
 /* Global time step dt = cfl * min over active cells and directions of
  * dx_d / (|v_d| + c_f,d) (Sec. 2.1.7, Sec. 3.2.3), written to *dt_host.
  * Synchronises `stream`.  Returns ATHMHD_ENONPHYS if this state or any step

@@ -23,7 +23,8 @@ EXPORTED = ["athmhd_version", "athmhd_create", "athmhd_create_batch", "athmhd_ba
             "athmhd_prim2cons", "athmhd_fill_ghosts", "athmhd_profile", "athmhd_last_error", "athmhd_destroy",
             "athmhd_step_vjp", "athmhd_prim2cons_vjp", "athmhd_set_floors", "athmhd_floor_count",
             "athmhd_step_stages", "athmhd_create_mesh", "athmhd_restrict", "athmhd_prolong",
-            "athmhd_restrict_box", "athmhd_prolong_box", "athmhd_newdt_noalloc", "athmhd_create_levels"]
+            "athmhd_restrict_box", "athmhd_prolong_box", "athmhd_newdt_noalloc", "athmhd_create_levels",
+            "athmhd_step_chain"]
 BATCH_TILES = [(16, 12), (12, 16), (14, 14), (16, 8)]  # active columns of the batch tile candidates
 
 
@@ -69,6 +70,7 @@ def lib():
                                         C.POINTER(C.c_double)]
         L.athmhd_set_graph.argtypes = [vp, C.c_int]
         L.athmhd_step.argtypes = [vp, vp, vp, C.c_double, C.c_int, vp]
+        L.athmhd_step_chain.argtypes = [vp, vp, vp, C.c_int, vp, vp, vp]
         L.athmhd_newdt.argtypes = [vp, vp, vp, C.c_int, C.POINTER(C.c_double), vp]
         L.athmhd_newdt_noalloc.argtypes = [vp, vp, vp, C.c_int, vp, vp, vp]
         L.athmhd_prim2cons.argtypes = [vp, vp, vp, vp, C.c_int, vp]
@@ -182,6 +184,16 @@ class Solver:
     def step(self, cons, bface, dt: float, stream=None) -> None:
         pc, pb, nb = self._pair(cons, bface)
         _check(lib().athmhd_step(self._h, pc, pb, float(dt), nb, _stream(stream)), self._h)
+
+    def step_chain(self, cons, bface, dt_dev, nbad_out=None, stream=None) -> None:
+        """athmhd_step_chain: one step with dt read from dt_dev[0] (float64
+        device tensor), which then holds the next step's dt; the non-physical
+        count goes to nbad_out[0] (int32 device tensor) when given.
+        Asynchronous."""
+        pc, pb, nb = self._pair(cons, bface)
+        nbp = None if nbad_out is None else _scalar_out(nbad_out, "int32")
+        _check(lib().athmhd_step_chain(self._h, pc, pb, nb, _scalar_out(dt_dev, "float64"), nbp, _stream(stream)),
+               self._h)
 
     def newdt(self, cons, bface, stream=None) -> float:
         pc, pb, nb = self._pair(cons, bface)
@@ -455,6 +467,12 @@ class BatchSolver:
     def step(self, cons, bface, dt: float, stream=None) -> None:
         pc, pb = self._pair(cons, bface)
         _check(lib().athmhd_step(self._h, pc, pb, float(dt), self.nblocks, _stream(stream)), self._h)
+
+    def step_chain(self, cons, bface, dt_dev, nbad_out=None, stream=None) -> None:
+        pc, pb = self._pair(cons, bface)
+        nbp = None if nbad_out is None else _scalar_out(nbad_out, "int32")
+        _check(lib().athmhd_step_chain(self._h, pc, pb, self.nblocks, _scalar_out(dt_dev, "float64"), nbp,
+                                       _stream(stream)), self._h)
 
     def newdt(self, cons, bface, stream=None) -> float:
         pc, pb = self._pair(cons, bface)

@@ -130,6 +130,20 @@ __global__ void k_set_u64(unsigned long long* p, unsigned long long v, int* bad,
   }
 }
 
+// End of a chained step: the next step's dt from the CFL minimum (cfl times
+// +inf when no cell gave a limit), and the non-physical count handed over and
+// cleared when the caller asked for it.
+__global__ void k_chain_finish(const unsigned long long* bits, double cfl, int* bad, double* dt_dev,
+                               int32_t* nbad_dev) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *dt_dev = cfl * __longlong_as_double((long long)*bits);
+    if (nbad_dev) {
+      *nbad_dev = bad[0];
+      bad[0] = 0;
+    }
+  }
+}
+
 // first node of a replayed step: puts this step's dt on the device
 __global__ void k_set_dt(double* p, double dt) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = dt;
@@ -357,6 +371,21 @@ hipError_t levels_stage(athmhd_t h, int recon, const double* xc, const double* x
   return e;
 }
 
+// The CFL minimum of a state folded into bits (atomic minimum of the bit
+// patterns of non-negative doubles).
+hipError_t launch_cfl(athmhd_t h, const double* cons, const double* bface, int nblocks, unsigned long long* bits,
+                      hipStream_t s) {
+  if (h->levels) {
+    hipError_t e = launch_newdt(h->g, h->cfg.gamma, cons, bface, 1, bits, h->floors, h->d_bad, s);
+    if (e != hipSuccess) return e;
+    return launch_newdt(h->gf, h->cfg.gamma, cons + h->g.cblock, bface + h->g.fblock, 8, bits, h->floors,
+                        h->d_bad, s);
+  }
+  if (h->batch) return launch_newdt_batch(h->d_desc, h->nbatch, 0, h->cfg.gamma, cons, bface, bits, h->floors,
+                                          h->d_bad, s);
+  return launch_newdt(h->g, h->cfg.gamma, cons, bface, nblocks, bits, h->floors, h->d_bad, s);
+}
+
 // x3 planes per workgroup of the fused stage kernel on nblocks uniform blocks
 int stage_kz(athmhd_t h, int nblocks) { return h->kz > 0 ? h->kz : fused_default_kz(h->g, nblocks, h->cus); }
 
@@ -389,9 +418,10 @@ hipError_t fill_ghosts(athmhd_t h, double* cons, double* bface, int nblocks, hip
 // dt_dev != NULL the stage kernels read dt from the device.
 // stages != NULL (uniform handles): the inputs of stages 1..S-1 are written
 // there (S-1 states, each all blocks' cons then all blocks' bface) instead of
-// the library's registers.
+// the library's registers.  dt_bits != NULL: the CFL minimum of the new
+// state is folded into it after the step.
 int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const double* dt_dev, int nblocks,
-                 hipStream_t s, double* stages = nullptr) {
+                 hipStream_t s, double* stages = nullptr, unsigned long long* dt_bits = nullptr) {
   const Scheme sc = scheme_of(h->cfg.integrator);
   const double* xc = cons;
   const double* xb = bface;
@@ -464,6 +494,8 @@ int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const doubl
   // a composite leaves its ghosts and restricted coarse faces filled, which
   // its newdt reads
   if (h->levels && (e = levels_ghosts(h, cons, bface, s)) != hipSuccess) return hip_fail(h, e, "level ghost launch");
+  if (dt_bits && (e = launch_cfl(h, cons, bface, nblocks, dt_bits, s)) != hipSuccess)
+    return hip_fail(h, e, "newdt launch");
   return ATHMHD_OK;
 }
 
@@ -581,7 +613,7 @@ int noalloc_scratch(athmhd_t h, int dev, DtPart** out) {
 
 extern "C" {
 
-int athmhd_version(void) { return 110; }
+int athmhd_version(void) { return 111; }
 
 int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
   if (!out) return fail(nullptr, ATHMHD_EINVAL, "out is NULL");
@@ -944,6 +976,25 @@ int athmhd_step(athmhd_t h, double* cons, double* bface, double dt, int nblocks,
     if (rc != ATHMHD_OK) return rc;
   }
   return replay_step(h, dt, s);
+}
+
+int athmhd_step_chain(athmhd_t h, double* cons, double* bface, int nblocks, double* dt_dev, int32_t* nbad_dev,
+                      void* stream) {
+  int rc = check_call(h, cons, bface, nblocks);
+  if (rc) return rc;
+  if (h->levels && h->floors.on()) return fail(h, ATHMHD_EUNSUP, "a two-level composite runs without floors");
+  if (!dt_dev) return fail(h, ATHMHD_EINVAL, "NULL dt_dev");
+  hipStream_t s = (hipStream_t)stream;
+  const double inf = INFINITY;
+  unsigned long long inf_bits;
+  std::memcpy(&inf_bits, &inf, 8);
+  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, h->d_dtmin, inf_bits, h->d_bad, 0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(h, e, "chain init launch");
+  if ((rc = enqueue_step(h, cons, bface, 0.0, dt_dev, nblocks, s, nullptr, h->d_dtmin)) != ATHMHD_OK) return rc;
+  hipLaunchKernelGGL(k_chain_finish, dim3(1), dim3(64), 0, s, h->d_dtmin, h->cfg.cfl, h->d_bad, dt_dev, nbad_dev);
+  e = hipGetLastError();
+  return e == hipSuccess ? ATHMHD_OK : hip_fail(h, e, "chain finish launch");
 }
 
 int athmhd_step_vjp(athmhd_t h, const double* cons_n, const double* bface_n, double dt, const double* stages,

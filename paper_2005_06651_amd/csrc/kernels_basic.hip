@@ -299,23 +299,12 @@ __global__ void __launch_bounds__(kThreads) k_newdt(Geo g, double gamma, Floors 
     const int r = t / g.n1;
     const int j = g.ng + r % g.n2, k = g.ng + r / g.n2;
     const int q = g.c(i, j, k);
-    double b1, b2, b3;
-    cell_field(g, fb, bface, blockIdx.y, i, j, k, b1, b2, b3);
+    double bc[3];
+    cell_field(g, fb, bface, blockIdx.y, i, j, k, bc[0], bc[1], bc[2]);
     const double uc[5] = {u[q], u[g.cvar + q], u[2 * g.cvar + q], u[3 * g.cvar + q], u[4 * g.cvar + q]};
-    const double bc[3] = {b1, b2, b3};
-    double w[5];
-    if (cell_prim(uc, bc, gamma - 1.0, fl, w) & 1) {
-      ++nbad;
-      continue;
-    }
-    const double ir = frcp(w[0]), v1 = w[1], v2 = w[2], v3 = w[3], p = w[4];
-    const double bs1 = b1 * b1, bs2 = b2 * b2, bs3 = b3 * b3;
-    const double c1 = fast_speed(ir, p, bs1, bs2 + bs3, gamma);
-    const double c2 = fast_speed(ir, p, bs2, bs3 + bs1, gamma);
-    const double c3 = fast_speed(ir, p, bs3, bs1 + bs2, gamma);
-    const double d = fmin(g.dx1 * frcp(fabs(v1) + c1), fmin(g.dx2 * frcp(fabs(v2) + c2), g.dx3 * frcp(fabs(v3) + c3)));
-    if (!(d > 0.0) || !(d < DBL_MAX)) ++nbad;
-    else best = fmin(best, d);
+    double d;
+    if (cfl_cell(uc, bc, gamma, fl, g.dx1, g.dx2, g.dx3, d)) best = fmin(best, d);
+    else ++nbad;
   }
   dt_workgroup_end<PARTS>(best, nbad, dt_bits, bad, parts, (int64_t)blockIdx.y * gridDim.x + blockIdx.x);
 }
@@ -476,23 +465,12 @@ __global__ void __launch_bounds__(kThreads) k_newdt_batch(const BatchDesc* __res
     const int r = t / g.n1;
     const int j = g.ng + r % g.n2, k = g.ng + r / g.n2;
     const int q = g.c(i, j, k);
-    double b1, b2, b3;
-    cell_field(g, fb, fb, 0, i, j, k, b1, b2, b3);  // batched blocks: their own neighbours
+    double bc[3];
+    cell_field(g, fb, fb, 0, i, j, k, bc[0], bc[1], bc[2]);  // batched blocks: their own neighbours
     const double uc[5] = {u[q], u[g.cvar + q], u[2 * g.cvar + q], u[3 * g.cvar + q], u[4 * g.cvar + q]};
-    const double bc[3] = {b1, b2, b3};
-    double w[5];
-    if (cell_prim(uc, bc, gamma - 1.0, fl, w) & 1) {
-      ++nbad;
-      continue;
-    }
-    const double ir = frcp(w[0]), v1 = w[1], v2 = w[2], v3 = w[3], p = w[4];
-    const double bs1 = b1 * b1, bs2 = b2 * b2, bs3 = b3 * b3;
-    const double c1 = fast_speed(ir, p, bs1, bs2 + bs3, gamma);
-    const double c2 = fast_speed(ir, p, bs2, bs3 + bs1, gamma);
-    const double c3 = fast_speed(ir, p, bs3, bs1 + bs2, gamma);
-    const double dd = fmin(g.dx1 * frcp(fabs(v1) + c1), fmin(g.dx2 * frcp(fabs(v2) + c2), g.dx3 * frcp(fabs(v3) + c3)));
-    if (!(dd > 0.0) || !(dd < DBL_MAX)) ++nbad;
-    else best = fmin(best, dd);
+    double d;
+    if (cfl_cell(uc, bc, gamma, fl, g.dx1, g.dx2, g.dx3, d)) best = fmin(best, d);
+    else ++nbad;
   }
   dt_workgroup_end<PARTS>(best, nbad, dt_bits, bad, parts, (int64_t)blockIdx.y * gridDim.x + blockIdx.x);
 }

@@ -11,6 +11,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cfloat>
+
 #include "common.hpp"
 
 namespace athmhd {
@@ -115,6 +117,26 @@ __device__ __forceinline__ double fast_speed(double irho, double p, double bnsq,
   double s = asq + (bnsq + btsq) * irho;
   double disc = fmax(s * s - 4.0 * asq * bnsq * irho, 0.0);
   return fsqrt(0.5 * (s + fsqrt(disc)));
+}
+
+// CFL limit of one cell (Sec. 2.1.7, Sec. 3.2.3): d = min over directions of
+// dx_d / (|v_d| + c_f,d) from its conserved state u and cell-centred field b.
+// Returns false (d untouched) for a non-physical cell or a limit that is not
+// positive and finite.  Every CFL reduction calls this, so a fused and a
+// separate reduction of the same state agree.
+__device__ __forceinline__ bool cfl_cell(const double* u, const double* b, double gamma, const Floors& fl,
+                                         double dx1, double dx2, double dx3, double& d) {
+  double w[5];
+  if (cell_prim(u, b, gamma - 1.0, fl, w) & 1) return false;
+  const double ir = frcp(w[0]), v1 = w[1], v2 = w[2], v3 = w[3], p = w[4];
+  const double bs1 = b[0] * b[0], bs2 = b[1] * b[1], bs3 = b[2] * b[2];
+  const double c1 = fast_speed(ir, p, bs1, bs2 + bs3, gamma);
+  const double c2 = fast_speed(ir, p, bs2, bs3 + bs1, gamma);
+  const double c3 = fast_speed(ir, p, bs3, bs1 + bs2, gamma);
+  const double dd = fmin(dx1 * frcp(fabs(v1) + c1), fmin(dx2 * frcp(fabs(v2) + c2), dx3 * frcp(fabs(v3) + c3)));
+  if (!(dd > 0.0) || !(dd < DBL_MAX)) return false;
+  d = dd;
+  return true;
 }
 
 // HLLE with Davis wave-speed bounds.

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version():
-    assert athmhd.lib().athmhd_version() == 110
+    assert athmhd.lib().athmhd_version() == 111
 
 
 def _create(**over):
@@ -159,6 +159,7 @@ def test_batch_calls_reject_non_batch_use():
     assert L.athmhd_batch_info(None, None, None, None) == athmhd.EINVAL
     assert L.athmhd_set_graph(None, 1) == athmhd.EINVAL
     assert L.athmhd_newdt_noalloc(None, None, None, 1, None, None, None) == athmhd.EINVAL
+    assert L.athmhd_step_chain(None, None, None, 1, None, None, None) == athmhd.EINVAL
 
 
 def test_octree_is_two_to_one_balanced():
