@@ -38,9 +38,15 @@ ALG_FLOPS_PER_ZONE_CYCLE = 2560.0
 # on this workload, scaled by the counters of a plain 1 GiB copy, and the hash
 # of the stage-kernel sources they were measured on (traffic is reported only
 # while the sources are unchanged).
-STAGE_TRAFFIC = {"bytes_per_launch": 3.468e+09, "fetch_bytes_per_launch": 2.295e+09,
-                 "write_bytes_per_launch": 1.172e+09, "fetch_scale": 1.9999, "write_scale": 1.0000,
-                 "source_hash": "38a041e3236d4fb2"}
+STAGE_TRAFFIC = {"bytes_per_launch": 3.511e+09, "fetch_bytes_per_launch": 2.321e+09,
+                 "write_bytes_per_launch": 1.190e+09, "fetch_scale": 1.9999, "write_scale": 1.0000,
+                 "source_hash": "070f8df4dc5fe766"}
+# FP64 VALU issue of the same stage launches (rocprofv3 SQ_INSTS_VALU per
+# launch over 256 CUs x 2.4 GHz x the launch duration, mean of the DC and PLM
+# stages) and the stage time those launches took under the profiler: with the
+# traffic above they say which roof binds (the larger measured fraction).
+STAGE_ISSUE = {"valu_issue_frac": 0.492, "profiled_ms_per_launch": 1.7647, "source_hash": "070f8df4dc5fe766"}
+HBM_FRAC_TARGET = 0.60       # the HBM-roofline fraction the stage kernel is measured against
 # The same for the level operators on the 256^3 block (per octant launch).
 LEVELS_SOURCES = ("kernels_amr.hip", "common.hpp")
 LEVELS_TRAFFIC = {"prolong": {"bytes_per_launch": 1.635e+09, "fetch_bytes_per_launch": 3.96e+08,
@@ -662,9 +668,25 @@ def main():
     achieved_tf = alg_flops / per_launch_s / 1e12
     achieved_gbs = alg_bytes / per_launch_s / 1e9
     traffic = None
+    issue = None
     if STAGE_TRAFFIC and STAGE_TRAFFIC.get("source_hash") == stage_source_hash() and args.kernel_path == "fused" \
             and n == 256 and ns == 0 and not args.charac:
         traffic = STAGE_TRAFFIC["bytes_per_launch"]
+        if STAGE_ISSUE.get("source_hash") == STAGE_TRAFFIC["source_hash"]:
+            issue = STAGE_ISSUE
+    # which roof binds: the larger of the measured FP64 VALU issue fraction
+    # and the measured HBM traffic fraction (counters of this kernel source);
+    # without current counters, the larger algorithmic fraction
+    alu_frac = achieved_tf / FP64_VECTOR_TFLOPS
+    hbm_frac = achieved_gbs / HBM_PEAK_GBS
+    if issue:
+        traffic_frac = traffic / (issue["profiled_ms_per_launch"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+        bound = "alu" if issue["valu_issue_frac"] >= traffic_frac else "hbm"
+        basis = {"valu_issue_frac": issue["valu_issue_frac"], "hbm_traffic_frac": traffic_frac,
+                 "source": "rocprofv3 SQ_INSTS_VALU, FETCH_SIZE, WRITE_SIZE of this kernel source"}
+    else:
+        bound = "alu" if alu_frac >= hbm_frac else "hbm"
+        basis = {"source": "algorithmic fractions (no counters for this kernel source)"}
     # sanity of the final state
     solver.fill_ghosts(tc, tb)
     torch.cuda.synchronize()
@@ -699,13 +721,17 @@ def main():
             "characteristic": bool(args.charac),
         },
         "roofline": {
-            "bound": "alu",
+            "bound": bound,
             "kernel": "k_stage_fused (reconstruct + HLLD + CT + update of one stage), per launch",
-            "achieved": achieved_tf,
-            "peak": FP64_VECTOR_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved_tf / FP64_VECTOR_TFLOPS,
+            "achieved": achieved_tf if bound == "alu" else achieved_gbs,
+            "peak": FP64_VECTOR_TFLOPS if bound == "alu" else HBM_PEAK_GBS,
+            "unit": "TFLOP/s" if bound == "alu" else "GB/s",
+            "frac": alu_frac if bound == "alu" else hbm_frac,
             "traffic": traffic,
+            "alu_frac": alu_frac,
+            "hbm_frac": hbm_frac,
+            "hbm_frac_target": HBM_FRAC_TARGET,
+            "bound_basis": basis,
             "alg_flops_per_launch": alg_flops,
             "stage_ms_per_launch": per_launch_s * 1e3,
             "launches": launches,

@@ -305,8 +305,13 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
 
   // ---- z window: planes p-LA .. p+LA of the own column
   ZCell win[NW];
-  // normal fields (lower x1, x2, x3 faces of the own cell) of planes p .. p+LA
-  double bnq[LA + 1][3];
+  // normal fields (lower x1, x2, x3 faces of the own cell) of planes
+  // p .. p+LA, carried from the look-ahead loads; with PPM's five-plane window
+  // they are read again from the cache each plane instead (fewer registers
+  // live through the plane: 4.6 % faster for PPM, 2.2 % slower for PLM)
+  constexpr bool RELOAD_BN = LA >= 2;
+  constexpr int NBQ = RELOAD_BN ? 1 : LA + 1;
+  double bnq[NBQ][3];
   {
     double w[8];
     Raw raw;
@@ -317,7 +322,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
       nbad += f & 1;
       nfl += f >> 1;
       to_zcell(w, win[o + 1]);
-      if (o >= LA) {
+      if (!RELOAD_BN && o >= LA) {
         bnq[o - LA][0] = raw.b1lo;
         bnq[o - LA][1] = raw.b2lo;
         bnq[o - LA][2] = raw.b3lo;
@@ -347,9 +352,16 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
       nbad += f & 1;
       nfl += f >> 1;
       to_zcell(w, win[NW - 1]);
-      bnq[LA][0] = pre.b1lo;
-      bnq[LA][1] = pre.b2lo;
-      bnq[LA][2] = pre.b3lo;
+      if (RELOAD_BN) {
+        const int f = g.f(own.i0, own.j0, read_index<MESH>(g, p, g.n3, g.N3 - 1));
+        bnq[0][0] = xb[f];
+        bnq[0][1] = xb[g.fvar + f];
+        bnq[0][2] = xb[2 * g.fvar + f];
+      } else {
+        bnq[NBQ - 1][0] = pre.b1lo;
+        bnq[NBQ - 1][1] = pre.b2lo;
+        bnq[NBQ - 1][2] = pre.b3lo;
+      }
     }
 
     // ---- 3. own cell of plane p: primitives to LDS, cell EMFs
@@ -585,7 +597,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
 
     // ---- 9. carry this plane's face EMFs / weights / cell EMFs upward
 #pragma unroll
-    for (int o = 0; o < LA; ++o) {
+    for (int o = 0; o < NBQ - 1; ++o) {
       bnq[o][0] = bnq[o + 1][0];
       bnq[o][1] = bnq[o + 1][1];
       bnq[o][2] = bnq[o + 1][2];

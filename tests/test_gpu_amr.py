@@ -13,6 +13,7 @@ must stay untouched, round trip and divergence properties on the device, a
 on refined cells (E within 1e-14 of the oracle, activations counted), and the
 error paths.
 """
+import gc
 import itertools
 
 import numpy as np
@@ -621,8 +622,12 @@ def test_level_operators_replay_from_a_graph(torch_dev, athmhd):
         refine_and_back()
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
+    # capture in thread-local mode after a collection: a tensor of an earlier
+    # test freed by the garbage collector during a global-mode capture can
+    # invalidate the capture from outside these calls
+    gc.collect()
     graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
+    with torch.cuda.graph(graph, capture_error_mode="thread_local"):
         refine_and_back()
     torch.cuda.synchronize()
     for rep in range(3):

@@ -5,6 +5,7 @@ partial results must not be mixed with the stale ones of the first call, which
 stay in the shared device array), on uniform and batched handles, and replayed
 from a captured graph."""
 import ctypes as C
+import gc
 import re
 
 import numpy as np
@@ -153,8 +154,10 @@ def test_noalloc_replays_from_a_graph(torch_dev, athmhd, orc):
         s.newdt_noalloc(tc, tb, dt, nbad)
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
+    # thread-local capture after a collection (see test_gpu_amr's graph test)
+    gc.collect()
     graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
+    with torch.cuda.graph(graph, capture_error_mode="thread_local"):
         s.newdt_noalloc(tc, tb, dt, nbad)
     for it in range(3):
         s.step(tc, tb, 2e-3 * (it + 1))
