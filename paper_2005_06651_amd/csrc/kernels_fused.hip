@@ -214,8 +214,15 @@ struct Smem {
 };
 
 enum {
-  X_FX = 0, X_FY = 5, X_E3X = 10, X_WX, X_E3Y, X_WY, X_E3C, X_E1Z, X_E2Z, X_WZ, X_E1C, X_E2C, X_E1CP, X_E2CP, X_N
+  X_FX = 0, X_FY = 5, X_E3X = 10, X_WX, X_E3Y, X_WY, X_E3C, X_E1Z, X_E2Z, X_WZ, X_E1C, X_E2C, X_E1CP, X_E2CP,
+  // the previous plane's x1-face E2 and weight, x2-face E1 and (DC, PLM) weight:
+  // read only by the own thread, kept here rather than in registers
+  X_E2XP, X_WXP, X_E1YP, X_WYP, X_N
 };
+// exchange slots of a stage: PPM's wider primitive plane leaves room for all
+// but the last (its x2-face weight stays in a register)
+template <int RECON>
+constexpr int exchange_slots() { return RECON >= 2 ? X_N - 1 : X_N; }
 
 // Face-field update of plane q from its corner EMFs in sc (E1, E2, E3 of the
 // own column's edges; the neighbours' at tid + 1 and tid + BX): completes B1
@@ -335,7 +342,8 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
   if (ring) load_raw<MESH>(g, xc, xb, rcol, k0 - 1, rpre);
 
   double qz_carry[7];  // left state of the next x3-face (right edge of the cell below)
-  double e2x_prev = 0.0, wx_prev = 0.5, e1y_prev = 0.0, wy_prev = 0.5, e1c_prev = 0.0, e2c_prev = 0.0;
+  constexpr bool WY_REG = exchange_slots<RECON>() < X_N;
+  double wy_prev = 0.5;  // PPM: the previous plane's x2-face weight
   double acc_prev[7];  // partial update of the plane below: 5 conserved, B1, B2
   double pwb[3] = {0.0, 0.0, 0.0};  // pointwise terms of B1, B2 (plane below) and B3 of the last plane
 #pragma unroll
@@ -427,10 +435,13 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
     // before the barrier above, lets the previous plane's corner EMFs read the
     // same slots without a third barrier per plane)
     sx[X_E3C * NT + tid] = e3c;
+    // the previous plane's cell EMFs move to their own slots first (the slots
+    // of the current plane still hold them: nobody reads these between the
+    // previous plane's corner EMFs and here)
+    sx[X_E1CP * NT + tid] = sx[X_E1C * NT + tid];
+    sx[X_E2CP * NT + tid] = sx[X_E2C * NT + tid];
     sx[X_E1C * NT + tid] = e1c;
     sx[X_E2C * NT + tid] = e2c;
-    sx[X_E1CP * NT + tid] = e1c_prev;
-    sx[X_E2CP * NT + tid] = e2c_prev;
     sx[X_E1Z * NT + tid] = e1z;
     sx[X_E2Z * NT + tid] = e2z;
     sx[X_WZ * NT + tid] = wz;
@@ -559,14 +570,17 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
     }
     if (ty >= 1 && zface) {
       // E1 at (i, j-1/2, p-1/2): a = x2, b = x3
-      c1 = corner_emf(e1y, e1y_prev, sx[X_E1Z * NT + tid], sx[X_E1Z * NT + tS], e1c, sx[X_E1C * NT + tS],
-                      e1c_prev, sx[X_E1CP * NT + tS], wy, wy_prev, sx[X_WZ * NT + tid], sx[X_WZ * NT + tS]);
+      double wyp = wy_prev;
+      if constexpr (!WY_REG) wyp = sx[X_WYP * NT + tid];
+      c1 = corner_emf(e1y, sx[X_E1YP * NT + tid], sx[X_E1Z * NT + tid], sx[X_E1Z * NT + tS],
+                      sx[X_E1C * NT + tid], sx[X_E1C * NT + tS], sx[X_E1CP * NT + tid], sx[X_E1CP * NT + tS], wy, wyp,
+                      sx[X_WZ * NT + tid], sx[X_WZ * NT + tS]);
     }
     if (tx >= 1 && zface) {
       // E2 at (i-1/2, j, p-1/2): a = x3, b = x1
-      c2 = corner_emf(sx[X_E2Z * NT + tid], sx[X_E2Z * NT + tW], e2x, e2x_prev, e2c, e2c_prev,
-                      sx[X_E2C * NT + tW], sx[X_E2CP * NT + tW], sx[X_WZ * NT + tid], sx[X_WZ * NT + tW], wx,
-                      wx_prev);
+      c2 = corner_emf(sx[X_E2Z * NT + tid], sx[X_E2Z * NT + tW], e2x, sx[X_E2XP * NT + tid],
+                      sx[X_E2C * NT + tid], sx[X_E2CP * NT + tid], sx[X_E2C * NT + tW], sx[X_E2CP * NT + tW],
+                      sx[X_WZ * NT + tid], sx[X_WZ * NT + tW], wx, sx[X_WXP * NT + tid]);
     }
     sc[0 * NT + tid] = c1;
     sc[1 * NT + tid] = c2;
@@ -602,12 +616,11 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
       bnq[o][1] = bnq[o + 1][1];
       bnq[o][2] = bnq[o + 1][2];
     }
-    e2x_prev = e2x;
-    wx_prev = wx;
-    e1y_prev = e1y;
-    wy_prev = wy;
-    e1c_prev = e1c;
-    e2c_prev = e2c;
+    sx[X_E2XP * NT + tid] = e2x;
+    sx[X_WXP * NT + tid] = wx;
+    sx[X_E1YP * NT + tid] = e1y;
+    if constexpr (WY_REG) wy_prev = wy;
+    else sx[X_WYP * NT + tid] = wy;
   }
   __syncthreads();
   if (act && kend >= k0)
@@ -625,7 +638,7 @@ k_stage_fused(UniformArgs a) {
   using T = TileU;
   using S = Smem<RECON, T>;
   __shared__ double sp[8 * S::PL];      // primitives of the current plane
-  __shared__ double sx[X_N * T::NT];    // exchange slots
+  __shared__ double sx[exchange_slots<RECON>() * T::NT];  // exchange slots
   __shared__ double sc[3 * T::NT];      // corner EMFs E1, E2, E3 of the current (half-)plane
   const int64_t bid = blockIdx.x;
   const int64_t logical = (bid % 8) * a.per_xcd + bid / 8;
@@ -650,7 +663,7 @@ template <int RECON, int RS, class T, bool FL, bool MF>
 __global__ void __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(2))) k_stage_batch(BatchArgs a) {
   using S = Smem<RECON, T>;
   __shared__ double sp[8 * S::PL];
-  __shared__ double sx[X_N * T::NT];
+  __shared__ double sx[exchange_slots<RECON>() * T::NT];
   __shared__ double sc[3 * T::NT];
   __shared__ int s_item;
   for (;;) {
