@@ -253,6 +253,30 @@ __device__ __forceinline__ void face_update(const Geo& g, const double* __restri
   bacc[6] = a6;
 }
 
+// The same, with the pointwise terms read here instead of carried in pwb
+// through the plane's registers.
+__device__ __forceinline__ void face_update_read(const Geo& g, const double* __restrict__ sc, int tid, int BX,
+                                                 int NT, int gi, int gj, int q, int k0, int kend, double i1,
+                                                 double i2, double i3, double bdt, const StageCoef& cf,
+                                                 const double* unb, const double* xb, double* bacc, double* ob) {
+  double pwb[3] = {0.0, 0.0, 0.0};
+  if (q < kend) {
+    const int f3 = 2 * g.fvar + g.f(gi, gj, q);
+    pwb[2] = cf.g1 * unb[f3];
+    if (cf.g0 != 0.0) pwb[2] += cf.g0 * xb[f3];
+  }
+  if (q - 1 >= k0) {
+    const int f = g.f(gi, gj, q - 1);
+    pwb[0] = cf.g1 * unb[f];
+    pwb[1] = cf.g1 * unb[g.fvar + f];
+    if (cf.g0 != 0.0) {
+      pwb[0] += cf.g0 * xb[f];
+      pwb[1] += cf.g0 * xb[g.fvar + f];
+    }
+  }
+  face_update(g, sc, tid, BX, NT, gi, gj, q, k0, kend, i1, i2, i3, bdt, pwb, bacc, ob);
+}
+
 // One tile (tile_x, tile_y) of a block over the active planes [k0, kend).
 // MF: also store the mass flux through the lower faces of the active cells,
 // which passive scalars are carried by.
@@ -345,7 +369,13 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
   constexpr bool WY_REG = exchange_slots<RECON>() < X_N;
   double wy_prev = 0.5;  // PPM: the previous plane's x2-face weight
   double acc_prev[7];  // partial update of the plane below: 5 conserved, B1, B2
-  double pwb[3] = {0.0, 0.0, 0.0};  // pointwise terms of B1, B2 (plane below) and B3 of the last plane
+  // pointwise terms of the face fields: carried from the plane that loads them
+  // to the next plane's face update on the uniform DC / PLM tile, read in the
+  // face update elsewhere, where registers are scarcer (PPM's window, the
+  // batch tiles): measured 0.9 % faster carried on the uniform PLM stage,
+  // 5.6 % (PPM) and 3.5 % (batch) faster read
+  constexpr bool CARRY_PW = LA < 2 && NT == TileU::NT;
+  double pwb[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int v = 0; v < 7; ++v) { acc_prev[v] = 0.0; qz_carry[v] = 0.0; }
 
@@ -447,8 +477,12 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
     sx[X_WZ * NT + tid] = wz;
     // ---- 8, for plane p-1: its face-field updates from the corner EMFs that
     // the previous iteration left in sc
-    if (act && p - 1 >= k0)
-      face_update(g, sc, tid, BX, NT, gi, gj, p - 1, k0, kend, i1, i2, i3, bdt, pwb, acc_prev, ob);
+    if (act && p - 1 >= k0) {
+      if constexpr (CARRY_PW)
+        face_update(g, sc, tid, BX, NT, gi, gj, p - 1, k0, kend, i1, i2, i3, bdt, pwb, acc_prev, ob);
+      else
+        face_update_read(g, sc, tid, BX, NT, gi, gj, p - 1, k0, kend, i1, i2, i3, bdt, sa.cf, unb, xb, acc_prev, ob);
+    }
 
     // ---- 6. Riemann problems on the lower x1-face and x2-face in plane p
     double e2x = 0.0, wx = 0.5, e1y = 0.0, wy = 0.5;
@@ -537,22 +571,26 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
     }
     const bool out_cell = act && zface && p - 1 >= k0;
     const bool out_b3 = act && zface && p < kend;
-    double pw[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // g1 U^n + g0 X of cell p-1 (5), B1, B2 at p-1, B3 at p
+    double pw[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // g1 U^n + g0 X of cell p-1 (5), B1, B2 at p-1, B3 at p (carried)
     {
       const int q = g.c(gi, gj, p - 1), f = g.f(gi, gj, p - 1), f3 = g.f(gi, gj, p);
       if (out_cell) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) pw[v] = sa.cf.g1 * unc[v * g.cvar + q];
-        pw[5] = sa.cf.g1 * unb[f];
-        pw[6] = sa.cf.g1 * unb[g.fvar + f];
+        if (CARRY_PW) {
+          pw[5] = sa.cf.g1 * unb[f];
+          pw[6] = sa.cf.g1 * unb[g.fvar + f];
+        }
         if (sa.cf.g0 != 0.0) {
 #pragma unroll
           for (int v = 0; v < 5; ++v) pw[v] += sa.cf.g0 * xc[v * g.cvar + q];
-          pw[5] += sa.cf.g0 * xb[f];
-          pw[6] += sa.cf.g0 * xb[g.fvar + f];
+          if (CARRY_PW) {
+            pw[5] += sa.cf.g0 * xb[f];
+            pw[6] += sa.cf.g0 * xb[g.fvar + f];
+          }
         }
       }
-      if (out_b3) {
+      if (CARRY_PW && out_b3) {
         pw[7] = sa.cf.g1 * unb[2 * g.fvar + f3];
         if (sa.cf.g0 != 0.0) pw[7] += sa.cf.g0 * xb[2 * g.fvar + f3];
       }
@@ -604,9 +642,11 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
 #pragma unroll
       for (int v = 0; v < 5; ++v) acc_prev[v] = acc[v];
       // the face fields of this plane are updated after the next barrier
-      pwb[0] = pw[5];
-      pwb[1] = pw[6];
-      pwb[2] = pw[7];
+      if (CARRY_PW) {
+        pwb[0] = pw[5];
+        pwb[1] = pw[6];
+        pwb[2] = pw[7];
+      }
     }
 
     // ---- 9. carry this plane's face EMFs / weights / cell EMFs upward
@@ -623,8 +663,12 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
     else sx[X_WYP * NT + tid] = wy;
   }
   __syncthreads();
-  if (act && kend >= k0)
-    face_update(g, sc, tid, BX, NT, gi, gj, kend, k0, kend, i1, i2, i3, bdt, pwb, acc_prev, ob);
+  if (act && kend >= k0) {
+    if constexpr (CARRY_PW)
+      face_update(g, sc, tid, BX, NT, gi, gj, kend, k0, kend, i1, i2, i3, bdt, pwb, acc_prev, ob);
+    else
+      face_update_read(g, sc, tid, BX, NT, gi, gj, kend, k0, kend, i1, i2, i3, bdt, sa.cf, unb, xb, acc_prev, ob);
+  }
   if (nbad && act) atomicAdd(sa.bad, 1);
   if (nfl && act) add_floor_count(sa.bad, (unsigned long long)nfl);
 }
