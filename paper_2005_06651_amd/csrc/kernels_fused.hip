@@ -280,7 +280,10 @@ __device__ __forceinline__ void face_update_read(const Geo& g, const double* __r
 // One tile (tile_x, tile_y) of a block over the active planes [k0, kend).
 // MF: also store the mass flux through the lower faces of the active cells,
 // which passive scalars are carried by.
-template <int RECON, int RS, class T, bool FL, bool MESH = false, bool MF = false>
+// SAME (donor cell only): the stage input is U^n itself (the first stage of
+// every scheme), so the output's pointwise terms come from the raw cell read
+// for the window one plane earlier, carried, instead of being read again.
+template <int RECON, int RS, class T, bool FL, bool MESH = false, bool MF = false, bool SAME = false>
 __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, const StageArgs& sa, int tile_x,
                                            int tile_y, int k0, int kend, double* __restrict__ sp,
                                            double* __restrict__ sx, double* __restrict__ sc) {
@@ -375,6 +378,11 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
   // batch tiles): measured 0.9 % faster carried on the uniform PLM stage,
   // 5.6 % (PPM) and 3.5 % (batch) faster read
   constexpr bool CARRY_PW = LA < 2 && NT == TileU::NT;
+  static_assert(!SAME || LA == 0, "the raw cell of the output plane is carried with the donor-cell window only");
+  // SAME: conserved state and lower B1, B2 of the previous plane's cell, and
+  // of the current plane's (from its look-ahead load, until the output step)
+  double ucar[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double unext[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   // the look-ahead loads for the next plane: issued before the corner EMFs
   // (more time to arrive), or after them where the registers they occupy
   // through the corner EMFs would be spilled (PPM, the batch tiles): measured
@@ -396,6 +404,12 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
       nbad += f & 1;
       nfl += f >> 1;
       to_zcell(w, win[NW - 1]);
+      if (SAME) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) unext[v] = pre.u[v];
+        unext[5] = pre.b1lo;
+        unext[6] = pre.b2lo;
+      }
       if (RELOAD_BN) {
         const int f = g.f(own.i0, own.j0, read_index<MESH>(g, p, g.n3, g.N3 - 1));
         bnq[0][0] = xb[f];
@@ -581,25 +595,44 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
     double pw[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // g1 U^n + g0 X of cell p-1 (5), B1, B2 at p-1, B3 at p (carried)
     {
       const int q = g.c(gi, gj, p - 1), f = g.f(gi, gj, p - 1), f3 = g.f(gi, gj, p);
-      if (out_cell) {
+      if (SAME) {
+        // the same sums from the carried raw values of cell p-1 and the lower
+        // B3 of plane p (its look-ahead load)
+        if (out_cell) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) pw[v] = sa.cf.g1 * unc[v * g.cvar + q];
-        if (CARRY_PW) {
-          pw[5] = sa.cf.g1 * unb[f];
-          pw[6] = sa.cf.g1 * unb[g.fvar + f];
-        }
-        if (sa.cf.g0 != 0.0) {
+          for (int v = 0; v < 7; ++v) pw[v] = sa.cf.g1 * ucar[v];
+          if (sa.cf.g0 != 0.0) {
 #pragma unroll
-          for (int v = 0; v < 5; ++v) pw[v] += sa.cf.g0 * xc[v * g.cvar + q];
-          if (CARRY_PW) {
-            pw[5] += sa.cf.g0 * xb[f];
-            pw[6] += sa.cf.g0 * xb[g.fvar + f];
+            for (int v = 0; v < 7; ++v) pw[v] += sa.cf.g0 * ucar[v];
           }
         }
-      }
-      if (CARRY_PW && out_b3) {
-        pw[7] = sa.cf.g1 * unb[2 * g.fvar + f3];
-        if (sa.cf.g0 != 0.0) pw[7] += sa.cf.g0 * xb[2 * g.fvar + f3];
+        if (out_b3) {
+          pw[7] = sa.cf.g1 * bnq[0][2];
+          if (sa.cf.g0 != 0.0) pw[7] += sa.cf.g0 * bnq[0][2];
+        }
+#pragma unroll
+        for (int v = 0; v < 7; ++v) ucar[v] = unext[v];
+      } else {
+        if (out_cell) {
+#pragma unroll
+          for (int v = 0; v < 5; ++v) pw[v] = sa.cf.g1 * unc[v * g.cvar + q];
+          if (CARRY_PW) {
+            pw[5] = sa.cf.g1 * unb[f];
+            pw[6] = sa.cf.g1 * unb[g.fvar + f];
+          }
+          if (sa.cf.g0 != 0.0) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) pw[v] += sa.cf.g0 * xc[v * g.cvar + q];
+            if (CARRY_PW) {
+              pw[5] += sa.cf.g0 * xb[f];
+              pw[6] += sa.cf.g0 * xb[g.fvar + f];
+            }
+          }
+        }
+        if (CARRY_PW && out_b3) {
+          pw[7] = sa.cf.g1 * unb[2 * g.fvar + f3];
+          if (sa.cf.g0 != 0.0) pw[7] += sa.cf.g0 * xb[2 * g.fvar + f3];
+        }
       }
     }
     __syncthreads();
@@ -687,7 +720,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
 // Uniform blocks: one workgroup per (tile, x3 segment, block), XCD-aware:
 // consecutive logical tiles land on the same XCD so that halo overlap hits its
 // L2.
-template <int RECON, int RS, bool FL, bool MESH, bool MF>
+template <int RECON, int RS, bool FL, bool MESH, bool MF, bool SAME = false>
 __global__ void __launch_bounds__(TileU::NT) __attribute__((amdgpu_waves_per_eu(2)))
 k_stage_fused(UniformArgs a) {
   using T = TileU;
@@ -709,7 +742,7 @@ k_stage_fused(UniformArgs a) {
                MF ? a.fm + blk * 3 * g.fvar : nullptr};
   const int k0 = g.ng + seg * a.kz;
   const int kend = min(k0 + a.kz, g.ng + g.n3);
-  stage_tile<RECON, RS, T, FL, MESH, MF>(g, bp, a.sa, tile_x, tile_y, k0, kend, sp, sx, sc);
+  stage_tile<RECON, RS, T, FL, MESH, MF, SAME>(g, bp, a.sa, tile_x, tile_y, k0, kend, sp, sx, sc);
 }
 
 // Batched blocks of uneven sizes: a persistent grid whose workgroups pull
@@ -743,6 +776,16 @@ template <int RECON, int RS, bool MESH, bool MF>
 hipError_t launch_fl(const UniformArgs& fa, hipStream_t s) {
   const unsigned grid = (unsigned)(8 * fa.per_xcd);
   constexpr int NT = TileU::NT;
+  if constexpr (RECON == 0) {
+    // the first stage of a scheme reads U^n as its input: carry its raw cells
+    if (fa.xc == fa.unc && fa.xb == fa.unb) {
+      if (fa.sa.fl.on())
+        hipLaunchKernelGGL((k_stage_fused<RECON, RS, true, MESH, MF, true>), dim3(grid), dim3(NT), 0, s, fa);
+      else
+        hipLaunchKernelGGL((k_stage_fused<RECON, RS, false, MESH, MF, true>), dim3(grid), dim3(NT), 0, s, fa);
+      return hipGetLastError();
+    }
+  }
   if (fa.sa.fl.on()) hipLaunchKernelGGL((k_stage_fused<RECON, RS, true, MESH, MF>), dim3(grid), dim3(NT), 0, s, fa);
   else hipLaunchKernelGGL((k_stage_fused<RECON, RS, false, MESH, MF>), dim3(grid), dim3(NT), 0, s, fa);
   return hipGetLastError();
