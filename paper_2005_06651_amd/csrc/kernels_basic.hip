@@ -309,6 +309,61 @@ __global__ void __launch_bounds__(kThreads) k_newdt(Geo g, double gamma, Floors 
   dt_workgroup_end<PARTS>(best, nbad, dt_bits, bad, parts, (int64_t)blockIdx.y * gridDim.x + blockIdx.x);
 }
 
+// The same reduction as a march along x3: one thread per (i, j) column of a
+// 64 x 4 tile of columns, over a segment of kz planes.  A cell's upper B3 is
+// the next cell's lower B3, kept in a register, so each face is read from
+// memory once: 64 B per cell against the grid-stride loop's re-reads of the
+// upper x2 and x3 faces.  The upper faces are found as cell_field finds them.
+constexpr int kMarchX = 64, kMarchY = kThreads / kMarchX;
+__global__ void __launch_bounds__(kThreads) k_newdt_march(Geo g, double gamma, Floors fl,
+                                                         const double* __restrict__ cons,
+                                                         const double* __restrict__ bface, int ntx, int kz,
+                                                         unsigned long long* __restrict__ dt_bits,
+                                                         int* __restrict__ bad) {
+  const int b = blockIdx.z;
+  const int i = g.ng + (int)(blockIdx.x % ntx) * kMarchX + (int)(threadIdx.x % kMarchX);
+  const int j = g.ng + (int)(blockIdx.x / ntx) * kMarchY + (int)(threadIdx.x / kMarchX);
+  const int k0 = g.ng + (int)blockIdx.y * kz, kend = min(k0 + kz, g.ng + g.n3);
+  const double* u = cons + (int64_t)b * g.cblock;
+  const double* fb = bface + (int64_t)b * g.fblock;
+  double best = DBL_MAX;
+  int nbad = 0;
+  if (i < g.ng + g.n1 && j < g.ng + g.n2 && k0 < kend) {
+    // this column's upper x1 and x2 faces: the stored ones (a composite's
+    // blocks), the periodic image in the block, or the next block of a mesh
+    const double* p1 = fb;
+    const double* p2 = fb;
+    int iu = i + 1, ju = j + 1;
+    if (g.mesh[0] >= 0 && iu == g.ng + g.n1) {
+      iu = g.ng;
+      if (g.mesh[0]) p1 = bface + (int64_t)next_block<0>(g, b) * g.fblock;
+    }
+    if (g.mesh[0] >= 0 && ju == g.ng + g.n2) {
+      ju = g.ng;
+      if (g.mesh[0]) p2 = bface + (int64_t)next_block<1>(g, b) * g.fblock;
+    }
+    double b3lo = fb[2 * g.fvar + g.f(i, j, k0)];
+    for (int k = k0; k < kend; ++k) {
+      const double* p3 = fb;
+      int ku = k + 1;
+      if (g.mesh[0] >= 0 && ku == g.ng + g.n3) {
+        ku = g.ng;
+        if (g.mesh[0]) p3 = bface + (int64_t)next_block<2>(g, b) * g.fblock;
+      }
+      const int q = g.c(i, j, k), f = g.f(i, j, k);
+      const double uc[5] = {u[q], u[g.cvar + q], u[2 * g.cvar + q], u[3 * g.cvar + q], u[4 * g.cvar + q]};
+      const double b3hi = p3[2 * g.fvar + g.f(i, j, ku)];
+      const double bc[3] = {0.5 * (fb[f] + p1[g.f(iu, j, k)]), 0.5 * (fb[g.fvar + f] + p2[g.fvar + g.f(i, ju, k)]),
+                            0.5 * (b3lo + b3hi)};
+      double d;
+      if (cfl_cell(uc, bc, gamma, fl, g.dx1, g.dx2, g.dx3, d)) best = fmin(best, d);
+      else ++nbad;
+      b3lo = b3hi;
+    }
+  }
+  dt_workgroup_end<false>(best, nbad, dt_bits, bad, nullptr, 0);
+}
+
 // Floors on the conserved state after a stage (floors enabled only): density
 // below the floor is raised to it, and where the pressure implied by (U, B)
 // is below the pressure floor the total energy is raised to give exactly that
@@ -597,13 +652,16 @@ hipError_t launch_prim2cons(const Geo& g, double gamma, const double* prim, cons
 
 hipError_t launch_newdt(const Geo& g, double gamma, const double* cons, const double* bface, int nb,
                         unsigned long long* dt_bits, const Floors& fl, int* bad, hipStream_t s) {
-  const int64_t nact = (int64_t)g.n1 * g.n2 * g.n3;
-  // about kDtBlocks workgroups in all, so that many small blocks do not
-  // queue tens of thousands of atomics on the one result word
-  const int64_t per_block = std::max<int64_t>(1, kDtBlocks / std::max(nb, 1));
-  const unsigned blocks = (unsigned)std::min<int64_t>(grid_for(nact), per_block);
-  hipLaunchKernelGGL(k_newdt<false>, dim3(blocks, nb), dim3(kThreads), 0, s, g, gamma, fl, cons, bface, dt_bits, bad,
-                     nullptr);
+  // x3 segments: about 2 kDtBlocks workgroups in all (enough to fill the chip,
+  // few enough atomics on the one result word), at least 8 planes each
+  const int ntx = (g.n1 + kMarchX - 1) / kMarchX, nty = (g.n2 + kMarchY - 1) / kMarchY;
+  const int64_t tiles = (int64_t)ntx * nty * std::max(nb, 1);
+  const int64_t want = (2 * kDtBlocks + tiles - 1) / tiles;
+  const int nseg0 = (int)std::max<int64_t>(1, std::min<int64_t>(want, std::max(1, g.n3 / 8)));
+  const int kz = (g.n3 + nseg0 - 1) / nseg0;
+  const int nseg = (g.n3 + kz - 1) / kz;
+  hipLaunchKernelGGL(k_newdt_march, dim3((unsigned)(ntx * nty), (unsigned)nseg, (unsigned)nb), dim3(kThreads), 0, s,
+                     g, gamma, fl, cons, bface, ntx, kz, dt_bits, bad);
   return hipGetLastError();
 }
 
