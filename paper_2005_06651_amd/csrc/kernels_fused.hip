@@ -377,7 +377,7 @@ __device__ __forceinline__ void stage_tile(const Geo& g, const BlockPtrs& bp, co
   // face update elsewhere, where registers are scarcer (PPM's window, the
   // batch tiles): measured 0.9 % faster carried on the uniform PLM stage,
   // 5.6 % (PPM) and 3.5 % (batch) faster read
-  constexpr bool CARRY_PW = LA < 2 && NT == TileU::NT;
+  constexpr bool CARRY_PW = (LA < 2 && NT == TileU::NT) || SAME;
   static_assert(!SAME || LA == 0, "the raw cell of the output plane is carried with the donor-cell window only");
   // SAME: conserved state and lower B1, B2 of the previous plane's cell, and
   // of the current plane's (from its look-ahead load, until the output step)
@@ -747,7 +747,7 @@ k_stage_fused(UniformArgs a) {
 
 // Batched blocks of uneven sizes: a persistent grid whose workgroups pull
 // (block, tile, x3 segment) items from a device queue until it is drained.
-template <int RECON, int RS, class T, bool FL, bool MF>
+template <int RECON, int RS, class T, bool FL, bool MF, bool SAME = false>
 __global__ void __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(2))) k_stage_batch(BatchArgs a) {
   using S = Smem<RECON, T>;
   __shared__ double sp[8 * S::PL];
@@ -764,7 +764,7 @@ __global__ void __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(2)))
     const BatchDesc& d = a.desc[w.block];
     BlockPtrs bp{a.xc + d.coff, a.xb + d.foff, a.unc + d.coff, a.unb + d.foff, a.oc + d.coff, a.ob + d.foff,
                  MF ? a.fm + d.foff : nullptr};
-    stage_tile<RECON, RS, T, FL, false, MF>(d.g, bp, a.sa, w.tile_x, w.tile_y, w.k0, w.kend, sp, sx, sc);
+    stage_tile<RECON, RS, T, FL, false, MF, SAME>(d.g, bp, a.sa, w.tile_x, w.tile_y, w.k0, w.kend, sp, sx, sc);
     __syncthreads();
   }
 }
@@ -809,14 +809,27 @@ __global__ void k_zero_u32(unsigned* p) {
   if (threadIdx.x == 0) *p = 0u;
 }
 
+template <class T, int RECON, bool MF, bool SAME>
+hipError_t launch_batch_s(int rs, const BatchArgs& ba, int grid, hipStream_t s) {
+  const bool fl = ba.sa.fl.on();
+  if (rs == 1 && fl)
+    hipLaunchKernelGGL((k_stage_batch<RECON, 1, T, true, MF, SAME>), dim3(grid), dim3(T::NT), 0, s, ba);
+  else if (rs == 1)
+    hipLaunchKernelGGL((k_stage_batch<RECON, 1, T, false, MF, SAME>), dim3(grid), dim3(T::NT), 0, s, ba);
+  else if (fl)
+    hipLaunchKernelGGL((k_stage_batch<RECON, 0, T, true, MF, SAME>), dim3(grid), dim3(T::NT), 0, s, ba);
+  else
+    hipLaunchKernelGGL((k_stage_batch<RECON, 0, T, false, MF, SAME>), dim3(grid), dim3(T::NT), 0, s, ba);
+  return hipGetLastError();
+}
+
 template <class T, int RECON, bool MF>
 hipError_t launch_batch_m(int rs, const BatchArgs& ba, int grid, hipStream_t s) {
-  const bool fl = ba.sa.fl.on();
-  if (rs == 1 && fl) hipLaunchKernelGGL((k_stage_batch<RECON, 1, T, true, MF>), dim3(grid), dim3(T::NT), 0, s, ba);
-  else if (rs == 1) hipLaunchKernelGGL((k_stage_batch<RECON, 1, T, false, MF>), dim3(grid), dim3(T::NT), 0, s, ba);
-  else if (fl) hipLaunchKernelGGL((k_stage_batch<RECON, 0, T, true, MF>), dim3(grid), dim3(T::NT), 0, s, ba);
-  else hipLaunchKernelGGL((k_stage_batch<RECON, 0, T, false, MF>), dim3(grid), dim3(T::NT), 0, s, ba);
-  return hipGetLastError();
+  // the first stage of a scheme reads U^n as its input: carry its raw cells
+  if constexpr (RECON == 0) {
+    if (ba.xc == ba.unc && ba.xb == ba.unb) return launch_batch_s<T, RECON, MF, true>(rs, ba, grid, s);
+  }
+  return launch_batch_s<T, RECON, MF, false>(rs, ba, grid, s);
 }
 
 template <class T, int RECON>
