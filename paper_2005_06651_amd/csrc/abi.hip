@@ -372,9 +372,10 @@ hipError_t levels_stage(athmhd_t h, int recon, const double* xc, const double* x
 }
 
 // The CFL minimum of a state folded into bits (atomic minimum of the bit
-// patterns of non-negative doubles).
+// patterns of non-negative doubles).  floor: the floors of the last stage
+// are applied in the same pass (uniform and mesh handles).
 hipError_t launch_cfl(athmhd_t h, const double* cons, const double* bface, int nblocks, unsigned long long* bits,
-                      hipStream_t s) {
+                      hipStream_t s, bool floor = false) {
   if (h->levels) {
     hipError_t e = launch_newdt(h->g, h->cfg.gamma, cons, bface, 1, bits, h->floors, h->d_bad, s);
     if (e != hipSuccess) return e;
@@ -383,7 +384,7 @@ hipError_t launch_cfl(athmhd_t h, const double* cons, const double* bface, int n
   }
   if (h->batch) return launch_newdt_batch(h->d_desc, h->nbatch, 0, h->cfg.gamma, cons, bface, bits, h->floors,
                                           h->d_bad, s);
-  return launch_newdt(h->g, h->cfg.gamma, cons, bface, nblocks, bits, h->floors, h->d_bad, s);
+  return launch_newdt(h->g, h->cfg.gamma, cons, bface, nblocks, bits, h->floors, h->d_bad, s, floor);
 }
 
 // x3 planes per workgroup of the fused stage kernel on nblocks uniform blocks
@@ -422,6 +423,9 @@ hipError_t fill_ghosts(athmhd_t h, double* cons, double* bface, int nblocks, hip
 // state is folded into it after the step.
 int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const double* dt_dev, int nblocks,
                  hipStream_t s, double* stages = nullptr, unsigned long long* dt_bits = nullptr) {
+  // a chained step with floors on a uniform or mesh handle floors its last
+  // stage's output in the CFL pass, which reads the whole state anyway
+  const bool floor_in_cfl = dt_bits && h->floors.on() && !h->batch && !h->levels;
   const Scheme sc = scheme_of(h->cfg.integrator);
   const double* xc = cons;
   const double* xb = bface;
@@ -479,7 +483,7 @@ int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const doubl
                                          h->floors, s);
       if (e != hipSuccess) return hip_fail(h, e, "scalar stage launch");
     }
-    if (h->floors.on()) {
+    if (h->floors.on() && !(last && floor_in_cfl)) {
       e = h->batch ? launch_floor_state_batch(h->d_desc, h->nbatch, h->cfg.gamma, h->floors, oc, ob, h->d_bad, s)
                    : launch_floor_state(h->g, h->cfg.gamma, h->floors, oc, ob, nblocks, h->d_bad, s);
       if (e != hipSuccess) return hip_fail(h, e, "floor launch");
@@ -494,7 +498,7 @@ int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const doubl
   // a composite leaves its ghosts and restricted coarse faces filled, which
   // its newdt reads
   if (h->levels && (e = levels_ghosts(h, cons, bface, s)) != hipSuccess) return hip_fail(h, e, "level ghost launch");
-  if (dt_bits && (e = launch_cfl(h, cons, bface, nblocks, dt_bits, s)) != hipSuccess)
+  if (dt_bits && (e = launch_cfl(h, cons, bface, nblocks, dt_bits, s, floor_in_cfl)) != hipSuccess)
     return hip_fail(h, e, "newdt launch");
   return ATHMHD_OK;
 }

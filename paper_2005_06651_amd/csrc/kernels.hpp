@@ -41,7 +41,9 @@ hipError_t launch_prim2cons(const Geo& g, double gamma, const double* prim, cons
 // dt_bits: device uint64 holding the bit pattern of the running minimum of
 // dx_d/(|v_d| + c_f) (initialise to +inf bits); bad: device int counter
 hipError_t launch_newdt(const Geo& g, double gamma, const double* cons, const double* bface, int nb,
-                        unsigned long long* dt_bits, const Floors& fl, int* bad, hipStream_t s);
+                        unsigned long long* dt_bits, const Floors& fl, int* bad, hipStream_t s, bool floor = false);
+// (floor: apply the floors of launch_floor_state to cons first, in the same
+// pass; floors must be on)
 
 // The same CFL reduction in two launches that use no atomics and need no
 // cleared memory: one partial result per workgroup (minimum of

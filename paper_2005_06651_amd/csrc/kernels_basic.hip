@@ -309,14 +309,38 @@ __global__ void __launch_bounds__(kThreads) k_newdt(Geo g, double gamma, Floors 
   dt_workgroup_end<PARTS>(best, nbad, dt_bits, bad, parts, (int64_t)blockIdx.y * gridDim.x + blockIdx.x);
 }
 
+// The floors on the values of one cell: uc = (rho, M1, M2, M3, E), b its
+// cell-centred field; raises rho to the density floor and E so that the
+// pressure is the pressure floor.  Bit 0: rho changed, bit 1: E changed.
+__device__ __forceinline__ int floor_values(double gm1, const Floors& fl, double* uc, const double* b) {
+  int hit = 0;
+  if (!(uc[0] >= fl.d)) {
+    uc[0] = fl.d;
+    hit = 1;
+  }
+  const double rho = uc[0];
+  const double m1 = uc[1], m2 = uc[2], m3 = uc[3];
+  const double kin = 0.5 * (m1 * m1 + m2 * m2 + m3 * m3) / rho;
+  const double mag = 0.5 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+  const double p = gm1 * (uc[4] - kin - mag);
+  if (!(p >= fl.p)) {
+    uc[4] = fl.p / gm1 + kin + mag;
+    hit |= 2;
+  }
+  return hit;
+}
+
 // The same reduction as a march along x3: one thread per (i, j) column of a
 // 64 x 4 tile of columns, over a segment of kz planes.  A cell's upper B3 is
 // the next cell's lower B3, kept in a register, so each face is read from
 // memory once: 64 B per cell against the grid-stride loop's re-reads of the
 // upper x2 and x3 faces.  The upper faces are found as cell_field finds them.
+// FLOOR: apply the floors of k_floor_state to each cell first, writing the
+// cells they change, so that the pass that ends a step with floors reads the
+// state once for both.
 constexpr int kMarchX = 64, kMarchY = kThreads / kMarchX;
-__global__ void __launch_bounds__(kThreads) k_newdt_march(Geo g, double gamma, Floors fl,
-                                                         const double* __restrict__ cons,
+template <bool FLOOR>
+__global__ void __launch_bounds__(kThreads) k_newdt_march(Geo g, double gamma, Floors fl, double* __restrict__ cons,
                                                          const double* __restrict__ bface, int ntx, int kz,
                                                          unsigned long long* __restrict__ dt_bits,
                                                          int* __restrict__ bad) {
@@ -324,10 +348,10 @@ __global__ void __launch_bounds__(kThreads) k_newdt_march(Geo g, double gamma, F
   const int i = g.ng + (int)(blockIdx.x % ntx) * kMarchX + (int)(threadIdx.x % kMarchX);
   const int j = g.ng + (int)(blockIdx.x / ntx) * kMarchY + (int)(threadIdx.x / kMarchX);
   const int k0 = g.ng + (int)blockIdx.y * kz, kend = min(k0 + kz, g.ng + g.n3);
-  const double* u = cons + (int64_t)b * g.cblock;
+  double* u = cons + (int64_t)b * g.cblock;
   const double* fb = bface + (int64_t)b * g.fblock;
   double best = DBL_MAX;
-  int nbad = 0;
+  int nbad = 0, nfloor = 0;
   if (i < g.ng + g.n1 && j < g.ng + g.n2 && k0 < kend) {
     // this column's upper x1 and x2 faces: the stored ones (a composite's
     // blocks), the periodic image in the block, or the next block of a mesh
@@ -351,16 +375,23 @@ __global__ void __launch_bounds__(kThreads) k_newdt_march(Geo g, double gamma, F
         if (g.mesh[0]) p3 = bface + (int64_t)next_block<2>(g, b) * g.fblock;
       }
       const int q = g.c(i, j, k), f = g.f(i, j, k);
-      const double uc[5] = {u[q], u[g.cvar + q], u[2 * g.cvar + q], u[3 * g.cvar + q], u[4 * g.cvar + q]};
+      double uc[5] = {u[q], u[g.cvar + q], u[2 * g.cvar + q], u[3 * g.cvar + q], u[4 * g.cvar + q]};
       const double b3hi = p3[2 * g.fvar + g.f(i, j, ku)];
       const double bc[3] = {0.5 * (fb[f] + p1[g.f(iu, j, k)]), 0.5 * (fb[g.fvar + f] + p2[g.fvar + g.f(i, ju, k)]),
                             0.5 * (b3lo + b3hi)};
+      if (FLOOR) {
+        const int hit = floor_values(gamma - 1.0, fl, uc, bc);
+        if (hit & 1) u[q] = uc[0];
+        if (hit & 2) u[4 * g.cvar + q] = uc[4];
+        nfloor += hit != 0;
+      }
       double d;
       if (cfl_cell(uc, bc, gamma, fl, g.dx1, g.dx2, g.dx3, d)) best = fmin(best, d);
       else ++nbad;
       b3lo = b3hi;
     }
   }
+  if (FLOOR && nfloor) add_floor_count(bad, (unsigned long long)nfloor);
   dt_workgroup_end<false>(best, nbad, dt_bits, bad, nullptr, 0);
 }
 
@@ -372,24 +403,13 @@ __global__ void __launch_bounds__(kThreads) k_newdt_march(Geo g, double gamma, F
 __device__ __forceinline__ int floor_cell(const Geo& g, double gm1, const Floors& fl, double* u,
                                           const double* fb, const double* all_fb, int b, int i, int j, int k) {
   const int q = g.c(i, j, k);
-  double b1, b2, b3;
-  cell_field(g, fb, all_fb, b, i, j, k, b1, b2, b3);
-  int hit = 0;
-  double rho = u[q];
-  if (!(rho >= fl.d)) {
-    rho = fl.d;
-    u[q] = rho;
-    hit = 1;
-  }
-  const double m1 = u[g.cvar + q], m2 = u[2 * g.cvar + q], m3 = u[3 * g.cvar + q];
-  const double kin = 0.5 * (m1 * m1 + m2 * m2 + m3 * m3) / rho;
-  const double mag = 0.5 * (b1 * b1 + b2 * b2 + b3 * b3);
-  const double p = gm1 * (u[4 * g.cvar + q] - kin - mag);
-  if (!(p >= fl.p)) {
-    u[4 * g.cvar + q] = fl.p / gm1 + kin + mag;
-    hit = 1;
-  }
-  return hit;
+  double bc[3];
+  cell_field(g, fb, all_fb, b, i, j, k, bc[0], bc[1], bc[2]);
+  double uc[5] = {u[q], u[g.cvar + q], u[2 * g.cvar + q], u[3 * g.cvar + q], u[4 * g.cvar + q]};
+  const int hit = floor_values(gm1, fl, uc, bc);
+  if (hit & 1) u[q] = uc[0];
+  if (hit & 2) u[4 * g.cvar + q] = uc[4];
+  return hit != 0;
 }
 
 __global__ void __launch_bounds__(kThreads) k_floor_state(Geo g, double gm1, Floors fl, double* __restrict__ cons,
@@ -651,7 +671,7 @@ hipError_t launch_prim2cons(const Geo& g, double gamma, const double* prim, cons
 }
 
 hipError_t launch_newdt(const Geo& g, double gamma, const double* cons, const double* bface, int nb,
-                        unsigned long long* dt_bits, const Floors& fl, int* bad, hipStream_t s) {
+                        unsigned long long* dt_bits, const Floors& fl, int* bad, hipStream_t s, bool floor) {
   // x3 segments: about 2 kDtBlocks workgroups in all (enough to fill the chip,
   // few enough atomics on the one result word), at least 8 planes each
   const int ntx = (g.n1 + kMarchX - 1) / kMarchX, nty = (g.n2 + kMarchY - 1) / kMarchY;
@@ -660,8 +680,13 @@ hipError_t launch_newdt(const Geo& g, double gamma, const double* cons, const do
   const int nseg0 = (int)std::max<int64_t>(1, std::min<int64_t>(want, std::max(1, g.n3 / 8)));
   const int kz = (g.n3 + nseg0 - 1) / nseg0;
   const int nseg = (g.n3 + kz - 1) / kz;
-  hipLaunchKernelGGL(k_newdt_march, dim3((unsigned)(ntx * nty), (unsigned)nseg, (unsigned)nb), dim3(kThreads), 0, s,
-                     g, gamma, fl, cons, bface, ntx, kz, dt_bits, bad);
+  const dim3 grid((unsigned)(ntx * nty), (unsigned)nseg, (unsigned)nb);
+  if (floor)
+    hipLaunchKernelGGL(k_newdt_march<true>, grid, dim3(kThreads), 0, s, g, gamma, fl, const_cast<double*>(cons), bface,
+                       ntx, kz, dt_bits, bad);
+  else
+    hipLaunchKernelGGL(k_newdt_march<false>, grid, dim3(kThreads), 0, s, g, gamma, fl, const_cast<double*>(cons),
+                       bface, ntx, kz, dt_bits, bad);
   return hipGetLastError();
 }
 

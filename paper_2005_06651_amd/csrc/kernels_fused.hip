@@ -849,8 +849,11 @@ hipError_t launch_batch_recon(int recon, int rs, const BatchArgs& ba, int grid, 
 int fused_default_kz(const Geo& g, int nb, int cus) {
   // the longest x3 segment (32 planes down to 4) that still gives the launch
   // at least 2.5 workgroups per CU: longer segments repeat less of the
-  // window start-up, more segments fill the chip on small blocks
+  // window start-up, more segments fill the chip on small blocks.  64 planes
+  // where that still leaves 16 workgroups per CU (512^3: 0.9 % faster with
+  // PPM; 256^3, with 2.5 per CU, 12 % slower)
   const int64_t tiles = (int64_t)((g.n1 + TileU::TX - 1) / TileU::TX) * ((g.n2 + TileU::TY - 1) / TileU::TY) * nb;
+  if (tiles * ((g.n3 + 63) / 64) >= 16 * (int64_t)cus) return 64 < g.n3 ? 64 : g.n3;
   int kz = 32;
   while (kz > 4 && 2 * tiles * ((g.n3 + kz - 1) / kz) < 5 * (int64_t)cus) kz /= 2;
   return kz < g.n3 ? kz : g.n3;
