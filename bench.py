@@ -38,14 +38,14 @@ ALG_FLOPS_PER_ZONE_CYCLE = 2560.0
 # on this workload, scaled by the counters of a plain 1 GiB copy, and the hash
 # of the stage-kernel sources they were measured on (traffic is reported only
 # while the sources are unchanged).
-STAGE_TRAFFIC = {"bytes_per_launch": 3.511e+09, "fetch_bytes_per_launch": 2.321e+09,
-                 "write_bytes_per_launch": 1.190e+09, "fetch_scale": 1.9999, "write_scale": 1.0000,
-                 "source_hash": "070f8df4dc5fe766"}
+STAGE_TRAFFIC = {"bytes_per_launch": 2.979e+09, "fetch_bytes_per_launch": 1.858e+09,
+                 "write_bytes_per_launch": 1.120e+09, "fetch_scale": 1.9999, "write_scale": 1.0000,
+                 "source_hash": "87ecf36491536450"}
 # FP64 VALU issue of the same stage launches (rocprofv3 SQ_INSTS_VALU per
 # launch over 256 CUs x 2.4 GHz x the launch duration, mean of the DC and PLM
 # stages) and the stage time those launches took under the profiler: with the
 # traffic above they say which roof binds (the larger measured fraction).
-STAGE_ISSUE = {"valu_issue_frac": 0.492, "profiled_ms_per_launch": 1.7647, "source_hash": "070f8df4dc5fe766"}
+STAGE_ISSUE = {"valu_issue_frac": 0.515, "profiled_ms_per_launch": 1.6658, "source_hash": "87ecf36491536450"}
 HBM_FRAC_TARGET = 0.60       # the HBM-roofline fraction the stage kernel is measured against
 # The same for the level operators on the 256^3 block (per octant launch).
 LEVELS_SOURCES = ("kernels_amr.hip", "common.hpp")
@@ -89,6 +89,10 @@ def parse():
     p.add_argument("--levels-n", type=int, default=256, help="levels: cells per side of the block")
     p.add_argument("--mesh-blocks", type=int, default=8, help="mesh: blocks per direction of the 256^3 domain")
     p.add_argument("--no-tune", action="store_true", help="batch: keep the default tile instead of autotuning")
+    p.add_argument("--coupled", action="store_true",
+                   help="batch: cubes of 16^3, 24^3 and 32^3 in x3 slabs tiling one 192x192x384 periodic domain at "
+                        "one cell width, exchanging their ghost entries (instead of the octree-shaped blocks that "
+                        "are each their own periodic neighbour)")
     p.add_argument("--graph", action="store_true", help="replay each step from a hipGraph")
     p.add_argument("--charac", action="store_true",
                    help="turbulence: PLM on characteristic variables (runs the unfused pipeline)")
@@ -206,21 +210,43 @@ def bench_batch(args):
     from paper_2005_06651_amd import athmhd, inputs
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    blocks = inputs.amr_batch(1024, seed=args.seed)
     ns = args.scalars
-    if ns > 0:
-        blocks = [inputs.with_scalars(b, ns, seed=args.seed + 100 + i) for i, b in enumerate(blocks)]
-    s = athmhd.BatchSolver([b.n for b in blocks], [b.dx for b in blocks], 2, blocks[0].gamma, recon="plm",
-                           riemann="hlld", integrator="vl2", cfl=0.3, nscalars=ns)
-    tb = torch.from_numpy(inputs.pack([b.bface for b in blocks])).to(dev)
-    tc = s.prim2cons(torch.from_numpy(inputs.pack([b.prim for b in blocks])).to(dev), tb)
+    if args.coupled:
+        if ns > 0:
+            raise SystemExit("--coupled takes no passive scalars")
+        dims, origins, domain = inputs.brick_layout(inputs.brick_slabs(seed=args.seed), 192)
+        dom = inputs.smooth_random(n=domain, seed=args.seed, ng=2)
+        pcs, fcs = inputs.split_boxes(dom.prim, dom.bface, 2, dims, origins)
+        s = athmhd.BatchSolver(dims, [dom.dx] * len(dims), 2, dom.gamma, recon="plm", riemann="hlld",
+                               integrator="vl2", cfl=0.3)
+        s.couple(origins, domain)
+        tb = torch.from_numpy(inputs.pack(fcs)).to(dev)
+        tc = s.prim2cons(torch.from_numpy(inputs.pack(pcs)).to(dev), tb)
+        s.fill_ghosts(tc, tb)
+        del dom, pcs, fcs
+        sizes = {n: sum(1 for d in dims if d[0] == n) for n in sorted({d[0] for d in dims})}
+        zones = sum(d[0] * d[1] * d[2] for d in dims)
+        workload = (f"{len(dims)} cube blocks ({', '.join(f'{c}x{n}^3' for n, c in sizes.items())}, nghost 2) in "
+                    f"x3 slabs tiling one {domain[0]}x{domain[1]}x{domain[2]} periodic domain at one cell width, "
+                    f"ghost entries exchanged between neighbours before every stage and after the last, one "
+                    f"smooth seeded state, VL2+PLM+HLLD+CT, CFL 0.3")
+    else:
+        blocks = inputs.amr_batch(1024, seed=args.seed)
+        if ns > 0:
+            blocks = [inputs.with_scalars(b, ns, seed=args.seed + 100 + i) for i, b in enumerate(blocks)]
+        s = athmhd.BatchSolver([b.n for b in blocks], [b.dx for b in blocks], 2, blocks[0].gamma, recon="plm",
+                               riemann="hlld", integrator="vl2", cfl=0.3, nscalars=ns)
+        tb = torch.from_numpy(inputs.pack([b.bface for b in blocks])).to(dev)
+        tc = s.prim2cons(torch.from_numpy(inputs.pack([b.prim for b in blocks])).to(dev), tb)
+        zones = sum(b.n[0] * b.n[1] * b.n[2] for b in blocks)
+        workload = ("1024 AMR-shaped blocks (410x16^3, 410x24^3, 204x32^3, nghost 2) of a seeded 2:1-balanced "
+                    "octree, smooth periodic states, VL2+PLM+HLLD+CT, CFL 0.3")
     stream = torch.cuda.Stream() if args.graph else torch.cuda.current_stream()
     tuned = None
     if not args.no_tune:
         tuned = s.tune(tc, tb, stream=stream)
     if args.graph:
         s.set_graph(True)
-    zones = sum(b.n[0] * b.n[1] * b.n[2] for b in blocks)
     with torch.cuda.stream(stream):
         # eager: chained steps (dt stays on the device); graph mode replays
         # athmhd_step with the dt of newdt
@@ -246,13 +272,11 @@ def bench_batch(args):
         s.newdt(tc, tb, stream=stream)  # raises if any step met a non-physical cell
     out = {
         "metric": "zone-cycles/s, FP64 3D MHD VL2+PLM+HLLD, 1 MI355X, batched uneven blocks"
-                  + (f", with {ns} passive scalar(s)" if ns else ""),
+                  + (", coupled" if args.coupled else "") + (f", with {ns} passive scalar(s)" if ns else ""),
         "value": zones * args.steps / elapsed, "unit": "zone-cycles/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "1024 AMR-shaped blocks (410x16^3, 410x24^3, 204x32^3, nghost 2) of a seeded "
-                               "2:1-balanced octree, smooth periodic states, VL2+PLM+HLLD+CT, CFL 0.3",
-                   "cells": zones, "tile": None if tuned is None else {"shape": athmhd.BATCH_TILES[tuned[0]],
+        "config": {"workload": workload, "cells": zones, "coupled": bool(args.coupled), "tile": None if tuned is None else {"shape": athmhd.BATCH_TILES[tuned[0]],
                                                                         "split": tuned[1]},
                    "graph": bool(args.graph), "nscalars": ns},
         "stage_ms_per_launch": stage_ms / max(launches, 1) if launches else None,

@@ -312,6 +312,29 @@ ATHMHD_API int athmhd_create_batch(const athmhd_config* base, const int32_t* dim
  * handle and, if offsets is not NULL, the per-block offsets (2 per block). */
 ATHMHD_API int athmhd_batch_info(athmhd_t h, int64_t* cons_len, int64_t* bface_len, int64_t* offsets);
 
+/* Couple a batch into one periodic mesh of blocks of uneven sizes and a
+ * single cell width (Sec. 2.1: a Mesh of MeshBlocks; Sec. 2.1.1: neighbouring
+ * blocks exchange ghost cells and faces).  origin[3b..3b+2] is the position,
+ * in cells of the domain, of block b's first active cell (x1 first); the
+ * blocks must tile the domain[0] x domain[1] x domain[2] cells exactly, each
+ * inside it, with equal dx1..dx3 (else ATHMHD_EINVAL).  Neighbours may
+ * differ in size: a block's ghost entries can come from several blocks.
+ *   - The library builds, on the host, a table naming for every shell entry
+ *     of every block (ghost cells, and every face entry other than the lower
+ *     faces of its active cells) the block that owns the same cell of the
+ *     domain, and uploads it (8 bytes per entry; the handle owns it).
+ *   - athmhd_step and athmhd_step_chain then exchange the shell entries by
+ *     that table before every stage (a device gather kernel) and once more
+ *     after the last, so every face is updated by exactly one block and the
+ *     stored state is whole after a step; athmhd_newdt and athmhd_prim2cons
+ *     read a block's upper faces from its own shell.  athmhd_fill_ghosts
+ *     runs the same exchange.
+ *   - Split into blocks, the result equals one periodic block covering the
+ *     whole domain.
+ * Not with passive scalars or floors (ATHMHD_EUNSUP; athmhd_set_floors on a
+ * coupled batch likewise); calling it twice is ATHMHD_EINVAL. */
+ATHMHD_API int athmhd_batch_couple(athmhd_t h, const int32_t* origin, const int32_t* domain);
+
 /* Choose the thread tile of the batched stage kernel: shape indexes the
  * candidate tiles (0: 16x12, 1: 12x16, 2: 14x14, 3: 16x8 active columns) and
  * split = 1 halves the x3 extent of each work item. */

@@ -24,7 +24,7 @@ EXPORTED = ["athmhd_version", "athmhd_create", "athmhd_create_batch", "athmhd_ba
             "athmhd_step_vjp", "athmhd_prim2cons_vjp", "athmhd_set_floors", "athmhd_floor_count",
             "athmhd_step_stages", "athmhd_create_mesh", "athmhd_restrict", "athmhd_prolong",
             "athmhd_restrict_box", "athmhd_prolong_box", "athmhd_newdt_noalloc", "athmhd_create_levels",
-            "athmhd_step_chain"]
+            "athmhd_step_chain", "athmhd_batch_couple"]
 BATCH_TILES = [(16, 12), (12, 16), (14, 14), (16, 8)]  # active columns of the batch tile candidates
 
 
@@ -66,6 +66,7 @@ def lib():
                                           C.POINTER(vp)]
         L.athmhd_batch_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.athmhd_batch_set_tile.argtypes = [vp, C.c_int, C.c_int]
+        L.athmhd_batch_couple.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.athmhd_batch_tune.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                         C.POINTER(C.c_double)]
         L.athmhd_set_graph.argtypes = [vp, C.c_int]
@@ -497,6 +498,18 @@ class BatchSolver:
     def fill_ghosts(self, cons, bface, stream=None) -> None:
         pc, pb = self._pair(cons, bface)
         _check(lib().athmhd_fill_ghosts(self._h, pc, pb, self.nblocks, _stream(stream)), self._h)
+
+    def couple(self, origins, domain) -> None:
+        """Make the blocks one periodic mesh: origins[b] is block b's first
+        active cell in the domain of domain[0] x domain[1] x domain[2] cells
+        (x1 first), which the blocks must tile exactly."""
+        import numpy as np
+        o = np.ascontiguousarray(np.array(origins, dtype=np.int32).reshape(-1))
+        d = np.ascontiguousarray(np.array(domain, dtype=np.int32).reshape(3))
+        if o.size != 3 * self.nblocks:
+            raise ValueError(f"expected {self.nblocks} origins")
+        _check(lib().athmhd_batch_couple(self._h, o.ctypes.data_as(C.POINTER(C.c_int32)),
+                                         d.ctypes.data_as(C.POINTER(C.c_int32))), self._h)
 
     def set_tile(self, shape: int, split: int = 0) -> None:
         _check(lib().athmhd_batch_set_tile(self._h, int(shape), int(split)), self._h)

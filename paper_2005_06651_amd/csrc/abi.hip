@@ -47,6 +47,11 @@ struct athmhd_s {
   int nitems = 0, items_cap = 0;
   unsigned* d_queue = nullptr;
   int shape = 0, split = 0, grid = 0;   // batch tile candidate, x3 split, persistent grid
+  // coupled batch (athmhd_batch_couple): the blocks tile one periodic domain
+  // and exchange their shell entries by table (k_exchange_batch)
+  bool coupled = false;
+  int64_t* d_xoff = nullptr;  // per block: first table entry of its shell
+  int2* d_xsrc = nullptr;     // per shell entry: owner block, packed stored position
   // state registers and scratch
   double* reg[2] = {nullptr, nullptr};  // two stage registers (cons followed by bface)
   int64_t reg_coff = 0;                  // offset of bface inside a register
@@ -242,6 +247,8 @@ void free_all(athmhd_t h) {
   if (h->d_desc) (void)hipFree(h->d_desc);
   if (h->d_items) (void)hipFree(h->d_items);
   if (h->d_queue) (void)hipFree(h->d_queue);
+  if (h->d_xoff) (void)hipFree(h->d_xoff);
+  if (h->d_xsrc) (void)hipFree(h->d_xsrc);
   if (h->h_pinned) (void)hipHostFree(h->h_pinned);
   if (h->adj_base) (void)hipFree(h->adj_base);
 }
@@ -398,7 +405,7 @@ hipError_t launch_stage(athmhd_t h, int recon, const double* xc, const double* x
   if (h->batch)
     return launch_stage_batch(h->shape, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, h->d_desc, h->d_items,
                               h->nitems, h->d_queue, xc, xb, unc, unb, oc, ob, cf, dt_dev, beta, h->grid, h->floors,
-                              h->d_bad, h->g.ns > 0 ? h->d_fm : nullptr, s);
+                              h->d_bad, h->g.ns > 0 ? h->d_fm : nullptr, s, h->coupled);
   if (!h->unfused)
     return launch_stage_fused(h->g, h->cfg.gamma, recon, h->cfg.riemann, h->cfg.ct_eps, xc, xb, unc, unb, oc, ob, cf,
                               dt_dev, beta, nblocks, stage_kz(h, nblocks), h->floors, h->d_bad,
@@ -410,6 +417,8 @@ hipError_t launch_stage(athmhd_t h, int recon, const double* xc, const double* x
 // depth: ghost layers a mesh exchange fills (0: all); other handles fill all
 hipError_t fill_ghosts(athmhd_t h, double* cons, double* bface, int nblocks, hipStream_t s, int depth = 0) {
   if (h->levels) return levels_ghosts(h, cons, bface, s);
+  if (h->batch && h->coupled)
+    return launch_exchange_batch(h->d_desc, h->nbatch, h->max_shell, h->d_xoff, h->d_xsrc, cons, bface, s);
   if (h->batch) return launch_fill_ghosts_batch(h->d_desc, h->nbatch, h->max_shell, cons, bface, s);
   if (h->mesh) return launch_mesh_ghosts(h->g, depth, cons, bface, s);
   return launch_fill_ghosts(h->g, cons, bface, nblocks, s);
@@ -431,9 +440,9 @@ int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const doubl
   const double* xb = bface;
   hipError_t e;
   // the fused kernels read periodic images directly; the unfused pipeline
-  // and the blocks of a coupled mesh read ghost entries, which are filled
-  // (exchanged between the mesh's blocks) before each stage
-  const bool ghosts = (h->unfused && !h->batch) || h->mesh;
+  // and the blocks of a coupled mesh or batch read ghost entries, which are
+  // filled (exchanged between the blocks) before each stage
+  const bool ghosts = (h->unfused && !h->batch) || h->mesh || h->coupled;
   const int64_t ncell = h->batch ? h->ctot : h->g.cblock * nblocks;
   const int64_t nface = h->batch ? h->ftot : h->g.fblock * nblocks;
   if (sc.nstage == 1) {
@@ -496,8 +505,11 @@ int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const doubl
     if ((e = launch_copy(bface, xb, nface, s)) != hipSuccess) return hip_fail(h, e, "copy launch");
   }
   // a composite leaves its ghosts and restricted coarse faces filled, which
-  // its newdt reads
+  // its newdt reads; so does a coupled batch, whose blocks read their upper
+  // faces (written by the neighbour that owns them) from their own shell
   if (h->levels && (e = levels_ghosts(h, cons, bface, s)) != hipSuccess) return hip_fail(h, e, "level ghost launch");
+  if (h->coupled && (e = fill_ghosts(h, cons, bface, nblocks, s)) != hipSuccess)
+    return hip_fail(h, e, "batch exchange launch");
   if (dt_bits && (e = launch_cfl(h, cons, bface, nblocks, dt_bits, s, floor_in_cfl)) != hipSuccess)
     return hip_fail(h, e, "newdt launch");
   return ATHMHD_OK;
@@ -617,7 +629,7 @@ int noalloc_scratch(athmhd_t h, int dev, DtPart** out) {
 
 extern "C" {
 
-int athmhd_version(void) { return 111; }
+int athmhd_version(void) { return 112; }
 
 int athmhd_create(const athmhd_config* cfg, int nblocks_max, athmhd_t* out) {
   if (!out) return fail(nullptr, ATHMHD_EINVAL, "out is NULL");
@@ -844,6 +856,104 @@ int athmhd_batch_info(athmhd_t h, int64_t* cons_len, int64_t* bface_len, int64_t
   return ATHMHD_OK;
 }
 
+int athmhd_batch_couple(athmhd_t h, const int32_t* origin, const int32_t* domain) {
+  if (!h) return ATHMHD_EINVAL;
+  if (!h->batch) return fail(h, ATHMHD_EINVAL, "not a batched handle");
+  if (h->coupled) return fail(h, ATHMHD_EINVAL, "the batch is already coupled");
+  if (!origin || !domain) return fail(h, ATHMHD_EINVAL, "NULL origin or domain");
+  if (h->g.ns > 0) return fail(h, ATHMHD_EUNSUP, "a coupled batch carries no passive scalars");
+  if (h->floors.on()) return fail(h, ATHMHD_EUNSUP, "a coupled batch takes no floors");
+  const int64_t D[3] = {domain[0], domain[1], domain[2]};
+  if (D[0] < 1 || D[1] < 1 || D[2] < 1 || D[0] * D[1] * D[2] > (int64_t)INT32_MAX)
+    return fail(h, ATHMHD_EINVAL, "domain %lld x %lld x %lld cells out of range", (long long)D[0], (long long)D[1],
+                (long long)D[2]);
+  const int nb = h->nbatch;
+  const Geo& g0 = h->desc[0].g;
+  for (int b = 0; b < nb; ++b) {
+    const Geo& g = h->desc[b].g;
+    if (g.dx1 != g0.dx1 || g.dx2 != g0.dx2 || g.dx3 != g0.dx3)
+      return fail(h, ATHMHD_EINVAL, "block %d: the blocks of a coupled batch share one cell width", b);
+    if (g.F1 > 1024 || g.F2 > 1024 || g.F3 > 1024)
+      return fail(h, ATHMHD_EINVAL, "block %d: stored extents above 1023 cells", b);
+    const int n[3] = {g.n1, g.n2, g.n3};
+    for (int d = 0; d < 3; ++d)
+      if (origin[3 * b + d] < 0 || origin[3 * b + d] + n[d] > D[d])
+        return fail(h, ATHMHD_EINVAL, "block %d lies outside the domain along x%d", b, d + 1);
+  }
+  // owner of every cell of the domain: each covered by exactly one block
+  std::vector<int32_t> owner((size_t)(D[0] * D[1] * D[2]), -1);
+  for (int b = 0; b < nb; ++b) {
+    const Geo& g = h->desc[b].g;
+    const int32_t* o = origin + 3 * b;
+    for (int k = 0; k < g.n3; ++k)
+      for (int j = 0; j < g.n2; ++j)
+        for (int i = 0; i < g.n1; ++i) {
+          int32_t& w = owner[(size_t)(((o[2] + k) * D[1] + o[1] + j) * D[0] + o[0] + i)];
+          if (w >= 0) return fail(h, ATHMHD_EINVAL, "blocks %d and %d overlap", w, b);
+          w = b;
+        }
+  }
+  for (size_t c = 0; c < owner.size(); ++c)
+    if (owner[c] < 0)
+      return fail(h, ATHMHD_EINVAL, "cell %zu of the domain (x1 fastest) belongs to no block", c);
+  // per block, its shell entries in the order of shell_entry
+  std::vector<int64_t> off(nb);
+  int64_t total = 0;
+  for (int b = 0; b < nb; ++b) {
+    const Geo& g = h->desc[b].g;
+    off[b] = total;
+    total += g.fvar - (int64_t)g.n1 * g.n2 * g.n3;
+  }
+  std::vector<int2> src((size_t)total);
+  for (int b = 0; b < nb; ++b) {
+    const Geo& g = h->desc[b].g;
+    const int64_t ns = g.fvar - (int64_t)g.n1 * g.n2 * g.n3;
+    for (int64_t t = 0; t < ns; ++t) {
+      int x[3];
+      shell_entry(g, t, x[0], x[1], x[2]);
+      int64_t X[3];
+      for (int d = 0; d < 3; ++d) {
+        X[d] = ((int64_t)origin[3 * b + d] + x[d] - g.ng) % D[d];
+        if (X[d] < 0) X[d] += D[d];
+      }
+      const int w = owner[(size_t)((X[2] * D[1] + X[1]) * D[0] + X[0])];
+      const int ng = h->desc[w].g.ng;
+      const int li = (int)(X[0] - origin[3 * w]) + ng, lj = (int)(X[1] - origin[3 * w + 1]) + ng,
+                lk = (int)(X[2] - origin[3 * w + 2]) + ng;
+      src[(size_t)(off[b] + t)] = make_int2(w, li | (lj << 10) | (lk << 20));
+    }
+  }
+  hipError_t e = hipMalloc(&h->d_xoff, nb * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc(&h->d_xsrc, (size_t)total * sizeof(int2));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    if (h->d_xoff) (void)hipFree(h->d_xoff);
+    h->d_xoff = nullptr;
+    h->d_xsrc = nullptr;
+    return fail(h, ATHMHD_ENOMEM, "exchange table of %.3f GB", (double)total * sizeof(int2) / 1e9);
+  }
+  // the blocks' upper boundary faces are stored (exchanged) entries from now
+  // on: newdt and prim2cons read them there (cell_field)
+  std::vector<BatchDesc> desc = h->desc;
+  for (BatchDesc& d : desc) d.g.mesh[0] = -1;
+  e = hipMemcpy(h->d_xoff, off.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(h->d_xsrc, src.data(), (size_t)total * sizeof(int2), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(h->d_desc, desc.data(), nb * sizeof(BatchDesc), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipMemcpy(h->d_desc, h->desc.data(), nb * sizeof(BatchDesc), hipMemcpyHostToDevice);
+    (void)hipFree(h->d_xoff);
+    (void)hipFree(h->d_xsrc);
+    h->d_xoff = nullptr;
+    h->d_xsrc = nullptr;
+    return hip_fail(h, e, "exchange table upload");
+  }
+  h->desc = desc;
+  h->g = h->desc[0].g;
+  h->coupled = true;
+  drop_graph(h);
+  return ATHMHD_OK;
+}
+
 int athmhd_batch_set_tile(athmhd_t h, int shape, int split) {
   if (!h) return ATHMHD_EINVAL;
   if (!h->batch) return fail(h, ATHMHD_EINVAL, "not a batched handle");
@@ -912,6 +1022,8 @@ int athmhd_set_floors(athmhd_t h, double dfloor, double pfloor) {
   if (!h) return ATHMHD_EINVAL;
   if (!(std::isfinite(dfloor) && dfloor >= 0.0 && std::isfinite(pfloor) && pfloor >= 0.0))
     return fail(h, ATHMHD_EINVAL, "floors must be finite and >= 0 (got %g, %g)", dfloor, pfloor);
+  if (h->coupled && (dfloor > 0.0 || pfloor > 0.0))
+    return fail(h, ATHMHD_EUNSUP, "a coupled batch takes no floors");
   h->floors = Floors{dfloor, pfloor};
   drop_graph(h);  // captured launches carry the floors as arguments
   return ATHMHD_OK;

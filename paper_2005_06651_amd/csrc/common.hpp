@@ -24,7 +24,9 @@ struct Geo {
   // Blocks per direction of a coupled mesh: equal blocks that tile one
   // periodic domain, block b at (b mod m0, (b / m0) mod m1, b / (m0 m1)), each
   // reading its neighbours' cells through its ghost entries (Sec. 2.1.1).
-  // All 0: every block is its own periodic neighbour.
+  // All 0: every block is its own periodic neighbour.  mesh[0] = -1: the
+  // block's upper boundary faces are stored entries filled from its
+  // neighbours (blocks of a two-level composite or of a coupled batch).
   int mesh[3];
 
   __host__ __device__ __forceinline__ int c(int i, int j, int k) const { return (k * N2 + j) * N1 + i; }
@@ -74,6 +76,41 @@ __host__ __device__ __forceinline__ int wrap_index(int idx, int n, int ng) {
   int r = (idx - ng) % n;
   if (r < 0) r += n;
   return ng + r;
+}
+
+// Entry t of a block's shell: the stored positions (i, j, k) of the face box
+// (F1 x F2 x F3) outside the block's active cells, t in [0, fvar - n1 n2 n3),
+// in the order x3 slabs (all i, j), x2 slabs (active k), x1 slabs (active j,
+// k).  A position names a cell (when inside the cell box) and the three lower
+// faces of that cell.
+__host__ __device__ __forceinline__ void shell_entry(const Geo& g, int64_t t64, int& i, int& j, int& k) {
+  // 32-bit unsigned index arithmetic: a block's face box holds fewer than
+  // 2^31 entries (checked when the block is created)
+  const unsigned t = (unsigned)t64;
+  const unsigned F1 = (unsigned)g.F1, F2 = (unsigned)g.F2;
+  const unsigned nz = (unsigned)(g.F3 - g.n3) * F2 * F1;
+  const unsigned ny = (unsigned)g.n3 * (F2 - (unsigned)g.n2) * F1;
+  if (t < nz) {
+    i = (int)(t % F1);
+    const unsigned r = t / F1;
+    j = (int)(r % F2);
+    const int q = (int)(r / F2);
+    k = q < g.ng ? q : q + g.n3;
+  } else if (t < nz + ny) {
+    const unsigned u = t - nz;
+    i = (int)(u % F1);
+    const unsigned r = u / F1, W = F2 - (unsigned)g.n2;
+    const int q = (int)(r % W);
+    j = q < g.ng ? q : q + g.n2;
+    k = g.ng + (int)(r / W);
+  } else {
+    const unsigned u = t - nz - ny, W = F1 - (unsigned)g.n1;
+    const int q = (int)(u % W);
+    i = q < g.ng ? q : q + g.n1;
+    const unsigned r = u / W;
+    j = g.ng + (int)(r % (unsigned)g.n2);
+    k = g.ng + (int)(r / (unsigned)g.n2);
+  }
 }
 
 // The next block (+1) along direction D from block b of a coupled mesh,

@@ -137,11 +137,14 @@ int batch_tile_threads(int shape);
 // One stage of all blocks in one persistent launch of `grid` workgroups that
 // drain the item queue.  dt_dev, if not NULL, supplies dt on the device
 // (bdt = beta * dt); otherwise coef.bdt is used.
+// mesh: the blocks tile one domain and read their (exchanged) ghost entries
+// instead of their own periodic images (then without floors and fm).
 hipError_t launch_stage_batch(int shape, double gamma, int recon, int rs, double ct_eps, const BatchDesc* desc,
                               const WorkItem* items, int nitems, unsigned* queue, const double* xc,
                               const double* xb, const double* unc, const double* unb, double* outc, double* outb,
                               StageCoef coef, const double* dt_dev, double beta, int grid, Floors fl, int* bad,
-                              double* fm, hipStream_t s);  // fm: NULL, or mass-flux output laid out like bface
+                              double* fm, hipStream_t s,  // fm: NULL, or mass-flux output laid out like bface
+                              bool mesh = false);
 // Passive scalars of one stage of batched blocks (same contract as
 // launch_scalar_stage; fm laid out like bface).  items: one per (block, tile of
 // scalar_batch_tile() x scalar_batch_tile() columns, x3 segment).
@@ -152,6 +155,11 @@ hipError_t launch_scalar_stage_batch(const BatchDesc* desc, const WorkItem* item
 // Ghost fill, prim->cons and the CFL reduction over all blocks of a batch.
 hipError_t launch_fill_ghosts_batch(const BatchDesc* desc, int nblocks, int64_t max_shell, double* cons,
                                     double* bface, hipStream_t s);
+// Blocks that tile one periodic domain: every shell entry of block b (in the
+// order of shell_entry) is copied from src[off[b] + t] = (owning block, its
+// stored position of the same domain cell packed as i | j << 10 | k << 20).
+hipError_t launch_exchange_batch(const BatchDesc* desc, int nblocks, int64_t max_shell, const int64_t* off,
+                                 const int2* src, double* cons, double* bface, hipStream_t s);
 hipError_t launch_prim2cons_batch(const BatchDesc* desc, int nblocks, int64_t max_cells, double gamma,
                                   const double* prim, const double* bface, double* cons, hipStream_t s);
 hipError_t launch_newdt_batch(const BatchDesc* desc, int nblocks, int64_t max_active, double gamma,

@@ -453,30 +453,10 @@ __global__ void __launch_bounds__(kThreads) k_fill_ghosts_batch(const BatchDesc*
                                                                double* bface) {
   const BatchDesc& d = desc[blockIdx.y];
   const Geo& g = d.g;
-  const int64_t nz = (int64_t)(g.F3 - g.n3) * g.F2 * g.F1;
-  const int64_t ny = (int64_t)g.n3 * (g.F2 - g.n2) * g.F1;
-  const int64_t nx = (int64_t)g.n3 * g.n2 * (g.F1 - g.n1);
-  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < nz + ny + nx;
-       t += (int64_t)gridDim.x * kThreads) {
+  const int64_t nshell = g.fvar - (int64_t)g.n1 * g.n2 * g.n3;
+  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < nshell; t += (int64_t)gridDim.x * kThreads) {
     int i, j, k;
-    if (t < nz) {
-      i = (int)(t % g.F1);
-      const int64_t r = t / g.F1;
-      j = (int)(r % g.F2);
-      k = ghost_index((int)(r / g.F2), g.n3, g.ng);
-    } else if (t < nz + ny) {
-      const int64_t u = t - nz;
-      i = (int)(u % g.F1);
-      const int64_t r = u / g.F1;
-      j = ghost_index((int)(r % (g.F2 - g.n2)), g.n2, g.ng);
-      k = g.ng + (int)(r / (g.F2 - g.n2));
-    } else {
-      const int64_t u = t - nz - ny;
-      i = ghost_index((int)(u % (g.F1 - g.n1)), g.n1, g.ng);
-      const int64_t r = u / (g.F1 - g.n1);
-      j = g.ng + (int)(r % g.n2);
-      k = g.ng + (int)(r / g.n2);
-    }
+    shell_entry(g, t, i, j, k);
     const int ii = wrap_index(i, g.n1, g.ng), jj = wrap_index(j, g.n2, g.ng), kk = wrap_index(k, g.n3, g.ng);
     double* cb = cons + d.coff;
     double* fb = bface + d.foff;
@@ -489,6 +469,42 @@ __global__ void __launch_bounds__(kThreads) k_fill_ghosts_batch(const BatchDesc*
     const int dd = g.f(i, j, k), ss = g.f(ii, jj, kk);
 #pragma unroll
     for (int c = 0; c < 3; ++c) fb[c * g.fvar + dd] = fb[c * g.fvar + ss];
+  }
+}
+
+// Ghost exchange of batched blocks that tile one periodic domain: shell entry
+// t of block b takes its cell and that cell's three lower faces from the
+// block owning the same cell of the domain, src[off[b] + t] = (owner, the
+// owner's stored position packed as i | j << 10 | k << 20).  Sources are
+// active entries and destinations shell entries, so no entry is both read
+// and written by a launch.
+__global__ void __launch_bounds__(kThreads) k_exchange_batch(const BatchDesc* __restrict__ desc,
+                                                            const int64_t* __restrict__ off,
+                                                            const int2* __restrict__ src, double* cons,
+                                                            double* bface) {
+  const BatchDesc& d = desc[blockIdx.y];
+  const Geo& g = d.g;
+  const int64_t nshell = g.fvar - (int64_t)g.n1 * g.n2 * g.n3;
+  const int2* sb = src + off[blockIdx.y];
+  double* cb = cons + d.coff;
+  double* fb = bface + d.foff;
+  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < nshell; t += (int64_t)gridDim.x * kThreads) {
+    int i, j, k;
+    shell_entry(g, t, i, j, k);
+    const int2 e = sb[t];
+    const BatchDesc& o = desc[e.x];
+    const int si = e.y & 1023, sj = (e.y >> 10) & 1023, sk = (e.y >> 20) & 1023;
+    const double* oc = cons + o.coff;
+    const double* ofb = bface + o.foff;
+    if (i < g.N1 && j < g.N2 && k < g.N3) {
+      const int dd = g.c(i, j, k), ss = o.g.c(si, sj, sk);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) cb[v * g.cvar + dd] = oc[v * o.g.cvar + ss];
+      for (int v = 5; v < 5 + g.ns; ++v) cb[v * g.cvar + dd] = oc[v * o.g.cvar + ss];
+    }
+    const int dd = g.f(i, j, k), ss = o.g.f(si, sj, sk);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fb[c * g.fvar + dd] = ofb[c * o.g.fvar + ss];
   }
 }
 
@@ -595,6 +611,13 @@ hipError_t launch_fill_ghosts_batch(const BatchDesc* desc, int nblocks, int64_t 
                                     double* bface, hipStream_t s) {
   const unsigned gx = (unsigned)std::min<int64_t>(grid_for(max_shell), 64);
   hipLaunchKernelGGL(k_fill_ghosts_batch, dim3(gx, nblocks), dim3(kThreads), 0, s, desc, cons, bface);
+  return hipGetLastError();
+}
+
+hipError_t launch_exchange_batch(const BatchDesc* desc, int nblocks, int64_t max_shell, const int64_t* off,
+                                 const int2* src, double* cons, double* bface, hipStream_t s) {
+  const unsigned gx = (unsigned)std::min<int64_t>(grid_for(max_shell), 64);
+  hipLaunchKernelGGL(k_exchange_batch, dim3(gx, nblocks), dim3(kThreads), 0, s, desc, off, src, cons, bface);
   return hipGetLastError();
 }
 

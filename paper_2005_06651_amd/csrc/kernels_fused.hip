@@ -747,7 +747,8 @@ k_stage_fused(UniformArgs a) {
 
 // Batched blocks of uneven sizes: a persistent grid whose workgroups pull
 // (block, tile, x3 segment) items from a device queue until it is drained.
-template <int RECON, int RS, class T, bool FL, bool MF, bool SAME = false>
+// MESH: the blocks tile one domain and read their exchanged ghost entries.
+template <int RECON, int RS, class T, bool FL, bool MF, bool SAME = false, bool MESH = false>
 __global__ void __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(2))) k_stage_batch(BatchArgs a) {
   using S = Smem<RECON, T>;
   __shared__ double sp[8 * S::PL];
@@ -764,7 +765,7 @@ __global__ void __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(2)))
     const BatchDesc& d = a.desc[w.block];
     BlockPtrs bp{a.xc + d.coff, a.xb + d.foff, a.unc + d.coff, a.unb + d.foff, a.oc + d.coff, a.ob + d.foff,
                  MF ? a.fm + d.foff : nullptr};
-    stage_tile<RECON, RS, T, FL, false, MF, SAME>(d.g, bp, a.sa, w.tile_x, w.tile_y, w.k0, w.kend, sp, sx, sc);
+    stage_tile<RECON, RS, T, FL, MESH, MF, SAME>(d.g, bp, a.sa, w.tile_x, w.tile_y, w.k0, w.kend, sp, sx, sc);
     __syncthreads();
   }
 }
@@ -837,8 +838,32 @@ hipError_t launch_batch_t(int rs, const BatchArgs& ba, int grid, hipStream_t s) 
   return ba.fm ? launch_batch_m<T, RECON, true>(rs, ba, grid, s) : launch_batch_m<T, RECON, false>(rs, ba, grid, s);
 }
 
+// blocks that tile one domain (no floors, no mass fluxes)
+template <class T, int RECON>
+hipError_t launch_batch_mesh(int rs, const BatchArgs& ba, int grid, hipStream_t s) {
+  if constexpr (RECON == 0) {
+    if (ba.xc == ba.unc && ba.xb == ba.unb) {
+      if (rs == 1)
+        hipLaunchKernelGGL((k_stage_batch<RECON, 1, T, false, false, true, true>), dim3(grid), dim3(T::NT), 0, s, ba);
+      else
+        hipLaunchKernelGGL((k_stage_batch<RECON, 0, T, false, false, true, true>), dim3(grid), dim3(T::NT), 0, s, ba);
+      return hipGetLastError();
+    }
+  }
+  if (rs == 1)
+    hipLaunchKernelGGL((k_stage_batch<RECON, 1, T, false, false, false, true>), dim3(grid), dim3(T::NT), 0, s, ba);
+  else
+    hipLaunchKernelGGL((k_stage_batch<RECON, 0, T, false, false, false, true>), dim3(grid), dim3(T::NT), 0, s, ba);
+  return hipGetLastError();
+}
+
 template <class T>
-hipError_t launch_batch_recon(int recon, int rs, const BatchArgs& ba, int grid, hipStream_t s) {
+hipError_t launch_batch_recon(int recon, int rs, const BatchArgs& ba, int grid, hipStream_t s, bool mesh) {
+  if (mesh) {
+    if (recon == 0) return launch_batch_mesh<T, 0>(rs, ba, grid, s);
+    if (recon == 1) return launch_batch_mesh<T, 1>(rs, ba, grid, s);
+    return launch_batch_mesh<T, 2>(rs, ba, grid, s);
+  }
   if (recon == 0) return launch_batch_t<T, 0>(rs, ba, grid, s);
   if (recon == 1) return launch_batch_t<T, 1>(rs, ba, grid, s);
   return launch_batch_t<T, 2>(rs, ba, grid, s);
@@ -910,7 +935,8 @@ hipError_t launch_stage_batch(int shape, double gamma, int recon, int rs, double
                               const WorkItem* items, int nitems, unsigned* queue, const double* xc,
                               const double* xb, const double* unc, const double* unb, double* outc, double* outb,
                               StageCoef coef, const double* dt_dev, double beta, int grid, Floors fl, int* bad,
-                              double* fm, hipStream_t s) {
+                              double* fm, hipStream_t s, bool mesh) {
+  if (mesh && (fl.on() || fm)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, queue);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -923,10 +949,10 @@ hipError_t launch_stage_batch(int shape, double gamma, int recon, int rs, double
   ba.xc = xc; ba.xb = xb; ba.unc = unc; ba.unb = unb; ba.oc = outc; ba.ob = outb;
   ba.fm = fm;
   switch (shape) {
-    case 0: return launch_batch_recon<Tile<18, 14>>(recon, rs, ba, grid, s);
-    case 1: return launch_batch_recon<Tile<14, 18>>(recon, rs, ba, grid, s);
-    case 2: return launch_batch_recon<Tile<16, 16>>(recon, rs, ba, grid, s);
-    default: return launch_batch_recon<Tile<18, 10>>(recon, rs, ba, grid, s);
+    case 0: return launch_batch_recon<Tile<18, 14>>(recon, rs, ba, grid, s, mesh);
+    case 1: return launch_batch_recon<Tile<14, 18>>(recon, rs, ba, grid, s, mesh);
+    case 2: return launch_batch_recon<Tile<16, 16>>(recon, rs, ba, grid, s, mesh);
+    default: return launch_batch_recon<Tile<18, 10>>(recon, rs, ba, grid, s, mesh);
   }
 }
 

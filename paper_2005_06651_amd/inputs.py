@@ -546,6 +546,77 @@ def join_mesh(cells: np.ndarray, faces: np.ndarray, ng: int, n_block, mesh):
     return dc, df
 
 
+def brick_layout(slabs, cross: int):
+    """Blocks of uneven cube sizes tiling one periodic domain at one cell
+    width: the domain of cross x cross x sum(slabs) cells is cut along x3 into
+    slabs of the given thicknesses, and each slab is tiled by cubes of its
+    thickness (cross must be a multiple of every thickness).  Across a slab
+    boundary the blocks' faces do not line up, so a block's ghost cells along
+    x3 come from several neighbours.  Returns (dims, origins, domain): block b
+    has dims[b] cells and its first active cell at origins[b] (x1 first).
+    Index arithmetic only."""
+    dims, origins = [], []
+    z = 0
+    for s in slabs:
+        s = int(s)
+        if cross % s:
+            raise ValueError(f"cross section {cross} is not a multiple of {s}")
+        for y in range(0, cross, s):
+            for x in range(0, cross, s):
+                dims.append((s, s, s))
+                origins.append((x, y, z))
+        z += s
+    return dims, origins, (cross, cross, z)
+
+
+def brick_slabs(nblocks: int = 1024, sizes=(16, 24, 32), fractions=(0.4, 0.4, 0.2), cross: int = 192,
+                seed: int = 3):
+    """Slab thicknesses for brick_layout whose cube counts come closest to
+    nblocks blocks in the given size mix (per size, the nearest whole number
+    of slabs), in a seeded order along x3."""
+    rng = np.random.default_rng(seed)
+    slabs = []
+    for s, f in zip(sizes, fractions):
+        per = (cross // s) ** 2
+        slabs += [s] * max(1, int(round(f * nblocks / per)))
+    rng.shuffle(slabs)
+    return [int(x) for x in slabs]
+
+
+def split_boxes(cells: np.ndarray, faces: np.ndarray, ng: int, dims, origins):
+    """Cut a periodic domain (one block of L[d] cells with ng ghost layers:
+    cells (nv, N3, N2, N1), faces (3, N3+1, N2+1, N1+1)) into blocks of their
+    own sizes, block b with dims[b] active cells from origins[b], each with
+    its own ng ghost layers and face entries taken from the periodic domain.
+    Returns two lists of per-block arrays.  Index arithmetic only."""
+    L = tuple(cells.shape[3 - d] - 2 * ng for d in range(3))
+    out_c, out_f = [], []
+    for n, o in zip(dims, origins):
+        M = tuple(n[d] + 2 * ng for d in range(3))
+        ci = [ng + (np.arange(M[d]) + o[d] - ng) % L[d] for d in range(3)]
+        fi = [ng + (np.arange(M[d] + 1) + o[d] - ng) % L[d] for d in range(3)]
+        out_c.append(np.ascontiguousarray(cells[:, ci[2][:, None, None], ci[1][None, :, None], ci[0][None, None, :]]))
+        out_f.append(np.ascontiguousarray(faces[:, fi[2][:, None, None], fi[1][None, :, None], fi[0][None, None, :]]))
+    return out_c, out_f
+
+
+def join_boxes(cells, faces, ng: int, dims, origins, domain):
+    """Inverse of split_boxes on the active entries: each block's active cells
+    and the lower faces of its active cells, placed into a periodic domain of
+    domain[d] cells with ng ghost layers (other entries left zero)."""
+    nv = cells[0].shape[0]
+    L = tuple(int(x) for x in domain)
+    dc = np.zeros((nv, L[2] + 2 * ng, L[1] + 2 * ng, L[0] + 2 * ng))
+    df = np.zeros((3, L[2] + 2 * ng + 1, L[1] + 2 * ng + 1, L[0] + 2 * ng + 1))
+    for c, f, n, o in zip(cells, faces, dims, origins):
+        a = (slice(None), slice(ng, ng + n[2]), slice(ng, ng + n[1]), slice(ng, ng + n[0]))
+        d = (slice(None), slice(ng + o[2], ng + o[2] + n[2]), slice(ng + o[1], ng + o[1] + n[1]),
+             slice(ng + o[0], ng + o[0] + n[0]))
+        dc[d] = c[a]
+        df[d] = f[a]
+    return dc, df
+
+
 def analytic_state(n, ng=2, box=(2.0, 1.0, 1.0), seed=0, gamma=5.0 / 3.0, amp=0.2, vamp=0.4, bamp=0.15,
                    B0=(0.6, 0.3, -0.2), modes=3) -> Block:
     """Smooth periodic state on an n-cell uniform grid of the given box, from

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version():
-    assert athmhd.lib().athmhd_version() == 111
+    assert athmhd.lib().athmhd_version() == 112
 
 
 def _create(**over):
