@@ -38,14 +38,14 @@ ALG_FLOPS_PER_ZONE_CYCLE = 2560.0
 # on this workload, scaled by the counters of a plain 1 GiB copy, and the hash
 # of the stage-kernel sources they were measured on (traffic is reported only
 # while the sources are unchanged).
-STAGE_TRAFFIC = {"bytes_per_launch": 2.979e+09, "fetch_bytes_per_launch": 1.858e+09,
+STAGE_TRAFFIC = {"bytes_per_launch": 2.977e+09, "fetch_bytes_per_launch": 1.858e+09,
                  "write_bytes_per_launch": 1.120e+09, "fetch_scale": 1.9999, "write_scale": 1.0000,
-                 "source_hash": "87ecf36491536450"}
+                 "source_hash": "d9dccd87daa965a6"}
 # FP64 VALU issue of the same stage launches (rocprofv3 SQ_INSTS_VALU per
 # launch over 256 CUs x 2.4 GHz x the launch duration, mean of the DC and PLM
 # stages) and the stage time those launches took under the profiler: with the
 # traffic above they say which roof binds (the larger measured fraction).
-STAGE_ISSUE = {"valu_issue_frac": 0.515, "profiled_ms_per_launch": 1.6658, "source_hash": "87ecf36491536450"}
+STAGE_ISSUE = {"valu_issue_frac": 0.508, "profiled_ms_per_launch": 1.6894, "source_hash": "d9dccd87daa965a6"}
 HBM_FRAC_TARGET = 0.60       # the HBM-roofline fraction the stage kernel is measured against
 # The same for the level operators on the 256^3 block (per octant launch).
 LEVELS_SOURCES = ("kernels_amr.hip", "common.hpp")
