@@ -52,6 +52,8 @@ struct athmhd_s {
   bool coupled = false;
   int64_t* d_xoff = nullptr;  // per block: first table entry of its shell
   int2* d_xsrc = nullptr;     // per shell entry: owner block, packed stored position
+  int2* d_xwork = nullptr;    // per exchange workgroup: block, first shell entry
+  int nxwork = 0;
   // state registers and scratch
   double* reg[2] = {nullptr, nullptr};  // two stage registers (cons followed by bface)
   int64_t reg_coff = 0;                  // offset of bface inside a register
@@ -249,6 +251,7 @@ void free_all(athmhd_t h) {
   if (h->d_queue) (void)hipFree(h->d_queue);
   if (h->d_xoff) (void)hipFree(h->d_xoff);
   if (h->d_xsrc) (void)hipFree(h->d_xsrc);
+  if (h->d_xwork) (void)hipFree(h->d_xwork);
   if (h->h_pinned) (void)hipHostFree(h->h_pinned);
   if (h->adj_base) (void)hipFree(h->adj_base);
 }
@@ -418,7 +421,7 @@ hipError_t launch_stage(athmhd_t h, int recon, const double* xc, const double* x
 hipError_t fill_ghosts(athmhd_t h, double* cons, double* bface, int nblocks, hipStream_t s, int depth = 0) {
   if (h->levels) return levels_ghosts(h, cons, bface, s);
   if (h->batch && h->coupled)
-    return launch_exchange_batch(h->d_desc, h->nbatch, h->max_shell, h->d_xoff, h->d_xsrc, cons, bface, s);
+    return launch_exchange_batch(h->d_desc, h->d_xoff, h->d_xsrc, h->d_xwork, h->nxwork, cons, bface, s);
   if (h->batch) return launch_fill_ghosts_batch(h->d_desc, h->nbatch, h->max_shell, cons, bface, s);
   if (h->mesh) return launch_mesh_ghosts(h->g, depth, cons, bface, s);
   return launch_fill_ghosts(h->g, cons, bface, nblocks, s);
@@ -923,13 +926,24 @@ int athmhd_batch_couple(athmhd_t h, const int32_t* origin, const int32_t* domain
       src[(size_t)(off[b] + t)] = make_int2(w, li | (lj << 10) | (lk << 20));
     }
   }
+  // workgroups of the exchange: chunks of exchange_chunk() entries of one block
+  std::vector<int2> work;
+  for (int b = 0; b < nb; ++b) {
+    const Geo& g = h->desc[b].g;
+    const int64_t ns = g.fvar - (int64_t)g.n1 * g.n2 * g.n3;
+    for (int64_t t0 = 0; t0 < ns; t0 += exchange_chunk()) work.push_back(make_int2(b, (int)t0));
+  }
+  if (work.size() > (size_t)INT32_MAX) return fail(h, ATHMHD_EINVAL, "exchange of %zu chunks", work.size());
   hipError_t e = hipMalloc(&h->d_xoff, nb * sizeof(int64_t));
   if (e == hipSuccess) e = hipMalloc(&h->d_xsrc, (size_t)total * sizeof(int2));
+  if (e == hipSuccess) e = hipMalloc(&h->d_xwork, work.size() * sizeof(int2));
   if (e != hipSuccess) {
     (void)hipGetLastError();
     if (h->d_xoff) (void)hipFree(h->d_xoff);
+    if (h->d_xsrc) (void)hipFree(h->d_xsrc);
     h->d_xoff = nullptr;
     h->d_xsrc = nullptr;
+    h->d_xwork = nullptr;
     return fail(h, ATHMHD_ENOMEM, "exchange table of %.3f GB", (double)total * sizeof(int2) / 1e9);
   }
   // the blocks' upper boundary faces are stored (exchanged) entries from now
@@ -938,15 +952,19 @@ int athmhd_batch_couple(athmhd_t h, const int32_t* origin, const int32_t* domain
   for (BatchDesc& d : desc) d.g.mesh[0] = -1;
   e = hipMemcpy(h->d_xoff, off.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(h->d_xsrc, src.data(), (size_t)total * sizeof(int2), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(h->d_xwork, work.data(), work.size() * sizeof(int2), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(h->d_desc, desc.data(), nb * sizeof(BatchDesc), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipMemcpy(h->d_desc, h->desc.data(), nb * sizeof(BatchDesc), hipMemcpyHostToDevice);
     (void)hipFree(h->d_xoff);
     (void)hipFree(h->d_xsrc);
+    (void)hipFree(h->d_xwork);
     h->d_xoff = nullptr;
     h->d_xsrc = nullptr;
+    h->d_xwork = nullptr;
     return hip_fail(h, e, "exchange table upload");
   }
+  h->nxwork = (int)work.size();
   h->desc = desc;
   h->g = h->desc[0].g;
   h->coupled = true;

@@ -158,8 +158,11 @@ hipError_t launch_fill_ghosts_batch(const BatchDesc* desc, int nblocks, int64_t 
 // Blocks that tile one periodic domain: every shell entry of block b (in the
 // order of shell_entry) is copied from src[off[b] + t] = (owning block, its
 // stored position of the same domain cell packed as i | j << 10 | k << 20).
-hipError_t launch_exchange_batch(const BatchDesc* desc, int nblocks, int64_t max_shell, const int64_t* off,
-                                 const int2* src, double* cons, double* bface, hipStream_t s);
+// work: nwork chunks (block, first entry) of exchange_chunk() entries each,
+// covering every block's shell.
+int exchange_chunk();
+hipError_t launch_exchange_batch(const BatchDesc* desc, const int64_t* off, const int2* src, const int2* work,
+                                 int nwork, double* cons, double* bface, hipStream_t s);
 hipError_t launch_prim2cons_batch(const BatchDesc* desc, int nblocks, int64_t max_cells, double gamma,
                                   const double* prim, const double* bface, double* cons, hipStream_t s);
 hipError_t launch_newdt_batch(const BatchDesc* desc, int nblocks, int64_t max_active, double gamma,

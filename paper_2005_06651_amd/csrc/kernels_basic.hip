@@ -477,18 +477,23 @@ __global__ void __launch_bounds__(kThreads) k_fill_ghosts_batch(const BatchDesc*
 // block owning the same cell of the domain, src[off[b] + t] = (owner, the
 // owner's stored position packed as i | j << 10 | k << 20).  Sources are
 // active entries and destinations shell entries, so no entry is both read
-// and written by a launch.
+// and written by a launch.  Workgroup w copies entries [t0, t0 + kXchgChunk)
+// of block b, (b, t0) = work[w], kXchgChunk / kThreads per thread.
+constexpr int kXchgChunk = 4 * kThreads;
 __global__ void __launch_bounds__(kThreads) k_exchange_batch(const BatchDesc* __restrict__ desc,
                                                             const int64_t* __restrict__ off,
-                                                            const int2* __restrict__ src, double* cons,
+                                                            const int2* __restrict__ src,
+                                                            const int2* __restrict__ work, double* cons,
                                                             double* bface) {
-  const BatchDesc& d = desc[blockIdx.y];
+  const int2 w = work[blockIdx.x];
+  const BatchDesc& d = desc[w.x];
   const Geo& g = d.g;
   const int64_t nshell = g.fvar - (int64_t)g.n1 * g.n2 * g.n3;
-  const int2* sb = src + off[blockIdx.y];
+  const int2* sb = src + off[w.x];
   double* cb = cons + d.coff;
   double* fb = bface + d.foff;
-  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < nshell; t += (int64_t)gridDim.x * kThreads) {
+  const int64_t tend = min(nshell, (int64_t)w.y + kXchgChunk);
+  for (int64_t t = (int64_t)w.y + threadIdx.x; t < tend; t += kThreads) {
     int i, j, k;
     shell_entry(g, t, i, j, k);
     const int2 e = sb[t];
@@ -614,10 +619,12 @@ hipError_t launch_fill_ghosts_batch(const BatchDesc* desc, int nblocks, int64_t 
   return hipGetLastError();
 }
 
-hipError_t launch_exchange_batch(const BatchDesc* desc, int nblocks, int64_t max_shell, const int64_t* off,
-                                 const int2* src, double* cons, double* bface, hipStream_t s) {
-  const unsigned gx = (unsigned)std::min<int64_t>(grid_for(max_shell), 64);
-  hipLaunchKernelGGL(k_exchange_batch, dim3(gx, nblocks), dim3(kThreads), 0, s, desc, off, src, cons, bface);
+int exchange_chunk() { return kXchgChunk; }
+
+hipError_t launch_exchange_batch(const BatchDesc* desc, const int64_t* off, const int2* src, const int2* work,
+                                 int nwork, double* cons, double* bface, hipStream_t s) {
+  if (nwork <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_exchange_batch, dim3(nwork), dim3(kThreads), 0, s, desc, off, src, work, cons, bface);
   return hipGetLastError();
 }
 
