@@ -340,14 +340,23 @@ __device__ __forceinline__ int floor_values(double gm1, const Floors& fl, double
 // state once for both.
 constexpr int kMarchX = 64, kMarchY = kThreads / kMarchX;
 template <bool FLOOR>
+// Workgroups are numbered (tile, x3 segment, block), tile (x1 first) fastest;
+// launch slot s runs number (s mod 8) per_xcd + s / 8, so that neighbouring
+// tiles, which share cache lines at their x1 edges, run on one XCD and meet
+// in its L2.
 __global__ void __launch_bounds__(kThreads) k_newdt_march(Geo g, double gamma, Floors fl, double* __restrict__ cons,
-                                                         const double* __restrict__ bface, int ntx, int kz,
+                                                         const double* __restrict__ bface, int ntx, int nty, int nseg,
+                                                         int kz, int total, int per_xcd,
                                                          unsigned long long* __restrict__ dt_bits,
                                                          int* __restrict__ bad) {
-  const int b = blockIdx.z;
-  const int i = g.ng + (int)(blockIdx.x % ntx) * kMarchX + (int)(threadIdx.x % kMarchX);
-  const int j = g.ng + (int)(blockIdx.x / ntx) * kMarchY + (int)(threadIdx.x / kMarchX);
-  const int k0 = g.ng + (int)blockIdx.y * kz, kend = min(k0 + kz, g.ng + g.n3);
+  const int logical = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+  if (logical >= total) return;  // the whole workgroup: the padding of the last XCD
+  const int ntiles = ntx * nty;
+  const int tile = logical % ntiles, seg = (logical / ntiles) % nseg;
+  const int b = logical / (ntiles * nseg);
+  const int i = g.ng + (tile % ntx) * kMarchX + (int)(threadIdx.x % kMarchX);
+  const int j = g.ng + (tile / ntx) * kMarchY + (int)(threadIdx.x / kMarchX);
+  const int k0 = g.ng + seg * kz, kend = min(k0 + kz, g.ng + g.n3);
   double* u = cons + (int64_t)b * g.cblock;
   const double* fb = bface + (int64_t)b * g.fblock;
   double best = DBL_MAX;
@@ -710,13 +719,16 @@ hipError_t launch_newdt(const Geo& g, double gamma, const double* cons, const do
   const int nseg0 = (int)std::max<int64_t>(1, std::min<int64_t>(want, std::max(1, g.n3 / 8)));
   const int kz = (g.n3 + nseg0 - 1) / nseg0;
   const int nseg = (g.n3 + kz - 1) / kz;
-  const dim3 grid((unsigned)(ntx * nty), (unsigned)nseg, (unsigned)nb);
+  const int64_t total = tiles * nseg;
+  if (total > INT32_MAX / 2) return hipErrorInvalidValue;
+  const int per_xcd = (int)((total + 7) / 8);
+  const dim3 grid((unsigned)(8 * per_xcd), 1u);
   if (floor)
     hipLaunchKernelGGL(k_newdt_march<true>, grid, dim3(kThreads), 0, s, g, gamma, fl, const_cast<double*>(cons), bface,
-                       ntx, kz, dt_bits, bad);
+                       ntx, nty, nseg, kz, (int)total, per_xcd, dt_bits, bad);
   else
     hipLaunchKernelGGL(k_newdt_march<false>, grid, dim3(kThreads), 0, s, g, gamma, fl, const_cast<double*>(cons),
-                       bface, ntx, kz, dt_bits, bad);
+                       bface, ntx, nty, nseg, kz, (int)total, per_xcd, dt_bits, bad);
   return hipGetLastError();
 }
 
