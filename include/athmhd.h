@@ -25,8 +25,10 @@
  * With nscalars = S > 0 passive scalars, cons holds 5 + S cell arrays per
  * block, the masses rho C_1 .. rho C_S after E, and prim the specific
  * densities C_1 .. C_S after P (see "Passive scalars" below).
- * Every block is its own periodic neighbour: ghost cells and the boundary
- * faces n_d+nghost are periodic images, filled by the library.
+ * Every block of an athmhd_create handle is its own periodic neighbour: ghost
+ * cells and the boundary faces n_d+nghost are periodic images, filled by the
+ * library.  The blocks of a coupled mesh (athmhd_create_mesh) or coupled batch
+ * (athmhd_batch_couple) exchange these entries with their neighbours instead.
  *
  * Streams: every call that takes `stream` (a hipStream_t, NULL = default
  * stream) is asynchronous on it unless stated otherwise.
@@ -301,7 +303,8 @@ ATHMHD_API int athmhd_create_mesh(const athmhd_config* cfg, int nbx, int nby, in
  * a batched handle are the concatenations of the per-block arrays (block b's
  * cons at offsets[2b], its bface at offsets[2b+1], see athmhd_batch_info);
  * nblocks in later calls must equal the batch size.  Every block is its own
- * periodic neighbour.  Each stage runs as one persistent launch whose
+ * periodic neighbour unless athmhd_batch_couple makes the blocks one periodic
+ * mesh.  Each stage runs as one persistent launch whose
  * workgroups pull (block, tile, x3 segment) items from a device queue; ghost
  * fill, prim2cons and newdt run over all blocks from a descriptor table.
  * Only the fused kernel path is supported (kernel_path must be 0). */
