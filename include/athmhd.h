@@ -326,12 +326,16 @@ ATHMHD_API int athmhd_batch_info(athmhd_t h, int64_t* cons_len, int64_t* bface_l
  *     of every block (ghost cells, and every face entry other than the lower
  *     faces of its active cells) the block that owns the same cell of the
  *     domain, and uploads it (8 bytes per entry; the handle owns it).
- *   - athmhd_step and athmhd_step_chain then exchange the shell entries by
- *     that table before every stage (a device gather kernel) and once more
- *     after the last, so every face is updated by exactly one block and the
- *     stored state is whole after a step; athmhd_newdt and athmhd_prim2cons
- *     read a block's upper faces from its own shell.  athmhd_fill_ghosts
- *     runs the same exchange.
+ *   - athmhd_step then exchanges the shell entries by that table before
+ *     every stage (a device gather kernel) and once more after the last, so
+ *     every face is updated by exactly one block and the stored state is
+ *     whole after a step; athmhd_newdt and athmhd_prim2cons read a block's
+ *     upper faces from its own shell.  athmhd_fill_ghosts runs the same
+ *     exchange.
+ *   - athmhd_step_chain does the same but for the exchange before its first
+ *     stage: it takes the shell entries of its input as current, as a step
+ *     or athmhd_fill_ghosts leaves them (call athmhd_fill_ghosts after
+ *     changing the active entries between chained steps).
  *   - Split into blocks, the result equals one periodic block covering the
  *     whole domain.
  * Not with passive scalars or floors (ATHMHD_EUNSUP; athmhd_set_floors on a

@@ -463,7 +463,10 @@ int enqueue_step(athmhd_t h, double* cons, double* bface, double dt, const doubl
     // the fused stage reads recon + 1 cells past the block (the reconstruction
     // stencil of the ring faces); the unfused pipeline reads every ghost layer
     const int depth = h->unfused ? 0 : recon + 1;
-    if (ghosts &&
+    // a chained step on a coupled batch takes its input's shell entries as
+    // current: every step ends with an exchange of its output
+    const bool current = h->coupled && dt_bits && st == 0;
+    if (ghosts && !current &&
         (e = fill_ghosts(h, const_cast<double*>(xc), const_cast<double*>(xb), nblocks, s, depth)) != hipSuccess)
       return hip_fail(h, e, "fill_ghosts launch");
     const bool last = st == sc.nstage - 1;

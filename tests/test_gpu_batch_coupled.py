@@ -135,9 +135,12 @@ def test_coupled_batch_equals_single_block_and_oracle(torch_dev, athmhd, orc, sl
 
 
 def test_coupled_batch_chain_graph_and_tuner(torch_dev, athmhd, orc):
-    """Chained steps equal newdt + step bit for bit; after the tuner has timed
-    its candidates, three steps replayed from a hipGraph equal three eager
-    steps bit for bit."""
+    """Chained steps (which take their input's shell entries as current)
+    equal newdt + step (which exchanges before every stage) bit for bit, also
+    after active entries next to block boundaries were changed and
+    athmhd_fill_ghosts was called; after the tuner has timed its candidates,
+    three steps replayed from a hipGraph equal three eager steps bit for
+    bit."""
     from test_gpu_chain import chain_vs_newdt_step
     torch, dev = torch_dev
     dims, origins, domain = inputs.brick_layout([8, 4, 8], 16)
@@ -145,6 +148,13 @@ def test_coupled_batch_chain_graph_and_tuner(torch_dev, athmhd, orc):
     cons = orc.prim2cons(orc.cfg_for(b), b.prim, b.bface)
     bs, tc, tf = coupled_batch(athmhd, torch, dev, cons, b.bface, 2, dims, origins, domain, b.dx, b.gamma)
     chain_vs_newdt_step(torch, dev, bs, tc, tf)
+    # raise the density of the first and last active cells of every block
+    pc, pf = tc.clone(), tf.clone()
+    for v, n in zip(bs.views(pc, "cons"), dims):
+        v[0, 2, 2, 2] *= 1.01
+        v[0, 1 + n[2], 1 + n[1], 1 + n[0]] *= 0.99
+    bs.fill_ghosts(pc, pf)
+    chain_vs_newdt_step(torch, dev, bs, pc, pf)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         bs.tune(tc, tf, stream=stream)
