@@ -363,7 +363,7 @@ def bench_adjoint(args):
         plateau.append(row)
         errs.append(min(row))
     out = {
-        "metric": "adjoint cost: (forward + backward) / forward time of a checkpointed 64-step rollout "
+        "metric": f"adjoint cost: (forward + backward) / forward time of a checkpointed {nsteps}-step rollout "
                   "gradient, FP64 VL2+PLM+HLLD+CT, 1 MI355X",
         "value": t_all / t_fwd, "unit": "ratio", "n_gpus": 1, "steps": nsteps, "warmup": 1,
         "ms_per_step": t_fwd / nsteps * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
