@@ -160,6 +160,7 @@ def test_batch_calls_reject_non_batch_use():
     assert L.athmhd_set_graph(None, 1) == athmhd.EINVAL
     assert L.athmhd_newdt_noalloc(None, None, None, 1, None, None, None) == athmhd.EINVAL
     assert L.athmhd_step_chain(None, None, None, 1, None, None, None) == athmhd.EINVAL
+    assert L.athmhd_batch_couple(None, None, None) == athmhd.EINVAL
 
 
 def test_octree_is_two_to_one_balanced():
