@@ -134,6 +134,62 @@ def test_coupled_batch_equals_single_block_and_oracle(torch_dev, athmhd, orc, sl
     single.close()
 
 
+# boxes of unequal shape whose faces do not line up along x1 and x2 either:
+# (origin, dims) tiling a 24 x 24 x 10 domain
+GENERAL_BOXES = [
+    ((0, 0, 0), (8, 24, 6)), ((8, 0, 0), (16, 10, 6)), ((8, 10, 0), (16, 14, 6)),
+    ((0, 0, 6), (12, 9, 4)), ((12, 0, 6), (12, 9, 4)), ((0, 9, 6), (5, 15, 4)), ((5, 9, 6), (19, 15, 4)),
+]
+
+
+@pytest.mark.parametrize("layout,kw", [
+    ("general", dict(integrator="vl2", recon="plm", riemann="hlld")),
+    ("general", dict(integrator="rk3", recon="ppm", riemann="hlld")),
+    ("thin", dict(integrator="rk3", recon="ppm", riemann="hlle")),
+])
+def test_coupled_batch_general_layouts(torch_dev, athmhd, orc, layout, kw):
+    """Blocks that are not cubes and whose neighbours differ along every
+    direction (seven boxes tiling 24 x 24 x 10), and slabs of 2-cell cubes
+    thinner than PPM's three ghost layers: three steps against the single
+    block (dt exactly, state to 1e-14) and the oracle (within the bar)."""
+    torch, dev = torch_dev
+    ng = 3 if kw["recon"] == "ppm" else 2
+    if layout == "general":
+        origins = [o for o, _ in GENERAL_BOXES]
+        dims = [n for _, n in GENERAL_BOXES]
+        domain = (24, 24, 10)
+    else:
+        dims, origins, domain = inputs.brick_layout([2, 4, 2, 6], 12)
+    b = inputs.smooth_random(n=domain, seed=46, ng=ng)
+    cfg = orc.cfg_for(b, **kw)
+    cons = orc.prim2cons(cfg, b.prim, b.bface)
+    single = athmhd.Solver(b.n, ng, b.dx, b.gamma, **kw)
+    bs, tc, tf = coupled_batch(athmhd, torch, dev, cons, b.bface, ng, dims, origins, domain, b.dx, b.gamma, **kw)
+    tsc, tsf = to_dev(torch, dev, cons), to_dev(torch, dev, b.bface)
+    rc, rb = cons.copy(), b.bface.copy()
+    for _ in range(3):
+        dt, bad = orc.newdt(cfg, rc, rb)
+        assert bad == 0
+        bdt = bs.newdt(tc, tf)
+        assert bdt == single.newdt(tsc, tsf)
+        assert orc.step(cfg, rc, rb, dt) == 0
+        single.step(tsc, tsf, dt)
+        bs.step(tc, tf, dt)
+    jc, jf = joined(bs, tc, tf, dims, origins, domain)
+    a = active(ng, b.n)
+    sc, sf = tsc.cpu().numpy(), tsf.cpu().numpy()
+    err_single = max(rel_l1(jc[a], sc[a]), rel_l1(jf[a], sf[a]))
+    err_oracle = max(rel_l1(jc[a], rc[a]), rel_l1(jf[a], rb[a]))
+    print(f"coupled batch, {layout} layout, {kw['integrator']}+{kw['recon']}: vs single block {err_single:.2e}, "
+          f"vs oracle {err_oracle:.2e}")
+    assert err_single <= 1e-14
+    assert err_oracle <= TOL
+    orc.fill_ghosts(cfg, jc, jf)
+    assert inputs.divb_metric(jf, b.n, ng, b.dx) <= 1e-13
+    bs.close()
+    single.close()
+
+
 def test_coupled_batch_chain_graph_and_tuner(torch_dev, athmhd, orc):
     """Chained steps (which take their input's shell entries as current)
     equal newdt + step (which exchanges before every stage) bit for bit, also
