@@ -190,6 +190,35 @@ def test_coupled_batch_general_layouts(torch_dev, athmhd, orc, layout, kw):
     single.close()
 
 
+@pytest.mark.parametrize("shape", [0, 1, 2, 3])
+@pytest.mark.parametrize("split", [0, 1])
+def test_coupled_batch_every_tile(torch_dev, athmhd, orc, shape, split):
+    """Every tile candidate of the batched stage kernel, with and without the
+    x3 split, on the seven general boxes: two VL2+PLM+HLLD steps equal the
+    single block's to 1e-14."""
+    torch, dev = torch_dev
+    origins = [o for o, _ in GENERAL_BOXES]
+    dims = [n for _, n in GENERAL_BOXES]
+    domain = (24, 24, 10)
+    b = inputs.smooth_random(n=domain, seed=47, ng=2)
+    cons = orc.prim2cons(orc.cfg_for(b), b.prim, b.bface)
+    single = athmhd.Solver(b.n, 2, b.dx, b.gamma)
+    bs, tc, tf = coupled_batch(athmhd, torch, dev, cons, b.bface, 2, dims, origins, domain, b.dx, b.gamma)
+    bs.set_tile(shape, split)
+    tsc, tsf = to_dev(torch, dev, cons), to_dev(torch, dev, b.bface)
+    for _ in range(2):
+        dt = single.newdt(tsc, tsf)
+        assert bs.newdt(tc, tf) == dt
+        single.step(tsc, tsf, dt)
+        bs.step(tc, tf, dt)
+    jc, jf = joined(bs, tc, tf, dims, origins, domain)
+    a = active(2, b.n)
+    sc, sf = tsc.cpu().numpy(), tsf.cpu().numpy()
+    assert max(rel_l1(jc[a], sc[a]), rel_l1(jf[a], sf[a])) <= 1e-14
+    bs.close()
+    single.close()
+
+
 def test_coupled_batch_chain_graph_and_tuner(torch_dev, athmhd, orc):
     """Chained steps (which take their input's shell entries as current)
     equal newdt + step (which exchanges before every stage) bit for bit, also
